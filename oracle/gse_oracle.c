@@ -1,0 +1,559 @@
+/*
+ * gse_oracle.c -- sequential CPU oracle (TEST INFRASTRUCTURE; see header).
+ *
+ * Each function names the passage of the paper it restates.  Everything is
+ * FP64 and sequential; sums run in row order, exactly as written in the
+ * definitions.  Build: gcc -O2 -std=c99 -ffp-contract=off -fPIC -shared.
+ */
+#include "gse_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+static uint64_t bits_of(double v) { uint64_t u; memcpy(&u, &v, sizeof u); return u; }
+
+/* ------------------------------------------------------------------------ */
+/* Section III-B.1: occurrences N_i of every distinct exponent e_i.  The    */
+/* 11-bit biased exponent field is the key; field 2047 (Inf/NaN) is counted */
+/* and reported so the caller can reject the input.                         */
+int64_t or_exponent_histogram(const double* val, int64_t nnz, uint32_t* hist) {
+    int64_t nonfinite = 0;
+    memset(hist, 0, 2048 * sizeof(uint32_t));
+    for (int64_t i = 0; i < nnz; ++i) {
+        unsigned e = (unsigned)((bits_of(val[i]) >> 52) & 0x7FF);
+        hist[e] += 1;
+        if (e == 2047) nonfinite += 1;
+    }
+    return nonfinite;
+}
+
+/* Section III-B.1 (sort exponents by occurrence, descending; keep the k most
+ * frequent) and Section III-B.2 (store each shared exponent incremented by
+ * one; the maximum exponent must be one of them so every value has a shared
+ * exponent above its own).
+ * Readings: field 0 (zero / subnormal) is never a candidate; ties in count go
+ * to the larger exponent; when the maximum exponent is not among the k most
+ * frequent it replaces the last (least frequent) slot; unused slots are 0; a
+ * set without any normal value gets the single slot 1023+1.
+ * Returns the number of slots used, or OR_ERR_RANGE when a shared exponent is
+ * below 63 (its fixed-point grid would leave the normal FP64 range). */
+int or_select_shared_exponents(const uint32_t* hist, int num_exp, int16_t* sem) {
+    if (num_exp < 1 || num_exp > OR_MAX_EXP) return OR_ERR_ARG;
+    unsigned char taken[2048];
+    memset(taken, 0, sizeof taken);
+    int chosen[OR_MAX_EXP];
+    int used = 0;
+    for (int slot = 0; slot < num_exp; ++slot) {
+        int best = -1;
+        for (int e = 2046; e >= 1; --e) {  /* high to low: ties keep the larger e */
+            if (taken[e] || hist[e] == 0) continue;
+            if (best < 0 || hist[e] > hist[best]) best = e;
+        }
+        if (best < 0) break;
+        taken[best] = 1;
+        chosen[used++] = best;
+    }
+    int max_e = 0;
+    for (int e = 2046; e >= 1; --e)
+        if (hist[e] > 0) { max_e = e; break; }
+    if (used == 0) {
+        chosen[0] = 1023;
+        used = 1;
+    } else if (!taken[max_e]) {
+        chosen[used - 1] = max_e;
+    }
+    for (int i = 0; i < OR_MAX_EXP; ++i) sem[i] = 0;
+    for (int i = 0; i < used; ++i) {
+        if (chosen[i] < 63) return OR_ERR_RANGE;
+        sem[i] = (int16_t)(chosen[i] + 1);
+    }
+    return used;
+}
+
+/* Algorithm 1 restated for the 64-bit SEM word with the index kept in the
+ * column (Section III-C.1).  Steps, in the paper's order:
+ *   sign and exponent field of the value;
+ *   if exp+1 is a shared exponent, that slot, with minDiff = 1;
+ *   otherwise the slot whose shared exponent is the nearest one above exp,
+ *   minDiff = SEM - exp;
+ *   the significand with its hidden one made explicit is shifted right by
+ *   minDiff (denormalisation) -- here onto a 63-bit field, so the field is
+ *   (hidden|fraction) << (11 - minDiff), truncated toward zero when the
+ *   shift is to the right;
+ *   sign, index and magnitude are packed.
+ * A subnormal or zero value has no hidden one and the exponent of the
+ * smallest normal (1) for the shift.  Returns OR_ERR_RANGE if a value has no
+ * shared exponent above its own (possible only with a reused table). */
+int or_encode_values(const double* val, const int32_t* col, int64_t nnz,
+                     const int16_t* sem, uint32_t* col_idx, uint16_t* head,
+                     uint16_t* tail1, uint32_t* tail2) {
+    for (int64_t i = 0; i < nnz; ++i) {
+        uint64_t u = bits_of(val[i]);
+        unsigned sign = (unsigned)(u >> 63);
+        int e = (int)((u >> 52) & 0x7FF);
+        uint64_t frac = u & ((1ull << 52) - 1);
+        int slot = -1;
+        int min_diff = 0;
+        for (int k = 0; k < OR_MAX_EXP; ++k) {
+            if (sem[k] != 0 && sem[k] == e + 1) { slot = k; min_diff = 1; break; }
+        }
+        if (slot < 0) {
+            int best = 1 << 30;
+            for (int k = 0; k < OR_MAX_EXP; ++k) {
+                int d = (int)sem[k] - e;
+                if (sem[k] != 0 && d > 0 && d < best) { best = d; slot = k; }
+            }
+            if (slot < 0) return OR_ERR_RANGE;
+            min_diff = best;
+        }
+        uint64_t sig = (e > 0) ? ((1ull << 52) | frac) : frac;
+        int shift_exp = (e > 0) ? e : 1;
+        int sh = 11 - ((int)sem[slot] - shift_exp);  /* = 11 - minDiff for normals */
+        uint64_t F;
+        if (sh >= 0) F = sig << sh;
+        else if (-sh >= 64) F = 0;
+        else F = sig >> (-sh);
+        (void)min_diff;
+        col_idx[i] = (uint32_t)col[i] | ((uint32_t)slot << 29);
+        head[i] = (uint16_t)((sign << 15) | (unsigned)(F >> 48));
+        tail1[i] = (uint16_t)((F >> 32) & 0xFFFF);
+        tail2[i] = (uint32_t)(F & 0xFFFFFFFFu);
+    }
+    return OR_OK;
+}
+
+/* Algorithm 2 and its two wider variants (Section III-C.2): the value read
+ * with s segments is +-F_W * 2^(SEM - 1023 - W), W = 15, 31, 63, where F_W is
+ * the top W magnitude bits of the SEM word; a zero field reads as 0. */
+double or_decode_one(uint32_t col_word, uint16_t h, uint16_t t1, uint32_t t2,
+                     const int16_t* sem, int s) {
+    int slot = (int)(col_word >> 29);
+    int W = (s == 1) ? 15 : (s == 2) ? 31 : 63;
+    uint64_t F63 = ((uint64_t)(h & 0x7FFFu) << 48) | ((uint64_t)t1 << 32) | (uint64_t)t2;
+    uint64_t F = F63 >> (63 - W);
+    if (F == 0) return 0.0;
+    double mag = ldexp((double)F, (int)sem[slot] - 1023 - W);
+    return (h >> 15) ? -mag : mag;
+}
+
+void or_decode(const uint32_t* col_idx, const uint16_t* head, const uint16_t* tail1,
+               const uint32_t* tail2, int64_t nnz, const int16_t* sem, int s,
+               double* out) {
+    for (int64_t i = 0; i < nnz; ++i)
+        out[i] = or_decode_one(col_idx[i], head[i], tail1[i], tail2[i], sem, s);
+}
+
+/* Whole conversion: histogram, table, per-value words, and the relative
+ * perturbation eta_s = ||A - A_s||_inf / ||A||_inf of each segment count. */
+int or_encode(const int32_t* row_ptr, const int32_t* col, const double* val,
+              int32_t n_rows, int32_t n_cols, int64_t nnz, int num_exp,
+              const int16_t* sem_in, int16_t* sem_out, uint32_t* col_idx,
+              uint16_t* head, uint16_t* tail1, uint32_t* tail2, double* eta3,
+              double* exact_frac) {
+    if (n_rows < 0 || n_cols < 0 || nnz < 0 || num_exp < 1 || num_exp > OR_MAX_EXP)
+        return OR_ERR_ARG;
+    if ((int64_t)n_cols > (1 << 29) || nnz >= (1ll << 31)) return OR_ERR_RANGE;
+    uint32_t* hist = (uint32_t*)malloc(2048 * sizeof(uint32_t));
+    if (!hist) return OR_ERR_ARG;
+    if (or_exponent_histogram(val, nnz, hist) > 0) { free(hist); return OR_ERR_NONFINITE; }
+    int rc;
+    if (sem_in) {
+        for (int i = 0; i < OR_MAX_EXP; ++i) sem_out[i] = (i < num_exp) ? sem_in[i] : 0;
+        for (int i = 0; i < OR_MAX_EXP; ++i) {
+            if (sem_out[i] != 0 && sem_out[i] < 64) { free(hist); return OR_ERR_RANGE; }
+            for (int k = 0; k < i; ++k)
+                if (sem_out[i] != 0 && sem_out[k] == sem_out[i]) { free(hist); return OR_ERR_ARG; }
+        }
+    } else {
+        rc = or_select_shared_exponents(hist, num_exp, sem_out);
+        if (rc < 0) { free(hist); return rc; }
+    }
+    uint64_t covered = 0;
+    for (int i = 0; i < OR_MAX_EXP; ++i)
+        if (sem_out[i] > 0) covered += hist[sem_out[i] - 1];
+    if (exact_frac) *exact_frac = nnz ? (double)covered / (double)nnz : 1.0;
+    free(hist);
+    rc = or_encode_values(val, col, nnz, sem_out, col_idx, head, tail1, tail2);
+    if (rc != OR_OK) return rc;
+    if (eta3) {
+        double amax = 0.0, emax[3] = {0.0, 0.0, 0.0};
+        for (int32_t r = 0; r < n_rows; ++r) {
+            double a = 0.0, es[3] = {0.0, 0.0, 0.0};
+            for (int32_t j = row_ptr[r]; j < row_ptr[r + 1]; ++j) {
+                a += fabs(val[j]);
+                for (int s = 1; s <= 3; ++s)
+                    es[s - 1] += fabs(val[j] - or_decode_one(col_idx[j], head[j], tail1[j],
+                                                             tail2[j], sem_out, s));
+            }
+            if (a > amax) amax = a;
+            for (int s = 0; s < 3; ++s) if (es[s] > emax[s]) emax[s] = es[s];
+        }
+        for (int s = 0; s < 3; ++s) eta3[s] = amax > 0.0 ? emax[s] / amax : 0.0;
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* FP64 CSR SpMV (the baseline the paper compares against, Section IV-A).    */
+void or_csr_spmv(int32_t n_rows, const int32_t* row_ptr, const int32_t* col,
+                 const double* val, const double* x, double* y) {
+    for (int32_t r = 0; r < n_rows; ++r) {
+        double sum = 0.0;
+        for (int32_t j = row_ptr[r]; j < row_ptr[r + 1]; ++j) sum += val[j] * x[col[j]];
+        y[r] = sum;
+    }
+}
+
+/* Algorithm 2 (s = 1) and the head+tail1 / head+tail1+tail2 operators:
+ * split column and slot, read the value with s segments, multiply and
+ * accumulate in FP64 in row order. */
+void or_gse_spmv(int32_t n_rows, const int32_t* row_ptr, const uint32_t* col_idx,
+                 const uint16_t* head, const uint16_t* tail1, const uint32_t* tail2,
+                 const int16_t* sem, int s, const double* x, double* y) {
+    for (int32_t r = 0; r < n_rows; ++r) {
+        double sum = 0.0;
+        for (int32_t j = row_ptr[r]; j < row_ptr[r + 1]; ++j) {
+            double v = or_decode_one(col_idx[j], head[j], tail1[j], tail2[j], sem, s);
+            sum += v * x[col_idx[j] & 0x1FFFFFFFu];
+        }
+        y[r] = sum;
+    }
+}
+
+void or_gse_spmv_rows(const int32_t* rows, int32_t n_sel, const int32_t* row_ptr,
+                      const uint32_t* col_idx, const uint16_t* head,
+                      const uint16_t* tail1, const uint32_t* tail2,
+                      const int16_t* sem, int s, const double* x, double* y_sel) {
+    for (int32_t q = 0; q < n_sel; ++q) {
+        int32_t r = rows[q];
+        double sum = 0.0;
+        for (int32_t j = row_ptr[r]; j < row_ptr[r + 1]; ++j) {
+            double v = or_decode_one(col_idx[j], head[j], tail1[j], tail2[j], sem, s);
+            sum += v * x[col_idx[j] & 0x1FFFFFFFu];
+        }
+        y_sel[q] = sum;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section III-D.  Metrics over the residual history at iteration j:
+ *   RSD   (Eq. 3): population standard deviation of resid[j-t..j-1] over
+ *                  their mean;
+ *   nDec  (Eqs. 4-5): number of i in [j-t, j-1] with resid[i] > resid[i+1];
+ *   relDec (Eq. 6): (resid[j-t] - resid[j-1]) / resid[j-t].              */
+void or_window_metrics(const double* resid, int32_t j, int32_t t,
+                       double* rsd, int32_t* ndec, double* reldec) {
+    double avg = 0.0;
+    for (int32_t i = j - t; i <= j - 1; ++i) avg += resid[i];
+    avg /= (double)t;
+    double var = 0.0;
+    for (int32_t i = j - t; i <= j - 1; ++i) var += (resid[i] - avg) * (resid[i] - avg);
+    var /= (double)t;
+    *rsd = sqrt(var) / avg;
+    int32_t n = 0;
+    for (int32_t i = j - t; i <= j - 1; ++i) n += (resid[i] > resid[i + 1]) ? 1 : 0;
+    *ndec = n;
+    *reldec = (resid[j - t] - resid[j - 1]) / resid[j - t];
+}
+
+/* Conditions 1-3, evaluated only at j = l + q*m (q >= 0) once t residuals
+ * exist.  Returns the first condition that holds (1, 2 or 3) or 0.        */
+int or_precision_trigger(const double* resid, int32_t j, const or_params* p) {
+    if (j < p->l || j < p->t || p->m <= 0 || ((j - p->l) % p->m) != 0) return OR_TRIG_NONE;
+    double rsd, reldec;
+    int32_t ndec;
+    or_window_metrics(resid, j, p->t, &rsd, &ndec, &reldec);
+    int below, at_or_above;
+    if (p->ndec_rule == 1) { below = 2 * ndec < p->t; at_or_above = !below; }
+    else { below = ndec < p->ndec_limit; at_or_above = !below; }
+    if (rsd > p->rsd_limit && below) return OR_TRIG_C1;
+    if (at_or_above && reldec < p->reldec_limit) return OR_TRIG_C2;
+    if (ndec == 0) return OR_TRIG_C3;
+    return OR_TRIG_NONE;
+}
+
+/* ------------------------------------------------------------------------ */
+static void apply_op(const or_matrix* A, int s, const double* x, double* y) {
+    if (s <= 0) or_csr_spmv(A->n_rows, A->row_ptr, A->col, A->val, x, y);
+    else or_gse_spmv(A->n_rows, A->row_ptr, A->col_idx, A->head, A->tail1, A->tail2,
+                     A->sem8, s, x, y);
+}
+
+static double dot(int32_t n, const double* a, const double* b) {
+    double s = 0.0;
+    for (int32_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* r = b - A_s x ; returns r.r */
+static double residual(const or_matrix* A, int s, const double* b, const double* x,
+                       double* r) {
+    apply_op(A, s, x, r);
+    for (int32_t i = 0; i < A->n_rows; ++i) r[i] = b[i] - r[i];
+    return dot(A->n_rows, r, r);
+}
+
+static int final_segments(const or_params* p) {
+    return p->fixed_segments < 0 ? 0 : 3;  /* 0: FP64 CSR operator */
+}
+
+/* Is the current operator the one convergence is judged on? */
+static int operator_is_final(const or_matrix* A, const or_params* p, int s) {
+    if (p->fixed_segments != 0) return 1;
+    if (s >= 3) return 1;
+    return A->eta3 && A->eta3[s - 1] == 0.0;
+}
+
+static void init_report(or_report* rep) {
+    memset(rep, 0, sizeof *rep);
+    rep->switch_iter[0] = rep->switch_iter[1] = -1;
+}
+
+/* CG (Hestenes-Stiefel form) with FP64 vectors; only the operator A_s uses
+ * the reduced segments.  The stepped scheme (Algorithm 3 with Conditions
+ * 1-3) raises s by one when a condition holds on the check grid.  Readings
+ * beyond the paper: a floor trigger (relres <= floor_c*eta_s), escalation
+ * when the tolerance is met with an inexact operator, escalation instead of
+ * failure on breakdown below s = 3, and at every switch the residual is
+ * recomputed with the new operator (r = b - A_{s+1} x) and, in restart mode,
+ * p = r.  Convergence is accepted only after the explicit residual with the
+ * final operator meets the tolerance. */
+int or_cg(const or_matrix* A, const double* b, double* x, const or_params* p,
+          or_report* rep, double* hist, int32_t* seg_hist) {
+    int32_t n = A->n_rows;
+    init_report(rep);
+    double* r = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* pv = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* q = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!r || !pv || !q) { free(r); free(pv); free(q); return OR_ERR_ARG; }
+    int stepped = (p->fixed_segments == 0);
+    int s = stepped ? p->start_segments : (p->fixed_segments > 0 ? p->fixed_segments : 0);
+    int fin = final_segments(p);
+    double nb = sqrt(dot(n, b, b));
+    if (nb == 0.0) {
+        for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+        rep->status = OR_OK;
+        if (hist) hist[0] = 0.0;
+        free(r); free(pv); free(q);
+        return OR_OK;
+    }
+    double rho = residual(A, s, b, x, r);
+    memcpy(pv, r, sizeof(double) * (size_t)n);
+    double relres = sqrt(rho) / nb;
+    if (hist) hist[0] = relres;
+    if (seg_hist) seg_hist[0] = s;
+    int32_t it = 0;
+    int nsw = 0;
+    int status = OR_NOT_CONVERGED;
+    for (;;) {
+        int trig = OR_TRIG_NONE;
+        if (relres <= p->tol) {
+            if (operator_is_final(A, p, s)) {
+                double rt = sqrt(residual(A, fin, b, x, q)) / nb;
+                if (rt <= p->tol) { status = OR_OK; break; }
+                rho = residual(A, s, b, x, r);  /* replace the drifted residual */
+                memcpy(pv, r, sizeof(double) * (size_t)n);
+                relres = sqrt(rho) / nb;
+                if (relres <= p->tol) { status = OR_NOT_CONVERGED; break; }
+            } else {
+                trig = OR_TRIG_TOL;
+            }
+        }
+        if (trig == OR_TRIG_NONE) {
+            if (it >= p->max_iter) break;
+            apply_op(A, s, pv, q);
+            double pq = dot(n, pv, q);
+            if (!(pq > 0.0) || !isfinite(pq)) {
+                if (stepped && s < 3) trig = OR_TRIG_BREAKDOWN;
+                else { status = OR_ERR_BREAKDOWN; break; }
+            } else {
+                double alpha = rho / pq;
+                for (int32_t i = 0; i < n; ++i) x[i] += alpha * pv[i];
+                for (int32_t i = 0; i < n; ++i) r[i] -= alpha * q[i];
+                double rho_new = dot(n, r, r);
+                it += 1;
+                rep->iters_per_seg[(s > 0 ? s : 3) - 1] += 1;
+                relres = sqrt(rho_new) / nb;
+                if (hist) hist[it] = relres;
+                if (seg_hist) seg_hist[it] = s;
+                double beta = rho_new / rho;
+                rho = rho_new;
+                for (int32_t i = 0; i < n; ++i) pv[i] = r[i] + beta * pv[i];
+                if (stepped && s < 3 && relres > p->tol) {
+                    double eta = A->eta3 ? A->eta3[s - 1] : 0.0;
+                    if (p->floor_c > 0.0 && eta > 0.0 && relres <= p->floor_c * eta)
+                        trig = OR_TRIG_FLOOR;
+                    else if (hist)
+                        trig = or_precision_trigger(hist, it, p);
+                }
+            }
+        }
+        if (trig != OR_TRIG_NONE) {
+            if (nsw < 2) { rep->switch_iter[nsw] = it; rep->switch_trigger[nsw] = trig; }
+            nsw += 1;
+            s += 1;
+            rho = residual(A, s, b, x, r);
+            if (p->switch_mode == 0) memcpy(pv, r, sizeof(double) * (size_t)n);
+            relres = sqrt(rho) / nb;
+        }
+    }
+    rep->status = status;
+    rep->iters = it;
+    rep->relres_recursive = relres;
+    rep->relres_true = sqrt(residual(A, fin, b, x, q)) / nb;
+    free(r); free(pv); free(q);
+    return status;
+}
+
+/* Givens rotation zeroing b against a, with r = sqrt(a^2 + b^2). */
+static void givens(double a, double b, double* c, double* s) {
+    double r = sqrt(a * a + b * b);
+    if (r == 0.0) { *c = 1.0; *s = 0.0; return; }
+    *c = a / r;
+    *s = b / r;
+}
+
+/* Restarted GMRES(m) with FP64 Arnoldi vectors, Givens rotations and the
+ * same stepped operator schedule as CG.  The monitored residual is the
+ * least-squares estimate |g_{j+1}|/||b||.  A switch ends the cycle; the next
+ * cycle starts from the explicit residual of the new operator. */
+int or_gmres(const or_matrix* A, const double* b, double* x, const or_params* p,
+             or_report* rep, double* hist, int32_t* seg_hist) {
+    int32_t n = A->n_rows;
+    int m = p->restart;
+    init_report(rep);
+    if (m < 1) return OR_ERR_ARG;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    double* V = (double*)malloc(sizeof(double) * nn * (size_t)(m + 1));
+    double* H = (double*)calloc((size_t)(m + 1) * (size_t)m, sizeof(double));
+    double* cs = (double*)malloc(sizeof(double) * (size_t)m);
+    double* sn = (double*)malloc(sizeof(double) * (size_t)m);
+    double* g = (double*)malloc(sizeof(double) * (size_t)(m + 1));
+    double* y = (double*)malloc(sizeof(double) * (size_t)m);
+    double* h2 = (double*)malloc(sizeof(double) * (size_t)(m + 1));
+    double* w = (double*)malloc(sizeof(double) * nn);
+    if (!V || !H || !cs || !sn || !g || !y || !h2 || !w) {
+        free(V); free(H); free(cs); free(sn); free(g); free(y); free(h2); free(w);
+        return OR_ERR_ARG;
+    }
+#define HH(i, j) H[(size_t)(i) * (size_t)m + (size_t)(j)]
+    int stepped = (p->fixed_segments == 0);
+    int s = stepped ? p->start_segments : (p->fixed_segments > 0 ? p->fixed_segments : 0);
+    int fin = final_segments(p);
+    double nb = sqrt(dot(n, b, b));
+    int32_t it = 0;
+    int nsw = 0;
+    int status = OR_NOT_CONVERGED;
+    double relres = 0.0;
+    if (nb == 0.0) {
+        for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+        rep->status = OR_OK;
+        if (hist) hist[0] = 0.0;
+        goto done;
+    }
+    for (;;) {
+        double beta = sqrt(residual(A, s, b, x, V));
+        relres = beta / nb;
+        if (it == 0) { if (hist) hist[0] = relres; if (seg_hist) seg_hist[0] = s; }
+        int trig = OR_TRIG_NONE;
+        if (relres <= p->tol) {
+            if (operator_is_final(A, p, s)) {
+                if (s == fin || p->fixed_segments != 0 || s == 3) { status = OR_OK; break; }
+                double rt = sqrt(residual(A, fin, b, x, w)) / nb;
+                if (rt <= p->tol) { status = OR_OK; break; }
+                trig = OR_TRIG_TOL;
+            } else {
+                trig = OR_TRIG_TOL;
+            }
+        }
+        if (trig != OR_TRIG_NONE) {
+            if (s >= 3) break;
+            if (nsw < 2) { rep->switch_iter[nsw] = it; rep->switch_trigger[nsw] = trig; }
+            nsw += 1;
+            s += 1;
+            continue;
+        }
+        if (it >= p->max_iter) break;
+        for (int32_t i = 0; i < n; ++i) V[i] /= beta;
+        for (int k = 0; k <= m; ++k) g[k] = 0.0;
+        g[0] = beta;
+        int k_used = 0;
+        for (int j = 0; j < m && it < p->max_iter; ++j) {
+            double* vj = V + (size_t)j * nn;
+            apply_op(A, s, vj, w);
+            if (p->orth == 1) {  /* classical Gram-Schmidt, applied twice */
+                for (int i = 0; i <= j; ++i) HH(i, j) = dot(n, V + (size_t)i * nn, w);
+                for (int i = 0; i <= j; ++i) {
+                    const double* vi = V + (size_t)i * nn;
+                    for (int32_t e = 0; e < n; ++e) w[e] -= HH(i, j) * vi[e];
+                }
+                for (int i = 0; i <= j; ++i) h2[i] = dot(n, V + (size_t)i * nn, w);
+                for (int i = 0; i <= j; ++i) {
+                    const double* vi = V + (size_t)i * nn;
+                    for (int32_t e = 0; e < n; ++e) w[e] -= h2[i] * vi[e];
+                    HH(i, j) += h2[i];
+                }
+            } else {  /* modified Gram-Schmidt */
+                for (int i = 0; i <= j; ++i) {
+                    const double* vi = V + (size_t)i * nn;
+                    double h = dot(n, vi, w);
+                    HH(i, j) = h;
+                    for (int32_t e = 0; e < n; ++e) w[e] -= h * vi[e];
+                }
+            }
+            double hn = sqrt(dot(n, w, w));
+            HH(j + 1, j) = hn;
+            for (int i = 0; i < j; ++i) {
+                double t0 = cs[i] * HH(i, j) + sn[i] * HH(i + 1, j);
+                HH(i + 1, j) = -sn[i] * HH(i, j) + cs[i] * HH(i + 1, j);
+                HH(i, j) = t0;
+            }
+            givens(HH(j, j), HH(j + 1, j), &cs[j], &sn[j]);
+            HH(j, j) = cs[j] * HH(j, j) + sn[j] * HH(j + 1, j);
+            HH(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            it += 1;
+            rep->iters_per_seg[(s > 0 ? s : 3) - 1] += 1;
+            k_used = j + 1;
+            relres = fabs(g[j + 1]) / nb;
+            if (hist) hist[it] = relres;
+            if (seg_hist) seg_hist[it] = s;
+            if (hn == 0.0) break;  /* happy breakdown: exact in this space */
+            double* vn = V + (size_t)(j + 1) * nn;
+            for (int32_t e = 0; e < n; ++e) vn[e] = w[e] / hn;
+            if (relres <= p->tol) break;
+            if (stepped && s < 3) {
+                double eta = A->eta3 ? A->eta3[s - 1] : 0.0;
+                if (p->floor_c > 0.0 && eta > 0.0 && relres <= p->floor_c * eta)
+                    trig = OR_TRIG_FLOOR;
+                else if (hist)
+                    trig = or_precision_trigger(hist, it, p);
+                if (trig != OR_TRIG_NONE) break;
+            }
+        }
+        for (int i = k_used - 1; i >= 0; --i) {
+            double acc = g[i];
+            for (int k = i + 1; k < k_used; ++k) acc -= HH(i, k) * y[k];
+            y[i] = acc / HH(i, i);
+        }
+        for (int k = 0; k < k_used; ++k) {
+            const double* vk = V + (size_t)k * nn;
+            for (int32_t e = 0; e < n; ++e) x[e] += y[k] * vk[e];
+        }
+        if (trig != OR_TRIG_NONE) {
+            if (nsw < 2) { rep->switch_iter[nsw] = it; rep->switch_trigger[nsw] = trig; }
+            nsw += 1;
+            s += 1;
+        }
+    }
+done:
+    rep->status = status;
+    rep->iters = it;
+    rep->relres_recursive = relres;
+    rep->relres_true = nb == 0.0 ? 0.0 : sqrt(residual(A, fin, b, x, w)) / nb;
+#undef HH
+    free(V); free(H); free(cs); free(sn); free(g); free(y); free(h2); free(w);
+    return status;
+}

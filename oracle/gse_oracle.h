@@ -1,0 +1,117 @@
+/*
+ * gse_oracle.h -- sequential CPU oracle for the group-shared-exponent (GSE)
+ * format with segmented mantissa storage (SEM), and for the CG / GMRES
+ * solvers built on it.
+ *
+ * TEST INFRASTRUCTURE.  This library is the reference the GPU library is
+ * checked against.  It is plain C99, single threaded, FP64, written for
+ * readability rather than speed, and shares no code, header or table with the
+ * GPU library.  Only the test-suite, the smoke check and the CPU-baseline leg
+ * of the benchmark load it.
+ *
+ * Format (Section III-B, Algorithms 1 and 2, Section III-C.1):
+ *   - a table of up to 8 shared exponents, each stored as (biased exponent+1);
+ *   - per non-zero: a 3-bit slot index kept in the top bits of the 32-bit
+ *     column index, and a 64-bit word  sign<<63 | F63  where F63 is |v| on the
+ *     fixed-point grid 2^(SEM-1023-63) of its slot, truncated toward zero;
+ *   - the word is split into three planes: head (bits 63..48), tail1
+ *     (bits 47..32) and tail2 (bits 31..0).  Reading s planes gives a
+ *     W_s = 15, 31 or 63 bit magnitude.
+ */
+#ifndef GSE_ORACLE_H
+#define GSE_ORACLE_H
+#include <stdint.h>
+
+#define OR_MAX_EXP 8
+
+enum { OR_OK = 0, OR_NOT_CONVERGED = 2, OR_ERR_ARG = -1, OR_ERR_NONFINITE = -2,
+       OR_ERR_RANGE = -3, OR_ERR_BREAKDOWN = -5 };
+
+/* switch triggers recorded in reports */
+enum { OR_TRIG_NONE = 0, OR_TRIG_C1 = 1, OR_TRIG_C2 = 2, OR_TRIG_C3 = 3,
+       OR_TRIG_FLOOR = 4, OR_TRIG_TOL = 5, OR_TRIG_BREAKDOWN = 6 };
+
+typedef struct {
+    double tol;          /* relative residual target ||r||/||b|| */
+    int32_t max_iter;    /* CG iteration cap; GMRES: restart*max_restarts */
+    int32_t restart;     /* GMRES cycle length */
+    int32_t max_restarts;
+    int32_t start_segments;  /* 1..3 */
+    int32_t fixed_segments;  /* 0: stepped, 1..3: fixed; -1: plain FP64 CSR */
+    int32_t l, t, m;         /* controller schedule (Section III-D) */
+    double rsd_limit;
+    int32_t ndec_limit;
+    double reldec_limit;
+    int32_t ndec_rule;       /* 0: compare nDec with ndec_limit, 1: with t/2 */
+    double floor_c;          /* switch once relres <= floor_c*eta_s (0: off) */
+    int32_t switch_mode;     /* CG: 0 restart p=r, 1 keep p */
+    int32_t orth;            /* GMRES: 0 MGS, 1 CGS2 */
+} or_params;
+
+typedef struct {
+    int32_t status;
+    int32_t iters;
+    int32_t iters_per_seg[3];
+    int32_t switch_iter[2];
+    int32_t switch_trigger[2];
+    double relres_recursive;
+    double relres_true;
+} or_report;
+
+/* ---- format ---- */
+int64_t or_exponent_histogram(const double* val, int64_t nnz, uint32_t* hist2048);
+int or_select_shared_exponents(const uint32_t* hist2048, int num_exp, int16_t* sem8);
+int or_encode_values(const double* val, const int32_t* col, int64_t nnz,
+                     const int16_t* sem8, uint32_t* col_idx, uint16_t* head,
+                     uint16_t* tail1, uint32_t* tail2);
+int or_encode(const int32_t* row_ptr, const int32_t* col, const double* val,
+              int32_t n_rows, int32_t n_cols, int64_t nnz, int num_exp,
+              const int16_t* sem_in, int16_t* sem_out, uint32_t* col_idx,
+              uint16_t* head, uint16_t* tail1, uint32_t* tail2, double* eta3,
+              double* exact_frac);
+double or_decode_one(uint32_t col_word, uint16_t head, uint16_t tail1,
+                     uint32_t tail2, const int16_t* sem8, int s);
+void or_decode(const uint32_t* col_idx, const uint16_t* head, const uint16_t* tail1,
+               const uint32_t* tail2, int64_t nnz, const int16_t* sem8, int s,
+               double* out);
+
+/* ---- SpMV ---- */
+void or_csr_spmv(int32_t n_rows, const int32_t* row_ptr, const int32_t* col,
+                 const double* val, const double* x, double* y);
+void or_gse_spmv(int32_t n_rows, const int32_t* row_ptr, const uint32_t* col_idx,
+                 const uint16_t* head, const uint16_t* tail1, const uint32_t* tail2,
+                 const int16_t* sem8, int s, const double* x, double* y);
+void or_gse_spmv_rows(const int32_t* rows, int32_t n_sel, const int32_t* row_ptr,
+                      const uint32_t* col_idx, const uint16_t* head,
+                      const uint16_t* tail1, const uint32_t* tail2,
+                      const int16_t* sem8, int s, const double* x, double* y_sel);
+
+/* ---- controller (Section III-D, Eqs. 3-6, Conditions 1-3) ---- */
+void or_window_metrics(const double* resid, int32_t j, int32_t t,
+                       double* rsd, int32_t* ndec, double* reldec);
+int or_precision_trigger(const double* resid, int32_t j, const or_params* p);
+
+/* ---- solvers ----
+ * The matrix is either plain FP64 CSR (fixed_segments == -1: col/val used) or
+ * GSE planes (col_idx/head/tail1/tail2/sem8 used).  x holds x0 on entry.
+ * hist (optional, may be NULL) receives relres per iteration, [max_iter+1];
+ * seg_hist (optional) the segment count used by each iteration.           */
+typedef struct {
+    int32_t n_rows;
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const double* val;
+    const uint32_t* col_idx;
+    const uint16_t* head;
+    const uint16_t* tail1;
+    const uint32_t* tail2;
+    const int16_t* sem8;
+    const double* eta3;
+} or_matrix;
+
+int or_cg(const or_matrix* A, const double* b, double* x, const or_params* p,
+          or_report* rep, double* hist, int32_t* seg_hist);
+int or_gmres(const or_matrix* A, const double* b, double* x, const or_params* p,
+             or_report* rep, double* hist, int32_t* seg_hist);
+
+#endif
