@@ -1,0 +1,246 @@
+/*
+ * gse.h -- C ABI of libgse: sparse matrices in the group-shared-exponent,
+ * segmented-mantissa format (GSE-SEM) on AMD Instinct MI355X (gfx950), and
+ * the stepped mixed-precision CG / GMRES solvers built on them.
+ *
+ * The paper: "Precision-Aware Iterative Algorithms Based on Group-Shared
+ * Exponents of Floating-Point Numbers" (arXiv 2411.04686).
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns a gse_status; nothing throws, exits or prints.  On an
+ *     error, gse_last_error() returns a thread-local message.
+ *   - All arguments are validated on the host before anything is launched.
+ *     A failing HIP call maps to GSE_ERR_HIP (its text in gse_last_error()).
+ *   - Device pointers are plain device addresses (hipMalloc or a framework
+ *     allocator); the library does not take ownership of any of them and
+ *     never allocates device memory: scratch comes from a caller workspace.
+ *   - `stream` is a hipStream_t passed as void* (NULL: the null stream).
+ *     gse_spmv is asynchronous on it; gse_encode, gse_plan, gse_cg and
+ *     gse_gmres synchronize it before returning.
+ *   - Matrices are CSR with int32 row pointers (ascending, row_ptr[0] == 0),
+ *     int32 column indices and FP64 values; the number of non-zeros must be
+ *     below 2^31 - 2^16 and the number of columns at most 2^29 (the top three
+ *     bits of each column word hold the shared-exponent slot).
+ *   - "Planes" are per-non-zero arrays.  They must hold gse_pad(nnz) entries
+ *     (nnz rounded up to a multiple of 16) and start on a 16-byte boundary;
+ *     entries past nnz are never interpreted (the kernels load them as part of
+ *     aligned vectors and mask them).
+ */
+#ifndef GSE_H
+#define GSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gse_status;
+#define GSE_OK 0
+#define GSE_PENDING 1           /* serving: ticket not finished yet */
+#define GSE_NOT_CONVERGED 2     /* solve stopped at its cap; report filled */
+#define GSE_ERR_ARG (-1)        /* invalid argument (NULL, size, alignment) */
+#define GSE_ERR_NONFINITE (-2)  /* Inf/NaN among the matrix values */
+#define GSE_ERR_RANGE (-3)      /* size limits, or a value the table cannot hold */
+#define GSE_ERR_NOMEM (-4)      /* workspace / arena too small */
+#define GSE_ERR_BREAKDOWN (-5)  /* CG p.Ap <= 0 or non-finite with all segments */
+#define GSE_ERR_HIP (-6)        /* a HIP runtime call failed */
+#define GSE_ERR_TICKET (-7)     /* serving: unknown ticket */
+
+#define GSE_MAX_EXP 8           /* shared exponents per matrix (3-bit index) */
+
+/* Number of entries a plane must hold for `nnz` non-zeros. */
+int64_t gse_pad(int64_t nnz);
+
+/* ------------------------------------------------------------------------
+ * Encoded matrix.  Section III-B (format), Section III-B.3 and Fig. 3
+ * (segmented storage), Section III-C.1 (slot index in the column word).
+ *
+ * Each non-zero v is stored as a 64-bit word  sign<<63 | F  where
+ * F = floor(|v| * 2^(1086 - SEM[slot])) is its magnitude on the fixed-point
+ * grid of its slot (the hidden one explicit, truncation toward zero), and
+ * SEM[slot] = e_slot + 1 is the shared exponent stored incremented.  The
+ * word is split into three planes:
+ *   head  = bits 63..48 (sign and 15 magnitude bits),
+ *   tail1 = bits 47..32,
+ *   tail2 = bits 31..0,
+ * and the column word is  col | slot << 29.  Reading s planes gives the value
+ * +-(F >> (63 - W_s)) * 2^(SEM - 1023 - W_s), W_s = 15, 31, 63.
+ *
+ * Caller-owned device buffers (set the pointers before gse_encode):
+ *   col_idx, head, tail1, tail2 : gse_pad(nnz) entries each, 16-byte aligned;
+ *   tile_row                    : tile_cap int32 entries, at least
+ *                                 gse_tile_entries(nnz) (the SpMV schedule).
+ * row_ptr is recorded by gse_encode and must stay valid while A is used.
+ * Host fields (sem, eta, exact_frac, tile_*) are written by the library.
+ */
+typedef struct gse_matrix {
+    int32_t n_rows;
+    int32_t n_cols;
+    int64_t nnz;
+    int32_t num_exp;           /* k, 1..8 (Section IV-B picks 8) */
+    int32_t num_used;          /* slots actually populated */
+    int16_t sem[GSE_MAX_EXP];  /* shared exponents, biased + 1; 0 = unused */
+    const int32_t* row_ptr;    /* device [n_rows + 1] */
+    uint32_t* col_idx;         /* device plane */
+    uint16_t* head;            /* device plane */
+    uint16_t* tail1;           /* device plane */
+    uint32_t* tail2;           /* device plane */
+    int32_t* tile_row;         /* device [tile_cap] */
+    int32_t tile_cap;
+    int32_t tile_nnz;          /* non-zeros per SpMV tile (set by gse_plan) */
+    int32_t n_tiles;
+    double eta[3];             /* ||A - A_s||_inf / ||A||_inf, s = 1, 2, 3 */
+    double exact_frac;         /* share of non-zeros whose exponent is shared */
+} gse_matrix;
+
+/* Plain FP64 CSR operand for the baseline operators on the same schedule.
+ * col and val must hold gse_pad(nnz) entries and be 16-byte aligned. */
+typedef struct gse_csr {
+    int32_t n_rows;
+    int32_t n_cols;
+    int64_t nnz;
+    const int32_t* row_ptr;    /* device [n_rows + 1] */
+    const int32_t* col;        /* device [gse_pad(nnz)] */
+    const double* val;         /* device [gse_pad(nnz)] */
+    int32_t* tile_row;         /* device [tile_cap] */
+    int32_t tile_cap;
+    int32_t tile_nnz;
+    int32_t n_tiles;
+} gse_csr;
+
+/* Entries tile_row needs for any tile size the library may choose. */
+int32_t gse_tile_entries(int64_t nnz);
+
+/* Device workspace gse_encode needs (bytes).  n_rows and nnz as in CSR. */
+gse_status gse_encode_workspace(int64_t nnz, int32_t n_rows, size_t* ws_bytes);
+
+/* Convert a device FP64 CSR matrix into GSE-SEM planes.
+ * Section III-B.1 (shared-exponent extraction: exponent histogram, the k
+ * most frequent), Section III-B.2 (table stored +1; the maximum exponent is
+ * forced into the last slot if the k most frequent miss it), Algorithm 1
+ * (per-value slot search, denormalised mantissa) in its 64-bit form.
+ *   row_ptr, col, val : device CSR (col/val: nnz entries, no padding needed).
+ *   num_exp           : k in 1..8.
+ *   sem_in            : host array of num_exp shared exponents (biased + 1)
+ *                       to reuse a table (Section III-B.1); NULL computes it.
+ *                       A reused table that leaves a value without a larger
+ *                       shared exponent gives GSE_ERR_RANGE.
+ *   A                 : in: plane pointers and tile_row/tile_cap; out: every
+ *                       other field; the SpMV schedule is built with the
+ *                       default tile size.
+ *   ws, ws_bytes      : device workspace of gse_encode_workspace() bytes.
+ * Errors: GSE_ERR_NONFINITE (Inf/NaN value), GSE_ERR_RANGE (sizes, a shared
+ * exponent below 63 whose grid would leave the normal range, uncovered
+ * value), GSE_ERR_ARG, GSE_ERR_NOMEM, GSE_ERR_HIP.  On error the planes are
+ * unspecified.  Synchronizes `stream`. */
+gse_status gse_encode(const int32_t* row_ptr, const int32_t* col, const double* val,
+                      int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t num_exp,
+                      const int16_t* sem_in, gse_matrix* A, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* (Re)build the SpMV tile schedule for tile_nnz non-zeros per tile
+ * (1024, 2048 or 4096).  Synchronizes `stream`. */
+gse_status gse_plan(gse_matrix* A, int32_t tile_nnz, void* stream);
+gse_status gse_csr_plan(gse_csr* M, int32_t tile_nnz, void* stream);
+
+/* y = A_s x with s = k_segments in {1, 2, 3}: the head-only operator of
+ * Algorithm 2 and its head+tail1 and head+tail1+tail2 variants
+ * (Section III-C.2).  Values are read with s planes and multiplied and
+ * accumulated in FP64 (Section III-C.2).  x: device [n_cols], y: device
+ * [n_rows]; x and y must not overlap.  Asynchronous on `stream`. */
+gse_status gse_spmv(const gse_matrix* A, int32_t k_segments, const double* x, double* y,
+                    void* stream);
+
+/* Baseline: y = A x with plain FP64 CSR values on the same tile schedule
+ * (the FP64-SpMV the paper compares against, Section IV-A). */
+gse_status gse_csr_spmv(const gse_csr* M, const double* x, double* y, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Solvers for A x = b (Section I), stepped mixed precision per Section III-D
+ * (Algorithm 3, Eqs. 3-6, Conditions 1-3).  Only the operator reads reduced
+ * segments; dot products, residuals and the x / r / p updates are FP64
+ * (Section IV-D.3). */
+#define GSE_CG 0
+#define GSE_GMRES 1
+
+#define GSE_TRIG_NONE 0
+#define GSE_TRIG_C1 1         /* Condition 1 */
+#define GSE_TRIG_C2 2         /* Condition 2 */
+#define GSE_TRIG_C3 3         /* Condition 3 */
+#define GSE_TRIG_FLOOR 4      /* relres <= floor_c * eta_s (addition) */
+#define GSE_TRIG_TOL 5        /* tolerance met with an inexact operator */
+#define GSE_TRIG_BREAKDOWN 6  /* CG breakdown below three segments */
+
+typedef struct gse_params {
+    double tol;               /* relative residual ||b - A x|| / ||b|| */
+    int32_t max_iter;         /* iteration cap (CG 5000, GMRES 30*500 in IV-A) */
+    int32_t restart;          /* GMRES cycle length (30 in IV-A) */
+    int32_t start_segments;   /* first s (1 per Algorithm 3) */
+    int32_t fixed_segments;   /* 0: stepped; 1..3: fixed s */
+    int32_t l, t, m;          /* controller schedule (Section III-D) */
+    double rsd_limit;         /* Condition 1 threshold */
+    int32_t ndec_limit;       /* nDec threshold for Conditions 1-2 */
+    double reldec_limit;      /* Condition 2 threshold */
+    int32_t ndec_rule;        /* 0: compare nDec with ndec_limit; 1: with t/2 */
+    double floor_c;           /* floor trigger factor, 0 disables */
+    int32_t switch_mode;      /* CG after a switch: 0 p = r, 1 keep p */
+    int32_t record_history;   /* 1: fill gse_solve_history() buffers */
+} gse_params;
+
+typedef struct gse_report {
+    gse_status status;
+    int32_t iters;
+    int32_t iters_per_seg[3];
+    int32_t switch_iter[2];       /* -1: no switch */
+    int32_t switch_trigger[2];    /* GSE_TRIG_* */
+    double relres_recursive;      /* the solver's own residual estimate */
+    double relres_true;           /* ||b - A_3 x|| / ||b|| recomputed at the end */
+    double time_ms;               /* wall time of the call */
+} gse_report;
+
+/* Fill `p` with the paper's CG (method GSE_CG) or GMRES presets
+ * (Section IV-D.1) and tol = 1e-10, floor_c = 10, restart 30. */
+gse_status gse_default_params(int32_t method, gse_params* p);
+
+/* Workspace bytes for a solve of an n_rows x n_rows system with up to
+ * n_tiles SpMV tiles (gse_tile_entries(nnz)). */
+gse_status gse_solver_workspace(int32_t method, int32_t n_rows, int64_t nnz, int32_t restart,
+                                int32_t max_iter, size_t* ws_bytes);
+
+/* Stepped (or fixed-segment) CG.  b: device [n], x: device [n], x0 on
+ * entry, solution on return.  Blocks until the solve ends.  Returns
+ * GSE_OK, GSE_NOT_CONVERGED, GSE_ERR_BREAKDOWN or an error. */
+gse_status gse_cg(const gse_matrix* A, const double* b, double* x, const gse_params* p,
+                  gse_report* rep, void* ws, size_t ws_bytes, void* stream);
+
+/* Stepped (or fixed-segment) restarted GMRES(p->restart), classical
+ * Gram-Schmidt applied twice, Givens rotations on the device. */
+gse_status gse_gmres(const gse_matrix* A, const double* b, double* x, const gse_params* p,
+                     gse_report* rep, void* ws, size_t ws_bytes, void* stream);
+
+/* Baselines: the same solvers with plain FP64 CSR values. */
+gse_status gse_csr_cg(const gse_csr* M, const double* b, double* x, const gse_params* p,
+                      gse_report* rep, void* ws, size_t ws_bytes, void* stream);
+gse_status gse_csr_gmres(const gse_csr* M, const double* b, double* x, const gse_params* p,
+                         gse_report* rep, void* ws, size_t ws_bytes, void* stream);
+
+/* Copy the residual history of the last solve that ran with record_history
+ * on `ws`: relres[i] and the segment count of iteration i, i = 0..iters.
+ * hist / seg: host arrays of at least cap entries.  Synchronizes. */
+gse_status gse_solve_history(const void* ws, int32_t cap, double* hist, int32_t* seg,
+                             void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostic: dst = src, `bytes` a multiple of 16, both 16-byte aligned;
+ * the reference streaming kernel for HBM bandwidth and counter scaling. */
+gse_status gse_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
+
+const char* gse_status_str(gse_status s);
+const char* gse_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSE_H */

@@ -1,0 +1,245 @@
+// api.hip -- the extern "C" entry points of libgse: host-side validation,
+// status mapping and the host part of encode / plan / SpMV.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "gse_internal.h"
+
+namespace gse {
+
+thread_local char g_err[512] = "";
+
+gse_status fail(gse_status code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+gse_status hip_fail(hipError_t e, const char* where) {
+  return fail(GSE_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int64_t pad_nnz(int64_t nnz) { return (nnz + kPadTo - 1) / kPadTo * kPadTo; }
+
+bool valid_tile(int32_t t) { return t == kWG * 4 || t == kWG * 8 || t == kWG * 16; }
+
+SpmvOperand operand_of(const gse_matrix* A) {
+  SpmvOperand o{};
+  o.row_ptr = A->row_ptr;
+  o.tile_row = A->tile_row;
+  o.col = A->col_idx;
+  o.head = A->head;
+  o.tail1 = A->tail1;
+  o.tail2 = A->tail2;
+  o.val = nullptr;
+  o.n_rows = A->n_rows;
+  o.n_tiles = A->n_tiles;
+  o.tile_nnz = A->tile_nnz;
+  o.nnz = (int32_t)A->nnz;
+  for (int i = 0; i < GSE_MAX_EXP; ++i) o.sem[i] = A->sem[i];
+  return o;
+}
+
+SpmvOperand operand_of(const gse_csr* M) {
+  SpmvOperand o{};
+  o.row_ptr = M->row_ptr;
+  o.tile_row = M->tile_row;
+  o.col = reinterpret_cast<const uint32_t*>(M->col);
+  o.head = nullptr;
+  o.tail1 = nullptr;
+  o.tail2 = nullptr;
+  o.val = M->val;
+  o.n_rows = M->n_rows;
+  o.n_tiles = M->n_tiles;
+  o.tile_nnz = M->tile_nnz;
+  o.nnz = (int32_t)M->nnz;
+  for (int i = 0; i < GSE_MAX_EXP; ++i) o.sem[i] = 0;
+  return o;
+}
+
+gse_status check_matrix(const gse_matrix* A) {
+  if (!A) return fail(GSE_ERR_ARG, "matrix is NULL");
+  if (!A->row_ptr || !A->col_idx || !A->head || !A->tail1 || !A->tail2 || !A->tile_row)
+    return fail(GSE_ERR_ARG, "matrix has a NULL device buffer");
+  if (A->n_rows < 0 || A->n_cols < 0 || A->nnz < 0) return fail(GSE_ERR_ARG, "negative size");
+  if (A->nnz > kMaxNnz) return fail(GSE_ERR_RANGE, "nnz %lld exceeds the limit", (long long)A->nnz);
+  if (!valid_tile(A->tile_nnz) || A->n_tiles != n_tiles_for(A->nnz, A->tile_nnz) ||
+      A->tile_cap < A->n_tiles + 1)
+    return fail(GSE_ERR_ARG, "matrix has no valid SpMV schedule (call gse_encode / gse_plan)");
+  return GSE_OK;
+}
+
+gse_status check_csr(const gse_csr* M) {
+  if (!M) return fail(GSE_ERR_ARG, "matrix is NULL");
+  if (!M->row_ptr || !M->col || !M->val || !M->tile_row)
+    return fail(GSE_ERR_ARG, "matrix has a NULL device buffer");
+  if (M->n_rows < 0 || M->n_cols < 0 || M->nnz < 0) return fail(GSE_ERR_ARG, "negative size");
+  if (M->nnz > kMaxNnz) return fail(GSE_ERR_RANGE, "nnz exceeds the limit");
+  if (!aligned16(M->col) || !aligned16(M->val))
+    return fail(GSE_ERR_ARG, "col/val must be 16-byte aligned");
+  if (!valid_tile(M->tile_nnz) || M->n_tiles != n_tiles_for(M->nnz, M->tile_nnz) ||
+      M->tile_cap < M->n_tiles + 1)
+    return fail(GSE_ERR_ARG, "matrix has no valid SpMV schedule (call gse_csr_plan)");
+  return GSE_OK;
+}
+
+}  // namespace gse
+
+using namespace gse;
+
+extern "C" {
+
+int64_t gse_pad(int64_t nnz) { return nnz < 0 ? 0 : pad_nnz(nnz); }
+
+int32_t gse_tile_entries(int64_t nnz) { return n_tiles_for(nnz < 0 ? 0 : nnz, kMinTile) + 2; }
+
+const char* gse_last_error(void) { return g_err; }
+
+const char* gse_status_str(gse_status s) {
+  switch (s) {
+    case GSE_OK: return "ok";
+    case GSE_PENDING: return "pending";
+    case GSE_NOT_CONVERGED: return "not converged";
+    case GSE_ERR_ARG: return "invalid argument";
+    case GSE_ERR_NONFINITE: return "non-finite value";
+    case GSE_ERR_RANGE: return "out of range";
+    case GSE_ERR_NOMEM: return "workspace too small";
+    case GSE_ERR_BREAKDOWN: return "breakdown";
+    case GSE_ERR_HIP: return "HIP error";
+    case GSE_ERR_TICKET: return "unknown ticket";
+    default: return "unknown status";
+  }
+}
+
+gse_status gse_encode_workspace(int64_t nnz, int32_t n_rows, size_t* ws_bytes) {
+  if (!ws_bytes || nnz < 0 || n_rows < 0) return fail(GSE_ERR_ARG, "bad arguments");
+  *ws_bytes = (sizeof(EncodeScratch) + 255) / 256 * 256;
+  return GSE_OK;
+}
+
+gse_status gse_plan(gse_matrix* A, int32_t tile_nnz, void* stream) {
+  if (!A || !A->row_ptr || !A->tile_row) return fail(GSE_ERR_ARG, "bad matrix");
+  if (!valid_tile(tile_nnz)) return fail(GSE_ERR_ARG, "tile_nnz %d not supported", tile_nnz);
+  const int32_t nt = n_tiles_for(A->nnz, tile_nnz);
+  if (A->tile_cap < nt + 1) return fail(GSE_ERR_NOMEM, "tile_row holds %d < %d", A->tile_cap, nt + 1);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_plan(A->row_ptr, A->n_rows, (int32_t)A->nnz, tile_nnz, nt, A->tile_row, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "gse_plan");
+  A->tile_nnz = tile_nnz;
+  A->n_tiles = nt;
+  return GSE_OK;
+}
+
+gse_status gse_csr_plan(gse_csr* M, int32_t tile_nnz, void* stream) {
+  if (!M || !M->row_ptr || !M->tile_row) return fail(GSE_ERR_ARG, "bad matrix");
+  if (!valid_tile(tile_nnz)) return fail(GSE_ERR_ARG, "tile_nnz %d not supported", tile_nnz);
+  if (M->nnz < 0 || M->nnz > kMaxNnz) return fail(GSE_ERR_RANGE, "nnz out of range");
+  const int32_t nt = n_tiles_for(M->nnz, tile_nnz);
+  if (M->tile_cap < nt + 1) return fail(GSE_ERR_NOMEM, "tile_row holds %d < %d", M->tile_cap, nt + 1);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_plan(M->row_ptr, M->n_rows, (int32_t)M->nnz, tile_nnz, nt, M->tile_row, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "gse_csr_plan");
+  M->tile_nnz = tile_nnz;
+  M->n_tiles = nt;
+  return GSE_OK;
+}
+
+gse_status gse_encode(const int32_t* row_ptr, const int32_t* col, const double* val, int32_t n_rows,
+                      int32_t n_cols, int64_t nnz, int32_t num_exp, const int16_t* sem_in,
+                      gse_matrix* A, void* ws, size_t ws_bytes, void* stream) {
+  if (!A) return fail(GSE_ERR_ARG, "matrix is NULL");
+  if (!row_ptr || (nnz > 0 && (!col || !val))) return fail(GSE_ERR_ARG, "NULL CSR array");
+  if (n_rows < 0 || n_cols < 0 || nnz < 0) return fail(GSE_ERR_ARG, "negative size");
+  if (num_exp < 1 || num_exp > GSE_MAX_EXP) return fail(GSE_ERR_ARG, "num_exp must be 1..8");
+  if (nnz > kMaxNnz) return fail(GSE_ERR_RANGE, "nnz %lld exceeds the limit", (long long)nnz);
+  if ((int64_t)n_cols > (int64_t(1) << 29)) return fail(GSE_ERR_RANGE, "n_cols exceeds 2^29");
+  if (!A->col_idx || !A->head || !A->tail1 || !A->tail2 || !A->tile_row)
+    return fail(GSE_ERR_ARG, "matrix planes / tile_row not set");
+  if (!aligned16(A->col_idx) || !aligned16(A->head) || !aligned16(A->tail1) || !aligned16(A->tail2))
+    return fail(GSE_ERR_ARG, "planes must be 16-byte aligned");
+  if (A->tile_cap < gse_tile_entries(nnz))
+    return fail(GSE_ERR_NOMEM, "tile_row holds %d < %d entries", A->tile_cap, gse_tile_entries(nnz));
+  size_t need = 0;
+  gse_encode_workspace(nnz, n_rows, &need);
+  if (!ws || ws_bytes < need) return fail(GSE_ERR_NOMEM, "encode workspace needs %zu bytes", need);
+  if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(GSE_ERR_ARG, "workspace must be 256-byte aligned");
+  if (sem_in) {
+    for (int i = 0; i < num_exp; ++i) {
+      if (sem_in[i] < 64 || sem_in[i] > 2047)
+        return fail(GSE_ERR_RANGE, "shared exponent %d out of range", (int)sem_in[i]);
+      for (int k = 0; k < i; ++k)
+        if (sem_in[k] == sem_in[i]) return fail(GSE_ERR_ARG, "duplicate shared exponent");
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  EncodeScratch* sc = reinterpret_cast<EncodeScratch*>(ws);
+  A->n_rows = n_rows;
+  A->n_cols = n_cols;
+  A->nnz = nnz;
+  A->num_exp = num_exp;
+  A->row_ptr = row_ptr;
+  hipError_t e = launch_encode(row_ptr, col, val, n_rows, (int32_t)nnz, num_exp, sem_in, A, sc, st);
+  if (e != hipSuccess) return hip_fail(e, "gse_encode launch");
+  const int32_t nt = n_tiles_for(nnz, kDefaultTile);
+  e = launch_plan(row_ptr, n_rows, (int32_t)nnz, kDefaultTile, nt, A->tile_row, st);
+  if (e != hipSuccess) return hip_fail(e, "gse_encode plan");
+  EncodeScratch h;
+  e = hipMemcpyAsync(&h, sc, sizeof h, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "gse_encode");
+  A->tile_nnz = kDefaultTile;
+  A->n_tiles = nt;
+  for (int i = 0; i < GSE_MAX_EXP; ++i) A->sem[i] = h.sem[i];
+  A->num_used = h.used;
+  A->exact_frac = nnz ? (double)h.covered / (double)nnz : 1.0;
+  double nrm[4];
+  for (int i = 0; i < 4; ++i) memcpy(&nrm[i], &h.norm_bits[i], sizeof(double));
+  for (int s = 0; s < 3; ++s) A->eta[s] = nrm[0] > 0.0 ? nrm[s + 1] / nrm[0] : 0.0;
+  if (h.nonfinite) return fail(GSE_ERR_NONFINITE, "%d non-finite values", h.nonfinite);
+  if (h.range_err & 1) return fail(GSE_ERR_RANGE, "a shared exponent is below 63");
+  if (h.range_err & 2) return fail(GSE_ERR_RANGE, "a value has no larger shared exponent in the table");
+  return GSE_OK;
+}
+
+gse_status gse_spmv(const gse_matrix* A, int32_t k_segments, const double* x, double* y, void* stream) {
+  gse_status s = check_matrix(A);
+  if (s != GSE_OK) return s;
+  if (k_segments < 1 || k_segments > 3) return fail(GSE_ERR_ARG, "k_segments must be 1..3");
+  if ((A->n_cols > 0 && !x) || (A->n_rows > 0 && !y)) return fail(GSE_ERR_ARG, "NULL vector");
+  if (A->n_rows == 0) return GSE_OK;
+  SpmvEpilogue ep{};
+  ep.epi = kEpiPlain;
+  hipError_t e = launch_spmv(k_segments, operand_of(A), x, y, ep, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "gse_spmv");
+  return GSE_OK;
+}
+
+gse_status gse_csr_spmv(const gse_csr* M, const double* x, double* y, void* stream) {
+  gse_status s = check_csr(M);
+  if (s != GSE_OK) return s;
+  if ((M->n_cols > 0 && !x) || (M->n_rows > 0 && !y)) return fail(GSE_ERR_ARG, "NULL vector");
+  if (M->n_rows == 0) return GSE_OK;
+  SpmvEpilogue ep{};
+  ep.epi = kEpiPlain;
+  hipError_t e = launch_spmv(kCsr64, operand_of(M), x, y, ep, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "gse_csr_spmv");
+  return GSE_OK;
+}
+
+gse_status gse_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  if (!src || !dst || (bytes & 15u) || !aligned16(src) || !aligned16(dst))
+    return fail(GSE_ERR_ARG, "copy needs 16-byte aligned buffers and a multiple of 16 bytes");
+  if (bytes == 0) return GSE_OK;
+  hipError_t e = launch_stream_copy(src, dst, bytes, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "gse_stream_copy");
+  return GSE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,278 @@
+// encode.hip -- FP64 CSR -> GSE-SEM planes on gfx950.
+//
+//   k_hist   exponent histogram (Section III-B.1: occurrences of each
+//            distinct exponent), LDS-privatised, 2048 bins; bin 2047 flags
+//            Inf/NaN.
+//   k_topk   one workgroup: the k most frequent exponents (count descending,
+//            larger exponent first on ties), the maximum exponent forced into
+//            the last slot when missing (Section III-B.2), stored +1.
+//   k_encode per value: slot of the smallest shared exponent above the value's
+//            own (an exact match when SEM = e + 1), magnitude on that slot's
+//            63-bit fixed-point grid (Algorithm 1, denormalised by minDiff,
+//            truncated), written to the four planes with 16-byte stores.
+//   k_eta    per row: sums of |a| and |a - a_s| for s = 1, 2, 3; the row
+//            maxima give eta_s = ||A - A_s||_inf / ||A||_inf.
+#include "gse_internal.h"
+
+namespace gse {
+namespace {
+
+struct SemIn {
+  int16_t sem[GSE_MAX_EXP];
+  int32_t have;
+};
+
+__global__ __launch_bounds__(256) void k_hist(const double* __restrict__ val, int nnz,
+                                              EncodeScratch* sc) {
+  __shared__ uint32_t h[2048];
+  for (int i = threadIdx.x; i < 2048; i += blockDim.x) h[i] = 0u;
+  __syncthreads();
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += stride) {
+    const uint64_t u = double_to_bits(val[i]);
+    atomicAdd(&h[(u >> 52) & 0x7FFu], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2048; i += blockDim.x)
+    if (h[i]) atomicAdd(&sc->hist[i], h[i]);
+}
+
+__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v,
+                                                            unsigned long long* red) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const unsigned long long o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  unsigned long long m = red[0];
+  for (int i = 1; i < kWaves; ++i) m = red[i] > m ? red[i] : m;
+  return m;
+}
+
+__global__ __launch_bounds__(256) void k_topk(EncodeScratch* sc, int num_exp, SemIn in) {
+  __shared__ uint32_t h[2048];
+  __shared__ unsigned char taken[2048];
+  __shared__ unsigned long long red[kWaves];
+  __shared__ int chosen[GSE_MAX_EXP];
+  for (int i = threadIdx.x; i < 2048; i += blockDim.x) {
+    h[i] = sc->hist[i];
+    taken[i] = 0;
+  }
+  __syncthreads();
+  if (in.have) {
+    if (threadIdx.x == 0) {
+      int used = 0;
+      unsigned long long cov = 0;
+      for (int i = 0; i < GSE_MAX_EXP; ++i) {
+        sc->sem[i] = in.sem[i];
+        if (in.sem[i] > 0) {
+          ++used;
+          cov += h[in.sem[i] - 1];
+        }
+      }
+      sc->used = used;
+      sc->covered = cov;
+      sc->nonfinite = (int)h[2047];
+    }
+    return;
+  }
+  int used = 0;
+  for (int slot = 0; slot < num_exp; ++slot) {
+    unsigned long long best = 0;
+    for (int e = 1 + threadIdx.x; e <= 2046; e += blockDim.x) {
+      if (!taken[e] && h[e] > 0) {
+        const unsigned long long key = ((unsigned long long)h[e] << 11) | (unsigned long long)e;
+        best = key > best ? key : best;
+      }
+    }
+    best = block_max_u64(best, red);
+    if (best == 0) break;
+    const int e = (int)(best & 0x7FFu);
+    if (threadIdx.x == 0) {
+      taken[e] = 1;
+      chosen[used] = e;
+    }
+    ++used;
+    __syncthreads();
+  }
+  unsigned long long me = 0;
+  for (int e = 1 + threadIdx.x; e <= 2046; e += blockDim.x)
+    if (h[e] > 0) me = (unsigned long long)e > me ? (unsigned long long)e : me;
+  const int max_e = (int)block_max_u64(me, red);
+  if (threadIdx.x == 0) {
+    if (used == 0) {
+      chosen[0] = 1023;
+      used = 1;
+    } else if (!taken[max_e]) {
+      chosen[used - 1] = max_e;
+    }
+    int range_err = 0;
+    unsigned long long cov = 0;
+    for (int i = 0; i < GSE_MAX_EXP; ++i) sc->sem[i] = 0;
+    for (int i = 0; i < used; ++i) {
+      if (chosen[i] < 63) range_err = 1;
+      sc->sem[i] = (int16_t)(chosen[i] + 1);
+      cov += h[chosen[i]];
+    }
+    sc->used = used;
+    sc->covered = cov;
+    sc->range_err = range_err;
+    sc->nonfinite = (int)h[2047];
+  }
+}
+
+// Groups of 8 values per thread; writes 32 + 16 + 16 + 32 bytes per group
+// (the planes are padded, so the tail group writes zeros past nnz).
+__global__ __launch_bounds__(256) void k_encode(const double* __restrict__ val,
+                                                const int32_t* __restrict__ col, int nnz,
+                                                EncodeScratch* sc, uint32_t* __restrict__ col_idx,
+                                                uint16_t* __restrict__ head,
+                                                uint16_t* __restrict__ tail1,
+                                                uint32_t* __restrict__ tail2) {
+  __shared__ int sem_s[GSE_MAX_EXP];
+  if (threadIdx.x < GSE_MAX_EXP) sem_s[threadIdx.x] = sc->sem[threadIdx.x];
+  __syncthreads();
+  int S[GSE_MAX_EXP];
+#pragma unroll
+  for (int k = 0; k < GSE_MAX_EXP; ++k) S[k] = sem_s[k];
+  const int n_groups = (nnz + 7) >> 3;
+  const int stride = gridDim.x * blockDim.x;
+  int bad = 0;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n_groups; g += stride) {
+    uint32_t cw[8], t2[8], hh[4], tt[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) hh[k] = tt[k] = 0u;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int j = g * 8 + k;
+      uint32_t c = 0, h16 = 0, t116 = 0, t232 = 0;
+      if (j < nnz) {
+        const uint64_t u = double_to_bits(val[j]);
+        const int e = (int)((u >> 52) & 0x7FFu);
+        int slot = -1, best = 1 << 30;
+#pragma unroll
+        for (int q = 0; q < GSE_MAX_EXP; ++q)
+          if (S[q] > e && S[q] < best) {
+            best = S[q];
+            slot = q;
+          }
+        uint64_t F = 0;
+        if (slot < 0) {
+          bad = 1;
+          slot = 0;
+        } else {
+          const uint64_t frac = u & ((uint64_t(1) << 52) - 1);
+          const uint64_t sig = e ? ((uint64_t(1) << 52) | frac) : frac;
+          const int sh = 11 - (best - (e ? e : 1));
+          F = (sh >= 0) ? (sig << sh) : ((-sh >= 64) ? 0 : (sig >> (-sh)));
+        }
+        c = (uint32_t)col[j] | ((uint32_t)slot << 29);
+        h16 = (uint32_t)((u >> 63) << 15) | (uint32_t)(F >> 48);
+        t116 = (uint32_t)((F >> 32) & 0xFFFFu);
+        t232 = (uint32_t)(F & 0xFFFFFFFFu);
+      }
+      cw[k] = c;
+      t2[k] = t232;
+      hh[k >> 1] |= h16 << ((k & 1) * 16);
+      tt[k >> 1] |= t116 << ((k & 1) * 16);
+    }
+    uint4* cp = reinterpret_cast<uint4*>(col_idx + g * 8);
+    cp[0] = make_uint4(cw[0], cw[1], cw[2], cw[3]);
+    cp[1] = make_uint4(cw[4], cw[5], cw[6], cw[7]);
+    *reinterpret_cast<uint4*>(head + g * 8) = make_uint4(hh[0], hh[1], hh[2], hh[3]);
+    *reinterpret_cast<uint4*>(tail1 + g * 8) = make_uint4(tt[0], tt[1], tt[2], tt[3]);
+    uint4* tp = reinterpret_cast<uint4*>(tail2 + g * 8);
+    tp[0] = make_uint4(t2[0], t2[1], t2[2], t2[3]);
+    tp[1] = make_uint4(t2[4], t2[5], t2[6], t2[7]);
+  }
+  if (bad) atomicOr(&sc->range_err, 2);
+}
+
+// Value read with s segments (exact; same decode as the SpMV operators).
+__device__ __forceinline__ double value_s(uint32_t c, uint32_t h, uint32_t t1, uint32_t t2,
+                                          const int* S, int s) {
+  const int W = (s == 1) ? 15 : (s == 2) ? 31 : 63;
+  const int sem = S[c >> 29];
+  const uint64_t F63 = ((uint64_t)(h & 0x7FFFu) << 48) | ((uint64_t)t1 << 32) | (uint64_t)t2;
+  const uint64_t F = F63 >> (63 - W);
+  const double sc = bits_to_double((uint64_t)(sem - W) << 52);
+  const double mag = (double)F * sc;  // F <= 53 significant bits: exact
+  return (h >> 15) ? -mag : mag;
+}
+
+// One wave per row; row maxima of the four sums go to norm_bits (as the
+// bit patterns of non-negative doubles, whose integer order is their order).
+__global__ __launch_bounds__(256) void k_eta(const int32_t* __restrict__ row_ptr, int n_rows,
+                                             const double* __restrict__ val,
+                                             const uint32_t* __restrict__ col_idx,
+                                             const uint16_t* __restrict__ head,
+                                             const uint16_t* __restrict__ tail1,
+                                             const uint32_t* __restrict__ tail2,
+                                             EncodeScratch* sc) {
+  __shared__ int sem_s[GSE_MAX_EXP];
+  if (threadIdx.x < GSE_MAX_EXP) sem_s[threadIdx.x] = sc->sem[threadIdx.x];
+  __syncthreads();
+  int S[GSE_MAX_EXP];
+#pragma unroll
+  for (int k = 0; k < GSE_MAX_EXP; ++k) S[k] = sem_s[k];
+  const int lane = threadIdx.x & 63;
+  const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nw = (gridDim.x * blockDim.x) >> 6;
+  double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+  for (int r = gw; r < n_rows; r += nw) {
+    double a = 0.0, e1 = 0.0, e2 = 0.0, e3 = 0.0;
+    for (int j = row_ptr[r] + lane; j < row_ptr[r + 1]; j += 64) {
+      const double v = val[j];
+      const uint32_t c = col_idx[j], h = head[j], t1 = tail1[j], t2 = tail2[j];
+      a += fabs(v);
+      e1 += fabs(v - value_s(c, h, t1, t2, S, 1));
+      e2 += fabs(v - value_s(c, h, t1, t2, S, 2));
+      e3 += fabs(v - value_s(c, h, t1, t2, S, 3));
+    }
+    a = wave_sum(a);
+    e1 = wave_sum(e1);
+    e2 = wave_sum(e2);
+    e3 = wave_sum(e3);
+    m0 = fmax(m0, a);
+    m1 = fmax(m1, e1);
+    m2 = fmax(m2, e2);
+    m3 = fmax(m3, e3);
+  }
+  if (lane == 0) {
+    atomicMax(&sc->norm_bits[0], (unsigned long long)double_to_bits(m0));
+    atomicMax(&sc->norm_bits[1], (unsigned long long)double_to_bits(m1));
+    atomicMax(&sc->norm_bits[2], (unsigned long long)double_to_bits(m2));
+    atomicMax(&sc->norm_bits[3], (unsigned long long)double_to_bits(m3));
+  }
+}
+
+}  // namespace
+
+hipError_t launch_encode(const int32_t* row_ptr, const int32_t* col, const double* val,
+                         int32_t n_rows, int32_t nnz, int32_t num_exp, const int16_t* sem_in,
+                         gse_matrix* A, EncodeScratch* sc, hipStream_t st) {
+  hipError_t e = hipMemsetAsync(sc, 0, sizeof(EncodeScratch), st);
+  if (e != hipSuccess) return e;
+  SemIn in{};
+  in.have = sem_in != nullptr;
+  for (int i = 0; i < GSE_MAX_EXP; ++i) in.sem[i] = (sem_in && i < num_exp) ? sem_in[i] : 0;
+  int hb = (nnz + 256 * 16 - 1) / (256 * 16);
+  hb = hb < 1 ? 1 : (hb > 2048 ? 2048 : hb);
+  hipLaunchKernelGGL(k_hist, dim3(hb), dim3(256), 0, st, val, nnz, sc);
+  hipLaunchKernelGGL(k_topk, dim3(1), dim3(256), 0, st, sc, num_exp, in);
+  const int groups = (nnz + 7) / 8;
+  int eb = (groups + 255) / 256;
+  eb = eb < 1 ? 1 : (eb > 16384 ? 16384 : eb);
+  hipLaunchKernelGGL(k_encode, dim3(eb), dim3(256), 0, st, val, col, nnz, sc, A->col_idx, A->head,
+                     A->tail1, A->tail2);
+  int rbk = (n_rows + 3) / 4;
+  rbk = rbk < 1 ? 1 : (rbk > 16384 ? 16384 : rbk);
+  hipLaunchKernelGGL(k_eta, dim3(rbk), dim3(256), 0, st, row_ptr, n_rows, val, A->col_idx, A->head,
+                     A->tail1, A->tail2, sc);
+  return hipGetLastError();
+}
+
+}  // namespace gse

@@ -1,0 +1,138 @@
+// gse_internal.h -- device helpers and launcher declarations shared by the
+// translation units of libgse (never installed; the public ABI is gse.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gse.h"
+
+namespace gse {
+
+constexpr int kWG = 256;            // threads per workgroup (4 wave64)
+constexpr int kWaves = kWG / 64;
+constexpr int kMinTile = 1024;      // smallest tile_nnz the schedule may use
+constexpr int kDefaultTile = 2048;
+constexpr int kExtra = 256;         // look-ahead elements staged for a crossing row
+constexpr int kPadTo = 16;          // planes hold nnz rounded up to this
+constexpr int kShortRow = 24;       // rows up to this length: one thread, serial sum
+constexpr int64_t kMaxNnz = (int64_t(1) << 31) - (int64_t(1) << 16);
+
+// Format identifiers for the SpMV templates: 1..3 = GSE-SEM with s segments,
+// 0 = plain FP64 CSR values.
+constexpr int kCsr64 = 0;
+
+// Epilogue of an SpMV launch.
+enum Epi : int {
+  kEpiPlain = 0,  // y = A x
+  kEpiDot = 1,    // y = A x, and the dot x.y over the launch
+  kEpiResid = 2,  // y = b - A x, and y.y
+};
+
+// ---------------------------------------------------------------- helpers --
+// Workgroup id -> tile id so that every XCD (8 per MI355X, workgroups handed
+// out round-robin) works on one contiguous range of tiles: neighbouring tiles
+// share x entries, which then stay in that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int wg, int n_wg) {
+  const int per = n_wg >> 3, rem = n_wg & 7;
+  const int xcd = wg & 7, local = wg >> 3;
+  return (xcd < rem) ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic block sum (fixed tree); every thread gets the result.
+__device__ __forceinline__ double block_sum(double v, double* red /* [kWaves] */) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) s += red[i];
+  return s;
+}
+
+// "Last workgroup" protocol: every workgroup publishes its partial; the one
+// that arrives last sees all of them (release/acquire at agent scope, i.e.
+// across the XCDs' L2 caches).  Returns true in that workgroup only.
+__device__ __forceinline__ bool last_block_arrive(unsigned* counter, bool* flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned t = atomicAdd(counter, 1u);
+    *flag = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  const bool last = *flag;
+  if (last) __threadfence();
+  return last;
+}
+
+// Sum of partials[0..n) by one workgroup in a fixed order.
+__device__ __forceinline__ double sum_partials(const double* partials, int n, double* red) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kWG)
+    s += __hip_atomic_load(partials + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return block_sum(s, red);
+}
+
+__device__ __forceinline__ double bits_to_double(uint64_t u) { return __longlong_as_double((long long)u); }
+__device__ __forceinline__ uint64_t double_to_bits(double d) { return (uint64_t)__double_as_longlong(d); }
+
+// ------------------------------------------------------------- launchers --
+struct SpmvOperand {
+  // GSE planes (fmt 1..3) or CSR values (fmt 0)
+  const int32_t* row_ptr;
+  const int32_t* tile_row;
+  const uint32_t* col;       // col | slot << 29 (GSE) or plain column (CSR)
+  const uint16_t* head;
+  const uint16_t* tail1;
+  const uint32_t* tail2;
+  const double* val;
+  int32_t n_rows;
+  int32_t n_tiles;
+  int32_t tile_nnz;
+  int32_t nnz;
+  int16_t sem[GSE_MAX_EXP];
+};
+
+struct SpmvEpilogue {
+  int epi;                 // Epi
+  const double* aux;       // kEpiDot: vector dotted with y (x itself for CG); kEpiResid: b
+  double* partials;        // [n_tiles] per-workgroup partial dots
+  unsigned* counter;       // last-workgroup counter (returns to 0 after the launch)
+  double* result;          // kEpiDot / kEpiResid: the finished dot
+  const int* gate;         // if non-null and *gate != 0 the launch does nothing
+};
+
+hipError_t launch_spmv(int fmt, const SpmvOperand& A, const double* x, double* y,
+                       const SpmvEpilogue& ep, hipStream_t st);
+hipError_t launch_plan(const int32_t* row_ptr, int32_t n_rows, int32_t nnz, int32_t tile_nnz,
+                       int32_t n_tiles, int32_t* tile_row, hipStream_t st);
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
+
+// Device record of gse_encode (lives at the start of the encode workspace).
+struct EncodeScratch {
+  uint32_t hist[2048];
+  int32_t nonfinite;
+  int32_t range_err;
+  int32_t used;
+  int32_t pad0;
+  int16_t sem[GSE_MAX_EXP];
+  unsigned long long covered;
+  unsigned long long norm_bits[4];  // max row sums |a|, |a - a_1|, |a - a_2|, |a - a_3| (as bits)
+};
+
+hipError_t launch_encode(const int32_t* row_ptr, const int32_t* col, const double* val,
+                         int32_t n_rows, int32_t nnz, int32_t num_exp, const int16_t* sem_in,
+                         gse_matrix* A, EncodeScratch* sc, hipStream_t st);
+
+int32_t n_tiles_for(int64_t nnz, int32_t tile_nnz);
+
+}  // namespace gse

@@ -1,0 +1,332 @@
+"""Python binding of libgse (ctypes).  Argument marshalling only.
+
+Every function of the C ABI (``include/gse.h``) is exposed under the same
+name; arguments are torch tensors on the GPU (their ``data_ptr()`` is passed)
+and the current torch stream.  All computation happens in the HIP library:
+if ``libgse.so`` has not been built this module raises on import of the
+library, there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgse.so")
+
+OK, PENDING, NOT_CONVERGED = 0, 1, 2
+ERR_ARG, ERR_NONFINITE, ERR_RANGE, ERR_NOMEM = -1, -2, -3, -4
+ERR_BREAKDOWN, ERR_HIP, ERR_TICKET = -5, -6, -7
+CG, GMRES = 0, 1
+TRIGGERS = {0: "none", 1: "C1", 2: "C2", 3: "C3", 4: "floor", 5: "tol", 6: "breakdown"}
+MAX_EXP = 8
+
+
+class GseError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libgse status {status}: {msg}")
+        self.status = status
+
+
+class gse_matrix(C.Structure):
+    _fields_ = [("n_rows", C.c_int32), ("n_cols", C.c_int32), ("nnz", C.c_int64),
+                ("num_exp", C.c_int32), ("num_used", C.c_int32), ("sem", C.c_int16 * 8),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("head", C.c_void_p),
+                ("tail1", C.c_void_p), ("tail2", C.c_void_p), ("tile_row", C.c_void_p),
+                ("tile_cap", C.c_int32), ("tile_nnz", C.c_int32), ("n_tiles", C.c_int32),
+                ("eta", C.c_double * 3), ("exact_frac", C.c_double)]
+
+
+class gse_csr(C.Structure):
+    _fields_ = [("n_rows", C.c_int32), ("n_cols", C.c_int32), ("nnz", C.c_int64),
+                ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p),
+                ("tile_row", C.c_void_p), ("tile_cap", C.c_int32), ("tile_nnz", C.c_int32),
+                ("n_tiles", C.c_int32)]
+
+
+class gse_params(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("restart", C.c_int32),
+                ("start_segments", C.c_int32), ("fixed_segments", C.c_int32),
+                ("l", C.c_int32), ("t", C.c_int32), ("m", C.c_int32),
+                ("rsd_limit", C.c_double), ("ndec_limit", C.c_int32),
+                ("reldec_limit", C.c_double), ("ndec_rule", C.c_int32),
+                ("floor_c", C.c_double), ("switch_mode", C.c_int32),
+                ("record_history", C.c_int32)]
+
+
+class gse_report(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("iters_per_seg", C.c_int32 * 3),
+                ("switch_iter", C.c_int32 * 2), ("switch_trigger", C.c_int32 * 2),
+                ("relres_recursive", C.c_double), ("relres_true", C.c_double),
+                ("time_ms", C.c_double)]
+
+    def as_dict(self):
+        return {"status": self.status, "iters": self.iters,
+                "iters_per_seg": list(self.iters_per_seg), "switch_iter": list(self.switch_iter),
+                "switch_trigger": [TRIGGERS.get(t, t) for t in self.switch_trigger],
+                "relres_recursive": self.relres_recursive, "relres_true": self.relres_true,
+                "time_ms": self.time_ms}
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_P = C.c_void_p
+_SIGS = {
+    "gse_pad": (C.c_int64, [C.c_int64]),
+    "gse_tile_entries": (C.c_int32, [C.c_int64]),
+    "gse_encode_workspace": (C.c_int32, [C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]),
+    "gse_encode": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int64, C.c_int32, _P,
+                               C.POINTER(gse_matrix), _P, C.c_size_t, _P]),
+    "gse_plan": (C.c_int32, [C.POINTER(gse_matrix), C.c_int32, _P]),
+    "gse_csr_plan": (C.c_int32, [C.POINTER(gse_csr), C.c_int32, _P]),
+    "gse_spmv": (C.c_int32, [C.POINTER(gse_matrix), C.c_int32, _P, _P, _P]),
+    "gse_csr_spmv": (C.c_int32, [C.POINTER(gse_csr), _P, _P, _P]),
+    "gse_default_params": (C.c_int32, [C.c_int32, C.POINTER(gse_params)]),
+    "gse_solver_workspace": (C.c_int32, [C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
+                                         C.POINTER(C.c_size_t)]),
+    "gse_cg": (C.c_int32, [C.POINTER(gse_matrix), _P, _P, C.POINTER(gse_params),
+                           C.POINTER(gse_report), _P, C.c_size_t, _P]),
+    "gse_gmres": (C.c_int32, [C.POINTER(gse_matrix), _P, _P, C.POINTER(gse_params),
+                              C.POINTER(gse_report), _P, C.c_size_t, _P]),
+    "gse_csr_cg": (C.c_int32, [C.POINTER(gse_csr), _P, _P, C.POINTER(gse_params),
+                               C.POINTER(gse_report), _P, C.c_size_t, _P]),
+    "gse_csr_gmres": (C.c_int32, [C.POINTER(gse_csr), _P, _P, C.POINTER(gse_params),
+                                  C.POINTER(gse_report), _P, C.c_size_t, _P]),
+    "gse_solve_history": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
+    "gse_stream_copy": (C.c_int32, [_P, _P, C.c_size_t, _P]),
+    "gse_status_str": (C.c_char_p, [C.c_int32]),
+    "gse_last_error": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load libgse.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name, None)
+            if fn is None:
+                continue
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(status: int, what: str) -> int:
+    if status < 0:
+        raise GseError(status, f"{what}: {lib().gse_last_error().decode()}")
+    return status
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+# ----------------------------------------------------------- raw C names ---
+def gse_pad(nnz: int) -> int:
+    return lib().gse_pad(nnz)
+
+
+def gse_tile_entries(nnz: int) -> int:
+    return lib().gse_tile_entries(nnz)
+
+
+def gse_encode_workspace(nnz: int, n_rows: int) -> int:
+    out = C.c_size_t()
+    _check(lib().gse_encode_workspace(nnz, n_rows, C.byref(out)), "gse_encode_workspace")
+    return out.value
+
+
+def gse_encode(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, sem_in, A: gse_matrix, ws,
+               stream=None) -> int:
+    si = None
+    if sem_in is not None:
+        arr = (C.c_int16 * len(sem_in))(*[int(s) for s in sem_in])
+        si = C.cast(arr, C.c_void_p)
+    return _check(lib().gse_encode(_ptr(row_ptr), _ptr(col), _ptr(val), n_rows, n_cols, nnz,
+                                   num_exp, si, C.byref(A), _ptr(ws), ws.numel() * ws.element_size(),
+                                   _stream(stream)), "gse_encode")
+
+
+def gse_plan(A: gse_matrix, tile_nnz: int, stream=None) -> int:
+    return _check(lib().gse_plan(C.byref(A), tile_nnz, _stream(stream)), "gse_plan")
+
+
+def gse_csr_plan(M: gse_csr, tile_nnz: int, stream=None) -> int:
+    return _check(lib().gse_csr_plan(C.byref(M), tile_nnz, _stream(stream)), "gse_csr_plan")
+
+
+def gse_spmv(A: gse_matrix, k_segments: int, x: torch.Tensor, y: torch.Tensor, stream=None) -> int:
+    return _check(lib().gse_spmv(C.byref(A), k_segments, _ptr(x), _ptr(y), _stream(stream)),
+                  "gse_spmv")
+
+
+def gse_csr_spmv(M: gse_csr, x: torch.Tensor, y: torch.Tensor, stream=None) -> int:
+    return _check(lib().gse_csr_spmv(C.byref(M), _ptr(x), _ptr(y), _stream(stream)),
+                  "gse_csr_spmv")
+
+
+def gse_default_params(method: int) -> gse_params:
+    p = gse_params()
+    _check(lib().gse_default_params(method, C.byref(p)), "gse_default_params")
+    return p
+
+
+def gse_solver_workspace(method: int, n_rows: int, nnz: int, restart: int, max_iter: int) -> int:
+    out = C.c_size_t()
+    _check(lib().gse_solver_workspace(method, n_rows, nnz, restart, max_iter, C.byref(out)),
+           "gse_solver_workspace")
+    return out.value
+
+
+def _solve(fn, name, A, b, x, p, ws, stream):
+    rep = gse_report()
+    st = fn(C.byref(A), _ptr(b), _ptr(x), C.byref(p), C.byref(rep), _ptr(ws),
+            ws.numel() * ws.element_size(), _stream(stream))
+    if st < 0 and st != ERR_BREAKDOWN:
+        _check(st, name)
+    return rep
+
+
+def gse_cg(A, b, x, p, ws, stream=None) -> gse_report:
+    return _solve(lib().gse_cg, "gse_cg", A, b, x, p, ws, stream)
+
+
+def gse_gmres(A, b, x, p, ws, stream=None) -> gse_report:
+    return _solve(lib().gse_gmres, "gse_gmres", A, b, x, p, ws, stream)
+
+
+def gse_csr_cg(M, b, x, p, ws, stream=None) -> gse_report:
+    return _solve(lib().gse_csr_cg, "gse_csr_cg", M, b, x, p, ws, stream)
+
+
+def gse_csr_gmres(M, b, x, p, ws, stream=None) -> gse_report:
+    return _solve(lib().gse_csr_gmres, "gse_csr_gmres", M, b, x, p, ws, stream)
+
+
+def gse_solve_history(ws, cap: int, stream=None):
+    import numpy as np
+    hist = np.zeros(cap, np.float64)
+    seg = np.zeros(cap, np.int32)
+    _check(lib().gse_solve_history(_ptr(ws), cap, C.c_void_p(hist.ctypes.data),
+                                   C.c_void_p(seg.ctypes.data), _stream(stream)),
+           "gse_solve_history")
+    return hist, seg
+
+
+def gse_stream_copy(src: torch.Tensor, dst: torch.Tensor, nbytes: int, stream=None) -> int:
+    return _check(lib().gse_stream_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)),
+                  "gse_stream_copy")
+
+
+# -------------------------------------------------------- tensor holders ---
+def _alloc(n, dtype, device):
+    return torch.empty(max(int(n), 1), dtype=dtype, device=device)
+
+
+class GseMatrix:
+    """Device planes of one encoded matrix plus its ``gse_matrix`` record."""
+
+    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n_cols: int,
+                 num_exp: int = 8, sem_in=None, stream=None):
+        dev = row_ptr.device
+        n_rows = row_ptr.numel() - 1
+        nnz = val.numel()
+        pad = gse_pad(nnz)
+        self.row_ptr = row_ptr
+        self.col_idx = _alloc(pad, torch.int32, dev)
+        self.head = _alloc(pad, torch.int16, dev)
+        self.tail1 = _alloc(pad, torch.int16, dev)
+        self.tail2 = _alloc(pad, torch.int32, dev)
+        cap = gse_tile_entries(nnz)
+        self.tile_row = _alloc(cap, torch.int32, dev)
+        self.ws = _alloc(gse_encode_workspace(nnz, n_rows), torch.uint8, dev)
+        A = gse_matrix()
+        A.col_idx = self.col_idx.data_ptr()
+        A.head = self.head.data_ptr()
+        A.tail1 = self.tail1.data_ptr()
+        A.tail2 = self.tail2.data_ptr()
+        A.tile_row = self.tile_row.data_ptr()
+        A.tile_cap = cap
+        self.A = A
+        gse_encode(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, sem_in, A, self.ws, stream)
+
+    @property
+    def n_rows(self):
+        return self.A.n_rows
+
+    @property
+    def nnz(self):
+        return self.A.nnz
+
+    @property
+    def sem(self):
+        return list(self.A.sem)
+
+    @property
+    def eta(self):
+        return list(self.A.eta)
+
+    def planes(self):
+        """(col_idx u32, head u16, tail1 u16, tail2 u32) as numpy arrays (host copy)."""
+        n = self.nnz
+        return (self.col_idx[:n].cpu().numpy().view("uint32"),
+                self.head[:n].cpu().numpy().view("uint16"),
+                self.tail1[:n].cpu().numpy().view("uint16"),
+                self.tail2[:n].cpu().numpy().view("uint32"))
+
+    def plan(self, tile_nnz: int, stream=None):
+        gse_plan(self.A, tile_nnz, stream)
+
+    def spmv(self, k_segments: int, x: torch.Tensor, y: torch.Tensor, stream=None):
+        gse_spmv(self.A, k_segments, x, y, stream)
+
+
+class CsrMatrix:
+    """Padded device copy of an FP64 CSR matrix for the baseline operators."""
+
+    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n_cols: int,
+                 tile_nnz: int = 2048, stream=None):
+        dev = row_ptr.device
+        nnz = val.numel()
+        pad = gse_pad(nnz)
+        self.row_ptr = row_ptr
+        self.col = torch.zeros(max(pad, 1), dtype=torch.int32, device=dev)
+        self.val = torch.zeros(max(pad, 1), dtype=torch.float64, device=dev)
+        if nnz:
+            self.col[:nnz].copy_(col)
+            self.val[:nnz].copy_(val)
+        cap = gse_tile_entries(nnz)
+        self.tile_row = _alloc(cap, torch.int32, dev)
+        M = gse_csr()
+        M.n_rows = row_ptr.numel() - 1
+        M.n_cols = n_cols
+        M.nnz = nnz
+        M.row_ptr = row_ptr.data_ptr()
+        M.col = self.col.data_ptr()
+        M.val = self.val.data_ptr()
+        M.tile_row = self.tile_row.data_ptr()
+        M.tile_cap = cap
+        self.M = M
+        gse_csr_plan(M, tile_nnz, stream)
+
+    def spmv(self, x: torch.Tensor, y: torch.Tensor, stream=None):
+        gse_csr_spmv(self.M, x, y, stream)

@@ -1,0 +1,193 @@
+"""GPU parity: encoder planes bit-exact, SpMV within tolerance of the oracle.
+
+Every case runs the HIP library through its C ABI (ctypes binding) and the
+oracle on the same seeded inputs.  Tolerances:
+  * planes, shared-exponent table, slot indices: bit-exact;
+  * SpMV at every segment count: the decoded values are exact on both sides,
+    only the summation order may differ, so the result must agree with the
+    oracle's same-s result within 1e-12 relative (norm-wise and, scaled by
+    sum |a_ij x_j|, componentwise);
+  * eta_s (a sum of rounded differences): 1e-12 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import (CSR, convdiff2d, diffusion3d, poisson2d, powerlaw, random_sparse,
+                       rhs_from_solution)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - collected on the CPU machine too
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2411_04686_amd import gse as G  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def to_dev(A: CSR):
+    return (torch.from_numpy(A.indptr).to(DEV), torch.from_numpy(A.indices).to(DEV),
+            torch.from_numpy(A.data).to(DEV))
+
+
+def cases():
+    return {
+        "poisson2d_64": lambda: poisson2d(64),
+        "diffusion3d_24": lambda: diffusion3d(24, 0),
+        "convdiff2d_64": lambda: convdiff2d(64, 1),
+        "powerlaw_20k": lambda: powerlaw(20_000, 2),
+        "random_empty_long": lambda: random_sparse(3000, 2500, 5, mean_row=4, empty_frac=0.2,
+                                                   long_rows=6, long_len=2400, exp_spread=60),
+        "random_ragged": lambda: random_sparse(1777, 1901, 6, mean_row=9, exp_spread=20),
+        "one_row_long": lambda: random_sparse(1, 9000, 7, mean_row=1, long_rows=1, long_len=8999),
+        "tiny": lambda: random_sparse(3, 3, 8, mean_row=2),
+    }
+
+
+@pytest.fixture(scope="module", params=list(cases()))
+def case(request):
+    A = cases()[request.param]()
+    enc = O.encode(A.indptr, A.indices, A.data, A.n_cols)
+    rp, ci, va = to_dev(A)
+    M = G.GseMatrix(rp, ci, va, A.n_cols)
+    return request.param, A, enc, M
+
+
+def test_encode_bit_exact(case):
+    name, A, enc, M = case
+    assert M.sem == [int(s) for s in enc.sem], name
+    for got, want, what in zip(M.planes(), (enc.col_idx, enc.head, enc.tail1, enc.tail2),
+                               ("col_idx", "head", "tail1", "tail2")):
+        assert np.array_equal(got, want), (name, what, np.nonzero(got != want)[0][:5])
+    assert M.A.exact_frac == enc.exact_frac
+    for s in range(3):
+        assert M.eta[s] == pytest.approx(enc.eta[s], rel=1e-12, abs=1e-300)
+
+
+def _check_close(got, ref, scale, tol=1e-12):
+    assert np.all(np.abs(got - ref) <= tol * scale + 1e-300)
+    nr = np.linalg.norm(ref)
+    if nr > 0:
+        assert np.linalg.norm(got - ref) <= tol * nr + 1e-300
+
+
+@pytest.mark.parametrize("tile", [1024, 2048, 4096])
+def test_spmv_all_segments(case, tile):
+    name, A, enc, M = case
+    M.plan(tile)
+    rng = np.random.default_rng(tile)
+    x = rng.uniform(-1, 1, A.n_cols)
+    xd = torch.from_numpy(x).to(DEV)
+    yd = torch.full((A.n_rows,), np.nan, dtype=torch.float64, device=DEV)
+    for s in (1, 2, 3):
+        M.spmv(s, xd, yd)
+        torch.cuda.synchronize()
+        y = yd.cpu().numpy()
+        ref = O.gse_spmv(A.indptr, enc, s, x)
+        dec = O.decode(enc, s)
+        scale = np.zeros(A.n_rows)
+        np.add.at(scale, np.repeat(np.arange(A.n_rows), np.diff(A.indptr)),
+                  np.abs(dec * x[A.indices]))
+        _check_close(y, ref, scale)
+    M.plan(2048)
+
+
+@pytest.mark.parametrize("tile", [1024, 4096])
+def test_csr64_spmv(case, tile):
+    name, A, enc, M = case
+    rp, ci, va = to_dev(A)
+    C64 = G.CsrMatrix(rp, ci, va, A.n_cols, tile_nnz=tile)
+    x = np.random.default_rng(3).uniform(-1, 1, A.n_cols)
+    yd = torch.empty(A.n_rows, dtype=torch.float64, device=DEV)
+    C64.spmv(torch.from_numpy(x).to(DEV), yd)
+    torch.cuda.synchronize()
+    ref = O.csr_spmv(A.indptr, A.indices, A.data, x)
+    scale = np.zeros(A.n_rows)
+    np.add.at(scale, np.repeat(np.arange(A.n_rows), np.diff(A.indptr)),
+              np.abs(A.data * x[A.indices]))
+    _check_close(yd.cpu().numpy(), ref, scale)
+
+
+def test_spmv_deterministic_and_x_ones(case):
+    """Two launches give identical bits; with x = 1 (Section IV-A protocol)
+    the row sums of the decoded matrix."""
+    name, A, enc, M = case
+    xd = torch.ones(A.n_cols, dtype=torch.float64, device=DEV)
+    y1 = torch.empty(A.n_rows, dtype=torch.float64, device=DEV)
+    y2 = torch.empty_like(y1)
+    M.spmv(1, xd, y1)
+    M.spmv(1, xd, y2)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    ref = O.gse_spmv(A.indptr, enc, 1, np.ones(A.n_cols))
+    assert np.allclose(y1.cpu().numpy(), ref, rtol=1e-12, atol=1e-300)
+
+
+def test_reused_table_and_errors():
+    A = diffusion3d(10, 3)
+    rp, ci, va = to_dev(A)
+    M1 = G.GseMatrix(rp, ci, va, A.n_cols)
+    B = diffusion3d(10, 4)  # same recipe, other draw: reuse the first table
+    rpb, cib, vab = to_dev(B)
+    sem = [s for s in M1.sem if s]
+    M2 = G.GseMatrix(rpb, cib, vab, B.n_cols, num_exp=len(sem), sem_in=sem)
+    enc = O.encode(B.indptr, B.indices, B.data, B.n_cols, num_exp=len(sem),
+                   sem_in=np.array(sem, np.int16))
+    assert M2.sem[: len(sem)] == sem
+    for got, want in zip(M2.planes(), (enc.col_idx, enc.head, enc.tail1, enc.tail2)):
+        assert np.array_equal(got, want)
+    # non-finite value
+    bad = va.clone()
+    bad[5] = float("nan")
+    with pytest.raises(G.GseError) as ei:
+        G.GseMatrix(rp, ci, bad, A.n_cols)
+    assert ei.value.status == G.ERR_NONFINITE
+    # a reused table that does not cover a value
+    big = va.clone()
+    big[7] = 1e30
+    with pytest.raises(G.GseError) as ei:
+        G.GseMatrix(rp, ci, big, A.n_cols, num_exp=len(sem), sem_in=sem)
+    assert ei.value.status == G.ERR_RANGE
+    # bad segment count
+    x = torch.ones(A.n_cols, dtype=torch.float64, device=DEV)
+    y = torch.empty(A.n_rows, dtype=torch.float64, device=DEV)
+    with pytest.raises(G.GseError) as ei:
+        M1.spmv(4, x, y)
+    assert ei.value.status == G.ERR_ARG
+
+
+def test_empty_matrix():
+    A = CSR(5, 5, np.zeros(6, np.int32), np.zeros(0, np.int32), np.zeros(0), "empty")
+    rp, ci, va = to_dev(A)
+    M = G.GseMatrix(rp, ci, va, 5)
+    x = torch.ones(5, dtype=torch.float64, device=DEV)
+    y = torch.full((5,), 7.0, dtype=torch.float64, device=DEV)
+    M.spmv(2, x, y)
+    torch.cuda.synchronize()
+    assert torch.equal(y, torch.zeros_like(y))
+
+
+def test_full_size_diffusion3d_128_sampled():
+    """The 128^3 operator at full size, in the launch configuration the
+    benchmark times: the whole planes bit-exact, sampled rows of y against the
+    oracle row by row."""
+    A = diffusion3d(128, 0)
+    rp, ci, va = to_dev(A)
+    M = G.GseMatrix(rp, ci, va, A.n_cols)
+    enc = O.encode(A.indptr, A.indices, A.data, A.n_cols)
+    assert M.sem == [int(s) for s in enc.sem]
+    for got, want in zip(M.planes(), (enc.col_idx, enc.head, enc.tail1, enc.tail2)):
+        assert np.array_equal(got, want)
+    x, _ = rhs_from_solution(A, 5)
+    xd = torch.from_numpy(x).to(DEV)
+    yd = torch.empty(A.n_rows, dtype=torch.float64, device=DEV)
+    rows = np.unique(np.concatenate([np.random.default_rng(1).integers(0, A.n_rows, 20000),
+                                     [0, 1, A.n_rows - 1]])).astype(np.int32)
+    for s in (1, 2, 3):
+        M.spmv(s, xd, yd)
+        torch.cuda.synchronize()
+        y = yd.cpu().numpy()[rows]
+        ref = O.gse_spmv_rows(rows, A.indptr, enc, s, x)
+        assert np.allclose(y, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())

@@ -1,0 +1,95 @@
+"""Host model of the SpMV tile schedule (no GPU).
+
+Replays, in Python, the index arithmetic of the tiled SpMV kernel (tile
+ranges, the row range each tile writes, the staged non-zero window, the
+vector-load groups of phase 1, the LDS product slots, the deferred-row list
+and the long-row tail) and checks on the test matrices and the full-size
+operators that every access stays inside its buffer and every row is written
+by exactly one tile.  The constants mirror csrc/gse_internal.h.
+"""
+import numpy as np
+import pytest
+
+from workloads import (diffusion3d, convdiff2d, poisson2d, powerlaw, random_sparse)
+
+WG, EXTRA, SHORT, PAD = 256, 256, 24, 16
+
+
+def lower_bound(a, v):
+    return int(np.searchsorted(a, v, side="left"))
+
+
+def check(indptr, n_cols, cols, E):
+    T = WG * E
+    n_rows = indptr.size - 1
+    nnz = int(indptr[-1])
+    pad = (nnz + PAD - 1) // PAD * PAD
+    n_tiles = max(1, -(-nnz // T))
+    starts = indptr[:n_rows]
+    tile_row = [lower_bound(starts, t * T) for t in range(n_tiles)] + [n_rows]
+    nprod = (T + EXTRA) + (T + EXTRA) // E
+    ndef_cap = (T + EXTRA) // (SHORT + 1) + 2
+    written = np.zeros(n_rows, np.int32)
+    assert tile_row[0] == 0 or n_rows == 0
+    for t in range(n_tiles):
+        j0, j1 = t * T, min(t * T + T, nnz)
+        ra, rb = tile_row[t], tile_row[t + 1]
+        assert ra <= rb
+        if ra == rb:
+            continue
+        js, je = int(indptr[ra]), int(indptr[rb])
+        assert j0 <= js <= j1 and je >= j1 or rb == n_rows
+        tail = (je - j1) <= EXTRA
+        jl = je if tail else j1
+        assert jl <= nnz and jl <= j1 + EXTRA
+        bases = [j0 + tid * E for tid in range(WG)]
+        bases += [j1 + tid * E for tid in range(EXTRA // E) if j1 + tid * E < jl]
+        for base in bases:
+            if base + E > js and base < jl:
+                assert base % E == 0 and base + E <= pad  # aligned vector loads in bounds
+                lo, hi = max(base, js), min(base + E, jl)
+                if hi > lo:
+                    li = np.arange(lo, hi) - j0
+                    slot = li + li // E
+                    assert slot.min() >= 0 and slot.max() < nprod
+                    assert cols[lo:hi].max() < n_cols
+        ndef = 0
+        for r in range(ra, rb):
+            written[r] += 1
+            s0, s1 = int(indptr[r]), int(indptr[r + 1])
+            if not tail and r == rb - 1:
+                assert s1 > j1 + EXTRA and s0 >= js
+                continue
+            assert js <= s0 <= s1 <= jl
+            if s1 - s0 > SHORT:
+                ndef += 1
+        assert ndef <= ndef_cap
+    assert np.all(written == 1)
+    return n_tiles
+
+
+MATS = {
+    "poisson2d_64": lambda: poisson2d(64),
+    "diffusion3d_24": lambda: diffusion3d(24, 0),
+    "convdiff2d_64": lambda: convdiff2d(64, 1),
+    "powerlaw_20k": lambda: powerlaw(20_000, 2),
+    "random_empty_long": lambda: random_sparse(3000, 2500, 5, mean_row=4, empty_frac=0.2,
+                                               long_rows=6, long_len=2400, exp_spread=60),
+    "random_ragged": lambda: random_sparse(1777, 1901, 6, mean_row=9, exp_spread=20),
+    "one_row_long": lambda: random_sparse(1, 9000, 7, mean_row=1, long_rows=1, long_len=8999),
+    "tiny": lambda: random_sparse(3, 3, 8, mean_row=2),
+    "empty": lambda: random_sparse(5, 5, 9, mean_row=0),
+}
+
+
+@pytest.mark.parametrize("name", list(MATS))
+@pytest.mark.parametrize("E", [4, 8, 16])
+def test_schedule_in_bounds(name, E):
+    A = MATS[name]()
+    check(A.indptr.astype(np.int64), A.n_cols, A.indices, E)
+
+
+@pytest.mark.parametrize("E", [8])
+def test_schedule_full_size_diffusion3d_128(E):
+    A = diffusion3d(128, 0)
+    assert check(A.indptr.astype(np.int64), A.n_cols, A.indices, E) == -(-A.nnz // (WG * E))
