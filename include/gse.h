@@ -91,6 +91,8 @@ typedef struct gse_matrix {
     int32_t tile_cap;
     int32_t tile_nnz;          /* non-zeros per SpMV tile (set by gse_plan) */
     int32_t n_tiles;
+    int32_t rv_lanes;          /* > 0: row-vector SpMV schedule, lanes per row; 0: tiles */
+    int32_t max_row_nnz;       /* longest row (set by gse_encode / gse_plan) */
     double eta[3];             /* ||A - A_s||_inf / ||A||_inf, s = 1, 2, 3 */
     double exact_frac;         /* share of non-zeros whose exponent is shared */
 } gse_matrix;
@@ -108,6 +110,8 @@ typedef struct gse_csr {
     int32_t tile_cap;
     int32_t tile_nnz;
     int32_t n_tiles;
+    int32_t rv_lanes;
+    int32_t max_row_nnz;
 } gse_csr;
 
 /* Entries tile_row needs for any tile size the library may choose. */
@@ -128,8 +132,8 @@ gse_status gse_encode_workspace(int64_t nnz, int32_t n_rows, size_t* ws_bytes);
  *                       A reused table that leaves a value without a larger
  *                       shared exponent gives GSE_ERR_RANGE.
  *   A                 : in: plane pointers and tile_row/tile_cap; out: every
- *                       other field; the SpMV schedule is built with the
- *                       default tile size.
+ *                       other field; the SpMV schedule is chosen as by
+ *                       gse_plan(A, 2048, -1).
  *   ws, ws_bytes      : device workspace of gse_encode_workspace() bytes.
  * Errors: GSE_ERR_NONFINITE (Inf/NaN value), GSE_ERR_RANGE (sizes, a shared
  * exponent below 63 whose grid would leave the normal range, uncovered
@@ -140,10 +144,17 @@ gse_status gse_encode(const int32_t* row_ptr, const int32_t* col, const double* 
                       const int16_t* sem_in, gse_matrix* A, void* ws, size_t ws_bytes,
                       void* stream);
 
-/* (Re)build the SpMV tile schedule for tile_nnz non-zeros per tile
- * (1024, 2048 or 4096).  Synchronizes `stream`. */
-gse_status gse_plan(gse_matrix* A, int32_t tile_nnz, void* stream);
-gse_status gse_csr_plan(gse_csr* M, int32_t tile_nnz, void* stream);
+/* (Re)build the SpMV schedule.  Two schedules exist:
+ *   tiles       (rv_lanes == 0): fixed runs of tile_nnz non-zeros (1024, 2048
+ *               or 4096) per workgroup step, rows of any length;
+ *   row-vector  (rv_lanes = 1, 2, 4, ..., 64): that many lanes per row,
+ *               for matrices whose rows are short and of similar length.
+ * rv_lanes == -1 picks one from the row lengths (row-vector with the power
+ * of two at or above the mean row length when no row is longer than 64 and
+ * four times the mean, tiles otherwise).  The tile table is always built.
+ * Synchronizes `stream`. */
+gse_status gse_plan(gse_matrix* A, int32_t tile_nnz, int32_t rv_lanes, void* stream);
+gse_status gse_csr_plan(gse_csr* M, int32_t tile_nnz, int32_t rv_lanes, void* stream);
 
 /* y = A_s x with s = k_segments in {1, 2, 3}: the head-only operator of
  * Algorithm 2 and its head+tail1 and head+tail1+tail2 variants

@@ -28,6 +28,40 @@ int64_t pad_nnz(int64_t nnz) { return (nnz + kPadTo - 1) / kPadTo * kPadTo; }
 
 bool valid_tile(int32_t t) { return t == kWG * 4 || t == kWG * 8 || t == kWG * 16; }
 
+bool valid_rv(int32_t L) { return L == 0 || (L >= 1 && L <= 64 && (L & (L - 1)) == 0); }
+
+// Row-vector lanes for near-uniform short rows, 0 (tiles) otherwise.
+int32_t auto_rv(int64_t nnz, int32_t n_rows, int32_t max_row) {
+  if (n_rows <= 0 || nnz == 0) return 0;
+  const double mean = (double)nnz / (double)n_rows;
+  if (max_row > 64 || (double)max_row > 4.0 * mean + 4.0) return 0;
+  int32_t L = 1;
+  while ((double)L < mean && L < 64) L <<= 1;
+  return L < 2 ? 2 : L;
+}
+
+// Tile table for tile_nnz plus the longest row; picks the schedule.
+gse_status plan_common(const int32_t* row_ptr, int32_t n_rows, int64_t nnz, int32_t* tile_row,
+                       int32_t tile_cap, int32_t tile_nnz, int32_t rv_lanes, hipStream_t st,
+                       int32_t* out_tiles, int32_t* out_rv, int32_t* out_maxrow) {
+  if (!valid_tile(tile_nnz)) return fail(GSE_ERR_ARG, "tile_nnz %d not supported", tile_nnz);
+  if (rv_lanes != -1 && !valid_rv(rv_lanes))
+    return fail(GSE_ERR_ARG, "rv_lanes %d not supported", rv_lanes);
+  const int32_t nt = n_tiles_for(nnz, tile_nnz);
+  if (tile_cap < nt + 2) return fail(GSE_ERR_NOMEM, "tile_row holds %d < %d", tile_cap, nt + 2);
+  int* scratch = tile_row + (tile_cap - 1);  // never part of a tile table
+  hipError_t e = launch_plan(row_ptr, n_rows, (int32_t)nnz, tile_nnz, nt, tile_row, st);
+  if (e == hipSuccess) e = launch_rowmax(row_ptr, n_rows, scratch, st);
+  int32_t maxrow = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&maxrow, scratch, sizeof maxrow, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "plan");
+  *out_tiles = nt;
+  *out_maxrow = maxrow;
+  *out_rv = (rv_lanes == -1) ? auto_rv(nnz, n_rows, maxrow) : rv_lanes;
+  return GSE_OK;
+}
+
 SpmvOperand operand_of(const gse_matrix* A) {
   SpmvOperand o{};
   o.row_ptr = A->row_ptr;
@@ -41,6 +75,7 @@ SpmvOperand operand_of(const gse_matrix* A) {
   o.n_tiles = A->n_tiles;
   o.tile_nnz = A->tile_nnz;
   o.nnz = (int32_t)A->nnz;
+  o.rv_lanes = A->rv_lanes;
   for (int i = 0; i < GSE_MAX_EXP; ++i) o.sem[i] = A->sem[i];
   return o;
 }
@@ -58,6 +93,7 @@ SpmvOperand operand_of(const gse_csr* M) {
   o.n_tiles = M->n_tiles;
   o.tile_nnz = M->tile_nnz;
   o.nnz = (int32_t)M->nnz;
+  o.rv_lanes = M->rv_lanes;
   for (int i = 0; i < GSE_MAX_EXP; ++i) o.sem[i] = 0;
   return o;
 }
@@ -69,7 +105,7 @@ gse_status check_matrix(const gse_matrix* A) {
   if (A->n_rows < 0 || A->n_cols < 0 || A->nnz < 0) return fail(GSE_ERR_ARG, "negative size");
   if (A->nnz > kMaxNnz) return fail(GSE_ERR_RANGE, "nnz %lld exceeds the limit", (long long)A->nnz);
   if (!valid_tile(A->tile_nnz) || A->n_tiles != n_tiles_for(A->nnz, A->tile_nnz) ||
-      A->tile_cap < A->n_tiles + 1)
+      A->tile_cap < A->n_tiles + 2 || !valid_rv(A->rv_lanes))
     return fail(GSE_ERR_ARG, "matrix has no valid SpMV schedule (call gse_encode / gse_plan)");
   return GSE_OK;
 }
@@ -83,7 +119,7 @@ gse_status check_csr(const gse_csr* M) {
   if (!aligned16(M->col) || !aligned16(M->val))
     return fail(GSE_ERR_ARG, "col/val must be 16-byte aligned");
   if (!valid_tile(M->tile_nnz) || M->n_tiles != n_tiles_for(M->nnz, M->tile_nnz) ||
-      M->tile_cap < M->n_tiles + 1)
+      M->tile_cap < M->n_tiles + 2 || !valid_rv(M->rv_lanes))
     return fail(GSE_ERR_ARG, "matrix has no valid SpMV schedule (call gse_csr_plan)");
   return GSE_OK;
 }
@@ -122,32 +158,31 @@ gse_status gse_encode_workspace(int64_t nnz, int32_t n_rows, size_t* ws_bytes) {
   return GSE_OK;
 }
 
-gse_status gse_plan(gse_matrix* A, int32_t tile_nnz, void* stream) {
+gse_status gse_plan(gse_matrix* A, int32_t tile_nnz, int32_t rv_lanes, void* stream) {
   if (!A || !A->row_ptr || !A->tile_row) return fail(GSE_ERR_ARG, "bad matrix");
-  if (!valid_tile(tile_nnz)) return fail(GSE_ERR_ARG, "tile_nnz %d not supported", tile_nnz);
-  const int32_t nt = n_tiles_for(A->nnz, tile_nnz);
-  if (A->tile_cap < nt + 1) return fail(GSE_ERR_NOMEM, "tile_row holds %d < %d", A->tile_cap, nt + 1);
-  hipStream_t st = (hipStream_t)stream;
-  hipError_t e = launch_plan(A->row_ptr, A->n_rows, (int32_t)A->nnz, tile_nnz, nt, A->tile_row, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_fail(e, "gse_plan");
+  if (A->nnz < 0 || A->nnz > kMaxNnz || A->n_rows < 0) return fail(GSE_ERR_RANGE, "bad sizes");
+  int32_t nt, rv, mr;
+  gse_status s = plan_common(A->row_ptr, A->n_rows, A->nnz, A->tile_row, A->tile_cap, tile_nnz,
+                             rv_lanes, (hipStream_t)stream, &nt, &rv, &mr);
+  if (s != GSE_OK) return s;
   A->tile_nnz = tile_nnz;
   A->n_tiles = nt;
+  A->rv_lanes = rv;
+  A->max_row_nnz = mr;
   return GSE_OK;
 }
 
-gse_status gse_csr_plan(gse_csr* M, int32_t tile_nnz, void* stream) {
+gse_status gse_csr_plan(gse_csr* M, int32_t tile_nnz, int32_t rv_lanes, void* stream) {
   if (!M || !M->row_ptr || !M->tile_row) return fail(GSE_ERR_ARG, "bad matrix");
-  if (!valid_tile(tile_nnz)) return fail(GSE_ERR_ARG, "tile_nnz %d not supported", tile_nnz);
-  if (M->nnz < 0 || M->nnz > kMaxNnz) return fail(GSE_ERR_RANGE, "nnz out of range");
-  const int32_t nt = n_tiles_for(M->nnz, tile_nnz);
-  if (M->tile_cap < nt + 1) return fail(GSE_ERR_NOMEM, "tile_row holds %d < %d", M->tile_cap, nt + 1);
-  hipStream_t st = (hipStream_t)stream;
-  hipError_t e = launch_plan(M->row_ptr, M->n_rows, (int32_t)M->nnz, tile_nnz, nt, M->tile_row, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_fail(e, "gse_csr_plan");
+  if (M->nnz < 0 || M->nnz > kMaxNnz || M->n_rows < 0) return fail(GSE_ERR_RANGE, "bad sizes");
+  int32_t nt, rv, mr;
+  gse_status s = plan_common(M->row_ptr, M->n_rows, M->nnz, M->tile_row, M->tile_cap, tile_nnz,
+                             rv_lanes, (hipStream_t)stream, &nt, &rv, &mr);
+  if (s != GSE_OK) return s;
   M->tile_nnz = tile_nnz;
   M->n_tiles = nt;
+  M->rv_lanes = rv;
+  M->max_row_nnz = mr;
   return GSE_OK;
 }
 
@@ -187,15 +222,18 @@ gse_status gse_encode(const int32_t* row_ptr, const int32_t* col, const double* 
   A->row_ptr = row_ptr;
   hipError_t e = launch_encode(row_ptr, col, val, n_rows, (int32_t)nnz, num_exp, sem_in, A, sc, st);
   if (e != hipSuccess) return hip_fail(e, "gse_encode launch");
-  const int32_t nt = n_tiles_for(nnz, kDefaultTile);
-  e = launch_plan(row_ptr, n_rows, (int32_t)nnz, kDefaultTile, nt, A->tile_row, st);
-  if (e != hipSuccess) return hip_fail(e, "gse_encode plan");
   EncodeScratch h;
   e = hipMemcpyAsync(&h, sc, sizeof h, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "gse_encode");
+  int32_t nt, rv, mr;
+  gse_status ps = plan_common(row_ptr, n_rows, nnz, A->tile_row, A->tile_cap, kDefaultTile, -1, st,
+                              &nt, &rv, &mr);
+  if (ps != GSE_OK) return ps;
   A->tile_nnz = kDefaultTile;
   A->n_tiles = nt;
+  A->rv_lanes = rv;
+  A->max_row_nnz = mr;
   for (int i = 0; i < GSE_MAX_EXP; ++i) A->sem[i] = h.sem[i];
   A->num_used = h.used;
   A->exact_frac = nnz ? (double)h.covered / (double)nnz : 1.0;
@@ -231,6 +269,100 @@ gse_status gse_csr_spmv(const gse_csr* M, const double* x, double* y, void* stre
   hipError_t e = launch_spmv(kCsr64, operand_of(M), x, y, ep, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "gse_csr_spmv");
   return GSE_OK;
+}
+
+gse_status gse_default_params(int32_t method, gse_params* p) {
+  if (!p || (method != GSE_CG && method != GSE_GMRES)) return fail(GSE_ERR_ARG, "bad arguments");
+  memset(p, 0, sizeof *p);
+  p->tol = 1e-10;
+  p->restart = 30;
+  p->start_segments = 1;
+  p->fixed_segments = 0;
+  p->ndec_rule = 0;
+  p->floor_c = 10.0;
+  p->switch_mode = 1;
+  p->record_history = 0;
+  if (method == GSE_CG) {  // Section IV-A (cap) and IV-D.1 (controller)
+    p->max_iter = 5000;
+    p->l = 3000;
+    p->t = 250;
+    p->m = 500;
+    p->rsd_limit = 0.50;
+    p->ndec_limit = 130;
+    p->reldec_limit = 0.45;
+  } else {
+    p->max_iter = 30 * 500;
+    p->l = 9000;
+    p->t = 300;
+    p->m = 1500;
+    p->rsd_limit = 0.03;
+    p->ndec_limit = 80;
+    p->reldec_limit = 0.08;
+  }
+  return GSE_OK;
+}
+
+gse_status gse_solver_workspace(int32_t method, int32_t n_rows, int64_t nnz, int32_t restart,
+                                int32_t max_iter, size_t* ws_bytes) {
+  if (!ws_bytes || n_rows < 0 || nnz < 0 || max_iter < 0 ||
+      (method != GSE_CG && method != GSE_GMRES) || (method == GSE_GMRES && restart < 1))
+    return fail(GSE_ERR_ARG, "bad arguments");
+  *ws_bytes = solver_workspace_bytes(method, n_rows, nnz, restart, max_iter);
+  return GSE_OK;
+}
+
+static gse_status check_solve(int32_t n_rows, int32_t n_cols, const double* b, double* x,
+                              const gse_params* p, gse_report* rep, const void* ws, int method) {
+  if (!p || !rep) return fail(GSE_ERR_ARG, "params / report is NULL");
+  if (n_rows != n_cols) return fail(GSE_ERR_ARG, "the matrix must be square");
+  if (n_rows > 0 && (!b || !x)) return fail(GSE_ERR_ARG, "NULL vector");
+  if (!aligned16(x)) return fail(GSE_ERR_ARG, "x must be 16-byte aligned");
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u))
+    return fail(GSE_ERR_ARG, "workspace must be non-NULL and 256-byte aligned");
+  if (!(p->tol > 0.0) || p->max_iter < 0) return fail(GSE_ERR_ARG, "tol must be > 0, max_iter >= 0");
+  if (p->start_segments < 1 || p->start_segments > 3 || p->fixed_segments < 0 || p->fixed_segments > 3)
+    return fail(GSE_ERR_ARG, "segment counts must be 1..3 (fixed: 0..3)");
+  if (p->l < 0 || p->t < 1 || p->m < 0) return fail(GSE_ERR_ARG, "controller needs l >= 0, t >= 1, m >= 0");
+  if (method == GSE_GMRES && p->restart < 1) return fail(GSE_ERR_ARG, "restart must be >= 1");
+  return GSE_OK;
+}
+
+gse_status gse_cg(const gse_matrix* A, const double* b, double* x, const gse_params* p,
+                  gse_report* rep, void* ws, size_t ws_bytes, void* stream) {
+  gse_status s = check_matrix(A);
+  if (s == GSE_OK) s = check_solve(A->n_rows, A->n_cols, b, x, p, rep, ws, GSE_CG);
+  if (s != GSE_OK) return s;
+  return cg_gse(A, operand_of(A), b, x, p, rep, ws, ws_bytes, (hipStream_t)stream);
+}
+
+gse_status gse_csr_cg(const gse_csr* M, const double* b, double* x, const gse_params* p,
+                      gse_report* rep, void* ws, size_t ws_bytes, void* stream) {
+  gse_status s = check_csr(M);
+  if (s == GSE_OK) s = check_solve(M->n_rows, M->n_cols, b, x, p, rep, ws, GSE_CG);
+  if (s != GSE_OK) return s;
+  return cg_csr(operand_of(M), b, x, p, rep, ws, ws_bytes, (hipStream_t)stream);
+}
+
+gse_status gse_gmres(const gse_matrix* A, const double* b, double* x, const gse_params* p,
+                     gse_report* rep, void* ws, size_t ws_bytes, void* stream) {
+  gse_status s = check_matrix(A);
+  if (s == GSE_OK) s = check_solve(A->n_rows, A->n_cols, b, x, p, rep, ws, GSE_GMRES);
+  if (s != GSE_OK) return s;
+  return gmres_gse(A, operand_of(A), b, x, p, rep, ws, ws_bytes, (hipStream_t)stream);
+}
+
+gse_status gse_csr_gmres(const gse_csr* M, const double* b, double* x, const gse_params* p,
+                         gse_report* rep, void* ws, size_t ws_bytes, void* stream) {
+  gse_status s = check_csr(M);
+  if (s == GSE_OK) s = check_solve(M->n_rows, M->n_cols, b, x, p, rep, ws, GSE_GMRES);
+  if (s != GSE_OK) return s;
+  return gmres_csr(operand_of(M), b, x, p, rep, ws, ws_bytes, (hipStream_t)stream);
+}
+
+gse_status gse_solve_history(const void* ws, int32_t cap, double* hist, int32_t* seg, void* stream) {
+  if (!ws || cap < 0 || (cap > 0 && (!hist || !seg))) return fail(GSE_ERR_ARG, "bad arguments");
+  if (cap == 0) return GSE_OK;
+  return solve_history(ws, cap, hist, seg, (hipStream_t)stream);
 }
 
 gse_status gse_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {

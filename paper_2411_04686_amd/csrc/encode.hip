@@ -203,8 +203,9 @@ __device__ __forceinline__ double value_s(uint32_t c, uint32_t h, uint32_t t1, u
   return (h >> 15) ? -mag : mag;
 }
 
-// One wave per row; row maxima of the four sums go to norm_bits (as the
-// bit patterns of non-negative doubles, whose integer order is their order).
+// Eight lanes per row, grid-stride over rows; the row maxima of the four
+// sums are reduced per workgroup and then merged into norm_bits (the bit
+// patterns of non-negative doubles order like the values).
 __global__ __launch_bounds__(256) void k_eta(const int32_t* __restrict__ row_ptr, int n_rows,
                                              const double* __restrict__ val,
                                              const uint32_t* __restrict__ col_idx,
@@ -213,39 +214,47 @@ __global__ __launch_bounds__(256) void k_eta(const int32_t* __restrict__ row_ptr
                                              const uint32_t* __restrict__ tail2,
                                              EncodeScratch* sc) {
   __shared__ int sem_s[GSE_MAX_EXP];
+  __shared__ double red[4][kWaves];
   if (threadIdx.x < GSE_MAX_EXP) sem_s[threadIdx.x] = sc->sem[threadIdx.x];
   __syncthreads();
   int S[GSE_MAX_EXP];
 #pragma unroll
   for (int k = 0; k < GSE_MAX_EXP; ++k) S[k] = sem_s[k];
-  const int lane = threadIdx.x & 63;
-  const int gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int nw = (gridDim.x * blockDim.x) >> 6;
-  double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
-  for (int r = gw; r < n_rows; r += nw) {
-    double a = 0.0, e1 = 0.0, e2 = 0.0, e3 = 0.0;
-    for (int j = row_ptr[r] + lane; j < row_ptr[r + 1]; j += 64) {
+  const int sub = threadIdx.x & 7;
+  const int grp = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const int ngrp = (gridDim.x * blockDim.x) >> 3;
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int r = grp; r < n_rows; r += ngrp) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    const int e = row_ptr[r + 1];
+    for (int j = row_ptr[r] + sub; j < e; j += 8) {
       const double v = val[j];
       const uint32_t c = col_idx[j], h = head[j], t1 = tail1[j], t2 = tail2[j];
-      a += fabs(v);
-      e1 += fabs(v - value_s(c, h, t1, t2, S, 1));
-      e2 += fabs(v - value_s(c, h, t1, t2, S, 2));
-      e3 += fabs(v - value_s(c, h, t1, t2, S, 3));
+      a[0] += fabs(v);
+      a[1] += fabs(v - value_s(c, h, t1, t2, S, 1));
+      a[2] += fabs(v - value_s(c, h, t1, t2, S, 2));
+      a[3] += fabs(v - value_s(c, h, t1, t2, S, 3));
     }
-    a = wave_sum(a);
-    e1 = wave_sum(e1);
-    e2 = wave_sum(e2);
-    e3 = wave_sum(e3);
-    m0 = fmax(m0, a);
-    m1 = fmax(m1, e1);
-    m2 = fmax(m2, e2);
-    m3 = fmax(m3, e3);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double t = a[q];
+      t += __shfl_xor(t, 4, 64);
+      t += __shfl_xor(t, 2, 64);
+      t += __shfl_xor(t, 1, 64);
+      m[q] = fmax(m[q], t);
+    }
   }
-  if (lane == 0) {
-    atomicMax(&sc->norm_bits[0], (unsigned long long)double_to_bits(m0));
-    atomicMax(&sc->norm_bits[1], (unsigned long long)double_to_bits(m1));
-    atomicMax(&sc->norm_bits[2], (unsigned long long)double_to_bits(m2));
-    atomicMax(&sc->norm_bits[3], (unsigned long long)double_to_bits(m3));
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double t = m[q];
+    for (int off = 32; off >= 1; off >>= 1) t = fmax(t, __shfl_xor(t, off, 64));
+    if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double t = 0.0;
+    for (int w = 0; w < kWaves; ++w) t = fmax(t, red[threadIdx.x][w]);
+    atomicMax(&sc->norm_bits[threadIdx.x], (unsigned long long)double_to_bits(t));
   }
 }
 
@@ -268,8 +277,8 @@ hipError_t launch_encode(const int32_t* row_ptr, const int32_t* col, const doubl
   eb = eb < 1 ? 1 : (eb > 16384 ? 16384 : eb);
   hipLaunchKernelGGL(k_encode, dim3(eb), dim3(256), 0, st, val, col, nnz, sc, A->col_idx, A->head,
                      A->tail1, A->tail2);
-  int rbk = (n_rows + 3) / 4;
-  rbk = rbk < 1 ? 1 : (rbk > 16384 ? 16384 : rbk);
+  int rbk = (n_rows + 31) / 32;
+  rbk = rbk < 1 ? 1 : (rbk > 1024 ? 1024 : rbk);
   hipLaunchKernelGGL(k_eta, dim3(rbk), dim3(256), 0, st, row_ptr, n_rows, val, A->col_idx, A->head,
                      A->tail1, A->tail2, sc);
   return hipGetLastError();

@@ -16,6 +16,9 @@ constexpr int kDefaultTile = 2048;
 constexpr int kExtra = 256;         // look-ahead elements staged for a crossing row
 constexpr int kPadTo = 16;          // planes hold nnz rounded up to this
 constexpr int kShortRow = 24;       // rows up to this length: one thread, serial sum
+constexpr int kSpec = 16;           // look-ahead non-zeros loaded before the row lookup
+constexpr int kRowStage = 1024;     // row pointers staged in LDS per tile
+constexpr int kRvBatch = 8;         // row-vector schedule: rows per lane group in flight
 constexpr int64_t kMaxNnz = (int64_t(1) << 31) - (int64_t(1) << 16);
 
 // Format identifiers for the SpMV templates: 1..3 = GSE-SEM with s segments,
@@ -58,27 +61,12 @@ __device__ __forceinline__ double block_sum(double v, double* red /* [kWaves] */
   return s;
 }
 
-// "Last workgroup" protocol: every workgroup publishes its partial; the one
-// that arrives last sees all of them (release/acquire at agent scope, i.e.
-// across the XCDs' L2 caches).  Returns true in that workgroup only.
-__device__ __forceinline__ bool last_block_arrive(unsigned* counter, bool* flag) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned t = atomicAdd(counter, 1u);
-    *flag = (t == gridDim.x - 1);
-  }
-  __syncthreads();
-  const bool last = *flag;
-  if (last) __threadfence();
-  return last;
-}
-
-// Sum of partials[0..n) by one workgroup in a fixed order.
+// Sum of partials[0..n) by one workgroup in a fixed order (every thread
+// gets the result).  The partials come from an earlier kernel on the same
+// stream, so the launch boundary has made them visible.
 __device__ __forceinline__ double sum_partials(const double* partials, int n, double* red) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += kWG)
-    s += __hip_atomic_load(partials + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int i = threadIdx.x; i < n; i += kWG) s += partials[i];
   return block_sum(s, red);
 }
 
@@ -99,16 +87,16 @@ struct SpmvOperand {
   int32_t n_tiles;
   int32_t tile_nnz;
   int32_t nnz;
+  int32_t rv_lanes;          // > 0: row-vector schedule with this many lanes per row
   int16_t sem[GSE_MAX_EXP];
 };
 
 struct SpmvEpilogue {
   int epi;                 // Epi
   const double* aux;       // kEpiDot: vector dotted with y (x itself for CG); kEpiResid: b
-  double* partials;        // [n_tiles] per-workgroup partial dots
-  unsigned* counter;       // last-workgroup counter (returns to 0 after the launch)
-  double* result;          // kEpiDot / kEpiResid: the finished dot
+  double* partials;        // [grid] per-workgroup partial dots (kEpiDot / kEpiResid)
   const int* gate;         // if non-null and *gate != 0 the launch does nothing
+  int* grid_out;           // host: receives the number of workgroups (= partials written)
 };
 
 hipError_t launch_spmv(int fmt, const SpmvOperand& A, const double* x, double* y,
@@ -116,6 +104,7 @@ hipError_t launch_spmv(int fmt, const SpmvOperand& A, const double* x, double* y
 hipError_t launch_plan(const int32_t* row_ptr, int32_t n_rows, int32_t nnz, int32_t tile_nnz,
                        int32_t n_tiles, int32_t* tile_row, hipStream_t st);
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
+hipError_t launch_rowmax(const int32_t* row_ptr, int32_t n_rows, int* out, hipStream_t st);
 
 // Device record of gse_encode (lives at the start of the encode workspace).
 struct EncodeScratch {
@@ -134,5 +123,19 @@ hipError_t launch_encode(const int32_t* row_ptr, const int32_t* col, const doubl
                          gse_matrix* A, EncodeScratch* sc, hipStream_t st);
 
 int32_t n_tiles_for(int64_t nnz, int32_t tile_nnz);
+
+// solvers.hip
+size_t solver_workspace_bytes(int32_t method, int32_t n_rows, int64_t nnz, int32_t restart,
+                              int32_t max_iter);
+gse_status cg_gse(const gse_matrix* A, const SpmvOperand& op, const double* b, double* x,
+                  const gse_params* p, gse_report* rep, void* ws, size_t ws_bytes, hipStream_t st);
+gse_status cg_csr(const SpmvOperand& op, const double* b, double* x, const gse_params* p,
+                  gse_report* rep, void* ws, size_t ws_bytes, hipStream_t st);
+gse_status gmres_gse(const gse_matrix* A, const SpmvOperand& op, const double* b, double* x,
+                     const gse_params* p, gse_report* rep, void* ws, size_t ws_bytes,
+                     hipStream_t st);
+gse_status gmres_csr(const SpmvOperand& op, const double* b, double* x, const gse_params* p,
+                     gse_report* rep, void* ws, size_t ws_bytes, hipStream_t st);
+gse_status solve_history(const void* ws, int32_t cap, double* hist, int32_t* seg, hipStream_t st);
 
 }  // namespace gse

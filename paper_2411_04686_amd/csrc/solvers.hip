@@ -1,0 +1,952 @@
+// solvers.hip -- stepped mixed-precision CG and GMRES(m) on gfx950.
+//
+// Only the operator reads reduced segments; dot products, residuals and the
+// x / r / p updates are FP64 (Section IV-D.3).  The iteration runs on the
+// device: scalars (rho, alpha, beta, the residual history, the segment
+// count) live in a state record in the workspace, reductions finish in the
+// last workgroup of the kernel that produced them (fixed order, so results
+// are reproducible), and the stepped controller of Section III-D
+// (Algorithm 3, Eqs. 3-6, Conditions 1-3) runs in that workgroup too.  The
+// host launches chunks of iterations and reads the state back between
+// chunks; a stop (switch, convergence candidate, breakdown, cap) makes the
+// rest of the chunk a no-op.
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+
+#include "gse_internal.h"
+
+namespace gse {
+
+gse_status fail(gse_status code, const char* fmt, ...);
+gse_status hip_fail(hipError_t e, const char* where);
+
+namespace {
+
+enum Stop : int { kRun = 0, kConv = 1, kSwitch = 2, kBreak = 3, kCap = 4 };
+
+// Device-resident solver state.
+struct SolverState {
+  double rho;        // r.r
+  double pq;         // p.q (CG) or scratch dot
+  double alpha, beta;
+  double nb;         // ||b||
+  double nb2;        // b.b
+  double relres;     // current recursive residual / ||b||
+  double tol;
+  double eta[3];
+  double floor_c;
+  double rsd_limit, reldec_limit;
+  double scratch[4];
+  int it;            // completed iterations
+  int s;             // segment count in use (0: FP64 CSR)
+  int stop;          // Stop
+  int trig;          // trigger of a switch
+  int k3_armed;      // CG: the x/p update of the last completed iteration is pending
+  int max_iter;
+  int stepped;
+  int fixed;
+  int l, t, m, ndec_limit, ndec_rule;
+  int pad0;
+  long long hist_off;  // byte offsets of the residual / segment histories
+  long long seg_off;   // in the workspace (read by gse_solve_history)
+  int hist_cap;
+  int pad1;
+};
+
+constexpr int kVecBlocks = 2048;
+
+// ------------------------------------------------------------ controller --
+// Conditions 1-3 at j = l + q*m once t residuals exist (Section III-D).
+// RSD (Eq. 3): population standard deviation over resid[j-t..j-1] divided
+// by their mean; nDec (Eqs. 4-5): decreases resid[i] > resid[i+1] for
+// i = j-t..j-1; relDec (Eq. 6): (resid[j-t] - resid[j-1]) / resid[j-t].
+// Called by every thread of one workgroup; returns the trigger (1..3) or 0.
+__device__ int grid_conditions(const SolverState* S, const double* hist, int j, double* red) {
+  const int t = S->t;
+  double sum = 0.0;
+  for (int i = threadIdx.x; i < t; i += kWG) sum += hist[j - t + i];
+  const double avg = block_sum(sum, red) / (double)t;
+  double var = 0.0, dec = 0.0;
+  for (int i = threadIdx.x; i < t; i += kWG) {
+    const double d = hist[j - t + i] - avg;
+    var += d * d;
+    dec += (hist[j - t + i] > hist[j - t + i + 1]) ? 1.0 : 0.0;
+  }
+  var = block_sum(var, red) / (double)t;
+  const int ndec = (int)block_sum(dec, red);
+  const double rsd = sqrt(var) / avg;
+  const double reldec = (hist[j - t] - hist[j - 1]) / hist[j - t];
+  bool below;
+  if (S->ndec_rule == 1) below = 2 * ndec < t;
+  else below = ndec < S->ndec_limit;
+  if (rsd > S->rsd_limit && below) return GSE_TRIG_C1;
+  if (!below && reldec < S->reldec_limit) return GSE_TRIG_C2;
+  if (ndec == 0) return GSE_TRIG_C3;
+  return GSE_TRIG_NONE;
+}
+
+// After iteration j recorded relres (values broadcast through LDS by the
+// caller): convergence, the floor and tolerance triggers, Conditions 1-3 on
+// the check grid, the cap.  Every thread of the workgroup calls it.
+__device__ void controller(SolverState* S, const double* hist, double* red, int j, double relres,
+                           int s) {
+  const bool exact_op = S->fixed != 0 || s >= 3 || S->eta[s - 1] == 0.0;
+  const bool on_grid = S->stepped && s < 3 && relres > S->tol && j >= S->l && j >= S->t &&
+                       S->m > 0 && ((j - S->l) % S->m) == 0;
+  int cond = GSE_TRIG_NONE;
+  if (on_grid) cond = grid_conditions(S, hist, j, red);  // uniform branch
+  if (threadIdx.x == 0) {
+    int stop = kRun, trig = GSE_TRIG_NONE;
+    if (relres <= S->tol) {
+      if (exact_op) stop = kConv;
+      else { stop = kSwitch; trig = GSE_TRIG_TOL; }
+    } else if (S->stepped && s < 3) {
+      const double eta = S->eta[s - 1];
+      if (S->floor_c > 0.0 && eta > 0.0 && relres <= S->floor_c * eta) {
+        stop = kSwitch;
+        trig = GSE_TRIG_FLOOR;
+      } else if (cond != GSE_TRIG_NONE) {
+        stop = kSwitch;
+        trig = cond;
+      }
+    }
+    if (stop == kRun && j >= S->max_iter) stop = kCap;
+    S->stop = stop;
+    S->trig = trig;
+  }
+}
+
+// ------------------------------------------------------------- finisher ---
+// out[k] = sum over i < n of partials[k*stride + i], k < nk, in a fixed order
+// (one workgroup; the partials were written by the previous kernel).
+__global__ __launch_bounds__(kWG) void k_finish(const double* __restrict__ partials, int n,
+                                                int stride, int nk, double* __restrict__ out,
+                                                const int* gate) {
+  __shared__ double red[kWaves];
+  if (gate && *gate) return;
+  for (int k = 0; k < nk; ++k) {
+    const double t = sum_partials(partials + (size_t)k * stride, n, red);
+    if (threadIdx.x == 0) out[k] = t;
+  }
+}
+
+// ----------------------------------------------------------- CG kernels ---
+// After q = A_s p (partials of p.q): alpha = rho / p.q, or a breakdown.
+// Also disarms the x/p update of the previous iteration (always runs).
+__global__ __launch_bounds__(kWG) void k_cg_alpha(SolverState* S, const double* __restrict__ partials,
+                                                  int n) {
+  __shared__ double red[kWaves];
+  if (threadIdx.x == 0) S->k3_armed = 0;
+  if (S->stop) return;
+  const double pq = sum_partials(partials, n, red);
+  if (threadIdx.x == 0) {
+    S->pq = pq;
+    if (!(pq > 0.0) || !isfinite(pq)) S->stop = kBreak;
+    else S->alpha = S->rho / pq;
+  }
+}
+
+// r -= alpha q, partials of r.r
+__global__ __launch_bounds__(kWG) void k_cg_rupdate(const SolverState* S, double* __restrict__ r,
+                                                    const double* __restrict__ q, int n,
+                                                    double* __restrict__ partials) {
+  __shared__ double red[kWaves];
+  if (S->stop) return;
+  const double alpha = S->alpha;
+  double acc = 0.0;
+  const int n2 = n >> 1;
+  double2* r2 = reinterpret_cast<double2*>(r);
+  const double2* q2 = reinterpret_cast<const double2*>(q);
+  for (int i = blockIdx.x * kWG + threadIdx.x; i < n2; i += gridDim.x * kWG) {
+    double2 rv = r2[i];
+    const double2 qv = q2[i];
+    rv.x -= alpha * qv.x;
+    rv.y -= alpha * qv.y;
+    r2[i] = rv;
+    acc += rv.x * rv.x;
+    acc += rv.y * rv.y;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const double v = r[n - 1] - alpha * q[n - 1];
+    r[n - 1] = v;
+    acc += v * v;
+  }
+  const double bs = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+}
+
+// rho' = r.r: beta, the residual history and the controller; arms the x/p
+// update.  One workgroup.
+__global__ __launch_bounds__(kWG) void k_cg_advance(SolverState* S, const double* __restrict__ partials,
+                                                    int n, double* hist, int* seg_hist) {
+  __shared__ double red[kWaves];
+  __shared__ int bc_j, bc_s;
+  __shared__ double bc_rel;
+  if (S->stop) return;
+  const double rho_new = sum_partials(partials, n, red);
+  if (threadIdx.x == 0) {
+    const int j = S->it + 1;
+    const double rel = sqrt(rho_new) / S->nb;
+    S->beta = rho_new / S->rho;
+    S->rho = rho_new;
+    S->it = j;
+    S->relres = rel;
+    hist[j] = rel;
+    seg_hist[j] = S->s;
+    S->k3_armed = 1;
+    bc_j = j;
+    bc_s = S->s;
+    bc_rel = rel;
+  }
+  __syncthreads();
+  controller(S, hist, red, bc_j, bc_rel, bc_s);
+}
+
+// x += alpha p; p = r + beta p (the p of the finished iteration).
+__global__ __launch_bounds__(kWG) void k_cg_xpupdate(const SolverState* S, double* __restrict__ x,
+                                                     double* __restrict__ p,
+                                                     const double* __restrict__ r, int n) {
+  if (!S->k3_armed) return;
+  const double alpha = S->alpha, beta = S->beta;
+  const int n2 = n >> 1;
+  double2* x2 = reinterpret_cast<double2*>(x);
+  double2* p2 = reinterpret_cast<double2*>(p);
+  const double2* r2 = reinterpret_cast<const double2*>(r);
+  for (int i = blockIdx.x * kWG + threadIdx.x; i < n2; i += gridDim.x * kWG) {
+    double2 xv = x2[i];
+    double2 pv = p2[i];
+    const double2 rv = r2[i];
+    xv.x += alpha * pv.x;
+    xv.y += alpha * pv.y;
+    pv.x = rv.x + beta * pv.x;
+    pv.y = rv.y + beta * pv.y;
+    x2[i] = xv;
+    p2[i] = pv;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    x[n - 1] += alpha * p[n - 1];
+    p[n - 1] = r[n - 1] + beta * p[n - 1];
+  }
+}
+
+// dst = src (n doubles)
+__global__ __launch_bounds__(kWG) void k_copy(double* __restrict__ dst, const double* __restrict__ src,
+                                              int n) {
+  for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) dst[i] = src[i];
+}
+
+// partials of a.b (grid-stride; one partial per workgroup)
+__global__ __launch_bounds__(kWG) void k_dot(const double* __restrict__ a, const double* __restrict__ b,
+                                             int n, double* __restrict__ partials) {
+  __shared__ double red[kWaves];
+  double acc = 0.0;
+  for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) acc += a[i] * b[i];
+  const double bs = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+}
+
+// ---------------------------------------------------------------- layout --
+struct Workspace {
+  SolverState* S;
+  double* partials;    // [np] per-workgroup partial sums
+  double* partials2;   // [np] a second set (two reductions in flight)
+  double* r;
+  double* p;
+  double* q;
+  double* w;
+  double* hist;        // [max_iter + 2]
+  int* seg_hist;       // [max_iter + 2]
+  double* gm;          // GMRES: V (restart+1) x n, then small arrays
+  size_t bytes;
+};
+
+size_t align_up(size_t v) { return (v + 255) / 256 * 256; }
+
+int64_t partial_entries(int32_t n_rows, int64_t nnz) {
+  int64_t a = (int64_t)n_tiles_for(nnz, kMinTile) + 16;
+  int64_t b = (int64_t)n_rows / 32 + 16;
+  int64_t c = (int64_t)64 * 1024 + 16;  // GMRES multi-dot partials (k x workgroups)
+  int64_t m = a > b ? a : b;
+  return m > c ? m : c;
+}
+
+// Small per-cycle GMRES arrays: H (m+1) x m, cs, sn, g, y, h scratch.
+int64_t gmres_small_entries(int32_t restart) {
+  const int64_t m = restart;
+  return (m + 1) * m + 4 * (m + 1) + 2 * (m + 1);
+}
+
+Workspace carve(void* base, int32_t method, int32_t n_rows, int64_t nnz, int32_t restart,
+                int32_t max_iter) {
+  Workspace w{};
+  char* p = reinterpret_cast<char*>(base);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* q = p ? p + off : nullptr;
+    off += align_up(bytes);
+    return q;
+  };
+  const size_t n = (size_t)(n_rows > 0 ? n_rows : 1);
+  w.S = reinterpret_cast<SolverState*>(take(sizeof(SolverState)));
+  w.partials = reinterpret_cast<double*>(take((size_t)partial_entries(n_rows, nnz) * sizeof(double)));
+  w.partials2 = reinterpret_cast<double*>(take((size_t)partial_entries(n_rows, nnz) * sizeof(double)));
+  w.r = reinterpret_cast<double*>(take(n * sizeof(double)));
+  w.p = reinterpret_cast<double*>(take(n * sizeof(double)));
+  w.q = reinterpret_cast<double*>(take(n * sizeof(double)));
+  w.w = reinterpret_cast<double*>(take(n * sizeof(double)));
+  w.hist = reinterpret_cast<double*>(take((size_t)(max_iter + 2) * sizeof(double)));
+  w.seg_hist = reinterpret_cast<int*>(take((size_t)(max_iter + 2) * sizeof(int)));
+  if (method == GSE_GMRES) {
+    w.gm = reinterpret_cast<double*>(
+        take(((size_t)(restart + 1) * n + (size_t)gmres_small_entries(restart)) * sizeof(double)));
+  }
+  w.bytes = off;
+  return w;
+}
+
+int vec_blocks(int n) {
+  int b = (n / 2 + kWG - 1) / kWG;
+  if (b < 1) b = 1;
+  return b > kVecBlocks ? kVecBlocks : b;
+}
+
+struct Operator {
+  int fmt;  // 1..3 GSE (stepped), 0 FP64 CSR
+  SpmvOperand op;
+  const double* eta;
+};
+
+// y = A_s x; with kEpiDot the dot aux.y, with kEpiResid y = b - A_s x and
+// y.y, are left as per-workgroup partials (their count in *grid) and, if
+// `result` is given, summed into *result by a one-workgroup finisher.
+hipError_t apply(const Operator& A, int s, const double* x, double* y, int epi, const double* aux,
+                 double* result, const Workspace& w, const int* gate, hipStream_t st,
+                 int* grid = nullptr) {
+  SpmvEpilogue ep{};
+  int g = 0;
+  ep.epi = epi;
+  ep.aux = aux;
+  ep.partials = w.partials;
+  ep.gate = gate;
+  ep.grid_out = &g;
+  hipError_t e = launch_spmv(A.fmt == 0 ? 0 : s, A.op, x, y, ep, st);
+  if (e != hipSuccess) return e;
+  if (grid) *grid = g;
+  if (result && epi != kEpiPlain) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kWG), 0, st, w.partials, g, 0, 1, result, gate);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t read_state(const Workspace& w, SolverState* h, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync(h, w.S, sizeof(SolverState), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e;
+}
+
+hipError_t write_state(const Workspace& w, const SolverState* h, hipStream_t st) {
+  return hipMemcpyAsync(w.S, h, sizeof(SolverState), hipMemcpyHostToDevice, st);
+}
+
+void init_state(SolverState* S, const gse_params* p, const Operator& A, int s0) {
+  memset(S, 0, sizeof *S);
+  S->tol = p->tol;
+  for (int i = 0; i < 3; ++i) S->eta[i] = A.eta ? A.eta[i] : 0.0;
+  S->floor_c = p->floor_c;
+  S->rsd_limit = p->rsd_limit;
+  S->reldec_limit = p->reldec_limit;
+  S->s = s0;
+  S->max_iter = p->max_iter;
+  S->stepped = (A.fmt != 0 && p->fixed_segments == 0) ? 1 : 0;
+  S->fixed = (A.fmt == 0) ? -1 : p->fixed_segments;
+  S->l = p->l;
+  S->t = p->t;
+  S->m = p->m;
+  S->ndec_limit = p->ndec_limit;
+  S->ndec_rule = p->ndec_rule;
+}
+
+// ------------------------------------------------------------------- CG ---
+gse_status run_cg(const Operator& A, const double* b, double* x, const gse_params* p,
+                  gse_report* rep, void* ws, size_t ws_bytes, hipStream_t st) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int n = A.op.n_rows;
+  Workspace w = carve(ws, GSE_CG, n, A.op.nnz, p->restart, p->max_iter);
+  if (w.bytes > ws_bytes) return fail(GSE_ERR_NOMEM, "solver workspace needs %zu bytes", w.bytes);
+  memset(rep, 0, sizeof *rep);
+  rep->switch_iter[0] = rep->switch_iter[1] = -1;
+  const bool stepped = A.fmt != 0 && p->fixed_segments == 0;
+  int s = (A.fmt == 0) ? 0 : (stepped ? p->start_segments : p->fixed_segments);
+  const int s_final = (A.fmt == 0) ? 0 : 3;
+  const int vb = vec_blocks(n);
+  hipError_t e;
+  SolverState h;
+  init_state(&h, p, A, s);
+  h.hist_off = (long long)((char*)w.hist - (char*)ws);
+  h.seg_off = (long long)((char*)w.seg_hist - (char*)ws);
+  h.hist_cap = p->max_iter + 2;
+  int nsw = 0;
+  gse_status status = GSE_NOT_CONVERGED;
+  // replacement: r = b - A_s x, rho = r.r, optionally p = r
+  auto restart = [&](int s_use, bool reset_p) -> hipError_t {
+    hipError_t err = apply(A, s_use, x, w.r, kEpiResid, b, &w.S->rho, w, nullptr, st);
+    if (err == hipSuccess && reset_p) {
+      hipLaunchKernelGGL(k_copy, dim3(vb), dim3(kWG), 0, st, w.p, w.r, n);
+      err = hipGetLastError();
+    }
+    return err;
+  };
+  auto true_relres = [&](double* out) -> hipError_t {
+    hipError_t err = apply(A, s_final, x, w.w, kEpiResid, b, &w.S->scratch[0], w, nullptr, st);
+    if (err != hipSuccess) return err;
+    SolverState t;
+    err = read_state(w, &t, st);
+    *out = t.nb > 0.0 ? sqrt(t.scratch[0]) / t.nb : 0.0;
+    return err;
+  };
+  e = write_state(w, &h, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_dot, dim3(vb), dim3(kWG), 0, st, b, b, n, w.partials);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kWG), 0, st, w.partials, vb, 0, 1, &w.S->nb2,
+                       nullptr);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = restart(s, true);
+  if (e == hipSuccess) e = read_state(w, &h, st);
+  if (e != hipSuccess) return hip_fail(e, "cg setup");
+  h.nb = sqrt(h.nb2);
+  if (h.nb == 0.0) {
+    e = hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "cg");
+    rep->status = GSE_OK;
+    return GSE_OK;
+  }
+  h.relres = sqrt(h.rho) / h.nb;
+  double h0 = h.relres;
+  int s0i = s;
+  e = hipMemcpyAsync(w.hist, &h0, sizeof h0, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(w.seg_hist, &s0i, sizeof s0i, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = write_state(w, &h, st);
+  if (e != hipSuccess) return hip_fail(e, "cg setup");
+
+  int chunk = 4;
+  bool done = false;
+  bool pending_check = h.relres <= p->tol;  // converged at x0 already
+  while (!done) {
+    if (pending_check) {
+      h.stop = kConv;
+    } else {
+      for (int k = 0; k < chunk; ++k) {
+        int g1 = 0;
+        e = apply(A, h.s, w.p, w.q, kEpiDot, w.p, nullptr, w, &w.S->stop, st, &g1);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(kWG), 0, st, w.S, w.partials, g1);
+        hipLaunchKernelGGL(k_cg_rupdate, dim3(vb), dim3(kWG), 0, st, w.S, w.r, w.q, n, w.partials2);
+        hipLaunchKernelGGL(k_cg_advance, dim3(1), dim3(kWG), 0, st, w.S, w.partials2, vb, w.hist,
+                           w.seg_hist);
+        hipLaunchKernelGGL(k_cg_xpupdate, dim3(vb), dim3(kWG), 0, st, w.S, x, w.p, w.r, n);
+        e = hipGetLastError();
+        if (e != hipSuccess) break;
+      }
+      if (e == hipSuccess) e = read_state(w, &h, st);
+      if (e != hipSuccess) return hip_fail(e, "cg iterations");
+      chunk = chunk < 64 ? chunk * 2 : 64;
+      if (h.stop == kRun) continue;
+    }
+    pending_check = false;
+    int reason = h.stop;
+    int trig = h.trig;
+    if (reason == kBreak) {
+      if (stepped && h.s < 3) {
+        reason = kSwitch;
+        trig = GSE_TRIG_BREAKDOWN;
+      } else {
+        status = GSE_ERR_BREAKDOWN;
+        break;
+      }
+    }
+    if (reason == kConv) {
+      double rt = 0.0;
+      e = true_relres(&rt);
+      if (e != hipSuccess) return hip_fail(e, "cg check");
+      if (rt <= p->tol) {
+        status = GSE_OK;
+        break;
+      }
+      // the recursive residual drifted from the true one: replace it
+      SolverState t;
+      e = restart(h.s, true);
+      if (e == hipSuccess) e = read_state(w, &t, st);
+      if (e != hipSuccess) return hip_fail(e, "cg replace");
+      h.rho = t.rho;
+      h.relres = sqrt(h.rho) / h.nb;
+      if (h.relres <= p->tol || h.it >= p->max_iter) break;
+    } else if (reason == kSwitch) {
+      if (nsw < 2) {
+        rep->switch_iter[nsw] = h.it;
+        rep->switch_trigger[nsw] = trig;
+      }
+      ++nsw;
+      h.s += 1;
+      SolverState t;
+      e = restart(h.s, p->switch_mode == 0);
+      if (e == hipSuccess) e = read_state(w, &t, st);
+      if (e != hipSuccess) return hip_fail(e, "cg switch");
+      h.rho = t.rho;
+      h.relres = sqrt(h.rho) / h.nb;
+      if (h.relres <= p->tol) pending_check = true;
+    } else if (reason == kCap) {
+      break;
+    }
+    if (h.it >= p->max_iter) break;
+    h.stop = kRun;
+    h.trig = 0;
+    h.k3_armed = 0;
+    chunk = 4;
+    e = write_state(w, &h, st);
+    if (e != hipSuccess) return hip_fail(e, "cg state");
+  }
+  // final report
+  SolverState f;
+  e = read_state(w, &f, st);
+  if (e != hipSuccess) return hip_fail(e, "cg report");
+  double rt = 0.0;
+  e = true_relres(&rt);
+  if (e != hipSuccess) return hip_fail(e, "cg report");
+  rep->status = status;
+  rep->iters = f.it;
+  rep->relres_recursive = f.relres;
+  rep->relres_true = rt;
+  {
+    // iterations per segment count from the segment history
+    const int cnt = f.it;
+    int* seg = new int[(size_t)cnt + 1];
+    e = hipMemcpyAsync(seg, w.seg_hist, sizeof(int) * (size_t)(cnt + 1), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      delete[] seg;
+      return hip_fail(e, "cg report");
+    }
+    for (int i = 1; i <= cnt; ++i) {
+      const int sg = seg[i] <= 0 ? 3 : seg[i];
+      rep->iters_per_seg[sg - 1] += 1;
+    }
+    delete[] seg;
+  }
+  rep->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return status;
+}
+
+
+// ----------------------------------------------------------- GMRES(m) ---
+// Arnoldi with classical Gram-Schmidt applied twice (CGS2); V holds m+1
+// basis vectors of n entries; small arrays: H (m+1) x m row-major, cs, sn,
+// g (m+1 each), h2 scratch.  Per step j (device, gated on stop):
+//   w = A_s v_j                       (SpMV into v_{j+1})
+//   h = V^T w                         (k_gm_dots, pass 1)
+//   w -= V h ; h2 = V^T w             (k_gm_axpy_dots, pass 2)
+//   w -= V h2 ; ||w||, H[:,j] = h+h2  (k_gm_axpy_norm, pass 3; the last
+//                                      workgroup applies the Givens
+//                                      rotations and runs the controller)
+//   v_{j+1} = w / ||w||               (k_gm_scale)
+constexpr int kGmBlocks = 1024;
+
+struct GmSmall {
+  double* H;
+  double* cs;
+  double* sn;
+  double* g;
+  double* h2;
+};
+
+template <int JB>
+__global__ __launch_bounds__(kWG) void k_gm_dots(const SolverState* S, const double* __restrict__ V,
+                                                 const double* __restrict__ w, int n, size_t ld,
+                                                 int j, double* __restrict__ partials) {
+  __shared__ double red[kWaves];
+  if (S->stop) return;
+  double acc[JB];
+#pragma unroll
+  for (int k = 0; k < JB; ++k) acc[k] = 0.0;
+  for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
+    const double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < JB; ++k)
+      if (k <= j) acc[k] += V[(size_t)k * ld + i] * wi;
+  }
+#pragma unroll
+  for (int k = 0; k < JB; ++k) {
+    if (k <= j) {
+      const double bs = block_sum(acc[k], red);
+      if (threadIdx.x == 0) partials[(size_t)k * gridDim.x + blockIdx.x] = bs;
+    }
+  }
+}
+
+// w -= V h (h finished from the previous pass); then partials of V_k . w,
+// or (NORM) of w.w.
+template <int JB, bool NORM>
+__global__ __launch_bounds__(kWG) void k_gm_axpy(const SolverState* S, const double* __restrict__ V,
+                                                 double* __restrict__ w, int n, size_t ld, int j,
+                                                 const double* __restrict__ h,
+                                                 double* __restrict__ partials) {
+  __shared__ double red[kWaves];
+  __shared__ double hs[JB];
+  if (S->stop) return;
+  if (threadIdx.x < JB) hs[threadIdx.x] = (threadIdx.x <= j) ? h[threadIdx.x] : 0.0;
+  __syncthreads();
+  constexpr int NA = NORM ? 1 : JB;
+  double acc[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) acc[k] = 0.0;
+  for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
+    double v[JB];
+    double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < JB; ++k)
+      if (k <= j) {
+        v[k] = V[(size_t)k * ld + i];
+        wi -= hs[k] * v[k];
+      }
+    w[i] = wi;
+    if constexpr (NORM) {
+      acc[0] += wi * wi;
+    } else {
+#pragma unroll
+      for (int k = 0; k < JB; ++k)
+        if (k <= j) acc[k] += v[k] * wi;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    if (k <= j) {
+      const double bs = block_sum(acc[k], red);
+      if (threadIdx.x == 0) partials[(size_t)k * gridDim.x + blockIdx.x] = bs;
+    }
+  }
+}
+
+// The Arnoldi column j is complete: H[:,j] = h1 + h2, H[j+1,j] = ||w||
+// (from the norm partials); rotations, residual estimate, controller.
+// One workgroup.
+__global__ __launch_bounds__(kWG) void k_gm_givens(SolverState* S, GmSmall sm, int m, int j,
+                                                   const double* __restrict__ h1,
+                                                   const double* __restrict__ h2,
+                                                   const double* __restrict__ norm_partials,
+                                                   int n_partials, double* hist, int* seg_hist) {
+  __shared__ double red[kWaves];
+  __shared__ int bc_j, bc_s, bc_go;
+  __shared__ double bc_rel;
+  if (S->stop) return;
+  const double wn2 = sum_partials(norm_partials, n_partials, red);
+  if (threadIdx.x == 0) {
+    double* Hc = sm.H;  // row-major (m+1) x m
+    for (int i = 0; i <= j; ++i) Hc[(size_t)i * m + j] = h1[i] + h2[i];
+    const double hn = sqrt(wn2);
+    Hc[(size_t)(j + 1) * m + j] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double a = Hc[(size_t)i * m + j], b = Hc[(size_t)(i + 1) * m + j];
+      Hc[(size_t)i * m + j] = sm.cs[i] * a + sm.sn[i] * b;
+      Hc[(size_t)(i + 1) * m + j] = -sm.sn[i] * a + sm.cs[i] * b;
+    }
+    const double a = Hc[(size_t)j * m + j], b = Hc[(size_t)(j + 1) * m + j];
+    const double rr = sqrt(a * a + b * b);
+    const double c = rr == 0.0 ? 1.0 : a / rr;
+    const double sv = rr == 0.0 ? 0.0 : b / rr;
+    sm.cs[j] = c;
+    sm.sn[j] = sv;
+    Hc[(size_t)j * m + j] = c * a + sv * b;
+    Hc[(size_t)(j + 1) * m + j] = 0.0;
+    sm.g[j + 1] = -sv * sm.g[j];
+    sm.g[j] = c * sm.g[j];
+    const int it = S->it + 1;
+    const double rel = fabs(sm.g[j + 1]) / S->nb;
+    S->it = it;
+    S->relres = rel;
+    S->scratch[1] = hn;     // norm of the new basis vector
+    S->scratch[2] = j + 1;  // columns completed in this cycle
+    hist[it] = rel;
+    seg_hist[it] = S->s;
+    bc_j = it;
+    bc_s = S->s;
+    bc_rel = rel;
+    bc_go = hn != 0.0;
+    if (hn == 0.0) S->stop = kConv;  // exact in this space: end the cycle
+  }
+  __syncthreads();
+  if (bc_go) controller(S, hist, red, bc_j, bc_rel, bc_s);
+}
+
+// v_{j+1} = w / ||w|| in place (only while the cycle goes on)
+__global__ __launch_bounds__(kWG) void k_gm_scale(SolverState* S, double* __restrict__ w, int n) {
+  if (S->stop) return;
+  const double hn = S->scratch[1];
+  const double inv = 1.0 / hn;
+  for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) w[i] *= inv;
+}
+
+// y = H(1:k,1:k) \ g(1:k) (every workgroup solves the small system the same
+// way), then x += V(:,1:k) y.  k = columns completed in the cycle.
+__global__ __launch_bounds__(kWG) void k_gm_update(const SolverState* S, GmSmall sm, int m,
+                                                   const double* __restrict__ V, size_t ld,
+                                                   double* __restrict__ x, int n) {
+  __shared__ double y[64];
+  const int k = (int)S->scratch[2];
+  if (threadIdx.x == 0) {
+    for (int i = k - 1; i >= 0; --i) {
+      double acc = sm.g[i];
+      for (int q = i + 1; q < k; ++q) acc -= sm.H[(size_t)i * m + q] * y[q];
+      y[i] = acc / sm.H[(size_t)i * m + i];
+    }
+  }
+  __syncthreads();
+  for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
+    double xi = x[i];
+    for (int q = 0; q < k; ++q) xi += y[q] * V[(size_t)q * ld + i];
+    x[i] = xi;
+  }
+}
+
+// v_0 = r / beta (r already in v_0), g = beta e_1, cycle bookkeeping reset.
+__global__ __launch_bounds__(kWG) void k_gm_start(SolverState* S, GmSmall sm, int m,
+                                                  double* __restrict__ v0, int n) {
+  const double beta = sqrt(S->rho);
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+  for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) v0[i] *= inv;
+  if (blockIdx.x == 0 && threadIdx.x <= m) {
+    sm.g[threadIdx.x] = threadIdx.x == 0 ? beta : 0.0;
+    if (threadIdx.x == 0) S->scratch[2] = 0.0;
+  }
+}
+
+gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_params* p,
+                     gse_report* rep, void* ws, size_t ws_bytes, hipStream_t st) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int n = A.op.n_rows;
+  const int m = p->restart;
+  if (m > 60) return fail(GSE_ERR_ARG, "restart must be <= 60");
+  Workspace w = carve(ws, GSE_GMRES, n, A.op.nnz, m, p->max_iter);
+  if (w.bytes > ws_bytes) return fail(GSE_ERR_NOMEM, "solver workspace needs %zu bytes", w.bytes);
+  memset(rep, 0, sizeof *rep);
+  rep->switch_iter[0] = rep->switch_iter[1] = -1;
+  const bool stepped = A.fmt != 0 && p->fixed_segments == 0;
+  const int s_final = (A.fmt == 0) ? 0 : 3;
+  const size_t ld = (size_t)(n > 0 ? n : 1);
+  double* V = w.gm;
+  GmSmall sm;
+  sm.H = V + (size_t)(m + 1) * ld;
+  sm.cs = sm.H + (size_t)(m + 1) * m;
+  sm.sn = sm.cs + (m + 1);
+  sm.g = sm.sn + (m + 1);
+  sm.h2 = sm.g + (m + 1);
+  double* h1 = sm.h2 + (m + 1);  // pass-1 dots (m+1), pass-2 dots in sm.h2
+  const int vb = vec_blocks(n);
+  const int gb = vb < kGmBlocks ? vb : kGmBlocks;
+  hipError_t e;
+  SolverState h;
+  const int s_start = (A.fmt == 0) ? 0 : (stepped ? p->start_segments : p->fixed_segments);
+  init_state(&h, p, A, s_start);
+  h.hist_off = (long long)((char*)w.hist - (char*)ws);
+  h.seg_off = (long long)((char*)w.seg_hist - (char*)ws);
+  h.hist_cap = p->max_iter + 2;
+  e = write_state(w, &h, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_dot, dim3(vb), dim3(kWG), 0, st, b, b, n, w.partials);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kWG), 0, st, w.partials, vb, 0, 1, &w.S->nb2,
+                       nullptr);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = read_state(w, &h, st);
+  if (e != hipSuccess) return hip_fail(e, "gmres setup");
+  h.nb = sqrt(h.nb2);
+  if (h.nb == 0.0) {
+    e = hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "gmres");
+    rep->status = GSE_OK;
+    return GSE_OK;
+  }
+  e = write_state(w, &h, st);
+  if (e != hipSuccess) return hip_fail(e, "gmres setup");
+  int nsw = 0;
+  gse_status status = GSE_NOT_CONVERGED;
+  bool first = true;
+  for (;;) {
+    // explicit residual of the current operator into v_0
+    SolverState t;
+    e = apply(A, h.s, x, V, kEpiResid, b, &w.S->rho, w, nullptr, st);
+    if (e == hipSuccess) e = read_state(w, &t, st);
+    if (e != hipSuccess) return hip_fail(e, "gmres residual");
+    h.rho = t.rho;
+    h.relres = sqrt(h.rho) / h.nb;
+    if (first) {
+      double h0 = h.relres;
+      int s0i = h.s;
+      e = hipMemcpyAsync(w.hist, &h0, sizeof h0, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(w.seg_hist, &s0i, sizeof s0i, hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) return hip_fail(e, "gmres setup");
+      first = false;
+    }
+    int trig = GSE_TRIG_NONE;
+    if (h.relres <= p->tol) {
+      const bool exact_op = h.fixed != 0 || h.s >= 3 || h.eta[h.s - 1] == 0.0;
+      if (exact_op) {
+        status = GSE_OK;
+        break;
+      }
+      trig = GSE_TRIG_TOL;
+    }
+    if (trig != GSE_TRIG_NONE) {
+      if (nsw < 2) {
+        rep->switch_iter[nsw] = h.it;
+        rep->switch_trigger[nsw] = trig;
+      }
+      ++nsw;
+      h.s += 1;
+      continue;
+    }
+    if (h.it >= p->max_iter) break;
+    h.stop = kRun;
+    h.trig = 0;
+    e = write_state(w, &h, st);
+    if (e != hipSuccess) return hip_fail(e, "gmres state");
+    hipLaunchKernelGGL(k_gm_start, dim3(vb), dim3(kWG), 0, st, w.S, sm, m, V, n);
+    for (int j = 0; j < m && e == hipSuccess; ++j) {
+      double* vj = V + (size_t)j * ld;
+      double* wv = V + (size_t)(j + 1) * ld;
+      e = apply(A, h.s, vj, wv, kEpiPlain, nullptr, nullptr, w, &w.S->stop, st);
+      if (e != hipSuccess) break;
+      const int* gate = &w.S->stop;
+      double* P = w.partials;
+#define GSE_GM_PASSES(JB)                                                                       \
+  hipLaunchKernelGGL((k_gm_dots<JB>), dim3(gb), dim3(kWG), 0, st, w.S, V, wv, n, ld, j, P);      \
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kWG), 0, st, P, gb, gb, j + 1, h1, gate);           \
+  hipLaunchKernelGGL((k_gm_axpy<JB, false>), dim3(gb), dim3(kWG), 0, st, w.S, V, wv, n, ld, j, h1, \
+                     P);                                                                        \
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kWG), 0, st, P, gb, gb, j + 1, sm.h2, gate);        \
+  hipLaunchKernelGGL((k_gm_axpy<JB, true>), dim3(gb), dim3(kWG), 0, st, w.S, V, wv, n, ld, j,     \
+                     sm.h2, P)
+      if (j < 8) {
+        GSE_GM_PASSES(8);
+      } else if (j < 16) {
+        GSE_GM_PASSES(16);
+      } else if (j < 32) {
+        GSE_GM_PASSES(32);
+      } else {
+        GSE_GM_PASSES(64);
+      }
+#undef GSE_GM_PASSES
+      hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(kWG), 0, st, w.S, sm, m, j, h1, sm.h2, P, gb,
+                         w.hist, w.seg_hist);
+      hipLaunchKernelGGL(k_gm_scale, dim3(vb), dim3(kWG), 0, st, w.S, wv, n);
+      e = hipGetLastError();
+    }
+    if (e != hipSuccess) return hip_fail(e, "gmres cycle");
+    hipLaunchKernelGGL(k_gm_update, dim3(vb), dim3(kWG), 0, st, w.S, sm, m, V, ld, x, n);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = read_state(w, &t, st);
+    if (e != hipSuccess) return hip_fail(e, "gmres update");
+    h.it = t.it;
+    h.relres = t.relres;
+    if (t.stop == kSwitch) {
+      if (nsw < 2) {
+        rep->switch_iter[nsw] = t.it;
+        rep->switch_trigger[nsw] = t.trig;
+      }
+      ++nsw;
+      h.s += 1;
+    }
+    if (t.stop == kCap && t.it >= p->max_iter) {
+      // one more explicit residual for the report, then stop
+      break;
+    }
+  }
+  SolverState f;
+  e = read_state(w, &f, st);
+  if (e != hipSuccess) return hip_fail(e, "gmres report");
+  double rt = 0.0;
+  {
+    e = apply(A, s_final, x, w.w, kEpiResid, b, &w.S->scratch[0], w, nullptr, st);
+    SolverState t;
+    if (e == hipSuccess) e = read_state(w, &t, st);
+    if (e != hipSuccess) return hip_fail(e, "gmres report");
+    rt = sqrt(t.scratch[0]) / f.nb;
+  }
+  rep->status = status;
+  rep->iters = f.it;
+  rep->relres_recursive = h.relres;
+  rep->relres_true = rt;
+  {
+    const int cnt = f.it;
+    int* seg = new int[(size_t)cnt + 1];
+    e = hipMemcpyAsync(seg, w.seg_hist, sizeof(int) * (size_t)(cnt + 1), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      delete[] seg;
+      return hip_fail(e, "gmres report");
+    }
+    for (int i = 1; i <= cnt; ++i) {
+      const int sg = seg[i] <= 0 ? 3 : seg[i];
+      rep->iters_per_seg[sg - 1] += 1;
+    }
+    delete[] seg;
+  }
+  rep->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return status;
+}
+
+}  // namespace
+
+gse_status solve_history(const void* ws, int32_t cap, double* hist, int32_t* seg, hipStream_t st) {
+  SolverState h;
+  hipError_t e = hipMemcpyAsync(&h, ws, sizeof h, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "gse_solve_history");
+  if (h.hist_cap <= 0 || h.hist_off <= 0) return fail(GSE_ERR_ARG, "no solve recorded in this workspace");
+  int cnt = h.it + 1;
+  if (cnt > h.hist_cap) cnt = h.hist_cap;
+  if (cnt > cap) cnt = cap;
+  const char* base = reinterpret_cast<const char*>(ws);
+  e = hipMemcpyAsync(hist, base + h.hist_off, sizeof(double) * (size_t)cnt, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(seg, base + h.seg_off, sizeof(int32_t) * (size_t)cnt, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "gse_solve_history");
+  return GSE_OK;
+}
+
+size_t solver_workspace_bytes(int32_t method, int32_t n_rows, int64_t nnz, int32_t restart,
+                              int32_t max_iter) {
+  return carve(nullptr, method, n_rows, nnz, restart, max_iter).bytes;
+}
+
+gse_status cg_gse(const gse_matrix* A, const SpmvOperand& op, const double* b, double* x,
+                  const gse_params* p, gse_report* rep, void* ws, size_t ws_bytes, hipStream_t st) {
+  Operator o{1, op, A->eta};
+  return run_cg(o, b, x, p, rep, ws, ws_bytes, st);
+}
+
+gse_status cg_csr(const SpmvOperand& op, const double* b, double* x, const gse_params* p,
+                  gse_report* rep, void* ws, size_t ws_bytes, hipStream_t st) {
+  Operator o{0, op, nullptr};
+  return run_cg(o, b, x, p, rep, ws, ws_bytes, st);
+}
+
+gse_status gmres_gse(const gse_matrix* A, const SpmvOperand& op, const double* b, double* x,
+                     const gse_params* p, gse_report* rep, void* ws, size_t ws_bytes,
+                     hipStream_t st) {
+  Operator o{1, op, A->eta};
+  return run_gmres(o, b, x, p, rep, ws, ws_bytes, st);
+}
+
+gse_status gmres_csr(const SpmvOperand& op, const double* b, double* x, const gse_params* p,
+                     gse_report* rep, void* ws, size_t ws_bytes, hipStream_t st) {
+  Operator o{0, op, nullptr};
+  return run_gmres(o, b, x, p, rep, ws, ws_bytes, st);
+}
+
+}  // namespace gse

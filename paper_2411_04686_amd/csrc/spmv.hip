@@ -13,17 +13,24 @@
 //     writes are those whose first non-zero lies in that range
 //     (tile_row[t] .. tile_row[t+1]-1, from gse_plan);
 //   * phase 1: every lane loads E consecutive non-zeros with 16-byte vector
-//     loads from each plane (fully coalesced), decodes, gathers x and stores
-//     the FP64 products in LDS; up to kExtra non-zeros past the tile are
-//     staged too when the tile's last row runs over its end;
-//   * phase 2: rows of up to kShortRow non-zeros are summed by one thread in
-//     row order (the order of the sequential definition);
+//     loads from each plane (fully coalesced; issued before the row lookup),
+//     decodes them and stores value and column in LDS; up to kExtra
+//     non-zeros past the tile are staged too when the tile's last row runs
+//     over its end;
+//   * phase 2: rows of up to kShortRow non-zeros are handled by one thread,
+//     neighbouring lanes on neighbouring rows (so the x gathers of banded
+//     matrices coalesce), summed in row order (the order of the sequential
+//     definition);
 //   * phase 3: longer rows staged in LDS are summed by one wave each;
 //   * phase 4: a row that runs more than kExtra past the tile is summed by the
 //     whole workgroup, reading the rest from memory.
 // Every sum has a fixed order, so results are bit-reproducible and identical
 // whether a matrix runs alone or next to others.
 #include "gse_internal.h"
+
+#ifndef GSE_NT_LOADS
+#define GSE_NT_LOADS 1
+#endif
 
 namespace gse {
 namespace {
@@ -33,16 +40,30 @@ struct Words {
   uint32_t w[N];
 };
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <typename V>
+__device__ __forceinline__ V stream_load(const V* p) {
+#if GSE_NT_LOADS
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+
 // Load N 32-bit words from a 16-byte aligned (N % 4 == 0) or 8-byte aligned
-// (N == 2) address.
+// (N == 2) address.  The planes are streamed once per SpMV, so the loads are
+// marked non-temporal to leave L2 to the gathered x.
 template <int N>
 __device__ __forceinline__ Words<N> load_words(const void* p) {
   Words<N> r;
   if constexpr (N % 4 == 0) {
-    const uint4* q = reinterpret_cast<const uint4*>(p);
+    const u32x4* q = reinterpret_cast<const u32x4*>(p);
 #pragma unroll
     for (int i = 0; i < N / 4; ++i) {
-      const uint4 v = q[i];
+      const u32x4 v = stream_load(q + i);
       r.w[4 * i + 0] = v.x;
       r.w[4 * i + 1] = v.y;
       r.w[4 * i + 2] = v.z;
@@ -50,7 +71,7 @@ __device__ __forceinline__ Words<N> load_words(const void* p) {
     }
   } else {
     static_assert(N == 2, "unsupported vector width");
-    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    const u32x2 v = stream_load(reinterpret_cast<const u32x2*>(p));
     r.w[0] = v.x;
     r.w[1] = v.y;
   }
@@ -105,89 +126,145 @@ __device__ __forceinline__ double decode(uint32_t c, uint32_t h, uint32_t t1, ui
   }
 }
 
-// Products of the E non-zeros [base, base+E) that fall in [lo, hi); the
-// others are left untouched.  base is a multiple of E.
+// Raw plane data of E consecutive non-zeros [base, base+E), base % E == 0.
 template <int FMT, int E>
-__device__ __forceinline__ void stage_products(const SpmvOperand& A, const double* __restrict__ x,
-                                               const double* scale, int base, int lo, int hi,
-                                               int j0, double* prod) {
-  Words<E> cw = load_words<E>(A.col + base);
-  Words<(E / 2 > 1 ? E / 2 : 2)> hw{}, t1w{};
-  Words<E> t2w{};
+struct Group {
+  static constexpr int HW = (E / 2 > 1) ? E / 2 : 2;
+  Words<E> cw;
+  Words<HW> hw;
+  Words<HW> t1w;
+  Words<E> t2w;
   double vv[E];
-  if constexpr (FMT != kCsr64) {
-    hw = load_words<(E / 2 > 1 ? E / 2 : 2)>(A.head + base);
-    if constexpr (FMT >= 2) t1w = load_words<(E / 2 > 1 ? E / 2 : 2)>(A.tail1 + base);
-    if constexpr (FMT >= 3) t2w = load_words<E>(A.tail2 + base);
-  } else {
-    const double2* q = reinterpret_cast<const double2*>(A.val + base);
+
+  __device__ __forceinline__ void load(const SpmvOperand& A, int base) {
+    cw = load_words<E>(A.col + base);
+    if constexpr (FMT != kCsr64) {
+      hw = load_words<HW>(A.head + base);
+      if constexpr (FMT >= 2) t1w = load_words<HW>(A.tail1 + base);
+      if constexpr (FMT >= 3) t2w = load_words<E>(A.tail2 + base);
+    } else {
+      const f64x2* q = reinterpret_cast<const f64x2*>(A.val + base);
 #pragma unroll
-    for (int i = 0; i < E / 2; ++i) {
-      const double2 d = q[i];
-      vv[2 * i] = d.x;
-      vv[2 * i + 1] = d.y;
+      for (int i = 0; i < E / 2; ++i) {
+        const f64x2 d = stream_load(q + i);
+        vv[2 * i] = d.x;
+        vv[2 * i + 1] = d.y;
+      }
     }
   }
+
+  // Decoded values and columns of the non-zeros in [lo, hi) into the LDS
+  // slots of the tile starting at j0 (one padding slot per 8 spreads the
+  // lanes of a wave over the banks).
+  __device__ __forceinline__ void stage(const double* scale, int base, int lo, int hi, int j0,
+                                        double* vals, int* cols) const {
 #pragma unroll
-  for (int k = 0; k < E; ++k) {
-    const int j = base + k;
-    if (j >= lo && j < hi) {
-      int column;
-      const uint32_t h = (FMT != kCsr64) ? u16_of(hw, k) : 0u;
-      const uint32_t t1 = (FMT >= 2) ? u16_of(t1w, k) : 0u;
-      const uint32_t t2 = (FMT >= 3) ? t2w.w[k] : 0u;
-      const double v = decode<FMT>(cw.w[k], h, t1, t2, (FMT == kCsr64) ? vv[k] : 0.0, scale, column);
-      const int li = j - j0;
-      prod[li + li / E] = v * x[column];
+    for (int k = 0; k < E; ++k) {
+      const int j = base + k;
+      if (j >= lo && j < hi) {
+        int column;
+        const uint32_t h = (FMT != kCsr64) ? u16_of(hw, k) : 0u;
+        const uint32_t t1 = (FMT >= 2) ? u16_of(t1w, k) : 0u;
+        const uint32_t t2 = (FMT >= 3) ? t2w.w[k] : 0u;
+        const double v = decode<FMT>(cw.w[k], h, t1, t2, (FMT == kCsr64) ? vv[k] : 0.0, scale,
+                                     column);
+        const int li = j - j0;
+        vals[li + (li >> 3)] = v;
+        cols[li + (li >> 3)] = column;
+      }
     }
   }
-}
+};
+
+// Plane data of one non-zero (look-ahead past the tile end).
+template <int FMT>
+struct Elem {
+  uint32_t c = 0, h = 0, t1 = 0, t2 = 0;
+  double v = 0.0;
+  __device__ __forceinline__ void load(const SpmvOperand& A, int j) {
+    c = A.col[j];
+    if constexpr (FMT != kCsr64) {
+      h = A.head[j];
+      if constexpr (FMT >= 2) t1 = A.tail1[j];
+      if constexpr (FMT >= 3) t2 = A.tail2[j];
+    } else {
+      v = A.val[j];
+    }
+  }
+  __device__ __forceinline__ double product(const double* __restrict__ x, const double* scale) const {
+    int column;
+    const double d = decode<FMT>(c, h, t1, t2, v, scale, column);
+    return d * x[column];
+  }
+  __device__ __forceinline__ void stage(const double* scale, int li, double* vals, int* cols) const {
+    int column;
+    const double d = decode<FMT>(c, h, t1, t2, v, scale, column);
+    vals[li + (li >> 3)] = d;
+    cols[li + (li >> 3)] = column;
+  }
+};
 
 // One product read straight from memory (phase 4).
 template <int FMT>
 __device__ __forceinline__ double product_at(const SpmvOperand& A, const double* __restrict__ x,
                                              const double* scale, int j) {
-  const uint32_t c = A.col[j];
-  uint32_t h = 0, t1 = 0, t2 = 0;
-  double v = 0.0;
-  if constexpr (FMT != kCsr64) {
-    h = A.head[j];
-    if constexpr (FMT >= 2) t1 = A.tail1[j];
-    if constexpr (FMT >= 3) t2 = A.tail2[j];
-  } else {
-    v = A.val[j];
-  }
-  int column;
-  const double d = decode<FMT>(c, h, t1, t2, v, scale, column);
-  return d * x[column];
+  Elem<FMT> e;
+  e.load(A, j);
+  return e.product(x, scale);
 }
 
 template <int E>
 struct TileLds {
   static constexpr int T = kWG * E;
-  static constexpr int NPROD = (T + kExtra) + (T + kExtra) / E;
+  static constexpr int NPROD = (T + kExtra) + (T + kExtra) / 8;
   static constexpr int NDEF = (T + kExtra) / (kShortRow + 1) + 2;
 };
 
+__device__ __forceinline__ int pslot(int li) { return li + (li >> 3); }
+
+// Position of a tile in the persistent schedule: the tiles are split into
+// eight contiguous ranges, one per XCD (workgroups are handed to the XCDs
+// round-robin), and the workgroups of an XCD interleave over its range, so
+// the tiles in flight on an XCD are neighbours and share x in its L2.
+struct TileWalk {
+  int t, end, step;
+  __device__ __forceinline__ TileWalk(int n_tiles) {
+    const int g = gridDim.x, wg = blockIdx.x;
+    const int xcd = wg & 7, local = wg >> 3;
+    const int nx = (g >> 3) + (((g & 7) > xcd) ? 1 : 0);
+    const int tb = (int)(((long long)n_tiles * xcd) >> 3);
+    end = (int)(((long long)n_tiles * (xcd + 1)) >> 3);
+    t = tb + local;
+    step = nx;
+  }
+};
+
+// Row bookkeeping of one tile (scalars, uniform over the workgroup).
+struct TileInfo {
+  int t, j0, j1, ra, rb;
+};
+
+// Persistent SpMV: every workgroup walks its tiles with a one-tile software
+// pipeline -- the plane data and row pointers of tile i+1 are in flight
+// while tile i is decoded, multiplied and reduced.
 template <int FMT, int E>
 __global__ __launch_bounds__(kWG) void k_spmv(SpmvOperand A, const double* __restrict__ x,
                                               double* __restrict__ y, SpmvEpilogue ep) {
   using L = TileLds<E>;
   constexpr int T = L::T;
-  __shared__ double prod[L::NPROD];
+  constexpr int NPF = 2;  // row pointers prefetched per thread (2 * 256 rows)
+  __shared__ double vals[L::NPROD];
+  __shared__ int cols[L::NPROD];
   __shared__ double scale[16];
+  __shared__ int rps[NPF * kWG + 1];
   __shared__ int deferred[L::NDEF];
   __shared__ int wave_cnt[kWaves];
   __shared__ double red[kWaves];
-  __shared__ bool last_flag;
 
   if (ep.gate && *ep.gate) return;
   const int tid = threadIdx.x;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int j0 = tile * T;
-  const int j1 = min(j0 + T, A.nnz);
-  const int ra = A.tile_row[tile];
-  const int rb = A.tile_row[tile + 1];
+  const int lane = tid & 63, wave = tid >> 6;
+  build_scale<FMT>(A, scale);
   double acc = 0.0;  // this thread's share of the epilogue dot
 
   auto finish_row = [&](int r, double sum) {
@@ -203,118 +280,209 @@ __global__ __launch_bounds__(kWG) void k_spmv(SpmvOperand A, const double* __res
     }
   };
 
-  if (ra < rb) {
-    build_scale<FMT>(A, scale);
-    const int js = A.row_ptr[ra];      // first non-zero this tile needs
-    const int je = A.row_ptr[rb];      // end of its last row
-    const bool tail_in_lds = (je - j1) <= kExtra;
-    const int jl = tail_in_lds ? je : j1;  // [js, jl) staged in LDS
-    __syncthreads();  // scale table ready
+  TileWalk walk(A.n_tiles);
+  // prefetch state of the next tile
+  Group<FMT, E> g_cur, g_nxt;
+  Elem<FMT> e_cur, e_nxt;
+  int rpv_cur[NPF], rpv_nxt[NPF];
+  TileInfo cur{}, nxt{};
 
-    // ---- phase 1: coalesced vector loads, decode, gather, products -> LDS
-    {
-      const int base = j0 + tid * E;
-      if (base + E > js && base < jl) stage_products<FMT, E>(A, x, scale, base, js, jl, j0, prod);
-      constexpr int extra_lanes = kExtra / E;
-      if (tid < extra_lanes) {
-        const int b2 = j1 + tid * E;
-        if (b2 < jl) stage_products<FMT, E>(A, x, scale, b2, js, jl, j0, prod);
-      }
+  auto issue_planes = [&](int t, TileInfo& ti, Group<FMT, E>& g, Elem<FMT>& e) {
+    ti.t = t;
+    ti.j0 = t * T;
+    ti.j1 = min(ti.j0 + T, A.nnz);
+    const int base = ti.j0 + tid * E;
+    if (base < A.nnz) g.load(A, base);
+    if (tid < kSpec && ti.j1 + tid < A.nnz) e.load(A, ti.j1 + tid);
+    ti.ra = A.tile_row[t];
+    ti.rb = A.tile_row[t + 1];
+  };
+  auto issue_rows = [&](const TileInfo& ti, int* rpv) {
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) {
+      const int i = k * kWG + tid;
+      rpv[k] = (i <= ti.rb - ti.ra) ? A.row_ptr[ti.ra + i] : 0;
     }
-    __syncthreads();
+  };
 
-    // ---- phase 2: short rows, one thread each, summed in row order
-    const int lane = tid & 63, wave = tid >> 6;
-    int ndef = 0;
-    const bool long_tail = !tail_in_lds;  // row rb-1 continues past the LDS copy
-    for (int cbase = ra; cbase < rb; cbase += kWG) {
-      const int r = cbase + tid;
-      bool defer = false;
-      if (r < rb && !(long_tail && r == rb - 1)) {
-        const int s0 = A.row_ptr[r];
-        const int s1 = A.row_ptr[r + 1];
-        if (s1 - s0 <= kShortRow) {
-          double sum = 0.0;
-          for (int j = s0; j < s1; ++j) {
-            const int li = j - j0;
-            sum += prod[li + li / E];
-          }
-          finish_row(r, sum);
-        } else {
-          defer = true;
+  bool have = walk.t < walk.end;
+  if (have) {
+    issue_planes(walk.t, cur, g_cur, e_cur);
+    issue_rows(cur, rpv_cur);
+  }
+  while (have) {
+    const int tn = walk.t + walk.step;
+    const bool have_n = tn < walk.end;
+    if (have_n) issue_planes(tn, nxt, g_nxt, e_nxt);
+
+    const int j0 = cur.j0, j1 = cur.j1, ra = cur.ra, rb = cur.rb;
+    if (ra < rb) {
+      const int nr = rb - ra;
+      const int nstage = min(nr, NPF * kWG - 1);  // rps[0..nstage] = row_ptr[ra..ra+nstage]
+      __syncthreads();  // the previous tile's LDS reads are done
+#pragma unroll
+      for (int k = 0; k < NPF; ++k) {
+        const int i = k * kWG + tid;
+        if (i <= nstage) rps[i] = rpv_cur[k];
+      }
+      __syncthreads();  // rps ready
+      const int js = rps[0];
+      const int je = (nr <= nstage) ? rps[nr] : A.row_ptr[rb];
+      const bool tail_in_lds = (je - j1) <= kExtra;
+      const int jl = tail_in_lds ? je : j1;  // [js, jl) staged in LDS
+
+      // ---- phase 1: decode the staged non-zeros into LDS (value, column)
+      const int base = j0 + tid * E;
+      if (base < jl && base + E > js) g_cur.stage(scale, base, js, jl, j0, vals, cols);
+      if (tid < kSpec && j1 + tid < jl) e_cur.stage(scale, j1 + tid - j0, vals, cols);
+      if (jl > j1 + kSpec) {  // longer look-ahead for the last row: second round
+        for (int j = j1 + kSpec + tid; j < jl; j += kWG) {
+          Elem<FMT> e;
+          e.load(A, j);
+          e.stage(scale, j - j0, vals, cols);
         }
       }
-      // deterministic compaction of the deferred rows (ordered by row)
-      const unsigned long long m = __ballot(defer);
-      if (lane == 0) wave_cnt[wave] = __popcll(m);
+      if (have_n) issue_rows(nxt, rpv_nxt);
       __syncthreads();
-      int off = ndef;
-      for (int w = 0; w < wave; ++w) off += wave_cnt[w];
-      if (defer) deferred[off + __popcll(m & ((1ull << lane) - 1ull))] = r;
-      int tot = 0;
-      for (int w = 0; w < kWaves; ++w) tot += wave_cnt[w];
-      ndef += tot;
-      __syncthreads();
-    }
 
-    // ---- phase 3: long rows inside LDS, one wave each
-    for (int d = wave; d < ndef; d += kWaves) {
-      const int r = deferred[d];
-      const int s0 = A.row_ptr[r];
-      const int s1 = A.row_ptr[r + 1];
-      double part = 0.0;
-      for (int j = s0 + lane; j < s1; j += 64) {
-        const int li = j - j0;
-        part += prod[li + li / E];
-      }
-      part = wave_sum(part);
-      if (lane == 0) finish_row(r, part);
-    }
+      auto rp_at = [&](int r) { return (r - ra <= nstage) ? rps[r - ra] : A.row_ptr[r]; };
 
-    // ---- phase 4: the row running far past the tile, whole workgroup
-    if (long_tail) {
-      const int r = rb - 1;
-      const int s0 = A.row_ptr[r];
-      double part = 0.0;
-      for (int j = s0 + tid; j < j1; j += kWG) {
-        const int li = j - j0;
-        part += prod[li + li / E];
+      // ---- phase 2: short rows, one thread each, summed in row order
+      int ndef = 0;
+      const bool long_tail = !tail_in_lds;  // row rb-1 continues past the LDS copy
+      for (int cbase = ra; cbase < rb; cbase += kWG) {
+        const int r = cbase + tid;
+        bool defer = false;
+        if (r < rb && !(long_tail && r == rb - 1)) {
+          const int s0 = rp_at(r);
+          const int s1 = rp_at(r + 1);
+          if (s1 - s0 <= kShortRow) {
+            // neighbouring lanes hold neighbouring rows: the gathers of a
+            // banded matrix fall in few cache lines; eight are issued at
+            // once; the row is summed in order, multiply and add rounded
+            // separately like the sequential definition
+            double sum = 0.0;
+            for (int jb = s0; jb < s1; jb += 8) {
+              double v[8], xv[8];
+              int c[8];
+#pragma unroll
+              for (int k = 0; k < 8; ++k) {
+                const int q = pslot(min(jb + k, s1 - 1) - j0);
+                v[k] = vals[q];
+                c[k] = (jb + k < s1) ? cols[q] : 0;
+              }
+#pragma unroll
+              for (int k = 0; k < 8; ++k) xv[k] = x[c[k]];
+#pragma unroll
+              for (int k = 0; k < 8; ++k) {
+                const double p = __dmul_rn(v[k], xv[k]);
+                sum = (jb + k < s1) ? __dadd_rn(sum, p) : sum;
+              }
+            }
+            finish_row(r, sum);
+          } else {
+            defer = true;
+          }
+        }
+        // deterministic compaction of the deferred rows (ordered by row)
+        const unsigned long long m = __ballot(defer);
+        if (lane == 0) wave_cnt[wave] = __popcll(m);
+        __syncthreads();
+        int off = ndef;
+        for (int w = 0; w < wave; ++w) off += wave_cnt[w];
+        if (defer) deferred[off + __popcll(m & ((1ull << lane) - 1ull))] = r;
+        int tot = 0;
+        for (int w = 0; w < kWaves; ++w) tot += wave_cnt[w];
+        ndef += tot;
+        __syncthreads();
       }
-      int j = j1 + tid;
-      for (; j + 3 * kWG < je; j += 4 * kWG) {
-        const double p0 = product_at<FMT>(A, x, scale, j);
-        const double p1 = product_at<FMT>(A, x, scale, j + kWG);
-        const double p2 = product_at<FMT>(A, x, scale, j + 2 * kWG);
-        const double p3 = product_at<FMT>(A, x, scale, j + 3 * kWG);
-        part += p0;
-        part += p1;
-        part += p2;
-        part += p3;
+
+      // ---- phase 3: long rows inside LDS, one wave each
+      for (int d = wave; d < ndef; d += kWaves) {
+        const int r = deferred[d];
+        const int s0 = rp_at(r);
+        const int s1 = rp_at(r + 1);
+        double part = 0.0;
+        for (int j = s0 + lane; j < s1; j += 64) {
+          const int q = pslot(j - j0);
+          part += vals[q] * x[cols[q]];
+        }
+        part = wave_sum(part);
+        if (lane == 0) finish_row(r, part);
       }
-      for (; j < je; j += kWG) part += product_at<FMT>(A, x, scale, j);
-      const double tot = block_sum(part, red);
-      if (tid == 0) finish_row(r, tot);
+
+      // ---- phase 4: the row running far past the tile, whole workgroup
+      if (long_tail) {
+        const int r = rb - 1;
+        const int s0 = rp_at(r);
+        double part = 0.0;
+        for (int j = s0 + tid; j < j1; j += kWG) {
+          const int q = pslot(j - j0);
+          part += vals[q] * x[cols[q]];
+        }
+        int j = j1 + tid;
+        for (; j + 3 * kWG < je; j += 4 * kWG) {
+          const double p0 = product_at<FMT>(A, x, scale, j);
+          const double p1 = product_at<FMT>(A, x, scale, j + kWG);
+          const double p2 = product_at<FMT>(A, x, scale, j + 2 * kWG);
+          const double p3 = product_at<FMT>(A, x, scale, j + 3 * kWG);
+          part += p0;
+          part += p1;
+          part += p2;
+          part += p3;
+        }
+        for (; j < je; j += kWG) part += product_at<FMT>(A, x, scale, j);
+        const double tot = block_sum(part, red);
+        if (tid == 0) finish_row(r, tot);
+      }
+    } else if (have_n) {
+      issue_rows(nxt, rpv_nxt);
     }
+    walk.t = tn;
+    have = have_n;
+    cur = nxt;
+    g_cur = g_nxt;
+    e_cur = e_nxt;
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) rpv_cur[k] = rpv_nxt[k];
   }
 
-  // ---- epilogue dot: per-workgroup partial, last workgroup finishes it
+  // ---- epilogue dot: one partial per workgroup (finished by the caller's
+  // next kernel, after the launch boundary has made them visible)
   if (ep.epi != kEpiPlain) {
     const double bs = block_sum(acc, red);
     if (tid == 0) ep.partials[blockIdx.x] = bs;
-    if (last_block_arrive(ep.counter, &last_flag)) {
-      const double tot = sum_partials(ep.partials, gridDim.x, red);
-      if (tid == 0) {
-        *ep.result = tot;
-        *ep.counter = 0u;
-      }
-    }
   }
+}
+
+// Resident workgroups of one kernel instance on this device (occupancy x
+// compute units), cached per instance.
+template <int FMT, int E>
+int resident_groups() {
+  static int cached = 0;
+  if (cached == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv<FMT, E>, kWG, 0) != hipSuccess)
+      return 0;
+    cached = cus * (per_cu > 0 ? per_cu : 1);
+  }
+  return cached;
 }
 
 template <int FMT, int E>
 hipError_t launch_fe(const SpmvOperand& A, const double* x, double* y, const SpmvEpilogue& ep,
                      hipStream_t st) {
-  hipLaunchKernelGGL((k_spmv<FMT, E>), dim3(A.n_tiles), dim3(kWG), 0, st, A, x, y, ep);
+  int g = resident_groups<FMT, E>();
+  if (g <= 0) return hipErrorInvalidDevice;
+  // at least one workgroup per XCD range, no more than the tiles need
+  const int need = (A.n_tiles + 7) / 8 * 8;
+  if (g > need) g = need;
+  if (g < 8) g = 8;
+  if (ep.grid_out) *ep.grid_out = g;
+  hipLaunchKernelGGL((k_spmv<FMT, E>), dim3(g), dim3(kWG), 0, st, A, x, y, ep);
   return hipGetLastError();
 }
 
@@ -325,6 +493,131 @@ hipError_t launch_f(const SpmvOperand& A, const double* x, double* y, const Spmv
     case kWG * 4: return launch_fe<FMT, 4>(A, x, y, ep, st);
     case kWG * 8: return launch_fe<FMT, 8>(A, x, y, ep, st);
     case kWG * 16: return launch_fe<FMT, 16>(A, x, y, ep, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Row-vector schedule for matrices whose rows are short and of similar
+// length (stencils): L lanes per row, 64/L rows per wave at a time and U
+// rows per lane group in flight.  Lane `sub` of a group reads the row's
+// non-zeros sub, sub+L, ... -- so a wave's loads cover consecutive
+// non-zeros (coalesced) -- decodes them, gathers x and accumulates; the
+// group then combines its L partial sums with a fixed butterfly.  No LDS
+// staging and no barriers: every wave is independent, which keeps many
+// loads in flight per compute unit.
+template <int FMT, int L>
+__global__ __launch_bounds__(kWG) void k_spmv_rv(SpmvOperand A, const double* __restrict__ x,
+                                                 double* __restrict__ y, SpmvEpilogue ep) {
+  constexpr int G = 64 / L;
+  constexpr int U = kRvBatch;
+  constexpr int RB = G * U;  // rows per wave
+  __shared__ double scale[16];
+  __shared__ double red[kWaves];
+
+  if (ep.gate && *ep.gate) return;
+  build_scale<FMT>(A, scale);
+  __syncthreads();
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane / L, sub = lane % L;
+  const int wblk = xcd_tile(blockIdx.x, gridDim.x) * kWaves + wave;
+  const int r0 = wblk * RB;
+  double acc = 0.0;
+
+  int s0[U], s1[U];
+  int mylen = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {  // all 2U row-pointer loads issued before any use
+    const int r = r0 + u * G + g;
+    const int rr = r < A.n_rows ? r : 0;
+    s0[u] = A.row_ptr[rr];
+    s1[u] = A.row_ptr[rr + 1];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (r0 + u * G + g >= A.n_rows) s1[u] = s0[u];
+    mylen = max(mylen, s1[u] - s0[u]);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) mylen = max(mylen, __shfl_xor(mylen, off, 64));
+  const int maxlen = mylen;  // uniform over the wave
+
+  double sum[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) sum[u] = 0.0;
+  for (int kb = 0; kb < maxlen; kb += L) {
+    Elem<FMT> e[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = s0[u] + kb + sub;
+      ok[u] = j < s1[u];
+      e[u].load(A, ok[u] ? j : 0);  // unconditional: all U loads in flight together
+    }
+    double d[U], xv[U];
+    int column[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      d[u] = decode<FMT>(e[u].c, e[u].h, e[u].t1, e[u].t2, e[u].v, scale, column[u]);
+      if (!ok[u]) column[u] = 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = x[column[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double p = __dmul_rn(d[u], xv[u]);
+      sum[u] = ok[u] ? __dadd_rn(sum[u], p) : sum[u];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+#pragma unroll
+    for (int off = L / 2; off >= 1; off >>= 1) sum[u] += __shfl_xor(sum[u], off, 64);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int r = r0 + u * G + g;
+    if (sub == 0 && r < A.n_rows) {
+      if (ep.epi == kEpiPlain) {
+        y[r] = sum[u];
+      } else if (ep.epi == kEpiDot) {
+        y[r] = sum[u];
+        acc += ep.aux[r] * sum[u];
+      } else {
+        const double v = ep.aux[r] - sum[u];
+        y[r] = v;
+        acc += v * v;
+      }
+    }
+  }
+
+  if (ep.epi != kEpiPlain) {
+    const double bs = block_sum(acc, red);
+    if (tid == 0) ep.partials[blockIdx.x] = bs;
+  }
+}
+
+template <int FMT, int L>
+hipError_t launch_rv(const SpmvOperand& A, const double* x, double* y, const SpmvEpilogue& ep,
+                     hipStream_t st) {
+  constexpr int rows_per_wg = (64 / L) * kRvBatch * kWaves;
+  int g = (A.n_rows + rows_per_wg - 1) / rows_per_wg;
+  if (g < 1) g = 1;
+  if (ep.grid_out) *ep.grid_out = g;
+  hipLaunchKernelGGL((k_spmv_rv<FMT, L>), dim3(g), dim3(kWG), 0, st, A, x, y, ep);
+  return hipGetLastError();
+}
+
+template <int FMT>
+hipError_t launch_rv_f(const SpmvOperand& A, const double* x, double* y, const SpmvEpilogue& ep,
+                       hipStream_t st) {
+  switch (A.rv_lanes) {
+    case 1: return launch_rv<FMT, 1>(A, x, y, ep, st);
+    case 2: return launch_rv<FMT, 2>(A, x, y, ep, st);
+    case 4: return launch_rv<FMT, 4>(A, x, y, ep, st);
+    case 8: return launch_rv<FMT, 8>(A, x, y, ep, st);
+    case 16: return launch_rv<FMT, 16>(A, x, y, ep, st);
+    case 32: return launch_rv<FMT, 32>(A, x, y, ep, st);
+    case 64: return launch_rv<FMT, 64>(A, x, y, ep, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -349,6 +642,22 @@ __global__ void k_plan(const int32_t* __restrict__ row_ptr, int32_t n_rows, int3
   tile_row[t] = lo;
 }
 
+// Longest row: grid-stride, workgroup maximum, one atomic per workgroup.
+__global__ __launch_bounds__(256) void k_rowmax(const int32_t* __restrict__ row_ptr, int n_rows,
+                                                int* __restrict__ out) {
+  __shared__ int red[kWaves];
+  int m = 0;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n_rows; r += gridDim.x * blockDim.x)
+    m = max(m, row_ptr[r + 1] - row_ptr[r]);
+  for (int off = 32; off >= 1; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kWaves; ++w) m = max(m, red[w]);
+    atomicMax(out, m);
+  }
+}
+
 __global__ void k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -364,6 +673,15 @@ int32_t n_tiles_for(int64_t nnz, int32_t tile_nnz) {
 
 hipError_t launch_spmv(int fmt, const SpmvOperand& A, const double* x, double* y,
                        const SpmvEpilogue& ep, hipStream_t st) {
+  if (A.rv_lanes > 0) {
+    switch (fmt) {
+      case 0: return launch_rv_f<0>(A, x, y, ep, st);
+      case 1: return launch_rv_f<1>(A, x, y, ep, st);
+      case 2: return launch_rv_f<2>(A, x, y, ep, st);
+      case 3: return launch_rv_f<3>(A, x, y, ep, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (fmt) {
     case 0: return launch_f<0>(A, x, y, ep, st);
     case 1: return launch_f<1>(A, x, y, ep, st);
@@ -380,6 +698,15 @@ hipError_t launch_plan(const int32_t* row_ptr, int32_t n_rows, int32_t nnz, int3
   const int blocks = (n_tiles + 1 + threads - 1) / threads;
   hipLaunchKernelGGL(k_plan, dim3(blocks), dim3(threads), 0, st, row_ptr, n_rows, tile_nnz, n_tiles,
                      tile_row);
+  return hipGetLastError();
+}
+
+hipError_t launch_rowmax(const int32_t* row_ptr, int32_t n_rows, int* out, hipStream_t st) {
+  hipError_t e = hipMemsetAsync(out, 0, sizeof(int), st);
+  if (e != hipSuccess) return e;
+  int blocks = (n_rows + 255) / 256;
+  blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+  hipLaunchKernelGGL(k_rowmax, dim3(blocks), dim3(256), 0, st, row_ptr, n_rows, out);
   return hipGetLastError();
 }
 

@@ -37,6 +37,7 @@ class gse_matrix(C.Structure):
                 ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("head", C.c_void_p),
                 ("tail1", C.c_void_p), ("tail2", C.c_void_p), ("tile_row", C.c_void_p),
                 ("tile_cap", C.c_int32), ("tile_nnz", C.c_int32), ("n_tiles", C.c_int32),
+                ("rv_lanes", C.c_int32), ("max_row_nnz", C.c_int32),
                 ("eta", C.c_double * 3), ("exact_frac", C.c_double)]
 
 
@@ -44,7 +45,7 @@ class gse_csr(C.Structure):
     _fields_ = [("n_rows", C.c_int32), ("n_cols", C.c_int32), ("nnz", C.c_int64),
                 ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p),
                 ("tile_row", C.c_void_p), ("tile_cap", C.c_int32), ("tile_nnz", C.c_int32),
-                ("n_tiles", C.c_int32)]
+                ("n_tiles", C.c_int32), ("rv_lanes", C.c_int32), ("max_row_nnz", C.c_int32)]
 
 
 class gse_params(C.Structure):
@@ -81,8 +82,8 @@ _SIGS = {
     "gse_encode_workspace": (C.c_int32, [C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]),
     "gse_encode": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int64, C.c_int32, _P,
                                C.POINTER(gse_matrix), _P, C.c_size_t, _P]),
-    "gse_plan": (C.c_int32, [C.POINTER(gse_matrix), C.c_int32, _P]),
-    "gse_csr_plan": (C.c_int32, [C.POINTER(gse_csr), C.c_int32, _P]),
+    "gse_plan": (C.c_int32, [C.POINTER(gse_matrix), C.c_int32, C.c_int32, _P]),
+    "gse_csr_plan": (C.c_int32, [C.POINTER(gse_csr), C.c_int32, C.c_int32, _P]),
     "gse_spmv": (C.c_int32, [C.POINTER(gse_matrix), C.c_int32, _P, _P, _P]),
     "gse_csr_spmv": (C.c_int32, [C.POINTER(gse_csr), _P, _P, _P]),
     "gse_default_params": (C.c_int32, [C.c_int32, C.POINTER(gse_params)]),
@@ -166,12 +167,13 @@ def gse_encode(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, sem_in, A: gse_m
                                    _stream(stream)), "gse_encode")
 
 
-def gse_plan(A: gse_matrix, tile_nnz: int, stream=None) -> int:
-    return _check(lib().gse_plan(C.byref(A), tile_nnz, _stream(stream)), "gse_plan")
+def gse_plan(A: gse_matrix, tile_nnz: int, rv_lanes: int = -1, stream=None) -> int:
+    return _check(lib().gse_plan(C.byref(A), tile_nnz, rv_lanes, _stream(stream)), "gse_plan")
 
 
-def gse_csr_plan(M: gse_csr, tile_nnz: int, stream=None) -> int:
-    return _check(lib().gse_csr_plan(C.byref(M), tile_nnz, _stream(stream)), "gse_csr_plan")
+def gse_csr_plan(M: gse_csr, tile_nnz: int, rv_lanes: int = -1, stream=None) -> int:
+    return _check(lib().gse_csr_plan(C.byref(M), tile_nnz, rv_lanes, _stream(stream)),
+                  "gse_csr_plan")
 
 
 def gse_spmv(A: gse_matrix, k_segments: int, x: torch.Tensor, y: torch.Tensor, stream=None) -> int:
@@ -293,8 +295,8 @@ class GseMatrix:
                 self.tail1[:n].cpu().numpy().view("uint16"),
                 self.tail2[:n].cpu().numpy().view("uint32"))
 
-    def plan(self, tile_nnz: int, stream=None):
-        gse_plan(self.A, tile_nnz, stream)
+    def plan(self, tile_nnz: int = 2048, rv_lanes: int = -1, stream=None):
+        gse_plan(self.A, tile_nnz, rv_lanes, stream)
 
     def spmv(self, k_segments: int, x: torch.Tensor, y: torch.Tensor, stream=None):
         gse_spmv(self.A, k_segments, x, y, stream)
@@ -304,7 +306,7 @@ class CsrMatrix:
     """Padded device copy of an FP64 CSR matrix for the baseline operators."""
 
     def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n_cols: int,
-                 tile_nnz: int = 2048, stream=None):
+                 tile_nnz: int = 2048, rv_lanes: int = -1, stream=None):
         dev = row_ptr.device
         nnz = val.numel()
         pad = gse_pad(nnz)
@@ -326,7 +328,10 @@ class CsrMatrix:
         M.tile_row = self.tile_row.data_ptr()
         M.tile_cap = cap
         self.M = M
-        gse_csr_plan(M, tile_nnz, stream)
+        gse_csr_plan(M, tile_nnz, rv_lanes, stream)
+
+    def plan(self, tile_nnz: int = 2048, rv_lanes: int = -1, stream=None):
+        gse_csr_plan(self.M, tile_nnz, rv_lanes, stream)
 
     def spmv(self, x: torch.Tensor, y: torch.Tensor, stream=None):
         gse_csr_spmv(self.M, x, y, stream)

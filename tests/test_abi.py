@@ -1,0 +1,103 @@
+"""The C ABI without a GPU: the library loads, exports every entry point that
+include/gse.h declares, and rejects bad arguments on the host before any
+launch (no compute call needs a device here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gse.h")
+LIB = os.path.join(ROOT, "paper_2411_04686_amd", "libgse.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(gse_[a-z_0-9]+)\s*\(", text, re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libgse.so is not built (run __graft_entry__.build())")
+    return C.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ("gse_encode", "gse_spmv", "gse_cg", "gse_gmres", "gse_plan", "gse_csr_spmv",
+                 "gse_solver_workspace", "gse_last_error"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    import importlib
+    import sys
+    sys.path.insert(0, ROOT)
+    g = importlib.import_module("paper_2411_04686_amd.gse")
+    assert set(declared()) <= set(g.exported_symbols())
+
+
+def test_host_side_helpers(lib):
+    lib.gse_pad.restype = C.c_int64
+    lib.gse_pad.argtypes = [C.c_int64]
+    assert [lib.gse_pad(n) for n in (0, 1, 16, 17)] == [0, 16, 16, 32]
+    lib.gse_tile_entries.restype = C.c_int32
+    lib.gse_tile_entries.argtypes = [C.c_int64]
+    assert lib.gse_tile_entries(0) == 3 and lib.gse_tile_entries(1025) == 4
+    lib.gse_status_str.restype = C.c_char_p
+    assert lib.gse_status_str(0) == b"ok" and lib.gse_status_str(-5) == b"breakdown"
+    ws = C.c_size_t()
+    assert lib.gse_encode_workspace(C.c_int64(1000), 10, C.byref(ws)) == 0 and ws.value > 8192
+    assert lib.gse_solver_workspace(0, 100, C.c_int64(500), 30, 100, C.byref(ws)) == 0
+    cg_bytes = ws.value
+    assert lib.gse_solver_workspace(1, 100, C.c_int64(500), 30, 100, C.byref(ws)) == 0
+    assert ws.value > cg_bytes  # GMRES adds the Krylov basis
+    assert lib.gse_solver_workspace(1, 100, C.c_int64(500), 0, 100, C.byref(ws)) == -1
+
+
+def test_default_params_are_the_paper_presets(lib):
+    import sys
+    sys.path.insert(0, ROOT)
+    from paper_2411_04686_amd.gse import gse_params
+    p = gse_params()
+    assert lib.gse_default_params(0, C.byref(p)) == 0
+    assert (p.l, p.t, p.m, p.ndec_limit) == (3000, 250, 500, 130)
+    assert (p.rsd_limit, p.reldec_limit, p.max_iter) == (0.5, 0.45, 5000)
+    assert lib.gse_default_params(1, C.byref(p)) == 0
+    assert (p.l, p.t, p.m, p.ndec_limit, p.restart) == (9000, 300, 1500, 80, 30)
+    assert (p.rsd_limit, p.reldec_limit, p.max_iter) == (0.03, 0.08, 15000)
+    assert p.tol == 1e-10
+    assert lib.gse_default_params(7, C.byref(p)) == -1
+
+
+def test_argument_errors_without_launch(lib):
+    import sys
+    sys.path.insert(0, ROOT)
+    from paper_2411_04686_amd.gse import gse_matrix
+    lib.gse_last_error.restype = C.c_char_p
+    assert lib.gse_spmv(None, 1, None, None, None) == -1
+    A = gse_matrix()
+    # planes not set
+    assert lib.gse_encode(C.c_void_p(16), None, None, 0, 0, C.c_int64(0), 8, None, C.byref(A),
+                          None, C.c_size_t(0), None) == -1
+    # num_exp out of range
+    assert lib.gse_encode(C.c_void_p(16), None, None, 0, 0, C.c_int64(0), 9, None, C.byref(A),
+                          None, C.c_size_t(0), None) == -1
+    # too many columns for a 29-bit column field
+    assert lib.gse_encode(C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), 1, 2**29 + 1,
+                          C.c_int64(1), 8, None, C.byref(A), None, C.c_size_t(0), None) == -3
+    assert b"2^29" in lib.gse_last_error()
+    # schedule missing -> spmv refuses
+    A.row_ptr = A.col_idx = A.head = A.tail1 = A.tail2 = A.tile_row = 256
+    assert lib.gse_spmv(C.byref(A), 1, C.c_void_p(256), C.c_void_p(256), None) == -1
+    # copy needs 16-byte multiples
+    assert lib.gse_stream_copy(C.c_void_p(16), C.c_void_p(32), C.c_size_t(17), None) == -1

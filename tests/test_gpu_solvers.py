@@ -1,0 +1,198 @@
+"""GPU parity of the stepped CG and GMRES solvers against the oracle.
+
+Solves are iterations, so several results are correct: both sides must reach
+the true relative residual ||b - A x|| / ||b|| <= 1e-10 (checked again here
+in FP64 on the host), agree on the solution within the accuracy the
+tolerance allows (relative difference <= 1e-6 for these well-conditioned
+systems), and take iteration counts within 10 % of each other.  Where the
+operator is exact (Poisson: integer stencil, eta_1 = 0) the stepped GPU
+solve must reproduce the GPU FP64 solve bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import CSR, convdiff2d, diffusion3d, poisson2d, rhs_from_solution
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2411_04686_amd import gse as G  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def to_dev(A: CSR):
+    return (torch.from_numpy(A.indptr).to(DEV), torch.from_numpy(A.indices).to(DEV),
+            torch.from_numpy(A.data).to(DEV))
+
+
+def true_relres(A: CSR, x, b):
+    r = b - A.to_scipy() @ x
+    return np.linalg.norm(r) / np.linalg.norm(b)
+
+
+def gpu_solve(kind, A: CSR, b, method, fixed=0, max_iter=5000, switch_mode=1, x0=None,
+              record=True, rv=-1):
+    rp, ci, va = to_dev(A)
+    p = G.gse_default_params(method)
+    p.max_iter = max_iter
+    p.fixed_segments = fixed
+    p.switch_mode = switch_mode
+    p.record_history = 1 if record else 0
+    ws = torch.empty(G.gse_solver_workspace(method, A.n_rows, A.nnz, p.restart, p.max_iter),
+                     dtype=torch.uint8, device=DEV)
+    x = torch.zeros(A.n_rows, dtype=torch.float64, device=DEV) if x0 is None else \
+        torch.from_numpy(x0).to(DEV)
+    bd = torch.from_numpy(b).to(DEV)
+    if kind == "gse":
+        M = G.GseMatrix(rp, ci, va, A.n_cols)
+        if rv != -1:
+            M.plan(2048, rv)
+        fn = G.gse_cg if method == G.CG else G.gse_gmres
+        rep = fn(M.A, bd, x, p, ws)
+    else:
+        M = G.CsrMatrix(rp, ci, va, A.n_cols, rv_lanes=rv)
+        fn = G.gse_csr_cg if method == G.CG else G.gse_csr_gmres
+        rep = fn(M.M, bd, x, p, ws)
+    torch.cuda.synchronize()
+    hist = seg = None
+    if record:
+        hist, seg = G.gse_solve_history(ws, rep.iters + 1)
+    return rep, x.cpu().numpy(), hist, seg
+
+
+def oracle_params(method, fixed=0, max_iter=5000, switch_mode=1):
+    preset = "paper_cg" if method == G.CG else "paper_gmres"
+    return O.make_params(tol=1e-10, max_iter=max_iter, restart=30, fixed_segments=fixed,
+                         preset=preset, switch_mode=switch_mode, orth=1)
+
+
+def test_cg_fp64_poisson_matches_oracle():
+    A = poisson2d(64)
+    x_true, b = rhs_from_solution(A, 0)
+    rep, x, hist, _ = gpu_solve("csr", A, b, G.CG)
+    ref = O.cg(A.indptr, b, oracle_params(G.CG, fixed=-1), A.indices, A.data)
+    assert rep.status == G.OK and ref.status == O.OK
+    assert abs(rep.iters - ref.iters) <= 2
+    assert rep.relres_true <= 1e-10 and true_relres(A, x, b) <= 1e-10
+    assert np.linalg.norm(x - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
+    n = min(len(hist), len(ref.hist))
+    assert np.allclose(hist[:n], ref.hist[:n], rtol=1e-6, atol=1e-13)
+
+
+def test_stepped_cg_identical_to_fp64_on_exact_stencil():
+    A = poisson2d(64)
+    _, b = rhs_from_solution(A, 1)
+    for rv in (-1, 0):
+        r64, x64, h64, _ = gpu_solve("csr", A, b, G.CG, rv=rv)
+        rst, xst, hst, sst = gpu_solve("gse", A, b, G.CG, rv=rv)
+        assert r64.status == G.OK and rst.status == G.OK
+        assert rst.iters == r64.iters and list(rst.iters_per_seg) == [rst.iters, 0, 0]
+        assert np.array_equal(xst, x64)
+        assert np.array_equal(hst, h64)
+        assert np.all(sst[1:] == 1)
+
+
+@pytest.mark.parametrize("switch_mode", [0, 1])
+def test_stepped_cg_variable_coefficients(switch_mode):
+    A = diffusion3d(20, 3)
+    x_true, b = rhs_from_solution(A, 3)
+    rep, x, hist, seg = gpu_solve("gse", A, b, G.CG, switch_mode=switch_mode)
+    enc = O.encode(A.indptr, A.indices, A.data, A.n_cols)
+    ref = O.cg(A.indptr, b, oracle_params(G.CG, switch_mode=switch_mode), A.indices, A.data,
+               enc)
+    assert rep.status == G.OK and ref.status == O.OK
+    assert rep.relres_true <= 1e-10 and true_relres(A, x, b) <= 1e-10
+    assert np.linalg.norm(x - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+    assert abs(rep.iters - ref.iters) <= max(3, ref.iters // 10)
+    assert rep.iters_per_seg[0] > 0 and rep.switch_iter[0] > 0
+    # segment history steps up by one at the switches and matches the report
+    d = np.diff(seg[1:])
+    assert np.all((d == 0) | (d == 1))
+    assert [int((seg[1:] == s).sum()) for s in (1, 2, 3)] == list(rep.iters_per_seg)
+    assert abs(rep.switch_iter[0] - ref.switch_iter[0]) <= 3
+
+
+def test_fixed_segments_cg():
+    A = diffusion3d(12, 4)
+    _, b = rhs_from_solution(A, 4)
+    rep3, x3, _, _ = gpu_solve("gse", A, b, G.CG, fixed=3)
+    assert rep3.status == G.OK and list(rep3.iters_per_seg) == [0, 0, rep3.iters]
+    rep1, x1, _, _ = gpu_solve("gse", A, b, G.CG, fixed=1, max_iter=400)
+    # with the head only the true residual floors near eta_1, far above 1e-10
+    assert rep1.status == G.NOT_CONVERGED and rep1.relres_true > 1e-8
+
+
+@pytest.mark.parametrize("kind", ["csr", "gse"])
+def test_gmres_convdiff_matches_oracle(kind):
+    A = convdiff2d(48, 2)
+    x_true, b = rhs_from_solution(A, 2)
+    rep, x, hist, seg = gpu_solve(kind, A, b, G.GMRES, max_iter=15000)
+    if kind == "csr":
+        ref = O.gmres(A.indptr, b, oracle_params(G.GMRES, fixed=-1, max_iter=15000), A.indices,
+                      A.data)
+    else:
+        enc = O.encode(A.indptr, A.indices, A.data, A.n_cols)
+        ref = O.gmres(A.indptr, b, oracle_params(G.GMRES, max_iter=15000), A.indices, A.data,
+                      enc)
+    assert rep.status == G.OK and ref.status == O.OK, (rep.as_dict(), ref.status)
+    assert rep.relres_true <= 1e-10 and true_relres(A, x, b) <= 1e-10
+    assert np.linalg.norm(x - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+    assert abs(rep.iters - ref.iters) <= max(5, ref.iters // 10)
+
+
+def test_gmres_first_cycle_residuals_match_oracle():
+    """Within one cycle the GMRES residual estimates follow the oracle's
+    (CGS2 on both sides) to rounding."""
+    A = convdiff2d(32, 5)
+    _, b = rhs_from_solution(A, 5)
+    rep, x, hist, _ = gpu_solve("csr", A, b, G.GMRES, max_iter=30)
+    ref = O.gmres(A.indptr, b, oracle_params(G.GMRES, fixed=-1, max_iter=30), A.indices, A.data)
+    assert rep.iters == ref.iters == 30
+    assert np.allclose(hist[:31], ref.hist[:31], rtol=1e-8, atol=1e-15)
+
+
+def test_cg_small_dense_and_edge_cases():
+    import scipy.sparse as sp
+    rng = np.random.default_rng(7)
+    for n in (1, 5, 12):
+        Mx = rng.standard_normal((n, n))
+        D = Mx @ Mx.T + n * np.eye(n)
+        A = CSR.from_scipy(sp.csr_matrix(D))
+        b = rng.standard_normal(n)
+        rep, x, _, _ = gpu_solve("gse", A, b, G.CG, fixed=3)
+        assert rep.status == G.OK
+        assert np.allclose(x, np.linalg.solve(D, b), rtol=1e-8, atol=1e-10)
+    # b = 0 -> x = 0
+    A = poisson2d(8)
+    rep, x, _, _ = gpu_solve("gse", A, np.zeros(A.n_rows), G.CG, x0=np.ones(A.n_rows))
+    assert rep.status == G.OK and np.all(x == 0)
+    # indefinite: breakdown with all segments
+    Ai = CSR.from_scipy(sp.csr_matrix(np.diag([1.0, -1.0, 2.0])))
+    rep, _, _, _ = gpu_solve("gse", Ai, np.ones(3), G.CG, fixed=3)
+    assert rep.status == G.ERR_BREAKDOWN
+    rep, _, _, _ = gpu_solve("csr", Ai, np.ones(3), G.CG)
+    assert rep.status == G.ERR_BREAKDOWN
+
+
+def test_solver_argument_errors():
+    A = poisson2d(8)
+    rp, ci, va = to_dev(A)
+    M = G.GseMatrix(rp, ci, va, A.n_cols)
+    p = G.gse_default_params(G.CG)
+    ws = torch.empty(1024, dtype=torch.uint8, device=DEV)
+    x = torch.zeros(A.n_rows, dtype=torch.float64, device=DEV)
+    b = torch.ones(A.n_rows, dtype=torch.float64, device=DEV)
+    with pytest.raises(G.GseError) as ei:
+        G.gse_cg(M.A, b, x, p, ws)
+    assert ei.value.status == G.ERR_NOMEM
+    p.start_segments = 4
+    ws = torch.empty(G.gse_solver_workspace(G.CG, A.n_rows, A.nnz, 30, p.max_iter),
+                     dtype=torch.uint8, device=DEV)
+    with pytest.raises(G.GseError) as ei:
+        G.gse_cg(M.A, b, x, p, ws)
+    assert ei.value.status == G.ERR_ARG

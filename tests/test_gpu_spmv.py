@@ -73,11 +73,16 @@ def _check_close(got, ref, scale, tol=1e-12):
         assert np.linalg.norm(got - ref) <= tol * nr + 1e-300
 
 
-@pytest.mark.parametrize("tile", [1024, 2048, 4096])
-def test_spmv_all_segments(case, tile):
+SCHEDULES = [(1024, 0), (2048, 0), (4096, 0), (2048, 1), (2048, 2), (2048, 8), (2048, 64)]
+
+
+@pytest.mark.parametrize("sched", SCHEDULES, ids=[f"t{t}_rv{r}" for t, r in SCHEDULES])
+def test_spmv_all_segments(case, sched):
     name, A, enc, M = case
-    M.plan(tile)
-    rng = np.random.default_rng(tile)
+    tile, rv = sched
+    M.plan(tile, rv)
+    assert M.A.rv_lanes == rv and M.A.tile_nnz == tile
+    rng = np.random.default_rng(tile + rv)
     x = rng.uniform(-1, 1, A.n_cols)
     xd = torch.from_numpy(x).to(DEV)
     yd = torch.full((A.n_rows,), np.nan, dtype=torch.float64, device=DEV)
@@ -91,14 +96,14 @@ def test_spmv_all_segments(case, tile):
         np.add.at(scale, np.repeat(np.arange(A.n_rows), np.diff(A.indptr)),
                   np.abs(dec * x[A.indices]))
         _check_close(y, ref, scale)
-    M.plan(2048)
+    M.plan()
 
 
-@pytest.mark.parametrize("tile", [1024, 4096])
-def test_csr64_spmv(case, tile):
+@pytest.mark.parametrize("sched", [(1024, 0), (4096, 0), (2048, 4), (2048, 16)])
+def test_csr64_spmv(case, sched):
     name, A, enc, M = case
     rp, ci, va = to_dev(A)
-    C64 = G.CsrMatrix(rp, ci, va, A.n_cols, tile_nnz=tile)
+    C64 = G.CsrMatrix(rp, ci, va, A.n_cols, tile_nnz=sched[0], rv_lanes=sched[1])
     x = np.random.default_rng(3).uniform(-1, 1, A.n_cols)
     yd = torch.empty(A.n_rows, dtype=torch.float64, device=DEV)
     C64.spmv(torch.from_numpy(x).to(DEV), yd)
@@ -169,13 +174,23 @@ def test_empty_matrix():
     assert torch.equal(y, torch.zeros_like(y))
 
 
+def test_default_schedule_choice():
+    """Stencils get the row-vector schedule, power-law rows the tiles."""
+    for A, want in ((diffusion3d(16, 0), 8), (poisson2d(32), 8), (powerlaw(20_000, 2), 0)):
+        rp, ci, va = to_dev(A)
+        M = G.GseMatrix(rp, ci, va, A.n_cols)
+        assert M.A.rv_lanes == want, A.name
+        assert M.A.max_row_nnz == int(np.diff(A.indptr).max())
+
+
 def test_full_size_diffusion3d_128_sampled():
     """The 128^3 operator at full size, in the launch configuration the
-    benchmark times: the whole planes bit-exact, sampled rows of y against the
-    oracle row by row."""
+    benchmark times (default schedule): the whole planes bit-exact, sampled
+    rows of y against the oracle row by row."""
     A = diffusion3d(128, 0)
     rp, ci, va = to_dev(A)
     M = G.GseMatrix(rp, ci, va, A.n_cols)
+    assert M.A.rv_lanes == 8
     enc = O.encode(A.indptr, A.indices, A.data, A.n_cols)
     assert M.sem == [int(s) for s in enc.sem]
     for got, want in zip(M.planes(), (enc.col_idx, enc.head, enc.tail1, enc.tail2)):

@@ -12,11 +12,31 @@ import pytest
 
 from workloads import (diffusion3d, convdiff2d, poisson2d, powerlaw, random_sparse)
 
-WG, EXTRA, SHORT, PAD = 256, 256, 24, 16
+WG, EXTRA, SHORT, PAD, SPEC = 256, 256, 24, 16, 16
 
 
 def lower_bound(a, v):
     return int(np.searchsorted(a, v, side="left"))
+
+
+def walk(n_tiles, g):
+    """Tiles visited by each persistent workgroup (mirrors TileWalk)."""
+    seen = []
+    for wg in range(g):
+        xcd, local = wg & 7, wg >> 3
+        nx = (g >> 3) + (1 if (g & 7) > xcd else 0)
+        tb, te = (n_tiles * xcd) >> 3, (n_tiles * (xcd + 1)) >> 3
+        seen += list(range(tb + local, te, nx))
+    return seen
+
+
+@pytest.mark.parametrize("n_tiles", [1, 5, 8, 9, 63, 1000, 7121])
+@pytest.mark.parametrize("resident", [8, 1536, 2048])
+def test_persistent_walk_covers_every_tile_once(n_tiles, resident):
+    g = min(resident, (n_tiles + 7) // 8 * 8)
+    g = max(g, 8)
+    seen = walk(n_tiles, g)
+    assert sorted(seen) == list(range(n_tiles))
 
 
 def check(indptr, n_cols, cols, E):
@@ -27,7 +47,7 @@ def check(indptr, n_cols, cols, E):
     n_tiles = max(1, -(-nnz // T))
     starts = indptr[:n_rows]
     tile_row = [lower_bound(starts, t * T) for t in range(n_tiles)] + [n_rows]
-    nprod = (T + EXTRA) + (T + EXTRA) // E
+    nprod = (T + EXTRA) + (T + EXTRA) // 8
     ndef_cap = (T + EXTRA) // (SHORT + 1) + 2
     written = np.zeros(n_rows, np.int32)
     assert tile_row[0] == 0 or n_rows == 0
@@ -42,17 +62,21 @@ def check(indptr, n_cols, cols, E):
         tail = (je - j1) <= EXTRA
         jl = je if tail else j1
         assert jl <= nnz and jl <= j1 + EXTRA
-        bases = [j0 + tid * E for tid in range(WG)]
-        bases += [j1 + tid * E for tid in range(EXTRA // E) if j1 + tid * E < jl]
-        for base in bases:
-            if base + E > js and base < jl:
-                assert base % E == 0 and base + E <= pad  # aligned vector loads in bounds
-                lo, hi = max(base, js), min(base + E, jl)
-                if hi > lo:
-                    li = np.arange(lo, hi) - j0
-                    slot = li + li // E
-                    assert slot.min() >= 0 and slot.max() < nprod
-                    assert cols[lo:hi].max() < n_cols
+        # plane loads issued before the row lookup (main vector groups, bounded
+        # by nnz only) and the one-element look-ahead of lanes < SPEC
+        for b in [j0 + tid * E for tid in range(WG)]:
+            if b < nnz:
+                assert b % E == 0 and b + E <= pad
+        # every staged non-zero [js, jl) lands in a valid LDS slot
+        if jl > js:
+            li = np.arange(js, jl) - j0
+            slot = li + li // 8
+            assert slot.min() >= 0 and slot.max() < nprod
+            assert cols[js:jl].max() < n_cols
+        # row pointers staged for rows ra .. ra + min(nr, 511)
+        nr = rb - ra
+        nstage = min(nr, 2 * WG - 1)
+        assert ra + nstage <= n_rows
         ndef = 0
         for r in range(ra, rb):
             written[r] += 1
