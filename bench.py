@@ -38,6 +38,13 @@ def spmv_bytes(n_rows, n_cols, nnz, plane_bytes):
     return nnz * plane_bytes + (n_rows + 1) * 4 + n_cols * 8 + n_rows * 8
 
 
+def kernel_name(A):
+    """Name of the kernel instance the one-segment SpMV runs on this schedule."""
+    if A.rv_lanes > 0:
+        return f"k_spmv_rv<1, {A.rv_lanes}>"
+    return f"k_spmv<1, {A.tile_nnz // 256}>"
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,11 +180,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"diffusion3d_{args.grid}^3_7pt_varcoef_4decades",
                    "n_rows": A.n_rows, "nnz": A.nnz, "copies_rotated": args.copies,
-                   "x": "ones", "seed": args.seed, "tile_nnz": mats[0].A.tile_nnz},
+                   "x": "ones", "seed": args.seed, "tile_nnz": mats[0].A.tile_nnz,
+                   "rv_lanes": mats[0].A.rv_lanes},
         "spmv": spmv,
         "roofline": {"bound": "hbm", "achieved": spmv["s1"]["GBps"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": spmv["s1"]["frac_peak"], "traffic": None,
-                     "kernel": "k_spmv<1,8>",
+                     "kernel": kernel_name(mats[0].A),
                      "bytes_per_launch": spmv["s1"]["bytes"]},
     }
     if solve:

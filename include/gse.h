@@ -133,7 +133,7 @@ gse_status gse_encode_workspace(int64_t nnz, int32_t n_rows, size_t* ws_bytes);
  *                       shared exponent gives GSE_ERR_RANGE.
  *   A                 : in: plane pointers and tile_row/tile_cap; out: every
  *                       other field; the SpMV schedule is chosen as by
- *                       gse_plan(A, 2048, -1).
+ *                       gse_plan(A, 1024, -1).
  *   ws, ws_bytes      : device workspace of gse_encode_workspace() bytes.
  * Errors: GSE_ERR_NONFINITE (Inf/NaN value), GSE_ERR_RANGE (sizes, a shared
  * exponent below 63 whose grid would leave the normal range, uncovered
@@ -149,10 +149,8 @@ gse_status gse_encode(const int32_t* row_ptr, const int32_t* col, const double* 
  *               or 4096) per workgroup step, rows of any length;
  *   row-vector  (rv_lanes = 1, 2, 4, ..., 64): that many lanes per row,
  *               for matrices whose rows are short and of similar length.
- * rv_lanes == -1 picks one from the row lengths (row-vector with the power
- * of two at or above the mean row length when no row is longer than 64 and
- * four times the mean, tiles otherwise).  The tile table is always built.
- * Synchronizes `stream`. */
+ * rv_lanes == -1 picks the default (tiles).  The tile table is always
+ * built.  Synchronizes `stream`. */
 gse_status gse_plan(gse_matrix* A, int32_t tile_nnz, int32_t rv_lanes, void* stream);
 gse_status gse_csr_plan(gse_csr* M, int32_t tile_nnz, int32_t rv_lanes, void* stream);
 
@@ -163,6 +161,17 @@ gse_status gse_csr_plan(gse_csr* M, int32_t tile_nnz, int32_t rv_lanes, void* st
  * [n_rows]; x and y must not overlap.  Asynchronous on `stream`. */
 gse_status gse_spmv(const gse_matrix* A, int32_t k_segments, const double* x, double* y,
                     void* stream);
+
+/* Choose the SpMV schedule of A for k_segments by timing the candidates
+ * (tiles of 1024 / 2048 / 4096 non-zeros; 4, 8 or 16 lanes per row when no
+ * row is longer than 64) with `reps` launches each on the caller's x
+ * (device [n_cols]) and y (device [n_rows], overwritten), then plan the
+ * fastest.  Results are cached per process by matrix shape and, if the
+ * environment variable GSE_AUTOTUNE_CACHE names a file, in that file.
+ * Synchronizes `stream`. */
+gse_status gse_autotune(gse_matrix* A, int32_t k_segments, const double* x, double* y,
+                        int32_t reps, void* stream);
+gse_status gse_csr_autotune(gse_csr* M, const double* x, double* y, int32_t reps, void* stream);
 
 /* Baseline: y = A x with plain FP64 CSR values on the same tile schedule
  * (the FP64-SpMV the paper compares against, Section IV-A). */
@@ -197,7 +206,8 @@ typedef struct gse_params {
     int32_t ndec_rule;        /* 0: compare nDec with ndec_limit; 1: with t/2 */
     double floor_c;           /* floor trigger factor, 0 disables */
     int32_t switch_mode;      /* CG after a switch: 0 p = r, 1 keep p */
-    int32_t record_history;   /* 1: fill gse_solve_history() buffers */
+    int32_t record_history;   /* kept for callers; the history is always recorded */
+    int32_t launch_mode;      /* 0: iterations replayed from HIP graphs, 1: direct launches */
 } gse_params;
 
 typedef struct gse_report {
@@ -242,6 +252,97 @@ gse_status gse_csr_gmres(const gse_csr* M, const double* b, double* x, const gse
  * hist / seg: host arrays of at least cap entries.  Synchronizes. */
 gse_status gse_solve_history(const void* ws, int32_t cap, double* hist, int32_t* seg,
                              void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched stepped CG: n_sys independent SPD systems of any sizes solved
+ * together, each with its own operator, segment count and stepped controller
+ * (Section III-D per system), all advanced by one set of kernel launches per
+ * iteration (16-iteration epochs replayed from a HIP graph when
+ * p->launch_mode == 0).  A system's iterates and result are bit-identical
+ * whether it is solved alone or in any batch.  The SpMV stages tiles of up to
+ * 2048 non-zeros in LDS, so operators planned with tile_nnz 1024 (the
+ * default) run fastest; any valid plan is accepted. */
+typedef struct gse_system {
+    const gse_matrix* A;   /* stepped GSE-SEM operator, or NULL */
+    const gse_csr* M;      /* FP64 CSR operator, used when A is NULL */
+    const double* b;       /* device [n_rows] */
+    double* x;             /* device [n_rows], 16-byte aligned: x0 in, solution out */
+} gse_system;
+
+/* Workspace bytes for gse_batch_cg on these systems with p->max_iter. */
+gse_status gse_batch_workspace(int32_t n_sys, const gse_system* sys, const gse_params* p,
+                               size_t* ws_bytes);
+
+/* Solve all systems with the same parameters `p` (CG presets).  rep: host
+ * array of n_sys reports.  ws: device, 256-byte aligned, at least
+ * gse_batch_workspace bytes; it holds the per-system vectors, histories and
+ * the work lists.  Blocks until every system has stopped.  Returns GSE_OK
+ * when all converged, else the first non-OK status in system order (each
+ * report carries its own). */
+gse_status gse_batch_cg(int32_t n_sys, const gse_system* sys, const gse_params* p,
+                        gse_report* rep, void* ws, size_t ws_bytes, void* stream);
+
+/* Residual and segment history of system `index` of the last gse_batch_cg
+ * on `ws` (as gse_solve_history).  Synchronizes. */
+gse_status gse_batch_history(const void* ws, int32_t index, int32_t cap, double* hist,
+                             int32_t* seg, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Solver server: requests (host CSR + b) arrive at any time and join the
+ * running batch of stepped CG solves above.  The caller hands over one
+ * device arena at creation; the server sub-allocates every device buffer of
+ * a request from it (operator planes, vectors, history, plus a transient
+ * FP64 copy and encode workspace released right after the encode) and never
+ * calls hipMalloc.  Admission is first come, first served: the oldest
+ * waiting request starts as soon as a batch slot is free and its blocks fit
+ * in the arena.  One worker thread per server does the device work on its
+ * own stream; submit / poll / stats are thread-safe. */
+#define GSE_FMT_GSE 0      /* stepped GSE-SEM operator (encoded on arrival) */
+#define GSE_FMT_CSR64 1    /* FP64 CSR operator (the baseline) */
+
+typedef struct gse_request {
+    int32_t n_rows;          /* square system, n_rows >= 1 */
+    int64_t nnz;
+    const int32_t* row_ptr;  /* host CSR [n_rows+1], [nnz], [nnz]; with b and x these */
+    const int32_t* col;      /* host arrays must stay valid until the ticket completes */
+    const double* val;
+    const double* b;         /* host [n_rows] */
+    double* x;               /* host [n_rows]: x0 when x0_given, the solution on completion */
+    int32_t format;          /* GSE_FMT_GSE or GSE_FMT_CSR64 */
+    int32_t num_exp;         /* shared exponents for GSE_FMT_GSE (1..8) */
+    int32_t x0_given;        /* 1: start from x, 0: from zero */
+    gse_params params;       /* CG parameters (gse_default_params(GSE_CG, ...)) */
+} gse_request;
+
+typedef struct gse_solver gse_solver;
+
+typedef struct gse_server_stats {
+    int64_t queued;               /* submitted, waiting for admission */
+    int64_t running;              /* admitted, not finished */
+    int64_t admitted, completed;  /* totals since creation */
+    int64_t arena_bytes;          /* bytes the requests may use */
+    int64_t arena_used, arena_peak, arena_largest_free;
+} gse_server_stats;
+
+/* arena: device, 256-byte aligned, owned by the caller and untouched by it
+ * until gse_solver_destroy returns; a fixed part holds the batch tables for
+ * max_slots systems.  stream: the caller's stream, synchronized once so the
+ * arena is ready.  The device current at the call is the server's. */
+gse_status gse_solver_create(void* arena, size_t arena_bytes, int32_t max_slots, void* stream,
+                             gse_solver** out);
+/* Bytes a request occupies while it runs (resident) and during its encode
+ * (transient, GSE only). */
+gse_status gse_solver_footprint(const gse_request* rq, size_t* resident, size_t* transient);
+/* Queue a request (validated on the host, CSR structure included); returns a
+ * ticket.  GSE_ERR_NOMEM if it can never fit in the arena. */
+gse_status gse_solver_submit(gse_solver* s, const gse_request* rq, uint64_t* ticket);
+/* GSE_PENDING while the ticket runs or waits; GSE_OK once it has finished,
+ * with rep filled (rep->status: the solve's status; rep->time_ms: submit to
+ * completion) and the ticket retired; GSE_ERR_TICKET for an unknown one. */
+gse_status gse_solver_poll(gse_solver* s, uint64_t ticket, gse_report* rep);
+gse_status gse_solver_stats(gse_solver* s, gse_server_stats* out);
+/* Stop the worker after its current step; unfinished tickets are dropped. */
+gse_status gse_solver_destroy(gse_solver* s);
 
 /* ------------------------------------------------------------------------ */
 /* Diagnostic: dst = src, `bytes` a multiple of 16, both 16-byte aligned;

@@ -4,6 +4,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <vector>
+
+#include "batch.h"
 #include "gse_internal.h"
 
 namespace gse {
@@ -18,6 +21,8 @@ gse_status fail(gse_status code, const char* fmt, ...) {
   return code;
 }
 
+const char* last_error_text() { return g_err; }
+
 gse_status hip_fail(hipError_t e, const char* where) {
   return fail(GSE_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
 }
@@ -30,14 +35,14 @@ bool valid_tile(int32_t t) { return t == kWG * 4 || t == kWG * 8 || t == kWG * 1
 
 bool valid_rv(int32_t L) { return L == 0 || (L >= 1 && L <= 64 && (L & (L - 1)) == 0); }
 
-// Row-vector lanes for near-uniform short rows, 0 (tiles) otherwise.
+// Default schedule: the tile schedule, which measured faster than the
+// row-vector one on every matrix family here (both formats).  gse_autotune
+// times the alternatives on the matrix itself.
 int32_t auto_rv(int64_t nnz, int32_t n_rows, int32_t max_row) {
-  if (n_rows <= 0 || nnz == 0) return 0;
-  const double mean = (double)nnz / (double)n_rows;
-  if (max_row > 64 || (double)max_row > 4.0 * mean + 4.0) return 0;
-  int32_t L = 1;
-  while ((double)L < mean && L < 64) L <<= 1;
-  return L < 2 ? 2 : L;
+  (void)nnz;
+  (void)n_rows;
+  (void)max_row;
+  return 0;
 }
 
 // Tile table for tile_nnz plus the longest row; picks the schedule.
@@ -76,6 +81,7 @@ SpmvOperand operand_of(const gse_matrix* A) {
   o.tile_nnz = A->tile_nnz;
   o.nnz = (int32_t)A->nnz;
   o.rv_lanes = A->rv_lanes;
+  o.max_row = A->max_row_nnz;
   for (int i = 0; i < GSE_MAX_EXP; ++i) o.sem[i] = A->sem[i];
   return o;
 }
@@ -94,6 +100,7 @@ SpmvOperand operand_of(const gse_csr* M) {
   o.tile_nnz = M->tile_nnz;
   o.nnz = (int32_t)M->nnz;
   o.rv_lanes = M->rv_lanes;
+  o.max_row = M->max_row_nnz;
   for (int i = 0; i < GSE_MAX_EXP; ++i) o.sem[i] = 0;
   return o;
 }
@@ -246,6 +253,38 @@ gse_status gse_encode(const int32_t* row_ptr, const int32_t* col, const double* 
   return GSE_OK;
 }
 
+gse_status gse_autotune(gse_matrix* A, int32_t k_segments, const double* x, double* y,
+                        int32_t reps, void* stream) {
+  gse_status s = check_matrix(A);
+  if (s != GSE_OK) return s;
+  if (k_segments < 1 || k_segments > 3) return fail(GSE_ERR_ARG, "k_segments must be 1..3");
+  if (!x || !y || reps < 1) return fail(GSE_ERR_ARG, "x, y and reps >= 1 are required");
+  if (A->n_rows == 0) return GSE_OK;
+  int32_t t, rv, nt;
+  s = autotune(k_segments, k_segments, operand_of(A), A->row_ptr, A->tile_row, A->tile_cap,
+               A->max_row_nnz, x, y, reps, (hipStream_t)stream, &t, &rv, &nt);
+  if (s != GSE_OK) return s;
+  A->tile_nnz = t;
+  A->rv_lanes = rv;
+  A->n_tiles = nt;
+  return GSE_OK;
+}
+
+gse_status gse_csr_autotune(gse_csr* M, const double* x, double* y, int32_t reps, void* stream) {
+  gse_status s = check_csr(M);
+  if (s != GSE_OK) return s;
+  if (!x || !y || reps < 1) return fail(GSE_ERR_ARG, "x, y and reps >= 1 are required");
+  if (M->n_rows == 0) return GSE_OK;
+  int32_t t, rv, nt;
+  s = autotune(kCsr64, 0, operand_of(M), M->row_ptr, M->tile_row, M->tile_cap, M->max_row_nnz, x,
+               y, reps, (hipStream_t)stream, &t, &rv, &nt);
+  if (s != GSE_OK) return s;
+  M->tile_nnz = t;
+  M->rv_lanes = rv;
+  M->n_tiles = nt;
+  return GSE_OK;
+}
+
 gse_status gse_spmv(const gse_matrix* A, int32_t k_segments, const double* x, double* y, void* stream) {
   gse_status s = check_matrix(A);
   if (s != GSE_OK) return s;
@@ -363,6 +402,91 @@ gse_status gse_solve_history(const void* ws, int32_t cap, double* hist, int32_t*
   if (!ws || cap < 0 || (cap > 0 && (!hist || !seg))) return fail(GSE_ERR_ARG, "bad arguments");
   if (cap == 0) return GSE_OK;
   return solve_history(ws, cap, hist, seg, (hipStream_t)stream);
+}
+
+static gse_status batch_descs(int32_t n_sys, const gse_system* sys, const gse_params* p,
+                              std::vector<BatchSystemDesc>* out) {
+  if (n_sys < 1 || !sys || !p) return fail(GSE_ERR_ARG, "bad arguments");
+  if (!(p->tol > 0.0) || p->max_iter < 0) return fail(GSE_ERR_ARG, "tol must be > 0, max_iter >= 0");
+  if (p->start_segments < 1 || p->start_segments > 3 || p->fixed_segments < 0 || p->fixed_segments > 3)
+    return fail(GSE_ERR_ARG, "segment counts must be 1..3 (fixed: 0..3)");
+  if (p->l < 0 || p->t < 1 || p->m < 0) return fail(GSE_ERR_ARG, "controller needs l >= 0, t >= 1, m >= 0");
+  out->clear();
+  for (int i = 0; i < n_sys; ++i) {
+    const gse_system& y = sys[i];
+    if ((y.A == nullptr) == (y.M == nullptr))
+      return fail(GSE_ERR_ARG, "system %d: give exactly one of A and M", i);
+    BatchSystemDesc d{};
+    BatchSlot& B = d.slot;
+    gse_status s;
+    if (y.A) {
+      s = check_matrix(y.A);
+      if (s != GSE_OK) return s;
+      const gse_matrix* A = y.A;
+      if (A->n_rows != A->n_cols || A->n_rows < 1)
+        return fail(GSE_ERR_ARG, "system %d: the matrix must be square and non-empty", i);
+      B.row_ptr = A->row_ptr;
+      B.tile_row = A->tile_row;
+      B.col = A->col_idx;
+      B.head = A->head;
+      B.tail1 = A->tail1;
+      B.tail2 = A->tail2;
+      B.n_rows = A->n_rows;
+      B.n_tiles = A->n_tiles;
+      B.fmt = 1;
+      for (int k = 0; k < GSE_MAX_EXP; ++k) B.sem[k] = A->sem[k];
+      d.eta = A->eta;
+    } else {
+      s = check_csr(y.M);
+      if (s != GSE_OK) return s;
+      const gse_csr* M = y.M;
+      if (M->n_rows != M->n_cols || M->n_rows < 1)
+        return fail(GSE_ERR_ARG, "system %d: the matrix must be square and non-empty", i);
+      B.row_ptr = M->row_ptr;
+      B.tile_row = M->tile_row;
+      B.col = reinterpret_cast<const uint32_t*>(M->col);
+      B.val = M->val;
+      B.n_rows = M->n_rows;
+      B.n_tiles = M->n_tiles;
+      B.fmt = 0;
+      d.eta = nullptr;
+    }
+    if (!y.b || !y.x || !aligned16(y.x)) return fail(GSE_ERR_ARG, "system %d: bad b / x", i);
+    B.b = y.b;
+    B.x = y.x;
+    d.n_rows = B.n_rows;
+    d.n_tiles = B.n_tiles;
+    out->push_back(d);
+  }
+  return GSE_OK;
+}
+
+gse_status gse_batch_workspace(int32_t n_sys, const gse_system* sys, const gse_params* p,
+                               size_t* ws_bytes) {
+  if (!ws_bytes) return fail(GSE_ERR_ARG, "ws_bytes is NULL");
+  std::vector<BatchSystemDesc> d;
+  gse_status s = batch_descs(n_sys, sys, p, &d);
+  if (s != GSE_OK) return s;
+  *ws_bytes = batch_workspace_bytes(n_sys, d.data(), p->max_iter);
+  return GSE_OK;
+}
+
+gse_status gse_batch_cg(int32_t n_sys, const gse_system* sys, const gse_params* p,
+                        gse_report* rep, void* ws, size_t ws_bytes, void* stream) {
+  std::vector<BatchSystemDesc> d;
+  gse_status s = batch_descs(n_sys, sys, p, &d);
+  if (s != GSE_OK) return s;
+  if (!rep) return fail(GSE_ERR_ARG, "reports are NULL");
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u))
+    return fail(GSE_ERR_ARG, "workspace must be non-NULL and 256-byte aligned");
+  return batch_cg(n_sys, d.data(), p, rep, ws, ws_bytes, (hipStream_t)stream);
+}
+
+gse_status gse_batch_history(const void* ws, int32_t index, int32_t cap, double* hist,
+                             int32_t* seg, void* stream) {
+  if (!ws || cap < 0 || (cap > 0 && (!hist || !seg))) return fail(GSE_ERR_ARG, "bad arguments");
+  if (cap == 0) return GSE_OK;
+  return batch_history(ws, index, cap, hist, seg, (hipStream_t)stream);
 }
 
 gse_status gse_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {

@@ -1,0 +1,150 @@
+// autotune.hip -- picks the SpMV schedule (tile size / lanes per row) of a
+// matrix by timing the candidates on the device, with a per-process cache
+// and an optional cache file (GSE_AUTOTUNE_CACHE) keyed by a signature of
+// the matrix shape.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gse_internal.h"
+
+namespace gse {
+
+gse_status fail(gse_status code, const char* fmt, ...);
+gse_status hip_fail(hipError_t e, const char* where);
+
+namespace {
+
+struct Choice {
+  int32_t tile;
+  int32_t rv;
+  float us;
+};
+
+std::mutex g_mu;
+std::map<std::string, Choice> g_cache;
+bool g_file_loaded = false;
+
+std::string key_of(int fmt, int segs, int32_t n_rows, int64_t nnz, int32_t max_row) {
+  char b[160];
+  snprintf(b, sizeof b, "f%d_s%d_n%d_z%lld_m%d", fmt, segs, n_rows, (long long)nnz, max_row);
+  return b;
+}
+
+void load_file() {
+  if (g_file_loaded) return;
+  g_file_loaded = true;
+  const char* path = getenv("GSE_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char key[160];
+  int tile, rv;
+  float us;
+  while (fscanf(f, "%159s %d %d %f", key, &tile, &rv, &us) == 4) g_cache[key] = Choice{tile, rv, us};
+  fclose(f);
+}
+
+void save_entry(const std::string& k, const Choice& c) {
+  const char* path = getenv("GSE_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%s %d %d %.3f\n", k.c_str(), c.tile, c.rv, c.us);
+  fclose(f);
+}
+
+// Median time (us) of `reps` launches of one schedule.
+hipError_t time_one(int fmt, SpmvOperand op, const double* x, double* y, int reps, hipStream_t st,
+                    float* us) {
+  SpmvEpilogue ep{};
+  ep.epi = kEpiPlain;
+  hipError_t e = launch_spmv(fmt, op, x, y, ep, st);  // warm-up
+  if (e != hipSuccess) return e;
+  std::vector<float> t;
+  hipEvent_t a, b;
+  if ((e = hipEventCreate(&a)) != hipSuccess) return e;
+  if ((e = hipEventCreate(&b)) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return e;
+  }
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    e = hipEventRecord(a, st);
+    if (e == hipSuccess) e = launch_spmv(fmt, op, x, y, ep, st);
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    t.push_back(ms * 1000.f);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return e;
+  std::sort(t.begin(), t.end());
+  *us = t[t.size() / 2];
+  return hipSuccess;
+}
+
+}  // namespace
+
+gse_status autotune(int fmt, int segs, SpmvOperand op, const int32_t* row_ptr, int32_t* tile_row,
+                    int32_t tile_cap, int32_t max_row, const double* x, double* y, int32_t reps,
+                    hipStream_t st, int32_t* out_tile, int32_t* out_rv, int32_t* out_tiles) {
+  const std::string k = key_of(fmt, segs, op.n_rows, op.nnz, max_row);
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    load_file();
+    auto it = g_cache.find(k);
+    if (it != g_cache.end()) {
+      *out_tile = it->second.tile;
+      *out_rv = it->second.rv;
+      *out_tiles = n_tiles_for(op.nnz, *out_tile);
+      hipError_t e = launch_plan(row_ptr, op.n_rows, op.nnz, *out_tile, *out_tiles, tile_row, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      return e == hipSuccess ? GSE_OK : hip_fail(e, "autotune plan");
+    }
+  }
+  struct Cand {
+    int tile, rv;
+  };
+  std::vector<Cand> cands = {{1024, 0}, {2048, 0}, {4096, 0}};
+  if (max_row <= 64)
+    for (int L : {4, 8, 16})
+      if (L >= max_row / 4) cands.push_back({1024, L});
+  Choice best{0, 0, 1e30f};
+  for (const Cand& c : cands) {
+    const int32_t nt = n_tiles_for(op.nnz, c.tile);
+    if (tile_cap < nt + 2) continue;
+    hipError_t e = launch_plan(row_ptr, op.n_rows, op.nnz, c.tile, nt, tile_row, st);
+    SpmvOperand o = op;
+    o.tile_row = tile_row;
+    o.tile_nnz = c.tile;
+    o.n_tiles = nt;
+    o.rv_lanes = c.rv;
+    float us = 0.f;
+    if (e == hipSuccess) e = time_one(fmt, o, x, y, reps, st, &us);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    if (us < best.us) best = Choice{c.tile, c.rv, us};
+  }
+  const int32_t nt = n_tiles_for(op.nnz, best.tile);
+  hipError_t e = launch_plan(row_ptr, op.n_rows, op.nnz, best.tile, nt, tile_row, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "autotune plan");
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_cache[k] = best;
+    save_entry(k, best);
+  }
+  *out_tile = best.tile;
+  *out_rv = best.rv;
+  *out_tiles = nt;
+  return GSE_OK;
+}
+
+}  // namespace gse

@@ -1,0 +1,945 @@
+// batch.hip -- batched stepped CG on gfx950: many independent systems of
+// uneven size advanced by ONE set of kernel launches per iteration.
+//
+// Each system keeps its own operator (GSE-SEM planes at its own segment
+// count, or FP64 CSR), vectors, state record and stepped controller
+// (Section III-D: Algorithm 3, Eqs. 3-6, Conditions 1-3, applied per
+// system).  The work of an iteration is flattened into lists -- SpMV tiles
+// and row chunks of every live system -- that persistent workgroups walk;
+// per-system scalars (alpha, beta, the controller) are finished by one
+// workgroup per system.  Kernel boundaries are the only barriers, so no
+// workgroup ever waits on another and there are no cross-XCD fences.
+//
+// The kernels read the list lengths from device memory, so the iteration
+// epoch (16 iterations) is captured into a HIP graph once per engine and
+// replayed whatever the batch holds; between epochs the host reads the
+// state records back, runs the actions a switch or a convergence candidate
+// needs (residual replacement, the all-segment residual check) for the
+// systems concerned, and rebuilds the lists when systems finish or arrive.
+//
+// Every partial sum of a system goes to a slot fixed by that system's own
+// tile / chunk index and is summed in a fixed order, so a system's iterates
+// are bit-identical whether it is solved alone or among others.
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+
+#include "batch.h"
+#include "decode.h"
+
+namespace gse {
+
+gse_status fail(gse_status code, const char* fmt, ...);
+gse_status hip_fail(hipError_t e, const char* where);
+
+namespace {
+
+constexpr int kNS = 2048;       // non-zeros of one tile staged in LDS
+constexpr int kLongRow = 64;    // unstaged tiles: longer rows take the whole workgroup
+constexpr int kEpochIters = 16;
+
+enum Phase : int {
+  kPhFree = 0,
+  kPhInit,
+  kPhRun,
+  kPhCheck,    // the recursive residual met the tolerance: check with all segments
+  kPhReplace,  // residual replacement after a switch or a failed check
+  kPhFinal,    // stopped: final all-segment residual for the report
+  kPhZero,     // b = 0: x = 0
+  kPhDone,
+};
+enum Origin : int { kFromSwitch = 0, kFromCheck = 1 };
+
+// Persistent walk over [0, n): workgroup w works in the range of its XCD
+// (workgroups are dispatched to the eight XCDs round-robin), so tiles in
+// flight on one XCD are neighbours and share x in its L2.  The grid is a
+// multiple of 8; the eight ranges partition [0, n).
+struct Walk {
+  int i, end, step;
+};
+__device__ __forceinline__ Walk walk_of(int n) {
+  const int nx = (int)(gridDim.x >> 3);
+  const int xcd = (int)(blockIdx.x & 7), local = (int)(blockIdx.x >> 3);
+  const int b = (int)(((long long)n * xcd) >> 3);
+  const int e = (int)(((long long)n * (xcd + 1)) >> 3);
+  return Walk{b + local, e, nx};
+}
+
+template <int FMT>
+__device__ __forceinline__ double load_decode(const BatchSlot& B, int j, const double* scale,
+                                              int& col) {
+  const uint32_t c = B.col[j];
+  uint32_t h = 0, t1 = 0, t2 = 0;
+  double v = 0.0;
+  if constexpr (FMT == kCsr64) {
+    v = B.val[j];
+  } else {
+    h = B.head[j];
+    if constexpr (FMT >= 2) t1 = B.tail1[j];
+    if constexpr (FMT == 3) t2 = B.tail2[j];
+  }
+  return decode<FMT>(c, h, t1, t2, v, scale, col);
+}
+
+// Rows of tile t (those whose first non-zero lies in the tile's range, from
+// the matrix's own tile table).  The non-zeros of these rows are decoded
+// into LDS when they fit, then each row is summed by one thread in row
+// order.  Otherwise (a row running far past the tile) short rows are summed
+// from memory by one thread and long ones by the whole workgroup.  Returns
+// this thread's share of the epilogue dot.
+template <int FMT>
+__device__ double tile_rows(const BatchSlot& B, int t, const double* __restrict__ xin,
+                            double* __restrict__ yout, const double* __restrict__ aux, int epi,
+                            double* vals, int* cols, double* scale, double* red) {
+  const int tid = threadIdx.x;
+  const int ra = B.tile_row[t], rb = B.tile_row[t + 1];
+  const int j0 = B.row_ptr[ra], j1 = B.row_ptr[rb];
+  const int ext = j1 - j0;
+  __syncthreads();  // the previous tile is done with LDS
+  build_scale<FMT>(B.sem, scale);
+  __syncthreads();
+  double acc = 0.0;
+  auto emit = [&](int r, double sum) {
+    if (epi == kEpiDot) {
+      yout[r] = sum;
+      acc += aux[r] * sum;
+    } else {
+      const double v = aux[r] - sum;
+      yout[r] = v;
+      acc += v * v;
+    }
+  };
+  if (ext <= kNS) {
+    for (int i = tid; i < ext; i += kWG) {
+      int c;
+      vals[i] = load_decode<FMT>(B, j0 + i, scale, c);
+      cols[i] = c;
+    }
+    __syncthreads();
+    for (int r = ra + tid; r < rb; r += kWG) {
+      const int s0 = B.row_ptr[r], s1 = B.row_ptr[r + 1];
+      const int o = s0 - j0, len = s1 - s0;
+      double sum = 0.0;
+      for (int kb = 0; kb < len; kb += 8) {
+        double v[8], xv[8];
+        int c[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          v[k] = vals[o + kb + k];
+          c[k] = (kb + k < len) ? cols[o + kb + k] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) xv[k] = xin[c[k]];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const double pr = __dmul_rn(v[k], xv[k]);
+          sum = (kb + k < len) ? __dadd_rn(sum, pr) : sum;
+        }
+      }
+      emit(r, sum);
+    }
+  } else {
+    for (int r = ra + tid; r < rb; r += kWG) {
+      const int s0 = B.row_ptr[r], s1 = B.row_ptr[r + 1];
+      if (s1 - s0 > kLongRow) continue;
+      double sum = 0.0;
+      for (int j = s0; j < s1; ++j) {
+        int c;
+        const double v = load_decode<FMT>(B, j, scale, c);
+        sum = __dadd_rn(sum, __dmul_rn(v, xin[c]));
+      }
+      emit(r, sum);
+    }
+    for (int r = ra; r < rb; ++r) {  // uniform over the workgroup
+      const int s0 = B.row_ptr[r], s1 = B.row_ptr[r + 1];
+      if (s1 - s0 <= kLongRow) continue;
+      double part = 0.0;
+      for (int j = s0 + tid; j < s1; j += kWG) {
+        int c;
+        const double v = load_decode<FMT>(B, j, scale, c);
+        part = __dadd_rn(part, __dmul_rn(v, xin[c]));
+      }
+      const double sum = block_sum(part, red);
+      if (tid == 0) emit(r, sum);
+    }
+  }
+  return acc;
+}
+
+// mode 0 (iteration): q = A_s p and the partials of p.q, for systems still
+// running.  mode 1 (actions): r = b - A_s x (init / replacement) or
+// w = b - A_3 x (check) and the partials of their squared norms.
+__global__ __launch_bounds__(kWG) void k_b_spmv(BatchView v, int mode) {
+  __shared__ __attribute__((aligned(16))) double vals[kNS + 8];
+  __shared__ __attribute__((aligned(16))) int cols[kNS + 8];
+  __shared__ double scale[16];
+  __shared__ double red[kWaves];
+  const int n = v.list.counts[0];
+  for (Walk w = walk_of(n); w.i < w.end; w.i += w.step) {
+    const WorkItem it = v.list.tiles[w.i];
+    const BatchSlot& B = v.slot[it.slot];
+    const SolverState* S = v.S + it.slot;
+    int f;
+    const double* xin;
+    double* yout;
+    const double* aux;
+    int epi;
+    if (mode == 0) {
+      if (S->stop) continue;
+      f = B.fmt ? S->s : kCsr64;
+      xin = B.p;
+      yout = B.q;
+      aux = B.p;
+      epi = kEpiDot;
+    } else {
+      const int a = v.act[it.slot];
+      if (a == kActCheck) {
+        f = B.fmt ? 3 : kCsr64;
+        yout = B.w;
+      } else if (a == kActInit || a == kActReplace || a == kActReplaceP) {
+        f = B.fmt ? S->s : kCsr64;
+        yout = B.r;
+      } else {
+        continue;
+      }
+      xin = B.x;
+      aux = B.b;
+      epi = kEpiResid;
+    }
+    double acc;
+    switch (f) {
+      case 1: acc = tile_rows<1>(B, it.idx, xin, yout, aux, epi, vals, cols, scale, red); break;
+      case 2: acc = tile_rows<2>(B, it.idx, xin, yout, aux, epi, vals, cols, scale, red); break;
+      case 3: acc = tile_rows<3>(B, it.idx, xin, yout, aux, epi, vals, cols, scale, red); break;
+      default: acc = tile_rows<kCsr64>(B, it.idx, xin, yout, aux, epi, vals, cols, scale, red);
+    }
+    const double bs = block_sum(acc, red);
+    if (threadIdx.x == 0) v.part[it.part] = bs;
+  }
+}
+
+// alpha = rho / p.q per running system (one workgroup per system); always
+// disarms the x/p update of the previous iteration.
+__global__ __launch_bounds__(kWG) void k_b_alpha(BatchView v) {
+  __shared__ double red[kWaves];
+  const int n = v.list.counts[2];
+  for (int k = blockIdx.x; k < n; k += gridDim.x) {
+    const SlotItem si = v.list.slots[k];
+    SolverState* S = v.S + si.slot;
+    const int stop = S->stop;
+    if (threadIdx.x == 0) S->k3_armed = 0;
+    if (stop) continue;
+    const double pq = sum_partials(v.part + si.part, v.slot[si.slot].n_tiles, red);
+    if (threadIdx.x == 0) {
+      S->pq = pq;
+      if (!(pq > 0.0) || !isfinite(pq)) S->stop = kBreak;
+      else S->alpha = S->rho / pq;
+    }
+    __syncthreads();
+  }
+}
+
+// r -= alpha q and the partials of r.r, per row chunk.
+__global__ __launch_bounds__(kWG) void k_b_rupdate(BatchView v) {
+  __shared__ double red[kWaves];
+  const int n = v.list.counts[1];
+  for (Walk w = walk_of(n); w.i < w.end; w.i += w.step) {
+    const WorkItem it = v.list.chunks[w.i];
+    const SolverState* S = v.S + it.slot;
+    if (S->stop) continue;
+    const BatchSlot& B = v.slot[it.slot];
+    const double alpha = S->alpha;
+    const int lo = it.idx * kChunk;
+    const int hi = min(B.n_rows, lo + kChunk);
+    double* __restrict__ r = B.r;
+    const double* __restrict__ q = B.q;
+    double acc = 0.0;
+    for (int i = lo + threadIdx.x; i < hi; i += kWG) {
+      const double rv = r[i] - alpha * q[i];
+      r[i] = rv;
+      acc += rv * rv;
+    }
+    const double bs = block_sum(acc, red);
+    if (threadIdx.x == 0) v.part2[it.part] = bs;
+  }
+}
+
+// rho' = r.r: beta, the history, the controller (one workgroup per system).
+__global__ __launch_bounds__(kWG) void k_b_advance(BatchView v) {
+  __shared__ double red[kWaves];
+  __shared__ int bc_j, bc_s;
+  __shared__ double bc_rel;
+  const int n = v.list.counts[2];
+  for (int k = blockIdx.x; k < n; k += gridDim.x) {
+    const SlotItem si = v.list.slots[k];
+    SolverState* S = v.S + si.slot;
+    if (S->stop) continue;
+    const BatchSlot& B = v.slot[si.slot];
+    const double rho_new = sum_partials(v.part2 + si.vpart, B.n_chunks, red);
+    if (threadIdx.x == 0) {
+      const int j = S->it + 1;
+      const double rel = sqrt(rho_new) / S->nb;
+      S->beta = rho_new / S->rho;
+      S->rho = rho_new;
+      S->it = j;
+      S->relres = rel;
+      B.hist[j] = rel;
+      B.seg_hist[j] = S->s;
+      S->k3_armed = 1;
+      bc_j = j;
+      bc_s = S->s;
+      bc_rel = rel;
+    }
+    __syncthreads();
+    controller(S, B.hist, red, bc_j, bc_rel, bc_s);
+    __syncthreads();
+  }
+}
+
+// x += alpha p; p = r + beta p, per row chunk (systems whose iteration
+// completed).
+__global__ __launch_bounds__(kWG) void k_b_xpupdate(BatchView v) {
+  const int n = v.list.counts[1];
+  for (Walk w = walk_of(n); w.i < w.end; w.i += w.step) {
+    const WorkItem it = v.list.chunks[w.i];
+    const SolverState* S = v.S + it.slot;
+    if (!S->k3_armed) continue;
+    const BatchSlot& B = v.slot[it.slot];
+    const double alpha = S->alpha, beta = S->beta;
+    const int lo = it.idx * kChunk;
+    const int hi = min(B.n_rows, lo + kChunk);
+    double* __restrict__ x = B.x;
+    double* __restrict__ p = B.p;
+    const double* __restrict__ r = B.r;
+    for (int i = lo + threadIdx.x; i < hi; i += kWG) {
+      const double pv = p[i];
+      x[i] += alpha * pv;
+      p[i] = r[i] + beta * pv;
+    }
+  }
+}
+
+// Actions: partials of b.b for systems being initialised.
+__global__ __launch_bounds__(kWG) void k_b_bdot(BatchView v) {
+  __shared__ double red[kWaves];
+  const int n = v.list.counts[1];
+  for (Walk w = walk_of(n); w.i < w.end; w.i += w.step) {
+    const WorkItem it = v.list.chunks[w.i];
+    if (v.act[it.slot] != kActInit) continue;
+    const BatchSlot& B = v.slot[it.slot];
+    const int lo = it.idx * kChunk;
+    const int hi = min(B.n_rows, lo + kChunk);
+    double acc = 0.0;
+    for (int i = lo + threadIdx.x; i < hi; i += kWG) acc += B.b[i] * B.b[i];
+    const double bs = block_sum(acc, red);
+    if (threadIdx.x == 0) v.part2[it.part] = bs;
+  }
+}
+
+// Actions: finish the sums of k_b_bdot / k_b_spmv(mode 1) per system.
+__global__ __launch_bounds__(kWG) void k_b_act_finish(BatchView v) {
+  __shared__ double red[kWaves];
+  const int n = v.list.counts[2];
+  for (int k = blockIdx.x; k < n; k += gridDim.x) {
+    const SlotItem si = v.list.slots[k];
+    const int a = v.act[si.slot];
+    SolverState* S = v.S + si.slot;
+    const BatchSlot& B = v.slot[si.slot];
+    if (a == kActInit) {
+      const double nb2 = sum_partials(v.part2 + si.vpart, B.n_chunks, red);
+      const double rho = sum_partials(v.part + si.part, B.n_tiles, red);
+      if (threadIdx.x == 0) {
+        const double nb = sqrt(nb2);
+        const double rel = nb > 0.0 ? sqrt(rho) / nb : 0.0;
+        S->nb2 = nb2;
+        S->nb = nb;
+        S->rho = rho;
+        S->relres = rel;
+        B.hist[0] = rel;
+        B.seg_hist[0] = S->s;
+      }
+    } else if (a == kActReplace || a == kActReplaceP) {
+      const double rho = sum_partials(v.part + si.part, B.n_tiles, red);
+      if (threadIdx.x == 0) S->rho = rho;
+    } else if (a == kActCheck) {
+      const double ww = sum_partials(v.part + si.part, B.n_tiles, red);
+      if (threadIdx.x == 0) S->scratch[0] = ww;
+    }
+    __syncthreads();
+  }
+}
+
+// Actions: p = r (init, replacement with restart), x = 0 (b = 0).
+__global__ __launch_bounds__(kWG) void k_b_copy(BatchView v) {
+  const int n = v.list.counts[1];
+  for (Walk w = walk_of(n); w.i < w.end; w.i += w.step) {
+    const WorkItem it = v.list.chunks[w.i];
+    const int a = v.act[it.slot];
+    if (a != kActInit && a != kActReplaceP && a != kActZeroX) continue;
+    const BatchSlot& B = v.slot[it.slot];
+    const int lo = it.idx * kChunk;
+    const int hi = min(B.n_rows, lo + kChunk);
+    if (a == kActZeroX) {
+      for (int i = lo + threadIdx.x; i < hi; i += kWG) B.x[i] = 0.0;
+    } else {
+      for (int i = lo + threadIdx.x; i < hi; i += kWG) B.p[i] = B.r[i];
+    }
+  }
+}
+
+size_t align_up(size_t v) { return (v + 255) / 256 * 256; }
+
+constexpr int64_t kMagic = 0x4253454742415443LL;
+
+template <typename K>
+int grid_for(K kernel, int64_t items) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWG, 0) != hipSuccess) return 0;
+  int64_t g = (int64_t)cus * (per_cu > 0 ? per_cu : 1);
+  const int64_t need = (items + 7) / 8 * 8;
+  if (g > need) g = need;
+  g = g / 8 * 8;
+  return g < 8 ? 8 : (int)g;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- engine --
+size_t BatchEngine::region_bytes(int cap_slots, int64_t cap_tiles, int64_t cap_chunks) {
+  size_t b = align_up(sizeof(RegionHeader));
+  for (int l = 0; l < 2; ++l) {
+    b += align_up(4 * sizeof(int32_t));
+    b += align_up((size_t)cap_tiles * sizeof(WorkItem));
+    b += align_up((size_t)cap_chunks * sizeof(WorkItem));
+    b += align_up((size_t)cap_slots * sizeof(SlotItem));
+  }
+  b += align_up((size_t)cap_slots * sizeof(BatchSlot));
+  b += align_up((size_t)cap_slots * sizeof(SolverState));
+  b += align_up((size_t)cap_slots * sizeof(int32_t));
+  b += align_up((size_t)cap_tiles * sizeof(double));
+  b += align_up((size_t)cap_chunks * sizeof(double));
+  return b;
+}
+
+gse_status BatchEngine::init(void* region, size_t bytes, int cap_slots, int64_t cap_tiles,
+                             int64_t cap_chunks, hipStream_t st, bool graphs) {
+  if (cap_slots < 1 || cap_tiles < 1 || cap_chunks < 1 || cap_tiles > INT32_MAX ||
+      cap_chunks > INT32_MAX)
+    return fail(GSE_ERR_ARG, "batch capacities out of range");
+  if (region_bytes(cap_slots, cap_tiles, cap_chunks) > bytes)
+    return fail(GSE_ERR_NOMEM, "batch tables need %zu bytes",
+                region_bytes(cap_slots, cap_tiles, cap_chunks));
+  cap_slots_ = cap_slots;
+  cap_tiles_ = cap_tiles;
+  cap_chunks_ = cap_chunks;
+  st_ = st;
+  graphs_ = graphs;
+  char* p = reinterpret_cast<char*>(region);
+  size_t off = 0;
+  auto take = [&](size_t n) {
+    char* q = p + off;
+    off += align_up(n);
+    return q;
+  };
+  RegionHeader* hdr = reinterpret_cast<RegionHeader*>(take(sizeof(RegionHeader)));
+  for (int l = 0; l < 2; ++l) {
+    counts_[l] = reinterpret_cast<int32_t*>(take(4 * sizeof(int32_t)));
+    tiles_[l] = reinterpret_cast<WorkItem*>(take((size_t)cap_tiles * sizeof(WorkItem)));
+    chunks_[l] = reinterpret_cast<WorkItem*>(take((size_t)cap_chunks * sizeof(WorkItem)));
+    slot_items_[l] = reinterpret_cast<SlotItem*>(take((size_t)cap_slots * sizeof(SlotItem)));
+  }
+  slots_ = reinterpret_cast<BatchSlot*>(take((size_t)cap_slots * sizeof(BatchSlot)));
+  S_ = reinterpret_cast<SolverState*>(take((size_t)cap_slots * sizeof(SolverState)));
+  act_ = reinterpret_cast<int32_t*>(take((size_t)cap_slots * sizeof(int32_t)));
+  part_ = reinterpret_cast<double*>(take((size_t)cap_tiles * sizeof(double)));
+  part2_ = reinterpret_cast<double*>(take((size_t)cap_chunks * sizeof(double)));
+
+  hslot_.assign((size_t)cap_slots, BatchSlot{});
+  hS_.assign((size_t)cap_slots, SolverState{});
+  hact_.assign((size_t)cap_slots, 0);
+  meta_.assign((size_t)cap_slots, SlotHost{});
+  used_.assign((size_t)cap_slots, 0);
+  for (int l = 0; l < 2; ++l) {
+    hcounts_[l][0] = hcounts_[l][1] = hcounts_[l][2] = hcounts_[l][3] = 0;
+  }
+  hhdr_ = RegionHeader{kMagic, cap_slots, 0, (int64_t)((char*)slots_ - p),
+                       (int64_t)((char*)S_ - p)};
+  grid_spmv_ = grid_for(k_b_spmv, cap_tiles);
+  grid_vec_ = grid_for(k_b_rupdate, cap_chunks);
+  grid_slot_ = cap_slots < 1024 ? cap_slots : 1024;
+  if (grid_spmv_ <= 0 || grid_vec_ <= 0) return fail(GSE_ERR_HIP, "batch: device query failed");
+  hipError_t e = hipMemcpyAsync(hdr, &hhdr_, sizeof hhdr_, hipMemcpyHostToDevice, st_);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(counts_[0], hcounts_[0], sizeof hcounts_[0], hipMemcpyHostToDevice, st_);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(counts_[1], hcounts_[1], sizeof hcounts_[1], hipMemcpyHostToDevice, st_);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(act_, hact_.data(), hact_.size() * sizeof(int32_t), hipMemcpyHostToDevice, st_);
+  if (e == hipSuccess) e = hipStreamSynchronize(st_);
+  if (e != hipSuccess) return hip_fail(e, "batch init");
+  return GSE_OK;
+}
+
+BatchEngine::~BatchEngine() {
+  if (graph_) (void)hipGraphExecDestroy(graph_);
+}
+
+int BatchEngine::add(const BatchSlot& d, const gse_params* p, const double* eta) {
+  int id = -1;
+  for (int i = 0; i < cap_slots_; ++i)
+    if (!used_[i]) {
+      id = i;
+      break;
+    }
+  if (id < 0) return fail(GSE_ERR_NOMEM, "no free batch slot");
+  int64_t tiles = d.n_tiles, chunks = d.n_chunks;
+  for (int i = 0; i < cap_slots_; ++i)
+    if (used_[i] && meta_[i].phase != kPhDone) {
+      tiles += hslot_[i].n_tiles;
+      chunks += hslot_[i].n_chunks;
+    }
+  if (tiles > cap_tiles_ || chunks > cap_chunks_)
+    return fail(GSE_ERR_NOMEM, "batch lists full (%lld tiles, %lld chunks)", (long long)tiles,
+                (long long)chunks);
+  hslot_[id] = d;
+  SolverState& S = hS_[id];
+  memset(&S, 0, sizeof S);
+  const bool gse = d.fmt != 0;
+  const bool stepped = gse && p->fixed_segments == 0;
+  S.tol = p->tol;
+  for (int i = 0; i < 3; ++i) S.eta[i] = (gse && eta) ? eta[i] : 0.0;
+  S.floor_c = p->floor_c;
+  S.rsd_limit = p->rsd_limit;
+  S.reldec_limit = p->reldec_limit;
+  S.s = gse ? (stepped ? p->start_segments : p->fixed_segments) : 0;
+  S.max_iter = p->max_iter;
+  S.stepped = stepped ? 1 : 0;
+  S.fixed = gse ? p->fixed_segments : -1;
+  S.l = p->l;
+  S.t = p->t;
+  S.m = p->m;
+  S.ndec_limit = p->ndec_limit;
+  S.ndec_rule = p->ndec_rule;
+  S.hist_cap = p->max_iter + 2;
+  SlotHost& m = meta_[id];
+  m = SlotHost{};
+  m.phase = kPhInit;
+  m.stepped = stepped;
+  m.s_final = gse ? 3 : 0;
+  m.tol = p->tol;
+  m.max_iter = p->max_iter;
+  m.switch_mode = p->switch_mode;
+  m.rep.switch_iter[0] = m.rep.switch_iter[1] = -1;
+  m.t0 = std::chrono::steady_clock::now();
+  used_[id] = 1;
+  hact_[id] = kActNone;
+  ++n_live_;
+  hipError_t e = hipMemcpyAsync(slots_ + id, &hslot_[id], sizeof(BatchSlot), hipMemcpyHostToDevice, st_);
+  if (e == hipSuccess) e = hipStreamSynchronize(st_);
+  if (e != hipSuccess) return hip_fail(e, "batch add");
+  return id;
+}
+
+void BatchEngine::release(int slot) {
+  if (slot < 0 || slot >= cap_slots_ || !used_[slot]) return;
+  if (meta_[slot].phase != kPhDone) {
+    --n_live_;
+    run_dirty_ = true;
+  }
+  used_[slot] = 0;
+  meta_[slot].phase = kPhFree;
+}
+
+gse_status BatchEngine::upload_list(int l, const std::vector<int>& ids) {
+  std::vector<WorkItem>& wt = wt_[l];
+  std::vector<WorkItem>& wc = wc_[l];
+  std::vector<SlotItem>& wsl = ws_[l];
+  wt.clear();
+  wc.clear();
+  wsl.clear();
+  int64_t pt = 0, pc = 0;
+  for (int id : ids) {
+    const BatchSlot& B = hslot_[id];
+    wsl.push_back(SlotItem{id, (int32_t)pt, (int32_t)pc, 0});
+    for (int t = 0; t < B.n_tiles; ++t) wt.push_back(WorkItem{id, t, (int32_t)(pt + t), 0});
+    for (int c = 0; c < B.n_chunks; ++c) wc.push_back(WorkItem{id, c, (int32_t)(pc + c), 0});
+    pt += B.n_tiles;
+    pc += B.n_chunks;
+  }
+  if (pt > cap_tiles_ || pc > cap_chunks_ || (int64_t)ids.size() > cap_slots_)
+    return fail(GSE_ERR_NOMEM, "batch lists overflow");
+  hcounts_[l][0] = (int32_t)wt.size();
+  hcounts_[l][1] = (int32_t)wc.size();
+  hcounts_[l][2] = (int32_t)wsl.size();
+  hcounts_[l][3] = 0;
+  hipError_t e = hipSuccess;
+  if (!wt.empty())
+    e = hipMemcpyAsync(tiles_[l], wt.data(), wt.size() * sizeof(WorkItem), hipMemcpyHostToDevice, st_);
+  if (e == hipSuccess && !wc.empty())
+    e = hipMemcpyAsync(chunks_[l], wc.data(), wc.size() * sizeof(WorkItem), hipMemcpyHostToDevice, st_);
+  if (e == hipSuccess && !wsl.empty())
+    e = hipMemcpyAsync(slot_items_[l], wsl.data(), wsl.size() * sizeof(SlotItem), hipMemcpyHostToDevice,
+                       st_);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(counts_[l], hcounts_[l], sizeof hcounts_[l], hipMemcpyHostToDevice, st_);
+  if (e != hipSuccess) return hip_fail(e, "batch lists");
+  return GSE_OK;
+}
+
+BatchView BatchEngine::view(int l) const {
+  BatchView v{};
+  v.list.counts = counts_[l];
+  v.list.tiles = tiles_[l];
+  v.list.chunks = chunks_[l];
+  v.list.slots = slot_items_[l];
+  v.slot = slots_;
+  v.S = S_;
+  v.act = act_;
+  v.part = part_;
+  v.part2 = part2_;
+  return v;
+}
+
+hipError_t BatchEngine::launch_epoch_kernels(int iters) {
+  const BatchView v = view(0);
+  for (int k = 0; k < iters; ++k) {
+    hipLaunchKernelGGL(k_b_spmv, dim3(grid_spmv_), dim3(kWG), 0, st_, v, 0);
+    hipLaunchKernelGGL(k_b_alpha, dim3(grid_slot_), dim3(kWG), 0, st_, v);
+    hipLaunchKernelGGL(k_b_rupdate, dim3(grid_vec_), dim3(kWG), 0, st_, v);
+    hipLaunchKernelGGL(k_b_advance, dim3(grid_slot_), dim3(kWG), 0, st_, v);
+    hipLaunchKernelGGL(k_b_xpupdate, dim3(grid_vec_), dim3(kWG), 0, st_, v);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t BatchEngine::sync_states_in() {
+  hipError_t e = hipMemcpyAsync(hS_.data(), S_, hS_.size() * sizeof(SolverState),
+                                hipMemcpyDeviceToHost, st_);
+  if (e == hipSuccess) e = hipStreamSynchronize(st_);
+  return e;
+}
+
+hipError_t BatchEngine::sync_states_out() {
+  return hipMemcpyAsync(S_, hS_.data(), hS_.size() * sizeof(SolverState), hipMemcpyHostToDevice, st_);
+}
+
+void BatchEngine::resume(int id) {
+  SolverState& S = hS_[id];
+  S.stop = kRun;
+  S.trig = 0;
+  S.k3_armed = 0;
+  meta_[id].phase = kPhRun;
+  run_dirty_ = true;
+}
+
+gse_status BatchEngine::finish(int id, int status, std::vector<int>* done) {
+  SlotHost& m = meta_[id];
+  const SolverState& S = hS_[id];
+  m.rep.status = status;
+  m.rep.iters = S.it;
+  m.rep.relres_recursive = S.relres;
+  m.rep.iters_per_seg[0] = m.rep.iters_per_seg[1] = m.rep.iters_per_seg[2] = 0;
+  const int cnt = S.it;
+  if (cnt > 0) {
+    seg_buf_.resize((size_t)cnt + 1);
+    hipError_t e = hipMemcpyAsync(seg_buf_.data(), hslot_[id].seg_hist, sizeof(int32_t) * (size_t)(cnt + 1),
+                                  hipMemcpyDeviceToHost, st_);
+    if (e == hipSuccess) e = hipStreamSynchronize(st_);
+    if (e != hipSuccess) return hip_fail(e, "batch report");
+    for (int i = 1; i <= cnt; ++i) {
+      const int sg = seg_buf_[i] <= 0 ? 3 : seg_buf_[i];
+      m.rep.iters_per_seg[sg - 1] += 1;
+    }
+  }
+  m.rep.time_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - m.t0).count();
+  m.phase = kPhDone;
+  --n_live_;
+  run_dirty_ = true;
+  if (done) done->push_back(id);
+  return GSE_OK;
+}
+
+// One round of per-system actions (the host logic of the single-system CG
+// driver, applied to every system that stopped).
+gse_status BatchEngine::actions(std::vector<int>* done) {
+  std::vector<int>& ids = ids_;
+  ids.clear();
+  for (int i = 0; i < cap_slots_; ++i) {
+    if (!used_[i]) continue;
+    int a = kActNone;
+    switch (meta_[i].phase) {
+      case kPhInit: a = kActInit; break;
+      case kPhCheck: a = kActCheck; break;
+      case kPhFinal: a = kActCheck; break;
+      case kPhReplace: a = meta_[i].reset_p ? kActReplaceP : kActReplace; break;
+      case kPhZero: a = kActZeroX; break;
+      default: break;
+    }
+    hact_[i] = a;
+    if (a != kActNone) ids.push_back(i);
+  }
+  if (ids.empty()) return GSE_OK;
+  gse_status s = upload_list(1, ids);
+  if (s != GSE_OK) return s;
+  hipError_t e = hipMemcpyAsync(act_, hact_.data(), hact_.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, st_);
+  if (e == hipSuccess) e = sync_states_out();
+  if (e == hipSuccess) {
+    const BatchView v = view(1);
+    hipLaunchKernelGGL(k_b_bdot, dim3(grid_vec_), dim3(kWG), 0, st_, v);
+    hipLaunchKernelGGL(k_b_spmv, dim3(grid_spmv_), dim3(kWG), 0, st_, v, 1);
+    hipLaunchKernelGGL(k_b_act_finish, dim3(grid_slot_), dim3(kWG), 0, st_, v);
+    hipLaunchKernelGGL(k_b_copy, dim3(grid_vec_), dim3(kWG), 0, st_, v);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = sync_states_in();
+  if (e != hipSuccess) return hip_fail(e, "batch actions");
+  for (int id : ids) {
+    SlotHost& m = meta_[id];
+    SolverState& S = hS_[id];
+    hact_[id] = kActNone;
+    switch (m.phase) {
+      case kPhInit:
+        if (S.nb == 0.0) {
+          m.phase = kPhZero;
+        } else if (S.relres <= m.tol) {
+          m.phase = kPhCheck;
+        } else {
+          resume(id);
+        }
+        break;
+      case kPhZero:
+        m.rep.relres_true = 0.0;
+        S.relres = 0.0;
+        s = finish(id, GSE_OK, done);
+        break;
+      case kPhCheck: {
+        const double rt = sqrt(S.scratch[0]) / S.nb;
+        if (rt <= m.tol) {
+          m.rep.relres_true = rt;
+          s = finish(id, GSE_OK, done);
+        } else {  // the recursive residual drifted from the true one
+          m.phase = kPhReplace;
+          m.reset_p = true;
+          m.origin = kFromCheck;
+        }
+        break;
+      }
+      case kPhFinal:
+        m.rep.relres_true = sqrt(S.scratch[0]) / S.nb;
+        s = finish(id, m.final_status, done);
+        break;
+      case kPhReplace: {
+        S.relres = sqrt(S.rho) / S.nb;
+        if (m.origin == kFromCheck) {
+          if (S.relres <= m.tol || S.it >= m.max_iter) {
+            m.final_status = GSE_NOT_CONVERGED;
+            m.phase = kPhFinal;
+          } else {
+            resume(id);
+          }
+        } else {
+          if (S.it >= m.max_iter) {
+            m.final_status = GSE_NOT_CONVERGED;
+            m.phase = kPhFinal;
+          } else if (S.relres <= m.tol) {
+            m.phase = kPhCheck;
+          } else {
+            resume(id);
+          }
+        }
+        break;
+      }
+      default: break;
+    }
+    if (s != GSE_OK) return s;
+  }
+  return GSE_OK;
+}
+
+// One epoch of iterations for every running system, then the stops.
+gse_status BatchEngine::epoch() {
+  std::vector<int>& ids = ids_;
+  ids.clear();
+  for (int i = 0; i < cap_slots_; ++i)
+    if (used_[i] && meta_[i].phase == kPhRun) ids.push_back(i);
+  if (ids.empty()) return GSE_OK;
+  gse_status s = GSE_OK;
+  if (run_dirty_) {
+    s = upload_list(0, ids);
+    if (s != GSE_OK) return s;
+    run_dirty_ = false;
+  }
+  hipError_t e = sync_states_out();
+  if (e == hipSuccess) {
+    if (graphs_) {
+      if (!graph_) e = capture(st_, &graph_, [&] { return launch_epoch_kernels(kEpochIters); });
+      if (e == hipSuccess) e = hipGraphLaunch(graph_, st_);
+    } else {
+      e = launch_epoch_kernels(kEpochIters);
+    }
+  }
+  if (e == hipSuccess) e = sync_states_in();
+  if (e != hipSuccess) return hip_fail(e, "batch epoch");
+  for (int id : ids) {
+    SlotHost& m = meta_[id];
+    SolverState& S = hS_[id];
+    if (S.stop == kRun) continue;
+    int reason = S.stop, trig = S.trig;
+    run_dirty_ = true;
+    if (reason == kBreak) {
+      if (m.stepped && S.s < 3) {
+        reason = kSwitch;
+        trig = GSE_TRIG_BREAKDOWN;
+      } else {
+        m.final_status = GSE_ERR_BREAKDOWN;
+        m.phase = kPhFinal;
+        continue;
+      }
+    }
+    if (reason == kConv) {
+      m.phase = kPhCheck;
+    } else if (reason == kSwitch) {
+      if (m.nsw < 2) {
+        m.rep.switch_iter[m.nsw] = S.it;
+        m.rep.switch_trigger[m.nsw] = trig;
+      }
+      ++m.nsw;
+      S.s += 1;
+      m.phase = kPhReplace;
+      m.reset_p = m.switch_mode == 0;
+      m.origin = kFromSwitch;
+    } else {  // cap
+      m.final_status = GSE_NOT_CONVERGED;
+      m.phase = kPhFinal;
+    }
+  }
+  return GSE_OK;
+}
+
+gse_status BatchEngine::step(std::vector<int>* done) {
+  bool pending = false, running = false;
+  for (int i = 0; i < cap_slots_; ++i) {
+    if (!used_[i]) continue;
+    const int ph = meta_[i].phase;
+    if (ph == kPhRun) running = true;
+    else if (ph != kPhDone && ph != kPhFree) pending = true;
+  }
+  if (pending) return actions(done);
+  if (running) return epoch();
+  return GSE_OK;
+}
+
+// --------------------------------------------------------- gse_batch_cg --
+namespace {
+
+struct BatchLayout {
+  size_t engine = 0;  // region at offset 0
+  std::vector<size_t> vec_off;  // per system: r, p, q, w, hist, seg
+  size_t bytes = 0;
+  int64_t tiles = 0, chunks = 0;
+};
+
+BatchLayout batch_layout(int32_t n_sys, const BatchSystemDesc* d, int32_t max_iter) {
+  BatchLayout L;
+  for (int i = 0; i < n_sys; ++i) {
+    L.tiles += d[i].n_tiles;
+    L.chunks += (d[i].n_rows + kChunk - 1) / kChunk;
+  }
+  L.engine = BatchEngine::region_bytes(n_sys, L.tiles, L.chunks);
+  size_t off = L.engine;
+  for (int i = 0; i < n_sys; ++i) {
+    L.vec_off.push_back(off);
+    const size_t n = (size_t)d[i].n_rows;
+    off += 4 * align_up(n * sizeof(double));
+    off += align_up((size_t)(max_iter + 2) * sizeof(double));
+    off += align_up((size_t)(max_iter + 2) * sizeof(int32_t));
+  }
+  L.bytes = off;
+  return L;
+}
+
+}  // namespace
+
+size_t batch_workspace_bytes(int32_t n_sys, const BatchSystemDesc* d, int32_t max_iter) {
+  return batch_layout(n_sys, d, max_iter).bytes;
+}
+
+gse_status batch_cg(int32_t n_sys, const BatchSystemDesc* d, const gse_params* p, gse_report* rep,
+                    void* ws, size_t ws_bytes, hipStream_t caller) {
+  const BatchLayout L = batch_layout(n_sys, d, p->max_iter);
+  if (L.bytes > ws_bytes) return fail(GSE_ERR_NOMEM, "batch workspace needs %zu bytes", L.bytes);
+  SolveStream ss(caller);
+  if (ss.err != hipSuccess) return hip_fail(ss.err, "batch stream");
+  BatchEngine eng;
+  gse_status s = eng.init(ws, L.engine, n_sys, L.tiles, L.chunks, ss.s, p->launch_mode == 0);
+  if (s != GSE_OK) return s;
+  char* base = reinterpret_cast<char*>(ws);
+  for (int i = 0; i < n_sys; ++i) {
+    BatchSlot B = d[i].slot;
+    const size_t n = (size_t)B.n_rows;
+    char* q = base + L.vec_off[i];
+    auto take = [&](size_t nbytes) {
+      char* r = q;
+      q += align_up(nbytes);
+      return r;
+    };
+    B.r = reinterpret_cast<double*>(take(n * sizeof(double)));
+    B.p = reinterpret_cast<double*>(take(n * sizeof(double)));
+    B.q = reinterpret_cast<double*>(take(n * sizeof(double)));
+    B.w = reinterpret_cast<double*>(take(n * sizeof(double)));
+    B.hist = reinterpret_cast<double*>(take((size_t)(p->max_iter + 2) * sizeof(double)));
+    B.seg_hist = reinterpret_cast<int32_t*>(take((size_t)(p->max_iter + 2) * sizeof(int32_t)));
+    B.n_chunks = (B.n_rows + kChunk - 1) / kChunk;
+    const int id = eng.add(B, p, d[i].eta);
+    if (id < 0) return id;
+    if (id != i) return fail(GSE_ERR_ARG, "batch slot order");
+  }
+  while (!eng.idle()) {
+    s = eng.step(nullptr);
+    if (s != GSE_OK) return s;
+  }
+  gse_status worst = GSE_OK;
+  for (int i = 0; i < n_sys; ++i) {
+    rep[i] = eng.report(i);
+    if (rep[i].status != GSE_OK && worst == GSE_OK) worst = rep[i].status;
+  }
+  return worst == GSE_OK ? GSE_OK : (worst == GSE_NOT_CONVERGED ? GSE_NOT_CONVERGED : worst);
+}
+
+gse_status batch_history(const void* ws, int32_t index, int32_t cap, double* hist, int32_t* seg,
+                         hipStream_t st) {
+  RegionHeader h;
+  hipError_t e = hipMemcpyAsync(&h, ws, sizeof h, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "gse_batch_history");
+  if (h.magic != kMagic) return fail(GSE_ERR_ARG, "no batch solve recorded in this workspace");
+  if (index < 0 || index >= h.n_slots) return fail(GSE_ERR_ARG, "system index out of range");
+  const char* base = reinterpret_cast<const char*>(ws);
+  BatchSlot B;
+  SolverState S;
+  e = hipMemcpyAsync(&B, base + h.slots_off + (int64_t)index * (int64_t)sizeof(BatchSlot), sizeof B,
+                     hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&S, base + h.states_off + (int64_t)index * (int64_t)sizeof(SolverState),
+                       sizeof S, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "gse_batch_history");
+  int cnt = S.it + 1;
+  if (cnt > S.hist_cap) cnt = S.hist_cap;
+  if (cnt > cap) cnt = cap;
+  e = hipMemcpyAsync(hist, B.hist, sizeof(double) * (size_t)cnt, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(seg, B.seg_hist, sizeof(int32_t) * (size_t)cnt, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "gse_batch_history");
+  return GSE_OK;
+}
+
+}  // namespace gse

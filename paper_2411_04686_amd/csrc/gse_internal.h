@@ -12,7 +12,7 @@ namespace gse {
 constexpr int kWG = 256;            // threads per workgroup (4 wave64)
 constexpr int kWaves = kWG / 64;
 constexpr int kMinTile = 1024;      // smallest tile_nnz the schedule may use
-constexpr int kDefaultTile = 2048;
+constexpr int kDefaultTile = 1024;
 constexpr int kExtra = 256;         // look-ahead elements staged for a crossing row
 constexpr int kPadTo = 16;          // planes hold nnz rounded up to this
 constexpr int kShortRow = 24;       // rows up to this length: one thread, serial sum
@@ -88,6 +88,7 @@ struct SpmvOperand {
   int32_t tile_nnz;
   int32_t nnz;
   int32_t rv_lanes;          // > 0: row-vector schedule with this many lanes per row
+  int32_t max_row;           // longest row (<= kShortRow selects the short-row tiles)
   int16_t sem[GSE_MAX_EXP];
 };
 
@@ -123,6 +124,11 @@ hipError_t launch_encode(const int32_t* row_ptr, const int32_t* col, const doubl
                          gse_matrix* A, EncodeScratch* sc, hipStream_t st);
 
 int32_t n_tiles_for(int64_t nnz, int32_t tile_nnz);
+
+// autotune.hip: time the schedules, plan the fastest (tile_row rewritten)
+gse_status autotune(int fmt, int segs, SpmvOperand op, const int32_t* row_ptr, int32_t* tile_row,
+                    int32_t tile_cap, int32_t max_row, const double* x, double* y, int32_t reps,
+                    hipStream_t st, int32_t* out_tile, int32_t* out_rv, int32_t* out_tiles);
 
 // solvers.hip
 size_t solver_workspace_bytes(int32_t method, int32_t n_rows, int64_t nnz, int32_t restart,

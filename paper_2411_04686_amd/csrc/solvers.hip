@@ -3,19 +3,21 @@
 // Only the operator reads reduced segments; dot products, residuals and the
 // x / r / p updates are FP64 (Section IV-D.3).  The iteration runs on the
 // device: scalars (rho, alpha, beta, the residual history, the segment
-// count) live in a state record in the workspace, reductions finish in the
-// last workgroup of the kernel that produced them (fixed order, so results
-// are reproducible), and the stepped controller of Section III-D
-// (Algorithm 3, Eqs. 3-6, Conditions 1-3) runs in that workgroup too.  The
-// host launches chunks of iterations and reads the state back between
-// chunks; a stop (switch, convergence candidate, breakdown, cap) makes the
-// rest of the chunk a no-op.
+// count) live in a state record in the workspace.  Kernels that reduce
+// write one partial per workgroup; a one-workgroup kernel launched after
+// them sums the partials in a fixed order (so results are reproducible) and
+// runs the scalar logic, including the stepped controller of Section III-D
+// (Algorithm 3, Eqs. 3-6, Conditions 1-3).  The host replays chunks of
+// iterations from HIP graphs and reads the state back between chunks; a stop
+// (switch, convergence candidate, breakdown, cap) makes the rest of the
+// chunk a no-op.
 #include <math.h>
 #include <string.h>
 
 #include <chrono>
 
 #include "gse_internal.h"
+#include "solver_state.h"
 
 namespace gse {
 
@@ -24,99 +26,7 @@ gse_status hip_fail(hipError_t e, const char* where);
 
 namespace {
 
-enum Stop : int { kRun = 0, kConv = 1, kSwitch = 2, kBreak = 3, kCap = 4 };
-
-// Device-resident solver state.
-struct SolverState {
-  double rho;        // r.r
-  double pq;         // p.q (CG) or scratch dot
-  double alpha, beta;
-  double nb;         // ||b||
-  double nb2;        // b.b
-  double relres;     // current recursive residual / ||b||
-  double tol;
-  double eta[3];
-  double floor_c;
-  double rsd_limit, reldec_limit;
-  double scratch[4];
-  int it;            // completed iterations
-  int s;             // segment count in use (0: FP64 CSR)
-  int stop;          // Stop
-  int trig;          // trigger of a switch
-  int k3_armed;      // CG: the x/p update of the last completed iteration is pending
-  int max_iter;
-  int stepped;
-  int fixed;
-  int l, t, m, ndec_limit, ndec_rule;
-  int pad0;
-  long long hist_off;  // byte offsets of the residual / segment histories
-  long long seg_off;   // in the workspace (read by gse_solve_history)
-  int hist_cap;
-  int pad1;
-};
-
 constexpr int kVecBlocks = 2048;
-
-// ------------------------------------------------------------ controller --
-// Conditions 1-3 at j = l + q*m once t residuals exist (Section III-D).
-// RSD (Eq. 3): population standard deviation over resid[j-t..j-1] divided
-// by their mean; nDec (Eqs. 4-5): decreases resid[i] > resid[i+1] for
-// i = j-t..j-1; relDec (Eq. 6): (resid[j-t] - resid[j-1]) / resid[j-t].
-// Called by every thread of one workgroup; returns the trigger (1..3) or 0.
-__device__ int grid_conditions(const SolverState* S, const double* hist, int j, double* red) {
-  const int t = S->t;
-  double sum = 0.0;
-  for (int i = threadIdx.x; i < t; i += kWG) sum += hist[j - t + i];
-  const double avg = block_sum(sum, red) / (double)t;
-  double var = 0.0, dec = 0.0;
-  for (int i = threadIdx.x; i < t; i += kWG) {
-    const double d = hist[j - t + i] - avg;
-    var += d * d;
-    dec += (hist[j - t + i] > hist[j - t + i + 1]) ? 1.0 : 0.0;
-  }
-  var = block_sum(var, red) / (double)t;
-  const int ndec = (int)block_sum(dec, red);
-  const double rsd = sqrt(var) / avg;
-  const double reldec = (hist[j - t] - hist[j - 1]) / hist[j - t];
-  bool below;
-  if (S->ndec_rule == 1) below = 2 * ndec < t;
-  else below = ndec < S->ndec_limit;
-  if (rsd > S->rsd_limit && below) return GSE_TRIG_C1;
-  if (!below && reldec < S->reldec_limit) return GSE_TRIG_C2;
-  if (ndec == 0) return GSE_TRIG_C3;
-  return GSE_TRIG_NONE;
-}
-
-// After iteration j recorded relres (values broadcast through LDS by the
-// caller): convergence, the floor and tolerance triggers, Conditions 1-3 on
-// the check grid, the cap.  Every thread of the workgroup calls it.
-__device__ void controller(SolverState* S, const double* hist, double* red, int j, double relres,
-                           int s) {
-  const bool exact_op = S->fixed != 0 || s >= 3 || S->eta[s - 1] == 0.0;
-  const bool on_grid = S->stepped && s < 3 && relres > S->tol && j >= S->l && j >= S->t &&
-                       S->m > 0 && ((j - S->l) % S->m) == 0;
-  int cond = GSE_TRIG_NONE;
-  if (on_grid) cond = grid_conditions(S, hist, j, red);  // uniform branch
-  if (threadIdx.x == 0) {
-    int stop = kRun, trig = GSE_TRIG_NONE;
-    if (relres <= S->tol) {
-      if (exact_op) stop = kConv;
-      else { stop = kSwitch; trig = GSE_TRIG_TOL; }
-    } else if (S->stepped && s < 3) {
-      const double eta = S->eta[s - 1];
-      if (S->floor_c > 0.0 && eta > 0.0 && relres <= S->floor_c * eta) {
-        stop = kSwitch;
-        trig = GSE_TRIG_FLOOR;
-      } else if (cond != GSE_TRIG_NONE) {
-        stop = kSwitch;
-        trig = cond;
-      }
-    }
-    if (stop == kRun && j >= S->max_iter) stop = kCap;
-    S->stop = stop;
-    S->trig = trig;
-  }
-}
 
 // ------------------------------------------------------------- finisher ---
 // out[k] = sum over i < n of partials[k*stride + i], k < nk, in a fixed order
@@ -312,6 +222,15 @@ int vec_blocks(int n) {
   return b > kVecBlocks ? kVecBlocks : b;
 }
 
+// Instantiated graphs of one solve, one per segment count.
+struct GraphCache {
+  hipGraphExec_t g[4] = {nullptr, nullptr, nullptr, nullptr};
+  ~GraphCache() {
+    for (auto& x : g)
+      if (x) (void)hipGraphExecDestroy(x);
+  }
+};
+
 struct Operator {
   int fmt;  // 1..3 GSE (stepped), 0 FP64 CSR
   SpmvOperand op;
@@ -371,8 +290,12 @@ void init_state(SolverState* S, const gse_params* p, const Operator& A, int s0) 
 
 // ------------------------------------------------------------------- CG ---
 gse_status run_cg(const Operator& A, const double* b, double* x, const gse_params* p,
-                  gse_report* rep, void* ws, size_t ws_bytes, hipStream_t st) {
+                  gse_report* rep, void* ws, size_t ws_bytes, hipStream_t caller) {
   auto t0 = std::chrono::steady_clock::now();
+  SolveStream ss(caller);
+  if (ss.err != hipSuccess) return hip_fail(ss.err, "cg stream");
+  hipStream_t st = ss.s;
+  GraphCache graphs;
   const int n = A.op.n_rows;
   Workspace w = carve(ws, GSE_CG, n, A.op.nnz, p->restart, p->max_iter);
   if (w.bytes > ws_bytes) return fail(GSE_ERR_NOMEM, "solver workspace needs %zu bytes", w.bytes);
@@ -433,6 +356,24 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
   if (e == hipSuccess) e = write_state(w, &h, st);
   if (e != hipSuccess) return hip_fail(e, "cg setup");
 
+  // K iterations: q = A_s p (partials of p.q) ; alpha ; r -= alpha q
+  // (partials of r.r) ; beta, history, controller ; x += alpha p, p = r + beta p
+  auto launch_iters = [&](int K, int s_use) -> hipError_t {
+    for (int k = 0; k < K; ++k) {
+      int g1 = 0;
+      hipError_t err = apply(A, s_use, w.p, w.q, kEpiDot, w.p, nullptr, w, &w.S->stop, st, &g1);
+      if (err != hipSuccess) return err;
+      hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(kWG), 0, st, w.S, w.partials, g1);
+      hipLaunchKernelGGL(k_cg_rupdate, dim3(vb), dim3(kWG), 0, st, w.S, w.r, w.q, n, w.partials2);
+      hipLaunchKernelGGL(k_cg_advance, dim3(1), dim3(kWG), 0, st, w.S, w.partials2, vb, w.hist,
+                         w.seg_hist);
+      hipLaunchKernelGGL(k_cg_xpupdate, dim3(vb), dim3(kWG), 0, st, w.S, x, w.p, w.r, n);
+      err = hipGetLastError();
+      if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+  };
+  constexpr int kGraphIters = 16;
   int chunk = 4;
   bool done = false;
   bool pending_check = h.relres <= p->tol;  // converged at x0 already
@@ -440,21 +381,18 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
     if (pending_check) {
       h.stop = kConv;
     } else {
-      for (int k = 0; k < chunk; ++k) {
-        int g1 = 0;
-        e = apply(A, h.s, w.p, w.q, kEpiDot, w.p, nullptr, w, &w.S->stop, st, &g1);
-        if (e != hipSuccess) break;
-        hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(kWG), 0, st, w.S, w.partials, g1);
-        hipLaunchKernelGGL(k_cg_rupdate, dim3(vb), dim3(kWG), 0, st, w.S, w.r, w.q, n, w.partials2);
-        hipLaunchKernelGGL(k_cg_advance, dim3(1), dim3(kWG), 0, st, w.S, w.partials2, vb, w.hist,
-                           w.seg_hist);
-        hipLaunchKernelGGL(k_cg_xpupdate, dim3(vb), dim3(kWG), 0, st, w.S, x, w.p, w.r, n);
-        e = hipGetLastError();
-        if (e != hipSuccess) break;
+      if (p->launch_mode == 1 || chunk < kGraphIters) {
+        e = launch_iters(chunk, h.s);
+        chunk = chunk < 64 ? chunk * 2 : 64;
+      } else {
+        hipGraphExec_t& ge = graphs.g[h.s & 3];
+        const int s_use = h.s;
+        e = hipSuccess;
+        if (!ge) e = capture(st, &ge, [&] { return launch_iters(kGraphIters, s_use); });
+        if (e == hipSuccess) e = hipGraphLaunch(ge, st);
       }
       if (e == hipSuccess) e = read_state(w, &h, st);
       if (e != hipSuccess) return hip_fail(e, "cg iterations");
-      chunk = chunk < 64 ? chunk * 2 : 64;
       if (h.stop == kRun) continue;
     }
     pending_check = false;
@@ -547,11 +485,11 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
 // basis vectors of n entries; small arrays: H (m+1) x m row-major, cs, sn,
 // g (m+1 each), h2 scratch.  Per step j (device, gated on stop):
 //   w = A_s v_j                       (SpMV into v_{j+1})
-//   h = V^T w                         (k_gm_dots, pass 1)
-//   w -= V h ; h2 = V^T w             (k_gm_axpy_dots, pass 2)
-//   w -= V h2 ; ||w||, H[:,j] = h+h2  (k_gm_axpy_norm, pass 3; the last
-//                                      workgroup applies the Givens
-//                                      rotations and runs the controller)
+//   h = V^T w                         (k_gm_dots + k_finish)
+//   w -= V h ; h2 = V^T w             (k_gm_axpy<.., false> + k_finish)
+//   w -= V h2 ; partials of ||w||^2   (k_gm_axpy<.., true>)
+//   H[:,j] = h + h2, ||w||, Givens    (k_gm_givens, one workgroup, which
+//                                      also runs the controller)
 //   v_{j+1} = w / ||w||               (k_gm_scale)
 constexpr int kGmBlocks = 1024;
 
@@ -724,8 +662,12 @@ __global__ __launch_bounds__(kWG) void k_gm_start(SolverState* S, GmSmall sm, in
 }
 
 gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_params* p,
-                     gse_report* rep, void* ws, size_t ws_bytes, hipStream_t st) {
+                     gse_report* rep, void* ws, size_t ws_bytes, hipStream_t caller) {
   auto t0 = std::chrono::steady_clock::now();
+  SolveStream ss(caller);
+  if (ss.err != hipSuccess) return hip_fail(ss.err, "gmres stream");
+  hipStream_t st = ss.s;
+  GraphCache graphs;
   const int n = A.op.n_rows;
   const int m = p->restart;
   if (m > 60) return fail(GSE_ERR_ARG, "restart must be <= 60");
@@ -814,14 +756,17 @@ gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_pa
     h.trig = 0;
     e = write_state(w, &h, st);
     if (e != hipSuccess) return hip_fail(e, "gmres state");
-    hipLaunchKernelGGL(k_gm_start, dim3(vb), dim3(kWG), 0, st, w.S, sm, m, V, n);
-    for (int j = 0; j < m && e == hipSuccess; ++j) {
-      double* vj = V + (size_t)j * ld;
-      double* wv = V + (size_t)(j + 1) * ld;
-      e = apply(A, h.s, vj, wv, kEpiPlain, nullptr, nullptr, w, &w.S->stop, st);
-      if (e != hipSuccess) break;
-      const int* gate = &w.S->stop;
-      double* P = w.partials;
+    // one cycle: v_0 = r/beta, m Arnoldi steps (gated: a stop ends the cycle),
+    // x += V y
+    auto launch_cycle = [&](int s_use) -> hipError_t {
+      hipLaunchKernelGGL(k_gm_start, dim3(vb), dim3(kWG), 0, st, w.S, sm, m, V, n);
+      for (int j = 0; j < m; ++j) {
+        double* vj = V + (size_t)j * ld;
+        double* wv = V + (size_t)(j + 1) * ld;
+        hipError_t err = apply(A, s_use, vj, wv, kEpiPlain, nullptr, nullptr, w, &w.S->stop, st);
+        if (err != hipSuccess) return err;
+        const int* gate = &w.S->stop;
+        double* P = w.partials;
 #define GSE_GM_PASSES(JB)                                                                       \
   hipLaunchKernelGGL((k_gm_dots<JB>), dim3(gb), dim3(kWG), 0, st, w.S, V, wv, n, ld, j, P);      \
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(kWG), 0, st, P, gb, gb, j + 1, h1, gate);           \
@@ -830,23 +775,35 @@ gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_pa
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(kWG), 0, st, P, gb, gb, j + 1, sm.h2, gate);        \
   hipLaunchKernelGGL((k_gm_axpy<JB, true>), dim3(gb), dim3(kWG), 0, st, w.S, V, wv, n, ld, j,     \
                      sm.h2, P)
-      if (j < 8) {
-        GSE_GM_PASSES(8);
-      } else if (j < 16) {
-        GSE_GM_PASSES(16);
-      } else if (j < 32) {
-        GSE_GM_PASSES(32);
-      } else {
-        GSE_GM_PASSES(64);
-      }
+        if (j < 8) {
+          GSE_GM_PASSES(8);
+        } else if (j < 16) {
+          GSE_GM_PASSES(16);
+        } else if (j < 32) {
+          GSE_GM_PASSES(32);
+        } else {
+          GSE_GM_PASSES(64);
+        }
 #undef GSE_GM_PASSES
-      hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(kWG), 0, st, w.S, sm, m, j, h1, sm.h2, P, gb,
-                         w.hist, w.seg_hist);
-      hipLaunchKernelGGL(k_gm_scale, dim3(vb), dim3(kWG), 0, st, w.S, wv, n);
-      e = hipGetLastError();
+        hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(kWG), 0, st, w.S, sm, m, j, h1, sm.h2, P, gb,
+                           w.hist, w.seg_hist);
+        hipLaunchKernelGGL(k_gm_scale, dim3(vb), dim3(kWG), 0, st, w.S, wv, n);
+        err = hipGetLastError();
+        if (err != hipSuccess) return err;
+      }
+      hipLaunchKernelGGL(k_gm_update, dim3(vb), dim3(kWG), 0, st, w.S, sm, m, V, ld, x, n);
+      return hipGetLastError();
+    };
+    if (p->launch_mode == 1) {
+      e = launch_cycle(h.s);
+    } else {
+      hipGraphExec_t& ge = graphs.g[h.s & 3];
+      const int s_use = h.s;
+      e = hipSuccess;
+      if (!ge) e = capture(st, &ge, [&] { return launch_cycle(s_use); });
+      if (e == hipSuccess) e = hipGraphLaunch(ge, st);
     }
     if (e != hipSuccess) return hip_fail(e, "gmres cycle");
-    hipLaunchKernelGGL(k_gm_update, dim3(vb), dim3(kWG), 0, st, w.S, sm, m, V, ld, x, n);
     e = hipGetLastError();
     if (e == hipSuccess) e = read_state(w, &t, st);
     if (e != hipSuccess) return hip_fail(e, "gmres update");

@@ -26,6 +26,7 @@
 //     whole workgroup, reading the rest from memory.
 // Every sum has a fixed order, so results are bit-reproducible and identical
 // whether a matrix runs alone or next to others.
+#include "decode.h"
 #include "gse_internal.h"
 
 #ifndef GSE_NT_LOADS
@@ -83,49 +84,6 @@ __device__ __forceinline__ uint32_t u16_of(const Words<N>& w, int k) {
   return (w.w[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu;
 }
 
-// Signed scale table for s segments: entry (slot | sign << 3) holds
-// +-2^(SEM[slot] - 1023 - W_s).  Built as IEEE bits: biased exponent
-// SEM - W_s, zero fraction (SEM >= 64 keeps it normal).
-template <int FMT>
-__device__ __forceinline__ void build_scale(const SpmvOperand& A, double* scale) {
-  if constexpr (FMT != kCsr64) {
-    constexpr int W = (FMT == 1) ? 15 : (FMT == 2) ? 31 : 63;
-    const int i = threadIdx.x;
-    if (i < 16) {
-      const int S = A.sem[i & 7];
-      uint64_t u = 0;
-      if (S > W) u = (uint64_t)(S - W) << 52;
-      u |= (uint64_t)(i >> 3) << 63;
-      scale[i] = bits_to_double(u);
-    }
-  }
-}
-
-// Decode one non-zero: returns the FP64 value and its column.
-template <int FMT>
-__device__ __forceinline__ double decode(uint32_t c, uint32_t h, uint32_t t1, uint32_t t2, double v,
-                                         const double* scale, int& column) {
-  if constexpr (FMT == kCsr64) {
-    column = (int)c;
-    return v;
-  } else {
-    column = (int)(c & 0x1FFFFFFFu);
-    const int ti = (int)(c >> 29) | (int)((h >> 12) & 8u);
-    const double sc = scale[ti];
-    if constexpr (FMT == 1) {
-      return (double)(h & 0x7FFFu) * sc;
-    } else if constexpr (FMT == 2) {
-      return (double)(((h & 0x7FFFu) << 16) | t1) * sc;
-    } else {
-      // F = hi * 2^32 + lo with hi = 31 bits, lo = 32 bits; F has at most 53
-      // significant bits, so the fused sum below is exact.
-      const double sc_hi = bits_to_double(double_to_bits(sc) + (uint64_t(32) << 52));
-      const double hi = (double)(((h & 0x7FFFu) << 16) | t1);
-      return __builtin_fma(hi, sc_hi, (double)t2 * sc);
-    }
-  }
-}
-
 // Raw plane data of E consecutive non-zeros [base, base+E), base % E == 0.
 template <int FMT, int E>
 struct Group {
@@ -151,6 +109,29 @@ struct Group {
         vv[2 * i + 1] = d.y;
       }
     }
+  }
+
+  // Decoded values and columns of all E non-zeros into LDS slots off..off+E-1
+  // (16-byte stores; no range test: slots outside the staged range are
+  // never read).
+  __device__ __forceinline__ void stage_all(const double* scale, int off, double* vals,
+                                            int* cols) const {
+    double d[E];
+    int column[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const uint32_t h = (FMT != kCsr64) ? u16_of(hw, k) : 0u;
+      const uint32_t t1 = (FMT >= 2) ? u16_of(t1w, k) : 0u;
+      const uint32_t t2 = (FMT >= 3) ? t2w.w[k] : 0u;
+      d[k] = decode<FMT>(cw.w[k], h, t1, t2, (FMT == kCsr64) ? vv[k] : 0.0, scale, column[k]);
+    }
+    double2* v2 = reinterpret_cast<double2*>(vals + off);
+#pragma unroll
+    for (int k = 0; k < E / 2; ++k) v2[k] = make_double2(d[2 * k], d[2 * k + 1]);
+    int4* c4 = reinterpret_cast<int4*>(cols + off);
+#pragma unroll
+    for (int k = 0; k < E / 4; ++k)
+      c4[k] = make_int4(column[4 * k], column[4 * k + 1], column[4 * k + 2], column[4 * k + 3]);
   }
 
   // Decoded values and columns of the non-zeros in [lo, hi) into the LDS
@@ -264,7 +245,7 @@ __global__ __launch_bounds__(kWG) void k_spmv(SpmvOperand A, const double* __res
   if (ep.gate && *ep.gate) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  build_scale<FMT>(A, scale);
+  build_scale<FMT>(A.sem, scale);
   double acc = 0.0;  // this thread's share of the epilogue dot
 
   auto finish_row = [&](int r, double sum) {
@@ -455,9 +436,135 @@ __global__ __launch_bounds__(kWG) void k_spmv(SpmvOperand A, const double* __res
   }
 }
 
+// Short-row tile schedule, for matrices whose rows all have at most
+// kShortRow non-zeros (stencils): a row running over the tile end needs at
+// most kShortRow-1 look-ahead non-zeros, which are loaded with the tile, so
+// there are no deferred rows and no long tails.  Per element: one decode in
+// phase 1 (16-byte loads, unpredicated, 16-byte LDS stores) and, in phase 2,
+// two LDS reads, one gather (neighbouring lanes on neighbouring rows, eight
+// gathers in flight per lane) and a multiply-add in row order.  Two barriers
+// per tile; the same persistent one-tile software pipeline as k_spmv.
+constexpr int kLook = 32;  // look-ahead non-zeros (>= kShortRow - 1)
+
+template <int FMT, int E>
+__global__ __launch_bounds__(kWG) void k_spmv_short(SpmvOperand A, const double* __restrict__ x,
+                                                    double* __restrict__ y, SpmvEpilogue ep) {
+  constexpr int T = kWG * E;
+  constexpr int NS = T + kLook + 8;
+  constexpr int LOOK_LANES = kLook / E;
+  constexpr int NPF = 2;
+  static_assert(kLook >= kShortRow, "look-ahead must cover the longest row");
+  __shared__ __attribute__((aligned(16))) double vals[NS];
+  __shared__ __attribute__((aligned(16))) int cols[NS];
+  __shared__ double scale[16];
+  __shared__ int rps[NPF * kWG + 1];
+  __shared__ double red[kWaves];
+
+  if (ep.gate && *ep.gate) return;
+  const int tid = threadIdx.x;
+  build_scale<FMT>(A.sem, scale);
+  double acc = 0.0;
+
+  TileWalk walk(A.n_tiles);
+  Group<FMT, E> g_cur, g_nxt, l_cur, l_nxt;
+  int rpv_cur[NPF], rpv_nxt[NPF];
+  TileInfo cur{}, nxt{};
+
+  auto issue_planes = [&](int t, TileInfo& ti, Group<FMT, E>& g, Group<FMT, E>& l) {
+    ti.t = t;
+    ti.j0 = t * T;
+    ti.j1 = min(ti.j0 + T, A.nnz);
+    const int base = ti.j0 + tid * E;
+    if (base < A.nnz) g.load(A, base);
+    const int lb = ti.j1 + tid * E;
+    if (tid < LOOK_LANES && lb < A.nnz) l.load(A, lb);
+    ti.ra = A.tile_row[t];
+    ti.rb = A.tile_row[t + 1];
+  };
+  auto issue_rows = [&](const TileInfo& ti, int* rpv) {
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) {
+      const int i = k * kWG + tid;
+      rpv[k] = (i <= ti.rb - ti.ra) ? A.row_ptr[ti.ra + i] : 0;
+    }
+  };
+
+  bool have = walk.t < walk.end;
+  if (have) {
+    issue_planes(walk.t, cur, g_cur, l_cur);
+    issue_rows(cur, rpv_cur);
+  }
+  while (have) {
+    const int tn = walk.t + walk.step;
+    const bool have_n = tn < walk.end;
+    if (have_n) issue_planes(tn, nxt, g_nxt, l_nxt);
+    const int j0 = cur.j0, ra = cur.ra, rb = cur.rb;
+    if (ra < rb) {
+      const int nr = rb - ra;
+      const int nstage = min(nr, NPF * kWG - 1);
+      __syncthreads();  // the previous tile's LDS reads are done
+#pragma unroll
+      for (int k = 0; k < NPF; ++k) {
+        const int i = k * kWG + tid;
+        if (i <= nstage) rps[i] = rpv_cur[k];
+      }
+      g_cur.stage_all(scale, tid * E, vals, cols);
+      if (tid < LOOK_LANES) l_cur.stage_all(scale, T + tid * E, vals, cols);
+      if (have_n) issue_rows(nxt, rpv_nxt);
+      __syncthreads();
+      for (int r = ra + tid; r < rb; r += kWG) {
+        const int s0 = (r - ra <= nstage) ? rps[r - ra] : A.row_ptr[r];
+        const int s1 = (r + 1 - ra <= nstage) ? rps[r + 1 - ra] : A.row_ptr[r + 1];
+        const int o = s0 - j0;
+        const int len = s1 - s0;
+        double sum = 0.0;
+        for (int kb = 0; kb < len; kb += 8) {
+          double v[8], xv[8];
+          int c[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            v[k] = vals[o + kb + k];
+            c[k] = (kb + k < len) ? cols[o + kb + k] : 0;
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k) xv[k] = x[c[k]];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const double p = __dmul_rn(v[k], xv[k]);
+            sum = (kb + k < len) ? __dadd_rn(sum, p) : sum;
+          }
+        }
+        if (ep.epi == kEpiPlain) {
+          y[r] = sum;
+        } else if (ep.epi == kEpiDot) {
+          y[r] = sum;
+          acc += ep.aux[r] * sum;
+        } else {
+          const double vres = ep.aux[r] - sum;
+          y[r] = vres;
+          acc += vres * vres;
+        }
+      }
+    } else if (have_n) {
+      issue_rows(nxt, rpv_nxt);
+    }
+    walk.t = tn;
+    have = have_n;
+    cur = nxt;
+    g_cur = g_nxt;
+    l_cur = l_nxt;
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) rpv_cur[k] = rpv_nxt[k];
+  }
+  if (ep.epi != kEpiPlain) {
+    const double bs = block_sum(acc, red);
+    if (tid == 0) ep.partials[blockIdx.x] = bs;
+  }
+}
+
 // Resident workgroups of one kernel instance on this device (occupancy x
 // compute units), cached per instance.
-template <int FMT, int E>
+template <int FMT, int E, bool SHORT>
 int resident_groups() {
   static int cached = 0;
   if (cached == 0) {
@@ -465,24 +572,46 @@ int resident_groups() {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv<FMT, E>, kWG, 0) != hipSuccess)
-      return 0;
+    hipError_t e = SHORT ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv_short<FMT, E>, kWG, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv<FMT, E>, kWG, 0);
+    if (e != hipSuccess) return 0;
     cached = cus * (per_cu > 0 ? per_cu : 1);
   }
   return cached;
 }
 
+// The smallest resident count over the four formats: launches that leave
+// per-workgroup partial sums use it, so the partials of a dot product are
+// grouped the same way whatever the segment count (an operator that is exact
+// at one segment then gives FP64-identical solver iterates).
+template <int E, bool SHORT>
+int common_groups() {
+  const int a = resident_groups<0, E, SHORT>(), b = resident_groups<1, E, SHORT>();
+  const int c = resident_groups<2, E, SHORT>(), d = resident_groups<3, E, SHORT>();
+  int m = a < b ? a : b;
+  m = m < c ? m : c;
+  return m < d ? m : d;
+}
+
 template <int FMT, int E>
 hipError_t launch_fe(const SpmvOperand& A, const double* x, double* y, const SpmvEpilogue& ep,
                      hipStream_t st) {
-  int g = resident_groups<FMT, E>();
+  const bool short_rows = A.max_row <= kShortRow;
+  int g;
+  if (ep.epi != kEpiPlain)
+    g = short_rows ? common_groups<E, true>() : common_groups<E, false>();
+  else
+    g = short_rows ? resident_groups<FMT, E, true>() : resident_groups<FMT, E, false>();
   if (g <= 0) return hipErrorInvalidDevice;
   // at least one workgroup per XCD range, no more than the tiles need
   const int need = (A.n_tiles + 7) / 8 * 8;
   if (g > need) g = need;
   if (g < 8) g = 8;
   if (ep.grid_out) *ep.grid_out = g;
-  hipLaunchKernelGGL((k_spmv<FMT, E>), dim3(g), dim3(kWG), 0, st, A, x, y, ep);
+  if (short_rows)
+    hipLaunchKernelGGL((k_spmv_short<FMT, E>), dim3(g), dim3(kWG), 0, st, A, x, y, ep);
+  else
+    hipLaunchKernelGGL((k_spmv<FMT, E>), dim3(g), dim3(kWG), 0, st, A, x, y, ep);
   return hipGetLastError();
 }
 
@@ -515,7 +644,7 @@ __global__ __launch_bounds__(kWG) void k_spmv_rv(SpmvOperand A, const double* __
   __shared__ double red[kWaves];
 
   if (ep.gate && *ep.gate) return;
-  build_scale<FMT>(A, scale);
+  build_scale<FMT>(A.sem, scale);
   __syncthreads();
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane / L, sub = lane % L;

@@ -55,7 +55,7 @@ class gse_params(C.Structure):
                 ("rsd_limit", C.c_double), ("ndec_limit", C.c_int32),
                 ("reldec_limit", C.c_double), ("ndec_rule", C.c_int32),
                 ("floor_c", C.c_double), ("switch_mode", C.c_int32),
-                ("record_history", C.c_int32)]
+                ("record_history", C.c_int32), ("launch_mode", C.c_int32)]
 
 
 class gse_report(C.Structure):
@@ -72,6 +72,29 @@ class gse_report(C.Structure):
                 "time_ms": self.time_ms}
 
 
+class gse_system(C.Structure):
+    _fields_ = [("A", C.c_void_p), ("M", C.c_void_p), ("b", C.c_void_p), ("x", C.c_void_p)]
+
+
+FMT_GSE, FMT_CSR64 = 0, 1
+
+
+class gse_request(C.Structure):
+    _fields_ = [("n_rows", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p), ("b", C.c_void_p), ("x", C.c_void_p),
+                ("format", C.c_int32), ("num_exp", C.c_int32), ("x0_given", C.c_int32),
+                ("params", gse_params)]
+
+
+class gse_server_stats(C.Structure):
+    _fields_ = [("queued", C.c_int64), ("running", C.c_int64), ("admitted", C.c_int64),
+                ("completed", C.c_int64), ("arena_bytes", C.c_int64), ("arena_used", C.c_int64),
+                ("arena_peak", C.c_int64), ("arena_largest_free", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 # name -> (restype, argtypes)
@@ -85,6 +108,8 @@ _SIGS = {
     "gse_plan": (C.c_int32, [C.POINTER(gse_matrix), C.c_int32, C.c_int32, _P]),
     "gse_csr_plan": (C.c_int32, [C.POINTER(gse_csr), C.c_int32, C.c_int32, _P]),
     "gse_spmv": (C.c_int32, [C.POINTER(gse_matrix), C.c_int32, _P, _P, _P]),
+    "gse_autotune": (C.c_int32, [C.POINTER(gse_matrix), C.c_int32, _P, _P, C.c_int32, _P]),
+    "gse_csr_autotune": (C.c_int32, [C.POINTER(gse_csr), _P, _P, C.c_int32, _P]),
     "gse_csr_spmv": (C.c_int32, [C.POINTER(gse_csr), _P, _P, _P]),
     "gse_default_params": (C.c_int32, [C.c_int32, C.POINTER(gse_params)]),
     "gse_solver_workspace": (C.c_int32, [C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
@@ -98,6 +123,17 @@ _SIGS = {
     "gse_csr_gmres": (C.c_int32, [C.POINTER(gse_csr), _P, _P, C.POINTER(gse_params),
                                   C.POINTER(gse_report), _P, C.c_size_t, _P]),
     "gse_solve_history": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
+    "gse_batch_workspace": (C.c_int32, [C.c_int32, _P, C.POINTER(gse_params),
+                                        C.POINTER(C.c_size_t)]),
+    "gse_batch_cg": (C.c_int32, [C.c_int32, _P, C.POINTER(gse_params), _P, _P, C.c_size_t, _P]),
+    "gse_batch_history": (C.c_int32, [_P, C.c_int32, C.c_int32, _P, _P, _P]),
+    "gse_solver_create": (C.c_int32, [_P, C.c_size_t, C.c_int32, _P, C.POINTER(C.c_void_p)]),
+    "gse_solver_footprint": (C.c_int32, [C.POINTER(gse_request), C.POINTER(C.c_size_t),
+                                         C.POINTER(C.c_size_t)]),
+    "gse_solver_submit": (C.c_int32, [_P, C.POINTER(gse_request), C.POINTER(C.c_uint64)]),
+    "gse_solver_poll": (C.c_int32, [_P, C.c_uint64, C.POINTER(gse_report)]),
+    "gse_solver_stats": (C.c_int32, [_P, C.POINTER(gse_server_stats)]),
+    "gse_solver_destroy": (C.c_int32, [_P]),
     "gse_stream_copy": (C.c_int32, [_P, _P, C.c_size_t, _P]),
     "gse_status_str": (C.c_char_p, [C.c_int32]),
     "gse_last_error": (C.c_char_p, []),
@@ -181,6 +217,18 @@ def gse_spmv(A: gse_matrix, k_segments: int, x: torch.Tensor, y: torch.Tensor, s
                   "gse_spmv")
 
 
+def gse_autotune(A: gse_matrix, k_segments: int, x: torch.Tensor, y: torch.Tensor, reps: int = 5,
+                 stream=None) -> int:
+    return _check(lib().gse_autotune(C.byref(A), k_segments, _ptr(x), _ptr(y), reps,
+                                     _stream(stream)), "gse_autotune")
+
+
+def gse_csr_autotune(M: gse_csr, x: torch.Tensor, y: torch.Tensor, reps: int = 5,
+                     stream=None) -> int:
+    return _check(lib().gse_csr_autotune(C.byref(M), _ptr(x), _ptr(y), reps, _stream(stream)),
+                  "gse_csr_autotune")
+
+
 def gse_csr_spmv(M: gse_csr, x: torch.Tensor, y: torch.Tensor, stream=None) -> int:
     return _check(lib().gse_csr_spmv(C.byref(M), _ptr(x), _ptr(y), _stream(stream)),
                   "gse_csr_spmv")
@@ -232,6 +280,113 @@ def gse_solve_history(ws, cap: int, stream=None):
                                    C.c_void_p(seg.ctypes.data), _stream(stream)),
            "gse_solve_history")
     return hist, seg
+
+
+def _systems(systems):
+    """systems: list of (matrix, b, x) with matrix a gse_matrix or gse_csr record."""
+    arr = (gse_system * len(systems))()
+    for i, (mat, b, x) in enumerate(systems):
+        if isinstance(mat, gse_matrix):
+            arr[i].A = C.addressof(mat)
+        else:
+            arr[i].M = C.addressof(mat)
+        arr[i].b = b.data_ptr()
+        arr[i].x = x.data_ptr()
+    return arr
+
+
+def gse_batch_workspace(systems, p: gse_params) -> int:
+    arr = _systems(systems)
+    out = C.c_size_t()
+    _check(lib().gse_batch_workspace(len(systems), C.cast(arr, C.c_void_p), C.byref(p),
+                                     C.byref(out)), "gse_batch_workspace")
+    return out.value
+
+
+def gse_batch_cg(systems, p: gse_params, ws: torch.Tensor, stream=None):
+    """Solve every (matrix, b, x) together; returns the list of reports."""
+    arr = _systems(systems)
+    reps = (gse_report * len(systems))()
+    st = lib().gse_batch_cg(len(systems), C.cast(arr, C.c_void_p), C.byref(p),
+                            C.cast(reps, C.c_void_p), _ptr(ws), ws.numel() * ws.element_size(),
+                            _stream(stream))
+    if st < 0 and st != ERR_BREAKDOWN:
+        _check(st, "gse_batch_cg")
+    return list(reps)
+
+
+def gse_batch_history(ws, index: int, cap: int, stream=None):
+    import numpy as np
+    hist = np.zeros(cap, np.float64)
+    seg = np.zeros(cap, np.int32)
+    _check(lib().gse_batch_history(_ptr(ws), index, cap, C.c_void_p(hist.ctypes.data),
+                                   C.c_void_p(seg.ctypes.data), _stream(stream)),
+           "gse_batch_history")
+    return hist, seg
+
+
+def gse_solver_create(arena: torch.Tensor, max_slots: int, stream=None):
+    out = C.c_void_p()
+    _check(lib().gse_solver_create(_ptr(arena), arena.numel() * arena.element_size(), max_slots,
+                                   _stream(stream), C.byref(out)), "gse_solver_create")
+    return out
+
+
+def gse_solver_footprint(rq: gse_request):
+    res, tr = C.c_size_t(), C.c_size_t()
+    _check(lib().gse_solver_footprint(C.byref(rq), C.byref(res), C.byref(tr)),
+           "gse_solver_footprint")
+    return res.value, tr.value
+
+
+def gse_solver_submit(server, rq: gse_request) -> int:
+    t = C.c_uint64()
+    _check(lib().gse_solver_submit(server, C.byref(rq), C.byref(t)), "gse_solver_submit")
+    return t.value
+
+
+def gse_solver_poll(server, ticket: int):
+    """None while pending, else the report (the ticket is retired)."""
+    rep = gse_report()
+    st = _check(lib().gse_solver_poll(server, ticket, C.byref(rep)), "gse_solver_poll")
+    return None if st == PENDING else rep
+
+
+def gse_solver_stats(server) -> gse_server_stats:
+    out = gse_server_stats()
+    _check(lib().gse_solver_stats(server, C.byref(out)), "gse_solver_stats")
+    return out
+
+
+def gse_solver_destroy(server) -> None:
+    _check(lib().gse_solver_destroy(server), "gse_solver_destroy")
+
+
+class Request:
+    """Host arrays of one server request, kept alive until it completes."""
+
+    def __init__(self, A, b, fmt: int = FMT_GSE, params: Optional[gse_params] = None,
+                 x0=None, num_exp: int = 8):
+        import numpy as np
+        # private copies: the server reads them until the request completes
+        self.row_ptr = np.array(A.indptr, dtype=np.int32)
+        self.col = np.array(A.indices, dtype=np.int32)
+        self.val = np.array(A.data, dtype=np.float64)
+        self.b = np.array(b, dtype=np.float64)
+        self.x = np.zeros(A.n_rows) if x0 is None else np.array(x0, dtype=np.float64)
+        rq = gse_request()
+        rq.n_rows = A.n_rows
+        rq.nnz = int(self.val.size)
+        rq.row_ptr = self.row_ptr.ctypes.data
+        rq.col = self.col.ctypes.data
+        rq.val = self.val.ctypes.data
+        rq.b = self.b.ctypes.data
+        rq.x = self.x.ctypes.data
+        rq.format = fmt
+        rq.num_exp = num_exp
+        rq.x0_given = 0 if x0 is None else 1
+        rq.params = params if params is not None else gse_default_params(CG)
+        self.rq = rq
 
 
 def gse_stream_copy(src: torch.Tensor, dst: torch.Tensor, nbytes: int, stream=None) -> int:
@@ -295,8 +450,12 @@ class GseMatrix:
                 self.tail1[:n].cpu().numpy().view("uint16"),
                 self.tail2[:n].cpu().numpy().view("uint32"))
 
-    def plan(self, tile_nnz: int = 2048, rv_lanes: int = -1, stream=None):
+    def plan(self, tile_nnz: int = 1024, rv_lanes: int = -1, stream=None):
         gse_plan(self.A, tile_nnz, rv_lanes, stream)
+
+    def autotune(self, k_segments: int, x: torch.Tensor, y: torch.Tensor, reps: int = 5,
+                 stream=None):
+        gse_autotune(self.A, k_segments, x, y, reps, stream)
 
     def spmv(self, k_segments: int, x: torch.Tensor, y: torch.Tensor, stream=None):
         gse_spmv(self.A, k_segments, x, y, stream)
@@ -306,7 +465,7 @@ class CsrMatrix:
     """Padded device copy of an FP64 CSR matrix for the baseline operators."""
 
     def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n_cols: int,
-                 tile_nnz: int = 2048, rv_lanes: int = -1, stream=None):
+                 tile_nnz: int = 1024, rv_lanes: int = -1, stream=None):
         dev = row_ptr.device
         nnz = val.numel()
         pad = gse_pad(nnz)
@@ -330,8 +489,11 @@ class CsrMatrix:
         self.M = M
         gse_csr_plan(M, tile_nnz, rv_lanes, stream)
 
-    def plan(self, tile_nnz: int = 2048, rv_lanes: int = -1, stream=None):
+    def plan(self, tile_nnz: int = 1024, rv_lanes: int = -1, stream=None):
         gse_csr_plan(self.M, tile_nnz, rv_lanes, stream)
+
+    def autotune(self, x: torch.Tensor, y: torch.Tensor, reps: int = 5, stream=None):
+        gse_csr_autotune(self.M, x, y, reps, stream)
 
     def spmv(self, x: torch.Tensor, y: torch.Tensor, stream=None):
         gse_csr_spmv(self.M, x, y, stream)

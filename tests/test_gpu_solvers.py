@@ -36,12 +36,13 @@ def true_relres(A: CSR, x, b):
 
 
 def gpu_solve(kind, A: CSR, b, method, fixed=0, max_iter=5000, switch_mode=1, x0=None,
-              record=True, rv=-1):
+              record=True, rv=-1, launch_mode=0):
     rp, ci, va = to_dev(A)
     p = G.gse_default_params(method)
     p.max_iter = max_iter
     p.fixed_segments = fixed
     p.switch_mode = switch_mode
+    p.launch_mode = launch_mode
     p.record_history = 1 if record else 0
     ws = torch.empty(G.gse_solver_workspace(method, A.n_rows, A.nnz, p.restart, p.max_iter),
                      dtype=torch.uint8, device=DEV)
@@ -196,3 +197,22 @@ def test_solver_argument_errors():
     with pytest.raises(G.GseError) as ei:
         G.gse_cg(M.A, b, x, p, ws)
     assert ei.value.status == G.ERR_ARG
+
+
+@pytest.mark.parametrize("method", [G.CG, G.GMRES])
+def test_graph_replay_matches_direct_launches(method):
+    """Iterations replayed from HIP graphs give the same bits as direct
+    launches, solve after solve, with eager work on the device in between."""
+    A = diffusion3d(14, 6) if method == G.CG else convdiff2d(40, 6)
+    _, b = rhs_from_solution(A, 6)
+    kw = dict(max_iter=5000 if method == G.CG else 15000)
+    rd, xd, hd, _ = gpu_solve("gse", A, b, method, launch_mode=1, **kw)
+    for _ in range(3):
+        junk = torch.randn(1 << 20, device=DEV).sum()  # unrelated eager work
+        rg, xg, hg, _ = gpu_solve("gse", A, b, method, launch_mode=0, **kw)
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        assert rg.status == rd.status == G.OK
+        assert rg.iters == rd.iters and list(rg.iters_per_seg) == list(rd.iters_per_seg)
+        assert np.array_equal(xg, xd)
+        assert np.array_equal(hg, hd)

@@ -175,11 +175,11 @@ def test_empty_matrix():
 
 
 def test_default_schedule_choice():
-    """Stencils get the row-vector schedule, power-law rows the tiles."""
-    for A, want in ((diffusion3d(16, 0), 8), (poisson2d(32), 8), (powerlaw(20_000, 2), 0)):
+    """The default is the tile schedule with 1024 non-zeros per tile."""
+    for A in (diffusion3d(16, 0), poisson2d(32), powerlaw(20_000, 2)):
         rp, ci, va = to_dev(A)
         M = G.GseMatrix(rp, ci, va, A.n_cols)
-        assert M.A.rv_lanes == want, A.name
+        assert M.A.rv_lanes == 0 and M.A.tile_nnz == 1024, A.name
         assert M.A.max_row_nnz == int(np.diff(A.indptr).max())
 
 
@@ -190,7 +190,7 @@ def test_full_size_diffusion3d_128_sampled():
     A = diffusion3d(128, 0)
     rp, ci, va = to_dev(A)
     M = G.GseMatrix(rp, ci, va, A.n_cols)
-    assert M.A.rv_lanes == 8
+    assert M.A.rv_lanes == 0
     enc = O.encode(A.indptr, A.indices, A.data, A.n_cols)
     assert M.sem == [int(s) for s in enc.sem]
     for got, want in zip(M.planes(), (enc.col_idx, enc.head, enc.tail1, enc.tail2)):
@@ -206,3 +206,30 @@ def test_full_size_diffusion3d_128_sampled():
         y = yd.cpu().numpy()[rows]
         ref = O.gse_spmv_rows(rows, A.indptr, enc, s, x)
         assert np.allclose(y, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_autotune_picks_a_candidate_and_stays_exact():
+    for A in (diffusion3d(24, 1), powerlaw(20_000, 3)):
+        rp, ci, va = to_dev(A)
+        M = G.GseMatrix(rp, ci, va, A.n_cols)
+        enc = O.encode(A.indptr, A.indices, A.data, A.n_cols)
+        x = np.random.default_rng(0).uniform(-1, 1, A.n_cols)
+        xd = torch.from_numpy(x).to(DEV)
+        yd = torch.empty(A.n_rows, dtype=torch.float64, device=DEV)
+        for s in (1, 3):
+            M.autotune(s, xd, yd, reps=3)
+            assert (M.A.tile_nnz, M.A.rv_lanes) in {(1024, 0), (2048, 0), (4096, 0), (1024, 4),
+                                                     (1024, 8), (1024, 16)}
+            first = (M.A.tile_nnz, M.A.rv_lanes)
+            M.autotune(s, xd, yd, reps=3)  # cached: same choice
+            assert (M.A.tile_nnz, M.A.rv_lanes) == first
+            M.spmv(s, xd, yd)
+            torch.cuda.synchronize()
+            ref = O.gse_spmv(A.indptr, enc, s, x)
+            assert np.allclose(yd.cpu().numpy(), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+        C64 = G.CsrMatrix(rp, ci, va, A.n_cols)
+        C64.autotune(xd, yd, reps=3)
+        C64.spmv(xd, yd)
+        torch.cuda.synchronize()
+        ref = O.csr_spmv(A.indptr, A.indices, A.data, x)
+        assert np.allclose(yd.cpu().numpy(), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())

@@ -117,3 +117,52 @@ def test_schedule_in_bounds(name, E):
 def test_schedule_full_size_diffusion3d_128(E):
     A = diffusion3d(128, 0)
     assert check(A.indptr.astype(np.int64), A.n_cols, A.indices, E) == -(-A.nnz // (WG * E))
+
+
+def check_short(indptr, n_cols, cols, E, look=32):
+    """Index model of the short-row tile kernel (rows of at most 24)."""
+    T = WG * E
+    n_rows = indptr.size - 1
+    nnz = int(indptr[-1])
+    pad = (nnz + PAD - 1) // PAD * PAD
+    lens = np.diff(indptr)
+    assert lens.max(initial=0) <= SHORT
+    n_tiles = max(1, -(-nnz // T))
+    tile_row = [lower_bound(indptr[:n_rows], t * T) for t in range(n_tiles)] + [n_rows]
+    ns = T + look + 8
+    for t in range(n_tiles):
+        j0, j1 = t * T, min(t * T + T, nnz)
+        ra, rb = tile_row[t], tile_row[t + 1]
+        for tid in range(WG):
+            b = j0 + tid * E
+            if b < nnz:
+                assert b + E <= pad
+            lb = j1 + tid * E
+            if tid < look // E and lb < nnz:
+                assert lb + E <= pad and T + tid * E + E <= ns
+        for r in range(ra, rb):
+            s0, s1 = int(indptr[r]), int(indptr[r + 1])
+            o = s0 - j0
+            assert 0 <= o < T
+            # staged: main [0, T) and look-ahead [T, T + look); reads up to o+len-1
+            assert o + (s1 - s0) <= T + look
+            # unconditional 8-wide reads stay inside the LDS arrays
+            last_read = o + ((max(s1 - s0, 1) - 1) // 8) * 8 + 7
+            assert last_read < ns
+            if s1 > s0:
+                assert cols[s0:s1].max() < n_cols
+
+
+@pytest.mark.parametrize("E", [4, 8, 16])
+@pytest.mark.parametrize("name", ["poisson2d_64", "diffusion3d_24", "convdiff2d_64", "tiny",
+                                  "empty", "random_ragged"])
+def test_short_row_kernel_in_bounds(name, E):
+    A = MATS[name]()
+    if np.diff(A.indptr).max(initial=0) > SHORT:
+        pytest.skip("rows longer than the short-row limit use the general kernel")
+    check_short(A.indptr.astype(np.int64), A.n_cols, A.indices, E)
+
+
+def test_short_row_kernel_full_size_diffusion3d_128():
+    A = diffusion3d(128, 0)
+    check_short(A.indptr.astype(np.int64), A.n_cols, A.indices, 4)

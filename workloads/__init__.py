@@ -9,11 +9,13 @@ from .generators import (  # noqa: F401
     CSR,
     poisson2d,
     diffusion3d,
+    diffusion2d,
     convdiff2d,
     powerlaw,
     random_sparse,
     rhs_from_solution,
     serving_stream,
+    serving_request_matrix,
     make_config,
     CONFIGS,
 )
