@@ -1,9 +1,9 @@
 """Benchmark: GSE-SEM SpMV bandwidth per segment count and stepped CG
 time-to-1e-10 against plain FP64 CSR on one MI355X.
 
-One step = the whole hot path on the 3-D 7-point variable-coefficient
-diffusion operator (128^3 cells, 14.58 M non-zeros, face coefficients
-log-uniform over four decades):
+Default workload (``--workload spmv_cg``), one step = the whole hot path on
+the 3-D 7-point variable-coefficient diffusion operator (128^3 cells,
+14.58 M non-zeros, face coefficients log-uniform over four decades):
   * SpMV with 1, 2 and 3 segments and the FP64 CSR baseline, each over
     ``--copies`` resident copies of the matrix in rotation so that the
     working set exceeds the 256 MB Infinity Cache (cold, HBM-bound);
@@ -12,14 +12,24 @@ Inputs are synthetic (seeded generator) and resident in HBM before timing.
 
 Prints one JSON line.  ``value`` is the GSE SpMV HBM bandwidth with one
 segment (algorithmic bytes / mean kernel time from HIP events on the launch
-stream); the other segment counts, the FP64 baseline and the solve times are
-reported beside it.
+stream); the other segment counts, the FP64 baseline, a streaming-copy
+ceiling and the solve times are reported beside it.
+
+Other workloads (one JSON line each):
+  * ``--workload gmres``: stepped GMRES(30) and FP64 GMRES(30) to 1e-10 on
+    the 2-D upwind convection-diffusion operator, 1024^2 cells;
+  * ``--workload serving``: a Poisson-arrival stream of 2-D / 3-D diffusion
+    systems through the solver server (stepped GSE, batched) against the
+    same server running FP64 CSR one request at a time; p50 / p99 latency
+    and solves per second.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,6 +40,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "GSE-SpMV HBM GB/s (% peak) per segment count; CG time-to-1e-10 vs FP64 CSR"
+KERNEL_SOURCES = ("paper_2411_04686_amd/csrc/spmv.hip", "paper_2411_04686_amd/csrc/decode.h",
+                  "paper_2411_04686_amd/csrc/gse_internal.h")
 
 
 def spmv_bytes(n_rows, n_cols, nnz, plane_bytes):
@@ -42,7 +54,36 @@ def kernel_name(A):
     """Name of the kernel instance the one-segment SpMV runs on this schedule."""
     if A.rv_lanes > 0:
         return f"k_spmv_rv<1, {A.rv_lanes}>"
-    return f"k_spmv<1, {A.tile_nnz // 256}>"
+    e = A.tile_nnz // 256
+    if A.max_row_nnz <= 24:
+        return f"k_spmv_short<1, {e}>"
+    return f"k_spmv<1, {e}>"
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_spmv_s1_diffusion3d_128.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    fields = dict(re.findall(r"^- (\w+): `([^`]*)`", text, re.M))
+    if fields.get("kernel") != kernel or fields.get("workload") != workload:
+        return None
+    if fields.get("source_digest") != source_digest():
+        return None
+    try:
+        return int(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -50,6 +91,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="spmv_cg", choices=["spmv_cg", "gmres", "serving"])
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copies", type=int, default=4)
@@ -57,6 +99,10 @@ def parse():
     ap.add_argument("--no-solve", action="store_true", help="SpMV only (profiling runs)")
     ap.add_argument("--cpu-baseline", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline (0: skip)")
+    ap.add_argument("--requests", type=int, default=48, help="serving: requests per load level")
+    ap.add_argument("--n-hi", type=float, default=1e5, help="serving: largest request size")
+    ap.add_argument("--arena-gb", type=float, default=32.0, help="serving: arena size")
+    ap.add_argument("--slots", type=int, default=64, help="serving: batch slots")
     return ap.parse_args()
 
 
@@ -81,15 +127,34 @@ def cpu_baseline(A, seconds):
                       f"({el:.1f} s, {per * 1e3:.1f} ms each, one thread)"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; "
-                                   f"--gpus {args.gpus} is not supported"}))
-        sys.exit(2)
-    import torch
+def copy_ceiling(G, torch, dev, stream):
+    """Streaming copy of 512 MiB (read + write), the practical HBM ceiling."""
+    n = 512 << 20
+    src = torch.empty(n, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        G.gse_stream_copy(src, dst, n)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        G.gse_stream_copy(src, dst, n)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    del src, dst
+    return round(2 * n / (ms * 1e-3) / 1e9, 1)
 
-    from paper_2411_04686_amd import gse as G
+
+def base_record(args, metric, value, unit, wall, higher=True):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(wall / max(args.steps, 1) * 1e3, 3),
+            "higher_is_better": higher, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic"}
+
+
+# ------------------------------------------------------------ spmv + CG ---
+def run_spmv_cg(args, torch, G):
     from workloads import diffusion3d, rhs_from_solution
 
     dev = torch.device("cuda:0")
@@ -104,6 +169,7 @@ def main():
     xs = torch.ones(A.n_cols, dtype=torch.float64, device=dev)
     ys = [torch.empty(A.n_rows, dtype=torch.float64, device=dev) for _ in range(args.copies)]
     stream = torch.cuda.current_stream()
+    copy_gbs = copy_ceiling(G, torch, dev, stream)
 
     kinds = [("s1", 6), ("s2", 8), ("s3", 12), ("fp64", 12)]
     times = {k: [] for k, _ in kinds}
@@ -127,7 +193,7 @@ def main():
     solve = {}
 
     def solve_pass(record):
-        if args.no_solve or not hasattr(G.lib(), "gse_cg"):
+        if args.no_solve:
             return
         bd = torch.from_numpy(b).to(dev)
         p = G.gse_default_params(G.CG)
@@ -165,29 +231,19 @@ def main():
                        "bytes": int(nbytes),
                        "GBps": round(nbytes / (mean * 1e-3) / 1e9, 1),
                        "frac_peak": round(nbytes / (mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-    out = {
-        "metric": METRIC,
-        "value": spmv["s1"]["GBps"],
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"diffusion3d_{args.grid}^3_7pt_varcoef_4decades",
-                   "n_rows": A.n_rows, "nnz": A.nnz, "copies_rotated": args.copies,
-                   "x": "ones", "seed": args.seed, "tile_nnz": mats[0].A.tile_nnz,
-                   "rv_lanes": mats[0].A.rv_lanes},
-        "spmv": spmv,
-        "roofline": {"bound": "hbm", "achieved": spmv["s1"]["GBps"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": spmv["s1"]["frac_peak"], "traffic": None,
-                     "kernel": kernel_name(mats[0].A),
-                     "bytes_per_launch": spmv["s1"]["bytes"]},
-    }
+    workload = f"diffusion3d_{args.grid}^3_7pt_varcoef_4decades"
+    kname = kernel_name(mats[0].A)
+    out = base_record(args, METRIC, spmv["s1"]["GBps"], "GB/s", wall)
+    out["config"] = {"workload": workload, "n_rows": A.n_rows, "nnz": A.nnz,
+                     "copies_rotated": args.copies, "x": "ones", "seed": args.seed,
+                     "tile_nnz": mats[0].A.tile_nnz, "rv_lanes": mats[0].A.rv_lanes}
+    out["spmv"] = spmv
+    out["copy_ceiling_GBps"] = copy_gbs
+    out["roofline"] = {"bound": "hbm", "achieved": spmv["s1"]["GBps"], "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": spmv["s1"]["frac_peak"],
+                       "traffic": measured_traffic(kname, workload), "kernel": kname,
+                       "bytes_per_launch": spmv["s1"]["bytes"],
+                       "mean_launch_us": spmv["s1"]["mean_us"]}
     if solve:
         g = solve["gse"][-1]
         f = solve["fp64"][-1]
@@ -195,6 +251,150 @@ def main():
                      "speedup": round(f["time_ms"] / g["time_ms"], 3) if g["time_ms"] else None}
     if args.cpu_baseline > 0:
         out["cpu_baseline"] = cpu_baseline(A, args.cpu_baseline)
+    return out
+
+
+# ---------------------------------------------------------------- GMRES ---
+def run_gmres(args, torch, G):
+    from workloads import convdiff2d, rhs_from_solution
+
+    dev = torch.device("cuda:0")
+    N = 1024
+    A = convdiff2d(N, args.seed)
+    _, b = rhs_from_solution(A, args.seed)
+    rp = torch.from_numpy(A.indptr).to(dev)
+    ci = torch.from_numpy(A.indices).to(dev)
+    va = torch.from_numpy(A.data).to(dev)
+    M = G.GseMatrix(rp, ci, va, A.n_cols)
+    C = G.CsrMatrix(rp, ci, va, A.n_cols)
+    bd = torch.from_numpy(b).to(dev)
+    p = G.gse_default_params(G.GMRES)
+    ws = torch.empty(G.gse_solver_workspace(G.GMRES, A.n_rows, A.nnz, p.restart, p.max_iter),
+                     dtype=torch.uint8, device=dev)
+    x = torch.zeros(A.n_rows, dtype=torch.float64, device=dev)
+    res = {}
+    for _ in range(args.warmup):
+        x.zero_()
+        G.gse_gmres(M.A, bd, x, p, ws)
+        x.zero_()
+        G.gse_csr_gmres(C.M, bd, x, p, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x.zero_()
+        res["gse"] = G.gse_gmres(M.A, bd, x, p, ws).as_dict()
+        x.zero_()
+        res["fp64"] = G.gse_csr_gmres(C.M, bd, x, p, ws).as_dict()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    g, f = res["gse"], res["fp64"]
+    out = base_record(args, "GMRES(30) time-to-1e-10, stepped GSE vs FP64 CSR", round(g["time_ms"], 3),
+                      "ms", wall, higher=False)
+    out["config"] = {"workload": f"convdiff2d_{N}^2_upwind_Pe10", "n_rows": A.n_rows, "nnz": A.nnz,
+                     "seed": args.seed, "restart": p.restart}
+    out["gmres"] = {"gse": g, "fp64": f,
+                    "speedup": round(f["time_ms"] / g["time_ms"], 3) if g["time_ms"] else None}
+    return out
+
+
+# -------------------------------------------------------------- serving ---
+def run_serving(args, torch, G):
+    from workloads import rhs_from_solution, serving_request_matrix, serving_stream
+
+    dev = torch.device("cuda:0")
+    stream_def = serving_stream(args.seed, count=args.requests, n_lo=1e3, n_hi=args.n_hi)
+    systems = []
+    for r in stream_def:
+        A = serving_request_matrix(r)
+        _, b = rhs_from_solution(A, r["seed"])
+        systems.append((A, b))
+    p = G.gse_default_params(G.CG)
+    p.max_iter = 20000
+    arena = torch.empty(int(args.arena_gb * (1 << 30)), dtype=torch.uint8, device=dev)
+
+    def run(fmt, slots, gaps):
+        """Submit every request after its gap (open loop); latencies in ms."""
+        server = G.gse_solver_create(arena, slots)
+        try:
+            reqs = [G.Request(A, b, fmt, params=p) for A, b in systems]
+            tickets, done = [], {}
+            t0 = time.perf_counter()
+            due = t0
+            for rq, gap in zip(reqs, gaps):
+                due += gap
+                while time.perf_counter() < due:
+                    for t in tickets:
+                        if t not in done:
+                            r = G.gse_solver_poll(server, t)
+                            if r is not None:
+                                done[t] = (r, time.perf_counter())
+                    time.sleep(0.0005)
+                tickets.append(G.gse_solver_submit(server, rq.rq))
+            while len(done) < len(tickets):
+                for t in tickets:
+                    if t not in done:
+                        r = G.gse_solver_poll(server, t)
+                        if r is not None:
+                            done[t] = (r, time.perf_counter())
+                time.sleep(0.0005)
+            t_end = max(v[1] for v in done.values())
+            stats = G.gse_solver_stats(server).as_dict()
+        finally:
+            G.gse_solver_destroy(server)
+        reps = [done[t][0] for t in tickets]
+        lat = np.array([r.time_ms for r in reps])
+        ok = sum(1 for r in reps if r.status == G.OK)
+        return {"solves_per_s": round(len(reps) / (t_end - t0), 2),
+                "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                "converged": ok, "requests": len(reps), "peak_arena_GB":
+                    round(stats["arena_peak"] / 2**30, 3)}, [rq.x.copy() for rq in reqs]
+
+    t0 = time.perf_counter()
+    zero = [0.0] * len(systems)
+    base, _ = run(G.FMT_CSR64, 1, zero)  # closed loop: the one-at-a-time throughput
+    lam = base["solves_per_s"]
+    rng = np.random.default_rng(args.seed + 1)
+    levels = {}
+    xs_mix = None
+    for f in (0.5, 1.0, 2.0):
+        gaps = list(rng.exponential(1.0 / (f * lam), size=len(systems)))
+        levels[f"{f}x"], xs = run(G.FMT_GSE, args.slots, gaps)
+        if f == 2.0:
+            xs_mix = xs
+    # the same requests one at a time through the same server: same bits
+    _, xs_alone = run(G.FMT_GSE, 1, zero)
+    bitwise = all(np.array_equal(a, b) for a, b in zip(xs_mix, xs_alone))
+    wall = time.perf_counter() - t0
+    out = base_record(args, "serving solves/s at 1x the one-at-a-time FP64 rate (stepped GSE, batched)",
+                      levels["1.0x"]["solves_per_s"], "solves/s", wall)
+    out["steps"] = 1
+    out["warmup"] = 0
+    ns = [A.n_rows for A, _ in systems]
+    out["config"] = {"workload": f"serving_poisson_arrivals_{len(systems)}req_n1e3..{args.n_hi:.0e}_2d3d_diffusion",
+                     "mean_n": int(np.mean(ns)), "max_n": int(max(ns)), "slots": args.slots,
+                     "arena_GB": args.arena_gb, "tol": 1e-10}
+    out["serving"] = {"fp64_one_at_a_time": base, "gse_batched": levels,
+                      "alone_vs_mix_bitwise": bool(bitwise)}
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; "
+                                   f"--gpus {args.gpus} is not supported"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2411_04686_amd import gse as G
+    G.lib()
+    if args.workload == "gmres":
+        out = run_gmres(args, torch, G)
+    elif args.workload == "serving":
+        out = run_serving(args, torch, G)
+    else:
+        out = run_spmv_cg(args, torch, G)
     print(json.dumps(out))
 
 

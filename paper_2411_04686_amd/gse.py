@@ -363,7 +363,8 @@ def gse_solver_destroy(server) -> None:
 
 
 class Request:
-    """Host arrays of one server request, kept alive until it completes."""
+    """Host arrays of one server request.  The server reads them (and writes
+    ``x``) until the ticket completes, so keep this object alive until then."""
 
     def __init__(self, A, b, fmt: int = FMT_GSE, params: Optional[gse_params] = None,
                  x0=None, num_exp: int = 8):

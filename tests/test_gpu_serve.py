@@ -141,8 +141,9 @@ def test_server_rejects_bad_requests():
             G.gse_solver_submit(server, badc.rq)
         assert ei.value.status == G.ERR_ARG
         big = diffusion3d(80, 0)
+        big_rq = G.Request(big, np.ones(big.n_rows))  # kept alive while the server reads it
         with pytest.raises(G.GseError) as ei:
-            G.gse_solver_submit(server, G.Request(big, np.ones(big.n_rows)).rq)
+            G.gse_solver_submit(server, big_rq.rq)
         assert ei.value.status == G.ERR_NOMEM
         with pytest.raises(G.GseError) as ei:
             G.gse_solver_poll(server, 12345)
