@@ -11,9 +11,10 @@ the 3-D 7-point variable-coefficient diffusion operator (128^3 cells,
 Inputs are synthetic (seeded generator) and resident in HBM before timing.
 
 Prints one JSON line.  ``value`` is the GSE SpMV HBM bandwidth with one
-segment (algorithmic bytes / mean kernel time from HIP events on the launch
-stream); the other segment counts, the FP64 baseline, a streaming-copy
-ceiling and the solve times are reported beside it.
+segment: algorithmic bytes / mean time per launch, from HIP events on the
+launch stream around rounds of back-to-back launches (one per copy); the
+other segment counts, the FP64 baseline, a streaming-copy ceiling and the
+solve times are reported beside it.
 
 Other workloads (one JSON line each):
   * ``--workload gmres``: stepped GMRES(30) and FP64 GMRES(30) to 1e-10 on
@@ -146,6 +147,11 @@ def copy_ceiling(G, torch, dev, stream):
     return round(2 * n / (ms * 1e-3) / 1e9, 1)
 
 
+def progress(msg):
+    """A progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def base_record(args, metric, value, unit, wall, higher=True):
     return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": round(wall / max(args.steps, 1) * 1e3, 3),
@@ -175,20 +181,23 @@ def run_spmv_cg(args, torch, G):
     times = {k: [] for k, _ in kinds}
 
     def spmv_pass(record):
+        # HIP events on the launch stream around each round of `copies`
+        # back-to-back launches (one per copy): the per-launch time is the
+        # round's time over `copies`, launch gaps included
         for kname, _ in kinds:
             for rep in range(args.reps):
+                if record:
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
                 for c in range(args.copies):
-                    if record:
-                        e0 = torch.cuda.Event(enable_timing=True)
-                        e1 = torch.cuda.Event(enable_timing=True)
-                        e0.record(stream)
                     if kname == "fp64":
                         csrs[c].spmv(xs, ys[c])
                     else:
                         mats[c].spmv(int(kname[1]), xs, ys[c])
-                    if record:
-                        e1.record(stream)
-                        times[kname].append((e0, e1))
+                if record:
+                    e1.record(stream)
+                    times[kname].append((e0, e1))
 
     solve = {}
 
@@ -221,7 +230,7 @@ def run_spmv_cg(args, torch, G):
 
     spmv = {}
     for kname, pb in kinds:
-        ms = np.array([a.elapsed_time(c) for a, c in times[kname]])
+        ms = np.array([a.elapsed_time(c) for a, c in times[kname]]) / args.copies
         nbytes = spmv_bytes(A.n_rows, A.n_cols, A.nnz, pb)
         mean = float(ms.mean())
         spmv[kname] = {"mean_us": round(mean * 1e3, 2),
@@ -273,6 +282,7 @@ def run_gmres(args, torch, G):
                      dtype=torch.uint8, device=dev)
     x = torch.zeros(A.n_rows, dtype=torch.float64, device=dev)
     res = {}
+    progress("gmres: operators ready")
     for _ in range(args.warmup):
         x.zero_()
         G.gse_gmres(M.A, bd, x, p, ws)
@@ -283,6 +293,7 @@ def run_gmres(args, torch, G):
     for _ in range(args.steps):
         x.zero_()
         res["gse"] = G.gse_gmres(M.A, bd, x, p, ws).as_dict()
+        progress(f"gmres: GSE {res['gse']}")
         x.zero_()
         res["fp64"] = G.gse_csr_gmres(C.M, bd, x, p, ws).as_dict()
     torch.cuda.synchronize()
@@ -352,14 +363,17 @@ def run_serving(args, torch, G):
 
     t0 = time.perf_counter()
     zero = [0.0] * len(systems)
+    progress(f"serving: {len(systems)} requests generated; FP64 one at a time")
     base, _ = run(G.FMT_CSR64, 1, zero)  # closed loop: the one-at-a-time throughput
     lam = base["solves_per_s"]
+    progress(f"serving: FP64 one at a time {base}")
     rng = np.random.default_rng(args.seed + 1)
     levels = {}
     xs_mix = None
     for f in (0.5, 1.0, 2.0):
         gaps = list(rng.exponential(1.0 / (f * lam), size=len(systems)))
         levels[f"{f}x"], xs = run(G.FMT_GSE, args.slots, gaps)
+        progress(f"serving: GSE batched at {f}x: {levels[f'{f}x']}")
         if f == 2.0:
             xs_mix = xs
     # the same requests one at a time through the same server: same bits

@@ -27,7 +27,9 @@ struct SolverState {
   int s;             // segment count in use (0: FP64 CSR)
   int stop;          // Stop
   int trig;          // trigger of a switch
-  int k3_armed;      // CG: the x/p update of the last completed iteration is pending
+  int k3_armed;      // batched CG: the x/p update of the last completed iteration is pending
+  int go;            // CG: this iteration's r step ran (read by the x step)
+  int it_next;       // CG: the iteration the r step started
   int max_iter;
   int stepped;
   int fixed;
@@ -37,6 +39,7 @@ struct SolverState {
   long long seg_off;   // in the workspace (read by gse_solve_history)
   int hist_cap;
   int pad1;
+  double rho_p[2];   // CG: r.r after `it` iterations lives in rho_p[it & 1]
 };
 
 // ------------------------------------------------------------ controller --

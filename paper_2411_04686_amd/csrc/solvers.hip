@@ -43,28 +43,43 @@ __global__ __launch_bounds__(kWG) void k_finish(const double* __restrict__ parti
 }
 
 // ----------------------------------------------------------- CG kernels ---
-// After q = A_s p (partials of p.q): alpha = rho / p.q, or a breakdown.
-// Also disarms the x/p update of the previous iteration (always runs).
-__global__ __launch_bounds__(kWG) void k_cg_alpha(SolverState* S, const double* __restrict__ partials,
-                                                  int n) {
-  __shared__ double red[kWaves];
-  if (threadIdx.x == 0) S->k3_armed = 0;
-  if (S->stop) return;
-  const double pq = sum_partials(partials, n, red);
-  if (threadIdx.x == 0) {
-    S->pq = pq;
-    if (!(pq > 0.0) || !isfinite(pq)) S->stop = kBreak;
-    else S->alpha = S->rho / pq;
-  }
-}
+// One iteration is three kernels: the SpMV q = A_s p (partials of p.q),
+// k_cg_rstep and k_cg_xstep.  The scalar steps need no kernel of their own:
+// every workgroup sums the partials of the kernel before it in the same
+// fixed order (so all of them get the same bits) and workgroup 0 publishes
+// the results.  Fields a kernel reads are never written by that kernel's
+// workgroup 0, so no workgroup depends on another inside one launch:
+//   rstep reads stop, it, rho_p[it & 1];  writes pq, alpha, go, it_next (and
+//         stop on a breakdown -- every workgroup reaches the same verdict);
+//   xstep reads go, it_next, alpha, rho_p[(it_next - 1) & 1];  writes the
+//         history, rho_p[it_next & 1], it, relres, beta and, through the
+//         controller, stop.
 
-// r -= alpha q, partials of r.r
-__global__ __launch_bounds__(kWG) void k_cg_rupdate(const SolverState* S, double* __restrict__ r,
-                                                    const double* __restrict__ q, int n,
-                                                    double* __restrict__ partials) {
+// r -= alpha q with alpha = rho / p.q; partials of r.r.
+__global__ __launch_bounds__(kWG) void k_cg_rstep(SolverState* S, double* __restrict__ r,
+                                                  const double* __restrict__ q, int n,
+                                                  const double* __restrict__ part_pq, int n_pq,
+                                                  double* __restrict__ part_rr) {
   __shared__ double red[kWaves];
-  if (S->stop) return;
-  const double alpha = S->alpha;
+  const int stop = S->stop;
+  if (blockIdx.x == 0 && threadIdx.x == 0) S->go = 0;
+  if (stop) return;
+  const int j = S->it;
+  const double rho = S->rho_p[j & 1];
+  const double pq = sum_partials(part_pq, n_pq, red);
+  const bool broke = !(pq > 0.0) || !isfinite(pq);
+  const double alpha = rho / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S->pq = pq;
+    if (broke) {
+      S->stop = kBreak;
+    } else {
+      S->alpha = alpha;
+      S->go = 1;
+      S->it_next = j + 1;
+    }
+  }
+  if (broke) return;
   double acc = 0.0;
   const int n2 = n >> 1;
   double2* r2 = reinterpret_cast<double2*>(r);
@@ -84,42 +99,24 @@ __global__ __launch_bounds__(kWG) void k_cg_rupdate(const SolverState* S, double
     acc += v * v;
   }
   const double bs = block_sum(acc, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+  if (threadIdx.x == 0) part_rr[blockIdx.x] = bs;
 }
 
-// rho' = r.r: beta, the residual history and the controller; arms the x/p
-// update.  One workgroup.
-__global__ __launch_bounds__(kWG) void k_cg_advance(SolverState* S, const double* __restrict__ partials,
-                                                    int n, double* hist, int* seg_hist) {
+// x += alpha p; p = r + beta p with beta = rho' / rho (rho' = r.r from the
+// partials); workgroup 0 records the history and runs the controller.
+__global__ __launch_bounds__(kWG) void k_cg_xstep(SolverState* S, double* __restrict__ x,
+                                                  double* __restrict__ p,
+                                                  const double* __restrict__ r, int n,
+                                                  const double* __restrict__ part_rr, int n_rr,
+                                                  double* hist, int* seg_hist) {
   __shared__ double red[kWaves];
-  __shared__ int bc_j, bc_s;
   __shared__ double bc_rel;
-  if (S->stop) return;
-  const double rho_new = sum_partials(partials, n, red);
-  if (threadIdx.x == 0) {
-    const int j = S->it + 1;
-    const double rel = sqrt(rho_new) / S->nb;
-    S->beta = rho_new / S->rho;
-    S->rho = rho_new;
-    S->it = j;
-    S->relres = rel;
-    hist[j] = rel;
-    seg_hist[j] = S->s;
-    S->k3_armed = 1;
-    bc_j = j;
-    bc_s = S->s;
-    bc_rel = rel;
-  }
-  __syncthreads();
-  controller(S, hist, red, bc_j, bc_rel, bc_s);
-}
-
-// x += alpha p; p = r + beta p (the p of the finished iteration).
-__global__ __launch_bounds__(kWG) void k_cg_xpupdate(const SolverState* S, double* __restrict__ x,
-                                                     double* __restrict__ p,
-                                                     const double* __restrict__ r, int n) {
-  if (!S->k3_armed) return;
-  const double alpha = S->alpha, beta = S->beta;
+  if (!S->go) return;
+  const int j = S->it_next;
+  const double rho_old = S->rho_p[(j - 1) & 1];
+  const double alpha = S->alpha;
+  const double rho_new = sum_partials(part_rr, n_rr, red);
+  const double beta = rho_new / rho_old;
   const int n2 = n >> 1;
   double2* x2 = reinterpret_cast<double2*>(x);
   double2* p2 = reinterpret_cast<double2*>(p);
@@ -139,6 +136,21 @@ __global__ __launch_bounds__(kWG) void k_cg_xpupdate(const SolverState* S, doubl
     x[n - 1] += alpha * p[n - 1];
     p[n - 1] = r[n - 1] + beta * p[n - 1];
   }
+  if (blockIdx.x != 0) return;
+  const int s = S->s;
+  if (threadIdx.x == 0) {
+    const double rel = sqrt(rho_new) / S->nb;
+    S->beta = beta;
+    S->rho_p[j & 1] = rho_new;
+    S->rho = rho_new;
+    S->it = j;
+    S->relres = rel;
+    hist[j] = rel;
+    seg_hist[j] = s;
+    bc_rel = rel;
+  }
+  __syncthreads();
+  controller(S, hist, red, j, bc_rel, s);
 }
 
 // dst = src (n doubles)
@@ -216,11 +228,15 @@ Workspace carve(void* base, int32_t method, int32_t n_rows, int64_t nnz, int32_t
   return w;
 }
 
-int vec_blocks(int n) {
+int vec_blocks(int n, int cap = kVecBlocks) {
   int b = (n / 2 + kWG - 1) / kWG;
   if (b < 1) b = 1;
-  return b > kVecBlocks ? kVecBlocks : b;
+  return b > cap ? cap : b;
 }
+
+// CG vector kernels: every workgroup sums the partials of the kernel before
+// it, so fewer (longer-running) workgroups keep that redundant read small.
+constexpr int kCgBlocks = 1024;
 
 // Instantiated graphs of one solve, one per segment count.
 struct GraphCache {
@@ -304,7 +320,7 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
   const bool stepped = A.fmt != 0 && p->fixed_segments == 0;
   int s = (A.fmt == 0) ? 0 : (stepped ? p->start_segments : p->fixed_segments);
   const int s_final = (A.fmt == 0) ? 0 : 3;
-  const int vb = vec_blocks(n);
+  const int vb = vec_blocks(n, kCgBlocks);
   hipError_t e;
   SolverState h;
   init_state(&h, p, A, s);
@@ -313,9 +329,10 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
   h.hist_cap = p->max_iter + 2;
   int nsw = 0;
   gse_status status = GSE_NOT_CONVERGED;
-  // replacement: r = b - A_s x, rho = r.r, optionally p = r
+  // replacement: r = b - A_s x, rho = r.r (into the slot of h.it), optionally p = r
   auto restart = [&](int s_use, bool reset_p) -> hipError_t {
-    hipError_t err = apply(A, s_use, x, w.r, kEpiResid, b, &w.S->rho, w, nullptr, st);
+    hipError_t err =
+        apply(A, s_use, x, w.r, kEpiResid, b, &w.S->rho_p[h.it & 1], w, nullptr, st);
     if (err == hipSuccess && reset_p) {
       hipLaunchKernelGGL(k_copy, dim3(vb), dim3(kWG), 0, st, w.p, w.r, n);
       err = hipGetLastError();
@@ -348,6 +365,7 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
     rep->status = GSE_OK;
     return GSE_OK;
   }
+  h.rho = h.rho_p[0];
   h.relres = sqrt(h.rho) / h.nb;
   double h0 = h.relres;
   int s0i = s;
@@ -356,18 +374,17 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
   if (e == hipSuccess) e = write_state(w, &h, st);
   if (e != hipSuccess) return hip_fail(e, "cg setup");
 
-  // K iterations: q = A_s p (partials of p.q) ; alpha ; r -= alpha q
-  // (partials of r.r) ; beta, history, controller ; x += alpha p, p = r + beta p
+  // K iterations: q = A_s p (partials of p.q) ; alpha, r -= alpha q
+  // (partials of r.r) ; beta, x += alpha p, p = r + beta p, history, controller
   auto launch_iters = [&](int K, int s_use) -> hipError_t {
     for (int k = 0; k < K; ++k) {
       int g1 = 0;
       hipError_t err = apply(A, s_use, w.p, w.q, kEpiDot, w.p, nullptr, w, &w.S->stop, st, &g1);
       if (err != hipSuccess) return err;
-      hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(kWG), 0, st, w.S, w.partials, g1);
-      hipLaunchKernelGGL(k_cg_rupdate, dim3(vb), dim3(kWG), 0, st, w.S, w.r, w.q, n, w.partials2);
-      hipLaunchKernelGGL(k_cg_advance, dim3(1), dim3(kWG), 0, st, w.S, w.partials2, vb, w.hist,
-                         w.seg_hist);
-      hipLaunchKernelGGL(k_cg_xpupdate, dim3(vb), dim3(kWG), 0, st, w.S, x, w.p, w.r, n);
+      hipLaunchKernelGGL(k_cg_rstep, dim3(vb), dim3(kWG), 0, st, w.S, w.r, w.q, n, w.partials, g1,
+                         w.partials2);
+      hipLaunchKernelGGL(k_cg_xstep, dim3(vb), dim3(kWG), 0, st, w.S, x, w.p, w.r, n, w.partials2,
+                         vb, w.hist, w.seg_hist);
       err = hipGetLastError();
       if (err != hipSuccess) return err;
     }
@@ -420,7 +437,8 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
       e = restart(h.s, true);
       if (e == hipSuccess) e = read_state(w, &t, st);
       if (e != hipSuccess) return hip_fail(e, "cg replace");
-      h.rho = t.rho;
+      h.rho_p[h.it & 1] = t.rho_p[h.it & 1];
+      h.rho = h.rho_p[h.it & 1];
       h.relres = sqrt(h.rho) / h.nb;
       if (h.relres <= p->tol || h.it >= p->max_iter) break;
     } else if (reason == kSwitch) {
@@ -434,7 +452,8 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
       e = restart(h.s, p->switch_mode == 0);
       if (e == hipSuccess) e = read_state(w, &t, st);
       if (e != hipSuccess) return hip_fail(e, "cg switch");
-      h.rho = t.rho;
+      h.rho_p[h.it & 1] = t.rho_p[h.it & 1];
+      h.rho = h.rho_p[h.it & 1];
       h.relres = sqrt(h.rho) / h.nb;
       if (h.relres <= p->tol) pending_check = true;
     } else if (reason == kCap) {
@@ -443,7 +462,7 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
     if (h.it >= p->max_iter) break;
     h.stop = kRun;
     h.trig = 0;
-    h.k3_armed = 0;
+    h.go = 0;
     chunk = 4;
     e = write_state(w, &h, st);
     if (e != hipSuccess) return hip_fail(e, "cg state");

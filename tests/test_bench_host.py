@@ -1,0 +1,55 @@
+"""Host-side parts of bench.py (no GPU): the one-GPU guard, the kernel-name
+rule and the reading of committed counter summaries."""
+import importlib.util
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def load_bench():
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    return m
+
+
+def test_more_than_one_gpu_is_refused():
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert out.returncode == 2 and "one GPU" in out.stdout
+
+
+def test_kernel_name_follows_the_schedule():
+    b = load_bench()
+
+    class A:
+        pass
+    a = A()
+    a.rv_lanes, a.tile_nnz, a.max_row_nnz = 0, 1024, 7
+    assert b.kernel_name(a) == "k_spmv_short<1, 4>"
+    a.max_row_nnz = 100
+    assert b.kernel_name(a) == "k_spmv<1, 4>"
+    a.rv_lanes = 8
+    assert b.kernel_name(a) == "k_spmv_rv<1, 8>"
+
+
+def test_traffic_summary_is_used_only_while_sources_match(tmp_path, monkeypatch):
+    b = load_bench()
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    for rel in b.KERNEL_SOURCES:
+        dst = tmp_path / rel
+        dst.parent.mkdir(parents=True, exist_ok=True)
+        dst.write_bytes(open(os.path.join(ROOT, rel), "rb").read())
+    monkeypatch.setattr(b, "ROOT", str(tmp_path))
+    digest = b.source_digest()
+    text = ("- kernel: `k_spmv_short<1, 4>`\n- workload: `w`\n"
+            f"- source_digest: `{digest}`\n- hbm_bytes_per_launch: `123456`\n")
+    (prof / "traffic_spmv_s1_diffusion3d_128.md").write_text(text)
+    assert b.measured_traffic("k_spmv_short<1, 4>", "w") == 123456
+    assert b.measured_traffic("k_spmv<1, 4>", "w") is None      # another kernel
+    assert b.measured_traffic("k_spmv_short<1, 4>", "v") is None  # another workload
+    (tmp_path / b.KERNEL_SOURCES[0]).write_text("// changed\n")
+    assert b.measured_traffic("k_spmv_short<1, 4>", "w") is None  # kernel changed since
