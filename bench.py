@@ -57,6 +57,8 @@ def kernel_name(A):
         return f"k_spmv_rv<1, {A.rv_lanes}>"
     e = A.tile_nnz // 256
     if A.max_row_nnz <= 24:
+        if A.tile_nnz == 1024 and A.nnz >= 1024:
+            return "k_spmv_ring<1>"
         return f"k_spmv_short<1, {e}>"
     return f"k_spmv<1, {e}>"
 

@@ -24,8 +24,12 @@
 //   * phase 3: longer rows staged in LDS are summed by one wave each;
 //   * phase 4: a row that runs more than kExtra past the tile is summed by the
 //     whole workgroup, reading the rest from memory.
-// Every sum has a fixed order, so results are bit-reproducible and identical
-// whether a matrix runs alone or next to others.
+// Matrices whose rows all hold at most kShortRow non-zeros (stencils) use a
+// lean variant without the row machinery of phases 3-4 (k_spmv_short) and,
+// in 1024-non-zero tiles, a ring schedule in which one producer wave streams
+// the planes into LDS for three consumer waves (k_spmv_ring).  Every sum has
+// a fixed order, so results are bit-reproducible and identical whether a
+// matrix runs alone or next to others.
 #include "decode.h"
 #include "gse_internal.h"
 
@@ -562,9 +566,283 @@ __global__ __launch_bounds__(kWG) void k_spmv_short(SpmvOperand A, const double*
   }
 }
 
+// ---------------------------------------------------------------------------
+// Ring schedule for short rows (no row longer than kShortRow), 1024-non-zero
+// tiles.  A workgroup is one producer wave and three consumer waves.  The
+// producer copies the plane bytes of the coming tiles (with the look-ahead)
+// and their row pointers straight into an LDS ring of D stages with
+// global_load_lds -- no registers, no decode -- and keeps D-1 tiles in
+// flight.  The consumers decode each non-zero from the ring, gather x and
+// sum their row in row order.  Vector-memory loads complete in issue order
+// within a wave, so a wave that both prefetches planes and gathers x must
+// wait for its prefetch whenever it waits for a gather; here the producer
+// issues nothing but ring loads (the tile table is read through scalar
+// loads) and its waits count exactly its own stages, while the consumers'
+// gathers never queue behind plane loads.  Two barriers per tile: A (the
+// stage has landed) and B (the stage has been consumed); the producer
+// refills the stage consumed in the previous tile between A and B.
+typedef __attribute__((address_space(3))) char lds_char;
+typedef __attribute__((address_space(3))) void lds_void;
+
+constexpr int kRingTile = 1024;          // non-zeros per tile (the plan's tile_nnz)
+constexpr int kRingConsumers = 3 * 64;   // consumer threads
+constexpr int kRingThreads = kRingConsumers + 64;
+
+template <int FMT>
+struct RingLayout {
+  static constexpr int T = kRingTile;
+  static constexpr int TL = T + kLook;      // staged non-zeros per tile
+  static constexpr int RP = 320;            // row pointers staged per tile
+  static constexpr int D = (FMT == 1 || FMT == 2) ? 4 : 3;
+  static constexpr int OFF_COL = 0;
+  static constexpr int OFF_HEAD = TL * 4;
+  static constexpr int OFF_T1 = OFF_HEAD + TL * 2;
+  static constexpr int OFF_T2 = OFF_T1 + TL * 2;
+  static constexpr int OFF_VAL = TL * 4;
+  static constexpr int END = (FMT == kCsr64) ? OFF_VAL + TL * 8
+                             : (FMT == 1)    ? OFF_HEAD + TL * 2
+                             : (FMT == 2)    ? OFF_T1 + TL * 2
+                                             : OFF_T2 + TL * 4;
+  static constexpr int OFF_RPS = END;
+  static constexpr int STAGE = (OFF_RPS + RP * 4 + 15) / 16 * 16;
+  // load instructions the producer issues per stage (64 lanes x 16 bytes,
+  // 64 x 4 bytes for row pointers)
+  static constexpr int NCOL = (TL * 4 / 16 + 63) / 64;
+  static constexpr int NHALF = (TL * 2 / 16 + 63) / 64;
+  static constexpr int NVAL = (TL * 8 / 16 + 63) / 64;
+  static constexpr int NRPS = RP / 64;
+  static constexpr int NI = NCOL + NRPS + ((FMT == kCsr64) ? NVAL
+                                           : (FMT == 1)    ? NHALF
+                                           : (FMT == 2)    ? 2 * NHALF
+                                                           : 2 * NHALF + NCOL);
+  // bytes the last load of a region writes past its end (into the next one)
+  static constexpr int SPILL_COL = NCOL * 1024 - TL * 4;
+  static constexpr int SPILL_HALF = NHALF * 1024 - TL * 2;
+  static constexpr int SPILL_VAL = NVAL * 1024 - TL * 8;
+  static_assert(kLook % 8 == 0 && RP % 64 == 0, "chunking");
+  static_assert(SPILL_COL <= TL * 2 && SPILL_COL <= RP * 4 && SPILL_HALF <= RP * 4 &&
+                    SPILL_HALF <= TL * 2 && SPILL_VAL <= RP * 4,
+                "a region's spill must stay inside the region loaded after it");
+  static_assert((D - 1) * NI < 64, "the vector-memory counter holds at most 63");
+};
+
+// s_waitcnt vmcnt(N), leaving the other counters alone (gfx9 encoding).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | 0x70 | 0xF00);
+}
+
+// The producer's stage k has landed once at most `later` stages issued
+// after it are still outstanding.
+template <int FMT>
+__device__ __forceinline__ void ring_wait(int later) {
+  constexpr int NI = RingLayout<FMT>::NI;
+  switch (later) {
+    case 0: wait_vmcnt<0>(); break;
+    case 1: wait_vmcnt<NI>(); break;
+    default: wait_vmcnt<2 * NI>(); break;
+  }
+}
+
+// Barrier of the producer: its own LDS writes (stage headers) are complete,
+// its ring loads stay in flight (a workgroup fence here would wait for them).
+__device__ __forceinline__ void producer_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Barrier of the consumers: LDS accesses ordered, nothing else waited for.
+__device__ __forceinline__ void consumer_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Producer: planes of tile t (non-zeros t*T .. t*T+TL-1) and row pointers
+// ra .. ra+RP-1 into `stage`.  Lane l of load i moves 16-byte chunk 64i+l
+// to region + 1024i + 16l.  Every lane of every load takes part (no branch
+// around a load: the LDS address of a load is one per wave, so loads must
+// not sit in divergent code); the chunks past a region's end land at the
+// start of the next region, which is loaded later by the same wave and so
+// overwritten (loads of one wave complete in issue order), and the row
+// pointers, loaded last, fill their region exactly.  Chunk addresses are
+// clamped into the padded planes (pad is a multiple of 16, so a chunk is
+// either inside or wholly past it) and row indices to n_rows; clamped data
+// lands in slots that are never read.
+template <int FMT>
+__device__ __forceinline__ void ring_issue(const SpmvOperand& A, lds_char* stage, int t, int ra,
+                                           int pad, int lane) {
+  using L = RingLayout<FMT>;
+  const int j0 = t * L::T;
+#pragma unroll
+  for (int i = 0; i < L::NCOL; ++i) {
+    const int e = min(j0 + 4 * (i * 64 + lane), pad - 4);
+    __builtin_amdgcn_global_load_lds(A.col + e, (lds_void*)(stage + L::OFF_COL + i * 1024), 16, 0, 0);
+  }
+  if constexpr (FMT == kCsr64) {
+#pragma unroll
+    for (int i = 0; i < L::NVAL; ++i) {
+      const int e = min(j0 + 2 * (i * 64 + lane), pad - 2);
+      __builtin_amdgcn_global_load_lds(A.val + e, (lds_void*)(stage + L::OFF_VAL + i * 1024), 16, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < L::NHALF; ++i) {
+      const int e = min(j0 + 8 * (i * 64 + lane), pad - 8);
+      __builtin_amdgcn_global_load_lds(A.head + e, (lds_void*)(stage + L::OFF_HEAD + i * 1024), 16, 0, 0);
+    }
+    if constexpr (FMT >= 2) {
+#pragma unroll
+      for (int i = 0; i < L::NHALF; ++i) {
+        const int e = min(j0 + 8 * (i * 64 + lane), pad - 8);
+        __builtin_amdgcn_global_load_lds(A.tail1 + e, (lds_void*)(stage + L::OFF_T1 + i * 1024), 16, 0, 0);
+      }
+    }
+    if constexpr (FMT == 3) {
+#pragma unroll
+      for (int i = 0; i < L::NCOL; ++i) {
+        const int e = min(j0 + 4 * (i * 64 + lane), pad - 4);
+        __builtin_amdgcn_global_load_lds(A.tail2 + e, (lds_void*)(stage + L::OFF_T2 + i * 1024), 16, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < L::NRPS; ++i) {
+    const int r = min(ra + i * 64 + lane, A.n_rows);
+    __builtin_amdgcn_global_load_lds(A.row_ptr + r, (lds_void*)(stage + L::OFF_RPS + i * 256), 4, 0, 0);
+  }
+}
+
+// Consumer: the decoded value and column of staged non-zero `pos`.
+template <int FMT>
+__device__ __forceinline__ double ring_value(const lds_char* stage, int pos, const double* scale,
+                                             int& column) {
+  using L = RingLayout<FMT>;
+  typedef const __attribute__((address_space(3))) uint32_t* u32p;
+  typedef const __attribute__((address_space(3))) uint16_t* u16p;
+  const uint32_t c = *reinterpret_cast<u32p>(stage + L::OFF_COL + 4 * pos);
+  uint32_t h = 0, t1 = 0, t2 = 0;
+  double v = 0.0;
+  if constexpr (FMT == kCsr64) {
+    v = *reinterpret_cast<const __attribute__((address_space(3))) double*>(stage + L::OFF_VAL + 8 * pos);
+  } else {
+    h = *reinterpret_cast<u16p>(stage + L::OFF_HEAD + 2 * pos);
+    if constexpr (FMT >= 2) t1 = *reinterpret_cast<u16p>(stage + L::OFF_T1 + 2 * pos);
+    if constexpr (FMT == 3) t2 = *reinterpret_cast<u32p>(stage + L::OFF_T2 + 4 * pos);
+  }
+  return decode<FMT>(c, h, t1, t2, v, scale, column);
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kRingThreads) void k_spmv_ring(SpmvOperand A,
+                                                            const double* __restrict__ x,
+                                                            double* __restrict__ y, SpmvEpilogue ep) {
+  using L = RingLayout<FMT>;
+  constexpr int PRODUCER = kRingConsumers / 64;  // wave index of the producer
+  __shared__ __attribute__((aligned(16))) char ring_raw[L::D * L::STAGE];
+  __shared__ int hdr[L::D][4];  // per stage: first row, row end, first non-zero
+  __shared__ double scale[16];
+  __shared__ double red[kRingThreads / 64];
+  lds_char* ring = (lds_char*)ring_raw;
+
+  if (ep.gate && *ep.gate) return;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  build_scale<FMT>(A.sem, scale);
+  const int pad = (A.nnz + 15) & ~15;
+  TileWalk walk(A.n_tiles);
+  const int count = walk.t < walk.end ? (walk.end - walk.t + walk.step - 1) / walk.step : 0;
+  double acc = 0.0;
+  __syncthreads();
+  if (wave == PRODUCER) {
+    // scalar loads of the tile table (constant address space): the wave's
+    // vector-memory counter holds ring loads only
+    const __attribute__((address_space(4))) int32_t* trow =
+        (const __attribute__((address_space(4))) int32_t*)(A.tile_row);
+    auto issue = [&](int k) {
+      const int t = walk.t + k * walk.step;
+      const int ra = trow[t];
+      const int rb = trow[t + 1];
+      const int st = k % L::D;
+      ring_issue<FMT>(A, ring + st * L::STAGE, t, ra, pad, lane);
+      if (lane == 0) {
+        hdr[st][0] = ra;
+        hdr[st][1] = rb;
+        hdr[st][2] = t * L::T;
+      }
+    };
+    for (int k = 0; k < L::D - 1 && k < count; ++k) issue(k);
+    for (int k = 0; k < count; ++k) {
+      ring_wait<FMT>(min(L::D - 2, count - 1 - k));
+      producer_barrier();  // A
+      if (k + L::D - 1 < count) issue(k + L::D - 1);  // the stage consumed in tile k-1
+      producer_barrier();  // B
+    }
+  } else {
+    for (int k = 0; k < count; ++k) {
+      consumer_barrier();  // A
+      const int st = k % L::D;
+      const lds_char* stage = ring + st * L::STAGE;
+      const int ra = hdr[st][0], rb = hdr[st][1], j0 = hdr[st][2];
+      const int nst = min(rb - ra, L::RP - 1);
+      const __attribute__((address_space(3))) int* rps =
+          reinterpret_cast<const __attribute__((address_space(3))) int*>(stage + L::OFF_RPS);
+      for (int r = ra + tid; r < rb; r += kRingConsumers) {
+        const int s0 = (r - ra <= nst) ? rps[r - ra] : A.row_ptr[r];
+        const int s1 = (r + 1 - ra <= nst) ? rps[r + 1 - ra] : A.row_ptr[r + 1];
+        const int o = s0 - j0;
+        const int len = s1 - s0;
+        double sum = 0.0;
+        for (int kb = 0; kb < len; kb += 8) {
+          double v[8], xv[8];
+          int c[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            int col;
+            v[q] = ring_value<FMT>(stage, o + kb + q, scale, col);
+            c[q] = (kb + q < len) ? col : 0;
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) xv[q] = x[c[q]];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const double p = __dmul_rn(v[q], xv[q]);
+            sum = (kb + q < len) ? __dadd_rn(sum, p) : sum;
+          }
+        }
+        if (ep.epi == kEpiPlain) {
+          y[r] = sum;
+        } else if (ep.epi == kEpiDot) {
+          y[r] = sum;
+          acc += ep.aux[r] * sum;
+        } else {
+          const double vres = ep.aux[r] - sum;
+          y[r] = vres;
+          acc += vres * vres;
+        }
+      }
+      consumer_barrier();  // B
+    }
+  }
+  if (ep.epi != kEpiPlain) {
+    const double w = wave_sum(acc);
+    __syncthreads();
+    if (lane == 0) red[wave] = w;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < kRingThreads / 64; ++i) t += red[i];
+      ep.partials[blockIdx.x] = t;
+    }
+  }
+}
+
 // Resident workgroups of one kernel instance on this device (occupancy x
 // compute units), cached per instance.
-template <int FMT, int E, bool SHORT>
+enum Kind : int { kGeneralTiles = 0, kShortTiles = 1, kRingTiles = 2 };
+
+template <int FMT, int E, int KIND>
 int resident_groups() {
   static int cached = 0;
   if (cached == 0) {
@@ -572,46 +850,61 @@ int resident_groups() {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return 0;
-    hipError_t e = SHORT ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv_short<FMT, E>, kWG, 0)
-                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv<FMT, E>, kWG, 0);
+    hipError_t e;
+    if constexpr (KIND == kRingTiles)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv_ring<FMT>, kRingThreads, 0);
+    else if constexpr (KIND == kShortTiles)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv_short<FMT, E>, kWG, 0);
+    else
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv<FMT, E>, kWG, 0);
     if (e != hipSuccess) return 0;
     cached = cus * (per_cu > 0 ? per_cu : 1);
   }
   return cached;
 }
 
-// The smallest resident count over the four formats: launches that leave
-// per-workgroup partial sums use it, so the partials of a dot product are
-// grouped the same way whatever the segment count (an operator that is exact
-// at one segment then gives FP64-identical solver iterates).
-template <int E, bool SHORT>
-int common_groups() {
-  const int a = resident_groups<0, E, SHORT>(), b = resident_groups<1, E, SHORT>();
-  const int c = resident_groups<2, E, SHORT>(), d = resident_groups<3, E, SHORT>();
-  int m = a < b ? a : b;
-  m = m < c ? m : c;
-  return m < d ? m : d;
+// Resident workgroups of the chosen kernel, at most what the tiles need and
+// at least one per XCD range.  Every format runs at its own best occupancy,
+// so launches that leave per-workgroup partial sums group them per format:
+// results are bit-reproducible for a given format and matrix, and two
+// formats that decode to the same values agree to rounding.
+template <int FMT, int E, int KIND>
+int grid_for(const SpmvOperand& A) {
+  int g = resident_groups<FMT, E, KIND>();
+  if (g <= 0) return 0;
+  const int need = (A.n_tiles + 7) / 8 * 8;
+  if (g > need) g = need;
+  if (g < 8) g = 8;
+  return g;
 }
 
+// Schedule for one tile size: the ring for short rows in 1024-non-zero
+// tiles, else the lean short-row tiles, else the general tiles.
 template <int FMT, int E>
 hipError_t launch_fe(const SpmvOperand& A, const double* x, double* y, const SpmvEpilogue& ep,
                      hipStream_t st) {
   const bool short_rows = A.max_row <= kShortRow;
-  int g;
-  if (ep.epi != kEpiPlain)
-    g = short_rows ? common_groups<E, true>() : common_groups<E, false>();
-  else
-    g = short_rows ? resident_groups<FMT, E, true>() : resident_groups<FMT, E, false>();
-  if (g <= 0) return hipErrorInvalidDevice;
-  // at least one workgroup per XCD range, no more than the tiles need
-  const int need = (A.n_tiles + 7) / 8 * 8;
-  if (g > need) g = need;
-  if (g < 8) g = 8;
-  if (ep.grid_out) *ep.grid_out = g;
-  if (short_rows)
+  int g = 0;
+  if constexpr (E * kWG == kRingTile) {
+    if (short_rows && A.nnz >= kRingTile) {
+      g = grid_for<FMT, E, kRingTiles>(A);
+      if (g <= 0) return hipErrorInvalidDevice;
+      if (ep.grid_out) *ep.grid_out = g;
+      hipLaunchKernelGGL((k_spmv_ring<FMT>), dim3(g), dim3(kRingThreads), 0, st, A, x, y, ep);
+      return hipGetLastError();
+    }
+  }
+  if (short_rows) {
+    g = grid_for<FMT, E, kShortTiles>(A);
+    if (g <= 0) return hipErrorInvalidDevice;
+    if (ep.grid_out) *ep.grid_out = g;
     hipLaunchKernelGGL((k_spmv_short<FMT, E>), dim3(g), dim3(kWG), 0, st, A, x, y, ep);
-  else
+  } else {
+    g = grid_for<FMT, E, kGeneralTiles>(A);
+    if (g <= 0) return hipErrorInvalidDevice;
+    if (ep.grid_out) *ep.grid_out = g;
     hipLaunchKernelGGL((k_spmv<FMT, E>), dim3(g), dim3(kWG), 0, st, A, x, y, ep);
+  }
   return hipGetLastError();
 }
 

@@ -27,9 +27,13 @@ def test_kernel_name_follows_the_schedule():
     class A:
         pass
     a = A()
-    a.rv_lanes, a.tile_nnz, a.max_row_nnz = 0, 1024, 7
+    a.rv_lanes, a.tile_nnz, a.max_row_nnz, a.nnz = 0, 1024, 7, 5000
+    assert b.kernel_name(a) == "k_spmv_ring<1>"
+    a.nnz = 900
     assert b.kernel_name(a) == "k_spmv_short<1, 4>"
-    a.max_row_nnz = 100
+    a.tile_nnz = 2048
+    assert b.kernel_name(a) == "k_spmv_short<1, 8>"
+    a.tile_nnz, a.max_row_nnz = 1024, 100
     assert b.kernel_name(a) == "k_spmv<1, 4>"
     a.rv_lanes = 8
     assert b.kernel_name(a) == "k_spmv_rv<1, 8>"

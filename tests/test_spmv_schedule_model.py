@@ -166,3 +166,89 @@ def test_short_row_kernel_in_bounds(name, E):
 def test_short_row_kernel_full_size_diffusion3d_128():
     A = diffusion3d(128, 0)
     check_short(A.indptr.astype(np.int64), A.n_cols, A.indices, 4)
+
+
+# ---- ring schedule (producer wave + LDS ring), short rows, 1024-nnz tiles ----
+RING_T, RING_LOOK, RING_RP, RING_CONS = 1024, 32, 320, 192
+
+
+def ring_layout(fmt):
+    TL = RING_T + RING_LOOK
+    D = 4 if fmt in (1, 2) else 3
+    off_head = TL * 4
+    off_t1 = off_head + TL * 2
+    off_t2 = off_t1 + TL * 2
+    off_val = TL * 4
+    end = {0: off_val + TL * 8, 1: off_head + TL * 2, 2: off_t1 + TL * 2, 3: off_t2 + TL * 4}[fmt]
+    stage = (end + RING_RP * 4 + 15) // 16 * 16
+    # regions in the order the producer loads them: (name, offset, bytes,
+    # elements per 16-byte chunk)
+    order = [("col", 0, TL * 4, 4)]
+    if fmt == 0:
+        order.append(("val", off_val, TL * 8, 2))
+    else:
+        order.append(("head", off_head, TL * 2, 8))
+        if fmt >= 2:
+            order.append(("tail1", off_t1, TL * 2, 8))
+        if fmt == 3:
+            order.append(("tail2", off_t2, TL * 4, 4))
+    loads = [(name, off, size, per, -(-size // 1024)) for name, off, size, per in order]
+    ni = sum(n for *_, n in loads) + RING_RP // 64
+    return dict(TL=TL, D=D, stage=stage, ni=ni, loads=loads, rps=end)
+
+
+def check_ring(indptr, n_cols, cols, fmt):
+    L = ring_layout(fmt)
+    TL, T = L["TL"], RING_T
+    n_rows = indptr.size - 1
+    nnz = int(indptr[-1])
+    assert nnz >= T  # the launcher's condition
+    pad = (nnz + 15) // 16 * 16
+    n_tiles = -(-nnz // T)
+    # the producer's waits stay inside the 6-bit counter
+    assert (L["D"] - 1) * L["ni"] < 64
+    # every lane of every load writes 16 bytes at region + 1024 i + 16 l: the
+    # bytes past a region's end land in the region loaded next (overwritten
+    # later by the same wave); the row pointers, loaded last, fit exactly
+    regions = L["loads"] + [("rps", L["rps"], RING_RP * 4, None, RING_RP // 64)]
+    for k, (name, off, size, per, n) in enumerate(L["loads"]):
+        spill_end = off + n * 1024
+        nxt = regions[k + 1]
+        assert nxt[1] == off + size, "regions are contiguous in load order"
+        assert spill_end <= nxt[1] + nxt[2], name
+    assert L["rps"] + (RING_RP // 64) * 256 == L["rps"] + RING_RP * 4 <= L["stage"]
+    tile_row = [lower_bound(indptr[:n_rows], t * T) for t in range(n_tiles)] + [n_rows]
+    for t in range(n_tiles):
+        j0 = t * T
+        ra, rb = tile_row[t], tile_row[t + 1]
+        if t < 1 or t >= n_tiles - 2:  # only the first and the last tiles clamp
+            for name, off, size, per, n in L["loads"]:
+                for c in range(n * 64):
+                    e = min(j0 + per * c, pad - per)
+                    assert 0 <= e and e + per <= pad
+            for i in range(RING_RP):
+                assert 0 <= min(ra + i, n_rows) <= n_rows
+        # consumers: staged positions read by each row (eight-wide batches)
+        if rb > ra:
+            s0 = indptr[ra:rb]
+            ln = indptr[ra + 1:rb + 1] - s0
+            o = s0 - j0
+            assert o.min() >= 0 and o.max() < T and (o + ln).max() <= TL
+            assert (o + (np.maximum(ln, 1) - 1) // 8 * 8 + 7).max() < TL
+    assert int(cols.max(initial=0)) < n_cols
+    assert L["D"] * L["stage"] <= 64 * 1024
+
+
+@pytest.mark.parametrize("fmt", [0, 1, 2, 3])
+@pytest.mark.parametrize("name", ["poisson2d_64", "diffusion3d_24", "convdiff2d_64", "random_ragged"])
+def test_ring_kernel_in_bounds(name, fmt):
+    A = MATS[name]()
+    if np.diff(A.indptr).max(initial=0) > SHORT or A.indptr[-1] < RING_T:
+        pytest.skip("the ring serves short rows in at least one full tile")
+    check_ring(A.indptr.astype(np.int64), A.n_cols, A.indices, fmt)
+
+
+def test_ring_kernel_full_size_diffusion3d_128():
+    A = diffusion3d(128, 0)
+    for fmt in (0, 1, 2, 3):
+        check_ring(A.indptr.astype(np.int64), A.n_cols, A.indices, fmt)
