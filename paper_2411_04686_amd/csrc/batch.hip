@@ -219,37 +219,42 @@ __global__ __launch_bounds__(kWG) void k_b_spmv(BatchView v, int mode) {
   }
 }
 
-// alpha = rho / p.q per running system (one workgroup per system); always
-// disarms the x/p update of the previous iteration.
-__global__ __launch_bounds__(kWG) void k_b_alpha(BatchView v) {
-  __shared__ double red[kWaves];
-  const int n = v.list.counts[2];
-  for (int k = blockIdx.x; k < n; k += gridDim.x) {
-    const SlotItem si = v.list.slots[k];
-    SolverState* S = v.S + si.slot;
-    const int stop = S->stop;
-    if (threadIdx.x == 0) S->k3_armed = 0;
-    if (stop) continue;
-    const double pq = sum_partials(v.part + si.part, v.slot[si.slot].n_tiles, red);
-    if (threadIdx.x == 0) {
-      S->pq = pq;
-      if (!(pq > 0.0) || !isfinite(pq)) S->stop = kBreak;
-      else S->alpha = S->rho / pq;
-    }
-    __syncthreads();
-  }
-}
+// The scalar steps of an iteration run inside the vector kernels, as in the
+// single-system solver: every workgroup that works on a system sums that
+// system's partials (a few per system) in a fixed order, and the workgroup
+// on the system's chunk 0 publishes the scalars.  Fields a kernel reads are
+// never written by another workgroup of that kernel (rho alternates between
+// two slots by iteration parity).  A chunk item carries its system's first
+// tile partial in `pad` and its own chunk partial in `part` (a system's
+// chunk partials are consecutive, so they start at part - idx).
 
-// r -= alpha q and the partials of r.r, per row chunk.
-__global__ __launch_bounds__(kWG) void k_b_rupdate(BatchView v) {
+// alpha = rho / p.q; r -= alpha q and the partials of r.r, per row chunk.
+__global__ __launch_bounds__(kWG) void k_b_rstep(BatchView v) {
   __shared__ double red[kWaves];
   const int n = v.list.counts[1];
   for (Walk w = walk_of(n); w.i < w.end; w.i += w.step) {
     const WorkItem it = v.list.chunks[w.i];
-    const SolverState* S = v.S + it.slot;
-    if (S->stop) continue;
+    SolverState* S = v.S + it.slot;
+    const int stop = S->stop;
+    if (it.idx == 0 && threadIdx.x == 0) S->go = 0;
+    if (stop) continue;
     const BatchSlot& B = v.slot[it.slot];
-    const double alpha = S->alpha;
+    const int j = S->it;
+    const double rho = S->rho_p[j & 1];
+    const double pq = sum_partials(v.part + it.pad, B.n_tiles, red);
+    const bool broke = !(pq > 0.0) || !isfinite(pq);
+    const double alpha = rho / pq;
+    if (it.idx == 0 && threadIdx.x == 0) {
+      S->pq = pq;
+      if (broke) {
+        S->stop = kBreak;
+      } else {
+        S->alpha = alpha;
+        S->go = 1;
+        S->it_next = j + 1;
+      }
+    }
+    if (broke) continue;
     const int lo = it.idx * kChunk;
     const int hi = min(B.n_rows, lo + kChunk);
     double* __restrict__ r = B.r;
@@ -265,48 +270,22 @@ __global__ __launch_bounds__(kWG) void k_b_rupdate(BatchView v) {
   }
 }
 
-// rho' = r.r: beta, the history, the controller (one workgroup per system).
-__global__ __launch_bounds__(kWG) void k_b_advance(BatchView v) {
+// beta = rho' / rho; x += alpha p, p = r + beta p per row chunk; on chunk 0
+// the history, the iteration count and the controller.
+__global__ __launch_bounds__(kWG) void k_b_xstep(BatchView v) {
   __shared__ double red[kWaves];
-  __shared__ int bc_j, bc_s;
   __shared__ double bc_rel;
-  const int n = v.list.counts[2];
-  for (int k = blockIdx.x; k < n; k += gridDim.x) {
-    const SlotItem si = v.list.slots[k];
-    SolverState* S = v.S + si.slot;
-    if (S->stop) continue;
-    const BatchSlot& B = v.slot[si.slot];
-    const double rho_new = sum_partials(v.part2 + si.vpart, B.n_chunks, red);
-    if (threadIdx.x == 0) {
-      const int j = S->it + 1;
-      const double rel = sqrt(rho_new) / S->nb;
-      S->beta = rho_new / S->rho;
-      S->rho = rho_new;
-      S->it = j;
-      S->relres = rel;
-      B.hist[j] = rel;
-      B.seg_hist[j] = S->s;
-      S->k3_armed = 1;
-      bc_j = j;
-      bc_s = S->s;
-      bc_rel = rel;
-    }
-    __syncthreads();
-    controller(S, B.hist, red, bc_j, bc_rel, bc_s);
-    __syncthreads();
-  }
-}
-
-// x += alpha p; p = r + beta p, per row chunk (systems whose iteration
-// completed).
-__global__ __launch_bounds__(kWG) void k_b_xpupdate(BatchView v) {
   const int n = v.list.counts[1];
   for (Walk w = walk_of(n); w.i < w.end; w.i += w.step) {
     const WorkItem it = v.list.chunks[w.i];
-    const SolverState* S = v.S + it.slot;
-    if (!S->k3_armed) continue;
+    SolverState* S = v.S + it.slot;
+    if (!S->go) continue;
     const BatchSlot& B = v.slot[it.slot];
-    const double alpha = S->alpha, beta = S->beta;
+    const int j = S->it_next;
+    const double rho_old = S->rho_p[(j - 1) & 1];
+    const double alpha = S->alpha;
+    const double rho_new = sum_partials(v.part2 + (it.part - it.idx), B.n_chunks, red);
+    const double beta = rho_new / rho_old;
     const int lo = it.idx * kChunk;
     const int hi = min(B.n_rows, lo + kChunk);
     double* __restrict__ x = B.x;
@@ -317,6 +296,22 @@ __global__ __launch_bounds__(kWG) void k_b_xpupdate(BatchView v) {
       x[i] += alpha * pv;
       p[i] = r[i] + beta * pv;
     }
+    if (it.idx != 0) continue;
+    const int s = S->s;
+    if (threadIdx.x == 0) {
+      const double rel = sqrt(rho_new) / S->nb;
+      S->beta = beta;
+      S->rho_p[j & 1] = rho_new;
+      S->rho = rho_new;
+      S->it = j;
+      S->relres = rel;
+      B.hist[j] = rel;
+      B.seg_hist[j] = s;
+      bc_rel = rel;
+    }
+    __syncthreads();
+    controller(S, B.hist, red, j, bc_rel, s);
+    __syncthreads();
   }
 }
 
@@ -355,13 +350,17 @@ __global__ __launch_bounds__(kWG) void k_b_act_finish(BatchView v) {
         S->nb2 = nb2;
         S->nb = nb;
         S->rho = rho;
+        S->rho_p[S->it & 1] = rho;
         S->relres = rel;
         B.hist[0] = rel;
         B.seg_hist[0] = S->s;
       }
     } else if (a == kActReplace || a == kActReplaceP) {
       const double rho = sum_partials(v.part + si.part, B.n_tiles, red);
-      if (threadIdx.x == 0) S->rho = rho;
+      if (threadIdx.x == 0) {
+        S->rho = rho;
+        S->rho_p[S->it & 1] = rho;
+      }
     } else if (a == kActCheck) {
       const double ww = sum_partials(v.part + si.part, B.n_tiles, red);
       if (threadIdx.x == 0) S->scratch[0] = ww;
@@ -468,7 +467,7 @@ gse_status BatchEngine::init(void* region, size_t bytes, int cap_slots, int64_t 
   hhdr_ = RegionHeader{kMagic, cap_slots, 0, (int64_t)((char*)slots_ - p),
                        (int64_t)((char*)S_ - p)};
   grid_spmv_ = grid_for(k_b_spmv, cap_tiles);
-  grid_vec_ = grid_for(k_b_rupdate, cap_chunks);
+  grid_vec_ = grid_for(k_b_rstep, cap_chunks);
   grid_slot_ = cap_slots < 1024 ? cap_slots : 1024;
   if (grid_spmv_ <= 0 || grid_vec_ <= 0) return fail(GSE_ERR_HIP, "batch: device query failed");
   hipError_t e = hipMemcpyAsync(hdr, &hhdr_, sizeof hhdr_, hipMemcpyHostToDevice, st_);
@@ -565,7 +564,7 @@ gse_status BatchEngine::upload_list(int l, const std::vector<int>& ids) {
     const BatchSlot& B = hslot_[id];
     wsl.push_back(SlotItem{id, (int32_t)pt, (int32_t)pc, 0});
     for (int t = 0; t < B.n_tiles; ++t) wt.push_back(WorkItem{id, t, (int32_t)(pt + t), 0});
-    for (int c = 0; c < B.n_chunks; ++c) wc.push_back(WorkItem{id, c, (int32_t)(pc + c), 0});
+    for (int c = 0; c < B.n_chunks; ++c) wc.push_back(WorkItem{id, c, (int32_t)(pc + c), (int32_t)pt});
     pt += B.n_tiles;
     pc += B.n_chunks;
   }
@@ -607,10 +606,8 @@ hipError_t BatchEngine::launch_epoch_kernels(int iters) {
   const BatchView v = view(0);
   for (int k = 0; k < iters; ++k) {
     hipLaunchKernelGGL(k_b_spmv, dim3(grid_spmv_), dim3(kWG), 0, st_, v, 0);
-    hipLaunchKernelGGL(k_b_alpha, dim3(grid_slot_), dim3(kWG), 0, st_, v);
-    hipLaunchKernelGGL(k_b_rupdate, dim3(grid_vec_), dim3(kWG), 0, st_, v);
-    hipLaunchKernelGGL(k_b_advance, dim3(grid_slot_), dim3(kWG), 0, st_, v);
-    hipLaunchKernelGGL(k_b_xpupdate, dim3(grid_vec_), dim3(kWG), 0, st_, v);
+    hipLaunchKernelGGL(k_b_rstep, dim3(grid_vec_), dim3(kWG), 0, st_, v);
+    hipLaunchKernelGGL(k_b_xstep, dim3(grid_vec_), dim3(kWG), 0, st_, v);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -632,7 +629,7 @@ void BatchEngine::resume(int id) {
   SolverState& S = hS_[id];
   S.stop = kRun;
   S.trig = 0;
-  S.k3_armed = 0;
+  S.go = 0;
   meta_[id].phase = kPhRun;
   run_dirty_ = true;
 }

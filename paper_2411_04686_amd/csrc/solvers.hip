@@ -29,14 +29,15 @@ namespace {
 constexpr int kVecBlocks = 2048;
 
 // ------------------------------------------------------------- finisher ---
-// out[k] = sum over i < n of partials[k*stride + i], k < nk, in a fixed order
-// (one workgroup; the partials were written by the previous kernel).
+// out[k] = sum over i < n of partials[k*stride + i], k < nk, each sum in a
+// fixed order by one workgroup (workgroup b takes k = b, b + grid, ...; the
+// partials were written by the previous kernel).
 __global__ __launch_bounds__(kWG) void k_finish(const double* __restrict__ partials, int n,
                                                 int stride, int nk, double* __restrict__ out,
                                                 const int* gate) {
   __shared__ double red[kWaves];
   if (gate && *gate) return;
-  for (int k = 0; k < nk; ++k) {
+  for (int k = blockIdx.x; k < nk; k += gridDim.x) {
     const double t = sum_partials(partials + (size_t)k * stride, n, red);
     if (threadIdx.x == 0) out[k] = t;
   }
@@ -520,11 +521,35 @@ struct GmSmall {
   double* h2;
 };
 
+// partials[k * stride + block] = workgroup sum of acc[k] for k < count: the
+// same arithmetic as block_sum (wave sums, then the waves in order), with
+// one barrier for all k.
+template <int NA>
+__device__ __forceinline__ void block_sums_out(const double (&acc)[NA], int count,
+                                               double* red /* [NA * kWaves] */,
+                                               double* __restrict__ partials, int stride) {
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    if (k < count) {
+      const double v = wave_sum(acc[k]);
+      if ((threadIdx.x & 63) == 0) red[k * kWaves + w] = v;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < count) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) t += red[threadIdx.x * kWaves + i];
+    partials[(size_t)threadIdx.x * stride + blockIdx.x] = t;
+  }
+}
+
 template <int JB>
 __global__ __launch_bounds__(kWG) void k_gm_dots(const SolverState* S, const double* __restrict__ V,
                                                  const double* __restrict__ w, int n, size_t ld,
                                                  int j, double* __restrict__ partials) {
-  __shared__ double red[kWaves];
+  __shared__ double red[JB * kWaves];
   if (S->stop) return;
   double acc[JB];
 #pragma unroll
@@ -535,13 +560,7 @@ __global__ __launch_bounds__(kWG) void k_gm_dots(const SolverState* S, const dou
     for (int k = 0; k < JB; ++k)
       if (k <= j) acc[k] += V[(size_t)k * ld + i] * wi;
   }
-#pragma unroll
-  for (int k = 0; k < JB; ++k) {
-    if (k <= j) {
-      const double bs = block_sum(acc[k], red);
-      if (threadIdx.x == 0) partials[(size_t)k * gridDim.x + blockIdx.x] = bs;
-    }
-  }
+  block_sums_out(acc, j + 1, red, partials, gridDim.x);
 }
 
 // w -= V h (h finished from the previous pass); then partials of V_k . w,
@@ -551,12 +570,12 @@ __global__ __launch_bounds__(kWG) void k_gm_axpy(const SolverState* S, const dou
                                                  double* __restrict__ w, int n, size_t ld, int j,
                                                  const double* __restrict__ h,
                                                  double* __restrict__ partials) {
-  __shared__ double red[kWaves];
+  constexpr int NA = NORM ? 1 : JB;
+  __shared__ double red[NA * kWaves];
   __shared__ double hs[JB];
   if (S->stop) return;
   if (threadIdx.x < JB) hs[threadIdx.x] = (threadIdx.x <= j) ? h[threadIdx.x] : 0.0;
   __syncthreads();
-  constexpr int NA = NORM ? 1 : JB;
   double acc[NA];
 #pragma unroll
   for (int k = 0; k < NA; ++k) acc[k] = 0.0;
@@ -578,13 +597,7 @@ __global__ __launch_bounds__(kWG) void k_gm_axpy(const SolverState* S, const dou
         if (k <= j) acc[k] += v[k] * wi;
     }
   }
-#pragma unroll
-  for (int k = 0; k < NA; ++k) {
-    if (k <= j) {
-      const double bs = block_sum(acc[k], red);
-      if (threadIdx.x == 0) partials[(size_t)k * gridDim.x + blockIdx.x] = bs;
-    }
-  }
+  block_sums_out(acc, NORM ? 1 : j + 1, red, partials, gridDim.x);
 }
 
 // The Arnoldi column j is complete: H[:,j] = h1 + h2, H[j+1,j] = ||w||
@@ -788,10 +801,10 @@ gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_pa
         double* P = w.partials;
 #define GSE_GM_PASSES(JB)                                                                       \
   hipLaunchKernelGGL((k_gm_dots<JB>), dim3(gb), dim3(kWG), 0, st, w.S, V, wv, n, ld, j, P);      \
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kWG), 0, st, P, gb, gb, j + 1, h1, gate);           \
+  hipLaunchKernelGGL(k_finish, dim3(j + 1), dim3(kWG), 0, st, P, gb, gb, j + 1, h1, gate);       \
   hipLaunchKernelGGL((k_gm_axpy<JB, false>), dim3(gb), dim3(kWG), 0, st, w.S, V, wv, n, ld, j, h1, \
                      P);                                                                        \
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kWG), 0, st, P, gb, gb, j + 1, sm.h2, gate);        \
+  hipLaunchKernelGGL(k_finish, dim3(j + 1), dim3(kWG), 0, st, P, gb, gb, j + 1, sm.h2, gate);    \
   hipLaunchKernelGGL((k_gm_axpy<JB, true>), dim3(gb), dim3(kWG), 0, st, w.S, V, wv, n, ld, j,     \
                      sm.h2, P)
         if (j < 8) {
