@@ -201,6 +201,17 @@ int64_t gmres_small_entries(int32_t restart) {
   return (m + 1) * m + 4 * (m + 1) + 2 * (m + 1);
 }
 
+// Row stride of the GMRES basis in doubles: whole 8 KiB pages plus 4 KiB,
+// so that the same element of consecutive basis vectors sits an odd number
+// of 4 KiB pages apart and the j+1 streams of a Gram-Schmidt pass spread
+// over the HBM channels instead of meeting in the same ones (a power-of-two
+// stride, e.g. n = 2^20, put them all in step).
+size_t gm_ld(int32_t n_rows) {
+  const size_t n = (size_t)(n_rows > 0 ? n_rows : 1);
+  const size_t bytes = (n * sizeof(double) + 8191) / 8192 * 8192 + 4096;
+  return bytes / sizeof(double);
+}
+
 Workspace carve(void* base, int32_t method, int32_t n_rows, int64_t nnz, int32_t restart,
                 int32_t max_iter) {
   Workspace w{};
@@ -223,7 +234,8 @@ Workspace carve(void* base, int32_t method, int32_t n_rows, int64_t nnz, int32_t
   w.seg_hist = reinterpret_cast<int*>(take((size_t)(max_iter + 2) * sizeof(int)));
   if (method == GSE_GMRES) {
     w.gm = reinterpret_cast<double*>(
-        take(((size_t)(restart + 1) * n + (size_t)gmres_small_entries(restart)) * sizeof(double)));
+        take(((size_t)(restart + 1) * gm_ld(n_rows) + (size_t)gmres_small_entries(restart)) *
+             sizeof(double)));
   }
   w.bytes = off;
   return w;
@@ -511,7 +523,7 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
 //   H[:,j] = h + h2, ||w||, Givens    (k_gm_givens, one workgroup, which
 //                                      also runs the controller)
 //   v_{j+1} = w / ||w||               (k_gm_scale)
-constexpr int kGmBlocks = 1024;
+constexpr int kGmBlocks = 512;  // measured best for the 1M-row passes (fewer, longer workgroups)
 
 struct GmSmall {
   double* H;
@@ -545,6 +557,12 @@ __device__ __forceinline__ void block_sums_out(const double (&acc)[NA], int coun
   }
 }
 
+// The basis-vector loads of one element are issued unconditionally, all
+// before the arithmetic: a load guarded by `k <= j` becomes a branch whose
+// body waits for its own load, which serialises the JB loads of a lane.
+// Vectors past v_j are read as v_j again (a cache hit) and enter with a zero
+// coefficient (axpy) or a discarded accumulator (dots), so the arithmetic on
+// the real terms, and its order, is that of the guarded loop.
 template <int JB>
 __global__ __launch_bounds__(kWG) void k_gm_dots(const SolverState* S, const double* __restrict__ V,
                                                  const double* __restrict__ w, int n, size_t ld,
@@ -555,10 +573,13 @@ __global__ __launch_bounds__(kWG) void k_gm_dots(const SolverState* S, const dou
 #pragma unroll
   for (int k = 0; k < JB; ++k) acc[k] = 0.0;
   for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
-    const double wi = w[i];
+    double v[JB];
 #pragma unroll
-    for (int k = 0; k < JB; ++k)
-      if (k <= j) acc[k] += V[(size_t)k * ld + i] * wi;
+    for (int k = 0; k < JB; ++k) v[k] = V[(size_t)(k <= j ? k : j) * ld + i];
+    const double wi = w[i];
+    __builtin_amdgcn_sched_barrier(0);  // keep every load ahead of the arithmetic
+#pragma unroll
+    for (int k = 0; k < JB; ++k) acc[k] += v[k] * wi;
   }
   block_sums_out(acc, j + 1, red, partials, gridDim.x);
 }
@@ -581,20 +602,18 @@ __global__ __launch_bounds__(kWG) void k_gm_axpy(const SolverState* S, const dou
   for (int k = 0; k < NA; ++k) acc[k] = 0.0;
   for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
     double v[JB];
-    double wi = w[i];
 #pragma unroll
-    for (int k = 0; k < JB; ++k)
-      if (k <= j) {
-        v[k] = V[(size_t)k * ld + i];
-        wi -= hs[k] * v[k];
-      }
+    for (int k = 0; k < JB; ++k) v[k] = V[(size_t)(k <= j ? k : j) * ld + i];
+    double wi = w[i];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < JB; ++k) wi -= hs[k] * v[k];
     w[i] = wi;
     if constexpr (NORM) {
       acc[0] += wi * wi;
     } else {
 #pragma unroll
-      for (int k = 0; k < JB; ++k)
-        if (k <= j) acc[k] += v[k] * wi;
+      for (int k = 0; k < JB; ++k) acc[k] += v[k] * wi;
     }
   }
   block_sums_out(acc, NORM ? 1 : j + 1, red, partials, gridDim.x);
@@ -602,39 +621,49 @@ __global__ __launch_bounds__(kWG) void k_gm_axpy(const SolverState* S, const dou
 
 // The Arnoldi column j is complete: H[:,j] = h1 + h2, H[j+1,j] = ||w||
 // (from the norm partials); rotations, residual estimate, controller.
-// One workgroup.
+// One workgroup: the column and the earlier rotations are gathered into LDS
+// by all threads, the rotations run in one thread from there, and the
+// rotated column is written back by all threads.
 __global__ __launch_bounds__(kWG) void k_gm_givens(SolverState* S, GmSmall sm, int m, int j,
                                                    const double* __restrict__ h1,
                                                    const double* __restrict__ h2,
                                                    const double* __restrict__ norm_partials,
                                                    int n_partials, double* hist, int* seg_hist) {
   __shared__ double red[kWaves];
+  __shared__ double col[64], c_s[64], s_s[64];
   __shared__ int bc_j, bc_s, bc_go;
   __shared__ double bc_rel;
   if (S->stop) return;
-  const double wn2 = sum_partials(norm_partials, n_partials, red);
-  if (threadIdx.x == 0) {
-    double* Hc = sm.H;  // row-major (m+1) x m
-    for (int i = 0; i <= j; ++i) Hc[(size_t)i * m + j] = h1[i] + h2[i];
-    const double hn = sqrt(wn2);
-    Hc[(size_t)(j + 1) * m + j] = hn;
-    for (int i = 0; i < j; ++i) {
-      const double a = Hc[(size_t)i * m + j], b = Hc[(size_t)(i + 1) * m + j];
-      Hc[(size_t)i * m + j] = sm.cs[i] * a + sm.sn[i] * b;
-      Hc[(size_t)(i + 1) * m + j] = -sm.sn[i] * a + sm.cs[i] * b;
+  const int t = threadIdx.x;
+  if (t <= j) {
+    col[t] = h1[t] + h2[t];
+    if (t < j) {
+      c_s[t] = sm.cs[t];
+      s_s[t] = sm.sn[t];
     }
-    const double a = Hc[(size_t)j * m + j], b = Hc[(size_t)(j + 1) * m + j];
+  }
+  const double wn2 = sum_partials(norm_partials, n_partials, red);  // has a barrier after the stores
+  if (t == 0) {
+    const double hn = sqrt(wn2);
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double a = col[i], b = col[i + 1];
+      col[i] = c_s[i] * a + s_s[i] * b;
+      col[i + 1] = -s_s[i] * a + c_s[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
     const double rr = sqrt(a * a + b * b);
     const double c = rr == 0.0 ? 1.0 : a / rr;
     const double sv = rr == 0.0 ? 0.0 : b / rr;
     sm.cs[j] = c;
     sm.sn[j] = sv;
-    Hc[(size_t)j * m + j] = c * a + sv * b;
-    Hc[(size_t)(j + 1) * m + j] = 0.0;
-    sm.g[j + 1] = -sv * sm.g[j];
-    sm.g[j] = c * sm.g[j];
+    col[j] = c * a + sv * b;
+    col[j + 1] = 0.0;
+    const double gj = sm.g[j];
+    sm.g[j + 1] = -sv * gj;
+    sm.g[j] = c * gj;
     const int it = S->it + 1;
-    const double rel = fabs(sm.g[j + 1]) / S->nb;
+    const double rel = fabs(-sv * gj) / S->nb;
     S->it = it;
     S->relres = rel;
     S->scratch[1] = hn;     // norm of the new basis vector
@@ -648,6 +677,7 @@ __global__ __launch_bounds__(kWG) void k_gm_givens(SolverState* S, GmSmall sm, i
     if (hn == 0.0) S->stop = kConv;  // exact in this space: end the cycle
   }
   __syncthreads();
+  if (t <= j + 1) sm.H[(size_t)t * m + j] = col[t];  // row-major (m+1) x m
   if (bc_go) controller(S, hist, red, bc_j, bc_rel, bc_s);
 }
 
@@ -660,23 +690,39 @@ __global__ __launch_bounds__(kWG) void k_gm_scale(SolverState* S, double* __rest
 }
 
 // y = H(1:k,1:k) \ g(1:k) (every workgroup solves the small system the same
-// way), then x += V(:,1:k) y.  k = columns completed in the cycle.
+// way), then x += V(:,1:k) y.  k = columns completed in the cycle (<= JB);
+// the loads are issued unconditionally as in the Gram-Schmidt passes, with
+// y = 0 past k.
+template <int JB>
 __global__ __launch_bounds__(kWG) void k_gm_update(const SolverState* S, GmSmall sm, int m,
                                                    const double* __restrict__ V, size_t ld,
                                                    double* __restrict__ x, int n) {
-  __shared__ double y[64];
+  __shared__ double y[JB];
+  __shared__ double Hs[JB * JB];  // the leading k x k block of H, gathered by all threads
   const int k = (int)S->scratch[2];
+  if (k <= 0) return;
+  for (int e = threadIdx.x; e < k * k; e += kWG) {
+    const int i = e / k, q = e - i * k;
+    Hs[i * JB + q] = sm.H[(size_t)i * m + q];
+  }
+  if ((int)threadIdx.x < JB) y[threadIdx.x] = (int)threadIdx.x < k ? sm.g[threadIdx.x] : 0.0;
+  __syncthreads();
   if (threadIdx.x == 0) {
     for (int i = k - 1; i >= 0; --i) {
-      double acc = sm.g[i];
-      for (int q = i + 1; q < k; ++q) acc -= sm.H[(size_t)i * m + q] * y[q];
-      y[i] = acc / sm.H[(size_t)i * m + i];
+      double acc = y[i];
+      for (int q = i + 1; q < k; ++q) acc -= Hs[i * JB + q] * y[q];
+      y[i] = acc / Hs[i * JB + i];
     }
   }
   __syncthreads();
   for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
+    double v[JB];
+#pragma unroll
+    for (int q = 0; q < JB; ++q) v[q] = V[(size_t)(q < k ? q : k - 1) * ld + i];
     double xi = x[i];
-    for (int q = 0; q < k; ++q) xi += y[q] * V[(size_t)q * ld + i];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < JB; ++q) xi += y[q] * v[q];
     x[i] = xi;
   }
 }
@@ -709,7 +755,7 @@ gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_pa
   rep->switch_iter[0] = rep->switch_iter[1] = -1;
   const bool stepped = A.fmt != 0 && p->fixed_segments == 0;
   const int s_final = (A.fmt == 0) ? 0 : 3;
-  const size_t ld = (size_t)(n > 0 ? n : 1);
+  const size_t ld = gm_ld(n);
   double* V = w.gm;
   GmSmall sm;
   sm.H = V + (size_t)(m + 1) * ld;
@@ -807,14 +853,23 @@ gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_pa
   hipLaunchKernelGGL(k_finish, dim3(j + 1), dim3(kWG), 0, st, P, gb, gb, j + 1, sm.h2, gate);    \
   hipLaunchKernelGGL((k_gm_axpy<JB, true>), dim3(gb), dim3(kWG), 0, st, w.S, V, wv, n, ld, j,     \
                      sm.h2, P)
-        if (j < 8) {
-          GSE_GM_PASSES(8);
-        } else if (j < 16) {
-          GSE_GM_PASSES(16);
-        } else if (j < 32) {
-          GSE_GM_PASSES(32);
-        } else {
-          GSE_GM_PASSES(64);
+        // vector count rounded up to a multiple of 4 (m <= 60)
+        switch ((j + 4) >> 2) {
+          case 1: GSE_GM_PASSES(4); break;
+          case 2: GSE_GM_PASSES(8); break;
+          case 3: GSE_GM_PASSES(12); break;
+          case 4: GSE_GM_PASSES(16); break;
+          case 5: GSE_GM_PASSES(20); break;
+          case 6: GSE_GM_PASSES(24); break;
+          case 7: GSE_GM_PASSES(28); break;
+          case 8: GSE_GM_PASSES(32); break;
+          case 9: GSE_GM_PASSES(36); break;
+          case 10: GSE_GM_PASSES(40); break;
+          case 11: GSE_GM_PASSES(44); break;
+          case 12: GSE_GM_PASSES(48); break;
+          case 13: GSE_GM_PASSES(52); break;
+          case 14: GSE_GM_PASSES(56); break;
+          default: GSE_GM_PASSES(60); break;
         }
 #undef GSE_GM_PASSES
         hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(kWG), 0, st, w.S, sm, m, j, h1, sm.h2, P, gb,
@@ -823,7 +878,16 @@ gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_pa
         err = hipGetLastError();
         if (err != hipSuccess) return err;
       }
-      hipLaunchKernelGGL(k_gm_update, dim3(vb), dim3(kWG), 0, st, w.S, sm, m, V, ld, x, n);
+      // k <= m columns: the tier of m bounds the unrolled loads
+#define GSE_GM_UPDATE(JB) \
+  hipLaunchKernelGGL((k_gm_update<JB>), dim3(gb), dim3(kWG), 0, st, w.S, sm, m, V, ld, x, n)
+      if (m <= 8) GSE_GM_UPDATE(8);
+      else if (m <= 16) GSE_GM_UPDATE(16);
+      else if (m <= 24) GSE_GM_UPDATE(24);
+      else if (m <= 32) GSE_GM_UPDATE(32);
+      else if (m <= 48) GSE_GM_UPDATE(48);
+      else GSE_GM_UPDATE(60);
+#undef GSE_GM_UPDATE
       return hipGetLastError();
     };
     if (p->launch_mode == 1) {

@@ -13,8 +13,8 @@ import numpy as np
 import pytest
 
 import oracle as O
-from workloads import (CSR, convdiff2d, diffusion3d, poisson2d, powerlaw, random_sparse,
-                       rhs_from_solution)
+from workloads import (CSR, convdiff2d, diagonal, diffusion3d, fixed_rows, poisson2d, powerlaw,
+                       random_sparse, rhs_from_solution)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -43,6 +43,11 @@ def cases():
         "random_ragged": lambda: random_sparse(1777, 1901, 6, mean_row=9, exp_spread=20),
         "one_row_long": lambda: random_sparse(1, 9000, 7, mean_row=1, long_rows=1, long_len=8999),
         "tiny": lambda: random_sparse(3, 3, 8, mean_row=2),
+        # tiles spanning more rows than the ring stages row pointers for
+        "diagonal_3000": lambda: diagonal(3000, 10),
+        "sparse_many_empty": lambda: random_sparse(6000, 6000, 9, mean_row=0.6, exp_spread=12),
+        # non-zeros an exact multiple of the tile: the look-ahead past the end
+        "fixed_rows_512x8": lambda: fixed_rows(512, 700, 8, 11),
     }
 
 

@@ -10,7 +10,8 @@ by exactly one tile.  The constants mirror csrc/gse_internal.h.
 import numpy as np
 import pytest
 
-from workloads import (diffusion3d, convdiff2d, poisson2d, powerlaw, random_sparse)
+from workloads import (diagonal, diffusion3d, convdiff2d, fixed_rows, poisson2d, powerlaw,
+                       random_sparse)
 
 WG, EXTRA, SHORT, PAD, SPEC = 256, 256, 24, 16, 16
 
@@ -103,6 +104,9 @@ MATS = {
     "one_row_long": lambda: random_sparse(1, 9000, 7, mean_row=1, long_rows=1, long_len=8999),
     "tiny": lambda: random_sparse(3, 3, 8, mean_row=2),
     "empty": lambda: random_sparse(5, 5, 9, mean_row=0),
+    "diagonal_3000": lambda: diagonal(3000, 10),
+    "sparse_many_empty": lambda: random_sparse(6000, 6000, 9, mean_row=0.6, exp_spread=12),
+    "fixed_rows_512x8": lambda: fixed_rows(512, 700, 8, 11),
 }
 
 
@@ -240,7 +244,8 @@ def check_ring(indptr, n_cols, cols, fmt):
 
 
 @pytest.mark.parametrize("fmt", [0, 1, 2, 3])
-@pytest.mark.parametrize("name", ["poisson2d_64", "diffusion3d_24", "convdiff2d_64", "random_ragged"])
+@pytest.mark.parametrize("name", ["poisson2d_64", "diffusion3d_24", "convdiff2d_64", "random_ragged",
+                                  "diagonal_3000", "sparse_many_empty", "fixed_rows_512x8"])
 def test_ring_kernel_in_bounds(name, fmt):
     A = MATS[name]()
     if np.diff(A.indptr).max(initial=0) > SHORT or A.indptr[-1] < RING_T:

@@ -13,6 +13,8 @@ from .generators import (  # noqa: F401
     convdiff2d,
     powerlaw,
     random_sparse,
+    diagonal,
+    fixed_rows,
     rhs_from_solution,
     serving_stream,
     serving_request_matrix,

@@ -195,6 +195,28 @@ def random_sparse(n_rows: int, n_cols: int, seed: int, mean_row: float = 6.0,
                vals.astype(np.float64), f"random_{n_rows}x{n_cols}_s{seed}")
 
 
+def diagonal(n: int, seed: int, exp_spread: float = 16.0) -> CSR:
+    """Diagonal matrix with positive values over a spread of binary exponents
+    (one non-zero per row: a 1024-non-zero tile spans 1024 rows)."""
+    rng = np.random.default_rng(seed)
+    vals = np.exp2(rng.uniform(-exp_spread / 2, exp_spread / 2, size=n)) * rng.uniform(1, 2, size=n)
+    idx = np.arange(n, dtype=np.int32)
+    indptr = np.arange(n + 1, dtype=np.int32)
+    return CSR(n, n, indptr, idx, vals.astype(np.float64), f"diagonal_{n}_s{seed}")
+
+
+def fixed_rows(n_rows: int, n_cols: int, row_len: int, seed: int, exp_spread: float = 8.0) -> CSR:
+    """Every row holds exactly `row_len` distinct random columns (so the
+    number of non-zeros is n_rows * row_len exactly)."""
+    rng = np.random.default_rng(seed)
+    cols = np.stack([np.sort(rng.choice(n_cols, size=row_len, replace=False)) for _ in range(n_rows)])
+    vals = rng.standard_normal(cols.size) * np.exp2(
+        rng.uniform(-exp_spread / 2, exp_spread / 2, size=cols.size))
+    indptr = (np.arange(n_rows + 1) * row_len).astype(np.int32)
+    return CSR(n_rows, n_cols, indptr, cols.reshape(-1).astype(np.int32), vals.astype(np.float64),
+               f"fixed_{n_rows}x{n_cols}_r{row_len}_s{seed}")
+
+
 def rhs_from_solution(A: CSR, seed: int):
     """``x_true ~ U[-1, 1]`` from ``seed`` and ``b = A @ x_true`` in FP64."""
     rng = np.random.default_rng(seed)
