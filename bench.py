@@ -149,6 +149,29 @@ def copy_ceiling(G, torch, dev, stream):
     return round(2 * n / (ms * 1e-3) / 1e9, 1)
 
 
+def copy_same_size(G, torch, dev, stream, nbytes, copies):
+    """Streaming copy moving `nbytes` per launch (half read, half written),
+    rotated over `copies` buffer pairs like the SpMV operands: the practical
+    ceiling for one launch of that size, fill and drain included."""
+    half = (nbytes // 2 + 255) // 256 * 256
+    pairs = [(torch.empty(half, dtype=torch.uint8, device=dev),
+              torch.empty(half, dtype=torch.uint8, device=dev)) for _ in range(copies)]
+    for a, b in pairs:
+        G.gse_stream_copy(a, b, half)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    rounds = 10
+    e0.record(stream)
+    for _ in range(rounds):
+        for a, b in pairs:
+            G.gse_stream_copy(a, b, half)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / (rounds * copies)
+    del pairs
+    return {"bytes": 2 * half, "mean_us": round(us, 2), "GBps": round(2 * half / (us * 1e-6) / 1e9, 1)}
+
+
 def progress(msg):
     """A progress line on stderr (the JSON result is the only stdout line)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -250,6 +273,7 @@ def run_spmv_cg(args, torch, G):
                      "tile_nnz": mats[0].A.tile_nnz, "rv_lanes": mats[0].A.rv_lanes}
     out["spmv"] = spmv
     out["copy_ceiling_GBps"] = copy_gbs
+    out["copy_same_size"] = copy_same_size(G, torch, dev, stream, spmv["s1"]["bytes"], args.copies)
     out["roofline"] = {"bound": "hbm", "achieved": spmv["s1"]["GBps"], "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": spmv["s1"]["frac_peak"],
                        "traffic": measured_traffic(kname, workload), "kernel": kname,

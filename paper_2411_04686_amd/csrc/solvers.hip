@@ -520,9 +520,11 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
 //   h = V^T w                         (k_gm_dots + k_finish)
 //   w -= V h ; h2 = V^T w             (k_gm_axpy<.., false> + k_finish)
 //   w -= V h2 ; partials of ||w||^2   (k_gm_axpy<.., true>)
-//   H[:,j] = h + h2, ||w||, Givens    (k_gm_givens, one workgroup, which
-//                                      also runs the controller)
-//   v_{j+1} = w / ||w||               (k_gm_scale)
+//   H[:,j] = h + h2, ||w||, Givens,   (k_gm_givens_scale: workgroup 0 runs
+//     controller; v_{j+1} = w/||w||     the small steps, the others scale)
+// The finishers stay kernels of their own: summing the (j+1) x 512
+// partials in every workgroup of the next pass instead cost more than the
+// launch it saved.
 constexpr int kGmBlocks = 512;  // measured best for the 1M-row passes (fewer, longer workgroups)
 
 struct GmSmall {
@@ -619,21 +621,38 @@ __global__ __launch_bounds__(kWG) void k_gm_axpy(const SolverState* S, const dou
   block_sums_out(acc, NORM ? 1 : j + 1, red, partials, gridDim.x);
 }
 
-// The Arnoldi column j is complete: H[:,j] = h1 + h2, H[j+1,j] = ||w||
-// (from the norm partials); rotations, residual estimate, controller.
-// One workgroup: the column and the earlier rotations are gathered into LDS
-// by all threads, the rotations run in one thread from there, and the
-// rotated column is written back by all threads.
-__global__ __launch_bounds__(kWG) void k_gm_givens(SolverState* S, GmSmall sm, int m, int j,
-                                                   const double* __restrict__ h1,
-                                                   const double* __restrict__ h2,
-                                                   const double* __restrict__ norm_partials,
-                                                   int n_partials, double* hist, int* seg_hist) {
+// The Arnoldi column j is complete.  Every workgroup sums the norm
+// partials (same order, same bits) into ||w||.  Workgroup 0: H[:,j] = h1 +
+// h2, H[j+1,j] = ||w||, the rotations, the residual estimate and the
+// controller (the column and the earlier rotations are gathered into LDS
+// by all its threads, the rotations run in one thread from there, and the
+// rotated column is written back by all threads).  The other workgroups:
+// v_{j+1} = w / ||w||.  Workgroup 0 may set stop while the others run;
+// whether they still scale then does not matter, because a stopped cycle
+// ends with x += V(:, 0..j) y and never reads v_{j+1}.
+__global__ __launch_bounds__(kWG) void k_gm_givens_scale(SolverState* S, GmSmall sm, int m, int j,
+                                                         const double* __restrict__ h1,
+                                                         const double* __restrict__ h2,
+                                                         const double* __restrict__ norm_partials,
+                                                         int n_partials, double* hist, int* seg_hist,
+                                                         double* __restrict__ w, int n) {
   __shared__ double red[kWaves];
   __shared__ double col[64], c_s[64], s_s[64];
   __shared__ int bc_j, bc_s, bc_go;
   __shared__ double bc_rel;
   if (S->stop) return;
+  const double wn2 = sum_partials(norm_partials, n_partials, red);
+  if (blockIdx.x != 0 || gridDim.x == 1) {
+    const double hn = sqrt(wn2);
+    if (hn != 0.0) {
+      const double inv = 1.0 / hn;
+      const int b0 = gridDim.x == 1 ? 0 : (int)blockIdx.x - 1;
+      const int nb = gridDim.x == 1 ? 1 : (int)gridDim.x - 1;
+      for (int i = b0 * kWG + threadIdx.x; i < n; i += nb * kWG) w[i] *= inv;
+    }
+    if (blockIdx.x != 0) return;
+  }
+  __syncthreads();  // every thread has read red (sum_partials) before it is reused
   const int t = threadIdx.x;
   if (t <= j) {
     col[t] = h1[t] + h2[t];
@@ -642,7 +661,7 @@ __global__ __launch_bounds__(kWG) void k_gm_givens(SolverState* S, GmSmall sm, i
       s_s[t] = sm.sn[t];
     }
   }
-  const double wn2 = sum_partials(norm_partials, n_partials, red);  // has a barrier after the stores
+  __syncthreads();
   if (t == 0) {
     const double hn = sqrt(wn2);
     col[j + 1] = hn;
@@ -679,14 +698,6 @@ __global__ __launch_bounds__(kWG) void k_gm_givens(SolverState* S, GmSmall sm, i
   __syncthreads();
   if (t <= j + 1) sm.H[(size_t)t * m + j] = col[t];  // row-major (m+1) x m
   if (bc_go) controller(S, hist, red, bc_j, bc_rel, bc_s);
-}
-
-// v_{j+1} = w / ||w|| in place (only while the cycle goes on)
-__global__ __launch_bounds__(kWG) void k_gm_scale(SolverState* S, double* __restrict__ w, int n) {
-  if (S->stop) return;
-  const double hn = S->scratch[1];
-  const double inv = 1.0 / hn;
-  for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) w[i] *= inv;
 }
 
 // y = H(1:k,1:k) \ g(1:k) (every workgroup solves the small system the same
@@ -872,9 +883,8 @@ gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_pa
           default: GSE_GM_PASSES(60); break;
         }
 #undef GSE_GM_PASSES
-        hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(kWG), 0, st, w.S, sm, m, j, h1, sm.h2, P, gb,
-                           w.hist, w.seg_hist);
-        hipLaunchKernelGGL(k_gm_scale, dim3(vb), dim3(kWG), 0, st, w.S, wv, n);
+        hipLaunchKernelGGL(k_gm_givens_scale, dim3(gb), dim3(kWG), 0, st, w.S, sm, m, j, h1, sm.h2,
+                           P, gb, w.hist, w.seg_hist, wv, n);
         err = hipGetLastError();
         if (err != hipSuccess) return err;
       }
