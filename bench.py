@@ -22,7 +22,12 @@ Other workloads (one JSON line each):
   * ``--workload serving``: a Poisson-arrival stream of 2-D / 3-D diffusion
     systems through the solver server (stepped GSE, batched) against the
     same server running FP64 CSR one request at a time; p50 / p99 latency
-    and solves per second.
+    and solves per second;
+  * ``--workload powerlaw``: the 4 M-row power-law SPD matrix (Zipf(2) row
+    lengths up to 10^4, values over six decades): SpMV per segment count on
+    autotuned tiles, then stepped GSE CG and FP64 CG to 1e-10;
+  * ``--workload poisson``: the 2-D Poisson 64 x 64 system, stepped GSE CG
+    and FP64 CG to 1e-10 (launch-bound; median over the steps).
 """
 from __future__ import annotations
 
@@ -94,7 +99,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="spmv_cg", choices=["spmv_cg", "gmres", "serving"])
+    ap.add_argument("--workload", default="spmv_cg",
+                    choices=["spmv_cg", "gmres", "serving", "powerlaw", "poisson"])
+    ap.add_argument("--pl-rows", type=int, default=4_000_000, help="powerlaw: rows")
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copies", type=int, default=4)
@@ -235,8 +242,12 @@ def run_spmv_cg(args, torch, G):
         ws = torch.empty(G.gse_solver_workspace(G.CG, A.n_rows, A.nnz, 30, p.max_iter),
                          dtype=torch.uint8, device=dev)
         x = torch.zeros(A.n_rows, dtype=torch.float64, device=dev)
+        # a solve's time_ms runs from its call to its return: nothing queued
+        # before it may be counted in it
+        torch.cuda.synchronize()
         rg = G.gse_cg(mats[0].A, bd, x, p, ws)
         x.zero_()
+        torch.cuda.synchronize()
         r64 = G.gse_csr_cg(csrs[0].M, bd, x, p, ws)
         if record:
             solve.setdefault("gse", []).append(rg.as_dict())
@@ -318,9 +329,11 @@ def run_gmres(args, torch, G):
     t0 = time.perf_counter()
     for _ in range(args.steps):
         x.zero_()
+        torch.cuda.synchronize()
         res["gse"] = G.gse_gmres(M.A, bd, x, p, ws).as_dict()
         progress(f"gmres: GSE {res['gse']}")
         x.zero_()
+        torch.cuda.synchronize()
         res["fp64"] = G.gse_csr_gmres(C.M, bd, x, p, ws).as_dict()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -331,6 +344,173 @@ def run_gmres(args, torch, G):
                      "seed": args.seed, "restart": p.restart}
     out["gmres"] = {"gse": g, "fp64": f,
                     "speedup": round(f["time_ms"] / g["time_ms"], 3) if g["time_ms"] else None}
+    return out
+
+
+# ------------------------------------------------------------ power law ---
+def run_powerlaw(args, torch, G):
+    """4 M-row power-law SPD matrix: SpMV per segment count after the
+    autotuner picked the tile shape, then stepped GSE CG vs FP64 CG to 1e-10.
+    The planes (0.4-0.8 GB) exceed the Infinity Cache, so every launch is
+    cold without rotated copies."""
+    from workloads import powerlaw, rhs_from_solution
+
+    dev = torch.device("cuda:0")
+    A = powerlaw(args.pl_rows, args.seed)
+    _, b = rhs_from_solution(A, args.seed)
+    progress(f"powerlaw: {A.n_rows} rows, {A.nnz} non-zeros generated")
+    rp = torch.from_numpy(A.indptr).to(dev)
+    ci = torch.from_numpy(A.indices).to(dev)
+    va = torch.from_numpy(A.data).to(dev)
+    M = G.GseMatrix(rp, ci, va, A.n_cols)
+    C = G.CsrMatrix(rp, ci, va, A.n_cols)
+    del ci, va
+    xs = torch.ones(A.n_cols, dtype=torch.float64, device=dev)
+    y = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
+    M.autotune(1, xs, y)
+    C.autotune(xs, y)
+    stream = torch.cuda.current_stream()
+    progress(f"powerlaw: autotuned tile_nnz {M.A.tile_nnz} rv_lanes {M.A.rv_lanes}")
+    kinds = [("s1", 6), ("s2", 8), ("s3", 12), ("fp64", 12)]
+    times = {k: [] for k, _ in kinds}
+
+    def run(kname):
+        if kname == "fp64":
+            C.spmv(xs, y)
+        else:
+            M.spmv(int(kname[1]), xs, y)
+
+    # CG runs on the symmetrically diagonal-scaled system D^-1/2 A D^-1/2 y =
+    # D^-1/2 b (unit diagonal; Jacobi-preconditioned CG in exact arithmetic):
+    # the rows' scales span six decades, and plain CG on A itself stalls near
+    # 4e-6 at the 5000-iteration cap.  Its Gershgorin bound gives kappa <= 21.
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.indptr))
+    diag = np.zeros(A.n_rows)
+    on = rows == A.indices
+    diag[rows[on]] = A.data[on]
+    dinv = 1.0 / np.sqrt(diag)
+    sval = A.data * dinv[rows] * dinv[A.indices]
+    del rows, on
+    sv = torch.from_numpy(sval).to(dev)
+    sc = torch.from_numpy(A.indices).to(dev)
+    MS = G.GseMatrix(rp, sc, sv, A.n_cols)
+    CS = G.CsrMatrix(rp, sc, sv, A.n_cols)
+    MS.autotune(1, xs, y)
+    CS.autotune(xs, y)
+    del sv, sc, sval
+    bd = torch.from_numpy(b * dinv).to(dev)
+    p = G.gse_default_params(G.CG)
+    ws = torch.empty(G.gse_solver_workspace(G.CG, A.n_rows, A.nnz, 30, p.max_iter),
+                     dtype=torch.uint8, device=dev)
+    x = torch.zeros(A.n_rows, dtype=torch.float64, device=dev)
+    solve = {}
+
+    cg_runs = {"gse": [], "fp64": []}
+
+    def step(record):
+        for kname, _ in kinds:
+            for _ in range(args.reps):
+                if record:
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                run(kname)
+                if record:
+                    e1.record(stream)
+                    times[kname].append((e0, e1))
+        x.zero_()
+        torch.cuda.synchronize()  # the SpMV launches above are not part of the solve
+        rg = G.gse_cg(MS.A, bd, x, p, ws)
+        x.zero_()
+        torch.cuda.synchronize()
+        r64 = G.gse_csr_cg(CS.M, bd, x, p, ws)
+        if record:
+            cg_runs["gse"].append(rg.as_dict())
+            cg_runs["fp64"].append(r64.as_dict())
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    spmv = {}
+    for kname, pb in kinds:
+        ms = np.array([a.elapsed_time(c) for a, c in times[kname]])
+        nbytes = spmv_bytes(A.n_rows, A.n_cols, A.nnz, pb)
+        mean = float(ms.mean())
+        spmv[kname] = {"mean_us": round(mean * 1e3, 2),
+                       "median_us": round(float(np.median(ms)) * 1e3, 2),
+                       "bytes": int(nbytes), "GBps": round(nbytes / (mean * 1e-3) / 1e9, 1),
+                       "frac_peak": round(nbytes / (mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    out = base_record(args, "GSE-SpMV HBM GB/s (s=1), power-law SPD; CG time-to-1e-10 vs FP64 CSR",
+                      spmv["s1"]["GBps"], "GB/s", wall)
+    out["config"] = {"workload": f"powerlaw_{A.n_rows}_zipf2_spd", "n_rows": A.n_rows, "nnz": A.nnz,
+                     "max_row": int(np.diff(A.indptr).max()), "seed": args.seed, "x": "ones",
+                     "tile_nnz": M.A.tile_nnz, "rv_lanes": M.A.rv_lanes}
+    out["spmv"] = spmv
+    out["roofline"] = {"bound": "hbm", "achieved": spmv["s1"]["GBps"], "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": spmv["s1"]["frac_peak"], "traffic": None,
+                       "bytes_per_launch": spmv["s1"]["bytes"], "mean_launch_us": spmv["s1"]["mean_us"]}
+    med = {k: float(np.median([r["time_ms"] for r in v])) for k, v in cg_runs.items()}
+    out["cg"] = {"system": "D^-1/2 A D^-1/2 y = D^-1/2 b (unit diagonal)",
+                 "gse": cg_runs["gse"][-1], "fp64": cg_runs["fp64"][-1],
+                 "median_ms": {k: round(v, 3) for k, v in med.items()},
+                 "speedup": round(med["fp64"] / med["gse"], 3) if med["gse"] else None,
+                 "eta_scaled": [float(e) for e in MS.eta]}
+    return out
+
+
+# -------------------------------------------------------------- Poisson ---
+def run_poisson(args, torch, G):
+    """2-D Poisson 64 x 64 (exact stencil values, eta_1 = 0): stepped GSE CG
+    and FP64 CG to 1e-10; the system is L2-resident, so this measures the
+    launch-bound regime.  `value` is the median stepped time over the steps."""
+    from workloads import poisson2d, rhs_from_solution
+
+    dev = torch.device("cuda:0")
+    A = poisson2d(64)
+    _, b = rhs_from_solution(A, args.seed)
+    rp = torch.from_numpy(A.indptr).to(dev)
+    ci = torch.from_numpy(A.indices).to(dev)
+    va = torch.from_numpy(A.data).to(dev)
+    M = G.GseMatrix(rp, ci, va, A.n_cols)
+    C = G.CsrMatrix(rp, ci, va, A.n_cols)
+    bd = torch.from_numpy(b).to(dev)
+    p = G.gse_default_params(G.CG)
+    ws = torch.empty(G.gse_solver_workspace(G.CG, A.n_rows, A.nnz, 30, p.max_iter),
+                     dtype=torch.uint8, device=dev)
+    x = torch.zeros(A.n_rows, dtype=torch.float64, device=dev)
+    runs = {"gse": [], "fp64": []}
+
+    def step():
+        x.zero_()
+        torch.cuda.synchronize()
+        rg = G.gse_cg(M.A, bd, x, p, ws).as_dict()
+        x.zero_()
+        torch.cuda.synchronize()
+        return rg, G.gse_csr_cg(C.M, bd, x, p, ws).as_dict()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rg, r64 = step()
+        runs["gse"].append(rg)
+        runs["fp64"].append(r64)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    med = {k: float(np.median([r["time_ms"] for r in v])) for k, v in runs.items()}
+    out = base_record(args, "CG time-to-1e-10, stepped GSE vs FP64 CSR (2-D Poisson 64x64)",
+                      round(med["gse"], 3), "ms", wall, higher=False)
+    out["config"] = {"workload": "poisson2d_64^2_5pt", "n_rows": A.n_rows, "nnz": A.nnz,
+                     "seed": args.seed}
+    out["cg"] = {"gse": runs["gse"][-1], "fp64": runs["fp64"][-1],
+                 "median_ms": {k: round(v, 3) for k, v in med.items()},
+                 "speedup": round(med["fp64"] / med["gse"], 3) if med["gse"] else None}
     return out
 
 
@@ -433,6 +613,10 @@ def main():
         out = run_gmres(args, torch, G)
     elif args.workload == "serving":
         out = run_serving(args, torch, G)
+    elif args.workload == "powerlaw":
+        out = run_powerlaw(args, torch, G)
+    elif args.workload == "poisson":
+        out = run_poisson(args, torch, G)
     else:
         out = run_spmv_cg(args, torch, G)
     print(json.dumps(out))
