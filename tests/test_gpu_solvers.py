@@ -38,10 +38,12 @@ def true_relres(A: CSR, x, b):
 
 
 def gpu_solve(kind, A: CSR, b, method, fixed=0, max_iter=5000, switch_mode=1, x0=None,
-              record=True, rv=-1, launch_mode=0):
+              record=True, rv=-1, launch_mode=0, restart=None):
     rp, ci, va = to_dev(A)
     p = G.gse_default_params(method)
     p.max_iter = max_iter
+    if restart is not None:
+        p.restart = restart
     p.fixed_segments = fixed
     p.switch_mode = switch_mode
     p.launch_mode = launch_mode
@@ -68,9 +70,9 @@ def gpu_solve(kind, A: CSR, b, method, fixed=0, max_iter=5000, switch_mode=1, x0
     return rep, x.cpu().numpy(), hist, seg
 
 
-def oracle_params(method, fixed=0, max_iter=5000, switch_mode=1):
+def oracle_params(method, fixed=0, max_iter=5000, switch_mode=1, restart=30):
     preset = "paper_cg" if method == G.CG else "paper_gmres"
-    return O.make_params(tol=1e-10, max_iter=max_iter, restart=30, fixed_segments=fixed,
+    return O.make_params(tol=1e-10, max_iter=max_iter, restart=restart, fixed_segments=fixed,
                          preset=preset, switch_mode=switch_mode, orth=1)
 
 
@@ -176,6 +178,43 @@ def test_gmres_first_cycle_residuals_match_oracle():
     ref = O.gmres(A.indptr, b, oracle_params(G.GMRES, fixed=-1, max_iter=30), A.indices, A.data)
     assert rep.iters == ref.iters == 30
     assert np.allclose(hist[:31], ref.hist[:31], rtol=1e-8, atol=1e-15)
+
+
+@pytest.mark.parametrize("restart", [5, 17, 45, 60])
+def test_gmres_restart_lengths_match_oracle(restart):
+    """Every restart length runs its own Gram-Schmidt instantiations (basis
+    counts rounded up to 4, up to 60) and update kernel: the residual
+    estimates of the first cycle follow the oracle's CGS2 to rounding, and
+    the restarted solve converges with the oracle's solution."""
+    A = convdiff2d(40, 9)  # no restart length converges inside one cycle
+    _, b = rhs_from_solution(A, 9)
+    rep, x, hist, _ = gpu_solve("csr", A, b, G.GMRES, max_iter=restart, restart=restart)
+    ref = O.gmres(A.indptr, b, oracle_params(G.GMRES, fixed=-1, max_iter=restart, restart=restart),
+                  A.indices, A.data)
+    assert rep.iters == ref.iters == restart
+    assert np.allclose(hist[:restart + 1], ref.hist[:restart + 1], rtol=1e-8, atol=1e-15)
+    rep, x, _, _ = gpu_solve("gse", A, b, G.GMRES, max_iter=15000, restart=restart)
+    assert rep.status == G.OK and true_relres(A, x, b) <= 1e-10
+    ref = O.gmres(A.indptr, b, oracle_params(G.GMRES, max_iter=15000, restart=restart), A.indices,
+                  A.data, O.encode(A.indptr, A.indices, A.data, A.n_cols))
+    assert ref.status == O.OK
+    assert np.linalg.norm(x - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+
+
+def test_gmres_small_dense_exact_within_one_cycle():
+    """n <= restart: the Krylov space is the whole space after n steps, so
+    GMRES ends with ||w|| = 0 (or below the tolerance) inside the first cycle
+    -- the one-workgroup launches and the lucky-breakdown path."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(11)
+    for n in (1, 3, 12, 29):
+        D = rng.standard_normal((n, n)) + n * np.eye(n)  # nonsymmetric, well conditioned
+        A = CSR.from_scipy(sp.csr_matrix(D))
+        b = rng.standard_normal(n)
+        rep, x, _, _ = gpu_solve("gse", A, b, G.GMRES, fixed=3, restart=30)
+        assert rep.status == G.OK, (n, rep.as_dict())
+        assert rep.iters <= n
+        assert np.allclose(x, np.linalg.solve(D, b), rtol=1e-8, atol=1e-10)
 
 
 def test_cg_small_dense_and_edge_cases():
