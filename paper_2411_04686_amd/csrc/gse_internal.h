@@ -48,8 +48,10 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Deterministic block sum (fixed tree); every thread gets the result.
-__device__ __forceinline__ double block_sum(double v, double* red /* [kWaves] */) {
+// Deterministic block sum (fixed tree) over a workgroup of NT threads;
+// every thread gets the result.
+template <int NT = kWG>
+__device__ __forceinline__ double block_sum(double v, double* red /* [NT / 64] */) {
   v = wave_sum(v);
   const int w = threadIdx.x >> 6;
   __syncthreads();
@@ -57,7 +59,7 @@ __device__ __forceinline__ double block_sum(double v, double* red /* [kWaves] */
   __syncthreads();
   double s = 0.0;
 #pragma unroll
-  for (int i = 0; i < kWaves; ++i) s += red[i];
+  for (int i = 0; i < NT / 64; ++i) s += red[i];
   return s;
 }
 

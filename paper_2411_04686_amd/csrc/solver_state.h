@@ -47,20 +47,22 @@ struct SolverState {
 // RSD (Eq. 3): population standard deviation over resid[j-t..j-1] divided
 // by their mean; nDec (Eqs. 4-5): decreases resid[i] > resid[i+1] for
 // i = j-t..j-1; relDec (Eq. 6): (resid[j-t] - resid[j-1]) / resid[j-t].
-// Called by every thread of one workgroup; returns the trigger (1..3) or 0.
+// Called by every thread of one workgroup of NT threads; returns the
+// trigger (1..3) or 0.
+template <int NT = kWG>
 __device__ inline int grid_conditions(const SolverState* S, const double* hist, int j, double* red) {
   const int t = S->t;
   double sum = 0.0;
-  for (int i = threadIdx.x; i < t; i += kWG) sum += hist[j - t + i];
-  const double avg = block_sum(sum, red) / (double)t;
+  for (int i = threadIdx.x; i < t; i += NT) sum += hist[j - t + i];
+  const double avg = block_sum<NT>(sum, red) / (double)t;
   double var = 0.0, dec = 0.0;
-  for (int i = threadIdx.x; i < t; i += kWG) {
+  for (int i = threadIdx.x; i < t; i += NT) {
     const double d = hist[j - t + i] - avg;
     var += d * d;
     dec += (hist[j - t + i] > hist[j - t + i + 1]) ? 1.0 : 0.0;
   }
-  var = block_sum(var, red) / (double)t;
-  const int ndec = (int)block_sum(dec, red);
+  var = block_sum<NT>(var, red) / (double)t;
+  const int ndec = (int)block_sum<NT>(dec, red);
   const double rsd = sqrt(var) / avg;
   const double reldec = (hist[j - t] - hist[j - 1]) / hist[j - t];
   bool below;
@@ -72,16 +74,24 @@ __device__ inline int grid_conditions(const SolverState* S, const double* hist, 
   return GSE_TRIG_NONE;
 }
 
+// Whether the controller evaluates Conditions 1-3 after iteration j (it
+// then reads the residual history of the last t iterations).
+__device__ inline bool on_check_grid(const SolverState* S, int j, double relres, int s) {
+  return S->stepped && s < 3 && relres > S->tol && j >= S->l && j >= S->t && S->m > 0 &&
+         ((j - S->l) % S->m) == 0;
+}
+
 // After iteration j recorded relres (values broadcast through LDS by the
 // caller): convergence, the floor and tolerance triggers, Conditions 1-3 on
-// the check grid, the cap.  Every thread of the workgroup calls it.
+// the check grid, the cap.  Every thread of the workgroup (NT threads)
+// calls it.
+template <int NT = kWG>
 __device__ inline void controller(SolverState* S, const double* hist, double* red, int j, double relres,
                            int s) {
   const bool exact_op = S->fixed != 0 || s >= 3 || S->eta[s - 1] == 0.0;
-  const bool on_grid = S->stepped && s < 3 && relres > S->tol && j >= S->l && j >= S->t &&
-                       S->m > 0 && ((j - S->l) % S->m) == 0;
+  const bool on_grid = on_check_grid(S, j, relres, s);
   int cond = GSE_TRIG_NONE;
-  if (on_grid) cond = grid_conditions(S, hist, j, red);  // uniform branch
+  if (on_grid) cond = grid_conditions<NT>(S, hist, j, red);  // uniform branch
   if (threadIdx.x == 0) {
     int stop = kRun, trig = GSE_TRIG_NONE;
     if (relres <= S->tol) {

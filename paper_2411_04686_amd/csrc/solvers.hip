@@ -15,7 +15,9 @@
 #include <string.h>
 
 #include <chrono>
+#include <type_traits>
 
+#include "decode.h"
 #include "gse_internal.h"
 #include "solver_state.h"
 
@@ -152,6 +154,281 @@ __global__ __launch_bounds__(kWG) void k_cg_xstep(SolverState* S, double* __rest
   }
   __syncthreads();
   controller(S, hist, red, j, bc_rel, s);
+}
+
+// ------------------------------------------------------ small systems ---
+// A system this small is bound by latency, not bytes: three launches per
+// iteration cost ~13 us on a 4096-row Poisson system.  One workgroup of
+// 1024 threads then runs every iteration of a segment count in a single
+// launch, with workgroup barriers where the large path has launch
+// boundaries, until the controller (or a breakdown) stops it.  The loop
+// keeps its state on the chip: thread t decodes its rows (t + k*1024, at
+// most L = 4, 6 or 8 non-zeros each, L from the longest row) into registers
+// once per launch and holds its entries of r there; p (which the product
+// gathers) and the solver record live in LDS; x is read early in a pass and
+// written late, off the critical path; q lives within a pass.  (Reading
+// the planes from L2 in every pass, row per thread, measured 10.7 us per
+// iteration: one CU's memory pipeline.)  The arithmetic is that of the
+// large path: rows summed in row order with the multiply and add rounded
+// separately, the same CG updates, the same controller; only the dot
+// products' summation tree differs (one workgroup's).
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallRpt = 4;                            // rows per thread at most
+constexpr int kSmallRows = kSmallThreads * kSmallRpt;   // systems up to this many rows
+constexpr int kSmallRow = 8;                            // ... whose rows hold at most 8 non-zeros
+
+// One non-zero decoded without the LDS table: the slot's exponent
+// SEM - 1023 - W_s comes from eight registers and the value is
+// ldexp(+-F, exponent), exact and bit-identical to F times the table's
+// power of two (the product is a normal number or zero for SEM >= 64).
+// The compiler may recompute it in every pass rather than hold 32 FP64
+// values per thread, so it costs ALU work only.
+// The eight slot exponents SEM - 1023 - W_s as 16-bit fields, two per
+// word (scalars: an array here would be indexed per lane from scratch).
+struct SlotExp {
+  uint32_t w01, w23, w45, w67;
+  __device__ __forceinline__ int operator()(uint32_t slot) const {
+    const uint32_t w = (slot & 4u) ? ((slot & 2u) ? w67 : w45) : ((slot & 2u) ? w23 : w01);
+    return (int)(int16_t)(uint16_t)(w >> ((slot & 1u) * 16u));
+  }
+};
+
+template <int FMT>
+__device__ __forceinline__ SlotExp slot_exponents(const int16_t* sem) {
+  constexpr int W = (FMT == 1) ? 15 : (FMT == 2) ? 31 : 63;
+  uint32_t w[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    w[i] = (uint32_t)(uint16_t)(int16_t)(sem[2 * i] - 1023 - W) |
+           ((uint32_t)(uint16_t)(int16_t)(sem[2 * i + 1] - 1023 - W) << 16);
+  return SlotExp{w[0], w[1], w[2], w[3]};
+}
+
+template <int FMT>
+__device__ __forceinline__ double small_elem(const SpmvOperand& A, int j, const SlotExp& ex,
+                                             int& column) {
+  const uint32_t c = A.col[j];
+  if constexpr (FMT == kCsr64) {
+    column = (int)c;
+    return A.val[j];
+  } else {
+    column = (int)(c & 0x1FFFFFFFu);
+    const int e = ex(c >> 29);
+    const uint32_t h = A.head[j];
+    double v;
+    if constexpr (FMT == 1) {
+      v = ldexp((double)(h & 0x7FFFu), e);
+    } else if constexpr (FMT == 2) {
+      v = ldexp((double)(((h & 0x7FFFu) << 16) | (uint32_t)A.tail1[j]), e);
+    } else {
+      const double hi = (double)(((h & 0x7FFFu) << 16) | (uint32_t)A.tail1[j]);
+      v = ldexp(hi, e + 32) + ldexp((double)A.tail2[j], e);  // at most 53 significant bits: exact
+    }
+    return (h & 0x8000u) ? -v : v;
+  }
+}
+
+// f(integral_constant<int, K>) for K = B .. E-1, expanded at compile time
+// (a loop over a thread's rows must index its register arrays with
+// constants; left as a loop, the arrays go to scratch).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// Barrier ordering LDS only: the loop's shared data lives in LDS, and a
+// full barrier would also wait for the history stores in flight.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// block_sum with LDS-only barriers (same tree, same bits).
+template <int NT>
+__device__ __forceinline__ double block_sum_lds(double v, double* red /* [NT / 64] */) {
+  v = wave_sum(v);
+  lds_barrier();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  lds_barrier();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) s += red[i];
+  return s;
+}
+
+template <int FMT, int RPT, int L>
+__global__ __launch_bounds__(kSmallThreads) void k_cg_small(SolverState* Sg, SpmvOperand A,
+                                                            double* __restrict__ xg,
+                                                            double* __restrict__ rg,
+                                                            double* __restrict__ pg,
+                                                            double* __restrict__ qg, double* hist,
+                                                            int* seg_hist) {
+  constexpr int NT = kSmallThreads;
+  static_assert(L % 2 == 0 && L <= kSmallRow, "row slots");
+  __shared__ double red[NT / 64];
+  __shared__ double pl[NT * RPT];
+  __shared__ SolverState Sl;
+  __shared__ double bc_rel;
+  const int tid = threadIdx.x;
+  const int n = A.n_rows;
+  if (tid == 0) Sl = *Sg;
+  const SlotExp ex = slot_exponents<FMT>(A.sem);
+  double rr[RPT], qr[RPT];  // x stays in memory: loaded early in a pass, stored late
+  double av[RPT][L];
+  uint32_t ac[RPT][L / 2];  // two 16-bit columns per word (n <= 4096)
+  int len[RPT];
+  static_for<0, RPT>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    const int i = tid + k * NT;
+    const bool in = i < n;
+    rr[k] = in ? rg[i] : 0.0;
+    qr[k] = 0.0;
+    if (in) pl[i] = pg[i];
+    const int s0 = in ? A.row_ptr[i] : 0;
+    const int s1 = in ? A.row_ptr[i + 1] : 0;
+    len[k] = s1 - s0;
+    int cc[L];
+#pragma unroll
+    for (int e = 0; e < L; ++e) {
+      // clamped into the row, or to entry 0 for an empty row (nnz > 0 then)
+      int jj = min(s0 + e, s1 - 1);
+      jj = jj < 0 ? 0 : jj;
+      int c = 0;
+      const double v = A.nnz > 0 ? small_elem<FMT>(A, jj, ex, c) : 0.0;
+      const bool use = e < s1 - s0;
+      av[k][e] = use ? v : 0.0;
+      cc[e] = use ? c : 0;
+    }
+#pragma unroll
+    for (int e = 0; e < L / 2; ++e) ac[k][e] = (uint32_t)cc[2 * e] | ((uint32_t)cc[2 * e + 1] << 16);
+  });
+  __syncthreads();
+  SolverState* S = &Sl;
+  for (;;) {
+    if (S->stop) break;
+    // x of this pass, loaded now and used after both reductions
+    double xo[RPT];
+    static_for<0, RPT>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      xo[k] = (tid + k * NT < n) ? xg[tid + k * NT] : 0.0;
+    });
+    // q = A_s p and p.q
+    double acc = 0.0;
+    static_for<0, RPT>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      double xv[L];
+      static_for<0, L>([&](auto ec) {
+        constexpr int e = decltype(ec)::value;
+        xv[e] = pl[(ac[k][e >> 1] >> (16 * (e & 1))) & 0xFFFFu];
+      });
+      double sum = 0.0;
+      static_for<0, L>([&](auto ec) {
+        constexpr int e = decltype(ec)::value;
+        const double pr = __dmul_rn(av[k][e], xv[e]);
+        sum = (e < len[k]) ? __dadd_rn(sum, pr) : sum;
+      });
+      qr[k] = sum;
+      if (tid + k * NT < n) acc += pl[tid + k * NT] * sum;
+    });
+    const double pq = block_sum_lds<NT>(acc, red);  // its barriers end the gathers from pl
+    const int j = S->it;
+    const double rho = S->rho_p[j & 1];
+    if (!(pq > 0.0) || !isfinite(pq)) {  // uniform: every thread holds the same pq
+      if (tid == 0) {
+        S->pq = pq;
+        S->stop = kBreak;
+      }
+      break;
+    }
+    const double alpha = rho / pq;
+    acc = 0.0;
+    static_for<0, RPT>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      if (tid + k * NT < n) {
+        const double v = rr[k] - alpha * qr[k];
+        rr[k] = v;
+        acc += v * v;
+      }
+    });
+    const double rho_new = block_sum_lds<NT>(acc, red);
+    const double beta = rho_new / rho;
+    static_for<0, RPT>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const int i = tid + k * NT;
+      if (i < n) {
+        const double pv = pl[i];
+        xg[i] = xo[k] + alpha * pv;
+        pl[i] = rr[k] + beta * pv;
+      }
+    });
+    const int s = S->s;
+    const int jn = j + 1;
+    if (tid == 0) {
+      const double rel = sqrt(rho_new) / S->nb;
+      S->pq = pq;
+      S->alpha = alpha;
+      S->beta = beta;
+      S->rho_p[jn & 1] = rho_new;
+      S->rho = rho_new;
+      S->it = jn;
+      S->relres = rel;
+      hist[jn] = rel;
+      seg_hist[jn] = s;
+      bc_rel = rel;
+    }
+    lds_barrier();
+    // Conditions 1-3 read the history from memory: then the history stores
+    // must be complete first (a full barrier); otherwise they stay in flight
+    if (on_check_grid(S, jn, bc_rel, s)) __syncthreads();
+    controller<NT>(S, hist, red, jn, bc_rel, s);
+    lds_barrier();  // p and the stop flag for the next pass
+  }
+  __syncthreads();
+  static_for<0, RPT>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    const int i = tid + k * NT;
+    if (i < n) {
+      rg[i] = rr[k];
+      pg[i] = pl[i];
+    }
+  });
+  if (tid == 0) *Sg = Sl;
+}
+
+bool cg_small_path(const SpmvOperand& op) {
+  return op.n_rows <= kSmallRows && op.max_row <= kSmallRow;
+}
+
+template <int RPT, int L>
+hipError_t launch_cg_small_rl(const SpmvOperand& op, int s, SolverState* S, double* x, double* r,
+                              double* p, double* q, double* hist, int* seg_hist, hipStream_t st) {
+  const dim3 g(1), b(kSmallThreads);
+  switch (s) {
+    case 0: hipLaunchKernelGGL((k_cg_small<0, RPT, L>), g, b, 0, st, S, op, x, r, p, q, hist, seg_hist); break;
+    case 1: hipLaunchKernelGGL((k_cg_small<1, RPT, L>), g, b, 0, st, S, op, x, r, p, q, hist, seg_hist); break;
+    case 2: hipLaunchKernelGGL((k_cg_small<2, RPT, L>), g, b, 0, st, S, op, x, r, p, q, hist, seg_hist); break;
+    default: hipLaunchKernelGGL((k_cg_small<3, RPT, L>), g, b, 0, st, S, op, x, r, p, q, hist, seg_hist); break;
+  }
+  return hipGetLastError();
+}
+
+template <int L>
+hipError_t launch_cg_small_l(const SpmvOperand& op, int s, SolverState* S, double* x, double* r,
+                             double* p, double* q, double* hist, int* seg_hist, hipStream_t st) {
+  if (op.n_rows <= kSmallThreads) return launch_cg_small_rl<1, L>(op, s, S, x, r, p, q, hist, seg_hist, st);
+  if (op.n_rows <= 2 * kSmallThreads) return launch_cg_small_rl<2, L>(op, s, S, x, r, p, q, hist, seg_hist, st);
+  return launch_cg_small_rl<4, L>(op, s, S, x, r, p, q, hist, seg_hist, st);
+}
+
+hipError_t launch_cg_small(const SpmvOperand& op, int s, SolverState* S, double* x, double* r,
+                           double* p, double* q, double* hist, int* seg_hist, hipStream_t st) {
+  if (op.max_row <= 4) return launch_cg_small_l<4>(op, s, S, x, r, p, q, hist, seg_hist, st);
+  if (op.max_row <= 6) return launch_cg_small_l<6>(op, s, S, x, r, p, q, hist, seg_hist, st);
+  return launch_cg_small_l<8>(op, s, S, x, r, p, q, hist, seg_hist, st);
 }
 
 // dst = src (n doubles)
@@ -407,11 +684,15 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
   int chunk = 4;
   bool done = false;
   bool pending_check = h.relres <= p->tol;  // converged at x0 already
+  const bool small = cg_small_path(A.op);
   while (!done) {
     if (pending_check) {
       h.stop = kConv;
     } else {
-      if (p->launch_mode == 1 || chunk < kGraphIters) {
+      if (small) {
+        // every iteration of this segment count in one launch
+        e = launch_cg_small(A.op, h.s, w.S, x, w.r, w.p, w.q, w.hist, w.seg_hist, st);
+      } else if (p->launch_mode == 1 || chunk < kGraphIters) {
         e = launch_iters(chunk, h.s);
         chunk = chunk < 64 ? chunk * 2 : 64;
       } else {

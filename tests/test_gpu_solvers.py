@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from workloads import CSR, convdiff2d, diffusion3d, poisson2d, rhs_from_solution
+from workloads import CSR, convdiff2d, diffusion2d, diffusion3d, poisson2d, rhs_from_solution
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -38,12 +38,14 @@ def true_relres(A: CSR, x, b):
 
 
 def gpu_solve(kind, A: CSR, b, method, fixed=0, max_iter=5000, switch_mode=1, x0=None,
-              record=True, rv=-1, launch_mode=0, restart=None):
+              record=True, rv=-1, launch_mode=0, restart=None, **ctrl):
     rp, ci, va = to_dev(A)
     p = G.gse_default_params(method)
     p.max_iter = max_iter
     if restart is not None:
         p.restart = restart
+    for k, v in ctrl.items():  # controller parameters (l, t, m, floor_c, ndec_limit, ...)
+        setattr(p, k, v)
     p.fixed_segments = fixed
     p.switch_mode = switch_mode
     p.launch_mode = launch_mode
@@ -215,6 +217,63 @@ def test_gmres_small_dense_exact_within_one_cycle():
         assert rep.status == G.OK, (n, rep.as_dict())
         assert rep.iters <= n
         assert np.allclose(x, np.linalg.solve(D, b), rtol=1e-8, atol=1e-10)
+
+
+def _tridiag(n, seed):
+    """1-D variable-coefficient diffusion plus a small shift (rows of at
+    most 3 non-zeros; CG converges in ~160 iterations)."""
+    import scipy.sparse as sp
+    k = 10.0 ** np.random.default_rng(seed).uniform(-1, 1, n + 1)
+    main = k[:-1] + k[1:] + 0.05 * k[:-1].mean()
+    off = -k[1:-1]
+    return CSR.from_scipy(sp.diags([off, main, off], [-1, 0, 1], format="csr"))
+
+
+@pytest.mark.parametrize("name", ["poisson_400", "tridiag_1500", "diff2d_4096", "diff3d_4096"])
+def test_small_system_cg_matches_oracle(name):
+    """Systems of at most 4096 rows with rows of at most 8 non-zeros run
+    all their iterations in one workgroup (one, two or four rows per thread;
+    4, 6 or 8 register slots per row): stepped GSE and FP64 CG against the
+    oracle."""
+    A = {"poisson_400": lambda: poisson2d(20), "tridiag_1500": lambda: _tridiag(1500, 4),
+         "diff2d_4096": lambda: diffusion2d(64, 4), "diff3d_4096": lambda: diffusion3d(16, 4)}[name]()
+    _, b = rhs_from_solution(A, 4)
+    enc = O.encode(A.indptr, A.indices, A.data, A.n_cols)
+    for kind in ("gse", "csr"):
+        rep, x, hist, seg = gpu_solve(kind, A, b, G.CG)
+        if kind == "gse":
+            ref = O.cg(A.indptr, b, oracle_params(G.CG), A.indices, A.data, enc)
+        else:
+            ref = O.cg(A.indptr, b, oracle_params(G.CG, fixed=-1), A.indices, A.data)
+        assert rep.status == G.OK and ref.status == O.OK, (kind, rep.as_dict())
+        assert rep.relres_true <= 1e-10 and true_relres(A, x, b) <= 1e-10
+        assert np.linalg.norm(x - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+        assert abs(rep.iters - ref.iters) <= max(3, ref.iters // 10)
+        if kind == "gse":
+            assert list(rep.iters_per_seg) == [int((seg[1:] == s).sum()) for s in (1, 2, 3)]
+            assert abs(rep.switch_iter[0] - ref.switch_iter[0]) <= 3
+
+
+def test_small_system_conditions_on_the_check_grid():
+    """A short check grid (l = 20, t = m = 10, no floor trigger): Conditions
+    1-3 are evaluated inside the one-workgroup loop and switch the segment
+    count where the oracle's controller does."""
+    A = diffusion2d(40, 5)
+    _, b = rhs_from_solution(A, 5)
+    ctrl = dict(l=20, t=10, m=10, ndec_limit=6, floor_c=0.0)
+    rep, x, hist, seg = gpu_solve("gse", A, b, G.CG, **ctrl)
+    ref = O.cg(A.indptr, b, O.make_params(tol=1e-10, max_iter=5000, preset="paper_cg", switch_mode=1,
+                                          orth=1, **ctrl),
+               A.indices, A.data, O.encode(A.indptr, A.indices, A.data, A.n_cols))
+    assert rep.status == G.OK and ref.status == O.OK
+    assert true_relres(A, x, b) <= 1e-10
+    assert list(rep.switch_iter) == list(ref.switch_iter)
+    assert list(rep.switch_trigger) == list(ref.switch_trigger)
+    assert rep.switch_trigger[0] in (1, 2, 3)  # Conditions 1-3, not the floor or tolerance
+    # the residual histories agree to the rounding CG accumulates over ~50
+    # iterations and a residual replacement (different reduction trees)
+    assert np.allclose(hist[: rep.switch_iter[1] + 1], ref.hist[: rep.switch_iter[1] + 1],
+                       rtol=1e-6, atol=0)
 
 
 def test_cg_small_dense_and_edge_cases():
