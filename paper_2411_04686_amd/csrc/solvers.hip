@@ -407,20 +407,25 @@ template <int RPT, int L>
 hipError_t launch_cg_small_rl(const SpmvOperand& op, int s, SolverState* S, double* x, double* r,
                               double* p, double* q, double* hist, int* seg_hist, hipStream_t st) {
   const dim3 g(1), b(kSmallThreads);
+#define GSE_SMALL(F) \
+  hipLaunchKernelGGL((k_cg_small<F, RPT, L>), g, b, 0, st, S, op, x, r, p, q, hist, seg_hist)
   switch (s) {
-    case 0: hipLaunchKernelGGL((k_cg_small<0, RPT, L>), g, b, 0, st, S, op, x, r, p, q, hist, seg_hist); break;
-    case 1: hipLaunchKernelGGL((k_cg_small<1, RPT, L>), g, b, 0, st, S, op, x, r, p, q, hist, seg_hist); break;
-    case 2: hipLaunchKernelGGL((k_cg_small<2, RPT, L>), g, b, 0, st, S, op, x, r, p, q, hist, seg_hist); break;
-    default: hipLaunchKernelGGL((k_cg_small<3, RPT, L>), g, b, 0, st, S, op, x, r, p, q, hist, seg_hist); break;
+    case 0: GSE_SMALL(0); break;
+    case 1: GSE_SMALL(1); break;
+    case 2: GSE_SMALL(2); break;
+    default: GSE_SMALL(3); break;
   }
+#undef GSE_SMALL
   return hipGetLastError();
 }
 
 template <int L>
 hipError_t launch_cg_small_l(const SpmvOperand& op, int s, SolverState* S, double* x, double* r,
                              double* p, double* q, double* hist, int* seg_hist, hipStream_t st) {
-  if (op.n_rows <= kSmallThreads) return launch_cg_small_rl<1, L>(op, s, S, x, r, p, q, hist, seg_hist, st);
-  if (op.n_rows <= 2 * kSmallThreads) return launch_cg_small_rl<2, L>(op, s, S, x, r, p, q, hist, seg_hist, st);
+  if (op.n_rows <= kSmallThreads)
+    return launch_cg_small_rl<1, L>(op, s, S, x, r, p, q, hist, seg_hist, st);
+  if (op.n_rows <= 2 * kSmallThreads)
+    return launch_cg_small_rl<2, L>(op, s, S, x, r, p, q, hist, seg_hist, st);
   return launch_cg_small_rl<4, L>(op, s, S, x, r, p, q, hist, seg_hist, st);
 }
 
