@@ -592,8 +592,12 @@ template <int FMT>
 struct RingLayout {
   static constexpr int T = kRingTile;
   static constexpr int TL = T + kLook;      // staged non-zeros per tile
-  static constexpr int RP = 320;            // row pointers staged per tile
-  static constexpr int D = (FMT == 1 || FMT == 2) ? 4 : 3;
+  static constexpr int RP = 256;            // row pointers staged per tile
+  // Three stages for every format: 22-42 KiB per workgroup, so six or seven
+  // workgroups share a CU (four stages of 320 row pointers fitted five for
+  // s = 1: same time on 128^3, 4-9 % slower on the 1024^2 operator, whose
+  // shorter runs per workgroup gain from the wider grid).
+  static constexpr int D = 3;
   static constexpr int OFF_COL = 0;
   static constexpr int OFF_HEAD = TL * 4;
   static constexpr int OFF_T1 = OFF_HEAD + TL * 2;

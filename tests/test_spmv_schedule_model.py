@@ -173,12 +173,12 @@ def test_short_row_kernel_full_size_diffusion3d_128():
 
 
 # ---- ring schedule (producer wave + LDS ring), short rows, 1024-nnz tiles ----
-RING_T, RING_LOOK, RING_RP, RING_CONS = 1024, 32, 320, 192
+RING_T, RING_LOOK, RING_RP, RING_CONS = 1024, 32, 256, 192
 
 
 def ring_layout(fmt):
     TL = RING_T + RING_LOOK
-    D = 4 if fmt in (1, 2) else 3
+    D = 3
     off_head = TL * 4
     off_t1 = off_head + TL * 2
     off_t2 = off_t1 + TL * 2
