@@ -145,12 +145,32 @@ __global__ __launch_bounds__(256) void k_encode(const double* __restrict__ val,
     uint32_t cw[8], t2[8], hh[4], tt[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) hh[k] = tt[k] = 0u;
+    // All sixteen loads of a group go out before any arithmetic: behind a
+    // per-value `j < nnz` branch each load waited for itself.  Only the
+    // last, partial group keeps the guard.
+    uint64_t uv[8];
+    int cv[8];
+    if (g * 8 + 8 <= nnz) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        uv[k] = double_to_bits(val[g * 8 + k]);
+        cv[k] = col[g * 8 + k];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int j = g * 8 + k;
+        uv[k] = j < nnz ? double_to_bits(val[j]) : 0u;
+        cv[k] = j < nnz ? col[j] : 0;
+      }
+    }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int j = g * 8 + k;
       uint32_t c = 0, h16 = 0, t116 = 0, t232 = 0;
       if (j < nnz) {
-        const uint64_t u = double_to_bits(val[j]);
+        const uint64_t u = uv[k];
         const int e = (int)((u >> 52) & 0x7FFu);
         int slot = -1, best = 1 << 30;
 #pragma unroll
@@ -169,7 +189,7 @@ __global__ __launch_bounds__(256) void k_encode(const double* __restrict__ val,
           const int sh = 11 - (best - (e ? e : 1));
           F = (sh >= 0) ? (sig << sh) : ((-sh >= 64) ? 0 : (sig >> (-sh)));
         }
-        c = (uint32_t)col[j] | ((uint32_t)slot << 29);
+        c = (uint32_t)cv[k] | ((uint32_t)slot << 29);
         h16 = (uint32_t)((u >> 63) << 15) | (uint32_t)(F >> 48);
         t116 = (uint32_t)((F >> 32) & 0xFFFFu);
         t232 = (uint32_t)(F & 0xFFFFFFFFu);
@@ -224,17 +244,31 @@ __global__ __launch_bounds__(256) void k_eta(const int32_t* __restrict__ row_ptr
   const int grp = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
   const int ngrp = (gridDim.x * blockDim.x) >> 3;
   double m[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int r = grp; r < n_rows; r += ngrp) {
-    double a[4] = {0.0, 0.0, 0.0, 0.0};
-    const int e = row_ptr[r + 1];
-    for (int j = row_ptr[r] + sub; j < e; j += 8) {
-      const double v = val[j];
-      const uint32_t c = col_idx[j], h = head[j], t1 = tail1[j], t2 = tail2[j];
-      a[0] += fabs(v);
-      a[1] += fabs(v - value_s(c, h, t1, t2, S, 1));
-      a[2] += fabs(v - value_s(c, h, t1, t2, S, 2));
-      a[3] += fabs(v - value_s(c, h, t1, t2, S, 3));
-    }
+  // One row per eight lanes, two rows per pass: the first eight entries of
+  // both rows are loaded unconditionally (clamped into the row, masked when
+  // past its end) before any arithmetic, so a pass costs one memory round
+  // trip after the row pointers; longer rows continue in a loop.  Each
+  // lane adds its entries of a row in the order j = start + sub, +8, ...
+  struct Ent {
+    double v;
+    uint32_t c, h, t1, t2;
+  };
+  auto load_ent = [&](int j) {
+    return Ent{val[j], col_idx[j], head[j], tail1[j], tail2[j]};
+  };
+  // adds the four terms of entry x, or exact zeros when !use (the sums are
+  // non-negative, so a + 0.0 == a) -- no branch for the loads to sink into
+  auto add_terms = [&](double (&a)[4], const Ent& x, bool use) {
+    const double t0 = fabs(x.v);
+    const double t1 = fabs(x.v - value_s(x.c, x.h, x.t1, x.t2, S, 1));
+    const double t2 = fabs(x.v - value_s(x.c, x.h, x.t1, x.t2, S, 2));
+    const double t3 = fabs(x.v - value_s(x.c, x.h, x.t1, x.t2, S, 3));
+    a[0] += use ? t0 : 0.0;
+    a[1] += use ? t1 : 0.0;
+    a[2] += use ? t2 : 0.0;
+    a[3] += use ? t3 : 0.0;
+  };
+  auto finish = [&](double (&a)[4]) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       double t = a[q];
@@ -243,6 +277,25 @@ __global__ __launch_bounds__(256) void k_eta(const int32_t* __restrict__ row_ptr
       t += __shfl_xor(t, 1, 64);
       m[q] = fmax(m[q], t);
     }
+  };
+  const int nnz = row_ptr[n_rows];
+  for (int r = grp; r < n_rows; r += 2 * ngrp) {
+    const int r2 = r + ngrp;
+    const bool has2 = r2 < n_rows;
+    const int a0 = row_ptr[r], a1 = row_ptr[r + 1];
+    const int b0 = has2 ? row_ptr[r2] : 0, b1 = has2 ? row_ptr[r2 + 1] : 0;
+    double a[4] = {0.0, 0.0, 0.0, 0.0}, b[4] = {0.0, 0.0, 0.0, 0.0};
+    if (nnz > 0) {
+      const int ja = a0 + sub, jb = b0 + sub;
+      const Ent ea = load_ent(max(min(ja, a1 - 1), 0));
+      const Ent eb = load_ent(max(min(jb, b1 - 1), 0));
+      add_terms(a, ea, ja < a1);
+      add_terms(b, eb, jb < b1);
+      for (int j = ja + 8; j < a1; j += 8) add_terms(a, load_ent(j), true);
+      for (int j = jb + 8; j < b1; j += 8) add_terms(b, load_ent(j), true);
+    }
+    finish(a);
+    if (has2) finish(b);
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -254,7 +307,13 @@ __global__ __launch_bounds__(256) void k_eta(const int32_t* __restrict__ row_ptr
   if (threadIdx.x < 4) {
     double t = 0.0;
     for (int w = 0; w < kWaves; ++w) t = fmax(t, red[threadIdx.x][w]);
-    atomicMax(&sc->norm_bits[threadIdx.x], (unsigned long long)double_to_bits(t));
+    // the four maxima share one cache line, where every atomic serialises:
+    // skip it when the value already there (possibly stale, hence only
+    // ever smaller) is not below this workgroup's
+    const unsigned long long bits = (unsigned long long)double_to_bits(t);
+    if (__hip_atomic_load(&sc->norm_bits[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+        bits)
+      atomicMax(&sc->norm_bits[threadIdx.x], bits);
   }
 }
 
@@ -278,7 +337,7 @@ hipError_t launch_encode(const int32_t* row_ptr, const int32_t* col, const doubl
   hipLaunchKernelGGL(k_encode, dim3(eb), dim3(256), 0, st, val, col, nnz, sc, A->col_idx, A->head,
                      A->tail1, A->tail2);
   int rbk = (n_rows + 31) / 32;
-  rbk = rbk < 1 ? 1 : (rbk > 1024 ? 1024 : rbk);
+  rbk = rbk < 1 ? 1 : (rbk > 4096 ? 4096 : rbk);
   hipLaunchKernelGGL(k_eta, dim3(rbk), dim3(256), 0, st, row_ptr, n_rows, val, A->col_idx, A->head,
                      A->tail1, A->tail2, sc);
   return hipGetLastError();
