@@ -207,7 +207,10 @@ typedef struct gse_params {
     double floor_c;           /* floor trigger factor, 0 disables */
     int32_t switch_mode;      /* CG after a switch: 0 p = r, 1 keep p */
     int32_t record_history;   /* kept for callers; the history is always recorded */
-    int32_t launch_mode;      /* 0: iterations replayed from HIP graphs, 1: direct launches */
+    int32_t launch_mode;      /* 0: iterations replayed from HIP graphs, 1: direct launches
+                                 (CG on systems of at most 4096 rows whose rows hold at most 8
+                                 non-zeros runs every iteration of a segment count in one
+                                 launch of one workgroup, in either mode) */
 } gse_params;
 
 typedef struct gse_report {
@@ -232,7 +235,8 @@ gse_status gse_solver_workspace(int32_t method, int32_t n_rows, int64_t nnz, int
 
 /* Stepped (or fixed-segment) CG.  b: device [n], x: device [n], x0 on
  * entry, solution on return.  Blocks until the solve ends.  Returns
- * GSE_OK, GSE_NOT_CONVERGED, GSE_ERR_BREAKDOWN or an error. */
+ * GSE_OK, GSE_NOT_CONVERGED, GSE_ERR_BREAKDOWN or an error.  Results are
+ * bit-reproducible for a given operator, format and parameter set. */
 gse_status gse_cg(const gse_matrix* A, const double* b, double* x, const gse_params* p,
                   gse_report* rep, void* ws, size_t ws_bytes, void* stream);
 
