@@ -737,7 +737,10 @@ __device__ __forceinline__ double ring_value(const lds_char* stage, int pos, con
   return decode<FMT>(c, h, t1, t2, v, scale, column);
 }
 
-template <int FMT>
+// B non-zeros per batch of a row: the operator's longest row when that is
+// at most eight (then one batch covers every row and no lane gathers for a
+// padding slot), else eight.  The sums run in row order for every B.
+template <int FMT, int B>
 __global__ __launch_bounds__(kRingThreads) void k_spmv_ring(SpmvOperand A,
                                                             const double* __restrict__ x,
                                                             double* __restrict__ y, SpmvEpilogue ep) {
@@ -797,19 +800,19 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_ring(SpmvOperand A,
         const int o = s0 - j0;
         const int len = s1 - s0;
         double sum = 0.0;
-        for (int kb = 0; kb < len; kb += 8) {
-          double v[8], xv[8];
-          int c[8];
+        for (int kb = 0; kb < len; kb += B) {
+          double v[B], xv[B];
+          int c[B];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
+          for (int q = 0; q < B; ++q) {
             int col;
             v[q] = ring_value<FMT>(stage, o + kb + q, scale, col);
             c[q] = (kb + q < len) ? col : 0;
           }
 #pragma unroll
-          for (int q = 0; q < 8; ++q) xv[q] = x[c[q]];
+          for (int q = 0; q < B; ++q) xv[q] = x[c[q]];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
+          for (int q = 0; q < B; ++q) {
             const double p = __dmul_rn(v[q], xv[q]);
             sum = (kb + q < len) ? __dadd_rn(sum, p) : sum;
           }
@@ -846,7 +849,7 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_ring(SpmvOperand A,
 // compute units), cached per instance.
 enum Kind : int { kGeneralTiles = 0, kShortTiles = 1, kRingTiles = 2 };
 
-template <int FMT, int E, int KIND>
+template <int FMT, int E, int KIND, int B = 8>
 int resident_groups() {
   static int cached = 0;
   if (cached == 0) {
@@ -856,7 +859,7 @@ int resident_groups() {
       return 0;
     hipError_t e;
     if constexpr (KIND == kRingTiles)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv_ring<FMT>, kRingThreads, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv_ring<FMT, B>, kRingThreads, 0);
     else if constexpr (KIND == kShortTiles)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv_short<FMT, E>, kWG, 0);
     else
@@ -872,14 +875,24 @@ int resident_groups() {
 // so launches that leave per-workgroup partial sums group them per format:
 // results are bit-reproducible for a given format and matrix, and two
 // formats that decode to the same values agree to rounding.
-template <int FMT, int E, int KIND>
+template <int FMT, int E, int KIND, int B = 8>
 int grid_for(const SpmvOperand& A) {
-  int g = resident_groups<FMT, E, KIND>();
+  int g = resident_groups<FMT, E, KIND, B>();
   if (g <= 0) return 0;
   const int need = (A.n_tiles + 7) / 8 * 8;
   if (g > need) g = need;
   if (g < 8) g = 8;
   return g;
+}
+
+template <int FMT, int B>
+hipError_t launch_ring(const SpmvOperand& A, const double* x, double* y, const SpmvEpilogue& ep,
+                       hipStream_t st) {
+  const int g = grid_for<FMT, 4, kRingTiles, B>(A);
+  if (g <= 0) return hipErrorInvalidDevice;
+  if (ep.grid_out) *ep.grid_out = g;
+  hipLaunchKernelGGL((k_spmv_ring<FMT, B>), dim3(g), dim3(kRingThreads), 0, st, A, x, y, ep);
+  return hipGetLastError();
 }
 
 // Schedule for one tile size: the ring for short rows in 1024-non-zero
@@ -891,11 +904,10 @@ hipError_t launch_fe(const SpmvOperand& A, const double* x, double* y, const Spm
   int g = 0;
   if constexpr (E * kWG == kRingTile) {
     if (short_rows && A.nnz >= kRingTile) {
-      g = grid_for<FMT, E, kRingTiles>(A);
-      if (g <= 0) return hipErrorInvalidDevice;
-      if (ep.grid_out) *ep.grid_out = g;
-      hipLaunchKernelGGL((k_spmv_ring<FMT>), dim3(g), dim3(kRingThreads), 0, st, A, x, y, ep);
-      return hipGetLastError();
+      if (A.max_row <= 3) return launch_ring<FMT, 3>(A, x, y, ep, st);
+      if (A.max_row <= 5) return launch_ring<FMT, 5>(A, x, y, ep, st);
+      if (A.max_row <= 7) return launch_ring<FMT, 7>(A, x, y, ep, st);
+      return launch_ring<FMT, 8>(A, x, y, ep, st);
     }
   }
   if (short_rows) {

@@ -238,7 +238,10 @@ def check_ring(indptr, n_cols, cols, fmt):
             ln = indptr[ra + 1:rb + 1] - s0
             o = s0 - j0
             assert o.min() >= 0 and o.max() < T and (o + ln).max() <= TL
-            assert (o + (np.maximum(ln, 1) - 1) // 8 * 8 + 7).max() < TL
+            # batch width: the longest row when at most eight, else eight
+            m = int(np.diff(indptr).max(initial=0))
+            B = 3 if m <= 3 else 5 if m <= 5 else 7 if m <= 7 else 8
+            assert (o + (np.maximum(ln, 1) - 1) // B * B + B - 1).max() < TL
     assert int(cols.max(initial=0)) < n_cols
     assert L["D"] * L["stage"] <= 64 * 1024
 
