@@ -30,6 +30,8 @@
 // the planes into LDS for three consumer waves (k_spmv_ring).  Every sum has
 // a fixed order, so results are bit-reproducible and identical whether a
 // matrix runs alone or next to others.
+#include <atomic>
+
 #include "decode.h"
 #include "gse_internal.h"
 
@@ -846,12 +848,14 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_ring(SpmvOperand A,
 }
 
 // Resident workgroups of one kernel instance on this device (occupancy x
-// compute units), cached per instance.
+// compute units), cached per instance.  Threads that race on the first call
+// compute and store the same value.
 enum Kind : int { kGeneralTiles = 0, kShortTiles = 1, kRingTiles = 2 };
 
 template <int FMT, int E, int KIND, int B = 8>
 int resident_groups() {
-  static int cached = 0;
+  static std::atomic<int> cache{0};
+  int cached = cache.load(std::memory_order_relaxed);
   if (cached == 0) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -866,6 +870,7 @@ int resident_groups() {
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv<FMT, E>, kWG, 0);
     if (e != hipSuccess) return 0;
     cached = cus * (per_cu > 0 ? per_cu : 1);
+    cache.store(cached, std::memory_order_relaxed);
   }
   return cached;
 }
