@@ -64,8 +64,10 @@ def kernel_name(A):
     if A.max_row_nnz <= 24:
         if A.tile_nnz == 1024 and A.nnz >= 1024:
             m = A.max_row_nnz
-            b = 3 if m <= 3 else 5 if m <= 5 else 7 if m <= 7 else 8
-            return f"k_spmv_ring<1, {b}>"
+            if m <= 8:
+                b = 3 if m <= 3 else 5 if m <= 5 else 7 if m <= 7 else 8
+                return f"k_spmv_rows<1, {b}>"
+            return "k_spmv_ring<1>"
         return f"k_spmv_short<1, {e}>"
     return f"k_spmv<1, {e}>"
 

@@ -27,7 +27,9 @@
 // Matrices whose rows all hold at most kShortRow non-zeros (stencils) use a
 // lean variant without the row machinery of phases 3-4 (k_spmv_short) and,
 // in 1024-non-zero tiles, a ring schedule in which one producer wave streams
-// the planes into LDS for three consumer waves (k_spmv_ring).  Every sum has
+// the planes into LDS for three consumer waves (k_spmv_ring; k_spmv_rows
+// when no row holds more than eight non-zeros: 192-row tiles, one row per
+// consumer lane).  Every sum has
 // a fixed order, so results are bit-reproducible and identical whether a
 // matrix runs alone or next to others.
 #include <atomic>
@@ -590,16 +592,14 @@ constexpr int kRingTile = 1024;          // non-zeros per tile (the plan's tile_
 constexpr int kRingConsumers = 3 * 64;   // consumer threads
 constexpr int kRingThreads = kRingConsumers + 64;
 
-template <int FMT>
-struct RingLayout {
-  static constexpr int T = kRingTile;
-  static constexpr int TL = T + kLook;      // staged non-zeros per tile
-  static constexpr int RP = 256;            // row pointers staged per tile
-  // Three stages for every format: 22-42 KiB per workgroup, so six or seven
-  // workgroups share a CU (four stages of 320 row pointers fitted five for
-  // s = 1: same time on 128^3, 4-9 % slower on the 1024^2 operator, whose
-  // shorter runs per workgroup gain from the wider grid).
-  static constexpr int D = 3;
+// LDS ring geometry: D stages, each holding the planes of TL staged
+// non-zeros (column words first, then the value or the segment planes) and
+// RP row pointers.
+template <int FMT, int TL_, int D_>
+struct RingGeom {
+  static constexpr int TL = TL_;            // staged non-zeros per stage
+  static constexpr int RP = 256;            // row pointers staged per stage
+  static constexpr int D = D_;
   static constexpr int OFF_COL = 0;
   static constexpr int OFF_HEAD = TL * 4;
   static constexpr int OFF_T1 = OFF_HEAD + TL * 2;
@@ -625,11 +625,21 @@ struct RingLayout {
   static constexpr int SPILL_COL = NCOL * 1024 - TL * 4;
   static constexpr int SPILL_HALF = NHALF * 1024 - TL * 2;
   static constexpr int SPILL_VAL = NVAL * 1024 - TL * 8;
-  static_assert(kLook % 8 == 0 && RP % 64 == 0, "chunking");
+  static_assert(TL % 16 == 0 && RP % 64 == 0, "chunking");
   static_assert(SPILL_COL <= TL * 2 && SPILL_COL <= RP * 4 && SPILL_HALF <= RP * 4 &&
                     SPILL_HALF <= TL * 2 && SPILL_VAL <= RP * 4,
                 "a region's spill must stay inside the region loaded after it");
   static_assert((D - 1) * NI < 64, "the vector-memory counter holds at most 63");
+};
+
+// Non-zero tiles of kRingTile entries plus the look-ahead.  Three stages for
+// every format: 22-42 KiB per workgroup, so six or seven workgroups share a
+// CU (four stages of 320 row pointers fitted five for s = 1: same time on
+// 128^3, 4-9 % slower on the 1024^2 operator, whose shorter runs per
+// workgroup gain from the wider grid).
+template <int FMT>
+struct RingLayout : RingGeom<FMT, kRingTile + kLook, 3> {
+  static constexpr int T = kRingTile;
 };
 
 // s_waitcnt vmcnt(N), leaving the other counters alone (gfx9 encoding).
@@ -641,9 +651,9 @@ __device__ __forceinline__ void wait_vmcnt() {
 
 // The producer's stage k has landed once at most `later` stages issued
 // after it are still outstanding.
-template <int FMT>
+template <class L>
 __device__ __forceinline__ void ring_wait(int later) {
-  constexpr int NI = RingLayout<FMT>::NI;
+  constexpr int NI = L::NI;
   switch (later) {
     case 0: wait_vmcnt<0>(); break;
     case 1: wait_vmcnt<NI>(); break;
@@ -675,11 +685,9 @@ __device__ __forceinline__ void consumer_barrier() {
 // clamped into the padded planes (pad is a multiple of 16, so a chunk is
 // either inside or wholly past it) and row indices to n_rows; clamped data
 // lands in slots that are never read.
-template <int FMT>
-__device__ __forceinline__ void ring_issue(const SpmvOperand& A, lds_char* stage, int t, int ra,
+template <int FMT, class L>
+__device__ __forceinline__ void ring_issue(const SpmvOperand& A, lds_char* stage, int j0, int ra,
                                            int pad, int lane) {
-  using L = RingLayout<FMT>;
-  const int j0 = t * L::T;
 #pragma unroll
   for (int i = 0; i < L::NCOL; ++i) {
     const int e = min(j0 + 4 * (i * 64 + lane), pad - 4);
@@ -720,10 +728,9 @@ __device__ __forceinline__ void ring_issue(const SpmvOperand& A, lds_char* stage
 }
 
 // Consumer: the decoded value and column of staged non-zero `pos`.
-template <int FMT>
+template <int FMT, class L>
 __device__ __forceinline__ double ring_value(const lds_char* stage, int pos, const double* scale,
                                              int& column) {
-  using L = RingLayout<FMT>;
   typedef const __attribute__((address_space(3))) uint32_t* u32p;
   typedef const __attribute__((address_space(3))) uint16_t* u16p;
   const uint32_t c = *reinterpret_cast<u32p>(stage + L::OFF_COL + 4 * pos);
@@ -739,10 +746,7 @@ __device__ __forceinline__ double ring_value(const lds_char* stage, int pos, con
   return decode<FMT>(c, h, t1, t2, v, scale, column);
 }
 
-// B non-zeros per batch of a row: the operator's longest row when that is
-// at most eight (then one batch covers every row and no lane gathers for a
-// padding slot), else eight.  The sums run in row order for every B.
-template <int FMT, int B>
+template <int FMT>
 __global__ __launch_bounds__(kRingThreads) void k_spmv_ring(SpmvOperand A,
                                                             const double* __restrict__ x,
                                                             double* __restrict__ y, SpmvEpilogue ep) {
@@ -773,7 +777,7 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_ring(SpmvOperand A,
       const int ra = trow[t];
       const int rb = trow[t + 1];
       const int st = k % L::D;
-      ring_issue<FMT>(A, ring + st * L::STAGE, t, ra, pad, lane);
+      ring_issue<FMT, L>(A, ring + st * L::STAGE, t * L::T, ra, pad, lane);
       if (lane == 0) {
         hdr[st][0] = ra;
         hdr[st][1] = rb;
@@ -782,7 +786,7 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_ring(SpmvOperand A,
     };
     for (int k = 0; k < L::D - 1 && k < count; ++k) issue(k);
     for (int k = 0; k < count; ++k) {
-      ring_wait<FMT>(min(L::D - 2, count - 1 - k));
+      ring_wait<L>(min(L::D - 2, count - 1 - k));
       producer_barrier();  // A
       if (k + L::D - 1 < count) issue(k + L::D - 1);  // the stage consumed in tile k-1
       producer_barrier();  // B
@@ -802,19 +806,19 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_ring(SpmvOperand A,
         const int o = s0 - j0;
         const int len = s1 - s0;
         double sum = 0.0;
-        for (int kb = 0; kb < len; kb += B) {
-          double v[B], xv[B];
-          int c[B];
+        for (int kb = 0; kb < len; kb += 8) {
+          double v[8], xv[8];
+          int c[8];
 #pragma unroll
-          for (int q = 0; q < B; ++q) {
+          for (int q = 0; q < 8; ++q) {
             int col;
-            v[q] = ring_value<FMT>(stage, o + kb + q, scale, col);
+            v[q] = ring_value<FMT, L>(stage, o + kb + q, scale, col);
             c[q] = (kb + q < len) ? col : 0;
           }
 #pragma unroll
-          for (int q = 0; q < B; ++q) xv[q] = x[c[q]];
+          for (int q = 0; q < 8; ++q) xv[q] = x[c[q]];
 #pragma unroll
-          for (int q = 0; q < B; ++q) {
+          for (int q = 0; q < 8; ++q) {
             const double p = __dmul_rn(v[q], xv[q]);
             sum = (kb + q < len) ? __dadd_rn(sum, p) : sum;
           }
@@ -847,10 +851,128 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_ring(SpmvOperand A,
   }
 }
 
+// Row-tile ring for operators whose rows all hold at most B <= 8 non-zeros
+// (stencils): tile t is rows 192t .. 192t+191, one row per consumer lane, so
+// every lane of the three consumer waves has a row and each row is one batch
+// of B.  The producer reads the tile's first row pointer through a scalar
+// load and stages the window that starts there, rounded down to 16
+// non-zeros (chunk alignment), with 192 B + 16 entries: the tile's rows hold
+// at most 192 B non-zeros, so the window covers them and every unconditional
+// B-wide read of a row.  No tile table: the schedule follows from n_rows.
+// Two stages: 18-35 KiB per workgroup, eight workgroups per CU at s = 1
+// (three stages, five per CU, were 2-6 % slower on 128^3 and up to 9 % on
+// the 1024^2 operator).
+constexpr int kRowTile = kRingConsumers;
+
+template <int FMT, int B>
+using RowRing = RingGeom<FMT, kRowTile * B + 16, 2>;
+
+template <int FMT, int B>
+__global__ __launch_bounds__(kRingThreads) void k_spmv_rows(SpmvOperand A,
+                                                            const double* __restrict__ x,
+                                                            double* __restrict__ y, SpmvEpilogue ep) {
+  using L = RowRing<FMT, B>;
+  constexpr int PRODUCER = kRingConsumers / 64;
+  __shared__ __attribute__((aligned(16))) char ring_raw[L::D * L::STAGE];
+  __shared__ int hdr[L::D][4];  // per stage: first row, row end, first staged non-zero
+  __shared__ double scale[16];
+  __shared__ double red[kRingThreads / 64];
+  lds_char* ring = (lds_char*)ring_raw;
+
+  if (ep.gate && *ep.gate) return;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  build_scale<FMT>(A.sem, scale);
+  const int pad = (A.nnz + 15) & ~15;
+  const int n_rt = (A.n_rows + kRowTile - 1) / kRowTile;
+  TileWalk walk(n_rt);
+  const int count = walk.t < walk.end ? (walk.end - walk.t + walk.step - 1) / walk.step : 0;
+  double acc = 0.0;
+  __syncthreads();
+  if (wave == PRODUCER) {
+    const __attribute__((address_space(4))) int32_t* rp =
+        (const __attribute__((address_space(4))) int32_t*)(A.row_ptr);
+    auto issue = [&](int k) {
+      const int t = walk.t + k * walk.step;
+      const int ra = t * kRowTile;
+      const int rb = min(ra + kRowTile, A.n_rows);
+      const int ja = rp[ra] & ~15;
+      const int st = k % L::D;
+      ring_issue<FMT, L>(A, ring + st * L::STAGE, ja, ra, pad, lane);
+      if (lane == 0) {
+        hdr[st][0] = ra;
+        hdr[st][1] = rb;
+        hdr[st][2] = ja;
+      }
+    };
+    for (int k = 0; k < L::D - 1 && k < count; ++k) issue(k);
+    for (int k = 0; k < count; ++k) {
+      ring_wait<L>(min(L::D - 2, count - 1 - k));
+      producer_barrier();  // A
+      if (k + L::D - 1 < count) issue(k + L::D - 1);  // the stage consumed in tile k-1
+      producer_barrier();  // B
+    }
+  } else {
+    for (int k = 0; k < count; ++k) {
+      consumer_barrier();  // A
+      const int st = k % L::D;
+      const lds_char* stage = ring + st * L::STAGE;
+      const int ra = hdr[st][0], rb = hdr[st][1], ja = hdr[st][2];
+      const __attribute__((address_space(3))) int* rps =
+          reinterpret_cast<const __attribute__((address_space(3))) int*>(stage + L::OFF_RPS);
+      const int r = ra + tid;
+      if (r < rb) {
+        const int s0 = rps[tid], s1 = rps[tid + 1];
+        const int o = s0 - ja;
+        const int len = s1 - s0;
+        double v[B], xv[B];
+        int c[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+          int col;
+          v[q] = ring_value<FMT, L>(stage, o + q, scale, col);
+          c[q] = (q < len) ? col : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < B; ++q) xv[q] = x[c[q]];
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+          const double p = __dmul_rn(v[q], xv[q]);
+          sum = (q < len) ? __dadd_rn(sum, p) : sum;
+        }
+        if (ep.epi == kEpiPlain) {
+          y[r] = sum;
+        } else if (ep.epi == kEpiDot) {
+          y[r] = sum;
+          acc += ep.aux[r] * sum;
+        } else {
+          const double vres = ep.aux[r] - sum;
+          y[r] = vres;
+          acc += vres * vres;
+        }
+      }
+      consumer_barrier();  // B
+    }
+  }
+  if (ep.epi != kEpiPlain) {
+    const double w = wave_sum(acc);
+    __syncthreads();
+    if (lane == 0) red[wave] = w;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < kRingThreads / 64; ++i) t += red[i];
+      ep.partials[blockIdx.x] = t;
+    }
+  }
+}
+
 // Resident workgroups of one kernel instance on this device (occupancy x
 // compute units), cached per instance.  Threads that race on the first call
 // compute and store the same value.
-enum Kind : int { kGeneralTiles = 0, kShortTiles = 1, kRingTiles = 2 };
+enum Kind : int { kGeneralTiles = 0, kShortTiles = 1, kRingTiles = 2, kRowTiles = 3 };
 
 template <int FMT, int E, int KIND, int B = 8>
 int resident_groups() {
@@ -862,8 +984,10 @@ int resident_groups() {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return 0;
     hipError_t e;
-    if constexpr (KIND == kRingTiles)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv_ring<FMT, B>, kRingThreads, 0);
+    if constexpr (KIND == kRowTiles)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv_rows<FMT, B>, kRingThreads, 0);
+    else if constexpr (KIND == kRingTiles)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv_ring<FMT>, kRingThreads, 0);
     else if constexpr (KIND == kShortTiles)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv_short<FMT, E>, kWG, 0);
     else
@@ -890,18 +1014,34 @@ int grid_for(const SpmvOperand& A) {
   return g;
 }
 
-template <int FMT, int B>
+template <int FMT>
 hipError_t launch_ring(const SpmvOperand& A, const double* x, double* y, const SpmvEpilogue& ep,
                        hipStream_t st) {
-  const int g = grid_for<FMT, 4, kRingTiles, B>(A);
+  const int g = grid_for<FMT, 4, kRingTiles>(A);
   if (g <= 0) return hipErrorInvalidDevice;
   if (ep.grid_out) *ep.grid_out = g;
-  hipLaunchKernelGGL((k_spmv_ring<FMT, B>), dim3(g), dim3(kRingThreads), 0, st, A, x, y, ep);
+  hipLaunchKernelGGL((k_spmv_ring<FMT>), dim3(g), dim3(kRingThreads), 0, st, A, x, y, ep);
   return hipGetLastError();
 }
 
-// Schedule for one tile size: the ring for short rows in 1024-non-zero
-// tiles, else the lean short-row tiles, else the general tiles.
+template <int FMT, int B>
+hipError_t launch_rows(const SpmvOperand& A, const double* x, double* y, const SpmvEpilogue& ep,
+                       hipStream_t st) {
+  int g = resident_groups<FMT, 4, kRowTiles, B>();
+  if (g <= 0) return hipErrorInvalidDevice;
+  const int n_rt = (A.n_rows + kRowTile - 1) / kRowTile;
+  const int need = (n_rt + 7) / 8 * 8;
+  if (g > need) g = need;
+  if (g < 8) g = 8;
+  if (ep.grid_out) *ep.grid_out = g;
+  hipLaunchKernelGGL((k_spmv_rows<FMT, B>), dim3(g), dim3(kRingThreads), 0, st, A, x, y, ep);
+  return hipGetLastError();
+}
+
+// Schedule for one tile size.  With the default 1024-non-zero tiles: the
+// row-tile ring when no row holds more than eight non-zeros, the non-zero
+// ring for rows of up to kShortRow; otherwise (or in smaller matrices) the
+// lean short-row tiles, else the general tiles.
 template <int FMT, int E>
 hipError_t launch_fe(const SpmvOperand& A, const double* x, double* y, const SpmvEpilogue& ep,
                      hipStream_t st) {
@@ -909,10 +1049,11 @@ hipError_t launch_fe(const SpmvOperand& A, const double* x, double* y, const Spm
   int g = 0;
   if constexpr (E * kWG == kRingTile) {
     if (short_rows && A.nnz >= kRingTile) {
-      if (A.max_row <= 3) return launch_ring<FMT, 3>(A, x, y, ep, st);
-      if (A.max_row <= 5) return launch_ring<FMT, 5>(A, x, y, ep, st);
-      if (A.max_row <= 7) return launch_ring<FMT, 7>(A, x, y, ep, st);
-      return launch_ring<FMT, 8>(A, x, y, ep, st);
+      if (A.max_row <= 3) return launch_rows<FMT, 3>(A, x, y, ep, st);
+      if (A.max_row <= 5) return launch_rows<FMT, 5>(A, x, y, ep, st);
+      if (A.max_row <= 7) return launch_rows<FMT, 7>(A, x, y, ep, st);
+      if (A.max_row <= 8) return launch_rows<FMT, 8>(A, x, y, ep, st);
+      return launch_ring<FMT>(A, x, y, ep, st);
     }
   }
   if (short_rows) {

@@ -28,10 +28,13 @@ def test_kernel_name_follows_the_schedule():
         pass
     a = A()
     a.rv_lanes, a.tile_nnz, a.max_row_nnz, a.nnz = 0, 1024, 7, 5000
-    assert b.kernel_name(a) == "k_spmv_ring<1, 7>"
-    for m, bw in ((1, 3), (3, 3), (4, 5), (5, 5), (6, 7), (8, 8), (24, 8)):
+    assert b.kernel_name(a) == "k_spmv_rows<1, 7>"
+    for m, bw in ((1, 3), (3, 3), (4, 5), (5, 5), (6, 7), (8, 8)):
         a.max_row_nnz = m
-        assert b.kernel_name(a) == f"k_spmv_ring<1, {bw}>"
+        assert b.kernel_name(a) == f"k_spmv_rows<1, {bw}>"
+    for m in (9, 24):
+        a.max_row_nnz = m
+        assert b.kernel_name(a) == "k_spmv_ring<1>"
     a.max_row_nnz = 7
     a.nnz = 900
     assert b.kernel_name(a) == "k_spmv_short<1, 4>"

@@ -176,9 +176,7 @@ def test_short_row_kernel_full_size_diffusion3d_128():
 RING_T, RING_LOOK, RING_RP, RING_CONS = 1024, 32, 256, 192
 
 
-def ring_layout(fmt):
-    TL = RING_T + RING_LOOK
-    D = 3
+def ring_layout(fmt, TL=RING_T + RING_LOOK, D=3):
     off_head = TL * 4
     off_t1 = off_head + TL * 2
     off_t2 = off_t1 + TL * 2
@@ -238,10 +236,7 @@ def check_ring(indptr, n_cols, cols, fmt):
             ln = indptr[ra + 1:rb + 1] - s0
             o = s0 - j0
             assert o.min() >= 0 and o.max() < T and (o + ln).max() <= TL
-            # batch width: the longest row when at most eight, else eight
-            m = int(np.diff(indptr).max(initial=0))
-            B = 3 if m <= 3 else 5 if m <= 5 else 7 if m <= 7 else 8
-            assert (o + (np.maximum(ln, 1) - 1) // B * B + B - 1).max() < TL
+            assert (o + (np.maximum(ln, 1) - 1) // 8 * 8 + 7).max() < TL
     assert int(cols.max(initial=0)) < n_cols
     assert L["D"] * L["stage"] <= 64 * 1024
 
@@ -260,3 +255,69 @@ def test_ring_kernel_full_size_diffusion3d_128():
     A = diffusion3d(128, 0)
     for fmt in (0, 1, 2, 3):
         check_ring(A.indptr.astype(np.int64), A.n_cols, A.indices, fmt)
+
+
+# ---- row-tile ring (rows of at most B <= 8 non-zeros, 192 rows per tile) ----
+ROW_TILE = RING_CONS
+
+
+def batch_width(max_row):
+    return 3 if max_row <= 3 else 5 if max_row <= 5 else 7 if max_row <= 7 else 8
+
+
+def check_rows(indptr, n_cols, cols, fmt, D=2):
+    n_rows = indptr.size - 1
+    nnz = int(indptr[-1])
+    lens = np.diff(indptr)
+    B = batch_width(int(lens.max(initial=0)))
+    assert lens.max(initial=0) <= B <= 8
+    TL = ROW_TILE * B + 16
+    L = ring_layout(fmt, TL, D)
+    pad = (nnz + 15) // 16 * 16
+    assert nnz >= RING_T  # the launcher's condition
+    assert (L["D"] - 1) * L["ni"] < 64
+    assert L["D"] * L["stage"] <= 64 * 1024
+    regions = L["loads"] + [("rps", L["rps"], RING_RP * 4, None, RING_RP // 64)]
+    for k, (name, off, size, per, n) in enumerate(L["loads"]):
+        nxt = regions[k + 1]
+        assert nxt[1] == off + size
+        assert off + n * 1024 <= nxt[1] + nxt[2], name
+        assert n * 1024 >= size  # the loads cover the region
+    n_rt = -(-n_rows // ROW_TILE)
+    covered = np.zeros(n_rows, np.int32)
+    for t in range(n_rt):
+        ra, rb = t * ROW_TILE, min(t * ROW_TILE + ROW_TILE, n_rows)
+        ja = int(indptr[ra]) & ~15
+        for name, off, size, per, n in L["loads"]:
+            e = np.minimum(ja + per * np.arange(n * 64), pad - per)
+            assert e.min() >= 0 and (e + per).max() <= pad
+            assert np.all(e % per == 0)
+        assert ra + RING_RP - 1 >= rb  # staged row pointers ra .. rb
+        s0 = indptr[ra:rb].astype(np.int64)
+        ln = indptr[ra + 1:rb + 1] - s0
+        o = s0 - ja
+        covered[ra:rb] += 1
+        if rb > ra:
+            assert o.min() >= 0
+            # every lane reads B staged entries from o, inside the stage
+            assert (o + B - 1).max() < TL
+            # the entries a row uses lie in chunks loaded from inside the planes
+            assert (s0 + ln).max() <= nnz
+    assert np.all(covered == 1)
+    assert int(cols.max(initial=0)) < n_cols
+
+
+@pytest.mark.parametrize("fmt", [0, 1, 2, 3])
+@pytest.mark.parametrize("name", ["poisson2d_64", "diffusion3d_24", "convdiff2d_64", "diagonal_3000",
+                                  "sparse_many_empty", "fixed_rows_512x8"])
+def test_row_ring_kernel_in_bounds(name, fmt):
+    A = MATS[name]()
+    if np.diff(A.indptr).max(initial=0) > 8 or A.indptr[-1] < RING_T:
+        pytest.skip("the row-tile ring serves rows of at most eight in at least one full tile")
+    check_rows(A.indptr.astype(np.int64), A.n_cols, A.indices, fmt)
+
+
+def test_row_ring_kernel_full_size_operators():
+    for A in (diffusion3d(128, 0), convdiff2d(1024, 0)):
+        for fmt in (0, 1, 2, 3):
+            check_rows(A.indptr.astype(np.int64), A.n_cols, A.indices, fmt)
