@@ -146,7 +146,9 @@ gse_status gse_encode(const int32_t* row_ptr, const int32_t* col, const double* 
 
 /* (Re)build the SpMV schedule.  Two schedules exist:
  *   tiles       (rv_lanes == 0): fixed runs of tile_nnz non-zeros (1024, 2048
- *               or 4096) per workgroup step, rows of any length;
+ *               or 4096) per workgroup step, rows of any length; with 1024
+ *               and no row longer than eight non-zeros, runs of 192 rows
+ *               instead (the tile table is then not read);
  *   row-vector  (rv_lanes = 1, 2, 4, ..., 64): that many lanes per row,
  *               for matrices whose rows are short and of similar length.
  * rv_lanes == -1 picks the default (tiles).  The tile table is always
