@@ -48,6 +48,12 @@ def cases():
         "sparse_many_empty": lambda: random_sparse(6000, 6000, 9, mean_row=0.6, exp_spread=12),
         # non-zeros an exact multiple of the tile: the look-ahead past the end
         "fixed_rows_512x8": lambda: fixed_rows(512, 700, 8, 11),
+        # every row exactly as long as the row-tile batch (the fullest staged
+        # window for B = 3, 5, 7) and a last tile of fewer than 192 rows
+        "fixed_rows_1000x3": lambda: fixed_rows(1000, 1200, 3, 12),
+        "fixed_rows_777x5": lambda: fixed_rows(777, 800, 5, 13),
+        "fixed_rows_1111x7": lambda: fixed_rows(1111, 1500, 7, 14),
+        "fixed_rows_500x6": lambda: fixed_rows(500, 640, 6, 15),
     }
 
 

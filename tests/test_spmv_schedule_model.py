@@ -107,6 +107,10 @@ MATS = {
     "diagonal_3000": lambda: diagonal(3000, 10),
     "sparse_many_empty": lambda: random_sparse(6000, 6000, 9, mean_row=0.6, exp_spread=12),
     "fixed_rows_512x8": lambda: fixed_rows(512, 700, 8, 11),
+    "fixed_rows_1000x3": lambda: fixed_rows(1000, 1200, 3, 12),
+    "fixed_rows_777x5": lambda: fixed_rows(777, 800, 5, 13),
+    "fixed_rows_1111x7": lambda: fixed_rows(1111, 1500, 7, 14),
+    "fixed_rows_500x6": lambda: fixed_rows(500, 640, 6, 15),
 }
 
 
@@ -309,7 +313,8 @@ def check_rows(indptr, n_cols, cols, fmt, D=2):
 
 @pytest.mark.parametrize("fmt", [0, 1, 2, 3])
 @pytest.mark.parametrize("name", ["poisson2d_64", "diffusion3d_24", "convdiff2d_64", "diagonal_3000",
-                                  "sparse_many_empty", "fixed_rows_512x8"])
+                                  "sparse_many_empty", "fixed_rows_512x8", "fixed_rows_1000x3",
+                                  "fixed_rows_777x5", "fixed_rows_1111x7", "fixed_rows_500x6"])
 def test_row_ring_kernel_in_bounds(name, fmt):
     A = MATS[name]()
     if np.diff(A.indptr).max(initial=0) > 8 or A.indptr[-1] < RING_T:
