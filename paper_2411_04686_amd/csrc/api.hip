@@ -434,6 +434,7 @@ static gse_status batch_descs(int32_t n_sys, const gse_system* sys, const gse_pa
       B.n_rows = A->n_rows;
       B.n_tiles = A->n_tiles;
       B.fmt = 1;
+      B.max_row = A->max_row_nnz;
       for (int k = 0; k < GSE_MAX_EXP; ++k) B.sem[k] = A->sem[k];
       d.eta = A->eta;
     } else {
@@ -449,6 +450,7 @@ static gse_status batch_descs(int32_t n_sys, const gse_system* sys, const gse_pa
       B.n_rows = M->n_rows;
       B.n_tiles = M->n_tiles;
       B.fmt = 0;
+      B.max_row = M->max_row_nnz;
       d.eta = nullptr;
     }
     if (!y.b || !y.x || !aligned16(y.x)) return fail(GSE_ERR_ARG, "system %d: bad b / x", i);

@@ -82,6 +82,37 @@ __device__ __forceinline__ double load_decode(const BatchSlot& B, int j, const d
   return decode<FMT>(c, h, t1, t2, v, scale, col);
 }
 
+// Row sums of a staged tile, one thread per row, BW non-zeros per batch: the
+// gathers of a batch are issued before any is used; slots past the row's
+// end gather x[0] and are left out of the sum.
+template <int BW, class Emit>
+__device__ __forceinline__ void sum_staged(const BatchSlot& B, int ra, int rb, int j0,
+                                           const double* vals, const int* cols,
+                                           const double* __restrict__ xin, Emit& emit) {
+  for (int r = ra + (int)threadIdx.x; r < rb; r += kWG) {
+    const int s0 = B.row_ptr[r], s1 = B.row_ptr[r + 1];
+    const int o = s0 - j0, len = s1 - s0;
+    double sum = 0.0;
+    for (int kb = 0; kb < len; kb += BW) {
+      double v[BW], xv[BW];
+      int c[BW];
+#pragma unroll
+      for (int k = 0; k < BW; ++k) {
+        v[k] = vals[o + kb + k];
+        c[k] = (kb + k < len) ? cols[o + kb + k] : 0;
+      }
+#pragma unroll
+      for (int k = 0; k < BW; ++k) xv[k] = xin[c[k]];
+#pragma unroll
+      for (int k = 0; k < BW; ++k) {
+        const double pr = __dmul_rn(v[k], xv[k]);
+        sum = (kb + k < len) ? __dadd_rn(sum, pr) : sum;
+      }
+    }
+    emit(r, sum);
+  }
+}
+
 // Rows of tile t (those whose first non-zero lies in the tile's range, from
 // the matrix's own tile table).  The non-zeros of these rows are decoded
 // into LDS when they fit, then each row is summed by one thread in row
@@ -117,28 +148,14 @@ __device__ double tile_rows(const BatchSlot& B, int t, const double* __restrict_
       cols[i] = c;
     }
     __syncthreads();
-    for (int r = ra + tid; r < rb; r += kWG) {
-      const int s0 = B.row_ptr[r], s1 = B.row_ptr[r + 1];
-      const int o = s0 - j0, len = s1 - s0;
-      double sum = 0.0;
-      for (int kb = 0; kb < len; kb += 8) {
-        double v[8], xv[8];
-        int c[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          v[k] = vals[o + kb + k];
-          c[k] = (kb + k < len) ? cols[o + kb + k] : 0;
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) xv[k] = xin[c[k]];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const double pr = __dmul_rn(v[k], xv[k]);
-          sum = (kb + k < len) ? __dadd_rn(sum, pr) : sum;
-        }
-      }
-      emit(r, sum);
-    }
+    // batches as wide as the longest row when that is at most seven (no
+    // gathers for padding slots), else eight; the same row-order sums
+    if (B.max_row <= 5)
+      sum_staged<5>(B, ra, rb, j0, vals, cols, xin, emit);
+    else if (B.max_row <= 7)
+      sum_staged<7>(B, ra, rb, j0, vals, cols, xin, emit);
+    else
+      sum_staged<8>(B, ra, rb, j0, vals, cols, xin, emit);
   } else {
     for (int r = ra + tid; r < rb; r += kWG) {
       const int s0 = B.row_ptr[r], s1 = B.row_ptr[r + 1];

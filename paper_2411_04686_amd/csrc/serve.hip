@@ -159,6 +159,7 @@ gse_status place(gse_solver* s, Ticket& t, gse::BatchSlot* B, const double** eta
     B->tail2 = A.tail2;
     B->n_tiles = A.n_tiles;
     B->fmt = 1;
+    B->max_row = A.max_row_nnz;
     for (int k = 0; k < GSE_MAX_EXP; ++k) B->sem[k] = A.sem[k];
     *eta = t.A.eta;
   } else {
@@ -188,6 +189,7 @@ gse_status place(gse_solver* s, Ticket& t, gse::BatchSlot* B, const double** eta
     B->val = M.val;
     B->n_tiles = M.n_tiles;
     B->fmt = 0;
+    B->max_row = M.max_row_nnz;
     *eta = nullptr;
   }
   B->b = reinterpret_cast<const double*>(at(L.b));
