@@ -67,8 +67,22 @@ __device__ __forceinline__ double block_sum(double v, double* red /* [NT / 64] *
 // gets the result).  The partials come from an earlier kernel on the same
 // stream, so the launch boundary has made them visible.
 __device__ __forceinline__ double sum_partials(const double* partials, int n, double* red) {
+  // Thread t adds entries t, t + kWG, t + 2 kWG, ... in that order, then
+  // the block sum.  Eight strides are loaded before any is added (indices
+  // past n clamped to a valid entry, their additions masked): a plain loop
+  // waits for each load before issuing the next.
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += kWG) s += partials[i];
+  for (int i = threadIdx.x; i < n; i += 8 * kWG) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = i + k * kWG;
+      v[k] = partials[e < n ? e : i];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s = (i + k * kWG < n) ? s + v[k] : s;
+  }
   return block_sum(s, red);
 }
 
