@@ -326,3 +326,36 @@ def test_row_ring_kernel_full_size_operators():
     for A in (diffusion3d(128, 0), convdiff2d(1024, 0)):
         for fmt in (0, 1, 2, 3):
             check_rows(A.indptr.astype(np.int64), A.n_cols, A.indices, fmt)
+
+
+def _random_structure(seed, n_rows, max_len, empty_frac):
+    """Row lengths drawn from 0..max_len (a share of empty rows and of rows
+    at the maximum), sorted random columns; only the index structure."""
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(0, max_len + 1, size=n_rows)
+    lens[rng.random(n_rows) < empty_frac] = 0
+    lens[rng.random(n_rows) < 0.2] = max_len
+    indptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    n_cols = max(n_rows, max_len)
+    cols = np.concatenate([np.sort(rng.choice(n_cols, size=l, replace=False)) for l in lens]
+                          + [np.zeros(0, np.int64)]).astype(np.int32)
+    return indptr, n_cols, cols
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("max_len", [1, 3, 4, 5, 6, 7, 8])
+def test_row_ring_random_structures(seed, max_len):
+    n_rows = (2500 if max_len == 1 else 700) + 97 * seed  # never a multiple of 192
+    indptr, n_cols, cols = _random_structure(seed, n_rows, max_len, 0.1 * (seed % 3))
+    if indptr[-1] < RING_T:
+        pytest.skip("fewer non-zeros than one ring tile")
+    for fmt in (0, 1, 2, 3):
+        check_rows(indptr, n_cols, cols, fmt)
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("max_len", [9, 16, 24])
+def test_ring_random_structures(seed, max_len):
+    indptr, n_cols, cols = _random_structure(seed, 900 + 131 * seed, max_len, 0.15)
+    for fmt in (0, 1, 2, 3):
+        check_ring(indptr, n_cols, cols, fmt)
