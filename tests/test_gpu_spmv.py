@@ -54,6 +54,12 @@ def cases():
         "fixed_rows_777x5": lambda: fixed_rows(777, 800, 5, 13),
         "fixed_rows_1111x7": lambda: fixed_rows(1111, 1500, 7, 14),
         "fixed_rows_500x6": lambda: fixed_rows(500, 640, 6, 15),
+        # ragged short rows with many empty ones and a wide exponent spread, on
+        # either side of the row-tile ring's limit (longest row 7 and 9)
+        "random_rows_max7": lambda: random_sparse(2023, 2100, 23, mean_row=1.5, empty_frac=0.3,
+                                                  exp_spread=30),
+        "random_rows_max9": lambda: random_sparse(2021, 2100, 21, mean_row=2, empty_frac=0.2,
+                                                  exp_spread=30),
     }
 
 

@@ -111,6 +111,10 @@ MATS = {
     "fixed_rows_777x5": lambda: fixed_rows(777, 800, 5, 13),
     "fixed_rows_1111x7": lambda: fixed_rows(1111, 1500, 7, 14),
     "fixed_rows_500x6": lambda: fixed_rows(500, 640, 6, 15),
+    "random_rows_max7": lambda: random_sparse(2023, 2100, 23, mean_row=1.5, empty_frac=0.3,
+                                              exp_spread=30),
+    "random_rows_max9": lambda: random_sparse(2021, 2100, 21, mean_row=2, empty_frac=0.2,
+                                              exp_spread=30),
 }
 
 
@@ -247,7 +251,8 @@ def check_ring(indptr, n_cols, cols, fmt):
 
 @pytest.mark.parametrize("fmt", [0, 1, 2, 3])
 @pytest.mark.parametrize("name", ["poisson2d_64", "diffusion3d_24", "convdiff2d_64", "random_ragged",
-                                  "diagonal_3000", "sparse_many_empty", "fixed_rows_512x8"])
+                                  "diagonal_3000", "sparse_many_empty", "fixed_rows_512x8",
+                                  "random_rows_max9"])
 def test_ring_kernel_in_bounds(name, fmt):
     A = MATS[name]()
     if np.diff(A.indptr).max(initial=0) > SHORT or A.indptr[-1] < RING_T:
@@ -314,7 +319,8 @@ def check_rows(indptr, n_cols, cols, fmt, D=2):
 @pytest.mark.parametrize("fmt", [0, 1, 2, 3])
 @pytest.mark.parametrize("name", ["poisson2d_64", "diffusion3d_24", "convdiff2d_64", "diagonal_3000",
                                   "sparse_many_empty", "fixed_rows_512x8", "fixed_rows_1000x3",
-                                  "fixed_rows_777x5", "fixed_rows_1111x7", "fixed_rows_500x6"])
+                                  "fixed_rows_777x5", "fixed_rows_1111x7", "fixed_rows_500x6",
+                                  "random_rows_max7"])
 def test_row_ring_kernel_in_bounds(name, fmt):
     A = MATS[name]()
     if np.diff(A.indptr).max(initial=0) > 8 or A.indptr[-1] < RING_T:
