@@ -558,6 +558,8 @@ def run_serving(args, torch, G):
         A = serving_request_matrix(r)
         _, b = rhs_from_solution(A, r["seed"])
         systems.append((A, b))
+        if len(systems) % 250 == 0:
+            progress(f"serving: {len(systems)} of {len(stream_def)} requests generated")
     p = G.gse_default_params(G.CG)
     p.max_iter = 20000
     arena = torch.empty(int(args.arena_gb * (1 << 30)), dtype=torch.uint8, device=dev)
@@ -580,12 +582,18 @@ def run_serving(args, torch, G):
                                 done[t] = (r, time.perf_counter())
                     time.sleep(0.0005)
                 tickets.append(G.gse_solver_submit(server, rq.rq))
+                if len(tickets) % 250 == 0:
+                    progress(f"serving: {len(tickets)} submitted, {len(done)} done")
+            reported = len(done) // 250
             while len(done) < len(tickets):
                 for t in tickets:
                     if t not in done:
                         r = G.gse_solver_poll(server, t)
                         if r is not None:
                             done[t] = (r, time.perf_counter())
+                if len(done) // 250 > reported:
+                    reported = len(done) // 250
+                    progress(f"serving: {len(done)} of {len(tickets)} done")
                 time.sleep(0.0005)
             t_end = max(v[1] for v in done.values())
             stats = G.gse_solver_stats(server).as_dict()
