@@ -458,14 +458,16 @@ int or_gmres(const or_matrix* A, const double* b, double* x, const or_params* p,
         if (it == 0) { if (hist) hist[0] = relres; if (seg_hist) seg_hist[0] = s; }
         int trig = OR_TRIG_NONE;
         if (relres <= p->tol) {
+            /* the residual just formed is the final operator's: done */
+            if (s == fin || s == 3) { status = OR_OK; break; }
+            /* otherwise convergence is judged on the final operator's residual;
+             * a fixed segment count cannot escalate and ends here either way */
             if (operator_is_final(A, p, s)) {
-                if (s == fin || p->fixed_segments != 0 || s == 3) { status = OR_OK; break; }
                 double rt = sqrt(residual(A, fin, b, x, w)) / nb;
                 if (rt <= p->tol) { status = OR_OK; break; }
-                trig = OR_TRIG_TOL;
-            } else {
-                trig = OR_TRIG_TOL;
+                if (p->fixed_segments != 0) break;
             }
+            trig = OR_TRIG_TOL;
         }
         if (trig != OR_TRIG_NONE) {
             if (s >= 3) break;
