@@ -207,7 +207,7 @@ typedef struct gse_params {
     double reldec_limit;      /* Condition 2 threshold */
     int32_t ndec_rule;        /* 0: compare nDec with ndec_limit; 1: with t/2 */
     double floor_c;           /* floor trigger factor, 0 disables */
-    int32_t switch_mode;      /* CG after a switch: 0 p = r, 1 keep p */
+    int32_t switch_mode;      /* CG after a switch: 0 p = r (default), 1 keep p */
     int32_t record_history;   /* kept for callers; the history is always recorded */
     int32_t launch_mode;      /* 0: iterations replayed from HIP graphs, 1: direct launches
                                  (CG on systems of at most 4096 rows whose rows hold at most 8

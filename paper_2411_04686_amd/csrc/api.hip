@@ -319,7 +319,7 @@ gse_status gse_default_params(int32_t method, gse_params* p) {
   p->fixed_segments = 0;
   p->ndec_rule = 0;
   p->floor_c = 10.0;
-  p->switch_mode = 1;
+  p->switch_mode = 0;  // p = r after a switch: a kept direction can stall CG
   p->record_history = 0;
   if (method == GSE_CG) {  // Section IV-A (cap) and IV-D.1 (controller)
     p->max_iter = 5000;

@@ -143,6 +143,9 @@ class BatchEngine {
   gse_status upload_list(int which, const std::vector<int>& ids);
   gse_status finish(int slot, int status, std::vector<int>* done);
   void resume(int slot);
+  // The recursive residual met the tolerance outside an iteration: check it
+  // with all segments on an exact operator, else switch up (trigger TOL).
+  void tol_met(int slot);
   BatchView view(int which) const;
   hipError_t launch_epoch_kernels(int iters);
   hipError_t sync_states_in();

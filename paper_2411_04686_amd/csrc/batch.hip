@@ -651,6 +651,25 @@ void BatchEngine::resume(int id) {
   run_dirty_ = true;
 }
 
+void BatchEngine::tol_met(int id) {
+  SlotHost& m = meta_[id];
+  SolverState& S = hS_[id];
+  const bool exact_op = !m.stepped || S.s >= 3 || S.eta[S.s - 1] == 0.0;
+  if (exact_op) {
+    m.phase = kPhCheck;
+    return;
+  }
+  if (m.nsw < 2) {
+    m.rep.switch_iter[m.nsw] = S.it;
+    m.rep.switch_trigger[m.nsw] = GSE_TRIG_TOL;
+  }
+  ++m.nsw;
+  S.s += 1;
+  m.phase = kPhReplace;
+  m.reset_p = m.switch_mode == 0;
+  m.origin = kFromSwitch;
+}
+
 gse_status BatchEngine::finish(int id, int status, std::vector<int>* done) {
   SlotHost& m = meta_[id];
   const SolverState& S = hS_[id];
@@ -723,7 +742,7 @@ gse_status BatchEngine::actions(std::vector<int>* done) {
         if (S.nb == 0.0) {
           m.phase = kPhZero;
         } else if (S.relres <= m.tol) {
-          m.phase = kPhCheck;
+          tol_met(id);
         } else {
           resume(id);
         }
@@ -759,11 +778,11 @@ gse_status BatchEngine::actions(std::vector<int>* done) {
             resume(id);
           }
         } else {
-          if (S.it >= m.max_iter) {
+          if (S.relres <= m.tol) {
+            tol_met(id);
+          } else if (S.it >= m.max_iter) {
             m.final_status = GSE_NOT_CONVERGED;
             m.phase = kPhFinal;
-          } else if (S.relres <= m.tol) {
-            m.phase = kPhCheck;
           } else {
             resume(id);
           }

@@ -692,7 +692,12 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
   const bool small = cg_small_path(A.op);
   while (!done) {
     if (pending_check) {
-      h.stop = kConv;
+      // the recursive residual meets the tolerance outside an iteration (at
+      // x0, or after a residual replacement): convergence is judged only on
+      // an exact operator; an inexact one escalates as the controller does
+      const bool exact_op = !stepped || h.s >= 3 || h.eta[h.s - 1] == 0.0;
+      h.stop = exact_op ? kConv : kSwitch;
+      h.trig = exact_op ? GSE_TRIG_NONE : GSE_TRIG_TOL;
     } else {
       if (small) {
         // every iteration of this segment count in one launch
@@ -758,7 +763,7 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
     } else if (reason == kCap) {
       break;
     }
-    if (h.it >= p->max_iter) break;
+    if (h.it >= p->max_iter && !pending_check) break;
     h.stop = kRun;
     h.trig = 0;
     h.go = 0;
@@ -1110,10 +1115,22 @@ gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_pa
     }
     int trig = GSE_TRIG_NONE;
     if (h.relres <= p->tol) {
-      const bool exact_op = h.fixed != 0 || h.s >= 3 || h.eta[h.s - 1] == 0.0;
-      if (exact_op) {
+      if (A.fmt == 0 || h.s >= 3) {  // the residual just formed is the all-segment one
         status = GSE_OK;
         break;
+      }
+      if (h.fixed != 0 || h.eta[h.s - 1] == 0.0) {
+        // convergence is judged on the all-segment residual; a fixed
+        // segment count cannot escalate, so it ends here either way
+        SolverState t3;
+        e = apply(A, s_final, x, w.w, kEpiResid, b, &w.S->scratch[0], w, nullptr, st);
+        if (e == hipSuccess) e = read_state(w, &t3, st);
+        if (e != hipSuccess) return hip_fail(e, "gmres check");
+        if (sqrt(t3.scratch[0]) / h.nb <= p->tol) {
+          status = GSE_OK;
+          break;
+        }
+        if (h.fixed != 0) break;
       }
       trig = GSE_TRIG_TOL;
     }
