@@ -44,8 +44,9 @@ class Report(C.Structure):
 class Matrix(C.Structure):
     _fields_ = [("n_rows", C.c_int32), ("row_ptr", C.c_void_p), ("col", C.c_void_p),
                 ("val", C.c_void_p), ("col_idx", C.c_void_p), ("head", C.c_void_p),
-                ("tail1", C.c_void_p), ("tail2", C.c_void_p), ("sem8", C.c_void_p),
-                ("eta3", C.c_void_p)]
+                ("tail1", C.c_void_p), ("tail2", C.c_void_p), ("sem64", C.c_void_p),
+                ("eta3", C.c_void_p), ("idx_bits", C.c_int32), ("lp_val", C.c_void_p),
+                ("lp_fmt", C.c_int32)]
 
 
 def lib():
@@ -55,25 +56,36 @@ def lib():
             _build.build()
         L = C.CDLL(_build.LIB)
         P = C.c_void_p
+        L.or_index_bits.restype = C.c_int
+        L.or_index_bits.argtypes = [C.c_int]
         L.or_exponent_histogram.restype = C.c_int64
         L.or_exponent_histogram.argtypes = [P, C.c_int64, P]
         L.or_select_shared_exponents.restype = C.c_int
         L.or_select_shared_exponents.argtypes = [P, C.c_int, P]
         L.or_encode_values.restype = C.c_int
-        L.or_encode_values.argtypes = [P, P, C.c_int64, P, P, P, P, P]
+        L.or_encode_values.argtypes = [P, P, C.c_int64, P, C.c_int, P, P, P, P]
         L.or_encode.restype = C.c_int
         L.or_encode.argtypes = [P, P, P, C.c_int32, C.c_int32, C.c_int64, C.c_int, P, P,
                                 P, P, P, P, P, P]
         L.or_decode_one.restype = C.c_double
-        L.or_decode_one.argtypes = [C.c_uint32, C.c_uint16, C.c_uint16, C.c_uint32, P, C.c_int]
+        L.or_decode_one.argtypes = [C.c_uint32, C.c_uint16, C.c_uint16, C.c_uint32, P, C.c_int,
+                                    C.c_int]
         L.or_decode.restype = None
-        L.or_decode.argtypes = [P, P, P, P, C.c_int64, P, C.c_int, P]
+        L.or_decode.argtypes = [P, P, P, P, C.c_int64, P, C.c_int, C.c_int, P]
+        L.or_lp_round.restype = C.c_uint16
+        L.or_lp_round.argtypes = [C.c_double, C.c_int, P]
+        L.or_lp_widen.restype = C.c_double
+        L.or_lp_widen.argtypes = [C.c_uint16, C.c_int]
+        L.or_lp_convert.restype = C.c_int64
+        L.or_lp_convert.argtypes = [P, C.c_int64, C.c_int, P]
+        L.or_lp_spmv.restype = None
+        L.or_lp_spmv.argtypes = [C.c_int32, P, P, P, C.c_int, P, P]
         L.or_csr_spmv.restype = None
         L.or_csr_spmv.argtypes = [C.c_int32, P, P, P, P, P]
         L.or_gse_spmv.restype = None
-        L.or_gse_spmv.argtypes = [C.c_int32, P, P, P, P, P, P, C.c_int, P, P]
+        L.or_gse_spmv.argtypes = [C.c_int32, P, P, P, P, P, P, C.c_int, C.c_int, P, P]
         L.or_gse_spmv_rows.restype = None
-        L.or_gse_spmv_rows.argtypes = [P, C.c_int32, P, P, P, P, P, P, C.c_int, P, P]
+        L.or_gse_spmv_rows.argtypes = [P, C.c_int32, P, P, P, P, P, P, C.c_int, C.c_int, P, P]
         L.or_window_metrics.restype = None
         L.or_window_metrics.argtypes = [P, C.c_int32, C.c_int32, P, P, P]
         L.or_precision_trigger.restype = C.c_int
@@ -108,36 +120,67 @@ def exponent_histogram(val):
     return hist, int(nonfinite)
 
 
+MAX_EXP = 64
+
+
+def index_bits(num_exp: int) -> int:
+    """Slot-index width for a table of num_exp shared exponents."""
+    return lib().or_index_bits(num_exp)
+
+
+def _table(sem):
+    """A shared-exponent table padded to the oracle's 64 entries."""
+    t = np.zeros(MAX_EXP, np.int16)
+    a = np.asarray(sem, dtype=np.int16).ravel()
+    t[:a.size] = a
+    return t
+
+
 def select_shared_exponents(hist, num_exp: int = 8):
+    """The table (first num_exp of 64 entries returned, at least 8)."""
     hist = _c(hist, np.uint32)
-    sem = np.zeros(8, dtype=np.int16)
+    sem = np.zeros(MAX_EXP, dtype=np.int16)
     rc = lib().or_select_shared_exponents(_p(hist), num_exp, _p(sem))
     if rc < 0:
         raise OracleError(rc, "select_shared_exponents")
-    return sem
+    return sem[:max(8, num_exp)].copy()
 
 
 @dataclasses.dataclass
 class Encoded:
-    sem: np.ndarray        # int16[8]
+    sem: np.ndarray        # int16[max(8, k)]: the table, unused entries 0
     col_idx: np.ndarray    # uint32[nnz]
     head: np.ndarray       # uint16[nnz]
     tail1: np.ndarray      # uint16[nnz]
     tail2: np.ndarray      # uint32[nnz]
     eta: np.ndarray        # float64[3]
     exact_frac: float
+    idx_bits: int = 3      # slot-index width in the column word
+
+    @property
+    def table(self):
+        return _table(self.sem)
+
+    def column(self):
+        return self.col_idx & np.uint32(0xFFFFFFFF >> self.idx_bits)
+
+    def slot(self):
+        if self.idx_bits == 0:
+            return np.zeros_like(self.col_idx)
+        return self.col_idx >> np.uint32(32 - self.idx_bits)
 
 
-def encode_values(val, col, sem):
+def encode_values(val, col, sem, idx_bits: int = 3):
     val = _c(val, np.float64)
     col = _c(col, np.int32)
-    sem = _c(sem, np.int16)
+    sem = _table(sem)
     nnz = val.size
     ci = np.empty(nnz, np.uint32)
     h = np.empty(nnz, np.uint16)
     t1 = np.empty(nnz, np.uint16)
     t2 = np.empty(nnz, np.uint32)
-    rc = lib().or_encode_values(_p(val), _p(col), nnz, _p(sem), _p(ci), _p(h), _p(t1), _p(t2))
+    rc = lib().or_encode_values(_p(val), _p(col), nnz, _p(sem), idx_bits, _p(ci), _p(h), _p(t1),
+                                _p(t2))
     if rc < 0:
         raise OracleError(rc, "encode_values")
     return ci, h, t1, t2
@@ -149,7 +192,7 @@ def encode(indptr, indices, data, n_cols: int, num_exp: int = 8, sem_in=None) ->
     data = _c(data, np.float64)
     n_rows = indptr.size - 1
     nnz = data.size
-    sem = np.zeros(8, np.int16)
+    sem = np.zeros(MAX_EXP, np.int16)
     ci = np.empty(max(nnz, 1), np.uint32)
     h = np.empty(max(nnz, 1), np.uint16)
     t1 = np.empty(max(nnz, 1), np.uint16)
@@ -157,24 +200,62 @@ def encode(indptr, indices, data, n_cols: int, num_exp: int = 8, sem_in=None) ->
     eta = np.zeros(3, np.float64)
     ef = C.c_double(0.0)
     si = None if sem_in is None else _c(sem_in, np.int16)
+    if si is not None and si.size < num_exp:
+        raise OracleError(ERR_ARG, "sem_in holds fewer than num_exp entries")
     rc = lib().or_encode(_p(indptr), _p(indices), _p(data), n_rows, n_cols, nnz, num_exp,
                          _p(si), _p(sem), _p(ci), _p(h), _p(t1), _p(t2), _p(eta),
                          C.addressof(ef))
     if rc < 0:
         raise OracleError(rc, "encode")
-    return Encoded(sem, ci[:nnz], h[:nnz], t1[:nnz], t2[:nnz], eta, ef.value)
+    return Encoded(sem[:max(8, num_exp)].copy(), ci[:nnz], h[:nnz], t1[:nnz], t2[:nnz], eta,
+                   ef.value, index_bits(num_exp))
 
 
 def decode(enc: Encoded, s: int):
     out = np.empty(enc.head.size, np.float64)
     lib().or_decode(_p(enc.col_idx), _p(enc.head), _p(enc.tail1), _p(enc.tail2),
-                    enc.head.size, _p(enc.sem), s, _p(out))
+                    enc.head.size, _p(enc.table), enc.idx_bits, s, _p(out))
     return out
 
 
-def decode_one(col_word: int, head: int, tail1: int, tail2: int, sem, s: int) -> float:
-    sem = _c(sem, np.int16)
-    return lib().or_decode_one(col_word, head, tail1, tail2, _p(sem), s)
+def decode_one(col_word: int, head: int, tail1: int, tail2: int, sem, s: int,
+               idx_bits: int = 3) -> float:
+    table = _table(sem)
+    return lib().or_decode_one(col_word, head, tail1, tail2, _p(table), idx_bits, s)
+
+
+# ------------------------------------------------- FP16 / BF16 comparators ---
+LP_FP16, LP_BF16 = 1, 2
+S_LP = -2  # fixed_segments value that selects the 16-bit operator
+
+
+def lp_round(v: float, fmt: int):
+    """(bits, overflowed) of one value rounded to FP16 / BF16."""
+    over = C.c_int(0)
+    h = lib().or_lp_round(float(v), fmt, C.addressof(over))
+    return int(h), bool(over.value)
+
+
+def lp_widen(h: int, fmt: int) -> float:
+    return lib().or_lp_widen(int(h), fmt)
+
+
+def lp_convert(val, fmt: int):
+    """(uint16 plane, number of overflows)."""
+    val = _c(val, np.float64)
+    out = np.empty(max(val.size, 1), np.uint16)
+    n = lib().or_lp_convert(_p(val), val.size, fmt, _p(out))
+    return out[:val.size], int(n)
+
+
+def lp_spmv(indptr, indices, val16, fmt: int, x):
+    indptr = _c(indptr, np.int32)
+    indices = _c(indices, np.int32)
+    val16 = _c(val16, np.uint16)
+    x = _c(x, np.float64)
+    y = np.empty(indptr.size - 1, np.float64)
+    lib().or_lp_spmv(indptr.size - 1, _p(indptr), _p(indices), _p(val16), fmt, _p(x), _p(y))
+    return y
 
 
 # ------------------------------------------------------------------ SpMV ---
@@ -192,8 +273,9 @@ def gse_spmv(indptr, enc: Encoded, s: int, x):
     indptr = _c(indptr, np.int32)
     x = _c(x, np.float64)
     y = np.empty(indptr.size - 1, np.float64)
+    table = enc.table
     lib().or_gse_spmv(indptr.size - 1, _p(indptr), _p(enc.col_idx), _p(enc.head),
-                      _p(enc.tail1), _p(enc.tail2), _p(enc.sem), s, _p(x), _p(y))
+                      _p(enc.tail1), _p(enc.tail2), _p(table), enc.idx_bits, s, _p(x), _p(y))
     return y
 
 
@@ -202,8 +284,10 @@ def gse_spmv_rows(rows, indptr, enc: Encoded, s: int, x):
     indptr = _c(indptr, np.int32)
     x = _c(x, np.float64)
     y = np.empty(rows.size, np.float64)
+    table = enc.table
     lib().or_gse_spmv_rows(_p(rows), rows.size, _p(indptr), _p(enc.col_idx), _p(enc.head),
-                           _p(enc.tail1), _p(enc.tail2), _p(enc.sem), s, _p(x), _p(y))
+                           _p(enc.tail1), _p(enc.tail2), _p(table), enc.idx_bits, s, _p(x),
+                           _p(y))
     return y
 
 
@@ -256,7 +340,7 @@ class SolveResult:
     seg_hist: np.ndarray
 
 
-def _matrix(indptr, indices=None, data=None, enc: Optional[Encoded] = None):
+def _matrix(indptr, indices=None, data=None, enc: Optional[Encoded] = None, lp=None):
     keep = [indptr, indices, data]
     m = Matrix()
     m.n_rows = indptr.size - 1
@@ -266,13 +350,20 @@ def _matrix(indptr, indices=None, data=None, enc: Optional[Encoded] = None):
     if enc is not None:
         m.col_idx, m.head, m.tail1, m.tail2 = (_p(enc.col_idx), _p(enc.head), _p(enc.tail1),
                                                _p(enc.tail2))
-        m.sem8 = _p(enc.sem)
+        table = enc.table
+        m.sem64 = _p(table)
         m.eta3 = _p(enc.eta)
-        keep.append(enc)
+        m.idx_bits = enc.idx_bits
+        keep.extend([enc, table])
+    if lp is not None:  # (uint16 plane, fmt)
+        plane = _c(lp[0], np.uint16)
+        m.lp_val = _p(plane)
+        m.lp_fmt = int(lp[1])
+        keep.append(plane)
     return m, keep
 
 
-def _solve(fn, indptr, b, params: Params, indices=None, data=None, enc=None, x0=None):
+def _solve(fn, indptr, b, params: Params, indices=None, data=None, enc=None, x0=None, lp=None):
     indptr = _c(indptr, np.int32)
     indices = None if indices is None else _c(indices, np.int32)
     data = None if data is None else _c(data, np.float64)
@@ -281,7 +372,7 @@ def _solve(fn, indptr, b, params: Params, indices=None, data=None, enc=None, x0=
     cap = params.max_iter + 2
     hist = np.full(cap, np.nan)
     seg = np.zeros(cap, np.int32)
-    m, keep = _matrix(indptr, indices, data, enc)
+    m, keep = _matrix(indptr, indices, data, enc, lp)
     rep = Report()
     fn(C.byref(m), _p(b), _p(x), C.byref(params), C.byref(rep), _p(hist), _p(seg))
     del keep
@@ -291,11 +382,15 @@ def _solve(fn, indptr, b, params: Params, indices=None, data=None, enc=None, x0=
                        seg[: rep.iters + 1])
 
 
-def cg(indptr, b, params: Params, indices=None, data=None, enc=None, x0=None) -> SolveResult:
-    """CG; ``params.fixed_segments == -1`` runs on the FP64 CSR values."""
-    return _solve(lib().or_cg, indptr, b, params, indices, data, enc, x0)
+def cg(indptr, b, params: Params, indices=None, data=None, enc=None, x0=None,
+       lp=None) -> SolveResult:
+    """CG; ``params.fixed_segments == -1`` runs on the FP64 CSR values, -2 on
+    the 16-bit values ``lp = (plane, fmt)``."""
+    return _solve(lib().or_cg, indptr, b, params, indices, data, enc, x0, lp)
 
 
-def gmres(indptr, b, params: Params, indices=None, data=None, enc=None, x0=None) -> SolveResult:
-    """Restarted GMRES(params.restart); ``fixed_segments == -1`` runs on FP64."""
-    return _solve(lib().or_gmres, indptr, b, params, indices, data, enc, x0)
+def gmres(indptr, b, params: Params, indices=None, data=None, enc=None, x0=None,
+          lp=None) -> SolveResult:
+    """Restarted GMRES(params.restart); ``fixed_segments == -1`` runs on FP64,
+    -2 on the 16-bit values ``lp``."""
+    return _solve(lib().or_gmres, indptr, b, params, indices, data, enc, x0, lp)

@@ -13,6 +13,25 @@
 
 static uint64_t bits_of(double v) { uint64_t u; memcpy(&u, &v, sizeof u); return u; }
 
+/* Section III-B.1: the number of shared exponents sets the width of the
+ * exponent index -- the fewest bits that number k slots, ceil(log2 k)
+ * (0 bits for a single shared exponent). */
+int or_index_bits(int num_exp) {
+    int b = 0;
+    while ((1 << b) < num_exp) b += 1;
+    return b;
+}
+
+/* Column and slot of a column word whose top idx_bits bits hold the slot
+ * (Section III-C.1). */
+static uint32_t column_of(uint32_t word, int idx_bits) {
+    return idx_bits == 0 ? word : (word & (0xFFFFFFFFu >> idx_bits));
+}
+
+static int slot_of(uint32_t word, int idx_bits) {
+    return idx_bits == 0 ? 0 : (int)(word >> (32 - idx_bits));
+}
+
 /* ------------------------------------------------------------------------ */
 /* Section III-B.1: occurrences N_i of every distinct exponent e_i.  The    */
 /* 11-bit biased exponent field is the key; field 2047 (Inf/NaN) is counted */
@@ -86,8 +105,9 @@ int or_select_shared_exponents(const uint32_t* hist, int num_exp, int16_t* sem) 
  * smallest normal (1) for the shift.  Returns OR_ERR_RANGE if a value has no
  * shared exponent above its own (possible only with a reused table). */
 int or_encode_values(const double* val, const int32_t* col, int64_t nnz,
-                     const int16_t* sem, uint32_t* col_idx, uint16_t* head,
+                     const int16_t* sem, int idx_bits, uint32_t* col_idx, uint16_t* head,
                      uint16_t* tail1, uint32_t* tail2) {
+    if (idx_bits < 0 || idx_bits > 6) return OR_ERR_ARG;
     for (int64_t i = 0; i < nnz; ++i) {
         uint64_t u = bits_of(val[i]);
         unsigned sign = (unsigned)(u >> 63);
@@ -115,7 +135,9 @@ int or_encode_values(const double* val, const int32_t* col, int64_t nnz,
         else if (-sh >= 64) F = 0;
         else F = sig >> (-sh);
         (void)min_diff;
-        col_idx[i] = (uint32_t)col[i] | ((uint32_t)slot << 29);
+        if (slot >= (1 << idx_bits)) return OR_ERR_ARG;
+        col_idx[i] = (uint32_t)col[i] |
+                     (idx_bits == 0 ? 0u : ((uint32_t)slot << (32 - idx_bits)));
         head[i] = (uint16_t)((sign << 15) | (unsigned)(F >> 48));
         tail1[i] = (uint16_t)((F >> 32) & 0xFFFF);
         tail2[i] = (uint32_t)(F & 0xFFFFFFFFu);
@@ -127,8 +149,8 @@ int or_encode_values(const double* val, const int32_t* col, int64_t nnz,
  * with s segments is +-F_W * 2^(SEM - 1023 - W), W = 15, 31, 63, where F_W is
  * the top W magnitude bits of the SEM word; a zero field reads as 0. */
 double or_decode_one(uint32_t col_word, uint16_t h, uint16_t t1, uint32_t t2,
-                     const int16_t* sem, int s) {
-    int slot = (int)(col_word >> 29);
+                     const int16_t* sem, int idx_bits, int s) {
+    int slot = slot_of(col_word, idx_bits);
     int W = (s == 1) ? 15 : (s == 2) ? 31 : 63;
     uint64_t F63 = ((uint64_t)(h & 0x7FFFu) << 48) | ((uint64_t)t1 << 32) | (uint64_t)t2;
     uint64_t F = F63 >> (63 - W);
@@ -138,10 +160,10 @@ double or_decode_one(uint32_t col_word, uint16_t h, uint16_t t1, uint32_t t2,
 }
 
 void or_decode(const uint32_t* col_idx, const uint16_t* head, const uint16_t* tail1,
-               const uint32_t* tail2, int64_t nnz, const int16_t* sem, int s,
-               double* out) {
+               const uint32_t* tail2, int64_t nnz, const int16_t* sem, int idx_bits,
+               int s, double* out) {
     for (int64_t i = 0; i < nnz; ++i)
-        out[i] = or_decode_one(col_idx[i], head[i], tail1[i], tail2[i], sem, s);
+        out[i] = or_decode_one(col_idx[i], head[i], tail1[i], tail2[i], sem, idx_bits, s);
 }
 
 /* Whole conversion: histogram, table, per-value words, and the relative
@@ -153,7 +175,9 @@ int or_encode(const int32_t* row_ptr, const int32_t* col, const double* val,
               double* exact_frac) {
     if (n_rows < 0 || n_cols < 0 || nnz < 0 || num_exp < 1 || num_exp > OR_MAX_EXP)
         return OR_ERR_ARG;
-    if ((int64_t)n_cols > (1 << 29) || nnz >= (1ll << 31)) return OR_ERR_RANGE;
+    int idx_bits = or_index_bits(num_exp);
+    /* the column field keeps 32 - idx_bits bits */
+    if ((int64_t)n_cols > (1ll << (32 - idx_bits)) || nnz >= (1ll << 31)) return OR_ERR_RANGE;
     uint32_t* hist = (uint32_t*)malloc(2048 * sizeof(uint32_t));
     if (!hist) return OR_ERR_ARG;
     if (or_exponent_histogram(val, nnz, hist) > 0) { free(hist); return OR_ERR_NONFINITE; }
@@ -174,7 +198,7 @@ int or_encode(const int32_t* row_ptr, const int32_t* col, const double* val,
         if (sem_out[i] > 0) covered += hist[sem_out[i] - 1];
     if (exact_frac) *exact_frac = nnz ? (double)covered / (double)nnz : 1.0;
     free(hist);
-    rc = or_encode_values(val, col, nnz, sem_out, col_idx, head, tail1, tail2);
+    rc = or_encode_values(val, col, nnz, sem_out, idx_bits, col_idx, head, tail1, tail2);
     if (rc != OR_OK) return rc;
     if (eta3) {
         double amax = 0.0, emax[3] = {0.0, 0.0, 0.0};
@@ -184,7 +208,7 @@ int or_encode(const int32_t* row_ptr, const int32_t* col, const double* val,
                 a += fabs(val[j]);
                 for (int s = 1; s <= 3; ++s)
                     es[s - 1] += fabs(val[j] - or_decode_one(col_idx[j], head[j], tail1[j],
-                                                             tail2[j], sem_out, s));
+                                                             tail2[j], sem_out, idx_bits, s));
             }
             if (a > amax) amax = a;
             for (int s = 0; s < 3; ++s) if (es[s] > emax[s]) emax[s] = es[s];
@@ -192,6 +216,92 @@ int or_encode(const int32_t* row_ptr, const int32_t* col, const double* val,
         for (int s = 0; s < 3; ++s) eta3[s] = amax > 0.0 ? emax[s] / amax : 0.0;
     }
     return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section IV-C: the FP16 and BF16 comparators.  Every value is rounded once,
+ * to nearest with ties to even, into a binary format with `ebits` exponent
+ * bits and `mbits` fraction bits (IEEE binary16: 5 and 10; bfloat16: 8 and
+ * 7); a magnitude that rounds beyond the largest finite value becomes an
+ * infinity (the overflow the paper reports for FP16).  Written from the
+ * formats' definitions: the value is a multiple of its quantum 2^(e - mbits)
+ * (2^(emin - mbits) below the normal range), rounded to the nearest one. */
+static uint16_t round_to_small(double v, int ebits, int mbits, int* overflow) {
+    const unsigned sign = signbit(v) ? 1u : 0u;
+    const int emax = (1 << (ebits - 1)) - 1, emin = 1 - emax;
+    const unsigned inf_bits = ((1u << ebits) - 1u) << mbits;
+    double a = fabs(v);
+    unsigned mag;
+    if (a == 0.0) {
+        mag = 0;
+    } else {
+        int ex;
+        frexp(a, &ex);              /* a = m 2^ex, 1/2 <= m < 1 */
+        int e = ex - 1;             /* a in [2^e, 2^(e+1)) */
+        int qe = (e < emin ? emin : e) - mbits;
+        double n = ldexp(a, -qe);   /* exact: a power-of-two scaling */
+        double fl = floor(n), d = n - fl;
+        double r = (d > 0.5 || (d == 0.5 && fmod(fl, 2.0) != 0.0)) ? fl + 1.0 : fl;
+        double rq = ldexp(r, qe);   /* the rounded magnitude */
+        double max_finite = ldexp(2.0 - ldexp(1.0, -mbits), emax);
+        if (rq > max_finite) {
+            mag = inf_bits;
+            if (overflow) *overflow += 1;
+        } else if (rq < ldexp(1.0, emin)) {
+            mag = (unsigned)r;      /* subnormal: the multiple of 2^(emin - mbits) */
+        } else {
+            int ex2;
+            frexp(rq, &ex2);
+            int E = ex2 - 1;
+            double frac = ldexp(rq, -E) - 1.0;  /* in [0, 1) */
+            mag = ((unsigned)(E + emax) << mbits) | (unsigned)ldexp(frac, mbits);
+        }
+    }
+    return (uint16_t)((sign << (ebits + mbits)) | mag);
+}
+
+static double widen_small(uint16_t h, int ebits, int mbits) {
+    const int emax = (1 << (ebits - 1)) - 1;
+    const unsigned sign = (unsigned)h >> (ebits + mbits);
+    const unsigned E = ((unsigned)h >> mbits) & ((1u << ebits) - 1u);
+    const unsigned F = (unsigned)h & ((1u << mbits) - 1u);
+    double mag;
+    if (E == 0) mag = ldexp((double)F, 1 - emax - mbits);
+    else if (E == (1u << ebits) - 1u) mag = F ? NAN : INFINITY;
+    else mag = ldexp(1.0 + ldexp((double)F, -mbits), (int)E - emax);
+    return sign ? -mag : mag;
+}
+
+static int lp_ebits(int fmt) { return fmt == OR_LP_FP16 ? 5 : 8; }
+static int lp_mbits(int fmt) { return fmt == OR_LP_FP16 ? 10 : 7; }
+
+uint16_t or_lp_round(double v, int fmt, int* overflow) {
+    return round_to_small(v, lp_ebits(fmt), lp_mbits(fmt), overflow);
+}
+
+double or_lp_widen(uint16_t h, int fmt) { return widen_small(h, lp_ebits(fmt), lp_mbits(fmt)); }
+
+int64_t or_lp_convert(const double* val, int64_t nnz, int fmt, uint16_t* out) {
+    int over = 0;
+    int64_t total = 0;
+    for (int64_t i = 0; i < nnz; ++i) {
+        over = 0;
+        out[i] = or_lp_round(val[i], fmt, &over);
+        total += over;
+    }
+    return total;
+}
+
+/* FP16- / BF16-SpMV: each stored value widened to FP64, FP64 multiply and
+ * accumulate in row order (Section IV-C). */
+void or_lp_spmv(int32_t n_rows, const int32_t* row_ptr, const int32_t* col,
+                const uint16_t* val16, int fmt, const double* x, double* y) {
+    for (int32_t r = 0; r < n_rows; ++r) {
+        double sum = 0.0;
+        for (int32_t j = row_ptr[r]; j < row_ptr[r + 1]; ++j)
+            sum += or_lp_widen(val16[j], fmt) * x[col[j]];
+        y[r] = sum;
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -210,12 +320,12 @@ void or_csr_spmv(int32_t n_rows, const int32_t* row_ptr, const int32_t* col,
  * accumulate in FP64 in row order. */
 void or_gse_spmv(int32_t n_rows, const int32_t* row_ptr, const uint32_t* col_idx,
                  const uint16_t* head, const uint16_t* tail1, const uint32_t* tail2,
-                 const int16_t* sem, int s, const double* x, double* y) {
+                 const int16_t* sem, int idx_bits, int s, const double* x, double* y) {
     for (int32_t r = 0; r < n_rows; ++r) {
         double sum = 0.0;
         for (int32_t j = row_ptr[r]; j < row_ptr[r + 1]; ++j) {
-            double v = or_decode_one(col_idx[j], head[j], tail1[j], tail2[j], sem, s);
-            sum += v * x[col_idx[j] & 0x1FFFFFFFu];
+            double v = or_decode_one(col_idx[j], head[j], tail1[j], tail2[j], sem, idx_bits, s);
+            sum += v * x[column_of(col_idx[j], idx_bits)];
         }
         y[r] = sum;
     }
@@ -224,13 +334,14 @@ void or_gse_spmv(int32_t n_rows, const int32_t* row_ptr, const uint32_t* col_idx
 void or_gse_spmv_rows(const int32_t* rows, int32_t n_sel, const int32_t* row_ptr,
                       const uint32_t* col_idx, const uint16_t* head,
                       const uint16_t* tail1, const uint32_t* tail2,
-                      const int16_t* sem, int s, const double* x, double* y_sel) {
+                      const int16_t* sem, int idx_bits, int s, const double* x,
+                      double* y_sel) {
     for (int32_t q = 0; q < n_sel; ++q) {
         int32_t r = rows[q];
         double sum = 0.0;
         for (int32_t j = row_ptr[r]; j < row_ptr[r + 1]; ++j) {
-            double v = or_decode_one(col_idx[j], head[j], tail1[j], tail2[j], sem, s);
-            sum += v * x[col_idx[j] & 0x1FFFFFFFu];
+            double v = or_decode_one(col_idx[j], head[j], tail1[j], tail2[j], sem, idx_bits, s);
+            sum += v * x[column_of(col_idx[j], idx_bits)];
         }
         y_sel[q] = sum;
     }
@@ -275,9 +386,10 @@ int or_precision_trigger(const double* resid, int32_t j, const or_params* p) {
 
 /* ------------------------------------------------------------------------ */
 static void apply_op(const or_matrix* A, int s, const double* x, double* y) {
-    if (s <= 0) or_csr_spmv(A->n_rows, A->row_ptr, A->col, A->val, x, y);
+    if (s == OR_S_LP) or_lp_spmv(A->n_rows, A->row_ptr, A->col, A->lp_val, A->lp_fmt, x, y);
+    else if (s <= 0) or_csr_spmv(A->n_rows, A->row_ptr, A->col, A->val, x, y);
     else or_gse_spmv(A->n_rows, A->row_ptr, A->col_idx, A->head, A->tail1, A->tail2,
-                     A->sem8, s, x, y);
+                     A->sem64, A->idx_bits, s, x, y);
 }
 
 static double dot(int32_t n, const double* a, const double* b) {
@@ -295,6 +407,7 @@ static double residual(const or_matrix* A, int s, const double* b, const double*
 }
 
 static int final_segments(const or_params* p) {
+    if (p->fixed_segments == OR_S_LP) return OR_S_LP;  /* the 16-bit operator judges itself */
     return p->fixed_segments < 0 ? 0 : 3;  /* 0: FP64 CSR operator */
 }
 
@@ -328,7 +441,9 @@ int or_cg(const or_matrix* A, const double* b, double* x, const or_params* p,
     double* q = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     if (!r || !pv || !q) { free(r); free(pv); free(q); return OR_ERR_ARG; }
     int stepped = (p->fixed_segments == 0);
-    int s = stepped ? p->start_segments : (p->fixed_segments > 0 ? p->fixed_segments : 0);
+    int s = stepped ? p->start_segments
+                    : (p->fixed_segments > 0 ? p->fixed_segments
+                                             : (p->fixed_segments == OR_S_LP ? OR_S_LP : 0));
     int fin = final_segments(p);
     double nb = sqrt(dot(n, b, b));
     if (nb == 0.0) {
@@ -439,7 +554,9 @@ int or_gmres(const or_matrix* A, const double* b, double* x, const or_params* p,
     }
 #define HH(i, j) H[(size_t)(i) * (size_t)m + (size_t)(j)]
     int stepped = (p->fixed_segments == 0);
-    int s = stepped ? p->start_segments : (p->fixed_segments > 0 ? p->fixed_segments : 0);
+    int s = stepped ? p->start_segments
+                    : (p->fixed_segments > 0 ? p->fixed_segments
+                                             : (p->fixed_segments == OR_S_LP ? OR_S_LP : 0));
     int fin = final_segments(p);
     double nb = sqrt(dot(n, b, b));
     int32_t it = 0;

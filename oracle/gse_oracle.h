@@ -10,10 +10,14 @@
  * of the benchmark load it.
  *
  * Format (Section III-B, Algorithms 1 and 2, Section III-C.1):
- *   - a table of up to 8 shared exponents, each stored as (biased exponent+1);
- *   - per non-zero: a 3-bit slot index kept in the top bits of the 32-bit
- *     column index, and a 64-bit word  sign<<63 | F63  where F63 is |v| on the
- *     fixed-point grid 2^(SEM-1023-63) of its slot, truncated toward zero;
+ *   - a table of up to 64 shared exponents, each stored as (biased
+ *     exponent+1);
+ *   - per non-zero: a slot index of b = ceil(log2 k) bits for a table of k
+ *     shared exponents (the number of shared exponents sets the index width,
+ *     Section III-B.1), kept in the top b bits of the 32-bit column index
+ *     (Section III-C.1), and a 64-bit word  sign<<63 | F63  where F63 is |v|
+ *     on the fixed-point grid 2^(SEM-1023-63) of its slot, truncated toward
+ *     zero;
  *   - the word is split into three planes: head (bits 63..48), tail1
  *     (bits 47..32) and tail2 (bits 31..0).  Reading s planes gives a
  *     W_s = 15, 31 or 63 bit magnitude.
@@ -22,7 +26,7 @@
 #define GSE_ORACLE_H
 #include <stdint.h>
 
-#define OR_MAX_EXP 8
+#define OR_MAX_EXP 64
 
 enum { OR_OK = 0, OR_NOT_CONVERGED = 2, OR_ERR_ARG = -1, OR_ERR_NONFINITE = -2,
        OR_ERR_RANGE = -3, OR_ERR_BREAKDOWN = -5 };
@@ -37,7 +41,8 @@ typedef struct {
     int32_t restart;     /* GMRES cycle length */
     int32_t max_restarts;
     int32_t start_segments;  /* 1..3 */
-    int32_t fixed_segments;  /* 0: stepped, 1..3: fixed; -1: plain FP64 CSR */
+    int32_t fixed_segments;  /* 0: stepped, 1..3: fixed; -1: plain FP64 CSR;
+                                -2: the FP16 / BF16 operator of the matrix (lp_val) */
     int32_t l, t, m;         /* controller schedule (Section III-D) */
     double rsd_limit;
     int32_t ndec_limit;
@@ -58,33 +63,50 @@ typedef struct {
     double relres_true;
 } or_report;
 
-/* ---- format ---- */
+/* ---- format ----
+ * Tables (sem64) always hold OR_MAX_EXP entries, unused ones 0.  idx_bits is
+ * the slot-index width b of the column word: column = word & (2^(32-b) - 1),
+ * slot = word >> (32 - b) (slot 0 when b = 0). */
+int or_index_bits(int num_exp);
 int64_t or_exponent_histogram(const double* val, int64_t nnz, uint32_t* hist2048);
-int or_select_shared_exponents(const uint32_t* hist2048, int num_exp, int16_t* sem8);
+int or_select_shared_exponents(const uint32_t* hist2048, int num_exp, int16_t* sem64);
 int or_encode_values(const double* val, const int32_t* col, int64_t nnz,
-                     const int16_t* sem8, uint32_t* col_idx, uint16_t* head,
+                     const int16_t* sem64, int idx_bits, uint32_t* col_idx, uint16_t* head,
                      uint16_t* tail1, uint32_t* tail2);
 int or_encode(const int32_t* row_ptr, const int32_t* col, const double* val,
               int32_t n_rows, int32_t n_cols, int64_t nnz, int num_exp,
-              const int16_t* sem_in, int16_t* sem_out, uint32_t* col_idx,
+              const int16_t* sem_in, int16_t* sem_out64, uint32_t* col_idx,
               uint16_t* head, uint16_t* tail1, uint32_t* tail2, double* eta3,
               double* exact_frac);
 double or_decode_one(uint32_t col_word, uint16_t head, uint16_t tail1,
-                     uint32_t tail2, const int16_t* sem8, int s);
+                     uint32_t tail2, const int16_t* sem64, int idx_bits, int s);
 void or_decode(const uint32_t* col_idx, const uint16_t* head, const uint16_t* tail1,
-               const uint32_t* tail2, int64_t nnz, const int16_t* sem8, int s,
-               double* out);
+               const uint32_t* tail2, int64_t nnz, const int16_t* sem64, int idx_bits,
+               int s, double* out);
+
+/* ---- FP16 / BF16 comparators (Section IV-C) ----
+ * fmt: OR_LP_FP16 (IEEE binary16) or OR_LP_BF16 (bfloat16).  Values are
+ * rounded once, to nearest with ties to even; overflow gives an infinity and
+ * is counted (or_lp_convert returns the number of overflows). */
+#define OR_LP_FP16 1
+#define OR_LP_BF16 2
+uint16_t or_lp_round(double v, int fmt, int* overflow);
+double or_lp_widen(uint16_t h, int fmt);
+int64_t or_lp_convert(const double* val, int64_t nnz, int fmt, uint16_t* out);
+void or_lp_spmv(int32_t n_rows, const int32_t* row_ptr, const int32_t* col,
+                const uint16_t* val16, int fmt, const double* x, double* y);
 
 /* ---- SpMV ---- */
 void or_csr_spmv(int32_t n_rows, const int32_t* row_ptr, const int32_t* col,
                  const double* val, const double* x, double* y);
 void or_gse_spmv(int32_t n_rows, const int32_t* row_ptr, const uint32_t* col_idx,
                  const uint16_t* head, const uint16_t* tail1, const uint32_t* tail2,
-                 const int16_t* sem8, int s, const double* x, double* y);
+                 const int16_t* sem64, int idx_bits, int s, const double* x, double* y);
 void or_gse_spmv_rows(const int32_t* rows, int32_t n_sel, const int32_t* row_ptr,
                       const uint32_t* col_idx, const uint16_t* head,
                       const uint16_t* tail1, const uint32_t* tail2,
-                      const int16_t* sem8, int s, const double* x, double* y_sel);
+                      const int16_t* sem64, int idx_bits, int s, const double* x,
+                      double* y_sel);
 
 /* ---- controller (Section III-D, Eqs. 3-6, Conditions 1-3) ---- */
 void or_window_metrics(const double* resid, int32_t j, int32_t t,
@@ -93,7 +115,7 @@ int or_precision_trigger(const double* resid, int32_t j, const or_params* p);
 
 /* ---- solvers ----
  * The matrix is either plain FP64 CSR (fixed_segments == -1: col/val used) or
- * GSE planes (col_idx/head/tail1/tail2/sem8 used).  x holds x0 on entry.
+ * GSE planes (col_idx/head/tail1/tail2/sem64/idx_bits used).  x holds x0 on entry.
  * hist (optional, may be NULL) receives relres per iteration, [max_iter+1];
  * seg_hist (optional) the segment count used by each iteration.           */
 typedef struct {
@@ -105,9 +127,14 @@ typedef struct {
     const uint16_t* head;
     const uint16_t* tail1;
     const uint32_t* tail2;
-    const int16_t* sem8;
+    const int16_t* sem64;
     const double* eta3;
+    int32_t idx_bits;
+    const uint16_t* lp_val;  /* FP16 / BF16 values (fixed_segments == -2) */
+    int32_t lp_fmt;
 } or_matrix;
+
+#define OR_S_LP (-2)
 
 int or_cg(const or_matrix* A, const double* b, double* x, const or_params* p,
           or_report* rep, double* hist, int32_t* seg_hist);
