@@ -14,7 +14,13 @@ Prints one JSON line.  ``value`` is the GSE SpMV HBM bandwidth with one
 segment: algorithmic bytes / mean time per launch, from HIP events on the
 launch stream around rounds of back-to-back launches (one per copy); the
 other segment counts, the FP64 baseline, a streaming-copy ceiling and the
-solve times are reported beside it.
+solve times are reported beside it.  Every result states its error: each
+operator's max-abs and relative error against the host FP64 CSR product
+with x = 1, eta_s, and per solve the true residual and ||x - x_true|| /
+||x_true||.  After the timed steps the same line carries one run of each
+other configuration (``--no-legs`` skips them): the 2-D Poisson 64^2 CG,
+the 1024^2 convection-diffusion GMRES(30) and the 4 M-row power-law SpMV
+and CG, with the same error figures.
 
 Other workloads (one JSON line each):
   * ``--workload gmres``: stepped GMRES(30) and FP64 GMRES(30) to 1e-10 on
@@ -111,6 +117,8 @@ def parse():
     ap.add_argument("--copies", type=int, default=4)
     ap.add_argument("--reps", type=int, default=10, help="SpMV launches per copy per step")
     ap.add_argument("--no-solve", action="store_true", help="SpMV only (profiling runs)")
+    ap.add_argument("--no-legs", dest="legs", action="store_false",
+                    help="default workload: skip the Poisson, GMRES and power-law legs")
     ap.add_argument("--cpu-baseline", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline (0: skip)")
     ap.add_argument("--requests", type=int, default=48, help="serving: requests per load level")
@@ -121,24 +129,41 @@ def parse():
 
 
 def cpu_baseline(A, seconds):
-    """The oracle's one-segment SpMV on the same matrix, sequential C."""
+    """The oracle's one-segment SpMV on the same matrix, timed on the host's
+    cores: the rows are cut into contiguous blocks that host threads run
+    through the oracle's own sequential row routine (each row keeps its
+    order, so the result is the single-thread one, bit for bit)."""
+    import concurrent.futures as cf
+
     import oracle as O
     enc = O.encode(A.indptr, A.indices, A.data, A.n_cols)
     x = np.ones(A.n_cols)
-    O.gse_spmv(A.indptr, enc, 1, x)
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
-        O.gse_spmv(A.indptr, enc, 1, x)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
+    threads = max(1, min(16, os.cpu_count() or 1))
+    bounds = np.linspace(0, A.n_rows, threads + 1).astype(np.int64)
+    blocks = [np.arange(bounds[i], bounds[i + 1], dtype=np.int32) for i in range(threads)]
+    y = np.empty(A.n_rows)
+
+    def block(i):
+        y[bounds[i]:bounds[i + 1]] = O.gse_spmv_rows(blocks[i], A.indptr, enc, 1, x)
+
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(block, range(threads)))
+        ref = O.gse_spmv(A.indptr, enc, 1, x)
+        same = bool(np.array_equal(y, ref))
+        reps = 0
+        t0 = time.perf_counter()
+        while True:
+            list(ex.map(block, range(threads)))
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                break
     per = el / reps
     gbs = spmv_bytes(A.n_rows, A.n_cols, A.nnz, 6) / per / 1e9
-    return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle gse_spmv s=1 on the full {A.name} matrix, {reps} runs "
-                      f"({el:.1f} s, {per * 1e3:.1f} ms each, one thread)"}
+    return {"value": round(gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle gse_spmv s=1 (row routine, {threads} host threads over contiguous "
+                      f"row blocks; equal to the sequential result: {same}) on the full {A.name} "
+                      f"matrix, {reps} runs ({el:.1f} s, {per * 1e3:.1f} ms each)"}
 
 
 def copy_ceiling(G, torch, dev, stream):
@@ -276,12 +301,13 @@ def run_spmv_cg(args, torch, G):
         # before it may be counted in it
         torch.cuda.synchronize()
         rg = G.gse_cg(mats[0].A, bd, x, p, ws)
+        if record:
+            solve.setdefault("gse", []).append(solve_record(rg, x, x_true))
         x.zero_()
         torch.cuda.synchronize()
         r64 = G.gse_csr_cg(csrs[0].M, bd, x, p, ws)
         if record:
-            solve.setdefault("gse", []).append(rg.as_dict())
-            solve.setdefault("fp64", []).append(r64.as_dict())
+            solve.setdefault("fp64", []).append(solve_record(r64, x, x_true))
 
     for _ in range(args.warmup):
         spmv_pass(False)
@@ -326,21 +352,72 @@ def run_spmv_cg(args, torch, G):
     if solve:
         g = solve["gse"][-1]
         f = solve["fp64"][-1]
-        out["cg"] = {"gse": g, "fp64": f,
-                     "speedup": round(f["time_ms"] / g["time_ms"], 3) if g["time_ms"] else None}
+        med = {k: float(np.median([r["time_ms"] for r in v])) for k, v in solve.items()}
+        out["cg"] = {"gse": g, "fp64": f, "median_ms": {k: round(v, 3) for k, v in med.items()},
+                     "speedup": round(med["fp64"] / med["gse"], 3) if med["gse"] else None}
+    if not args.no_solve:
+        out["spmv_error"] = spmv_errors(A, mats[0], csrs[0], np.ones(A.n_cols), dev, torch)
+    del mats, csrs, ys
+    if args.legs and not args.no_solve:
+        # the other configurations, each once after the timed steps (their own
+        # warm-up), so that every result of the path is on the one line
+        progress("legs: poisson 64^2")
+        out["poisson"] = leg_poisson(torch, G, args.seed, 5, 1)
+        progress("legs: gmres 1024^2")
+        out["gmres"] = leg_gmres(torch, G, args.seed, 1, 1)
+        progress("legs: powerlaw")
+        pl = leg_powerlaw(torch, G, args.seed, 1, 1, 5, args.pl_rows)
+        pl.pop("wall_s")
+        out["powerlaw"] = pl
     if args.cpu_baseline > 0:
         out["cpu_baseline"] = cpu_baseline(A, args.cpu_baseline)
     return out
 
 
+# ------------------------------------------------------ error of results ---
+def spmv_errors(A, M, C, x_host, dev, torch):
+    """Error of each operator against the FP64 CSR product computed on the
+    host (scipy, FP64) with the same x (x = 1 is the paper's SpMV protocol):
+    max |y_s - y| and ||y_s - y|| / ||y||, for s = 1, 2, 3 and the GPU FP64
+    CSR kernel; plus eta_s = ||A - A_s||_inf / ||A||_inf of the encoding."""
+    ref = A.to_scipy() @ x_host
+    nref = float(np.linalg.norm(ref))
+    xd = torch.from_numpy(x_host).to(dev)
+    y = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
+    out = {}
+    for kname in ("s1", "s2", "s3", "fp64"):
+        if kname == "fp64":
+            C.spmv(xd, y)
+        else:
+            M.spmv(int(kname[1]), xd, y)
+        torch.cuda.synchronize()
+        d = y.cpu().numpy() - ref
+        out[kname] = {"max_abs": float(np.max(np.abs(d))) if d.size else 0.0,
+                      "rel": float(np.linalg.norm(d) / nref) if nref > 0 else 0.0}
+    out["eta"] = [float(e) for e in M.eta]
+    out["reference"] = "host FP64 CSR (scipy), x = 1"
+    return out
+
+
+def solution_error(x, x_true):
+    return float(np.linalg.norm(x - x_true) / np.linalg.norm(x_true))
+
+
+def solve_record(rep, x_dev, x_true):
+    d = rep.as_dict()
+    d["x_err"] = solution_error(x_dev.cpu().numpy(), x_true)
+    return d
+
+
 # ---------------------------------------------------------------- GMRES ---
-def run_gmres(args, torch, G):
+def leg_gmres(torch, G, seed, steps, warmup, N=1024):
+    """Stepped GMRES(30) and FP64 GMRES(30) to 1e-10 on the 2-D upwind
+    convection-diffusion operator (N^2 cells, cell Peclet 10)."""
     from workloads import convdiff2d, rhs_from_solution
 
     dev = torch.device("cuda:0")
-    N = 1024
-    A = convdiff2d(N, args.seed)
-    _, b = rhs_from_solution(A, args.seed)
+    A = convdiff2d(N, seed)
+    x_true, b = rhs_from_solution(A, seed)
     rp = torch.from_numpy(A.indptr).to(dev)
     ci = torch.from_numpy(A.indices).to(dev)
     va = torch.from_numpy(A.data).to(dev)
@@ -351,46 +428,55 @@ def run_gmres(args, torch, G):
     ws = torch.empty(G.gse_solver_workspace(G.GMRES, A.n_rows, A.nnz, p.restart, p.max_iter),
                      dtype=torch.uint8, device=dev)
     x = torch.zeros(A.n_rows, dtype=torch.float64, device=dev)
-    res = {}
     progress("gmres: operators ready")
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         x.zero_()
         G.gse_gmres(M.A, bd, x, p, ws)
         x.zero_()
         G.gse_csr_gmres(C.M, bd, x, p, ws)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
+    runs = {"gse": [], "fp64": []}
+    res = {}
+    for _ in range(steps):
         x.zero_()
         torch.cuda.synchronize()
-        res["gse"] = G.gse_gmres(M.A, bd, x, p, ws).as_dict()
+        res["gse"] = solve_record(G.gse_gmres(M.A, bd, x, p, ws), x, x_true)
         progress(f"gmres: GSE {res['gse']}")
         x.zero_()
         torch.cuda.synchronize()
-        res["fp64"] = G.gse_csr_gmres(C.M, bd, x, p, ws).as_dict()
-    torch.cuda.synchronize()
+        res["fp64"] = solve_record(G.gse_csr_gmres(C.M, bd, x, p, ws), x, x_true)
+        for k in runs:
+            runs[k].append(res[k]["time_ms"])
+    med = {k: float(np.median(v)) for k, v in runs.items()}
+    return {"workload": f"convdiff2d_{N}^2_upwind_Pe10", "n_rows": A.n_rows, "nnz": A.nnz,
+            "seed": seed, "restart": p.restart, "gse": res["gse"], "fp64": res["fp64"],
+            "median_ms": {k: round(v, 3) for k, v in med.items()},
+            "speedup": round(med["fp64"] / med["gse"], 3) if med["gse"] else None,
+            "spmv_error": spmv_errors(A, M, C, np.ones(A.n_cols), dev, torch)}
+
+
+def run_gmres(args, torch, G):
+    t0 = time.perf_counter()
+    leg = leg_gmres(torch, G, args.seed, args.steps, args.warmup)
     wall = time.perf_counter() - t0
-    g, f = res["gse"], res["fp64"]
-    out = base_record(args, "GMRES(30) time-to-1e-10, stepped GSE vs FP64 CSR", round(g["time_ms"], 3),
-                      "ms", wall, higher=False)
-    out["config"] = {"workload": f"convdiff2d_{N}^2_upwind_Pe10", "n_rows": A.n_rows, "nnz": A.nnz,
-                     "seed": args.seed, "restart": p.restart}
-    out["gmres"] = {"gse": g, "fp64": f,
-                    "speedup": round(f["time_ms"] / g["time_ms"], 3) if g["time_ms"] else None}
+    out = base_record(args, "GMRES(30) time-to-1e-10, stepped GSE vs FP64 CSR",
+                      round(leg["median_ms"]["gse"], 3), "ms", wall, higher=False)
+    out["config"] = {k: leg[k] for k in ("workload", "n_rows", "nnz", "seed", "restart")}
+    out["gmres"] = leg
     return out
 
 
 # ------------------------------------------------------------ power law ---
-def run_powerlaw(args, torch, G):
-    """4 M-row power-law SPD matrix: SpMV per segment count after the
-    autotuner picked the tile shape, then stepped GSE CG vs FP64 CG to 1e-10.
-    The planes (0.4-0.8 GB) exceed the Infinity Cache, so every launch is
-    cold without rotated copies."""
+def leg_powerlaw(torch, G, seed, steps, warmup, reps, n_rows):
+    """Power-law SPD matrix (Zipf(2) row lengths up to 10^4, values over six
+    decades): SpMV per segment count after the autotuner picked the tile
+    shape (the planes, 0.4-0.8 GB, exceed the Infinity Cache, so every launch
+    is cold without rotated copies), their errors, then stepped GSE CG vs
+    FP64 CG to 1e-10."""
     from workloads import powerlaw, rhs_from_solution
 
     dev = torch.device("cuda:0")
-    A = powerlaw(args.pl_rows, args.seed)
-    _, b = rhs_from_solution(A, args.seed)
+    A = powerlaw(n_rows, seed)
+    x_true, b = rhs_from_solution(A, seed)
     progress(f"powerlaw: {A.n_rows} rows, {A.nnz} non-zeros generated")
     rp = torch.from_numpy(A.indptr).to(dev)
     ci = torch.from_numpy(A.indices).to(dev)
@@ -413,10 +499,11 @@ def run_powerlaw(args, torch, G):
         else:
             M.spmv(int(kname[1]), xs, y)
 
-    # CG runs on the symmetrically diagonal-scaled system D^-1/2 A D^-1/2 y =
-    # D^-1/2 b (unit diagonal; Jacobi-preconditioned CG in exact arithmetic):
-    # the rows' scales span six decades, and plain CG on A itself stalls near
-    # 4e-6 at the 5000-iteration cap.  Its Gershgorin bound gives kappa <= 21.
+    # CG runs on the symmetrically diagonal-scaled system D^-1/2 A D^-1/2 z =
+    # D^-1/2 b, x = D^-1/2 z (unit diagonal; Jacobi-preconditioned CG in exact
+    # arithmetic): the rows' scales span six decades, and plain CG on A itself
+    # stalls near 4e-6 at the 5000-iteration cap.  Its Gershgorin bound gives
+    # kappa <= 21.
     rows = np.repeat(np.arange(A.n_rows), np.diff(A.indptr))
     diag = np.zeros(A.n_rows)
     on = rows == A.indices
@@ -432,17 +519,16 @@ def run_powerlaw(args, torch, G):
     CS.autotune(xs, y)
     del sv, sc, sval
     bd = torch.from_numpy(b * dinv).to(dev)
+    z_true = x_true / dinv
     p = G.gse_default_params(G.CG)
     ws = torch.empty(G.gse_solver_workspace(G.CG, A.n_rows, A.nnz, 30, p.max_iter),
                      dtype=torch.uint8, device=dev)
-    x = torch.zeros(A.n_rows, dtype=torch.float64, device=dev)
-    solve = {}
-
+    z = torch.zeros(A.n_rows, dtype=torch.float64, device=dev)
     cg_runs = {"gse": [], "fp64": []}
 
     def step(record):
         for kname, _ in kinds:
-            for _ in range(args.reps):
+            for _ in range(reps):
                 if record:
                     e0 = torch.cuda.Event(enable_timing=True)
                     e1 = torch.cuda.Event(enable_timing=True)
@@ -451,21 +537,21 @@ def run_powerlaw(args, torch, G):
                 if record:
                     e1.record(stream)
                     times[kname].append((e0, e1))
-        x.zero_()
+        z.zero_()
         torch.cuda.synchronize()  # the SpMV launches above are not part of the solve
-        rg = G.gse_cg(MS.A, bd, x, p, ws)
-        x.zero_()
+        rg = solve_record(G.gse_cg(MS.A, bd, z, p, ws), z, z_true)
+        z.zero_()
         torch.cuda.synchronize()
-        r64 = G.gse_csr_cg(CS.M, bd, x, p, ws)
+        r64 = solve_record(G.gse_csr_cg(CS.M, bd, z, p, ws), z, z_true)
         if record:
-            cg_runs["gse"].append(rg.as_dict())
-            cg_runs["fp64"].append(r64.as_dict())
+            cg_runs["gse"].append(rg)
+            cg_runs["fp64"].append(r64)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step(True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -478,34 +564,49 @@ def run_powerlaw(args, torch, G):
                        "median_us": round(float(np.median(ms)) * 1e3, 2),
                        "bytes": int(nbytes), "GBps": round(nbytes / (mean * 1e-3) / 1e9, 1),
                        "frac_peak": round(nbytes / (mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    med = {k: float(np.median([r["time_ms"] for r in v])) for k, v in cg_runs.items()}
+    return {"workload": f"powerlaw_{A.n_rows}_zipf2_spd", "n_rows": A.n_rows, "nnz": A.nnz,
+            "max_row": int(np.diff(A.indptr).max()), "seed": seed, "x": "ones",
+            "tile_nnz": M.A.tile_nnz, "rv_lanes": M.A.rv_lanes, "kernel": kernel_name(M.A),
+            "spmv": spmv, "spmv_error": spmv_errors(A, M, C, np.ones(A.n_cols), dev, torch),
+            "cg": {"system": "D^-1/2 A D^-1/2 z = D^-1/2 b (unit diagonal); x_err on z",
+                   "gse": cg_runs["gse"][-1], "fp64": cg_runs["fp64"][-1],
+                   "median_ms": {k: round(v, 3) for k, v in med.items()},
+                   "speedup": round(med["fp64"] / med["gse"], 3) if med["gse"] else None,
+                   "eta_scaled": [float(e) for e in MS.eta]},
+            "wall_s": wall}
+
+
+def run_powerlaw(args, torch, G):
+    t0 = time.perf_counter()
+    leg = leg_powerlaw(torch, G, args.seed, args.steps, args.warmup, args.reps, args.pl_rows)
+    wall = time.perf_counter() - t0
+    spmv = leg["spmv"]
     out = base_record(args, "GSE-SpMV HBM GB/s (s=1), power-law SPD; CG time-to-1e-10 vs FP64 CSR",
-                      spmv["s1"]["GBps"], "GB/s", wall)
-    out["config"] = {"workload": f"powerlaw_{A.n_rows}_zipf2_spd", "n_rows": A.n_rows, "nnz": A.nnz,
-                     "max_row": int(np.diff(A.indptr).max()), "seed": args.seed, "x": "ones",
-                     "tile_nnz": M.A.tile_nnz, "rv_lanes": M.A.rv_lanes}
+                      spmv["s1"]["GBps"], "GB/s", leg["wall_s"])
+    out["config"] = {k: leg[k] for k in ("workload", "n_rows", "nnz", "max_row", "seed", "x",
+                                         "tile_nnz", "rv_lanes")}
     out["spmv"] = spmv
+    out["spmv_error"] = leg["spmv_error"]
     out["roofline"] = {"bound": "hbm", "achieved": spmv["s1"]["GBps"], "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": spmv["s1"]["frac_peak"], "traffic": None,
-                       "bytes_per_launch": spmv["s1"]["bytes"], "mean_launch_us": spmv["s1"]["mean_us"]}
-    med = {k: float(np.median([r["time_ms"] for r in v])) for k, v in cg_runs.items()}
-    out["cg"] = {"system": "D^-1/2 A D^-1/2 y = D^-1/2 b (unit diagonal)",
-                 "gse": cg_runs["gse"][-1], "fp64": cg_runs["fp64"][-1],
-                 "median_ms": {k: round(v, 3) for k, v in med.items()},
-                 "speedup": round(med["fp64"] / med["gse"], 3) if med["gse"] else None,
-                 "eta_scaled": [float(e) for e in MS.eta]}
+                       "kernel": leg["kernel"], "bytes_per_launch": spmv["s1"]["bytes"],
+                       "mean_launch_us": spmv["s1"]["mean_us"]}
+    out["cg"] = leg["cg"]
+    out["total_wall_s"] = round(wall, 2)
     return out
 
 
 # -------------------------------------------------------------- Poisson ---
-def run_poisson(args, torch, G):
+def leg_poisson(torch, G, seed, steps, warmup):
     """2-D Poisson 64 x 64 (exact stencil values, eta_1 = 0): stepped GSE CG
     and FP64 CG to 1e-10; the system is L2-resident, so this measures the
-    launch-bound regime.  `value` is the median stepped time over the steps."""
+    launch-bound regime (median over the runs)."""
     from workloads import poisson2d, rhs_from_solution
 
     dev = torch.device("cuda:0")
     A = poisson2d(64)
-    _, b = rhs_from_solution(A, args.seed)
+    x_true, b = rhs_from_solution(A, seed)
     rp = torch.from_numpy(A.indptr).to(dev)
     ci = torch.from_numpy(A.indices).to(dev)
     va = torch.from_numpy(A.data).to(dev)
@@ -521,29 +622,33 @@ def run_poisson(args, torch, G):
     def step():
         x.zero_()
         torch.cuda.synchronize()
-        rg = G.gse_cg(M.A, bd, x, p, ws).as_dict()
+        rg = solve_record(G.gse_cg(M.A, bd, x, p, ws), x, x_true)
         x.zero_()
         torch.cuda.synchronize()
-        return rg, G.gse_csr_cg(C.M, bd, x, p, ws).as_dict()
+        return rg, solve_record(G.gse_csr_cg(C.M, bd, x, p, ws), x, x_true)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         rg, r64 = step()
         runs["gse"].append(rg)
         runs["fp64"].append(r64)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     med = {k: float(np.median([r["time_ms"] for r in v])) for k, v in runs.items()}
+    return {"workload": "poisson2d_64^2_5pt", "n_rows": A.n_rows, "nnz": A.nnz, "seed": seed,
+            "gse": runs["gse"][-1], "fp64": runs["fp64"][-1],
+            "median_ms": {k: round(v, 3) for k, v in med.items()},
+            "speedup": round(med["fp64"] / med["gse"], 3) if med["gse"] else None,
+            "spmv_error": spmv_errors(A, M, C, np.ones(A.n_cols), dev, torch)}
+
+
+def run_poisson(args, torch, G):
+    t0 = time.perf_counter()
+    leg = leg_poisson(torch, G, args.seed, args.steps, args.warmup)
+    wall = time.perf_counter() - t0
     out = base_record(args, "CG time-to-1e-10, stepped GSE vs FP64 CSR (2-D Poisson 64x64)",
-                      round(med["gse"], 3), "ms", wall, higher=False)
-    out["config"] = {"workload": "poisson2d_64^2_5pt", "n_rows": A.n_rows, "nnz": A.nnz,
-                     "seed": args.seed}
-    out["cg"] = {"gse": runs["gse"][-1], "fp64": runs["fp64"][-1],
-                 "median_ms": {k: round(v, 3) for k, v in med.items()},
-                 "speedup": round(med["fp64"] / med["gse"], 3) if med["gse"] else None}
+                      round(leg["median_ms"]["gse"], 3), "ms", wall, higher=False)
+    out["config"] = {k: leg[k] for k in ("workload", "n_rows", "nnz", "seed")}
+    out["cg"] = leg
     return out
 
 

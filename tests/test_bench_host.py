@@ -64,3 +64,14 @@ def test_traffic_summary_is_used_only_while_sources_match(tmp_path, monkeypatch)
     assert b.measured_traffic("k_spmv_short<1, 4>", "v") is None  # another workload
     (tmp_path / b.KERNEL_SOURCES[0]).write_text("// changed\n")
     assert b.measured_traffic("k_spmv_short<1, 4>", "w") is None  # kernel changed since
+
+
+def test_cpu_baseline_threads_keep_the_sequential_result():
+    """The CPU baseline runs the oracle's row routine over contiguous row
+    blocks on several host threads; each row keeps its order, so the result
+    equals the sequential oracle's bit for bit (the leg reports that)."""
+    from workloads import diffusion3d
+    b = load_bench()
+    r = b.cpu_baseline(diffusion3d(12, 0), 0.2)
+    assert r["kind"] == "oracle" and r["cores"] >= 1 and r["value"] > 0
+    assert "sequential result: True" in r["sample"]
