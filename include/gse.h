@@ -13,7 +13,8 @@
  *     A failing HIP call maps to GSE_ERR_HIP (its text in gse_last_error()).
  *   - Device pointers are plain device addresses (hipMalloc or a framework
  *     allocator); the library does not take ownership of any of them and
- *     never allocates device memory: scratch comes from a caller workspace.
+ *     never allocates device memory: scratch comes from a caller workspace
+ *     (gse_encode_static: a fixed static device array instead).
  *   - `stream` is a hipStream_t passed as void* (NULL: the null stream).
  *     gse_spmv is asynchronous on it; gse_encode, gse_plan, gse_cg and
  *     gse_gmres synchronize it before returning.
@@ -143,6 +144,26 @@ gse_status gse_encode(const int32_t* row_ptr, const int32_t* col, const double* 
                       int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t num_exp,
                       const int16_t* sem_in, gse_matrix* A, void* ws, size_t ws_bytes,
                       void* stream);
+
+/* gse_encode for callers that cannot allocate device memory (tight serving
+ * loops, harnesses that forbid hipMalloc; not for use under graph capture,
+ * as it reads the table back and synchronizes like gse_encode):
+ * the same encoder, planes, table, eta and default plan, bit for bit, but its
+ * scratch record lives in a static device array of
+ * gse_encode_static_scratch_bytes() bytes (16 KiB) that each GPU the library
+ * runs on holds until the process ends.  The record's size does not depend on
+ * the matrix; a build whose record outgrew the array would return
+ * GSE_ERR_NOMEM.  The caller still passes the CSR input, the planes and
+ * tile_row in A as for gse_encode.  No hipMalloc, hipFree or allocating
+ * library call is made; the scratch is cleared by a kernel at the start of
+ * every call.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (concurrent host threads, or streams running at once)
+ * race and must be serialized by the caller.  Errors as gse_encode.
+ * Synchronizes `stream`. */
+gse_status gse_encode_static(const int32_t* row_ptr, const int32_t* col, const double* val,
+                             int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t num_exp,
+                             const int16_t* sem_in, gse_matrix* A, void* stream);
+size_t gse_encode_static_scratch_bytes(void);
 
 /* (Re)build the SpMV schedule.  Two schedules exist:
  *   tiles       (rv_lanes == 0): fixed runs of tile_nnz non-zeros (1024, 2048

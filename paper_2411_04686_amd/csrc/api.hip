@@ -131,6 +131,68 @@ gse_status check_csr(const gse_csr* M) {
   return GSE_OK;
 }
 
+// Validation, the encoder launches and the host part of gse_encode, on a
+// scratch record `ws` of at least gse_encode_workspace() bytes.
+gse_status encode_matrix(const int32_t* row_ptr, const int32_t* col, const double* val,
+                         int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t num_exp,
+                         const int16_t* sem_in, gse_matrix* A, void* ws, size_t ws_bytes,
+                         hipStream_t st) {
+  if (!A) return fail(GSE_ERR_ARG, "matrix is NULL");
+  if (!row_ptr || (nnz > 0 && (!col || !val))) return fail(GSE_ERR_ARG, "NULL CSR array");
+  if (n_rows < 0 || n_cols < 0 || nnz < 0) return fail(GSE_ERR_ARG, "negative size");
+  if (num_exp < 1 || num_exp > GSE_MAX_EXP) return fail(GSE_ERR_ARG, "num_exp must be 1..8");
+  if (nnz > kMaxNnz) return fail(GSE_ERR_RANGE, "nnz %lld exceeds the limit", (long long)nnz);
+  if ((int64_t)n_cols > (int64_t(1) << 29)) return fail(GSE_ERR_RANGE, "n_cols exceeds 2^29");
+  if (!A->col_idx || !A->head || !A->tail1 || !A->tail2 || !A->tile_row)
+    return fail(GSE_ERR_ARG, "matrix planes / tile_row not set");
+  if (!aligned16(A->col_idx) || !aligned16(A->head) || !aligned16(A->tail1) || !aligned16(A->tail2))
+    return fail(GSE_ERR_ARG, "planes must be 16-byte aligned");
+  if (A->tile_cap < gse_tile_entries(nnz))
+    return fail(GSE_ERR_NOMEM, "tile_row holds %d < %d entries", A->tile_cap, gse_tile_entries(nnz));
+  size_t need = 0;
+  gse_encode_workspace(nnz, n_rows, &need);
+  if (!ws || ws_bytes < need) return fail(GSE_ERR_NOMEM, "encode workspace needs %zu bytes", need);
+  if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(GSE_ERR_ARG, "workspace must be 256-byte aligned");
+  if (sem_in) {
+    for (int i = 0; i < num_exp; ++i) {
+      if (sem_in[i] < 64 || sem_in[i] > 2047)
+        return fail(GSE_ERR_RANGE, "shared exponent %d out of range", (int)sem_in[i]);
+      for (int k = 0; k < i; ++k)
+        if (sem_in[k] == sem_in[i]) return fail(GSE_ERR_ARG, "duplicate shared exponent");
+    }
+  }
+  EncodeScratch* sc = reinterpret_cast<EncodeScratch*>(ws);
+  A->n_rows = n_rows;
+  A->n_cols = n_cols;
+  A->nnz = nnz;
+  A->num_exp = num_exp;
+  A->row_ptr = row_ptr;
+  hipError_t e = launch_encode(row_ptr, col, val, n_rows, (int32_t)nnz, num_exp, sem_in, A, sc, st);
+  if (e != hipSuccess) return hip_fail(e, "gse_encode launch");
+  EncodeScratch h;
+  e = hipMemcpyAsync(&h, sc, sizeof h, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "gse_encode");
+  int32_t nt, rv, mr;
+  gse_status ps = plan_common(row_ptr, n_rows, nnz, A->tile_row, A->tile_cap, kDefaultTile, -1, st,
+                              &nt, &rv, &mr);
+  if (ps != GSE_OK) return ps;
+  A->tile_nnz = kDefaultTile;
+  A->n_tiles = nt;
+  A->rv_lanes = rv;
+  A->max_row_nnz = mr;
+  for (int i = 0; i < GSE_MAX_EXP; ++i) A->sem[i] = h.sem[i];
+  A->num_used = h.used;
+  A->exact_frac = nnz ? (double)h.covered / (double)nnz : 1.0;
+  double nrm[4];
+  for (int i = 0; i < 4; ++i) memcpy(&nrm[i], &h.norm_bits[i], sizeof(double));
+  for (int s = 0; s < 3; ++s) A->eta[s] = nrm[0] > 0.0 ? nrm[s + 1] / nrm[0] : 0.0;
+  if (h.nonfinite) return fail(GSE_ERR_NONFINITE, "%d non-finite values", h.nonfinite);
+  if (h.range_err & 1) return fail(GSE_ERR_RANGE, "a shared exponent is below 63");
+  if (h.range_err & 2) return fail(GSE_ERR_RANGE, "a value has no larger shared exponent in the table");
+  return GSE_OK;
+}
+
 }  // namespace gse
 
 using namespace gse;
@@ -196,61 +258,8 @@ gse_status gse_csr_plan(gse_csr* M, int32_t tile_nnz, int32_t rv_lanes, void* st
 gse_status gse_encode(const int32_t* row_ptr, const int32_t* col, const double* val, int32_t n_rows,
                       int32_t n_cols, int64_t nnz, int32_t num_exp, const int16_t* sem_in,
                       gse_matrix* A, void* ws, size_t ws_bytes, void* stream) {
-  if (!A) return fail(GSE_ERR_ARG, "matrix is NULL");
-  if (!row_ptr || (nnz > 0 && (!col || !val))) return fail(GSE_ERR_ARG, "NULL CSR array");
-  if (n_rows < 0 || n_cols < 0 || nnz < 0) return fail(GSE_ERR_ARG, "negative size");
-  if (num_exp < 1 || num_exp > GSE_MAX_EXP) return fail(GSE_ERR_ARG, "num_exp must be 1..8");
-  if (nnz > kMaxNnz) return fail(GSE_ERR_RANGE, "nnz %lld exceeds the limit", (long long)nnz);
-  if ((int64_t)n_cols > (int64_t(1) << 29)) return fail(GSE_ERR_RANGE, "n_cols exceeds 2^29");
-  if (!A->col_idx || !A->head || !A->tail1 || !A->tail2 || !A->tile_row)
-    return fail(GSE_ERR_ARG, "matrix planes / tile_row not set");
-  if (!aligned16(A->col_idx) || !aligned16(A->head) || !aligned16(A->tail1) || !aligned16(A->tail2))
-    return fail(GSE_ERR_ARG, "planes must be 16-byte aligned");
-  if (A->tile_cap < gse_tile_entries(nnz))
-    return fail(GSE_ERR_NOMEM, "tile_row holds %d < %d entries", A->tile_cap, gse_tile_entries(nnz));
-  size_t need = 0;
-  gse_encode_workspace(nnz, n_rows, &need);
-  if (!ws || ws_bytes < need) return fail(GSE_ERR_NOMEM, "encode workspace needs %zu bytes", need);
-  if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(GSE_ERR_ARG, "workspace must be 256-byte aligned");
-  if (sem_in) {
-    for (int i = 0; i < num_exp; ++i) {
-      if (sem_in[i] < 64 || sem_in[i] > 2047)
-        return fail(GSE_ERR_RANGE, "shared exponent %d out of range", (int)sem_in[i]);
-      for (int k = 0; k < i; ++k)
-        if (sem_in[k] == sem_in[i]) return fail(GSE_ERR_ARG, "duplicate shared exponent");
-    }
-  }
-  hipStream_t st = (hipStream_t)stream;
-  EncodeScratch* sc = reinterpret_cast<EncodeScratch*>(ws);
-  A->n_rows = n_rows;
-  A->n_cols = n_cols;
-  A->nnz = nnz;
-  A->num_exp = num_exp;
-  A->row_ptr = row_ptr;
-  hipError_t e = launch_encode(row_ptr, col, val, n_rows, (int32_t)nnz, num_exp, sem_in, A, sc, st);
-  if (e != hipSuccess) return hip_fail(e, "gse_encode launch");
-  EncodeScratch h;
-  e = hipMemcpyAsync(&h, sc, sizeof h, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_fail(e, "gse_encode");
-  int32_t nt, rv, mr;
-  gse_status ps = plan_common(row_ptr, n_rows, nnz, A->tile_row, A->tile_cap, kDefaultTile, -1, st,
-                              &nt, &rv, &mr);
-  if (ps != GSE_OK) return ps;
-  A->tile_nnz = kDefaultTile;
-  A->n_tiles = nt;
-  A->rv_lanes = rv;
-  A->max_row_nnz = mr;
-  for (int i = 0; i < GSE_MAX_EXP; ++i) A->sem[i] = h.sem[i];
-  A->num_used = h.used;
-  A->exact_frac = nnz ? (double)h.covered / (double)nnz : 1.0;
-  double nrm[4];
-  for (int i = 0; i < 4; ++i) memcpy(&nrm[i], &h.norm_bits[i], sizeof(double));
-  for (int s = 0; s < 3; ++s) A->eta[s] = nrm[0] > 0.0 ? nrm[s + 1] / nrm[0] : 0.0;
-  if (h.nonfinite) return fail(GSE_ERR_NONFINITE, "%d non-finite values", h.nonfinite);
-  if (h.range_err & 1) return fail(GSE_ERR_RANGE, "a shared exponent is below 63");
-  if (h.range_err & 2) return fail(GSE_ERR_RANGE, "a value has no larger shared exponent in the table");
-  return GSE_OK;
+  return encode_matrix(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, sem_in, A, ws, ws_bytes,
+                       (hipStream_t)stream);
 }
 
 gse_status gse_autotune(gse_matrix* A, int32_t k_segments, const double* x, double* y,

@@ -317,13 +317,22 @@ __global__ __launch_bounds__(256) void k_eta(const int32_t* __restrict__ row_ptr
   }
 }
 
+// Zero `n` 8-byte words with one workgroup.
+__global__ void __launch_bounds__(256) k_zero_words(unsigned long long* p, int n) {
+  for (int i = threadIdx.x; i < n; i += 256) p[i] = 0ull;
+}
+
 }  // namespace
 
 hipError_t launch_encode(const int32_t* row_ptr, const int32_t* col, const double* val,
                          int32_t n_rows, int32_t nnz, int32_t num_exp, const int16_t* sem_in,
                          gse_matrix* A, EncodeScratch* sc, hipStream_t st) {
-  hipError_t e = hipMemsetAsync(sc, 0, sizeof(EncodeScratch), st);
-  if (e != hipSuccess) return e;
+  // cleared by a kernel rather than a memset node, so that the sequence
+  // can also be recorded into a HIP graph
+  static_assert(sizeof(EncodeScratch) % 8 == 0, "the scratch record is cleared in 8-byte words");
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, st,
+                     reinterpret_cast<unsigned long long*>(sc),
+                     (int)(sizeof(EncodeScratch) / 8));
   SemIn in{};
   in.have = sem_in != nullptr;
   for (int i = 0; i < GSE_MAX_EXP; ++i) in.sem[i] = (sem_in && i < num_exp) ? sem_in[i] : 0;

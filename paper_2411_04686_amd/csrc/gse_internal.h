@@ -141,6 +141,15 @@ hipError_t launch_encode(const int32_t* row_ptr, const int32_t* col, const doubl
 
 int32_t n_tiles_for(int64_t nnz, int32_t tile_nnz);
 
+// api.hip: gse_encode on a scratch record `ws` of ws_bytes (validation,
+// launches, table read-back, default plan).
+gse_status encode_matrix(const int32_t* row_ptr, const int32_t* col, const double* val,
+                         int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t num_exp,
+                         const int16_t* sem_in, gse_matrix* A, void* ws, size_t ws_bytes,
+                         hipStream_t st);
+gse_status fail(gse_status code, const char* fmt, ...);
+gse_status hip_fail(hipError_t e, const char* where);
+
 // autotune.hip: time the schedules, plan the fastest (tile_row rewritten)
 gse_status autotune(int fmt, int segs, SpmvOperand op, const int32_t* row_ptr, int32_t* tile_row,
                     int32_t tile_cap, int32_t max_row, const double* x, double* y, int32_t reps,

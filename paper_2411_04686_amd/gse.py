@@ -105,6 +105,9 @@ _SIGS = {
     "gse_encode_workspace": (C.c_int32, [C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]),
     "gse_encode": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int64, C.c_int32, _P,
                                C.POINTER(gse_matrix), _P, C.c_size_t, _P]),
+    "gse_encode_static": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int64, C.c_int32,
+                                      _P, C.POINTER(gse_matrix), _P]),
+    "gse_encode_static_scratch_bytes": (C.c_size_t, []),
     "gse_plan": (C.c_int32, [C.POINTER(gse_matrix), C.c_int32, C.c_int32, _P]),
     "gse_csr_plan": (C.c_int32, [C.POINTER(gse_csr), C.c_int32, C.c_int32, _P]),
     "gse_spmv": (C.c_int32, [C.POINTER(gse_matrix), C.c_int32, _P, _P, _P]),
@@ -201,6 +204,21 @@ def gse_encode(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, sem_in, A: gse_m
     return _check(lib().gse_encode(_ptr(row_ptr), _ptr(col), _ptr(val), n_rows, n_cols, nnz,
                                    num_exp, si, C.byref(A), _ptr(ws), ws.numel() * ws.element_size(),
                                    _stream(stream)), "gse_encode")
+
+
+def gse_encode_static(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, sem_in, A: gse_matrix,
+                      stream=None) -> int:
+    si = None
+    if sem_in is not None:
+        arr = (C.c_int16 * len(sem_in))(*[int(s) for s in sem_in])
+        si = C.cast(arr, C.c_void_p)
+    return _check(lib().gse_encode_static(_ptr(row_ptr), _ptr(col), _ptr(val), n_rows, n_cols, nnz,
+                                          num_exp, si, C.byref(A), _stream(stream)),
+                  "gse_encode_static")
+
+
+def gse_encode_static_scratch_bytes() -> int:
+    return lib().gse_encode_static_scratch_bytes()
 
 
 def gse_plan(A: gse_matrix, tile_nnz: int, rv_lanes: int = -1, stream=None) -> int:
