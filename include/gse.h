@@ -20,8 +20,9 @@
  *     gse_gmres synchronize it before returning.
  *   - Matrices are CSR with int32 row pointers (ascending, row_ptr[0] == 0),
  *     int32 column indices and FP64 values; the number of non-zeros must be
- *     below 2^31 - 2^16 and the number of columns at most 2^29 (the top three
- *     bits of each column word hold the shared-exponent slot).
+ *     below 2^31 - 2^16.  With k shared exponents the top b = ceil(log2 k)
+ *     bits of each column word hold the slot index, so the number of columns
+ *     is at most 2^(32 - b) (2^29 for the default k = 8, 2^26 for k = 64).
  *   - "Planes" are per-non-zero arrays.  They must hold gse_pad(nnz) entries
  *     (nnz rounded up to a multiple of 16) and start on a 16-byte boundary;
  *     entries past nnz are never interpreted (the kernels load them as part of
@@ -49,7 +50,7 @@ typedef int32_t gse_status;
 #define GSE_ERR_HIP (-6)        /* a HIP runtime call failed */
 #define GSE_ERR_TICKET (-7)     /* serving: unknown ticket */
 
-#define GSE_MAX_EXP 8           /* shared exponents per matrix (3-bit index) */
+#define GSE_MAX_EXP 64          /* shared exponents per matrix (up to a 6-bit index) */
 
 /* Number of entries a plane must hold for `nnz` non-zeros. */
 int64_t gse_pad(int64_t nnz);
@@ -66,7 +67,10 @@ int64_t gse_pad(int64_t nnz);
  *   head  = bits 63..48 (sign and 15 magnitude bits),
  *   tail1 = bits 47..32,
  *   tail2 = bits 31..0,
- * and the column word is  col | slot << 29.  Reading s planes gives the value
+ * and the column word is  col | slot << (32 - b), where b = ceil(log2 k) is
+ * the slot-index width for k shared exponents (Section III-B.1: the number
+ * of shared exponents sets the index width; b = 0 stores the bare column).
+ * Reading s planes gives the value
  * +-(F >> (63 - W_s)) * 2^(SEM - 1023 - W_s), W_s = 15, 31, 63.
  *
  * Caller-owned device buffers (set the pointers before gse_encode):
@@ -80,8 +84,9 @@ typedef struct gse_matrix {
     int32_t n_rows;
     int32_t n_cols;
     int64_t nnz;
-    int32_t num_exp;           /* k, 1..8 (Section IV-B picks 8) */
+    int32_t num_exp;           /* k, 1..64 (Section IV-B sweeps 2..64 and picks 8) */
     int32_t num_used;          /* slots actually populated */
+    int32_t idx_bits;          /* slot-index width b = ceil(log2 num_exp) (written by encode) */
     int16_t sem[GSE_MAX_EXP];  /* shared exponents, biased + 1; 0 = unused */
     const int32_t* row_ptr;    /* device [n_rows + 1] */
     uint32_t* col_idx;         /* device plane */
@@ -127,7 +132,7 @@ gse_status gse_encode_workspace(int64_t nnz, int32_t n_rows, size_t* ws_bytes);
  * forced into the last slot if the k most frequent miss it), Algorithm 1
  * (per-value slot search, denormalised mantissa) in its 64-bit form.
  *   row_ptr, col, val : device CSR (col/val: nnz entries, no padding needed).
- *   num_exp           : k in 1..8.
+ *   num_exp           : k in 1..64; the slot index takes ceil(log2 k) bits.
  *   sem_in            : host array of num_exp shared exponents (biased + 1)
  *                       to reuse a table (Section III-B.1); NULL computes it.
  *                       A reused table that leaves a value without a larger
@@ -201,6 +206,53 @@ gse_status gse_csr_autotune(gse_csr* M, const double* x, double* y, int32_t reps
 gse_status gse_csr_spmv(const gse_csr* M, const double* x, double* y, void* stream);
 
 /* ------------------------------------------------------------------------
+ * The FP16 / BF16 comparators (Section IV-C): every value stored as one
+ * IEEE binary16 (GSE_LP_FP16) or bfloat16 (GSE_LP_BF16) word -- the same
+ * width as the GSE-SEM head -- next to its plain int32 column, widened to
+ * FP64 in the SpMV and multiplied and accumulated in FP64. */
+#define GSE_LP_FP16 1
+#define GSE_LP_BF16 2
+
+typedef struct gse_lp_matrix {
+    int32_t n_rows;
+    int32_t n_cols;
+    int64_t nnz;
+    int32_t fmt;               /* GSE_LP_FP16 or GSE_LP_BF16 */
+    int32_t pad;
+    const int32_t* row_ptr;    /* device [n_rows + 1], recorded by gse_lp_convert */
+    int32_t* col;              /* device plane [gse_pad(nnz)], 16-byte aligned */
+    uint16_t* val;             /* device plane [gse_pad(nnz)], 16-byte aligned */
+    int32_t* tile_row;         /* device [tile_cap] */
+    int32_t tile_cap;
+    int32_t tile_nnz;
+    int32_t n_tiles;
+    int32_t rv_lanes;
+    int32_t max_row_nnz;
+    int32_t pad2;
+    int64_t overflow;          /* values that rounded past the largest finite one (to +-inf) */
+    double eta;                /* ||A - A_h||_inf / ||A||_inf (inf after an overflow) */
+} gse_lp_matrix;
+
+/* Device workspace gse_lp_convert needs (bytes). */
+gse_status gse_lp_workspace(size_t* ws_bytes);
+
+/* Round a device FP64 CSR matrix to FP16 or BF16: each value rounded once,
+ * to nearest with ties to even (a magnitude past the largest finite value
+ * becomes an infinity and is counted in M->overflow -- the overflow the
+ * paper reports for FP16, Section IV-D.2); columns copied.  M: in: col, val,
+ * tile_row, tile_cap; out: every other field, the schedule as by
+ * gse_lp_plan(M, 1024, -1).  ws: device, 256-byte aligned, of
+ * gse_lp_workspace() bytes.  Synchronizes `stream`. */
+gse_status gse_lp_convert(const int32_t* row_ptr, const int32_t* col, const double* val,
+                          int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t fmt,
+                          gse_lp_matrix* M, void* ws, size_t ws_bytes, void* stream);
+gse_status gse_lp_plan(gse_lp_matrix* M, int32_t tile_nnz, int32_t rv_lanes, void* stream);
+
+/* y = A_h x with the 16-bit values widened to FP64 (FP16-SpMV / BF16-SpMV of
+ * Section IV-C), on the same schedules as gse_spmv.  Asynchronous. */
+gse_status gse_lp_spmv(const gse_lp_matrix* M, const double* x, double* y, void* stream);
+
+/* ------------------------------------------------------------------------
  * Solvers for A x = b (Section I), stepped mixed precision per Section III-D
  * (Algorithm 3, Eqs. 3-6, Conditions 1-3).  Only the operator reads reduced
  * segments; dot products, residuals and the x / r / p updates are FP64
@@ -267,6 +319,17 @@ gse_status gse_cg(const gse_matrix* A, const double* b, double* x, const gse_par
  * Gram-Schmidt applied twice, Givens rotations on the device. */
 gse_status gse_gmres(const gse_matrix* A, const double* b, double* x, const gse_params* p,
                      gse_report* rep, void* ws, size_t ws_bytes, void* stream);
+
+/* The FP16 / BF16 comparator solvers of Section IV-D.3: the same CG and
+ * GMRES with the fixed 16-bit operator A_h (p->fixed_segments and the
+ * controller are ignored).  Convergence is judged on A_h's own residual
+ * (relres_true is ||b - A_h x|| / ||b||); the distance to the FP64 matrix's
+ * solution is the caller's to measure.  A non-finite value (an overflowed
+ * FP16 entry) ends the solve with GSE_ERR_BREAKDOWN or GSE_NOT_CONVERGED. */
+gse_status gse_lp_cg(const gse_lp_matrix* M, const double* b, double* x, const gse_params* p,
+                     gse_report* rep, void* ws, size_t ws_bytes, void* stream);
+gse_status gse_lp_gmres(const gse_lp_matrix* M, const double* b, double* x, const gse_params* p,
+                        gse_report* rep, void* ws, size_t ws_bytes, void* stream);
 
 /* Baselines: the same solvers with plain FP64 CSR values. */
 gse_status gse_csr_cg(const gse_csr* M, const double* b, double* x, const gse_params* p,
@@ -336,7 +399,7 @@ typedef struct gse_request {
     const double* b;         /* host [n_rows] */
     double* x;               /* host [n_rows]: x0 when x0_given, the solution on completion */
     int32_t format;          /* GSE_FMT_GSE or GSE_FMT_CSR64 */
-    int32_t num_exp;         /* shared exponents for GSE_FMT_GSE (1..8) */
+    int32_t num_exp;         /* shared exponents for GSE_FMT_GSE (1..64) */
     int32_t x0_given;        /* 1: start from x, 0: from zero */
     gse_params params;       /* CG parameters (gse_default_params(GSE_CG, ...)) */
 } gse_request;

@@ -82,6 +82,7 @@ SpmvOperand operand_of(const gse_matrix* A) {
   o.nnz = (int32_t)A->nnz;
   o.rv_lanes = A->rv_lanes;
   o.max_row = A->max_row_nnz;
+  o.split = col_split(A->idx_bits);
   for (int i = 0; i < GSE_MAX_EXP; ++i) o.sem[i] = A->sem[i];
   return o;
 }
@@ -101,6 +102,7 @@ SpmvOperand operand_of(const gse_csr* M) {
   o.nnz = (int32_t)M->nnz;
   o.rv_lanes = M->rv_lanes;
   o.max_row = M->max_row_nnz;
+  o.split = col_split(0);
   for (int i = 0; i < GSE_MAX_EXP; ++i) o.sem[i] = 0;
   return o;
 }
@@ -111,6 +113,8 @@ gse_status check_matrix(const gse_matrix* A) {
     return fail(GSE_ERR_ARG, "matrix has a NULL device buffer");
   if (A->n_rows < 0 || A->n_cols < 0 || A->nnz < 0) return fail(GSE_ERR_ARG, "negative size");
   if (A->nnz > kMaxNnz) return fail(GSE_ERR_RANGE, "nnz %lld exceeds the limit", (long long)A->nnz);
+  if (A->num_exp < 1 || A->num_exp > GSE_MAX_EXP || A->idx_bits != index_bits(A->num_exp))
+    return fail(GSE_ERR_ARG, "matrix has no valid shared-exponent table (call gse_encode)");
   if (!valid_tile(A->tile_nnz) || A->n_tiles != n_tiles_for(A->nnz, A->tile_nnz) ||
       A->tile_cap < A->n_tiles + 2 || !valid_rv(A->rv_lanes))
     return fail(GSE_ERR_ARG, "matrix has no valid SpMV schedule (call gse_encode / gse_plan)");
@@ -140,9 +144,12 @@ gse_status encode_matrix(const int32_t* row_ptr, const int32_t* col, const doubl
   if (!A) return fail(GSE_ERR_ARG, "matrix is NULL");
   if (!row_ptr || (nnz > 0 && (!col || !val))) return fail(GSE_ERR_ARG, "NULL CSR array");
   if (n_rows < 0 || n_cols < 0 || nnz < 0) return fail(GSE_ERR_ARG, "negative size");
-  if (num_exp < 1 || num_exp > GSE_MAX_EXP) return fail(GSE_ERR_ARG, "num_exp must be 1..8");
+  if (num_exp < 1 || num_exp > GSE_MAX_EXP) return fail(GSE_ERR_ARG, "num_exp must be 1..64");
   if (nnz > kMaxNnz) return fail(GSE_ERR_RANGE, "nnz %lld exceeds the limit", (long long)nnz);
-  if ((int64_t)n_cols > (int64_t(1) << 29)) return fail(GSE_ERR_RANGE, "n_cols exceeds 2^29");
+  const int ib = index_bits(num_exp);
+  if ((int64_t)n_cols > (int64_t(1) << (32 - ib)))
+    return fail(GSE_ERR_RANGE, "n_cols exceeds 2^%d (the column field left by a %d-bit slot index)",
+                32 - ib, ib);
   if (!A->col_idx || !A->head || !A->tail1 || !A->tail2 || !A->tile_row)
     return fail(GSE_ERR_ARG, "matrix planes / tile_row not set");
   if (!aligned16(A->col_idx) || !aligned16(A->head) || !aligned16(A->tail1) || !aligned16(A->tail2))
@@ -166,6 +173,7 @@ gse_status encode_matrix(const int32_t* row_ptr, const int32_t* col, const doubl
   A->n_cols = n_cols;
   A->nnz = nnz;
   A->num_exp = num_exp;
+  A->idx_bits = ib;
   A->row_ptr = row_ptr;
   hipError_t e = launch_encode(row_ptr, col, val, n_rows, (int32_t)nnz, num_exp, sem_in, A, sc, st);
   if (e != hipSuccess) return hip_fail(e, "gse_encode launch");
@@ -192,6 +200,7 @@ gse_status encode_matrix(const int32_t* row_ptr, const int32_t* col, const doubl
   if (h.range_err & 2) return fail(GSE_ERR_RANGE, "a value has no larger shared exponent in the table");
   return GSE_OK;
 }
+
 
 }  // namespace gse
 
@@ -407,6 +416,22 @@ gse_status gse_csr_gmres(const gse_csr* M, const double* b, double* x, const gse
   return gmres_csr(operand_of(M), b, x, p, rep, ws, ws_bytes, (hipStream_t)stream);
 }
 
+gse_status gse_lp_cg(const gse_lp_matrix* M, const double* b, double* x, const gse_params* p,
+                     gse_report* rep, void* ws, size_t ws_bytes, void* stream) {
+  gse_status s = check_lp(M);
+  if (s == GSE_OK) s = check_solve(M->n_rows, M->n_cols, b, x, p, rep, ws, GSE_CG);
+  if (s != GSE_OK) return s;
+  return cg_lp(M, b, x, p, rep, ws, ws_bytes, (hipStream_t)stream);
+}
+
+gse_status gse_lp_gmres(const gse_lp_matrix* M, const double* b, double* x, const gse_params* p,
+                        gse_report* rep, void* ws, size_t ws_bytes, void* stream) {
+  gse_status s = check_lp(M);
+  if (s == GSE_OK) s = check_solve(M->n_rows, M->n_cols, b, x, p, rep, ws, GSE_GMRES);
+  if (s != GSE_OK) return s;
+  return gmres_lp(M, b, x, p, rep, ws, ws_bytes, (hipStream_t)stream);
+}
+
 gse_status gse_solve_history(const void* ws, int32_t cap, double* hist, int32_t* seg, void* stream) {
   if (!ws || cap < 0 || (cap > 0 && (!hist || !seg))) return fail(GSE_ERR_ARG, "bad arguments");
   if (cap == 0) return GSE_OK;
@@ -444,6 +469,7 @@ static gse_status batch_descs(int32_t n_sys, const gse_system* sys, const gse_pa
       B.n_tiles = A->n_tiles;
       B.fmt = 1;
       B.max_row = A->max_row_nnz;
+      B.split = col_split(A->idx_bits);
       for (int k = 0; k < GSE_MAX_EXP; ++k) B.sem[k] = A->sem[k];
       d.eta = A->eta;
     } else {
@@ -460,6 +486,7 @@ static gse_status batch_descs(int32_t n_sys, const gse_system* sys, const gse_pa
       B.n_tiles = M->n_tiles;
       B.fmt = 0;
       B.max_row = M->max_row_nnz;
+      B.split = col_split(0);
       d.eta = nullptr;
     }
     if (!y.b || !y.x || !aligned16(y.x)) return fail(GSE_ERR_ARG, "system %d: bad b / x", i);

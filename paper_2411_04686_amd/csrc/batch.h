@@ -34,6 +34,7 @@ struct BatchSlot {
   int32_t n_chunks;
   int32_t fmt;  // 1: GSE-SEM (stepped), 0: FP64 CSR
   int32_t max_row;  // non-zeros of the longest row
+  ColSplit split;   // column / slot fields of the column words
   int16_t sem[GSE_MAX_EXP];
 };
 

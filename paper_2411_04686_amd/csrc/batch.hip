@@ -67,7 +67,7 @@ __device__ __forceinline__ Walk walk_of(int n) {
 }
 
 template <int FMT>
-__device__ __forceinline__ double load_decode(const BatchSlot& B, int j, const double* scale,
+__device__ __forceinline__ double load_decode(const BatchSlot& B, int j, const DecodeCtx& scale,
                                               int& col) {
   const uint32_t c = B.col[j];
   uint32_t h = 0, t1 = 0, t2 = 0;
@@ -122,14 +122,15 @@ __device__ __forceinline__ void sum_staged(const BatchSlot& B, int ra, int rb, i
 template <int FMT>
 __device__ double tile_rows(const BatchSlot& B, int t, const double* __restrict__ xin,
                             double* __restrict__ yout, const double* __restrict__ aux, int epi,
-                            double* vals, int* cols, double* scale, double* red) {
+                            double* vals, int* cols, uint32_t* scale_tab, double* red) {
   const int tid = threadIdx.x;
   const int ra = B.tile_row[t], rb = B.tile_row[t + 1];
   const int j0 = B.row_ptr[ra], j1 = B.row_ptr[rb];
   const int ext = j1 - j0;
   __syncthreads();  // the previous tile is done with LDS
-  build_scale<FMT>(B.sem, scale);
+  build_scale<FMT>(B.sem, scale_tab);
   __syncthreads();
+  const DecodeCtx scale{scale_tab, B.split};
   double acc = 0.0;
   auto emit = [&](int r, double sum) {
     if (epi == kEpiDot) {
@@ -190,7 +191,7 @@ __device__ double tile_rows(const BatchSlot& B, int t, const double* __restrict_
 __global__ __launch_bounds__(kWG) void k_b_spmv(BatchView v, int mode) {
   __shared__ __attribute__((aligned(16))) double vals[kNS + 8];
   __shared__ __attribute__((aligned(16))) int cols[kNS + 8];
-  __shared__ double scale[16];
+  __shared__ uint32_t scale[kScaleEntries];
   __shared__ double red[kWaves];
   const int n = v.list.counts[0];
   for (Walk w = walk_of(n); w.i < w.end; w.i += w.step) {

@@ -6,20 +6,25 @@
 
 namespace gse {
 
-// Signed scale table for s segments: entry (slot | sign << 3) holds
-// +-2^(SEM[slot] - 1023 - W_s).  Built as IEEE bits: biased exponent
-// SEM - W_s, zero fraction (SEM >= 64 keeps it normal).
+// What the decode needs: the scale table (in LDS) and the split of the
+// column words.
+struct DecodeCtx {
+  const uint32_t* tab;
+  ColSplit split;
+};
+
+// Scale table for s segments: entry `slot` holds the high word of
+// 2^(SEM[slot] - 1023 - W_s) as IEEE bits -- biased exponent SEM - W_s, zero
+// fraction (SEM >= 64 keeps it normal); the low word is zero, and the value's
+// sign goes into bit 31 of the high word.  Every thread of the workgroup
+// takes part.
 template <int FMT>
-__device__ __forceinline__ void build_scale(const int16_t* sem, double* scale) {
-  if constexpr (FMT != kCsr64) {
+__device__ __forceinline__ void build_scale(const int16_t* sem, uint32_t* tab) {
+  if constexpr (is_gse(FMT)) {
     constexpr int W = (FMT == 1) ? 15 : (FMT == 2) ? 31 : 63;
-    const int i = threadIdx.x;
-    if (i < 16) {
-      const int S = sem[i & 7];
-      uint64_t u = 0;
-      if (S > W) u = (uint64_t)(S - W) << 52;
-      u |= (uint64_t)(i >> 3) << 63;
-      scale[i] = bits_to_double(u);
+    for (int i = threadIdx.x; i < kScaleEntries; i += blockDim.x) {
+      const int S = sem[i];
+      tab[i] = S > W ? (uint32_t)(S - W) << 20 : 0u;
     }
   }
 }
@@ -27,24 +32,33 @@ __device__ __forceinline__ void build_scale(const int16_t* sem, double* scale) {
 // Decode one non-zero: returns the FP64 value and its column.
 template <int FMT>
 __device__ __forceinline__ double decode(uint32_t c, uint32_t h, uint32_t t1, uint32_t t2, double v,
-                                         const double* scale, int& column) {
+                                         const DecodeCtx& dc, int& column) {
   if constexpr (FMT == kCsr64) {
     column = (int)c;
     return v;
+  } else if constexpr (FMT == kFp16) {
+    // binary16 -> binary32 -> binary64: both widenings are exact
+    column = (int)c;
+    return (double)(float)__builtin_bit_cast(_Float16, (unsigned short)h);
+  } else if constexpr (FMT == kBf16) {
+    // bfloat16 is the top half of a binary32
+    column = (int)c;
+    return (double)__uint_as_float(h << 16);
   } else {
-    column = (int)(c & 0x1FFFFFFFu);
-    const int ti = (int)(c >> 29) | (int)((h >> 12) & 8u);
-    const double sc = scale[ti];
+    column = (int)(c & dc.split.col_mask);
+    const uint32_t slot = (c >> dc.split.shift) & dc.split.slot_mask;
+    const uint32_t hi = dc.tab[slot] | ((h & 0x8000u) << 16);
+    const double sc = __hiloint2double((int)hi, 0);
     if constexpr (FMT == 1) {
       return (double)(h & 0x7FFFu) * sc;
     } else if constexpr (FMT == 2) {
       return (double)(((h & 0x7FFFu) << 16) | t1) * sc;
     } else {
-      // F = hi * 2^32 + lo with hi = 31 bits, lo = 32 bits; F has at most 53
-      // significant bits, so the fused sum below is exact.
-      const double sc_hi = bits_to_double(double_to_bits(sc) + (uint64_t(32) << 52));
-      const double hi = (double)(((h & 0x7FFFu) << 16) | t1);
-      return __builtin_fma(hi, sc_hi, (double)t2 * sc);
+      // F = hi31 * 2^32 + lo32; F has at most 53 significant bits, so the
+      // fused sum below is exact (2^32 * sc: 32 added to the exponent field).
+      const double sc_hi = __hiloint2double((int)(hi + (32u << 20)), 0);
+      const double fhi = (double)(((h & 0x7FFFu) << 16) | t1);
+      return __builtin_fma(fhi, sc_hi, (double)t2 * sc);
     }
   }
 }

@@ -7,9 +7,11 @@
 //            larger exponent first on ties), the maximum exponent forced into
 //            the last slot when missing (Section III-B.2), stored +1.
 //   k_encode per value: slot of the smallest shared exponent above the value's
-//            own (an exact match when SEM = e + 1), magnitude on that slot's
-//            63-bit fixed-point grid (Algorithm 1, denormalised by minDiff,
-//            truncated), written to the four planes with 16-byte stores.
+//            own (an exact match when SEM = e + 1; looked up per exponent
+//            field in a table k_topk fills), magnitude on that slot's 63-bit
+//            fixed-point grid (Algorithm 1, denormalised by minDiff,
+//            truncated), the slot in the top ceil(log2 k) bits of the column
+//            word, written to the four planes with 16-byte stores.
 //   k_eta    per row: sums of |a| and |a - a_s| for s = 1, 2, 3; the row
 //            maxima give eta_s = ||A - A_s||_inf / ||A||_inf.
 #include "gse_internal.h"
@@ -52,11 +54,31 @@ __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v
   return m;
 }
 
+// Slot of the smallest shared exponent above each exponent field (the
+// slot search of Algorithm 1, done once per field instead of per value):
+// -1 when no shared exponent is above it, and for the Inf/NaN field.
+__device__ __forceinline__ void fill_slot_lookup(const int16_t* tab, EncodeScratch* sc) {
+  for (int e = threadIdx.x; e < 2048; e += blockDim.x) {
+    int slot = -1, best = 1 << 30;
+    if (e < 2047) {
+      for (int q = 0; q < GSE_MAX_EXP; ++q) {
+        const int S = tab[q];
+        if (S > e && S < best) {
+          best = S;
+          slot = q;
+        }
+      }
+    }
+    sc->slot_of[e] = (int8_t)slot;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_topk(EncodeScratch* sc, int num_exp, SemIn in) {
   __shared__ uint32_t h[2048];
   __shared__ unsigned char taken[2048];
   __shared__ unsigned long long red[kWaves];
   __shared__ int chosen[GSE_MAX_EXP];
+  __shared__ int16_t tab[GSE_MAX_EXP];
   for (int i = threadIdx.x; i < 2048; i += blockDim.x) {
     h[i] = sc->hist[i];
     taken[i] = 0;
@@ -68,6 +90,7 @@ __global__ __launch_bounds__(256) void k_topk(EncodeScratch* sc, int num_exp, Se
       unsigned long long cov = 0;
       for (int i = 0; i < GSE_MAX_EXP; ++i) {
         sc->sem[i] = in.sem[i];
+        tab[i] = in.sem[i];
         if (in.sem[i] > 0) {
           ++used;
           cov += h[in.sem[i] - 1];
@@ -77,6 +100,8 @@ __global__ __launch_bounds__(256) void k_topk(EncodeScratch* sc, int num_exp, Se
       sc->covered = cov;
       sc->nonfinite = (int)h[2047];
     }
+    __syncthreads();
+    fill_slot_lookup(tab, sc);
     return;
   }
   int used = 0;
@@ -111,10 +136,14 @@ __global__ __launch_bounds__(256) void k_topk(EncodeScratch* sc, int num_exp, Se
     }
     int range_err = 0;
     unsigned long long cov = 0;
-    for (int i = 0; i < GSE_MAX_EXP; ++i) sc->sem[i] = 0;
+    for (int i = 0; i < GSE_MAX_EXP; ++i) {
+      sc->sem[i] = 0;
+      tab[i] = 0;
+    }
     for (int i = 0; i < used; ++i) {
       if (chosen[i] < 63) range_err = 1;
       sc->sem[i] = (int16_t)(chosen[i] + 1);
+      tab[i] = (int16_t)(chosen[i] + 1);
       cov += h[chosen[i]];
     }
     sc->used = used;
@@ -122,22 +151,25 @@ __global__ __launch_bounds__(256) void k_topk(EncodeScratch* sc, int num_exp, Se
     sc->range_err = range_err;
     sc->nonfinite = (int)h[2047];
   }
+  __syncthreads();
+  fill_slot_lookup(tab, sc);
 }
 
 // Groups of 8 values per thread; writes 32 + 16 + 16 + 32 bytes per group
 // (the planes are padded, so the tail group writes zeros past nnz).
 __global__ __launch_bounds__(256) void k_encode(const double* __restrict__ val,
                                                 const int32_t* __restrict__ col, int nnz,
-                                                EncodeScratch* sc, uint32_t* __restrict__ col_idx,
+                                                EncodeScratch* sc, int idx_bits,
+                                                uint32_t* __restrict__ col_idx,
                                                 uint16_t* __restrict__ head,
                                                 uint16_t* __restrict__ tail1,
                                                 uint32_t* __restrict__ tail2) {
   __shared__ int sem_s[GSE_MAX_EXP];
+  __shared__ int8_t slot_s[2048];
   if (threadIdx.x < GSE_MAX_EXP) sem_s[threadIdx.x] = sc->sem[threadIdx.x];
+  for (int e = threadIdx.x; e < 2048; e += blockDim.x) slot_s[e] = sc->slot_of[e];
   __syncthreads();
-  int S[GSE_MAX_EXP];
-#pragma unroll
-  for (int k = 0; k < GSE_MAX_EXP; ++k) S[k] = sem_s[k];
+  const uint32_t shift = idx_bits > 0 ? 32u - (uint32_t)idx_bits : 0u;
   const int n_groups = (nnz + 7) >> 3;
   const int stride = gridDim.x * blockDim.x;
   int bad = 0;
@@ -172,24 +204,19 @@ __global__ __launch_bounds__(256) void k_encode(const double* __restrict__ val,
       if (j < nnz) {
         const uint64_t u = uv[k];
         const int e = (int)((u >> 52) & 0x7FFu);
-        int slot = -1, best = 1 << 30;
-#pragma unroll
-        for (int q = 0; q < GSE_MAX_EXP; ++q)
-          if (S[q] > e && S[q] < best) {
-            best = S[q];
-            slot = q;
-          }
+        int slot = slot_s[e];
         uint64_t F = 0;
         if (slot < 0) {
           bad = 1;
           slot = 0;
         } else {
+          const int best = sem_s[slot];
           const uint64_t frac = u & ((uint64_t(1) << 52) - 1);
           const uint64_t sig = e ? ((uint64_t(1) << 52) | frac) : frac;
           const int sh = 11 - (best - (e ? e : 1));
           F = (sh >= 0) ? (sig << sh) : ((-sh >= 64) ? 0 : (sig >> (-sh)));
         }
-        c = (uint32_t)cv[k] | ((uint32_t)slot << 29);
+        c = (uint32_t)cv[k] | (idx_bits > 0 ? ((uint32_t)slot << shift) : 0u);
         h16 = (uint32_t)((u >> 63) << 15) | (uint32_t)(F >> 48);
         t116 = (uint32_t)((F >> 32) & 0xFFFFu);
         t232 = (uint32_t)(F & 0xFFFFFFFFu);
@@ -213,9 +240,9 @@ __global__ __launch_bounds__(256) void k_encode(const double* __restrict__ val,
 
 // Value read with s segments (exact; same decode as the SpMV operators).
 __device__ __forceinline__ double value_s(uint32_t c, uint32_t h, uint32_t t1, uint32_t t2,
-                                          const int* S, int s) {
+                                          const int* S, const ColSplit& cs, int s) {
   const int W = (s == 1) ? 15 : (s == 2) ? 31 : 63;
-  const int sem = S[c >> 29];
+  const int sem = S[(c >> cs.shift) & cs.slot_mask];
   const uint64_t F63 = ((uint64_t)(h & 0x7FFFu) << 48) | ((uint64_t)t1 << 32) | (uint64_t)t2;
   const uint64_t F = F63 >> (63 - W);
   const double sc = bits_to_double((uint64_t)(sem - W) << 52);
@@ -232,14 +259,12 @@ __global__ __launch_bounds__(256) void k_eta(const int32_t* __restrict__ row_ptr
                                              const uint16_t* __restrict__ head,
                                              const uint16_t* __restrict__ tail1,
                                              const uint32_t* __restrict__ tail2,
-                                             EncodeScratch* sc) {
+                                             EncodeScratch* sc, ColSplit cs) {
   __shared__ int sem_s[GSE_MAX_EXP];
   __shared__ double red[4][kWaves];
   if (threadIdx.x < GSE_MAX_EXP) sem_s[threadIdx.x] = sc->sem[threadIdx.x];
   __syncthreads();
-  int S[GSE_MAX_EXP];
-#pragma unroll
-  for (int k = 0; k < GSE_MAX_EXP; ++k) S[k] = sem_s[k];
+  const int* S = sem_s;
   const int sub = threadIdx.x & 7;
   const int grp = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
   const int ngrp = (gridDim.x * blockDim.x) >> 3;
@@ -260,9 +285,9 @@ __global__ __launch_bounds__(256) void k_eta(const int32_t* __restrict__ row_ptr
   // non-negative, so a + 0.0 == a) -- no branch for the loads to sink into
   auto add_terms = [&](double (&a)[4], const Ent& x, bool use) {
     const double t0 = fabs(x.v);
-    const double t1 = fabs(x.v - value_s(x.c, x.h, x.t1, x.t2, S, 1));
-    const double t2 = fabs(x.v - value_s(x.c, x.h, x.t1, x.t2, S, 2));
-    const double t3 = fabs(x.v - value_s(x.c, x.h, x.t1, x.t2, S, 3));
+    const double t1 = fabs(x.v - value_s(x.c, x.h, x.t1, x.t2, S, cs, 1));
+    const double t2 = fabs(x.v - value_s(x.c, x.h, x.t1, x.t2, S, cs, 2));
+    const double t3 = fabs(x.v - value_s(x.c, x.h, x.t1, x.t2, S, cs, 3));
     a[0] += use ? t0 : 0.0;
     a[1] += use ? t1 : 0.0;
     a[2] += use ? t2 : 0.0;
@@ -343,12 +368,12 @@ hipError_t launch_encode(const int32_t* row_ptr, const int32_t* col, const doubl
   const int groups = (nnz + 7) / 8;
   int eb = (groups + 255) / 256;
   eb = eb < 1 ? 1 : (eb > 16384 ? 16384 : eb);
-  hipLaunchKernelGGL(k_encode, dim3(eb), dim3(256), 0, st, val, col, nnz, sc, A->col_idx, A->head,
-                     A->tail1, A->tail2);
+  hipLaunchKernelGGL(k_encode, dim3(eb), dim3(256), 0, st, val, col, nnz, sc, A->idx_bits,
+                     A->col_idx, A->head, A->tail1, A->tail2);
   int rbk = (n_rows + 31) / 32;
   rbk = rbk < 1 ? 1 : (rbk > 4096 ? 4096 : rbk);
   hipLaunchKernelGGL(k_eta, dim3(rbk), dim3(256), 0, st, row_ptr, n_rows, val, A->col_idx, A->head,
-                     A->tail1, A->tail2, sc);
+                     A->tail1, A->tail2, sc, col_split(A->idx_bits));
   return hipGetLastError();
 }
 

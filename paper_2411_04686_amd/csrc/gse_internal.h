@@ -22,8 +22,18 @@ constexpr int kRvBatch = 8;         // row-vector schedule: rows per lane group 
 constexpr int64_t kMaxNnz = (int64_t(1) << 31) - (int64_t(1) << 16);
 
 // Format identifiers for the SpMV templates: 1..3 = GSE-SEM with s segments,
-// 0 = plain FP64 CSR values.
+// 0 = plain FP64 CSR values, 4 / 5 = the FP16 / BF16 comparators (one 16-bit
+// value per non-zero in the head plane, bare column words).
 constexpr int kCsr64 = 0;
+constexpr int kFp16 = 4;
+constexpr int kBf16 = 5;
+
+// Planes a format reads besides the column words: 0 the FP64 values, 1 the
+// 16-bit plane (GSE head, FP16, BF16), 2 head + tail1, 3 all three.
+__host__ __device__ constexpr int planes_of(int fmt) {
+  return fmt == kCsr64 ? 0 : (fmt >= kFp16 ? 1 : fmt);
+}
+__host__ __device__ constexpr bool is_gse(int fmt) { return fmt >= 1 && fmt <= 3; }
 
 // Epilogue of an SpMV launch.
 enum Epi : int {
@@ -89,12 +99,41 @@ __device__ __forceinline__ double sum_partials(const double* partials, int n, do
 __device__ __forceinline__ double bits_to_double(uint64_t u) { return __longlong_as_double((long long)u); }
 __device__ __forceinline__ uint64_t double_to_bits(double d) { return (uint64_t)__double_as_longlong(d); }
 
+// ------------------------------------------------------- column words --
+// With k shared exponents the slot index takes the top b = ceil(log2 k) bits
+// of the 32-bit column word (b = 0: the word is the bare column).
+__host__ __device__ inline int index_bits(int num_exp) {
+  int b = 0;
+  while ((1 << b) < num_exp) ++b;
+  return b;
+}
+
+// How a column word splits: column = word & col_mask, slot = (word >> shift)
+// & slot_mask (shift 0 and slot_mask 0 for b = 0; col_mask all ones for the
+// FP64 CSR operand, whose words are bare columns).
+struct ColSplit {
+  uint32_t shift;
+  uint32_t slot_mask;
+  uint32_t col_mask;
+};
+
+__host__ __device__ inline ColSplit col_split(int idx_bits) {
+  ColSplit c;
+  c.shift = idx_bits > 0 ? 32u - (uint32_t)idx_bits : 0u;
+  c.slot_mask = (1u << idx_bits) - 1u;
+  c.col_mask = 0xFFFFFFFFu >> idx_bits;
+  return c;
+}
+
+// Scale table entries: one per slot.
+constexpr int kScaleEntries = GSE_MAX_EXP;
+
 // ------------------------------------------------------------- launchers --
 struct SpmvOperand {
   // GSE planes (fmt 1..3) or CSR values (fmt 0)
   const int32_t* row_ptr;
   const int32_t* tile_row;
-  const uint32_t* col;       // col | slot << 29 (GSE) or plain column (CSR)
+  const uint32_t* col;       // col | slot << (32 - b) (GSE) or plain column (CSR)
   const uint16_t* head;
   const uint16_t* tail1;
   const uint32_t* tail2;
@@ -105,6 +144,7 @@ struct SpmvOperand {
   int32_t nnz;
   int32_t rv_lanes;          // > 0: row-vector schedule with this many lanes per row
   int32_t max_row;           // longest row (<= kShortRow selects the short-row tiles)
+  ColSplit split;            // column / slot fields of the column words
   int16_t sem[GSE_MAX_EXP];
 };
 
@@ -126,6 +166,7 @@ hipError_t launch_rowmax(const int32_t* row_ptr, int32_t n_rows, int* out, hipSt
 // Device record of gse_encode (lives at the start of the encode workspace).
 struct EncodeScratch {
   uint32_t hist[2048];
+  int8_t slot_of[2048];  // slot of the smallest shared exponent above each field; -1: none
   int32_t nonfinite;
   int32_t range_err;
   int32_t used;
@@ -155,6 +196,11 @@ gse_status autotune(int fmt, int segs, SpmvOperand op, const int32_t* row_ptr, i
                     int32_t tile_cap, int32_t max_row, const double* x, double* y, int32_t reps,
                     hipStream_t st, int32_t* out_tile, int32_t* out_rv, int32_t* out_tiles);
 
+// lowprec.hip: the FP16 / BF16 operand
+SpmvOperand operand_of(const gse_lp_matrix* M);
+int lp_launch_format(const gse_lp_matrix* M);
+gse_status check_lp(const gse_lp_matrix* M);
+
 // solvers.hip
 size_t solver_workspace_bytes(int32_t method, int32_t n_rows, int64_t nnz, int32_t restart,
                               int32_t max_iter);
@@ -162,6 +208,10 @@ gse_status cg_gse(const gse_matrix* A, const SpmvOperand& op, const double* b, d
                   const gse_params* p, gse_report* rep, void* ws, size_t ws_bytes, hipStream_t st);
 gse_status cg_csr(const SpmvOperand& op, const double* b, double* x, const gse_params* p,
                   gse_report* rep, void* ws, size_t ws_bytes, hipStream_t st);
+gse_status cg_lp(const gse_lp_matrix* M, const double* b, double* x, const gse_params* p,
+                 gse_report* rep, void* ws, size_t ws_bytes, hipStream_t st);
+gse_status gmres_lp(const gse_lp_matrix* M, const double* b, double* x, const gse_params* p,
+                    gse_report* rep, void* ws, size_t ws_bytes, hipStream_t st);
 gse_status gmres_gse(const gse_matrix* A, const SpmvOperand& op, const double* b, double* x,
                      const gse_params* p, gse_report* rep, void* ws, size_t ws_bytes,
                      hipStream_t st);

@@ -212,8 +212,8 @@ __device__ __forceinline__ double small_elem(const SpmvOperand& A, int j, const 
     column = (int)c;
     return A.val[j];
   } else {
-    column = (int)(c & 0x1FFFFFFFu);
-    const int e = ex(c >> 29);
+    column = (int)(c & A.split.col_mask);
+    const int e = ex((c >> A.split.shift) & A.split.slot_mask);
     const uint32_t h = A.head[j];
     double v;
     if constexpr (FMT == 1) {
@@ -400,7 +400,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_cg_small(SolverState* Sg, Spm
 }
 
 bool cg_small_path(const SpmvOperand& op) {
-  return op.n_rows <= kSmallRows && op.max_row <= kSmallRow;
+  // (the eight slot exponents held in scalar words cover index widths <= 3)
+  return op.n_rows <= kSmallRows && op.max_row <= kSmallRow && op.split.slot_mask <= 7u;
 }
 
 template <int RPT, int L>
@@ -543,9 +544,10 @@ struct GraphCache {
 };
 
 struct Operator {
-  int fmt;  // 1..3 GSE (stepped), 0 FP64 CSR
+  int fmt;  // 1..3 GSE (stepped), 0 a fixed operator (FP64 CSR, FP16 or BF16)
   SpmvOperand op;
   const double* eta;
+  int launch_fmt = kCsr64;  // SpMV format of a fixed operator: kCsr64, kFp16 or kBf16
 };
 
 // y = A_s x; with kEpiDot the dot aux.y, with kEpiResid y = b - A_s x and
@@ -561,7 +563,7 @@ hipError_t apply(const Operator& A, int s, const double* x, double* y, int epi, 
   ep.partials = w.partials;
   ep.gate = gate;
   ep.grid_out = &g;
-  hipError_t e = launch_spmv(A.fmt == 0 ? 0 : s, A.op, x, y, ep, st);
+  hipError_t e = launch_spmv(A.fmt == 0 ? A.launch_fmt : s, A.op, x, y, ep, st);
   if (e != hipSuccess) return e;
   if (grid) *grid = g;
   if (result && epi != kEpiPlain) {
@@ -689,7 +691,7 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
   int chunk = 4;
   bool done = false;
   bool pending_check = h.relres <= p->tol;  // converged at x0 already
-  const bool small = cg_small_path(A.op);
+  const bool small = cg_small_path(A.op) && A.launch_fmt == kCsr64;
   while (!done) {
     if (pending_check) {
       // the recursive residual meets the tolerance outside an iteration (at
@@ -1312,6 +1314,18 @@ gse_status gmres_gse(const gse_matrix* A, const SpmvOperand& op, const double* b
 gse_status gmres_csr(const SpmvOperand& op, const double* b, double* x, const gse_params* p,
                      gse_report* rep, void* ws, size_t ws_bytes, hipStream_t st) {
   Operator o{0, op, nullptr};
+  return run_gmres(o, b, x, p, rep, ws, ws_bytes, st);
+}
+
+gse_status cg_lp(const gse_lp_matrix* M, const double* b, double* x, const gse_params* p,
+                 gse_report* rep, void* ws, size_t ws_bytes, hipStream_t st) {
+  Operator o{0, operand_of(M), nullptr, lp_launch_format(M)};
+  return run_cg(o, b, x, p, rep, ws, ws_bytes, st);
+}
+
+gse_status gmres_lp(const gse_lp_matrix* M, const double* b, double* x, const gse_params* p,
+                    gse_report* rep, void* ws, size_t ws_bytes, hipStream_t st) {
+  Operator o{0, operand_of(M), nullptr, lp_launch_format(M)};
   return run_gmres(o, b, x, p, rep, ws, ws_bytes, st);
 }
 

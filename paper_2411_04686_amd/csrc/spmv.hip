@@ -106,8 +106,8 @@ struct Group {
     cw = load_words<E>(A.col + base);
     if constexpr (FMT != kCsr64) {
       hw = load_words<HW>(A.head + base);
-      if constexpr (FMT >= 2) t1w = load_words<HW>(A.tail1 + base);
-      if constexpr (FMT >= 3) t2w = load_words<E>(A.tail2 + base);
+      if constexpr (planes_of(FMT) >= 2) t1w = load_words<HW>(A.tail1 + base);
+      if constexpr (planes_of(FMT) >= 3) t2w = load_words<E>(A.tail2 + base);
     } else {
       const f64x2* q = reinterpret_cast<const f64x2*>(A.val + base);
 #pragma unroll
@@ -122,15 +122,15 @@ struct Group {
   // Decoded values and columns of all E non-zeros into LDS slots off..off+E-1
   // (16-byte stores; no range test: slots outside the staged range are
   // never read).
-  __device__ __forceinline__ void stage_all(const double* scale, int off, double* vals,
+  __device__ __forceinline__ void stage_all(const DecodeCtx& scale, int off, double* vals,
                                             int* cols) const {
     double d[E];
     int column[E];
 #pragma unroll
     for (int k = 0; k < E; ++k) {
       const uint32_t h = (FMT != kCsr64) ? u16_of(hw, k) : 0u;
-      const uint32_t t1 = (FMT >= 2) ? u16_of(t1w, k) : 0u;
-      const uint32_t t2 = (FMT >= 3) ? t2w.w[k] : 0u;
+      const uint32_t t1 = (planes_of(FMT) >= 2) ? u16_of(t1w, k) : 0u;
+      const uint32_t t2 = (planes_of(FMT) >= 3) ? t2w.w[k] : 0u;
       d[k] = decode<FMT>(cw.w[k], h, t1, t2, (FMT == kCsr64) ? vv[k] : 0.0, scale, column[k]);
     }
     double2* v2 = reinterpret_cast<double2*>(vals + off);
@@ -145,7 +145,7 @@ struct Group {
   // Decoded values and columns of the non-zeros in [lo, hi) into the LDS
   // slots of the tile starting at j0 (one padding slot per 8 spreads the
   // lanes of a wave over the banks).
-  __device__ __forceinline__ void stage(const double* scale, int base, int lo, int hi, int j0,
+  __device__ __forceinline__ void stage(const DecodeCtx& scale, int base, int lo, int hi, int j0,
                                         double* vals, int* cols) const {
 #pragma unroll
     for (int k = 0; k < E; ++k) {
@@ -153,8 +153,8 @@ struct Group {
       if (j >= lo && j < hi) {
         int column;
         const uint32_t h = (FMT != kCsr64) ? u16_of(hw, k) : 0u;
-        const uint32_t t1 = (FMT >= 2) ? u16_of(t1w, k) : 0u;
-        const uint32_t t2 = (FMT >= 3) ? t2w.w[k] : 0u;
+        const uint32_t t1 = (planes_of(FMT) >= 2) ? u16_of(t1w, k) : 0u;
+        const uint32_t t2 = (planes_of(FMT) >= 3) ? t2w.w[k] : 0u;
         const double v = decode<FMT>(cw.w[k], h, t1, t2, (FMT == kCsr64) ? vv[k] : 0.0, scale,
                                      column);
         const int li = j - j0;
@@ -174,18 +174,18 @@ struct Elem {
     c = A.col[j];
     if constexpr (FMT != kCsr64) {
       h = A.head[j];
-      if constexpr (FMT >= 2) t1 = A.tail1[j];
-      if constexpr (FMT >= 3) t2 = A.tail2[j];
+      if constexpr (planes_of(FMT) >= 2) t1 = A.tail1[j];
+      if constexpr (planes_of(FMT) >= 3) t2 = A.tail2[j];
     } else {
       v = A.val[j];
     }
   }
-  __device__ __forceinline__ double product(const double* __restrict__ x, const double* scale) const {
+  __device__ __forceinline__ double product(const double* __restrict__ x, const DecodeCtx& scale) const {
     int column;
     const double d = decode<FMT>(c, h, t1, t2, v, scale, column);
     return d * x[column];
   }
-  __device__ __forceinline__ void stage(const double* scale, int li, double* vals, int* cols) const {
+  __device__ __forceinline__ void stage(const DecodeCtx& scale, int li, double* vals, int* cols) const {
     int column;
     const double d = decode<FMT>(c, h, t1, t2, v, scale, column);
     vals[li + (li >> 3)] = d;
@@ -196,7 +196,7 @@ struct Elem {
 // One product read straight from memory (phase 4).
 template <int FMT>
 __device__ __forceinline__ double product_at(const SpmvOperand& A, const double* __restrict__ x,
-                                             const double* scale, int j) {
+                                             const DecodeCtx& scale, int j) {
   Elem<FMT> e;
   e.load(A, j);
   return e.product(x, scale);
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kWG) void k_spmv(SpmvOperand A, const double* __res
   constexpr int NPF = 2;  // row pointers prefetched per thread (2 * 256 rows)
   __shared__ double vals[L::NPROD];
   __shared__ int cols[L::NPROD];
-  __shared__ double scale[16];
+  __shared__ uint32_t scale_tab[kScaleEntries];
   __shared__ int rps[NPF * kWG + 1];
   __shared__ int deferred[L::NDEF];
   __shared__ int wave_cnt[kWaves];
@@ -253,7 +253,8 @@ __global__ __launch_bounds__(kWG) void k_spmv(SpmvOperand A, const double* __res
   if (ep.gate && *ep.gate) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  build_scale<FMT>(A.sem, scale);
+  build_scale<FMT>(A.sem, scale_tab);
+  const DecodeCtx scale{scale_tab, A.split};
   double acc = 0.0;  // this thread's share of the epilogue dot
 
   auto finish_row = [&](int r, double sum) {
@@ -464,13 +465,14 @@ __global__ __launch_bounds__(kWG) void k_spmv_short(SpmvOperand A, const double*
   static_assert(kLook >= kShortRow, "look-ahead must cover the longest row");
   __shared__ __attribute__((aligned(16))) double vals[NS];
   __shared__ __attribute__((aligned(16))) int cols[NS];
-  __shared__ double scale[16];
+  __shared__ uint32_t scale_tab[kScaleEntries];
   __shared__ int rps[NPF * kWG + 1];
   __shared__ double red[kWaves];
 
   if (ep.gate && *ep.gate) return;
   const int tid = threadIdx.x;
-  build_scale<FMT>(A.sem, scale);
+  build_scale<FMT>(A.sem, scale_tab);
+  const DecodeCtx scale{scale_tab, A.split};
   double acc = 0.0;
 
   TileWalk walk(A.n_tiles);
@@ -606,8 +608,8 @@ struct RingGeom {
   static constexpr int OFF_T2 = OFF_T1 + TL * 2;
   static constexpr int OFF_VAL = TL * 4;
   static constexpr int END = (FMT == kCsr64) ? OFF_VAL + TL * 8
-                             : (FMT == 1)    ? OFF_HEAD + TL * 2
-                             : (FMT == 2)    ? OFF_T1 + TL * 2
+                             : (planes_of(FMT) == 1)    ? OFF_HEAD + TL * 2
+                             : (planes_of(FMT) == 2)    ? OFF_T1 + TL * 2
                                              : OFF_T2 + TL * 4;
   static constexpr int OFF_RPS = END;
   static constexpr int STAGE = (OFF_RPS + RP * 4 + 15) / 16 * 16;
@@ -618,8 +620,8 @@ struct RingGeom {
   static constexpr int NVAL = (TL * 8 / 16 + 63) / 64;
   static constexpr int NRPS = RP / 64;
   static constexpr int NI = NCOL + NRPS + ((FMT == kCsr64) ? NVAL
-                                           : (FMT == 1)    ? NHALF
-                                           : (FMT == 2)    ? 2 * NHALF
+                                           : (planes_of(FMT) == 1)    ? NHALF
+                                           : (planes_of(FMT) == 2)    ? 2 * NHALF
                                                            : 2 * NHALF + NCOL);
   // bytes the last load of a region writes past its end (into the next one)
   static constexpr int SPILL_COL = NCOL * 1024 - TL * 4;
@@ -705,14 +707,14 @@ __device__ __forceinline__ void ring_issue(const SpmvOperand& A, lds_char* stage
       const int e = min(j0 + 8 * (i * 64 + lane), pad - 8);
       __builtin_amdgcn_global_load_lds(A.head + e, (lds_void*)(stage + L::OFF_HEAD + i * 1024), 16, 0, 0);
     }
-    if constexpr (FMT >= 2) {
+    if constexpr (planes_of(FMT) >= 2) {
 #pragma unroll
       for (int i = 0; i < L::NHALF; ++i) {
         const int e = min(j0 + 8 * (i * 64 + lane), pad - 8);
         __builtin_amdgcn_global_load_lds(A.tail1 + e, (lds_void*)(stage + L::OFF_T1 + i * 1024), 16, 0, 0);
       }
     }
-    if constexpr (FMT == 3) {
+    if constexpr (planes_of(FMT) == 3) {
 #pragma unroll
       for (int i = 0; i < L::NCOL; ++i) {
         const int e = min(j0 + 4 * (i * 64 + lane), pad - 4);
@@ -729,7 +731,7 @@ __device__ __forceinline__ void ring_issue(const SpmvOperand& A, lds_char* stage
 
 // Consumer: the decoded value and column of staged non-zero `pos`.
 template <int FMT, class L>
-__device__ __forceinline__ double ring_value(const lds_char* stage, int pos, const double* scale,
+__device__ __forceinline__ double ring_value(const lds_char* stage, int pos, const DecodeCtx& scale,
                                              int& column) {
   typedef const __attribute__((address_space(3))) uint32_t* u32p;
   typedef const __attribute__((address_space(3))) uint16_t* u16p;
@@ -740,8 +742,8 @@ __device__ __forceinline__ double ring_value(const lds_char* stage, int pos, con
     v = *reinterpret_cast<const __attribute__((address_space(3))) double*>(stage + L::OFF_VAL + 8 * pos);
   } else {
     h = *reinterpret_cast<u16p>(stage + L::OFF_HEAD + 2 * pos);
-    if constexpr (FMT >= 2) t1 = *reinterpret_cast<u16p>(stage + L::OFF_T1 + 2 * pos);
-    if constexpr (FMT == 3) t2 = *reinterpret_cast<u32p>(stage + L::OFF_T2 + 4 * pos);
+    if constexpr (planes_of(FMT) >= 2) t1 = *reinterpret_cast<u16p>(stage + L::OFF_T1 + 2 * pos);
+    if constexpr (planes_of(FMT) == 3) t2 = *reinterpret_cast<u32p>(stage + L::OFF_T2 + 4 * pos);
   }
   return decode<FMT>(c, h, t1, t2, v, scale, column);
 }
@@ -754,14 +756,15 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_ring(SpmvOperand A,
   constexpr int PRODUCER = kRingConsumers / 64;  // wave index of the producer
   __shared__ __attribute__((aligned(16))) char ring_raw[L::D * L::STAGE];
   __shared__ int hdr[L::D][4];  // per stage: first row, row end, first non-zero
-  __shared__ double scale[16];
+  __shared__ uint32_t scale_tab[kScaleEntries];
   __shared__ double red[kRingThreads / 64];
   lds_char* ring = (lds_char*)ring_raw;
 
   if (ep.gate && *ep.gate) return;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  build_scale<FMT>(A.sem, scale);
+  build_scale<FMT>(A.sem, scale_tab);
+  const DecodeCtx scale{scale_tab, A.split};
   const int pad = (A.nnz + 15) & ~15;
   TileWalk walk(A.n_tiles);
   const int count = walk.t < walk.end ? (walk.end - walk.t + walk.step - 1) / walk.step : 0;
@@ -875,14 +878,15 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_rows(SpmvOperand A,
   constexpr int PRODUCER = kRingConsumers / 64;
   __shared__ __attribute__((aligned(16))) char ring_raw[L::D * L::STAGE];
   __shared__ int hdr[L::D][4];  // per stage: first row, row end, first staged non-zero
-  __shared__ double scale[16];
+  __shared__ uint32_t scale_tab[kScaleEntries];
   __shared__ double red[kRingThreads / 64];
   lds_char* ring = (lds_char*)ring_raw;
 
   if (ep.gate && *ep.gate) return;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  build_scale<FMT>(A.sem, scale);
+  build_scale<FMT>(A.sem, scale_tab);
+  const DecodeCtx scale{scale_tab, A.split};
   const int pad = (A.nnz + 15) & ~15;
   const int n_rt = (A.n_rows + kRowTile - 1) / kRowTile;
   TileWalk walk(n_rt);
@@ -1095,11 +1099,12 @@ __global__ __launch_bounds__(kWG) void k_spmv_rv(SpmvOperand A, const double* __
   constexpr int G = 64 / L;
   constexpr int U = kRvBatch;
   constexpr int RB = G * U;  // rows per wave
-  __shared__ double scale[16];
+  __shared__ uint32_t scale_tab[kScaleEntries];
   __shared__ double red[kWaves];
 
   if (ep.gate && *ep.gate) return;
-  build_scale<FMT>(A.sem, scale);
+  build_scale<FMT>(A.sem, scale_tab);
+  const DecodeCtx scale{scale_tab, A.split};
   __syncthreads();
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane / L, sub = lane % L;
@@ -1263,6 +1268,8 @@ hipError_t launch_spmv(int fmt, const SpmvOperand& A, const double* x, double* y
       case 1: return launch_rv_f<1>(A, x, y, ep, st);
       case 2: return launch_rv_f<2>(A, x, y, ep, st);
       case 3: return launch_rv_f<3>(A, x, y, ep, st);
+      case kFp16: return launch_rv_f<kFp16>(A, x, y, ep, st);
+      case kBf16: return launch_rv_f<kBf16>(A, x, y, ep, st);
       default: return hipErrorInvalidValue;
     }
   }
@@ -1271,6 +1278,8 @@ hipError_t launch_spmv(int fmt, const SpmvOperand& A, const double* x, double* y
     case 1: return launch_f<1>(A, x, y, ep, st);
     case 2: return launch_f<2>(A, x, y, ep, st);
     case 3: return launch_f<3>(A, x, y, ep, st);
+    case kFp16: return launch_f<kFp16>(A, x, y, ep, st);
+    case kBf16: return launch_f<kBf16>(A, x, y, ep, st);
     default: return hipErrorInvalidValue;
   }
 }

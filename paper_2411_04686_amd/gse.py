@@ -33,7 +33,8 @@ class GseError(RuntimeError):
 
 class gse_matrix(C.Structure):
     _fields_ = [("n_rows", C.c_int32), ("n_cols", C.c_int32), ("nnz", C.c_int64),
-                ("num_exp", C.c_int32), ("num_used", C.c_int32), ("sem", C.c_int16 * 8),
+                ("num_exp", C.c_int32), ("num_used", C.c_int32), ("idx_bits", C.c_int32),
+                ("sem", C.c_int16 * 64),
                 ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("head", C.c_void_p),
                 ("tail1", C.c_void_p), ("tail2", C.c_void_p), ("tile_row", C.c_void_p),
                 ("tile_cap", C.c_int32), ("tile_nnz", C.c_int32), ("n_tiles", C.c_int32),
@@ -79,6 +80,15 @@ class gse_system(C.Structure):
 FMT_GSE, FMT_CSR64 = 0, 1
 
 
+class gse_lp_matrix(C.Structure):
+    _fields_ = [("n_rows", C.c_int32), ("n_cols", C.c_int32), ("nnz", C.c_int64),
+                ("fmt", C.c_int32), ("pad", C.c_int32), ("row_ptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p), ("tile_row", C.c_void_p),
+                ("tile_cap", C.c_int32), ("tile_nnz", C.c_int32), ("n_tiles", C.c_int32),
+                ("rv_lanes", C.c_int32), ("max_row_nnz", C.c_int32), ("pad2", C.c_int32),
+                ("overflow", C.c_int64), ("eta", C.c_double)]
+
+
 class gse_request(C.Structure):
     _fields_ = [("n_rows", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
                 ("col", C.c_void_p), ("val", C.c_void_p), ("b", C.c_void_p), ("x", C.c_void_p),
@@ -114,6 +124,15 @@ _SIGS = {
     "gse_autotune": (C.c_int32, [C.POINTER(gse_matrix), C.c_int32, _P, _P, C.c_int32, _P]),
     "gse_csr_autotune": (C.c_int32, [C.POINTER(gse_csr), _P, _P, C.c_int32, _P]),
     "gse_csr_spmv": (C.c_int32, [C.POINTER(gse_csr), _P, _P, _P]),
+    "gse_lp_workspace": (C.c_int32, [C.POINTER(C.c_size_t)]),
+    "gse_lp_convert": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int64, C.c_int32,
+                                   C.POINTER(gse_lp_matrix), _P, C.c_size_t, _P]),
+    "gse_lp_plan": (C.c_int32, [C.POINTER(gse_lp_matrix), C.c_int32, C.c_int32, _P]),
+    "gse_lp_spmv": (C.c_int32, [C.POINTER(gse_lp_matrix), _P, _P, _P]),
+    "gse_lp_cg": (C.c_int32, [C.POINTER(gse_lp_matrix), _P, _P, C.POINTER(gse_params),
+                              C.POINTER(gse_report), _P, C.c_size_t, _P]),
+    "gse_lp_gmres": (C.c_int32, [C.POINTER(gse_lp_matrix), _P, _P, C.POINTER(gse_params),
+                                 C.POINTER(gse_report), _P, C.c_size_t, _P]),
     "gse_default_params": (C.c_int32, [C.c_int32, C.POINTER(gse_params)]),
     "gse_solver_workspace": (C.c_int32, [C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32,
                                          C.POINTER(C.c_size_t)]),
@@ -221,6 +240,31 @@ def gse_encode_static_scratch_bytes() -> int:
     return lib().gse_encode_static_scratch_bytes()
 
 
+LP_FP16, LP_BF16 = 1, 2
+
+
+def gse_lp_workspace() -> int:
+    out = C.c_size_t()
+    _check(lib().gse_lp_workspace(C.byref(out)), "gse_lp_workspace")
+    return out.value
+
+
+def gse_lp_convert(row_ptr, col, val, n_rows, n_cols, nnz, fmt, M: gse_lp_matrix, ws,
+                   stream=None) -> int:
+    return _check(lib().gse_lp_convert(_ptr(row_ptr), _ptr(col), _ptr(val), n_rows, n_cols, nnz,
+                                       fmt, C.byref(M), _ptr(ws), ws.numel() * ws.element_size(),
+                                       _stream(stream)), "gse_lp_convert")
+
+
+def gse_lp_plan(M: gse_lp_matrix, tile_nnz: int, rv_lanes: int = -1, stream=None) -> int:
+    return _check(lib().gse_lp_plan(C.byref(M), tile_nnz, rv_lanes, _stream(stream)),
+                  "gse_lp_plan")
+
+
+def gse_lp_spmv(M: gse_lp_matrix, x, y, stream=None) -> int:
+    return _check(lib().gse_lp_spmv(C.byref(M), _ptr(x), _ptr(y), _stream(stream)), "gse_lp_spmv")
+
+
 def gse_plan(A: gse_matrix, tile_nnz: int, rv_lanes: int = -1, stream=None) -> int:
     return _check(lib().gse_plan(C.byref(A), tile_nnz, rv_lanes, _stream(stream)), "gse_plan")
 
@@ -288,6 +332,14 @@ def gse_csr_cg(M, b, x, p, ws, stream=None) -> gse_report:
 
 def gse_csr_gmres(M, b, x, p, ws, stream=None) -> gse_report:
     return _solve(lib().gse_csr_gmres, "gse_csr_gmres", M, b, x, p, ws, stream)
+
+
+def gse_lp_cg(M, b, x, p, ws, stream=None) -> gse_report:
+    return _solve(lib().gse_lp_cg, "gse_lp_cg", M, b, x, p, ws, stream)
+
+
+def gse_lp_gmres(M, b, x, p, ws, stream=None) -> gse_report:
+    return _solve(lib().gse_lp_gmres, "gse_lp_gmres", M, b, x, p, ws, stream)
 
 
 def gse_solve_history(ws, cap: int, stream=None):
@@ -455,7 +507,7 @@ class GseMatrix:
 
     @property
     def sem(self):
-        return list(self.A.sem)
+        return list(self.A.sem)[:max(8, self.A.num_exp)]
 
     @property
     def eta(self):
@@ -478,6 +530,45 @@ class GseMatrix:
 
     def spmv(self, k_segments: int, x: torch.Tensor, y: torch.Tensor, stream=None):
         gse_spmv(self.A, k_segments, x, y, stream)
+
+
+class LpMatrix:
+    """Device planes of one FP16 / BF16 comparator matrix plus its
+    ``gse_lp_matrix`` record."""
+
+    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n_cols: int,
+                 fmt: int = LP_FP16, stream=None):
+        dev = row_ptr.device
+        n_rows = row_ptr.numel() - 1
+        nnz = val.numel()
+        pad = gse_pad(nnz)
+        self.row_ptr = row_ptr
+        self.col = _alloc(pad, torch.int32, dev)
+        self.val = _alloc(pad, torch.int16, dev)
+        cap = gse_tile_entries(nnz)
+        self.tile_row = _alloc(cap, torch.int32, dev)
+        self.ws = _alloc(gse_lp_workspace(), torch.uint8, dev)
+        M = gse_lp_matrix()
+        M.col = self.col.data_ptr()
+        M.val = self.val.data_ptr()
+        M.tile_row = self.tile_row.data_ptr()
+        M.tile_cap = cap
+        self.M = M
+        gse_lp_convert(row_ptr, col, val, n_rows, n_cols, nnz, fmt, M, self.ws, stream)
+
+    @property
+    def n_rows(self):
+        return self.M.n_rows
+
+    def values(self):
+        """The 16-bit words (uint16, host copy)."""
+        return self.val[:self.M.nnz].cpu().numpy().view("uint16")
+
+    def plan(self, tile_nnz: int = 1024, rv_lanes: int = -1, stream=None):
+        gse_lp_plan(self.M, tile_nnz, rv_lanes, stream)
+
+    def spmv(self, x: torch.Tensor, y: torch.Tensor, stream=None):
+        gse_lp_spmv(self.M, x, y, stream)
 
 
 class CsrMatrix:

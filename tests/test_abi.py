@@ -101,3 +101,19 @@ def test_argument_errors_without_launch(lib):
     assert lib.gse_spmv(C.byref(A), 1, C.c_void_p(256), C.c_void_p(256), None) == -1
     # copy needs 16-byte multiples
     assert lib.gse_stream_copy(C.c_void_p(16), C.c_void_p(32), C.c_size_t(17), None) == -1
+
+
+def test_column_limit_follows_the_index_width(lib):
+    """k = 64 leaves 26 column bits: a wider matrix is refused on the host
+    before any device work (the device pointers are never touched)."""
+    import sys
+    sys.path.insert(0, ROOT)
+    from paper_2411_04686_amd import gse as G
+    L = G.lib()
+    A = G.gse_matrix()
+    fake = C.c_void_p(256)
+    for k, n_cols, want in ((64, (1 << 26) + 1, -3), (16, (1 << 28) + 1, -3), (0, 10, -1),
+                            (65, 10, -1)):
+        st = L.gse_encode(fake, fake, fake, 1, n_cols, 1, k, None, C.byref(A), fake, 1 << 20,
+                          None)
+        assert st == want, (k, n_cols, st)

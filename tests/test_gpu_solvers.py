@@ -335,3 +335,58 @@ def test_graph_replay_matches_direct_launches(method):
         assert rg.iters == rd.iters and list(rg.iters_per_seg) == list(rd.iters_per_seg)
         assert np.array_equal(xg, xd)
         assert np.array_equal(hg, hd)
+
+
+@pytest.mark.parametrize("k", [2, 16, 64])
+def test_stepped_cg_with_other_table_sizes(k):
+    """Stepped CG on tables of k = 2, 16, 64 shared exponents (slot index of
+    1, 4, 6 bits) against the oracle's CG on the same encoding; a 1600-row
+    system whose index is wider than 3 bits runs the multi-launch path."""
+    for A in (diffusion3d(18, 7), diffusion2d(40, 8)):
+        _, b = rhs_from_solution(A, 7)
+        rp, ci, va = to_dev(A)
+        M = G.GseMatrix(rp, ci, va, A.n_cols, num_exp=k)
+        p = G.gse_default_params(G.CG)
+        p.switch_mode = 0
+        ws = torch.empty(G.gse_solver_workspace(G.CG, A.n_rows, A.nnz, 30, p.max_iter),
+                         dtype=torch.uint8, device=DEV)
+        x = torch.zeros(A.n_rows, dtype=torch.float64, device=DEV)
+        rep = G.gse_cg(M.A, torch.from_numpy(b).to(DEV), x, p, ws)
+        torch.cuda.synchronize()
+        xs = x.cpu().numpy()
+        enc = O.encode(A.indptr, A.indices, A.data, A.n_cols, num_exp=k)
+        ref = O.cg(A.indptr, b, O.make_params(tol=1e-10, max_iter=5000, preset="paper_cg",
+                                              switch_mode=0, orth=1), A.indices, A.data, enc)
+        assert rep.status == G.OK and ref.status == O.OK, (k, rep.as_dict())
+        assert rep.relres_true <= 1e-10 and true_relres(A, xs, b) <= 1e-10
+        assert np.linalg.norm(xs - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+        assert abs(rep.iters - ref.iters) <= max(3, ref.iters // 10)
+
+
+def test_batch_with_other_table_sizes():
+    """Batched CG on systems encoded with k = 4 and k = 32 (2- and 5-bit slot
+    indices) side by side: each against the oracle's CG."""
+    systems = [(diffusion3d(12, 9), 4), (diffusion2d(50, 10), 32)]
+    keep, triples = [], []
+    p = G.gse_default_params(G.CG)
+    p.switch_mode = 0
+    for A, k in systems:
+        _, b = rhs_from_solution(A, 9)
+        rp, ci, va = to_dev(A)
+        M = G.GseMatrix(rp, ci, va, A.n_cols, num_exp=k)
+        bd = torch.from_numpy(b).to(DEV)
+        xd = torch.zeros(A.n_rows, dtype=torch.float64, device=DEV)
+        keep.append((M, bd, xd, b))
+        triples.append((M.A, bd, xd))
+    ws = torch.empty(G.gse_batch_workspace(triples, p), dtype=torch.uint8, device=DEV)
+    reps = G.gse_batch_cg(triples, p, ws)
+    torch.cuda.synchronize()
+    for (A, k), rep, (_, _, xd, b) in zip(systems, reps, keep):
+        enc = O.encode(A.indptr, A.indices, A.data, A.n_cols, num_exp=k)
+        ref = O.cg(A.indptr, b, O.make_params(tol=1e-10, max_iter=5000, preset="paper_cg",
+                                              switch_mode=0, orth=1), A.indices, A.data, enc)
+        xs = xd.cpu().numpy()
+        assert rep.status == G.OK and ref.status == O.OK
+        assert true_relres(A, xs, b) <= 1e-10
+        assert np.linalg.norm(xs - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+        assert abs(rep.iters - ref.iters) <= max(3, ref.iters // 10)

@@ -250,3 +250,67 @@ def test_autotune_picks_a_candidate_and_stays_exact():
         torch.cuda.synchronize()
         ref = O.csr_spmv(A.indptr, A.indices, A.data, x)
         assert np.allclose(yd.cpu().numpy(), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("num_exp", [1, 3, 5])
+@pytest.mark.parametrize("name", ["diffusion3d_24", "powerlaw_20k", "random_ragged",
+                                  "convdiff2d_64"])
+def test_computed_tables_of_fewer_exponents(name, num_exp):
+    """Tables of k = 1, 3, 5 shared exponents computed on the device (the k
+    most frequent, the maximum forced into the last slot): table, planes and
+    eta equal the oracle's, and SpMV at every segment count agrees."""
+    A = cases()[name]()
+    enc = O.encode(A.indptr, A.indices, A.data, A.n_cols, num_exp=num_exp)
+    rp, ci, va = to_dev(A)
+    M = G.GseMatrix(rp, ci, va, A.n_cols, num_exp=num_exp)
+    assert M.sem == [int(s) for s in enc.sem] and M.A.num_used <= num_exp
+    for got, want in zip(M.planes(), (enc.col_idx, enc.head, enc.tail1, enc.tail2)):
+        assert np.array_equal(got, want), (name, num_exp)
+    assert M.A.exact_frac == enc.exact_frac
+    for s in range(3):
+        assert M.eta[s] == pytest.approx(enc.eta[s], rel=1e-12, abs=1e-300)
+    x = np.random.default_rng(num_exp).uniform(-1, 1, A.n_cols)
+    xd = torch.from_numpy(x).to(DEV)
+    yd = torch.empty(A.n_rows, dtype=torch.float64, device=DEV)
+    for s in (1, 2, 3):
+        M.spmv(s, xd, yd)
+        torch.cuda.synchronize()
+        ref = O.gse_spmv(A.indptr, enc, s, x)
+        dec = O.decode(enc, s)
+        scale = np.zeros(A.n_rows)
+        np.add.at(scale, np.repeat(np.arange(A.n_rows), np.diff(A.indptr)),
+                  np.abs(dec * x[A.indices]))
+        _check_close(yd.cpu().numpy(), ref, scale)
+
+
+@pytest.mark.parametrize("k", [2, 4, 16, 32, 64])
+@pytest.mark.parametrize("name", ["powerlaw_20k", "random_empty_long", "diffusion3d_24"])
+def test_index_width_follows_the_table_size(name, k):
+    """k shared exponents put a ceil(log2 k)-bit slot index in the column word
+    (Section III-B.1, III-C.1; the k sweep of Section IV-B): table, planes,
+    eta bit-exact against the oracle and SpMV at every segment count on the
+    default schedule, the general tiles and the row-vector schedule."""
+    A = cases()[name]()
+    enc = O.encode(A.indptr, A.indices, A.data, A.n_cols, num_exp=k)
+    rp, ci, va = to_dev(A)
+    M = G.GseMatrix(rp, ci, va, A.n_cols, num_exp=k)
+    assert M.A.idx_bits == enc.idx_bits == O.index_bits(k)
+    assert M.sem == [int(s) for s in enc.sem]
+    for got, want in zip(M.planes(), (enc.col_idx, enc.head, enc.tail1, enc.tail2)):
+        assert np.array_equal(got, want), (name, k)
+    for s in range(3):
+        assert M.eta[s] == pytest.approx(enc.eta[s], rel=1e-12, abs=1e-300)
+    x = np.random.default_rng(k).uniform(-1, 1, A.n_cols)
+    xd = torch.from_numpy(x).to(DEV)
+    yd = torch.empty(A.n_rows, dtype=torch.float64, device=DEV)
+    dec = {s: O.decode(enc, s) for s in (1, 2, 3)}
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.indptr))
+    for sched in ((1024, -1), (2048, 0), (2048, 8)):
+        M.plan(*sched)
+        for s in (1, 2, 3):
+            M.spmv(s, xd, yd)
+            torch.cuda.synchronize()
+            ref = O.gse_spmv(A.indptr, enc, s, x)
+            scale = np.zeros(A.n_rows)
+            np.add.at(scale, rows, np.abs(dec[s] * x[A.indices]))
+            _check_close(yd.cpu().numpy(), ref, scale)
