@@ -45,8 +45,8 @@ class Matrix(C.Structure):
     _fields_ = [("n_rows", C.c_int32), ("row_ptr", C.c_void_p), ("col", C.c_void_p),
                 ("val", C.c_void_p), ("col_idx", C.c_void_p), ("head", C.c_void_p),
                 ("tail1", C.c_void_p), ("tail2", C.c_void_p), ("sem64", C.c_void_p),
-                ("eta3", C.c_void_p), ("idx_bits", C.c_int32), ("lp_val", C.c_void_p),
-                ("lp_fmt", C.c_int32)]
+                ("eta3", C.c_void_p), ("idx_bits", C.c_int32), ("layout", C.c_int32),
+                ("lp_val", C.c_void_p), ("lp_fmt", C.c_int32)]
 
 
 def lib():
@@ -63,15 +63,15 @@ def lib():
         L.or_select_shared_exponents.restype = C.c_int
         L.or_select_shared_exponents.argtypes = [P, C.c_int, P]
         L.or_encode_values.restype = C.c_int
-        L.or_encode_values.argtypes = [P, P, C.c_int64, P, C.c_int, P, P, P, P]
+        L.or_encode_values.argtypes = [P, P, C.c_int64, P, C.c_int, C.c_int, P, P, P, P]
         L.or_encode.restype = C.c_int
-        L.or_encode.argtypes = [P, P, P, C.c_int32, C.c_int32, C.c_int64, C.c_int, P, P,
-                                P, P, P, P, P, P]
+        L.or_encode.argtypes = [P, P, P, C.c_int32, C.c_int32, C.c_int64, C.c_int, C.c_int, P,
+                                P, P, P, P, P, P, P, P]
         L.or_decode_one.restype = C.c_double
         L.or_decode_one.argtypes = [C.c_uint32, C.c_uint16, C.c_uint16, C.c_uint32, P, C.c_int,
-                                    C.c_int]
+                                    C.c_int, C.c_int]
         L.or_decode.restype = None
-        L.or_decode.argtypes = [P, P, P, P, C.c_int64, P, C.c_int, C.c_int, P]
+        L.or_decode.argtypes = [P, P, P, P, C.c_int64, P, C.c_int, C.c_int, C.c_int, P]
         L.or_lp_round.restype = C.c_uint16
         L.or_lp_round.argtypes = [C.c_double, C.c_int, P]
         L.or_lp_widen.restype = C.c_double
@@ -83,9 +83,10 @@ def lib():
         L.or_csr_spmv.restype = None
         L.or_csr_spmv.argtypes = [C.c_int32, P, P, P, P, P]
         L.or_gse_spmv.restype = None
-        L.or_gse_spmv.argtypes = [C.c_int32, P, P, P, P, P, P, C.c_int, C.c_int, P, P]
+        L.or_gse_spmv.argtypes = [C.c_int32, P, P, P, P, P, P, C.c_int, C.c_int, C.c_int, P, P]
         L.or_gse_spmv_rows.restype = None
-        L.or_gse_spmv_rows.argtypes = [P, C.c_int32, P, P, P, P, P, P, C.c_int, C.c_int, P, P]
+        L.or_gse_spmv_rows.argtypes = [P, C.c_int32, P, P, P, P, P, P, C.c_int, C.c_int, C.c_int,
+                                       P, P]
         L.or_window_metrics.restype = None
         L.or_window_metrics.argtypes = [P, C.c_int32, C.c_int32, P, P, P]
         L.or_precision_trigger.restype = C.c_int
@@ -155,22 +156,28 @@ class Encoded:
     tail2: np.ndarray      # uint32[nnz]
     eta: np.ndarray        # float64[3]
     exact_frac: float
-    idx_bits: int = 3      # slot-index width in the column word
+    idx_bits: int = 3      # slot-index width
+    layout: int = 0        # 0: slot in the column word, 1: in the value (head's top bits)
 
     @property
     def table(self):
         return _table(self.sem)
 
     def column(self):
+        if self.layout == 1:
+            return self.col_idx.copy()
         return self.col_idx & np.uint32(0xFFFFFFFF >> self.idx_bits)
 
     def slot(self):
         if self.idx_bits == 0:
             return np.zeros_like(self.col_idx)
+        if self.layout == 1:
+            return ((self.head >> np.uint16(15 - self.idx_bits)) &
+                    np.uint16((1 << self.idx_bits) - 1)).astype(np.uint32)
         return self.col_idx >> np.uint32(32 - self.idx_bits)
 
 
-def encode_values(val, col, sem, idx_bits: int = 3):
+def encode_values(val, col, sem, idx_bits: int = 3, layout: int = 0):
     val = _c(val, np.float64)
     col = _c(col, np.int32)
     sem = _table(sem)
@@ -179,14 +186,17 @@ def encode_values(val, col, sem, idx_bits: int = 3):
     h = np.empty(nnz, np.uint16)
     t1 = np.empty(nnz, np.uint16)
     t2 = np.empty(nnz, np.uint32)
-    rc = lib().or_encode_values(_p(val), _p(col), nnz, _p(sem), idx_bits, _p(ci), _p(h), _p(t1),
-                                _p(t2))
+    rc = lib().or_encode_values(_p(val), _p(col), nnz, _p(sem), idx_bits, layout, _p(ci), _p(h),
+                                _p(t1), _p(t2))
     if rc < 0:
         raise OracleError(rc, "encode_values")
     return ci, h, t1, t2
 
 
-def encode(indptr, indices, data, n_cols: int, num_exp: int = 8, sem_in=None) -> Encoded:
+def encode(indptr, indices, data, n_cols: int, num_exp: int = 8, sem_in=None,
+           layout: int = -1) -> Encoded:
+    """layout: 0 slot in the column word, 1 in the value, -1 the column word
+    unless n_cols needs more than its 32 - idx_bits bits."""
     indptr = _c(indptr, np.int32)
     indices = _c(indices, np.int32)
     data = _c(data, np.float64)
@@ -202,26 +212,27 @@ def encode(indptr, indices, data, n_cols: int, num_exp: int = 8, sem_in=None) ->
     si = None if sem_in is None else _c(sem_in, np.int16)
     if si is not None and si.size < num_exp:
         raise OracleError(ERR_ARG, "sem_in holds fewer than num_exp entries")
-    rc = lib().or_encode(_p(indptr), _p(indices), _p(data), n_rows, n_cols, nnz, num_exp,
+    lo = C.c_int(0)
+    rc = lib().or_encode(_p(indptr), _p(indices), _p(data), n_rows, n_cols, nnz, num_exp, layout,
                          _p(si), _p(sem), _p(ci), _p(h), _p(t1), _p(t2), _p(eta),
-                         C.addressof(ef))
+                         C.addressof(ef), C.addressof(lo))
     if rc < 0:
         raise OracleError(rc, "encode")
     return Encoded(sem[:max(8, num_exp)].copy(), ci[:nnz], h[:nnz], t1[:nnz], t2[:nnz], eta,
-                   ef.value, index_bits(num_exp))
+                   ef.value, index_bits(num_exp), lo.value)
 
 
 def decode(enc: Encoded, s: int):
     out = np.empty(enc.head.size, np.float64)
     lib().or_decode(_p(enc.col_idx), _p(enc.head), _p(enc.tail1), _p(enc.tail2),
-                    enc.head.size, _p(enc.table), enc.idx_bits, s, _p(out))
+                    enc.head.size, _p(enc.table), enc.idx_bits, enc.layout, s, _p(out))
     return out
 
 
 def decode_one(col_word: int, head: int, tail1: int, tail2: int, sem, s: int,
-               idx_bits: int = 3) -> float:
+               idx_bits: int = 3, layout: int = 0) -> float:
     table = _table(sem)
-    return lib().or_decode_one(col_word, head, tail1, tail2, _p(table), idx_bits, s)
+    return lib().or_decode_one(col_word, head, tail1, tail2, _p(table), idx_bits, layout, s)
 
 
 # ------------------------------------------------- FP16 / BF16 comparators ---
@@ -275,7 +286,8 @@ def gse_spmv(indptr, enc: Encoded, s: int, x):
     y = np.empty(indptr.size - 1, np.float64)
     table = enc.table
     lib().or_gse_spmv(indptr.size - 1, _p(indptr), _p(enc.col_idx), _p(enc.head),
-                      _p(enc.tail1), _p(enc.tail2), _p(table), enc.idx_bits, s, _p(x), _p(y))
+                      _p(enc.tail1), _p(enc.tail2), _p(table), enc.idx_bits, enc.layout, s, _p(x),
+                      _p(y))
     return y
 
 
@@ -286,8 +298,8 @@ def gse_spmv_rows(rows, indptr, enc: Encoded, s: int, x):
     y = np.empty(rows.size, np.float64)
     table = enc.table
     lib().or_gse_spmv_rows(_p(rows), rows.size, _p(indptr), _p(enc.col_idx), _p(enc.head),
-                           _p(enc.tail1), _p(enc.tail2), _p(table), enc.idx_bits, s, _p(x),
-                           _p(y))
+                           _p(enc.tail1), _p(enc.tail2), _p(table), enc.idx_bits, enc.layout, s,
+                           _p(x), _p(y))
     return y
 
 
@@ -354,6 +366,7 @@ def _matrix(indptr, indices=None, data=None, enc: Optional[Encoded] = None, lp=N
         m.sem64 = _p(table)
         m.eta3 = _p(enc.eta)
         m.idx_bits = enc.idx_bits
+        m.layout = enc.layout
         keep.extend([enc, table])
     if lp is not None:  # (uint16 plane, fmt)
         plane = _c(lp[0], np.uint16)

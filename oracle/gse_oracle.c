@@ -22,15 +22,23 @@ int or_index_bits(int num_exp) {
     return b;
 }
 
-/* Column and slot of a column word whose top idx_bits bits hold the slot
- * (Section III-C.1). */
-static uint32_t column_of(uint32_t word, int idx_bits) {
-    return idx_bits == 0 ? word : (word & (0xFFFFFFFFu >> idx_bits));
+/* Where the slot index lives (Section III-C.1): in the top idx_bits bits
+ * of the column word (layout 0), or -- Algorithm 1's EI_bit, the fallback
+ * when the column field is too narrow -- in the top idx_bits bits of the
+ * value word below its sign (layout 1), where it takes magnitude bits. */
+static uint32_t column_of(uint32_t word, int idx_bits, int layout) {
+    if (layout == 1 || idx_bits == 0) return word;
+    return word & (0xFFFFFFFFu >> idx_bits);
 }
 
-static int slot_of(uint32_t word, int idx_bits) {
-    return idx_bits == 0 ? 0 : (int)(word >> (32 - idx_bits));
+static int slot_of(uint32_t word, uint16_t head, int idx_bits, int layout) {
+    if (idx_bits == 0) return 0;
+    if (layout == 1) return (int)((head >> (15 - idx_bits)) & ((1u << idx_bits) - 1u));
+    return (int)(word >> (32 - idx_bits));
 }
+
+/* Bits of the magnitude field: 63, less the index when it sits in the value. */
+static int field_bits(int idx_bits, int layout) { return layout == 1 ? 63 - idx_bits : 63; }
 
 /* ------------------------------------------------------------------------ */
 /* Section III-B.1: occurrences N_i of every distinct exponent e_i.  The    */
@@ -105,9 +113,10 @@ int or_select_shared_exponents(const uint32_t* hist, int num_exp, int16_t* sem) 
  * smallest normal (1) for the shift.  Returns OR_ERR_RANGE if a value has no
  * shared exponent above its own (possible only with a reused table). */
 int or_encode_values(const double* val, const int32_t* col, int64_t nnz,
-                     const int16_t* sem, int idx_bits, uint32_t* col_idx, uint16_t* head,
-                     uint16_t* tail1, uint32_t* tail2) {
-    if (idx_bits < 0 || idx_bits > 6) return OR_ERR_ARG;
+                     const int16_t* sem, int idx_bits, int layout, uint32_t* col_idx,
+                     uint16_t* head, uint16_t* tail1, uint32_t* tail2) {
+    if (idx_bits < 0 || idx_bits > 6 || (layout != 0 && layout != 1)) return OR_ERR_ARG;
+    const int fb = field_bits(idx_bits, layout);
     for (int64_t i = 0; i < nnz; ++i) {
         uint64_t u = bits_of(val[i]);
         unsigned sign = (unsigned)(u >> 63);
@@ -129,16 +138,24 @@ int or_encode_values(const double* val, const int32_t* col, int64_t nnz,
         }
         uint64_t sig = (e > 0) ? ((1ull << 52) | frac) : frac;
         int shift_exp = (e > 0) ? e : 1;
-        int sh = 11 - ((int)sem[slot] - shift_exp);  /* = 11 - minDiff for normals */
+        /* the field holds fb bits: the hidden one of a value with minDiff = 1
+         * lands on its top bit (bit fb - 1) */
+        int sh = (fb - 52) - ((int)sem[slot] - shift_exp);
         uint64_t F;
         if (sh >= 0) F = sig << sh;
         else if (-sh >= 64) F = 0;
         else F = sig >> (-sh);
         (void)min_diff;
         if (slot >= (1 << idx_bits)) return OR_ERR_ARG;
-        col_idx[i] = (uint32_t)col[i] |
-                     (idx_bits == 0 ? 0u : ((uint32_t)slot << (32 - idx_bits)));
-        head[i] = (uint16_t)((sign << 15) | (unsigned)(F >> 48));
+        unsigned idx_in_head = 0;
+        if (layout == 1) {
+            col_idx[i] = (uint32_t)col[i];
+            if (idx_bits > 0) idx_in_head = (unsigned)slot << (15 - idx_bits);
+        } else {
+            col_idx[i] = (uint32_t)col[i] |
+                         (idx_bits == 0 ? 0u : ((uint32_t)slot << (32 - idx_bits)));
+        }
+        head[i] = (uint16_t)((sign << 15) | idx_in_head | (unsigned)(F >> 48));
         tail1[i] = (uint16_t)((F >> 32) & 0xFFFF);
         tail2[i] = (uint32_t)(F & 0xFFFFFFFFu);
     }
@@ -149,11 +166,14 @@ int or_encode_values(const double* val, const int32_t* col, int64_t nnz,
  * with s segments is +-F_W * 2^(SEM - 1023 - W), W = 15, 31, 63, where F_W is
  * the top W magnitude bits of the SEM word; a zero field reads as 0. */
 double or_decode_one(uint32_t col_word, uint16_t h, uint16_t t1, uint32_t t2,
-                     const int16_t* sem, int idx_bits, int s) {
-    int slot = slot_of(col_word, idx_bits);
-    int W = (s == 1) ? 15 : (s == 2) ? 31 : 63;
-    uint64_t F63 = ((uint64_t)(h & 0x7FFFu) << 48) | ((uint64_t)t1 << 32) | (uint64_t)t2;
-    uint64_t F = F63 >> (63 - W);
+                     const int16_t* sem, int idx_bits, int layout, int s) {
+    int slot = slot_of(col_word, h, idx_bits, layout);
+    int fb = field_bits(idx_bits, layout);
+    /* s segments keep the head's magnitude bits, then 16 and 32 more */
+    int W = fb - ((s == 1) ? 48 : (s == 2) ? 32 : 0);
+    uint64_t head_mag = (uint64_t)(h & (0x7FFFu >> (63 - fb)));
+    uint64_t Ff = (head_mag << 48) | ((uint64_t)t1 << 32) | (uint64_t)t2;
+    uint64_t F = Ff >> (fb - W);
     if (F == 0) return 0.0;
     double mag = ldexp((double)F, (int)sem[slot] - 1023 - W);
     return (h >> 15) ? -mag : mag;
@@ -161,23 +181,29 @@ double or_decode_one(uint32_t col_word, uint16_t h, uint16_t t1, uint32_t t2,
 
 void or_decode(const uint32_t* col_idx, const uint16_t* head, const uint16_t* tail1,
                const uint32_t* tail2, int64_t nnz, const int16_t* sem, int idx_bits,
-               int s, double* out) {
+               int layout, int s, double* out) {
     for (int64_t i = 0; i < nnz; ++i)
-        out[i] = or_decode_one(col_idx[i], head[i], tail1[i], tail2[i], sem, idx_bits, s);
+        out[i] = or_decode_one(col_idx[i], head[i], tail1[i], tail2[i], sem, idx_bits, layout,
+                               s);
 }
 
 /* Whole conversion: histogram, table, per-value words, and the relative
  * perturbation eta_s = ||A - A_s||_inf / ||A||_inf of each segment count. */
 int or_encode(const int32_t* row_ptr, const int32_t* col, const double* val,
-              int32_t n_rows, int32_t n_cols, int64_t nnz, int num_exp,
+              int32_t n_rows, int32_t n_cols, int64_t nnz, int num_exp, int layout,
               const int16_t* sem_in, int16_t* sem_out, uint32_t* col_idx,
               uint16_t* head, uint16_t* tail1, uint32_t* tail2, double* eta3,
-              double* exact_frac) {
+              double* exact_frac, int* layout_out) {
     if (n_rows < 0 || n_cols < 0 || nnz < 0 || num_exp < 1 || num_exp > OR_MAX_EXP)
         return OR_ERR_ARG;
     int idx_bits = or_index_bits(num_exp);
-    /* the column field keeps 32 - idx_bits bits */
-    if ((int64_t)n_cols > (1ll << (32 - idx_bits)) || nnz >= (1ll << 31)) return OR_ERR_RANGE;
+    /* the column field keeps 32 - idx_bits bits; past that the index moves
+     * into the value (layout -1 chooses so, Section III-C.1) */
+    if (layout < 0) layout = ((int64_t)n_cols > (1ll << (32 - idx_bits))) ? 1 : 0;
+    if (layout != 0 && layout != 1) return OR_ERR_ARG;
+    if (layout_out) *layout_out = layout;
+    if ((layout == 0 && (int64_t)n_cols > (1ll << (32 - idx_bits))) || nnz >= (1ll << 31))
+        return OR_ERR_RANGE;
     uint32_t* hist = (uint32_t*)malloc(2048 * sizeof(uint32_t));
     if (!hist) return OR_ERR_ARG;
     if (or_exponent_histogram(val, nnz, hist) > 0) { free(hist); return OR_ERR_NONFINITE; }
@@ -198,7 +224,7 @@ int or_encode(const int32_t* row_ptr, const int32_t* col, const double* val,
         if (sem_out[i] > 0) covered += hist[sem_out[i] - 1];
     if (exact_frac) *exact_frac = nnz ? (double)covered / (double)nnz : 1.0;
     free(hist);
-    rc = or_encode_values(val, col, nnz, sem_out, idx_bits, col_idx, head, tail1, tail2);
+    rc = or_encode_values(val, col, nnz, sem_out, idx_bits, layout, col_idx, head, tail1, tail2);
     if (rc != OR_OK) return rc;
     if (eta3) {
         double amax = 0.0, emax[3] = {0.0, 0.0, 0.0};
@@ -208,7 +234,8 @@ int or_encode(const int32_t* row_ptr, const int32_t* col, const double* val,
                 a += fabs(val[j]);
                 for (int s = 1; s <= 3; ++s)
                     es[s - 1] += fabs(val[j] - or_decode_one(col_idx[j], head[j], tail1[j],
-                                                             tail2[j], sem_out, idx_bits, s));
+                                                             tail2[j], sem_out, idx_bits, layout,
+                                                             s));
             }
             if (a > amax) amax = a;
             for (int s = 0; s < 3; ++s) if (es[s] > emax[s]) emax[s] = es[s];
@@ -320,12 +347,14 @@ void or_csr_spmv(int32_t n_rows, const int32_t* row_ptr, const int32_t* col,
  * accumulate in FP64 in row order. */
 void or_gse_spmv(int32_t n_rows, const int32_t* row_ptr, const uint32_t* col_idx,
                  const uint16_t* head, const uint16_t* tail1, const uint32_t* tail2,
-                 const int16_t* sem, int idx_bits, int s, const double* x, double* y) {
+                 const int16_t* sem, int idx_bits, int layout, int s, const double* x,
+                 double* y) {
     for (int32_t r = 0; r < n_rows; ++r) {
         double sum = 0.0;
         for (int32_t j = row_ptr[r]; j < row_ptr[r + 1]; ++j) {
-            double v = or_decode_one(col_idx[j], head[j], tail1[j], tail2[j], sem, idx_bits, s);
-            sum += v * x[column_of(col_idx[j], idx_bits)];
+            double v = or_decode_one(col_idx[j], head[j], tail1[j], tail2[j], sem, idx_bits,
+                                     layout, s);
+            sum += v * x[column_of(col_idx[j], idx_bits, layout)];
         }
         y[r] = sum;
     }
@@ -334,14 +363,15 @@ void or_gse_spmv(int32_t n_rows, const int32_t* row_ptr, const uint32_t* col_idx
 void or_gse_spmv_rows(const int32_t* rows, int32_t n_sel, const int32_t* row_ptr,
                       const uint32_t* col_idx, const uint16_t* head,
                       const uint16_t* tail1, const uint32_t* tail2,
-                      const int16_t* sem, int idx_bits, int s, const double* x,
+                      const int16_t* sem, int idx_bits, int layout, int s, const double* x,
                       double* y_sel) {
     for (int32_t q = 0; q < n_sel; ++q) {
         int32_t r = rows[q];
         double sum = 0.0;
         for (int32_t j = row_ptr[r]; j < row_ptr[r + 1]; ++j) {
-            double v = or_decode_one(col_idx[j], head[j], tail1[j], tail2[j], sem, idx_bits, s);
-            sum += v * x[column_of(col_idx[j], idx_bits)];
+            double v = or_decode_one(col_idx[j], head[j], tail1[j], tail2[j], sem, idx_bits,
+                                     layout, s);
+            sum += v * x[column_of(col_idx[j], idx_bits, layout)];
         }
         y_sel[q] = sum;
     }
@@ -389,7 +419,7 @@ static void apply_op(const or_matrix* A, int s, const double* x, double* y) {
     if (s == OR_S_LP) or_lp_spmv(A->n_rows, A->row_ptr, A->col, A->lp_val, A->lp_fmt, x, y);
     else if (s <= 0) or_csr_spmv(A->n_rows, A->row_ptr, A->col, A->val, x, y);
     else or_gse_spmv(A->n_rows, A->row_ptr, A->col_idx, A->head, A->tail1, A->tail2,
-                     A->sem64, A->idx_bits, s, x, y);
+                     A->sem64, A->idx_bits, A->layout, s, x, y);
 }
 
 static double dot(int32_t n, const double* a, const double* b) {

@@ -17,7 +17,8 @@
  *     Section III-B.1), kept in the top b bits of the 32-bit column index
  *     (Section III-C.1), and a 64-bit word  sign<<63 | F63  where F63 is |v|
  *     on the fixed-point grid 2^(SEM-1023-63) of its slot, truncated toward
- *     zero;
+ *     zero; or, when the column field is too narrow, the index in the value
+ *     word (Algorithm 1's EI_bit): sign | index | F on a 63-b bit field;
  *   - the word is split into three planes: head (bits 63..48), tail1
  *     (bits 47..32) and tail2 (bits 31..0).  Reading s planes gives a
  *     W_s = 15, 31 or 63 bit magnitude.
@@ -71,18 +72,21 @@ int or_index_bits(int num_exp);
 int64_t or_exponent_histogram(const double* val, int64_t nnz, uint32_t* hist2048);
 int or_select_shared_exponents(const uint32_t* hist2048, int num_exp, int16_t* sem64);
 int or_encode_values(const double* val, const int32_t* col, int64_t nnz,
-                     const int16_t* sem64, int idx_bits, uint32_t* col_idx, uint16_t* head,
-                     uint16_t* tail1, uint32_t* tail2);
+                     const int16_t* sem64, int idx_bits, int layout, uint32_t* col_idx,
+                     uint16_t* head, uint16_t* tail1, uint32_t* tail2);
+/* layout: 0 index in the column word, 1 in the value (Algorithm 1's EI_bit:
+ * sign | index | 63 - idx_bits magnitude bits), -1 the column word unless the
+ * column field is too narrow for n_cols; *layout_out receives the choice. */
 int or_encode(const int32_t* row_ptr, const int32_t* col, const double* val,
-              int32_t n_rows, int32_t n_cols, int64_t nnz, int num_exp,
+              int32_t n_rows, int32_t n_cols, int64_t nnz, int num_exp, int layout,
               const int16_t* sem_in, int16_t* sem_out64, uint32_t* col_idx,
               uint16_t* head, uint16_t* tail1, uint32_t* tail2, double* eta3,
-              double* exact_frac);
+              double* exact_frac, int* layout_out);
 double or_decode_one(uint32_t col_word, uint16_t head, uint16_t tail1,
-                     uint32_t tail2, const int16_t* sem64, int idx_bits, int s);
+                     uint32_t tail2, const int16_t* sem64, int idx_bits, int layout, int s);
 void or_decode(const uint32_t* col_idx, const uint16_t* head, const uint16_t* tail1,
                const uint32_t* tail2, int64_t nnz, const int16_t* sem64, int idx_bits,
-               int s, double* out);
+               int layout, int s, double* out);
 
 /* ---- FP16 / BF16 comparators (Section IV-C) ----
  * fmt: OR_LP_FP16 (IEEE binary16) or OR_LP_BF16 (bfloat16).  Values are
@@ -101,11 +105,12 @@ void or_csr_spmv(int32_t n_rows, const int32_t* row_ptr, const int32_t* col,
                  const double* val, const double* x, double* y);
 void or_gse_spmv(int32_t n_rows, const int32_t* row_ptr, const uint32_t* col_idx,
                  const uint16_t* head, const uint16_t* tail1, const uint32_t* tail2,
-                 const int16_t* sem64, int idx_bits, int s, const double* x, double* y);
+                 const int16_t* sem64, int idx_bits, int layout, int s, const double* x,
+                 double* y);
 void or_gse_spmv_rows(const int32_t* rows, int32_t n_sel, const int32_t* row_ptr,
                       const uint32_t* col_idx, const uint16_t* head,
                       const uint16_t* tail1, const uint32_t* tail2,
-                      const int16_t* sem64, int idx_bits, int s, const double* x,
+                      const int16_t* sem64, int idx_bits, int layout, int s, const double* x,
                       double* y_sel);
 
 /* ---- controller (Section III-D, Eqs. 3-6, Conditions 1-3) ---- */
@@ -130,6 +135,7 @@ typedef struct {
     const int16_t* sem64;
     const double* eta3;
     int32_t idx_bits;
+    int32_t layout;          /* 0: slot in the column word, 1: in the value */
     const uint16_t* lp_val;  /* FP16 / BF16 values (fixed_segments == -2) */
     int32_t lp_fmt;
 } or_matrix;

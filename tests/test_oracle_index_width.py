@@ -85,9 +85,14 @@ def test_column_field_limit_follows_the_index_width(k):
     assert int(enc.column()[0]) == limit - 1 and int(enc.slot()[0]) == 0
     assert O.decode(enc, 3)[0] == 3.0
     if b > 1:
+        # forced into the column word it no longer fits ...
         with pytest.raises(O.OracleError) as ei:
-            O.encode(indptr, col, np.array([3.0]), limit + 1, num_exp=k)
+            O.encode(indptr, col, np.array([3.0]), limit + 1, num_exp=k, layout=0)
         assert ei.value.code == O.ERR_RANGE
+        # ... so by default the index moves into the value (Section III-C.1)
+        enc = O.encode(indptr, col, np.array([3.0]), limit + 1, num_exp=k)
+        assert enc.layout == 1 and int(enc.column()[0]) == limit - 1
+        assert O.decode(enc, 3)[0] == 3.0
 
 
 def test_truncation_error_never_grows_with_k():
