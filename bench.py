@@ -359,6 +359,13 @@ def run_spmv_cg(args, torch, G):
         out["spmv_error"] = spmv_errors(A, mats[0], csrs[0], np.ones(A.n_cols), dev, torch)
     del mats, csrs, ys
     if args.legs and not args.no_solve:
+        progress("legs: FP16 / BF16 comparators and the k sweep on the 128^3 operator")
+        out["lowprec_spmv"] = leg_lowprec_spmv(torch, G, A, args.copies)
+        if solve:
+            out["lowprec_cg"] = leg_lowprec_solve(torch, G, A, b, x_true, G.CG, solve["gse"][-1],
+                                                  solve["fp64"][-1])
+        out["k_sweep"] = leg_k_sweep(torch, G, A, args.copies)
+    if args.legs and not args.no_solve:
         # the other configurations, each once after the timed steps (their own
         # warm-up), so that every result of the path is on the one line
         progress("legs: poisson 64^2")
@@ -409,6 +416,129 @@ def solve_record(rep, x_dev, x_true):
     return d
 
 
+def rotated_launch_us(torch, stream, launches, reps=10):
+    """Mean time per launch (us) of `launches` (one closure per resident
+    copy) run back to back in rounds, HIP events around each round."""
+    for f in launches:
+        f()
+    ev = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for f in launches:
+            f()
+        e1.record(stream)
+        ev.append((e0, e1))
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in ev])) * 1e3 / len(launches)
+
+
+def host_product_errors(y_dev, ref):
+    d = y_dev.cpu().numpy() - ref
+    nref = float(np.linalg.norm(ref))
+    with np.errstate(invalid="ignore"):
+        return {"max_abs": float(np.max(np.abs(d))) if d.size else 0.0,
+                "rel": float(np.linalg.norm(d) / nref) if nref > 0 else 0.0}
+
+
+def leg_k_sweep(torch, G, A, copies, ks=(2, 4, 8, 16, 32, 64)):
+    """The k sweep of Section IV-B: the head-only SpMV with tables of k
+    shared exponents (slot index of ceil(log2 k) bits): time per launch over
+    `copies` rotated copies, and max-abs / relative error against the host
+    FP64 product with x = 1, eta_1 and the share of exactly represented
+    exponents."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    ref = A.to_scipy() @ np.ones(A.n_cols)
+    rp = torch.from_numpy(A.indptr).to(dev)
+    ci = torch.from_numpy(A.indices).to(dev)
+    va = torch.from_numpy(A.data).to(dev)
+    xs = torch.ones(A.n_cols, dtype=torch.float64, device=dev)
+    ys = [torch.empty(A.n_rows, dtype=torch.float64, device=dev) for _ in range(copies)]
+    out = {}
+    for k in ks:
+        mats = [G.GseMatrix(rp.clone(), ci, va, A.n_cols, num_exp=k) for _ in range(copies)]
+        us = rotated_launch_us(torch, stream,
+                               [lambda m=m, y=y: m.spmv(1, xs, y) for m, y in zip(mats, ys)])
+        mats[0].spmv(1, xs, ys[0])
+        torch.cuda.synchronize()
+        nbytes = spmv_bytes(A.n_rows, A.n_cols, A.nnz, 6)
+        out[str(k)] = {"idx_bits": mats[0].A.idx_bits, "s1_us": round(us, 2),
+                       "GBps": round(nbytes / (us * 1e-6) / 1e9, 1),
+                       **host_product_errors(ys[0], ref), "eta1": float(mats[0].eta[0]),
+                       "exact_frac": round(float(mats[0].A.exact_frac), 4)}
+        del mats
+    return out
+
+
+def leg_lowprec_spmv(torch, G, A, copies):
+    """FP16- and BF16-SpMV (Section IV-C): time per launch over rotated
+    copies, error against the host FP64 product with x = 1, eta_h and the
+    number of values that overflowed to infinity."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    ref = A.to_scipy() @ np.ones(A.n_cols)
+    rp = torch.from_numpy(A.indptr).to(dev)
+    ci = torch.from_numpy(A.indices).to(dev)
+    va = torch.from_numpy(A.data).to(dev)
+    xs = torch.ones(A.n_cols, dtype=torch.float64, device=dev)
+    ys = [torch.empty(A.n_rows, dtype=torch.float64, device=dev) for _ in range(copies)]
+    out = {}
+    for name, fmt in (("fp16", G.LP_FP16), ("bf16", G.LP_BF16)):
+        mats = [G.LpMatrix(rp.clone(), ci, va, A.n_cols, fmt=fmt) for _ in range(copies)]
+        us = rotated_launch_us(torch, stream,
+                               [lambda m=m, y=y: m.spmv(xs, y) for m, y in zip(mats, ys)])
+        mats[0].spmv(xs, ys[0])
+        torch.cuda.synchronize()
+        nbytes = spmv_bytes(A.n_rows, A.n_cols, A.nnz, 6)
+        out[name] = {"mean_us": round(us, 2), "GBps": round(nbytes / (us * 1e-6) / 1e9, 1),
+                     **host_product_errors(ys[0], ref), "eta": float(mats[0].M.eta),
+                     "overflow": int(mats[0].M.overflow)}
+        del mats
+    return out
+
+
+def leg_lowprec_solve(torch, G, A, b, x_true, method, gse_rep, fp64_rep):
+    """The FP16 / BF16 solver comparators (Section IV-D.3) on the same system:
+    iterations, time, the residual of their own operator and the true one,
+    and the Eq. 7 projection of the stepped GSE solve without conversion
+    cost: (time / iterations of FP16) x iterations of GSE, against FP64."""
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(A.indptr).to(dev)
+    ci = torch.from_numpy(A.indices).to(dev)
+    va = torch.from_numpy(A.data).to(dev)
+    bd = torch.from_numpy(b).to(dev)
+    p = G.gse_default_params(method)
+    if method == G.CG:
+        p.max_iter = 20000
+    ws = torch.empty(G.gse_solver_workspace(method, A.n_rows, A.nnz, p.restart, p.max_iter),
+                     dtype=torch.uint8, device=dev)
+    fn = G.gse_lp_gmres if method == G.GMRES else G.gse_lp_cg
+    out = {}
+    for name, fmt in (("fp16", G.LP_FP16), ("bf16", G.LP_BF16)):
+        M = G.LpMatrix(rp, ci, va, A.n_cols, fmt=fmt)
+        x = torch.zeros(A.n_rows, dtype=torch.float64, device=dev)
+        fn(M.M, bd, x, p, ws)  # warm-up (graph capture)
+        x.zero_()
+        torch.cuda.synchronize()
+        rep = fn(M.M, bd, x, p, ws)
+        xh = x.cpu().numpy()
+        d = rep.as_dict()
+        d["relres_fp64"] = float(np.linalg.norm(b - A.to_scipy() @ xh) / np.linalg.norm(b))
+        d["x_err"] = solution_error(xh, x_true)
+        d["overflow"] = int(M.M.overflow)
+        out[name] = d
+    f16 = out["fp16"]
+    if f16["iters"] > 0 and f16["time_ms"] > 0:
+        star = f16["time_ms"] / f16["iters"] * gse_rep["iters"]
+        out["gse_star_eq7"] = {"time_ms": round(star, 3),
+                               "speedup_vs_fp64": round(fp64_rep["time_ms"] / star, 3),
+                               "speedup_gse_measured": round(fp64_rep["time_ms"] /
+                                                             gse_rep["time_ms"], 3)}
+    return out
+
+
 # ---------------------------------------------------------------- GMRES ---
 def leg_gmres(torch, G, seed, steps, warmup, N=1024):
     """Stepped GMRES(30) and FP64 GMRES(30) to 1e-10 on the 2-D upwind
@@ -447,11 +577,15 @@ def leg_gmres(torch, G, seed, steps, warmup, N=1024):
         for k in runs:
             runs[k].append(res[k]["time_ms"])
     med = {k: float(np.median(v)) for k, v in runs.items()}
+    errs = spmv_errors(A, M, C, np.ones(A.n_cols), dev, torch)
+    del M, C, ws
     return {"workload": f"convdiff2d_{N}^2_upwind_Pe10", "n_rows": A.n_rows, "nnz": A.nnz,
             "seed": seed, "restart": p.restart, "gse": res["gse"], "fp64": res["fp64"],
             "median_ms": {k: round(v, 3) for k, v in med.items()},
             "speedup": round(med["fp64"] / med["gse"], 3) if med["gse"] else None,
-            "spmv_error": spmv_errors(A, M, C, np.ones(A.n_cols), dev, torch)}
+            "spmv_error": errs,
+            "lowprec_gmres": leg_lowprec_solve(torch, G, A, b, x_true, G.GMRES, res["gse"],
+                                               res["fp64"])}
 
 
 def run_gmres(args, torch, G):
@@ -565,15 +699,23 @@ def leg_powerlaw(torch, G, seed, steps, warmup, reps, n_rows):
                        "bytes": int(nbytes), "GBps": round(nbytes / (mean * 1e-3) / 1e9, 1),
                        "frac_peak": round(nbytes / (mean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     med = {k: float(np.median([r["time_ms"] for r in v])) for k, v in cg_runs.items()}
+    errs = spmv_errors(A, M, C, np.ones(A.n_cols), dev, torch)
+    kname = kernel_name(M.A)
+    tile, rv = M.A.tile_nnz, M.A.rv_lanes
+    eta_scaled = [float(e) for e in MS.eta]
+    del M, C, MS, CS, ws
+    progress("powerlaw: FP16 / BF16 SpMV and the k sweep")
+    lowprec = leg_lowprec_spmv(torch, G, A, 1)
+    ksweep = leg_k_sweep(torch, G, A, 1)
     return {"workload": f"powerlaw_{A.n_rows}_zipf2_spd", "n_rows": A.n_rows, "nnz": A.nnz,
             "max_row": int(np.diff(A.indptr).max()), "seed": seed, "x": "ones",
-            "tile_nnz": M.A.tile_nnz, "rv_lanes": M.A.rv_lanes, "kernel": kernel_name(M.A),
-            "spmv": spmv, "spmv_error": spmv_errors(A, M, C, np.ones(A.n_cols), dev, torch),
+            "tile_nnz": tile, "rv_lanes": rv, "kernel": kname,
+            "spmv": spmv, "spmv_error": errs, "lowprec_spmv": lowprec, "k_sweep": ksweep,
             "cg": {"system": "D^-1/2 A D^-1/2 z = D^-1/2 b (unit diagonal); x_err on z",
                    "gse": cg_runs["gse"][-1], "fp64": cg_runs["fp64"][-1],
                    "median_ms": {k: round(v, 3) for k, v in med.items()},
                    "speedup": round(med["fp64"] / med["gse"], 3) if med["gse"] else None,
-                   "eta_scaled": [float(e) for e in MS.eta]},
+                   "eta_scaled": eta_scaled},
             "wall_s": wall}
 
 
@@ -745,6 +887,17 @@ def run_serving(args, torch, G):
     return out
 
 
+def json_safe(v):
+    """Non-finite floats as strings ("inf", "-inf", "nan"): the line stays strict JSON."""
+    if isinstance(v, float) and not np.isfinite(v):
+        return "nan" if np.isnan(v) else ("inf" if v > 0 else "-inf")
+    if isinstance(v, dict):
+        return {k: json_safe(x) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [json_safe(x) for x in v]
+    return v
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -765,7 +918,7 @@ def main():
         out = run_poisson(args, torch, G)
     else:
         out = run_spmv_cg(args, torch, G)
-    print(json.dumps(out))
+    print(json.dumps(json_safe(out), allow_nan=False))
 
 
 if __name__ == "__main__":
