@@ -600,7 +600,7 @@ def run_gmres(args, torch, G):
 
 
 # ------------------------------------------------------------ power law ---
-def leg_powerlaw(torch, G, seed, steps, warmup, reps, n_rows):
+def leg_powerlaw(torch, G, seed, steps, warmup, reps, n_rows, extras=True):
     """Power-law SPD matrix (Zipf(2) row lengths up to 10^4, values over six
     decades): SpMV per segment count after the autotuner picked the tile
     shape (the planes, 0.4-0.8 GB, exceed the Infinity Cache, so every launch
@@ -704,9 +704,11 @@ def leg_powerlaw(torch, G, seed, steps, warmup, reps, n_rows):
     tile, rv = M.A.tile_nnz, M.A.rv_lanes
     eta_scaled = [float(e) for e in MS.eta]
     del M, C, MS, CS, ws
-    progress("powerlaw: FP16 / BF16 SpMV and the k sweep")
-    lowprec = leg_lowprec_spmv(torch, G, A, 1)
-    ksweep = leg_k_sweep(torch, G, A, 1)
+    lowprec = ksweep = None
+    if extras:
+        progress("powerlaw: FP16 / BF16 SpMV and the k sweep")
+        lowprec = leg_lowprec_spmv(torch, G, A, 1)
+        ksweep = leg_k_sweep(torch, G, A, 1)
     return {"workload": f"powerlaw_{A.n_rows}_zipf2_spd", "n_rows": A.n_rows, "nnz": A.nnz,
             "max_row": int(np.diff(A.indptr).max()), "seed": seed, "x": "ones",
             "tile_nnz": tile, "rv_lanes": rv, "kernel": kname,
@@ -721,7 +723,8 @@ def leg_powerlaw(torch, G, seed, steps, warmup, reps, n_rows):
 
 def run_powerlaw(args, torch, G):
     t0 = time.perf_counter()
-    leg = leg_powerlaw(torch, G, args.seed, args.steps, args.warmup, args.reps, args.pl_rows)
+    leg = leg_powerlaw(torch, G, args.seed, args.steps, args.warmup, args.reps, args.pl_rows,
+                       extras=args.legs)
     wall = time.perf_counter() - t0
     spmv = leg["spmv"]
     out = base_record(args, "GSE-SpMV HBM GB/s (s=1), power-law SPD; CG time-to-1e-10 vs FP64 CSR",
