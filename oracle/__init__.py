@@ -315,7 +315,7 @@ PRESETS = {
 
 def make_params(tol=1e-10, max_iter=5000, restart=30, max_restarts=500, start_segments=1,
                 fixed_segments=0, preset="paper_cg", ndec_rule=0, floor_c=10.0,
-                switch_mode=0, orth=0, **over) -> Params:
+                switch_mode=2, orth=0, **over) -> Params:
     d = dict(PRESETS[preset])
     d.update(over)
     return Params(tol, max_iter, restart, max_restarts, start_segments, fixed_segments,

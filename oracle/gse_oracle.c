@@ -538,8 +538,14 @@ int or_cg(const or_matrix* A, const double* b, double* x, const or_params* p,
             if (nsw < 2) { rep->switch_iter[nsw] = it; rep->switch_trigger[nsw] = trig; }
             nsw += 1;
             s += 1;
+            double rho_old = rho;
             rho = residual(A, s, b, x, r);
-            if (p->switch_mode == 0) memcpy(pv, r, sizeof(double) * (size_t)n);
+            /* the direction is kept (switch_mode 1), restarted as p = r
+             * (switch_mode 0), or -- switch_mode 2 -- kept only while the
+             * replacement leaves the residual norm within a factor of two */
+            int reset_p = p->switch_mode == 0 ||
+                          (p->switch_mode == 2 && (rho > 4.0 * rho_old || 4.0 * rho < rho_old));
+            if (reset_p) memcpy(pv, r, sizeof(double) * (size_t)n);
             relres = sqrt(rho) / nb;
         }
     }

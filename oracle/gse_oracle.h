@@ -50,7 +50,8 @@ typedef struct {
     double reldec_limit;
     int32_t ndec_rule;       /* 0: compare nDec with ndec_limit, 1: with t/2 */
     double floor_c;          /* switch once relres <= floor_c*eta_s (0: off) */
-    int32_t switch_mode;     /* CG: 0 restart p=r, 1 keep p */
+    int32_t switch_mode;     /* CG after a switch: 0 restart p = r, 1 keep p, 2 keep p while
+                                the residual replacement keeps ||r|| within a factor 2 */
     int32_t orth;            /* GMRES: 0 MGS, 1 CGS2 */
 } or_params;
 
