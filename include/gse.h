@@ -21,8 +21,9 @@
  *   - Matrices are CSR with int32 row pointers (ascending, row_ptr[0] == 0),
  *     int32 column indices and FP64 values; the number of non-zeros must be
  *     below 2^31 - 2^16.  With k shared exponents the top b = ceil(log2 k)
- *     bits of each column word hold the slot index, so the number of columns
- *     is at most 2^(32 - b) (2^29 for the default k = 8, 2^26 for k = 64).
+ *     bits of each column word hold the slot index, so up to 2^(32 - b)
+ *     columns (2^29 for the default k = 8, 2^26 for k = 64); wider matrices
+ *     keep the index in the value word instead (GSE_IDX_VALUE).
  *   - "Planes" are per-non-zero arrays.  They must hold gse_pad(nnz) entries
  *     (nnz rounded up to a multiple of 16) and start on a 16-byte boundary;
  *     entries past nnz are never interpreted (the kernels load them as part of
@@ -52,6 +53,11 @@ typedef int32_t gse_status;
 
 #define GSE_MAX_EXP 64          /* shared exponents per matrix (up to a 6-bit index) */
 
+/* Where the slot index lives (gse_matrix.idx_layout). */
+#define GSE_IDX_AUTO 0          /* input: the column word unless n_cols needs its top bits */
+#define GSE_IDX_COLUMN 1        /* top bits of the column word */
+#define GSE_IDX_VALUE 2         /* top bits of the value word, below the sign */
+
 /* Number of entries a plane must hold for `nnz` non-zeros. */
 int64_t gse_pad(int64_t nnz);
 
@@ -70,6 +76,11 @@ int64_t gse_pad(int64_t nnz);
  * and the column word is  col | slot << (32 - b), where b = ceil(log2 k) is
  * the slot-index width for k shared exponents (Section III-B.1: the number
  * of shared exponents sets the index width; b = 0 stores the bare column).
+ * When the column field is too narrow for n_cols (or on request), the slot
+ * goes into the value instead (Section III-C.1, Algorithm 1's EI_bit): the
+ * word is  sign<<63 | slot<<(63-b) | F  with F = floor(|v| 2^(1086-b-SEM))
+ * on a 63 - b bit field, the head keeps 15 - b magnitude bits, the column
+ * word is the bare column, and W_s = 15 - b, 31 - b, 63 - b.
  * Reading s planes gives the value
  * +-(F >> (63 - W_s)) * 2^(SEM - 1023 - W_s), W_s = 15, 31, 63.
  *
@@ -87,6 +98,7 @@ typedef struct gse_matrix {
     int32_t num_exp;           /* k, 1..64 (Section IV-B sweeps 2..64 and picks 8) */
     int32_t num_used;          /* slots actually populated */
     int32_t idx_bits;          /* slot-index width b = ceil(log2 num_exp) (written by encode) */
+    int32_t idx_layout;        /* in: GSE_IDX_AUTO / COLUMN / VALUE; out: COLUMN or VALUE */
     int16_t sem[GSE_MAX_EXP];  /* shared exponents, biased + 1; 0 = unused */
     const int32_t* row_ptr;    /* device [n_rows + 1] */
     uint32_t* col_idx;         /* device plane */
@@ -137,7 +149,8 @@ gse_status gse_encode_workspace(int64_t nnz, int32_t n_rows, size_t* ws_bytes);
  *                       to reuse a table (Section III-B.1); NULL computes it.
  *                       A reused table that leaves a value without a larger
  *                       shared exponent gives GSE_ERR_RANGE.
- *   A                 : in: plane pointers and tile_row/tile_cap; out: every
+ *   A                 : in: plane pointers, tile_row/tile_cap and idx_layout
+ *                       (GSE_IDX_AUTO unless a layout is wanted); out: every
  *                       other field; the SpMV schedule is chosen as by
  *                       gse_plan(A, 1024, -1).
  *   ws, ws_bytes      : device workspace of gse_encode_workspace() bytes.
@@ -280,7 +293,9 @@ typedef struct gse_params {
     double reldec_limit;      /* Condition 2 threshold */
     int32_t ndec_rule;        /* 0: compare nDec with ndec_limit; 1: with t/2 */
     double floor_c;           /* floor trigger factor, 0 disables */
-    int32_t switch_mode;      /* CG after a switch: 0 p = r (default), 1 keep p */
+    int32_t switch_mode;      /* CG after a switch: 0 p = r, 1 keep p, 2 (default) keep p
+                                 unless the residual replacement changes ||r|| by more
+                                 than a factor of 2, then p = r */
     int32_t record_history;   /* kept for callers; the history is always recorded */
     int32_t launch_mode;      /* 0: iterations replayed from HIP graphs, 1: direct launches
                                  (CG on systems of at most 4096 rows whose rows hold at most 8

@@ -82,7 +82,7 @@ SpmvOperand operand_of(const gse_matrix* A) {
   o.nnz = (int32_t)A->nnz;
   o.rv_lanes = A->rv_lanes;
   o.max_row = A->max_row_nnz;
-  o.split = col_split(A->idx_bits);
+  o.split = col_split(A->idx_bits, A->idx_layout == GSE_IDX_VALUE);
   for (int i = 0; i < GSE_MAX_EXP; ++i) o.sem[i] = A->sem[i];
   return o;
 }
@@ -113,7 +113,8 @@ gse_status check_matrix(const gse_matrix* A) {
     return fail(GSE_ERR_ARG, "matrix has a NULL device buffer");
   if (A->n_rows < 0 || A->n_cols < 0 || A->nnz < 0) return fail(GSE_ERR_ARG, "negative size");
   if (A->nnz > kMaxNnz) return fail(GSE_ERR_RANGE, "nnz %lld exceeds the limit", (long long)A->nnz);
-  if (A->num_exp < 1 || A->num_exp > GSE_MAX_EXP || A->idx_bits != index_bits(A->num_exp))
+  if (A->num_exp < 1 || A->num_exp > GSE_MAX_EXP || A->idx_bits != index_bits(A->num_exp) ||
+      (A->idx_layout != GSE_IDX_COLUMN && A->idx_layout != GSE_IDX_VALUE))
     return fail(GSE_ERR_ARG, "matrix has no valid shared-exponent table (call gse_encode)");
   if (!valid_tile(A->tile_nnz) || A->n_tiles != n_tiles_for(A->nnz, A->tile_nnz) ||
       A->tile_cap < A->n_tiles + 2 || !valid_rv(A->rv_lanes))
@@ -147,7 +148,12 @@ gse_status encode_matrix(const int32_t* row_ptr, const int32_t* col, const doubl
   if (num_exp < 1 || num_exp > GSE_MAX_EXP) return fail(GSE_ERR_ARG, "num_exp must be 1..64");
   if (nnz > kMaxNnz) return fail(GSE_ERR_RANGE, "nnz %lld exceeds the limit", (long long)nnz);
   const int ib = index_bits(num_exp);
-  if ((int64_t)n_cols > (int64_t(1) << (32 - ib)))
+  const bool too_wide = (int64_t)n_cols > (int64_t(1) << (32 - ib));
+  int layout = A->idx_layout;
+  if (layout == GSE_IDX_AUTO) layout = too_wide ? GSE_IDX_VALUE : GSE_IDX_COLUMN;
+  if (layout != GSE_IDX_COLUMN && layout != GSE_IDX_VALUE)
+    return fail(GSE_ERR_ARG, "idx_layout must be GSE_IDX_AUTO, GSE_IDX_COLUMN or GSE_IDX_VALUE");
+  if (layout == GSE_IDX_COLUMN && too_wide)
     return fail(GSE_ERR_RANGE, "n_cols exceeds 2^%d (the column field left by a %d-bit slot index)",
                 32 - ib, ib);
   if (!A->col_idx || !A->head || !A->tail1 || !A->tail2 || !A->tile_row)
@@ -174,6 +180,7 @@ gse_status encode_matrix(const int32_t* row_ptr, const int32_t* col, const doubl
   A->nnz = nnz;
   A->num_exp = num_exp;
   A->idx_bits = ib;
+  A->idx_layout = layout;
   A->row_ptr = row_ptr;
   hipError_t e = launch_encode(row_ptr, col, val, n_rows, (int32_t)nnz, num_exp, sem_in, A, sc, st);
   if (e != hipSuccess) return hip_fail(e, "gse_encode launch");
@@ -337,7 +344,7 @@ gse_status gse_default_params(int32_t method, gse_params* p) {
   p->fixed_segments = 0;
   p->ndec_rule = 0;
   p->floor_c = 10.0;
-  p->switch_mode = 0;  // p = r after a switch: a kept direction can stall CG
+  p->switch_mode = 2;  // p kept after a switch unless the replacement moves ||r|| by 2x
   p->record_history = 0;
   if (method == GSE_CG) {  // Section IV-A (cap) and IV-D.1 (controller)
     p->max_iter = 5000;
@@ -469,7 +476,7 @@ static gse_status batch_descs(int32_t n_sys, const gse_system* sys, const gse_pa
       B.n_tiles = A->n_tiles;
       B.fmt = 1;
       B.max_row = A->max_row_nnz;
-      B.split = col_split(A->idx_bits);
+      B.split = col_split(A->idx_bits, A->idx_layout == GSE_IDX_VALUE);
       for (int k = 0; k < GSE_MAX_EXP; ++k) B.sem[k] = A->sem[k];
       d.eta = A->eta;
     } else {

@@ -61,6 +61,7 @@ enum Act : int32_t {
   kActReplaceP = 3,  // r = b - A_s x, rho, p = r
   kActCheck = 4,     // w = b - A_3 x, ||w||^2 in scratch[0]
   kActZeroX = 5,     // x = 0 (b = 0)
+  kActResetP = 6,    // p = r (after a replacement that moved ||r|| by more than 2x)
 };
 
 // One work list on the device: counts {tiles, chunks, slots} and entries.
@@ -92,6 +93,7 @@ struct SlotHost {
   double tol = 0.0;
   int max_iter = 0;
   int switch_mode = 1;
+  double rho_before = 0.0;  // r.r when the switch was decided (switch_mode 2)
   int final_status = 0;
   std::chrono::steady_clock::time_point t0;
   gse_report rep{};

@@ -47,6 +47,7 @@ enum Phase : int {
   kPhReplace,  // residual replacement after a switch or a failed check
   kPhFinal,    // stopped: final all-segment residual for the report
   kPhZero,     // b = 0: x = 0
+  kPhResetP,   // p = r after a replacement that moved ||r|| by more than 2x
   kPhDone,
 };
 enum Origin : int { kFromSwitch = 0, kFromCheck = 1 };
@@ -128,7 +129,7 @@ __device__ double tile_rows(const BatchSlot& B, int t, const double* __restrict_
   const int j0 = B.row_ptr[ra], j1 = B.row_ptr[rb];
   const int ext = j1 - j0;
   __syncthreads();  // the previous tile is done with LDS
-  build_scale<FMT>(B.sem, scale_tab);
+  build_scale<FMT>(B.sem, scale_tab, B.split.ei);
   __syncthreads();
   const DecodeCtx scale{scale_tab, B.split};
   double acc = 0.0;
@@ -387,13 +388,14 @@ __global__ __launch_bounds__(kWG) void k_b_act_finish(BatchView v) {
   }
 }
 
-// Actions: p = r (init, replacement with restart), x = 0 (b = 0).
+// Actions: p = r (init, replacement with restart, reset after a large
+// replacement), x = 0 (b = 0).
 __global__ __launch_bounds__(kWG) void k_b_copy(BatchView v) {
   const int n = v.list.counts[1];
   for (Walk w = walk_of(n); w.i < w.end; w.i += w.step) {
     const WorkItem it = v.list.chunks[w.i];
     const int a = v.act[it.slot];
-    if (a != kActInit && a != kActReplaceP && a != kActZeroX) continue;
+    if (a != kActInit && a != kActReplaceP && a != kActZeroX && a != kActResetP) continue;
     const BatchSlot& B = v.slot[it.slot];
     const int lo = it.idx * kChunk;
     const int hi = min(B.n_rows, lo + kChunk);
@@ -668,6 +670,7 @@ void BatchEngine::tol_met(int id) {
   S.s += 1;
   m.phase = kPhReplace;
   m.reset_p = m.switch_mode == 0;
+  m.rho_before = S.rho_p[S.it & 1];
   m.origin = kFromSwitch;
 }
 
@@ -712,6 +715,7 @@ gse_status BatchEngine::actions(std::vector<int>* done) {
       case kPhCheck: a = kActCheck; break;
       case kPhFinal: a = kActCheck; break;
       case kPhReplace: a = meta_[i].reset_p ? kActReplaceP : kActReplace; break;
+      case kPhResetP: a = kActResetP; break;
       case kPhZero: a = kActZeroX; break;
       default: break;
     }
@@ -769,7 +773,13 @@ gse_status BatchEngine::actions(std::vector<int>* done) {
         m.rep.relres_true = sqrt(S.scratch[0]) / S.nb;
         s = finish(id, m.final_status, done);
         break;
-      case kPhReplace: {
+      case kPhReplace:
+      case kPhResetP: {
+        if (m.phase == kPhReplace && m.origin == kFromSwitch && m.switch_mode == 2 &&
+            restart_direction(2, m.rho_before, S.rho)) {
+          m.phase = kPhResetP;  // one more round: p = r
+          break;
+        }
         S.relres = sqrt(S.rho) / S.nb;
         if (m.origin == kFromCheck) {
           if (S.relres <= m.tol || S.it >= m.max_iter) {
@@ -848,6 +858,7 @@ gse_status BatchEngine::epoch() {
       S.s += 1;
       m.phase = kPhReplace;
       m.reset_p = m.switch_mode == 0;
+      m.rho_before = S.rho_p[S.it & 1];
       m.origin = kFromSwitch;
     } else {  // cap
       m.final_status = GSE_NOT_CONVERGED;

@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void k_topk(EncodeScratch* sc, int num_exp, Se
 // (the planes are padded, so the tail group writes zeros past nnz).
 __global__ __launch_bounds__(256) void k_encode(const double* __restrict__ val,
                                                 const int32_t* __restrict__ col, int nnz,
-                                                EncodeScratch* sc, int idx_bits,
+                                                EncodeScratch* sc, int idx_bits, int in_value,
                                                 uint32_t* __restrict__ col_idx,
                                                 uint16_t* __restrict__ head,
                                                 uint16_t* __restrict__ tail1,
@@ -169,7 +169,10 @@ __global__ __launch_bounds__(256) void k_encode(const double* __restrict__ val,
   if (threadIdx.x < GSE_MAX_EXP) sem_s[threadIdx.x] = sc->sem[threadIdx.x];
   for (int e = threadIdx.x; e < 2048; e += blockDim.x) slot_s[e] = sc->slot_of[e];
   __syncthreads();
+  // the slot goes to the top of the column word, or (in_value) below the
+  // sign of the value word, whose magnitude field then loses idx_bits bits
   const uint32_t shift = idx_bits > 0 ? 32u - (uint32_t)idx_bits : 0u;
+  const int ei = in_value ? idx_bits : 0;
   const int n_groups = (nnz + 7) >> 3;
   const int stride = gridDim.x * blockDim.x;
   int bad = 0;
@@ -213,11 +216,17 @@ __global__ __launch_bounds__(256) void k_encode(const double* __restrict__ val,
           const int best = sem_s[slot];
           const uint64_t frac = u & ((uint64_t(1) << 52) - 1);
           const uint64_t sig = e ? ((uint64_t(1) << 52) | frac) : frac;
-          const int sh = 11 - (best - (e ? e : 1));
+          const int sh = 11 - ei - (best - (e ? e : 1));
           F = (sh >= 0) ? (sig << sh) : ((-sh >= 64) ? 0 : (sig >> (-sh)));
         }
-        c = (uint32_t)cv[k] | (idx_bits > 0 ? ((uint32_t)slot << shift) : 0u);
-        h16 = (uint32_t)((u >> 63) << 15) | (uint32_t)(F >> 48);
+        if (in_value) {
+          c = (uint32_t)cv[k];
+          h16 = (uint32_t)((u >> 63) << 15) | ((uint32_t)slot << (15 - idx_bits)) |
+                (uint32_t)(F >> 48);
+        } else {
+          c = (uint32_t)cv[k] | (idx_bits > 0 ? ((uint32_t)slot << shift) : 0u);
+          h16 = (uint32_t)((u >> 63) << 15) | (uint32_t)(F >> 48);
+        }
         t116 = (uint32_t)((F >> 32) & 0xFFFFu);
         t232 = (uint32_t)(F & 0xFFFFFFFFu);
       }
@@ -241,10 +250,11 @@ __global__ __launch_bounds__(256) void k_encode(const double* __restrict__ val,
 // Value read with s segments (exact; same decode as the SpMV operators).
 __device__ __forceinline__ double value_s(uint32_t c, uint32_t h, uint32_t t1, uint32_t t2,
                                           const int* S, const ColSplit& cs, int s) {
-  const int W = (s == 1) ? 15 : (s == 2) ? 31 : 63;
-  const int sem = S[(c >> cs.shift) & cs.slot_mask];
-  const uint64_t F63 = ((uint64_t)(h & 0x7FFFu) << 48) | ((uint64_t)t1 << 32) | (uint64_t)t2;
-  const uint64_t F = F63 >> (63 - W);
+  const int fb = 63 - cs.ei;  // bits of the magnitude field
+  const int W = fb - ((s == 1) ? 48 : (s == 2) ? 32 : 0);
+  const int sem = S[((c >> cs.shift) & cs.slot_mask) | ((h >> cs.hshift) & cs.hmask)];
+  const uint64_t Ff = ((uint64_t)(h & cs.mag_mask) << 48) | ((uint64_t)t1 << 32) | (uint64_t)t2;
+  const uint64_t F = Ff >> (fb - W);
   const double sc = bits_to_double((uint64_t)(sem - W) << 52);
   const double mag = (double)F * sc;  // F <= 53 significant bits: exact
   return (h >> 15) ? -mag : mag;
@@ -368,12 +378,13 @@ hipError_t launch_encode(const int32_t* row_ptr, const int32_t* col, const doubl
   const int groups = (nnz + 7) / 8;
   int eb = (groups + 255) / 256;
   eb = eb < 1 ? 1 : (eb > 16384 ? 16384 : eb);
+  const bool in_value = A->idx_layout == GSE_IDX_VALUE;
   hipLaunchKernelGGL(k_encode, dim3(eb), dim3(256), 0, st, val, col, nnz, sc, A->idx_bits,
-                     A->col_idx, A->head, A->tail1, A->tail2);
+                     in_value ? 1 : 0, A->col_idx, A->head, A->tail1, A->tail2);
   int rbk = (n_rows + 31) / 32;
   rbk = rbk < 1 ? 1 : (rbk > 4096 ? 4096 : rbk);
   hipLaunchKernelGGL(k_eta, dim3(rbk), dim3(256), 0, st, row_ptr, n_rows, val, A->col_idx, A->head,
-                     A->tail1, A->tail2, sc, col_split(A->idx_bits));
+                     A->tail1, A->tail2, sc, col_split(A->idx_bits, in_value));
   return hipGetLastError();
 }
 

@@ -108,20 +108,42 @@ __host__ __device__ inline int index_bits(int num_exp) {
   return b;
 }
 
-// How a column word splits: column = word & col_mask, slot = (word >> shift)
-// & slot_mask (shift 0 and slot_mask 0 for b = 0; col_mask all ones for the
-// FP64 CSR operand, whose words are bare columns).
+// Where a non-zero's column and slot are: column = word & col_mask; slot =
+// ((word >> shift) & slot_mask) | ((head >> hshift) & hmask) -- one of the
+// two masks is zero: the slot is in the top of the column word (shift
+// 32 - b), or in the head below the sign (hshift 15 - b, Algorithm 1's
+// EI_bit).  mag_mask keeps the head's magnitude bits (15 - ei of them) and
+// ei shortens W_s.  b = 0: no index at all; the FP64 CSR operand's words
+// are bare columns.
 struct ColSplit {
   uint32_t shift;
   uint32_t slot_mask;
   uint32_t col_mask;
+  uint32_t hshift;
+  uint32_t hmask;
+  uint32_t mag_mask;
+  int32_t ei;
 };
 
-__host__ __device__ inline ColSplit col_split(int idx_bits) {
+__host__ __device__ inline ColSplit col_split(int idx_bits, bool in_value = false) {
   ColSplit c;
-  c.shift = idx_bits > 0 ? 32u - (uint32_t)idx_bits : 0u;
-  c.slot_mask = (1u << idx_bits) - 1u;
-  c.col_mask = 0xFFFFFFFFu >> idx_bits;
+  if (in_value) {
+    c.shift = 0u;
+    c.slot_mask = 0u;
+    c.col_mask = 0xFFFFFFFFu;
+    c.hshift = 15u - (uint32_t)idx_bits;
+    c.hmask = (1u << idx_bits) - 1u;
+    c.mag_mask = 0x7FFFu >> idx_bits;
+    c.ei = idx_bits;
+  } else {
+    c.shift = idx_bits > 0 ? 32u - (uint32_t)idx_bits : 0u;
+    c.slot_mask = (1u << idx_bits) - 1u;
+    c.col_mask = 0xFFFFFFFFu >> idx_bits;
+    c.hshift = 0u;
+    c.hmask = 0u;
+    c.mag_mask = 0x7FFFu;
+    c.ei = 0;
+  }
   return c;
 }
 

@@ -160,7 +160,7 @@ gse_status place(gse_solver* s, Ticket& t, gse::BatchSlot* B, const double** eta
     B->n_tiles = A.n_tiles;
     B->fmt = 1;
     B->max_row = A.max_row_nnz;
-    B->split = gse::col_split(A.idx_bits);
+    B->split = gse::col_split(A.idx_bits, A.idx_layout == GSE_IDX_VALUE);
     for (int k = 0; k < GSE_MAX_EXP; ++k) B->sem[k] = A.sem[k];
     *eta = t.A.eta;
   } else {
@@ -393,9 +393,7 @@ gse_status check_request(const gse_request* rq) {
     return gse::fail(GSE_ERR_ARG, "NULL request array");
   if (rq->format == GSE_FMT_GSE && (rq->num_exp < 1 || rq->num_exp > GSE_MAX_EXP))
     return gse::fail(GSE_ERR_ARG, "num_exp must be 1..64");
-  const int ib = rq->format == GSE_FMT_GSE ? gse::index_bits(rq->num_exp) : 0;
-  if ((int64_t)rq->n_rows > (int64_t(1) << (32 - ib)))
-    return gse::fail(GSE_ERR_RANGE, "n exceeds 2^%d", 32 - ib);
+  // (a system wider than the column field keeps its slot index in the value)
   const gse_params& p = rq->params;
   if (!(p.tol > 0.0) || p.max_iter < 0) return gse::fail(GSE_ERR_ARG, "tol must be > 0, max_iter >= 0");
   if (p.start_segments < 1 || p.start_segments > 3 || p.fixed_segments < 0 || p.fixed_segments > 3)

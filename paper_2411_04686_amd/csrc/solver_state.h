@@ -113,6 +113,16 @@ __device__ inline void controller(SolverState* S, const double* hist, double* re
   }
 }
 
+// CG direction after a residual replacement at a switch: restart p = r
+// (mode 0), keep p (mode 1), or keep it only while the replacement leaves
+// the residual norm within a factor of two (mode 2; rho = r.r before and
+// after).  A kept direction serves when the operators differ by little at
+// the residual's scale; after a large jump (the tolerance escalation, a warm
+// start) it can stall CG.
+__host__ __device__ inline bool restart_direction(int mode, double rho_old, double rho_new) {
+  return mode == 0 || (mode == 2 && (rho_new > 4.0 * rho_old || 4.0 * rho_new < rho_old));
+}
+
 // ------------------------------------------------------------- streams --
 // A non-blocking stream of this thread on the current device: solves run on
 // it (it can be captured into a HIP graph, the legacy null stream cannot)

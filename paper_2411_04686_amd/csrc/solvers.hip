@@ -400,8 +400,10 @@ __global__ __launch_bounds__(kSmallThreads) void k_cg_small(SolverState* Sg, Spm
 }
 
 bool cg_small_path(const SpmvOperand& op) {
-  // (the eight slot exponents held in scalar words cover index widths <= 3)
-  return op.n_rows <= kSmallRows && op.max_row <= kSmallRow && op.split.slot_mask <= 7u;
+  // (the eight slot exponents held in scalar words cover index widths <= 3
+  // in the column word)
+  return op.n_rows <= kSmallRows && op.max_row <= kSmallRow && op.split.slot_mask <= 7u &&
+         op.split.hmask == 0u;
 }
 
 template <int RPT, int L>
@@ -754,10 +756,16 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
       }
       ++nsw;
       h.s += 1;
+      const double rho_old = h.rho_p[h.it & 1];
       SolverState t;
       e = restart(h.s, p->switch_mode == 0);
       if (e == hipSuccess) e = read_state(w, &t, st);
       if (e != hipSuccess) return hip_fail(e, "cg switch");
+      if (p->switch_mode == 2 && restart_direction(2, rho_old, t.rho_p[h.it & 1])) {
+        hipLaunchKernelGGL(k_copy, dim3(vb), dim3(kWG), 0, st, w.p, w.r, n);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "cg switch");
+      }
       h.rho_p[h.it & 1] = t.rho_p[h.it & 1];
       h.rho = h.rho_p[h.it & 1];
       h.relres = sqrt(h.rho) / h.nb;

@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kWG) void k_spmv(SpmvOperand A, const double* __res
   if (ep.gate && *ep.gate) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  build_scale<FMT>(A.sem, scale_tab);
+  build_scale<FMT>(A.sem, scale_tab, A.split.ei);
   const DecodeCtx scale{scale_tab, A.split};
   double acc = 0.0;  // this thread's share of the epilogue dot
 
@@ -471,7 +471,7 @@ __global__ __launch_bounds__(kWG) void k_spmv_short(SpmvOperand A, const double*
 
   if (ep.gate && *ep.gate) return;
   const int tid = threadIdx.x;
-  build_scale<FMT>(A.sem, scale_tab);
+  build_scale<FMT>(A.sem, scale_tab, A.split.ei);
   const DecodeCtx scale{scale_tab, A.split};
   double acc = 0.0;
 
@@ -763,7 +763,7 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_ring(SpmvOperand A,
   if (ep.gate && *ep.gate) return;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  build_scale<FMT>(A.sem, scale_tab);
+  build_scale<FMT>(A.sem, scale_tab, A.split.ei);
   const DecodeCtx scale{scale_tab, A.split};
   const int pad = (A.nnz + 15) & ~15;
   TileWalk walk(A.n_tiles);
@@ -885,7 +885,7 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_rows(SpmvOperand A,
   if (ep.gate && *ep.gate) return;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  build_scale<FMT>(A.sem, scale_tab);
+  build_scale<FMT>(A.sem, scale_tab, A.split.ei);
   const DecodeCtx scale{scale_tab, A.split};
   const int pad = (A.nnz + 15) & ~15;
   const int n_rt = (A.n_rows + kRowTile - 1) / kRowTile;
@@ -1103,7 +1103,7 @@ __global__ __launch_bounds__(kWG) void k_spmv_rv(SpmvOperand A, const double* __
   __shared__ double red[kWaves];
 
   if (ep.gate && *ep.gate) return;
-  build_scale<FMT>(A.sem, scale_tab);
+  build_scale<FMT>(A.sem, scale_tab, A.split.ei);
   const DecodeCtx scale{scale_tab, A.split};
   __syncthreads();
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;

@@ -34,7 +34,7 @@ class GseError(RuntimeError):
 class gse_matrix(C.Structure):
     _fields_ = [("n_rows", C.c_int32), ("n_cols", C.c_int32), ("nnz", C.c_int64),
                 ("num_exp", C.c_int32), ("num_used", C.c_int32), ("idx_bits", C.c_int32),
-                ("sem", C.c_int16 * 64),
+                ("idx_layout", C.c_int32), ("sem", C.c_int16 * 64),
                 ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("head", C.c_void_p),
                 ("tail1", C.c_void_p), ("tail2", C.c_void_p), ("tile_row", C.c_void_p),
                 ("tile_cap", C.c_int32), ("tile_nnz", C.c_int32), ("n_tiles", C.c_int32),
@@ -241,6 +241,7 @@ def gse_encode_static_scratch_bytes() -> int:
 
 
 LP_FP16, LP_BF16 = 1, 2
+IDX_AUTO, IDX_COLUMN, IDX_VALUE = 0, 1, 2
 
 
 def gse_lp_workspace() -> int:
@@ -474,7 +475,7 @@ class GseMatrix:
     """Device planes of one encoded matrix plus its ``gse_matrix`` record."""
 
     def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n_cols: int,
-                 num_exp: int = 8, sem_in=None, stream=None):
+                 num_exp: int = 8, sem_in=None, stream=None, idx_layout: int = IDX_AUTO):
         dev = row_ptr.device
         n_rows = row_ptr.numel() - 1
         nnz = val.numel()
@@ -494,6 +495,7 @@ class GseMatrix:
         A.tail2 = self.tail2.data_ptr()
         A.tile_row = self.tile_row.data_ptr()
         A.tile_cap = cap
+        A.idx_layout = idx_layout
         self.A = A
         gse_encode(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, sem_in, A, self.ws, stream)
 

@@ -90,12 +90,18 @@ def test_argument_errors_without_launch(lib):
     assert lib.gse_encode(C.c_void_p(16), None, None, 0, 0, C.c_int64(0), 8, None, C.byref(A),
                           None, C.c_size_t(0), None) == -1
     # num_exp out of range
-    assert lib.gse_encode(C.c_void_p(16), None, None, 0, 0, C.c_int64(0), 9, None, C.byref(A),
+    assert lib.gse_encode(C.c_void_p(16), None, None, 0, 0, C.c_int64(0), 65, None, C.byref(A),
                           None, C.c_size_t(0), None) == -1
-    # too many columns for a 29-bit column field
+    # too many columns for a 29-bit column field when the index must stay there
+    A.idx_layout = 1  # GSE_IDX_COLUMN
     assert lib.gse_encode(C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), 1, 2**29 + 1,
                           C.c_int64(1), 8, None, C.byref(A), None, C.c_size_t(0), None) == -3
     assert b"2^29" in lib.gse_last_error()
+    # by default such a matrix keeps the index in the value: no range error
+    # (it fails only later, on the planes this test never set)
+    A.idx_layout = 0  # GSE_IDX_AUTO
+    assert lib.gse_encode(C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), 1, 2**29 + 1,
+                          C.c_int64(1), 8, None, C.byref(A), None, C.c_size_t(0), None) == -1
     # schedule missing -> spmv refuses
     A.row_ptr = A.col_idx = A.head = A.tail1 = A.tail2 = A.tile_row = 256
     assert lib.gse_spmv(C.byref(A), 1, C.c_void_p(256), C.c_void_p(256), None) == -1
@@ -104,14 +110,16 @@ def test_argument_errors_without_launch(lib):
 
 
 def test_column_limit_follows_the_index_width(lib):
-    """k = 64 leaves 26 column bits: a wider matrix is refused on the host
-    before any device work (the device pointers are never touched)."""
+    """k = 64 leaves 26 column bits: with the index forced into the column
+    word a wider matrix is refused on the host before any device work (the
+    device pointers are never touched)."""
     import sys
     sys.path.insert(0, ROOT)
     from paper_2411_04686_amd import gse as G
     L = G.lib()
     A = G.gse_matrix()
     fake = C.c_void_p(256)
+    A.idx_layout = 1  # the index forced into the column word
     for k, n_cols, want in ((64, (1 << 26) + 1, -3), (16, (1 << 28) + 1, -3), (0, 10, -1),
                             (65, 10, -1)):
         st = L.gse_encode(fake, fake, fake, 1, n_cols, 1, k, None, C.byref(A), fake, 1 << 20,

@@ -75,3 +75,11 @@ def test_cpu_baseline_threads_keep_the_sequential_result():
     r = b.cpu_baseline(diffusion3d(12, 0), 0.2)
     assert r["kind"] == "oracle" and r["cores"] >= 1 and r["value"] > 0
     assert "sequential result: True" in r["sample"]
+
+
+def test_bench_line_stays_strict_json():
+    import json
+    b = load_bench()
+    v = b.json_safe({"a": float("inf"), "b": [1.0, float("nan")], "c": {"d": -float("inf")}})
+    assert json.loads(json.dumps(v, allow_nan=False)) == {"a": "inf", "b": [1.0, "nan"],
+                                                          "c": {"d": "-inf"}}

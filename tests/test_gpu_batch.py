@@ -73,7 +73,7 @@ def oracle_solve(s: Sys):
     A = s.A
     if s.kind == "gse":
         enc = O.encode(A.indptr, A.indices, A.data, A.n_cols)
-        prm = O.make_params(tol=1e-10, max_iter=5000, preset="paper_cg", switch_mode=0, orth=1)
+        prm = O.make_params(tol=1e-10, max_iter=5000, preset="paper_cg", switch_mode=2, orth=1)
         return O.cg(A.indptr, s.b_host, prm, A.indices, A.data, enc)
     prm = O.make_params(tol=1e-10, max_iter=5000, preset="paper_cg", fixed_segments=-1, orth=1)
     return O.cg(A.indptr, s.b_host, prm, A.indices, A.data)

@@ -116,6 +116,31 @@ def test_single_system_decisions_match_oracle(name):
     assert_results(rep, x, ref, A, b, name, exact_trajectory=case["method"] == "gmres")
 
 
+@pytest.mark.parametrize("name", ["cg_multi_warm", "cg_small_warm", "cg_multi_tol_chain"])
+def test_adaptive_direction_matches_oracle(name):
+    """switch_mode 2 (the default): after the warm start's or the tolerance
+    escalation's large replacement the direction restarts, at floor
+    switches it is kept -- on the GPU as in the oracle."""
+    case = dict(CASES[name])
+    A, b, enc, x0 = build(case)
+    ref = run_oracle(case, A, b, enc, x0, switch_mode=2)
+    method, p = gpu_params(case)
+    p.switch_mode = 2
+    rp = torch.from_numpy(A.indptr).to(DEV)
+    ci = torch.from_numpy(A.indices).to(DEV)
+    va = torch.from_numpy(A.data).to(DEV)
+    M = G.GseMatrix(rp, ci, va, A.n_cols)
+    ws = torch.empty(G.gse_solver_workspace(method, A.n_rows, A.nnz, p.restart, p.max_iter),
+                     dtype=torch.uint8, device=DEV)
+    x = torch.zeros(A.n_rows, dtype=torch.float64, device=DEV) if x0 is None else \
+        torch.from_numpy(np.ascontiguousarray(x0)).to(DEV)
+    rep = G.gse_cg(M.A, torch.from_numpy(b).to(DEV), x, p, ws)
+    torch.cuda.synchronize()
+    hist, seg = G.gse_solve_history(ws, rep.iters + 1)
+    assert_decisions(rep, hist, seg, list(M.eta), oracle_params(case), 0, name)
+    assert_results(rep, x.cpu().numpy(), ref, A, b, name, exact_trajectory=False)
+
+
 @pytest.mark.parametrize("name", ["cg_multi_c1", "cg_multi_warm", "gmres_c2"])
 def test_direct_launches_take_the_same_decisions(name):
     case = CASES[name]
@@ -139,20 +164,24 @@ def _batch_systems(warm=False):
 
 
 def _batch_params(ctrl):
-    return O.make_params(tol=1e-10, max_iter=5000, preset="paper_cg", switch_mode=0, orth=1, **ctrl)
+    ctrl = dict(ctrl)
+    mode = ctrl.pop("switch_mode", 0)
+    return O.make_params(tol=1e-10, max_iter=5000, preset="paper_cg", switch_mode=mode, orth=1,
+                         **ctrl)
 
 
 def _batch_oracle(A, b, enc, x0, ctrl):
     return O.cg(A.indptr, b, _batch_params(ctrl), A.indices, A.data, enc, x0=x0)
 
 
+@pytest.mark.parametrize("mode", [0, 2], ids=["restart", "adaptive"])
 @pytest.mark.parametrize("warm", [False, True], ids=["short_grid", "warm_start"])
-def test_batch_decisions_match_oracle(warm):
+def test_batch_decisions_match_oracle(warm, mode):
     ctrl = {} if warm else BATCH_CTRL
     systems = _batch_systems(warm)
     p = G.gse_default_params(G.CG)
     p.max_iter = 5000
-    p.switch_mode = 0
+    p.switch_mode = mode
     for k, v in ctrl.items():
         setattr(p, k, v)
     keep, triples = [], []
@@ -172,7 +201,7 @@ def test_batch_decisions_match_oracle(warm):
     for i, ((name, A, b, enc, x0), rep, (M, _, xd)) in enumerate(zip(systems, reps, keep)):
         hist, seg = G.gse_batch_history(ws, i, rep.iters + 1)
         assert_decisions(rep, hist, seg, list(M.eta), _batch_params(ctrl), 0, name)
-        ref = _batch_oracle(A, b, enc, x0, ctrl)
+        ref = _batch_oracle(A, b, enc, x0, dict(ctrl, switch_mode=mode))
         assert_results(rep, xd.cpu().numpy(), ref, A, b, name, exact_trajectory=False)
 
 

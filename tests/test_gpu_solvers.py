@@ -123,7 +123,7 @@ def test_spmv_products_identical_across_formats_on_exact_stencil():
         assert torch.equal(ys, y64)
 
 
-@pytest.mark.parametrize("switch_mode", [0, 1])
+@pytest.mark.parametrize("switch_mode", [0, 1, 2])
 def test_stepped_cg_variable_coefficients(switch_mode):
     A = diffusion3d(20, 3)
     x_true, b = rhs_from_solution(A, 3)
@@ -390,3 +390,34 @@ def test_batch_with_other_table_sizes():
         assert true_relres(A, xs, b) <= 1e-10
         assert np.linalg.norm(xs - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
         assert abs(rep.iters - ref.iters) <= max(3, ref.iters // 10)
+
+
+def test_stepped_cg_with_the_index_in_the_value():
+    """Stepped CG (multi-launch; the one-workgroup loop keeps the column
+    layout) and batched CG on encodings with the slot in the value word,
+    against the oracle's CG on the same layout."""
+    A = diffusion2d(40, 12)
+    _, b = rhs_from_solution(A, 12)
+    rp, ci, va = to_dev(A)
+    M = G.GseMatrix(rp, ci, va, A.n_cols, idx_layout=G.IDX_VALUE)
+    p = G.gse_default_params(G.CG)
+    p.switch_mode = 0
+    ws = torch.empty(G.gse_solver_workspace(G.CG, A.n_rows, A.nnz, 30, p.max_iter),
+                     dtype=torch.uint8, device=DEV)
+    x = torch.zeros(A.n_rows, dtype=torch.float64, device=DEV)
+    bd = torch.from_numpy(b).to(DEV)
+    rep = G.gse_cg(M.A, bd, x, p, ws)
+    enc = O.encode(A.indptr, A.indices, A.data, A.n_cols, layout=1)
+    ref = O.cg(A.indptr, b, O.make_params(tol=1e-10, max_iter=5000, preset="paper_cg",
+                                          switch_mode=0, orth=1), A.indices, A.data, enc)
+    xs = x.cpu().numpy()
+    assert rep.status == G.OK and ref.status == O.OK
+    assert true_relres(A, xs, b) <= 1e-10
+    assert np.linalg.norm(xs - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+    assert abs(rep.iters - ref.iters) <= max(3, ref.iters // 10)
+    xb = torch.zeros(A.n_rows, dtype=torch.float64, device=DEV)
+    wsb = torch.empty(G.gse_batch_workspace([(M.A, bd, xb)], p), dtype=torch.uint8, device=DEV)
+    rb, = G.gse_batch_cg([(M.A, bd, xb)], p, wsb)
+    torch.cuda.synchronize()
+    assert rb.status == G.OK
+    assert np.linalg.norm(xb.cpu().numpy() - ref.x) <= 1e-6 * np.linalg.norm(ref.x)

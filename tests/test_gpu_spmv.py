@@ -314,3 +314,72 @@ def test_index_width_follows_the_table_size(name, k):
             scale = np.zeros(A.n_rows)
             np.add.at(scale, rows, np.abs(dec[s] * x[A.indices]))
             _check_close(yd.cpu().numpy(), ref, scale)
+
+
+@pytest.mark.parametrize("k", [2, 8, 16, 64])
+@pytest.mark.parametrize("name", ["powerlaw_20k", "random_empty_long", "diffusion3d_24"])
+def test_index_in_value_layout(name, k):
+    """The slot index in the value word (Algorithm 1's EI_bit, the fallback
+    of Section III-C.1): planes bit-exact against the oracle's layout 1, and
+    SpMV at every segment count (W_s = 15 - b, 31 - b, 63 - b) on the default
+    schedule, the general tiles and the row-vector schedule."""
+    A = cases()[name]()
+    enc = O.encode(A.indptr, A.indices, A.data, A.n_cols, num_exp=k, layout=1)
+    rp, ci, va = to_dev(A)
+    M = G.GseMatrix(rp, ci, va, A.n_cols, num_exp=k, idx_layout=G.IDX_VALUE)
+    assert M.A.idx_layout == G.IDX_VALUE and enc.layout == 1
+    assert M.sem == [int(s) for s in enc.sem]
+    for got, want in zip(M.planes(), (enc.col_idx, enc.head, enc.tail1, enc.tail2)):
+        assert np.array_equal(got, want), (name, k)
+    for s in range(3):
+        assert M.eta[s] == pytest.approx(enc.eta[s], rel=1e-12, abs=1e-300)
+    x = np.random.default_rng(k + 1).uniform(-1, 1, A.n_cols)
+    xd = torch.from_numpy(x).to(DEV)
+    yd = torch.empty(A.n_rows, dtype=torch.float64, device=DEV)
+    dec = {s: O.decode(enc, s) for s in (1, 2, 3)}
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.indptr))
+    for sched in ((1024, -1), (2048, 0), (2048, 8)):
+        M.plan(*sched)
+        for s in (1, 2, 3):
+            M.spmv(s, xd, yd)
+            torch.cuda.synchronize()
+            ref = O.gse_spmv(A.indptr, enc, s, x)
+            scale = np.zeros(A.n_rows)
+            np.add.at(scale, rows, np.abs(dec[s] * x[A.indices]))
+            _check_close(yd.cpu().numpy(), ref, scale)
+
+
+def test_wide_matrix_moves_the_index_into_the_value():
+    """k = 64 leaves 26 column bits (67,108,864 columns); a matrix with more
+    columns is encoded with the index in the value by default, and its SpMV
+    (x of 537 MB) matches the oracle on every row."""
+    import scipy.sparse as sp
+    n_cols = (1 << 26) + 12345
+    rng = np.random.default_rng(26)
+    n_rows, per = 3000, 7
+    cols = np.sort(rng.choice(n_cols, size=(n_rows, per), replace=True), axis=1)
+    cols[:, -1] = n_cols - 1 - rng.integers(0, 100, n_rows)  # the far end of x
+    cols = np.sort(cols, axis=1)
+    vals = rng.standard_normal((n_rows, per)) * np.exp2(rng.integers(-30, 30, (n_rows, per)))
+    M = sp.csr_matrix((vals.ravel(), cols.ravel(), np.arange(0, n_rows * per + 1, per)),
+                      shape=(n_rows, n_cols))
+    M.sum_duplicates()
+    A = CSR.from_scipy(M)
+    enc = O.encode(A.indptr, A.indices, A.data, A.n_cols, num_exp=64)
+    assert enc.layout == 1
+    rp, ci, va = to_dev(A)
+    G_M = G.GseMatrix(rp, ci, va, A.n_cols, num_exp=64)
+    assert G_M.A.idx_layout == G.IDX_VALUE
+    for got, want in zip(G_M.planes(), (enc.col_idx, enc.head, enc.tail1, enc.tail2)):
+        assert np.array_equal(got, want)
+    x = torch.linspace(-1.0, 1.0, n_cols, dtype=torch.float64, device=DEV)
+    y = torch.empty(n_rows, dtype=torch.float64, device=DEV)
+    xh = x.cpu().numpy()
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.indptr))
+    for s in (1, 3):
+        G_M.spmv(s, x, y)
+        torch.cuda.synchronize()
+        ref = O.gse_spmv(A.indptr, enc, s, xh)
+        scale = np.zeros(A.n_rows)  # rows sum values over 60 binades: cancellation
+        np.add.at(scale, rows, np.abs(O.decode(enc, s) * xh[A.indices]))
+        _check_close(y.cpu().numpy(), ref, scale)
