@@ -46,7 +46,8 @@ class Matrix(C.Structure):
                 ("val", C.c_void_p), ("col_idx", C.c_void_p), ("head", C.c_void_p),
                 ("tail1", C.c_void_p), ("tail2", C.c_void_p), ("sem64", C.c_void_p),
                 ("eta3", C.c_void_p), ("idx_bits", C.c_int32), ("layout", C.c_int32),
-                ("lp_val", C.c_void_p), ("lp_fmt", C.c_int32)]
+                ("lp_val", C.c_void_p), ("lp_fmt", C.c_int32), ("block_sem", C.c_void_p),
+                ("block_rows", C.c_int32)]
 
 
 def lib():
@@ -70,6 +71,12 @@ def lib():
         L.or_decode_one.restype = C.c_double
         L.or_decode_one.argtypes = [C.c_uint32, C.c_uint16, C.c_uint16, C.c_uint32, P, C.c_int,
                                     C.c_int, C.c_int]
+        L.or_encode_blocks.restype = C.c_int
+        L.or_encode_blocks.argtypes = [P, P, P, C.c_int32, C.c_int32, C.c_int64, C.c_int, C.c_int,
+                                       C.c_int32, P, P, P, P, P, P, P, P, P]
+        L.or_gse_spmv_blocks.restype = None
+        L.or_gse_spmv_blocks.argtypes = [C.c_int32, P, P, P, P, P, P, C.c_int32, C.c_int, C.c_int,
+                                         C.c_int, P, P]
         L.or_decode.restype = None
         L.or_decode.argtypes = [P, P, P, P, C.c_int64, P, C.c_int, C.c_int, C.c_int, P]
         L.or_lp_round.restype = C.c_uint16
@@ -222,6 +229,69 @@ def encode(indptr, indices, data, n_cols: int, num_exp: int = 8, sem_in=None,
                    ef.value, index_bits(num_exp), lo.value)
 
 
+@dataclasses.dataclass
+class EncodedBlocks(Encoded):
+    """Planes with one table per block of ``block_rows`` rows (Section
+    III-B.1, sampling); ``block_sem[b]`` is block b's table (64 entries)."""
+    block_sem: np.ndarray = None   # int16[n_blocks, 64]
+    block_rows: int = 0
+
+    def table_of_rows(self, indptr):
+        """The table each non-zero is read with: int16[nnz, 64]."""
+        n_rows = np.asarray(indptr).size - 1
+        blk = np.arange(n_rows) // self.block_rows
+        return self.block_sem[np.repeat(blk, np.diff(np.asarray(indptr)))]
+
+
+def encode_blocks(indptr, indices, data, n_cols: int, num_exp: int = 8, block_rows: int = 256,
+                  sample_rows=None, layout: int = -1) -> EncodedBlocks:
+    """Per-row-block tables; ``sample_rows`` (one row of each block, drawn by
+    the caller) picks each table from that row's exponents, None from all of
+    the block's values."""
+    indptr = _c(indptr, np.int32)
+    indices = _c(indices, np.int32)
+    data = _c(data, np.float64)
+    n_rows = indptr.size - 1
+    nnz = data.size
+    n_blocks = -(-n_rows // block_rows) if block_rows > 0 else 0
+    bs = np.zeros((max(n_blocks, 1), MAX_EXP), np.int16)
+    ci = np.empty(max(nnz, 1), np.uint32)
+    h = np.empty(max(nnz, 1), np.uint16)
+    t1 = np.empty(max(nnz, 1), np.uint16)
+    t2 = np.empty(max(nnz, 1), np.uint32)
+    eta = np.zeros(3, np.float64)
+    ef = C.c_double(0.0)
+    lo = C.c_int(0)
+    sr = None if sample_rows is None else _c(sample_rows, np.int32)
+    if sr is not None and sr.size < n_blocks:
+        raise OracleError(ERR_ARG, "sample_rows holds fewer rows than there are blocks")
+    rc = lib().or_encode_blocks(_p(indptr), _p(indices), _p(data), n_rows, n_cols, nnz, num_exp,
+                                layout, block_rows, _p(sr), _p(bs), _p(ci), _p(h), _p(t1), _p(t2),
+                                _p(eta), C.addressof(ef), C.addressof(lo))
+    if rc < 0:
+        raise OracleError(rc, "encode_blocks")
+    return EncodedBlocks(np.zeros(max(8, num_exp), np.int16), ci[:nnz], h[:nnz], t1[:nnz],
+                         t2[:nnz], eta, ef.value, index_bits(num_exp), lo.value,
+                         bs[:n_blocks].copy(), block_rows)
+
+
+def decode_blocks(indptr, enc: EncodedBlocks, s: int):
+    """Every value read with s segments and the table of its row's block."""
+    indptr = _c(indptr, np.int32)
+    out = np.empty(enc.head.size, np.float64)
+    for b in range(enc.block_sem.shape[0]):
+        j0 = int(indptr[min(b * enc.block_rows, indptr.size - 1)])
+        j1 = int(indptr[min((b + 1) * enc.block_rows, indptr.size - 1)])
+        table = _c(enc.block_sem[b], np.int16)
+        seg = np.empty(max(j1 - j0, 1), np.float64)
+        ci, h, t1, t2 = (_c(a[j0:j1], a.dtype) for a in (enc.col_idx, enc.head, enc.tail1,
+                                                            enc.tail2))
+        lib().or_decode(_p(ci), _p(h), _p(t1), _p(t2), j1 - j0, _p(table), enc.idx_bits,
+                        enc.layout, s, _p(seg))
+        out[j0:j1] = seg[:j1 - j0]
+    return out
+
+
 def decode(enc: Encoded, s: int):
     out = np.empty(enc.head.size, np.float64)
     lib().or_decode(_p(enc.col_idx), _p(enc.head), _p(enc.tail1), _p(enc.tail2),
@@ -284,6 +354,12 @@ def gse_spmv(indptr, enc: Encoded, s: int, x):
     indptr = _c(indptr, np.int32)
     x = _c(x, np.float64)
     y = np.empty(indptr.size - 1, np.float64)
+    if isinstance(enc, EncodedBlocks):
+        bs = _c(enc.block_sem, np.int16)
+        lib().or_gse_spmv_blocks(indptr.size - 1, _p(indptr), _p(enc.col_idx), _p(enc.head),
+                                 _p(enc.tail1), _p(enc.tail2), _p(bs), enc.block_rows,
+                                 enc.idx_bits, enc.layout, s, _p(x), _p(y))
+        return y
     table = enc.table
     lib().or_gse_spmv(indptr.size - 1, _p(indptr), _p(enc.col_idx), _p(enc.head),
                       _p(enc.tail1), _p(enc.tail2), _p(table), enc.idx_bits, enc.layout, s, _p(x),
@@ -368,6 +444,11 @@ def _matrix(indptr, indices=None, data=None, enc: Optional[Encoded] = None, lp=N
         m.idx_bits = enc.idx_bits
         m.layout = enc.layout
         keep.extend([enc, table])
+        if isinstance(enc, EncodedBlocks):
+            bs = _c(enc.block_sem, np.int16)
+            m.block_sem = _p(bs)
+            m.block_rows = enc.block_rows
+            keep.append(bs)
     if lp is not None:  # (uint16 plane, fmt)
         plane = _c(lp[0], np.uint16)
         m.lp_val = _p(plane)

@@ -246,6 +246,120 @@ int or_encode(const int32_t* row_ptr, const int32_t* col, const double* val,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Section III-B.1, last part: for a low preprocessing cost the matrix is cut
+ * into row blocks and the exponent distribution of one randomly drawn row of
+ * each block stands for the distribution of that block.  Reading taken: every
+ * block of block_rows rows (the last one may be shorter) gets a table of its
+ * own, of the same size k and index width as a global table.  The table is
+ * selected as for the whole matrix (count descending, ties to the larger
+ * exponent, the sample's maximum forced in) from the histogram of the sample:
+ * the drawn row (sample_rows[b], a row of block b) or, with sample_rows NULL,
+ * every value of the block.  A drawn row need not hold the block's largest
+ * exponent, which every value of the block needs a shared exponent above
+ * (Section III-B.2): when the table misses it, it takes the next free slot,
+ * or the last slot when all k are in use.  Tables are written to
+ * block_sem[b * OR_MAX_EXP + i]; row r reads the table of block r / block_rows. */
+static int block_table(const uint32_t* sample_hist, int block_max_e, int num_exp,
+                       int16_t* sem) {
+    int used = or_select_shared_exponents(sample_hist, num_exp, sem);
+    if (used < 0) return used;
+    if (block_max_e <= 0) return used;
+    for (int i = 0; i < used; ++i)
+        if (sem[i] == block_max_e + 1) return used;
+    if (used < num_exp) used += 1;
+    sem[used - 1] = (int16_t)(block_max_e + 1);
+    return used;
+}
+
+static const int16_t* table_of_row(const int16_t* block_sem, int32_t block_rows, int32_t r) {
+    return block_sem + (int64_t)(r / block_rows) * OR_MAX_EXP;
+}
+
+int or_encode_blocks(const int32_t* row_ptr, const int32_t* col, const double* val,
+                     int32_t n_rows, int32_t n_cols, int64_t nnz, int num_exp, int layout,
+                     int32_t block_rows, const int32_t* sample_rows, int16_t* block_sem,
+                     uint32_t* col_idx, uint16_t* head, uint16_t* tail1, uint32_t* tail2,
+                     double* eta3, double* exact_frac, int* layout_out) {
+    if (n_rows < 0 || n_cols < 0 || nnz < 0 || num_exp < 1 || num_exp > OR_MAX_EXP ||
+        block_rows < 1)
+        return OR_ERR_ARG;
+    int idx_bits = or_index_bits(num_exp);
+    if (layout < 0) layout = ((int64_t)n_cols > (1ll << (32 - idx_bits))) ? 1 : 0;
+    if (layout != 0 && layout != 1) return OR_ERR_ARG;
+    if (layout_out) *layout_out = layout;
+    if ((layout == 0 && (int64_t)n_cols > (1ll << (32 - idx_bits))) || nnz >= (1ll << 31))
+        return OR_ERR_RANGE;
+    uint32_t* own = (uint32_t*)malloc(2048 * sizeof(uint32_t));
+    uint32_t* sample = (uint32_t*)malloc(2048 * sizeof(uint32_t));
+    if (!own || !sample) { free(own); free(sample); return OR_ERR_ARG; }
+    int32_t n_blocks = (int32_t)(((int64_t)n_rows + block_rows - 1) / block_rows);
+    uint64_t covered = 0;
+    int rc = OR_OK;
+    for (int32_t bk = 0; bk < n_blocks && rc == OR_OK; ++bk) {
+        int32_t r0 = bk * block_rows;
+        int32_t r1 = (int32_t)((int64_t)r0 + block_rows < n_rows ? r0 + block_rows : n_rows);
+        int64_t j0 = row_ptr[r0], j1 = row_ptr[r1];
+        /* the block's own exponents: for the coverage count and its maximum */
+        if (or_exponent_histogram(val + j0, j1 - j0, own) > 0) { rc = OR_ERR_NONFINITE; break; }
+        int max_e = 0;
+        for (int e = 2046; e >= 1; --e)
+            if (own[e] > 0) { max_e = e; break; }
+        const uint32_t* hist = own;
+        if (sample_rows) {
+            int32_t sr = sample_rows[bk];
+            if (sr < r0 || sr >= r1) { rc = OR_ERR_ARG; break; }
+            or_exponent_histogram(val + row_ptr[sr], row_ptr[sr + 1] - row_ptr[sr], sample);
+            hist = sample;
+        }
+        int16_t* sem = block_sem + (int64_t)bk * OR_MAX_EXP;
+        int used = block_table(hist, max_e, num_exp, sem);
+        if (used < 0) { rc = used; break; }
+        for (int i = 0; i < used; ++i) covered += own[sem[i] - 1];
+        rc = or_encode_values(val + j0, col + j0, j1 - j0, sem, idx_bits, layout, col_idx + j0,
+                              head + j0, tail1 + j0, tail2 + j0);
+    }
+    free(own);
+    free(sample);
+    if (rc != OR_OK) return rc;
+    if (exact_frac) *exact_frac = nnz ? (double)covered / (double)nnz : 1.0;
+    if (eta3) {
+        double amax = 0.0, emax[3] = {0.0, 0.0, 0.0};
+        for (int32_t r = 0; r < n_rows; ++r) {
+            const int16_t* sem = table_of_row(block_sem, block_rows, r);
+            double a = 0.0, es[3] = {0.0, 0.0, 0.0};
+            for (int32_t j = row_ptr[r]; j < row_ptr[r + 1]; ++j) {
+                a += fabs(val[j]);
+                for (int s = 1; s <= 3; ++s)
+                    es[s - 1] += fabs(val[j] - or_decode_one(col_idx[j], head[j], tail1[j],
+                                                             tail2[j], sem, idx_bits, layout, s));
+            }
+            if (a > amax) amax = a;
+            for (int s = 0; s < 3; ++s) if (es[s] > emax[s]) emax[s] = es[s];
+        }
+        for (int s = 0; s < 3; ++s) eta3[s] = amax > 0.0 ? emax[s] / amax : 0.0;
+    }
+    return OR_OK;
+}
+
+/* Algorithm 2 and its wider variants with per-block tables: row r decodes
+ * its values with the table of its block. */
+void or_gse_spmv_blocks(int32_t n_rows, const int32_t* row_ptr, const uint32_t* col_idx,
+                        const uint16_t* head, const uint16_t* tail1, const uint32_t* tail2,
+                        const int16_t* block_sem, int32_t block_rows, int idx_bits, int layout,
+                        int s, const double* x, double* y) {
+    for (int32_t r = 0; r < n_rows; ++r) {
+        const int16_t* sem = table_of_row(block_sem, block_rows, r);
+        double sum = 0.0;
+        for (int32_t j = row_ptr[r]; j < row_ptr[r + 1]; ++j) {
+            double v = or_decode_one(col_idx[j], head[j], tail1[j], tail2[j], sem, idx_bits,
+                                     layout, s);
+            sum += v * x[column_of(col_idx[j], idx_bits, layout)];
+        }
+        y[r] = sum;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Section IV-C: the FP16 and BF16 comparators.  Every value is rounded once,
  * to nearest with ties to even, into a binary format with `ebits` exponent
  * bits and `mbits` fraction bits (IEEE binary16: 5 and 10; bfloat16: 8 and
@@ -418,6 +532,9 @@ int or_precision_trigger(const double* resid, int32_t j, const or_params* p) {
 static void apply_op(const or_matrix* A, int s, const double* x, double* y) {
     if (s == OR_S_LP) or_lp_spmv(A->n_rows, A->row_ptr, A->col, A->lp_val, A->lp_fmt, x, y);
     else if (s <= 0) or_csr_spmv(A->n_rows, A->row_ptr, A->col, A->val, x, y);
+    else if (A->block_rows > 0)
+        or_gse_spmv_blocks(A->n_rows, A->row_ptr, A->col_idx, A->head, A->tail1, A->tail2,
+                           A->block_sem, A->block_rows, A->idx_bits, A->layout, s, x, y);
     else or_gse_spmv(A->n_rows, A->row_ptr, A->col_idx, A->head, A->tail1, A->tail2,
                      A->sem64, A->idx_bits, A->layout, s, x, y);
 }

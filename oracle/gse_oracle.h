@@ -89,6 +89,21 @@ void or_decode(const uint32_t* col_idx, const uint16_t* head, const uint16_t* ta
                const uint32_t* tail2, int64_t nnz, const int16_t* sem64, int idx_bits,
                int layout, int s, double* out);
 
+/* Per-row-block tables (Section III-B.1, sampling): block b covers rows
+ * [b*block_rows, (b+1)*block_rows) and has the table block_sem[b*64 .. b*64+63].
+ * sample_rows: one row of each block whose exponents choose its table, or
+ * NULL to choose from all of the block's values.  Errors as or_encode, and
+ * OR_ERR_ARG for a sample row outside its block. */
+int or_encode_blocks(const int32_t* row_ptr, const int32_t* col, const double* val,
+                     int32_t n_rows, int32_t n_cols, int64_t nnz, int num_exp, int layout,
+                     int32_t block_rows, const int32_t* sample_rows, int16_t* block_sem,
+                     uint32_t* col_idx, uint16_t* head, uint16_t* tail1, uint32_t* tail2,
+                     double* eta3, double* exact_frac, int* layout_out);
+void or_gse_spmv_blocks(int32_t n_rows, const int32_t* row_ptr, const uint32_t* col_idx,
+                        const uint16_t* head, const uint16_t* tail1, const uint32_t* tail2,
+                        const int16_t* block_sem, int32_t block_rows, int idx_bits, int layout,
+                        int s, const double* x, double* y);
+
 /* ---- FP16 / BF16 comparators (Section IV-C) ----
  * fmt: OR_LP_FP16 (IEEE binary16) or OR_LP_BF16 (bfloat16).  Values are
  * rounded once, to nearest with ties to even; overflow gives an infinity and
@@ -139,6 +154,8 @@ typedef struct {
     int32_t layout;          /* 0: slot in the column word, 1: in the value */
     const uint16_t* lp_val;  /* FP16 / BF16 values (fixed_segments == -2) */
     int32_t lp_fmt;
+    const int16_t* block_sem;  /* per-row-block tables (or_encode_blocks) when block_rows > 0 */
+    int32_t block_rows;
 } or_matrix;
 
 #define OR_S_LP (-2)

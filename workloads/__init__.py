@@ -9,6 +9,8 @@ from .generators import (  # noqa: F401
     CSR,
     poisson2d,
     diffusion3d,
+    layered3d,
+    block_sample_rows,
     diffusion2d,
     convdiff2d,
     powerlaw,

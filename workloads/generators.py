@@ -108,6 +108,58 @@ def diffusion3d(N: int, seed: int, decades: float = 4.0) -> CSR:
     return _from_banded(n, cols, vals, valid, f"diffusion3d_{N}_s{seed}")
 
 
+def layered3d(N: int, seed: int, contrast: float = 8.0, local: float = 1.0,
+              layers: int = 16) -> CSR:
+    """3-D 7-point diffusion in a layered medium, N^3 grid.
+
+    The grid is cut along k (the slowest row index) into ``layers`` slabs of
+    equal thickness; slab q has the level ``c_q ~ U(-contrast/2, contrast/2)``
+    (decades) and every cell face inside it the coefficient
+    ``10**(c_q + U(-local/2, local/2))``; a face between two slabs takes the
+    lower level of the two.  Off-diagonals are ``-kappa`` of the shared face, the
+    diagonal the sum of the cell's six faces (boundary faces included), so the
+    operator is symmetric positive definite.  Contiguous rows share a slab,
+    so the exponents of a block of rows spread over ``local`` decades plus
+    the diagonal while the whole matrix spans ``contrast + local``.
+    """
+    rng = np.random.default_rng(seed)
+    level = rng.uniform(-contrast / 2.0, contrast / 2.0, size=layers)
+    slab = (np.arange(N) * layers) // N                       # slab of each k plane
+    lev_k = level[slab]                                      # [k]
+    lev_kface = np.empty(N + 1)
+    lev_kface[0], lev_kface[N] = lev_k[0], lev_k[-1]
+    lev_kface[1:N] = np.minimum(lev_k[:-1], lev_k[1:])
+    lo, hi = -local / 2.0, local / 2.0
+    kx = 10.0 ** (lev_k[:, None, None] + rng.uniform(lo, hi, size=(N, N, N + 1)))
+    ky = 10.0 ** (lev_k[:, None, None] + rng.uniform(lo, hi, size=(N, N + 1, N)))
+    kz = 10.0 ** (lev_kface[:, None, None] + rng.uniform(lo, hi, size=(N + 1, N, N)))
+    diag = (kx[:, :, :-1] + kx[:, :, 1:]) + (ky[:, :-1, :] + ky[:, 1:, :]) \
+        + (kz[:-1] + kz[1:])
+    n = N ** 3
+    r = np.arange(n, dtype=np.int64)
+    i = r % N
+    j = (r // N) % N
+    k = r // (N * N)
+    cols = np.stack([r - N * N, r - N, r - 1, r, r + 1, r + N, r + N * N], axis=1)
+    vals = np.stack([-kz[:-1].ravel(), -ky[:, :-1, :].ravel(), -kx[:, :, :-1].ravel(),
+                     diag.ravel(),
+                     -kx[:, :, 1:].ravel(), -ky[:, 1:, :].ravel(), -kz[1:].ravel()], axis=1)
+    valid = np.stack([k > 0, j > 0, i > 0, np.ones(n, bool),
+                      i < N - 1, j < N - 1, k < N - 1], axis=1)
+    return _from_banded(n, cols, vals, valid, f"layered3d_{N}_s{seed}")
+
+
+def block_sample_rows(n_rows: int, block_rows: int, seed: int) -> np.ndarray:
+    """One uniformly drawn row of each block of ``block_rows`` rows (the last
+    block may be shorter): the random rows whose exponents stand for their
+    block's when the shared exponents are chosen by sampling."""
+    rng = np.random.default_rng(seed)
+    n_blocks = -(-n_rows // block_rows)
+    start = np.arange(n_blocks, dtype=np.int64) * block_rows
+    size = np.minimum(block_rows, n_rows - start)
+    return (start + np.floor(rng.random(n_blocks) * size).astype(np.int64)).astype(np.int32)
+
+
 def convdiff2d(N: int, seed: int, peclet: float = 10.0) -> CSR:
     """2-D convection-diffusion, first-order upwind 5-point stencil, N x N.
 
@@ -279,12 +331,14 @@ CONFIGS = {
     "diffusion3d_128": lambda seed=0: diffusion3d(128, seed),
     "convdiff2d_1024": lambda seed=0: convdiff2d(1024, seed),
     "powerlaw_4m": lambda seed=0: powerlaw(4_000_000, seed),
+    "layered3d_128": lambda seed=0: layered3d(128, seed),
     # reduced instances (same recipes)
     "diffusion3d_24": lambda seed=0: diffusion3d(24, seed),
     "diffusion3d_48": lambda seed=0: diffusion3d(48, seed),
     "convdiff2d_64": lambda seed=0: convdiff2d(64, seed),
     "convdiff2d_128": lambda seed=0: convdiff2d(128, seed),
     "powerlaw_50k": lambda seed=0: powerlaw(50_000, seed),
+    "layered3d_24": lambda seed=0: layered3d(24, seed),
 }
 
 
