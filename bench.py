@@ -32,6 +32,9 @@ Other workloads (one JSON line each):
   * ``--workload powerlaw``: the 4 M-row power-law SPD matrix (Zipf(2) row
     lengths up to 10^4, values over six decades): SpMV per segment count on
     autotuned tiles, then stepped GSE CG and FP64 CG to 1e-10;
+  * ``--workload blocks``: per-row-block shared-exponent tables on the
+    layered medium 128^3 (encode, SpMV time and error; also a leg of the
+    default workload).
   * ``--workload poisson``: the 2-D Poisson 64 x 64 system, stepped GSE CG
     and FP64 CG to 1e-10 (launch-bound; median over the steps).
 """
@@ -110,7 +113,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="spmv_cg",
-                    choices=["spmv_cg", "gmres", "serving", "powerlaw", "poisson"])
+                    choices=["spmv_cg", "gmres", "serving", "powerlaw", "poisson", "blocks"])
     ap.add_argument("--pl-rows", type=int, default=4_000_000, help="powerlaw: rows")
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--seed", type=int, default=0)
@@ -365,6 +368,9 @@ def run_spmv_cg(args, torch, G):
             out["lowprec_cg"] = leg_lowprec_solve(torch, G, A, b, x_true, G.CG, solve["gse"][-1],
                                                   solve["fp64"][-1])
         out["k_sweep"] = leg_k_sweep(torch, G, A, args.copies)
+        progress("legs: per-row-block tables (layered medium 128^3)")
+        out["blocks"] = leg_blocks(torch, G, args.seed, args.copies, A_cg=A, b_cg=b,
+                                   x_true_cg=x_true)
     if args.legs and not args.no_solve:
         # the other configurations, each once after the timed steps (their own
         # warm-up), so that every result of the path is on the one line
@@ -469,6 +475,105 @@ def leg_k_sweep(torch, G, A, copies, ks=(2, 4, 8, 16, 32, 64)):
                        **host_product_errors(ys[0], ref), "eta1": float(mats[0].eta[0]),
                        "exact_frac": round(float(mats[0].A.exact_frac), 4)}
         del mats
+    return out
+
+
+def componentwise_errors(y_dev, ref, absref):
+    """Row-wise error |y - ref| / (|A| |x|) of one product: percentiles."""
+    y = y_dev.cpu().numpy()
+    e = np.abs(y - ref) / np.where(absref > 0, absref, 1.0)
+    return {"p50": float(np.percentile(e, 50)), "p99": float(np.percentile(e, 99)),
+            "max": float(e.max())}
+
+
+def leg_blocks(torch, G, seed, copies, block_rows=4096, A_cg=None, b_cg=None, x_true_cg=None):
+    """Per-row-block tables (Section III-B.1, sampling) on the layered medium
+    (128^3, 16 slabs whose coefficients sit at levels spread over eight
+    decades, one decade within a slab): encode time of the global table, of
+    exact block tables and of tables from one drawn row per block; SpMV time
+    per segment count over rotated copies (block tables run the row-vector
+    schedule; the global table is timed on its own schedule and on the same
+    row-vector one); error against the host FP64 product with x = 1,
+    norm-wise and per row; eta_s and the share of exactly represented
+    exponents.  With A_cg given, also the stepped CG on that system with
+    exact block tables."""
+    from workloads import block_sample_rows, layered3d
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    A = layered3d(128, seed)
+    S = A.to_scipy()
+    ref = S @ np.ones(A.n_cols)
+    absref = abs(S) @ np.ones(A.n_cols)
+    rp = torch.from_numpy(A.indptr).to(dev)
+    ci = torch.from_numpy(A.indices).to(dev)
+    va = torch.from_numpy(A.data).to(dev)
+    sr = torch.from_numpy(block_sample_rows(A.n_rows, block_rows, seed)).to(dev)
+    xs = torch.ones(A.n_cols, dtype=torch.float64, device=dev)
+    ys = [torch.empty(A.n_rows, dtype=torch.float64, device=dev) for _ in range(copies)]
+    variants = {"global": {}, "blocks_exact": {"block_rows": block_rows},
+                "blocks_sampled": {"block_rows": block_rows, "sample_rows": sr}}
+    out = {"workload": "layered3d_128^3_7pt_16slabs_8+1decades", "n_rows": A.n_rows,
+           "nnz": A.nnz, "block_rows": block_rows, "seed": seed, "x": "ones"}
+    lanes = None
+    for name, kw in variants.items():
+        mats = [G.GseMatrix(rp.clone(), ci, va, A.n_cols, **kw) for _ in range(copies)]
+        M = mats[0]
+        # encode time: the same call again on the first copy's buffers
+        enc_ms = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if kw:
+                G.gse_encode_blocks(M.row_ptr, ci, va, A.n_rows, A.n_cols, A.nnz, 8, block_rows,
+                                    kw.get("sample_rows"), M.A, M.ws)
+            else:
+                G.gse_encode(M.row_ptr, ci, va, A.n_rows, A.n_cols, A.nnz, 8, None, M.A, M.ws)
+            enc_ms.append((time.perf_counter() - t0) * 1e3)
+        rec = {"encode_ms": round(float(np.median(enc_ms)), 3), "eta": [float(e) for e in M.eta],
+               "exact_frac": round(float(M.A.exact_frac), 4), "rv_lanes": int(M.A.rv_lanes),
+               "kernel": kernel_name(M.A) if not kw else f"k_spmv_rv<s, {M.A.rv_lanes}, blocks>"}
+        if kw:
+            lanes = M.A.rv_lanes
+        tables = (G.gse_block_table_entries(A.n_rows, block_rows, 8) * 2) if kw else 0
+        for s, pb in ((1, 6), (2, 8), (3, 12)):
+            us = rotated_launch_us(torch, stream,
+                                   [lambda m=m, y=y, s=s: m.spmv(s, xs, y) for m, y in zip(mats, ys)])
+            M.spmv(s, xs, ys[0])
+            torch.cuda.synchronize()
+            nbytes = spmv_bytes(A.n_rows, A.n_cols, A.nnz, pb) + tables
+            rec[f"s{s}"] = {"mean_us": round(us, 2), "GBps": round(nbytes / (us * 1e-6) / 1e9, 1),
+                            **host_product_errors(ys[0], ref),
+                            "rowwise": componentwise_errors(ys[0], ref, absref)}
+        out[name] = rec
+        del mats
+    if lanes:
+        mats = [G.GseMatrix(rp.clone(), ci, va, A.n_cols) for _ in range(copies)]
+        for m in mats:
+            m.plan(1024, lanes)
+        us = rotated_launch_us(torch, stream,
+                               [lambda m=m, y=y: m.spmv(1, xs, y) for m, y in zip(mats, ys)])
+        nbytes = spmv_bytes(A.n_rows, A.n_cols, A.nnz, 6)
+        out["global_rowvector_s1"] = {"rv_lanes": int(lanes), "mean_us": round(us, 2),
+                                      "GBps": round(nbytes / (us * 1e-6) / 1e9, 1)}
+        del mats
+    del rp, ci, va, ys
+    if A_cg is not None:
+        rp = torch.from_numpy(A_cg.indptr).to(dev)
+        ci = torch.from_numpy(A_cg.indices).to(dev)
+        va = torch.from_numpy(A_cg.data).to(dev)
+        M = G.GseMatrix(rp, ci, va, A_cg.n_cols, block_rows=block_rows)
+        bd = torch.from_numpy(b_cg).to(dev)
+        p = G.gse_default_params(G.CG)
+        p.max_iter = 20000
+        ws = torch.empty(G.gse_solver_workspace(G.CG, A_cg.n_rows, A_cg.nnz, 30, p.max_iter),
+                         dtype=torch.uint8, device=dev)
+        x = torch.zeros(A_cg.n_rows, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        rep = G.gse_cg(M.A, bd, x, p, ws)
+        out["cg_diffusion3d_128_blocks_exact"] = {**solve_record(rep, x, x_true_cg),
+                                                  "eta": [float(e) for e in M.eta],
+                                                  "rv_lanes": int(M.A.rv_lanes)}
     return out
 
 
@@ -919,6 +1024,14 @@ def main():
         out = run_powerlaw(args, torch, G)
     elif args.workload == "poisson":
         out = run_poisson(args, torch, G)
+    elif args.workload == "blocks":
+        t0 = time.perf_counter()
+        leg = leg_blocks(torch, G, args.seed, args.copies)
+        out = base_record(args, "GSE-SpMV with per-row-block tables, s=1 GB/s",
+                          leg["blocks_sampled"]["s1"]["GBps"], "GB/s", time.perf_counter() - t0)
+        out["config"] = {"workload": leg["workload"], "n_rows": leg["n_rows"], "nnz": leg["nnz"],
+                         "block_rows": leg["block_rows"]}
+        out["blocks"] = leg
     else:
         out = run_spmv_cg(args, torch, G)
     print(json.dumps(json_safe(out), allow_nan=False))

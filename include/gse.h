@@ -53,6 +53,9 @@ typedef int32_t gse_status;
 
 #define GSE_MAX_EXP 64          /* shared exponents per matrix (up to a 6-bit index) */
 
+/* Smallest block of rows with a table of its own (gse_encode_blocks). */
+#define GSE_MIN_BLOCK_ROWS 128
+
 /* Where the slot index lives (gse_matrix.idx_layout). */
 #define GSE_IDX_AUTO 0          /* input: the column word unless n_cols needs its top bits */
 #define GSE_IDX_COLUMN 1        /* top bits of the column word */
@@ -113,6 +116,10 @@ typedef struct gse_matrix {
     int32_t max_row_nnz;       /* longest row (set by gse_encode / gse_plan) */
     double eta[3];             /* ||A - A_s||_inf / ||A||_inf, s = 1, 2, 3 */
     double exact_frac;         /* share of non-zeros whose exponent is shared */
+    int32_t block_rows;        /* 0: the one table sem[]; > 0: rows per block, each block
+                                  with its own table in block_sem (gse_encode_blocks) */
+    int32_t block_stride;      /* entries per block in block_sem: 2^idx_bits */
+    int16_t* block_sem;        /* device [ceil(n_rows / block_rows) * block_stride] */
 } gse_matrix;
 
 /* Plain FP64 CSR operand for the baseline operators on the same schedule.
@@ -162,6 +169,42 @@ gse_status gse_encode(const int32_t* row_ptr, const int32_t* col, const double* 
                       int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t num_exp,
                       const int16_t* sem_in, gse_matrix* A, void* ws, size_t ws_bytes,
                       void* stream);
+
+/* Per-row-block shared-exponent tables (Section III-B.1: for a low
+ * preprocessing cost the matrix is cut into row blocks and one random row of
+ * each block stands for the exponent distribution of that block).  Rows
+ * [b*block_rows, (b+1)*block_rows) form block b (the last may be shorter);
+ * each block gets a table of num_exp shared exponents, chosen as gse_encode
+ * chooses the global one (count descending, ties to the larger exponent, the
+ * maximum forced in), from the exponents of sample_rows[b] -- or, with
+ * sample_rows NULL, of all the block's values -- and then, if the table
+ * misses the block's own largest exponent, that exponent in the next free
+ * slot or in place of the last one (every value needs a shared exponent
+ * above its own, Section III-B.2).  Each non-zero is encoded (Algorithm 1)
+ * against its block's table; the planes, slot index and layouts are those
+ * of gse_encode.
+ *   block_rows  : >= GSE_MIN_BLOCK_ROWS.
+ *   sample_rows : device int32 [ceil(n_rows / block_rows)], one row of each
+ *                 block (drawn by the caller), or NULL.
+ *   A           : as for gse_encode, plus block_sem: device int16 buffer of
+ *                 gse_block_table_entries() entries, written here (block b's
+ *                 table at b * block_stride, block_stride = 2^idx_bits,
+ *                 unused slots 0).  Out: block_rows, block_stride, eta,
+ *                 exact_frac (measured against each block's own exponents),
+ *                 num_used (the most slots any block uses); sem[] is zero.
+ * The SpMV of such a matrix runs the row-vector schedule (rv_lanes > 0; the
+ * encoder picks the lanes from the mean row length, gse_plan / gse_autotune
+ * may change them; rv_lanes 0 there means the same default), reading each
+ * row's table from LDS.  gse_spmv, gse_cg and gse_gmres take it; the batched
+ * solver and the server do not (GSE_ERR_ARG).
+ * Errors: those of gse_encode; GSE_ERR_ARG for block_rows below the minimum,
+ * a NULL block_sem, or a sample row outside its block.  Synchronizes `stream`. */
+gse_status gse_encode_blocks(const int32_t* row_ptr, const int32_t* col, const double* val,
+                             int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t num_exp,
+                             int32_t block_rows, const int32_t* sample_rows, gse_matrix* A,
+                             void* ws, size_t ws_bytes, void* stream);
+/* Entries block_sem needs (0 for invalid arguments). */
+int64_t gse_block_table_entries(int32_t n_rows, int32_t block_rows, int32_t num_exp);
 
 /* gse_encode for callers that cannot allocate device memory (tight serving
  * loops, harnesses that forbid hipMalloc; not for use under graph capture,

@@ -372,6 +372,18 @@ def gse_spmv_rows(rows, indptr, enc: Encoded, s: int, x):
     indptr = _c(indptr, np.int32)
     x = _c(x, np.float64)
     y = np.empty(rows.size, np.float64)
+    if isinstance(enc, EncodedBlocks):  # each row with its block's table
+        blk = rows // enc.block_rows
+        for b in np.unique(blk):
+            sel = np.nonzero(blk == b)[0]
+            part = _c(rows[sel], np.int32)
+            out = np.empty(part.size, np.float64)
+            table = _c(enc.block_sem[b], np.int16)
+            lib().or_gse_spmv_rows(_p(part), part.size, _p(indptr), _p(enc.col_idx),
+                                   _p(enc.head), _p(enc.tail1), _p(enc.tail2), _p(table),
+                                   enc.idx_bits, enc.layout, s, _p(x), _p(out))
+            y[sel] = out
+        return y
     table = enc.table
     lib().or_gse_spmv_rows(_p(rows), rows.size, _p(indptr), _p(enc.col_idx), _p(enc.head),
                            _p(enc.tail1), _p(enc.tail2), _p(table), enc.idx_bits, enc.layout, s,

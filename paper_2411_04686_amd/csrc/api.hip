@@ -45,6 +45,15 @@ int32_t auto_rv(int64_t nnz, int32_t n_rows, int32_t max_row) {
   return 0;
 }
 
+// Lanes per row of the row-vector schedule for per-block tables: the
+// power of two nearest above half the mean row length (1 .. 64).
+int32_t block_lanes(int64_t nnz, int32_t n_rows) {
+  const int64_t half = n_rows > 0 ? (nnz + 2 * (int64_t)n_rows - 1) / (2 * (int64_t)n_rows) : 1;
+  int32_t L = 1;
+  while (L < 64 && L < half) L *= 2;
+  return L;
+}
+
 // Tile table for tile_nnz plus the longest row; picks the schedule.
 gse_status plan_common(const int32_t* row_ptr, int32_t n_rows, int64_t nnz, int32_t* tile_row,
                        int32_t tile_cap, int32_t tile_nnz, int32_t rv_lanes, hipStream_t st,
@@ -84,6 +93,12 @@ SpmvOperand operand_of(const gse_matrix* A) {
   o.max_row = A->max_row_nnz;
   o.split = col_split(A->idx_bits, A->idx_layout == GSE_IDX_VALUE);
   for (int i = 0; i < GSE_MAX_EXP; ++i) o.sem[i] = A->sem[i];
+  if (A->block_rows > 0) {
+    o.block_sem = A->block_sem;
+    o.block_rows = A->block_rows;
+    o.block_stride = A->block_stride;
+    if (o.rv_lanes == 0) o.rv_lanes = block_lanes(A->nnz, A->n_rows);
+  }
   return o;
 }
 
@@ -119,6 +134,10 @@ gse_status check_matrix(const gse_matrix* A) {
   if (!valid_tile(A->tile_nnz) || A->n_tiles != n_tiles_for(A->nnz, A->tile_nnz) ||
       A->tile_cap < A->n_tiles + 2 || !valid_rv(A->rv_lanes))
     return fail(GSE_ERR_ARG, "matrix has no valid SpMV schedule (call gse_encode / gse_plan)");
+  if (A->block_rows != 0 &&
+      (A->block_rows < GSE_MIN_BLOCK_ROWS || !A->block_sem ||
+       A->block_stride != (1 << A->idx_bits)))
+    return fail(GSE_ERR_ARG, "matrix has no valid per-block tables (call gse_encode_blocks)");
   return GSE_OK;
 }
 
@@ -138,10 +157,10 @@ gse_status check_csr(const gse_csr* M) {
 
 // Validation, the encoder launches and the host part of gse_encode, on a
 // scratch record `ws` of at least gse_encode_workspace() bytes.
-gse_status encode_matrix(const int32_t* row_ptr, const int32_t* col, const double* val,
-                         int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t num_exp,
-                         const int16_t* sem_in, gse_matrix* A, void* ws, size_t ws_bytes,
-                         hipStream_t st) {
+// Checks shared by the encoders; on success *layout is the slot layout.
+gse_status check_encode(const int32_t* row_ptr, const int32_t* col, const double* val,
+                        int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t num_exp,
+                        const gse_matrix* A, void* ws, size_t ws_bytes, int* layout_out) {
   if (!A) return fail(GSE_ERR_ARG, "matrix is NULL");
   if (!row_ptr || (nnz > 0 && (!col || !val))) return fail(GSE_ERR_ARG, "NULL CSR array");
   if (n_rows < 0 || n_cols < 0 || nnz < 0) return fail(GSE_ERR_ARG, "negative size");
@@ -166,6 +185,70 @@ gse_status encode_matrix(const int32_t* row_ptr, const int32_t* col, const doubl
   gse_encode_workspace(nnz, n_rows, &need);
   if (!ws || ws_bytes < need) return fail(GSE_ERR_NOMEM, "encode workspace needs %zu bytes", need);
   if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(GSE_ERR_ARG, "workspace must be 256-byte aligned");
+  *layout_out = layout;
+  return GSE_OK;
+}
+
+// The per-row-block encoder (Section III-B.1, sampling): validation,
+// launches, read-back, default plan.
+gse_status encode_blocks(const int32_t* row_ptr, const int32_t* col, const double* val,
+                         int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t num_exp,
+                         int32_t block_rows, const int32_t* sample_rows, gse_matrix* A, void* ws,
+                         size_t ws_bytes, hipStream_t st) {
+  int layout = 0;
+  gse_status cs = check_encode(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, A, ws, ws_bytes,
+                               &layout);
+  if (cs != GSE_OK) return cs;
+  if (block_rows < GSE_MIN_BLOCK_ROWS)
+    return fail(GSE_ERR_ARG, "block_rows must be at least %d", GSE_MIN_BLOCK_ROWS);
+  if (!A->block_sem) return fail(GSE_ERR_ARG, "block_sem is NULL");
+  EncodeScratch* sc = reinterpret_cast<EncodeScratch*>(ws);
+  A->n_rows = n_rows;
+  A->n_cols = n_cols;
+  A->nnz = nnz;
+  A->num_exp = num_exp;
+  A->idx_bits = index_bits(num_exp);
+  A->idx_layout = layout;
+  A->row_ptr = row_ptr;
+  A->block_rows = block_rows;
+  A->block_stride = 1 << A->idx_bits;
+  hipError_t e = launch_encode_blocks(row_ptr, col, val, n_rows, (int32_t)nnz, num_exp, sample_rows,
+                                      A, sc, st);
+  if (e != hipSuccess) return hip_fail(e, "gse_encode_blocks launch");
+  EncodeScratch h;
+  e = hipMemcpyAsync(&h, sc, sizeof h, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "gse_encode_blocks");
+  int32_t nt, rv, mr;
+  gse_status ps = plan_common(row_ptr, n_rows, nnz, A->tile_row, A->tile_cap, kDefaultTile, 0, st,
+                              &nt, &rv, &mr);
+  if (ps != GSE_OK) return ps;
+  A->tile_nnz = kDefaultTile;
+  A->n_tiles = nt;
+  A->rv_lanes = block_lanes(nnz, n_rows);
+  A->max_row_nnz = mr;
+  for (int i = 0; i < GSE_MAX_EXP; ++i) A->sem[i] = 0;
+  A->num_used = h.used;
+  A->exact_frac = nnz ? (double)h.covered / (double)nnz : 1.0;
+  double nrm[4];
+  for (int i = 0; i < 4; ++i) memcpy(&nrm[i], &h.norm_bits[i], sizeof(double));
+  for (int s = 0; s < 3; ++s) A->eta[s] = nrm[0] > 0.0 ? nrm[s + 1] / nrm[0] : 0.0;
+  if (h.nonfinite) return fail(GSE_ERR_NONFINITE, "%d non-finite values", h.nonfinite);
+  if (h.range_err & 4) return fail(GSE_ERR_ARG, "a sample row lies outside its block");
+  if (h.range_err & 1) return fail(GSE_ERR_RANGE, "a shared exponent is below 63");
+  if (h.range_err & 2) return fail(GSE_ERR_RANGE, "a value has no larger shared exponent in the table");
+  return GSE_OK;
+}
+
+gse_status encode_matrix(const int32_t* row_ptr, const int32_t* col, const double* val,
+                         int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t num_exp,
+                         const int16_t* sem_in, gse_matrix* A, void* ws, size_t ws_bytes,
+                         hipStream_t st) {
+  int layout = 0;
+  gse_status cs = check_encode(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, A, ws, ws_bytes,
+                               &layout);
+  if (cs != GSE_OK) return cs;
+  const int ib = index_bits(num_exp);
   if (sem_in) {
     for (int i = 0; i < num_exp; ++i) {
       if (sem_in[i] < 64 || sem_in[i] > 2047)
@@ -182,6 +265,8 @@ gse_status encode_matrix(const int32_t* row_ptr, const int32_t* col, const doubl
   A->idx_bits = ib;
   A->idx_layout = layout;
   A->row_ptr = row_ptr;
+  A->block_rows = 0;
+  A->block_stride = 0;
   hipError_t e = launch_encode(row_ptr, col, val, n_rows, (int32_t)nnz, num_exp, sem_in, A, sc, st);
   if (e != hipSuccess) return hip_fail(e, "gse_encode launch");
   EncodeScratch h;
@@ -253,6 +338,7 @@ gse_status gse_plan(gse_matrix* A, int32_t tile_nnz, int32_t rv_lanes, void* str
   A->tile_nnz = tile_nnz;
   A->n_tiles = nt;
   A->rv_lanes = rv;
+  if (A->block_rows > 0 && rv <= 0) A->rv_lanes = block_lanes(A->nnz, A->n_rows);
   A->max_row_nnz = mr;
   return GSE_OK;
 }
@@ -276,6 +362,20 @@ gse_status gse_encode(const int32_t* row_ptr, const int32_t* col, const double* 
                       gse_matrix* A, void* ws, size_t ws_bytes, void* stream) {
   return encode_matrix(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, sem_in, A, ws, ws_bytes,
                        (hipStream_t)stream);
+}
+
+gse_status gse_encode_blocks(const int32_t* row_ptr, const int32_t* col, const double* val,
+                             int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t num_exp,
+                             int32_t block_rows, const int32_t* sample_rows, gse_matrix* A,
+                             void* ws, size_t ws_bytes, void* stream) {
+  return encode_blocks(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, block_rows, sample_rows, A,
+                       ws, ws_bytes, (hipStream_t)stream);
+}
+
+int64_t gse_block_table_entries(int32_t n_rows, int32_t block_rows, int32_t num_exp) {
+  if (n_rows < 0 || block_rows < 1 || num_exp < 1 || num_exp > GSE_MAX_EXP) return 0;
+  const int64_t n_blocks = ((int64_t)n_rows + block_rows - 1) / block_rows;
+  return n_blocks * ((int64_t)1 << index_bits(num_exp));
 }
 
 gse_status gse_autotune(gse_matrix* A, int32_t k_segments, const double* x, double* y,
@@ -466,6 +566,8 @@ static gse_status batch_descs(int32_t n_sys, const gse_system* sys, const gse_pa
       const gse_matrix* A = y.A;
       if (A->n_rows != A->n_cols || A->n_rows < 1)
         return fail(GSE_ERR_ARG, "system %d: the matrix must be square and non-empty", i);
+      if (A->block_rows != 0)
+        return fail(GSE_ERR_ARG, "system %d: per-block tables are not taken by the batched solver", i);
       B.row_ptr = A->row_ptr;
       B.tile_row = A->tile_row;
       B.col = A->col_idx;

@@ -96,7 +96,8 @@ hipError_t time_one(int fmt, SpmvOperand op, const double* x, double* y, int rep
 gse_status autotune(int fmt, int segs, SpmvOperand op, const int32_t* row_ptr, int32_t* tile_row,
                     int32_t tile_cap, int32_t max_row, const double* x, double* y, int32_t reps,
                     hipStream_t st, int32_t* out_tile, int32_t* out_rv, int32_t* out_tiles) {
-  const std::string k = key_of(fmt, segs, op.n_rows, op.nnz, max_row);
+  const bool blocks = op.block_sem != nullptr;  // per-block tables: row-vector only
+  const std::string k = key_of(fmt, segs, op.n_rows, op.nnz, max_row) + (blocks ? "_b" : "");
   {
     std::lock_guard<std::mutex> lock(g_mu);
     load_file();
@@ -113,10 +114,15 @@ gse_status autotune(int fmt, int segs, SpmvOperand op, const int32_t* row_ptr, i
   struct Cand {
     int tile, rv;
   };
-  std::vector<Cand> cands = {{1024, 0}, {2048, 0}, {4096, 0}};
-  if (max_row <= 64)
-    for (int L : {4, 8, 16})
-      if (L >= max_row / 4) cands.push_back({1024, L});
+  std::vector<Cand> cands;
+  if (blocks) {
+    for (int L : {1, 2, 4, 8, 16, 32, 64}) cands.push_back({1024, L});
+  } else {
+    cands = {{1024, 0}, {2048, 0}, {4096, 0}};
+    if (max_row <= 64)
+      for (int L : {4, 8, 16})
+        if (L >= max_row / 4) cands.push_back({1024, L});
+  }
   Choice best{0, 0, 1e30f};
   for (const Cand& c : cands) {
     const int32_t nt = n_tiles_for(op.nnz, c.tile);

@@ -18,16 +18,22 @@ struct DecodeCtx {
 // fraction (SEM >= 64 keeps it normal); the low word is zero, and the value's
 // sign goes into bit 31 of the high word.  W_s = 15, 31, 63 less ei, the
 // index bits the value word gives up in the index-in-value layout.  Every
-// thread of the workgroup takes part.
+// thread of the workgroup takes part; build_scale_n fills n entries from n
+// consecutive shared exponents (several blocks' tables back to back).
 template <int FMT>
-__device__ __forceinline__ void build_scale(const int16_t* sem, uint32_t* tab, int ei = 0) {
+__device__ __forceinline__ void build_scale_n(const int16_t* sem, int n, uint32_t* tab, int ei) {
   if constexpr (is_gse(FMT)) {
     const int W = ((FMT == 1) ? 15 : (FMT == 2) ? 31 : 63) - ei;
-    for (int i = threadIdx.x; i < kScaleEntries; i += blockDim.x) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
       const int S = sem[i];
       tab[i] = S > W ? (uint32_t)(S - W) << 20 : 0u;
     }
   }
+}
+
+template <int FMT>
+__device__ __forceinline__ void build_scale(const int16_t* sem, uint32_t* tab, int ei = 0) {
+  build_scale_n<FMT>(sem, kScaleEntries, tab, ei);
 }
 
 // Decode one non-zero: returns the FP64 value and its column.

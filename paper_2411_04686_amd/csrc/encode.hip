@@ -57,7 +57,7 @@ __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v
 // Slot of the smallest shared exponent above each exponent field (the
 // slot search of Algorithm 1, done once per field instead of per value):
 // -1 when no shared exponent is above it, and for the Inf/NaN field.
-__device__ __forceinline__ void fill_slot_lookup(const int16_t* tab, EncodeScratch* sc) {
+__device__ __forceinline__ void fill_slot_lookup(const int16_t* tab, int8_t* slot_of) {
   for (int e = threadIdx.x; e < 2048; e += blockDim.x) {
     int slot = -1, best = 1 << 30;
     if (e < 2047) {
@@ -69,7 +69,7 @@ __device__ __forceinline__ void fill_slot_lookup(const int16_t* tab, EncodeScrat
         }
       }
     }
-    sc->slot_of[e] = (int8_t)slot;
+    slot_of[e] = (int8_t)slot;
   }
 }
 
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_topk(EncodeScratch* sc, int num_exp, Se
       sc->nonfinite = (int)h[2047];
     }
     __syncthreads();
-    fill_slot_lookup(tab, sc);
+    fill_slot_lookup(tab, sc->slot_of);
     return;
   }
   int used = 0;
@@ -152,7 +152,49 @@ __global__ __launch_bounds__(256) void k_topk(EncodeScratch* sc, int num_exp, Se
     sc->nonfinite = (int)h[2047];
   }
   __syncthreads();
-  fill_slot_lookup(tab, sc);
+  fill_slot_lookup(tab, sc->slot_of);
+}
+
+// One value (bits u, column cv) against a table: the slot of the smallest
+// shared exponent above the value's exponent field (slot_s, -1: none ->
+// *bad), the magnitude on that slot's grid (Algorithm 1: hidden one made
+// explicit, shifted right by minDiff, truncated; the field holds 63 - ei
+// bits), and the words of the four planes.  *exact: the value's exponent is
+// itself shared (SEM = e + 1).
+struct Words4 {
+  uint32_t c, h16, t1, t2;
+};
+
+__device__ __forceinline__ Words4 encode_value(uint64_t u, int cv, const int8_t* slot_s,
+                                               const int* sem_s, int idx_bits, int in_value,
+                                               int* bad, int* exact) {
+  const int ei = in_value ? idx_bits : 0;
+  const int e = (int)((u >> 52) & 0x7FFu);
+  int slot = slot_s[e];
+  uint64_t F = 0;
+  if (slot < 0) {
+    *bad = 1;
+    slot = 0;
+  } else {
+    const int best = sem_s[slot];
+    *exact = best == e + 1;
+    const uint64_t frac = u & ((uint64_t(1) << 52) - 1);
+    const uint64_t sig = e ? ((uint64_t(1) << 52) | frac) : frac;
+    const int sh = 11 - ei - (best - (e ? e : 1));
+    F = (sh >= 0) ? (sig << sh) : ((-sh >= 64) ? 0 : (sig >> (-sh)));
+  }
+  Words4 w;
+  if (in_value) {
+    w.c = (uint32_t)cv;
+    w.h16 = (uint32_t)((u >> 63) << 15) | ((uint32_t)slot << (15 - idx_bits)) |
+            (uint32_t)(F >> 48);
+  } else {
+    w.c = (uint32_t)cv | (idx_bits > 0 ? ((uint32_t)slot << (32 - idx_bits)) : 0u);
+    w.h16 = (uint32_t)((u >> 63) << 15) | (uint32_t)(F >> 48);
+  }
+  w.t1 = (uint32_t)((F >> 32) & 0xFFFFu);
+  w.t2 = (uint32_t)(F & 0xFFFFFFFFu);
+  return w;
 }
 
 // Groups of 8 values per thread; writes 32 + 16 + 16 + 32 bytes per group
@@ -171,8 +213,6 @@ __global__ __launch_bounds__(256) void k_encode(const double* __restrict__ val,
   __syncthreads();
   // the slot goes to the top of the column word, or (in_value) below the
   // sign of the value word, whose magnitude field then loses idx_bits bits
-  const uint32_t shift = idx_bits > 0 ? 32u - (uint32_t)idx_bits : 0u;
-  const int ei = in_value ? idx_bits : 0;
   const int n_groups = (nnz + 7) >> 3;
   const int stride = gridDim.x * blockDim.x;
   int bad = 0;
@@ -205,30 +245,12 @@ __global__ __launch_bounds__(256) void k_encode(const double* __restrict__ val,
       const int j = g * 8 + k;
       uint32_t c = 0, h16 = 0, t116 = 0, t232 = 0;
       if (j < nnz) {
-        const uint64_t u = uv[k];
-        const int e = (int)((u >> 52) & 0x7FFu);
-        int slot = slot_s[e];
-        uint64_t F = 0;
-        if (slot < 0) {
-          bad = 1;
-          slot = 0;
-        } else {
-          const int best = sem_s[slot];
-          const uint64_t frac = u & ((uint64_t(1) << 52) - 1);
-          const uint64_t sig = e ? ((uint64_t(1) << 52) | frac) : frac;
-          const int sh = 11 - ei - (best - (e ? e : 1));
-          F = (sh >= 0) ? (sig << sh) : ((-sh >= 64) ? 0 : (sig >> (-sh)));
-        }
-        if (in_value) {
-          c = (uint32_t)cv[k];
-          h16 = (uint32_t)((u >> 63) << 15) | ((uint32_t)slot << (15 - idx_bits)) |
-                (uint32_t)(F >> 48);
-        } else {
-          c = (uint32_t)cv[k] | (idx_bits > 0 ? ((uint32_t)slot << shift) : 0u);
-          h16 = (uint32_t)((u >> 63) << 15) | (uint32_t)(F >> 48);
-        }
-        t116 = (uint32_t)((F >> 32) & 0xFFFFu);
-        t232 = (uint32_t)(F & 0xFFFFFFFFu);
+        int exact = 0;
+        const Words4 w = encode_value(uv[k], cv[k], slot_s, sem_s, idx_bits, in_value, &bad, &exact);
+        c = w.c;
+        h16 = w.h16;
+        t116 = w.t1;
+        t232 = w.t2;
       }
       cw[k] = c;
       t2[k] = t232;
@@ -247,12 +269,16 @@ __global__ __launch_bounds__(256) void k_encode(const double* __restrict__ val,
   if (bad) atomicOr(&sc->range_err, 2);
 }
 
-// Value read with s segments (exact; same decode as the SpMV operators).
-__device__ __forceinline__ double value_s(uint32_t c, uint32_t h, uint32_t t1, uint32_t t2,
-                                          const int* S, const ColSplit& cs, int s) {
+__device__ __forceinline__ int slot_in(uint32_t c, uint32_t h, const ColSplit& cs) {
+  return (int)(((c >> cs.shift) & cs.slot_mask) | ((h >> cs.hshift) & cs.hmask));
+}
+
+// Value read with s segments (exact; same decode as the SpMV operators);
+// sem is the shared exponent of the value's slot.
+__device__ __forceinline__ double value_s(uint32_t h, uint32_t t1, uint32_t t2, int sem,
+                                          const ColSplit& cs, int s) {
   const int fb = 63 - cs.ei;  // bits of the magnitude field
   const int W = fb - ((s == 1) ? 48 : (s == 2) ? 32 : 0);
-  const int sem = S[((c >> cs.shift) & cs.slot_mask) | ((h >> cs.hshift) & cs.hmask)];
   const uint64_t Ff = ((uint64_t)(h & cs.mag_mask) << 48) | ((uint64_t)t1 << 32) | (uint64_t)t2;
   const uint64_t F = Ff >> (fb - W);
   const double sc = bits_to_double((uint64_t)(sem - W) << 52);
@@ -262,19 +288,25 @@ __device__ __forceinline__ double value_s(uint32_t c, uint32_t h, uint32_t t1, u
 
 // Eight lanes per row, grid-stride over rows; the row maxima of the four
 // sums are reduced per workgroup and then merged into norm_bits (the bit
-// patterns of non-negative doubles order like the values).
+// patterns of non-negative doubles order like the values).  BLK: row r reads
+// the table of its block, bsem + (r / block_rows) * stride.
+template <bool BLK>
 __global__ __launch_bounds__(256) void k_eta(const int32_t* __restrict__ row_ptr, int n_rows,
                                              const double* __restrict__ val,
                                              const uint32_t* __restrict__ col_idx,
                                              const uint16_t* __restrict__ head,
                                              const uint16_t* __restrict__ tail1,
                                              const uint32_t* __restrict__ tail2,
-                                             EncodeScratch* sc, ColSplit cs) {
+                                             EncodeScratch* sc, ColSplit cs,
+                                             const int16_t* __restrict__ bsem, int block_rows,
+                                             int stride) {
   __shared__ int sem_s[GSE_MAX_EXP];
   __shared__ double red[4][kWaves];
   if (threadIdx.x < GSE_MAX_EXP) sem_s[threadIdx.x] = sc->sem[threadIdx.x];
   __syncthreads();
-  const int* S = sem_s;
+  auto table_of = [&](int r) -> const int16_t* {
+    return BLK ? bsem + (size_t)(r / block_rows) * stride : nullptr;
+  };
   const int sub = threadIdx.x & 7;
   const int grp = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
   const int ngrp = (gridDim.x * blockDim.x) >> 3;
@@ -292,12 +324,15 @@ __global__ __launch_bounds__(256) void k_eta(const int32_t* __restrict__ row_ptr
     return Ent{val[j], col_idx[j], head[j], tail1[j], tail2[j]};
   };
   // adds the four terms of entry x, or exact zeros when !use (the sums are
-  // non-negative, so a + 0.0 == a) -- no branch for the loads to sink into
-  auto add_terms = [&](double (&a)[4], const Ent& x, bool use) {
+  // non-negative, so a + 0.0 == a) -- no branch for the loads to sink into;
+  // Sb: the row's block table (BLK)
+  auto add_terms = [&](double (&a)[4], const Ent& x, bool use, const int16_t* Sb) {
+    const int slot = slot_in(x.c, x.h, cs);
+    const int sem = BLK ? (int)Sb[slot] : sem_s[slot];
     const double t0 = fabs(x.v);
-    const double t1 = fabs(x.v - value_s(x.c, x.h, x.t1, x.t2, S, cs, 1));
-    const double t2 = fabs(x.v - value_s(x.c, x.h, x.t1, x.t2, S, cs, 2));
-    const double t3 = fabs(x.v - value_s(x.c, x.h, x.t1, x.t2, S, cs, 3));
+    const double t1 = fabs(x.v - value_s(x.h, x.t1, x.t2, sem, cs, 1));
+    const double t2 = fabs(x.v - value_s(x.h, x.t1, x.t2, sem, cs, 2));
+    const double t3 = fabs(x.v - value_s(x.h, x.t1, x.t2, sem, cs, 3));
     a[0] += use ? t0 : 0.0;
     a[1] += use ? t1 : 0.0;
     a[2] += use ? t2 : 0.0;
@@ -321,13 +356,15 @@ __global__ __launch_bounds__(256) void k_eta(const int32_t* __restrict__ row_ptr
     const int b0 = has2 ? row_ptr[r2] : 0, b1 = has2 ? row_ptr[r2 + 1] : 0;
     double a[4] = {0.0, 0.0, 0.0, 0.0}, b[4] = {0.0, 0.0, 0.0, 0.0};
     if (nnz > 0) {
+      const int16_t* Sa = table_of(r);
+      const int16_t* Sb = table_of(has2 ? r2 : r);
       const int ja = a0 + sub, jb = b0 + sub;
       const Ent ea = load_ent(max(min(ja, a1 - 1), 0));
       const Ent eb = load_ent(max(min(jb, b1 - 1), 0));
-      add_terms(a, ea, ja < a1);
-      add_terms(b, eb, jb < b1);
-      for (int j = ja + 8; j < a1; j += 8) add_terms(a, load_ent(j), true);
-      for (int j = jb + 8; j < b1; j += 8) add_terms(b, load_ent(j), true);
+      add_terms(a, ea, ja < a1, Sa);
+      add_terms(b, eb, jb < b1, Sb);
+      for (int j = ja + 8; j < a1; j += 8) add_terms(a, load_ent(j), true, Sa);
+      for (int j = jb + 8; j < b1; j += 8) add_terms(b, load_ent(j), true, Sb);
     }
     finish(a);
     if (has2) finish(b);
@@ -350,6 +387,136 @@ __global__ __launch_bounds__(256) void k_eta(const int32_t* __restrict__ row_ptr
         bits)
       atomicMax(&sc->norm_bits[threadIdx.x], bits);
   }
+}
+
+// Per-row-block tables: workgroup b owns rows [b*R, min((b+1)*R, n_rows)).
+// The table comes from the exponent histogram of the sample (row
+// sample_rows[b], or the whole block when sample_rows is null) by the rules
+// of k_topk; then the block's own largest exponent goes into the next free
+// slot, or the last, if the table misses it.  The block's values are encoded
+// against that table with one thread per value.  The last workgroup also
+// zeroes the planes' padding.
+__global__ __launch_bounds__(256) void k_blk_encode(
+    const int32_t* __restrict__ row_ptr, int n_rows, const int32_t* __restrict__ col,
+    const double* __restrict__ val, int nnz, int pad, int block_rows,
+    const int32_t* __restrict__ sample_rows, int num_exp, int idx_bits, int in_value, int stride,
+    int16_t* __restrict__ block_sem, EncodeScratch* sc, uint32_t* __restrict__ col_idx,
+    uint16_t* __restrict__ head, uint16_t* __restrict__ tail1, uint32_t* __restrict__ tail2) {
+  __shared__ uint32_t h[2048];
+  __shared__ unsigned char taken[2048];
+  __shared__ int8_t slot_s[2048];
+  __shared__ unsigned long long red[kWaves];
+  __shared__ int chosen[GSE_MAX_EXP];
+  __shared__ int sem_s[GSE_MAX_EXP];
+  __shared__ int16_t tab[GSE_MAX_EXP];
+  const int tid = threadIdx.x;
+  const int b = blockIdx.x;
+  const int r0 = (int)((long long)b * block_rows);
+  const int r1 = (int)min((long long)r0 + block_rows, (long long)n_rows);
+  const int j0 = row_ptr[r0], j1 = row_ptr[r1];
+  for (int i = tid; i < 2048; i += blockDim.x) {
+    h[i] = 0u;
+    taken[i] = 0;
+  }
+  __syncthreads();
+  int s0 = j0, s1 = j1;
+  bool bad_sample = false;
+  if (sample_rows) {
+    const int sr = sample_rows[b];
+    if (sr < r0 || sr >= r1) {
+      bad_sample = true;
+      s0 = s1 = 0;
+    } else {
+      s0 = row_ptr[sr];
+      s1 = row_ptr[sr + 1];
+    }
+  }
+  for (int j = s0 + tid; j < s1; j += blockDim.x) atomicAdd(&h[(double_to_bits(val[j]) >> 52) & 0x7FFu], 1u);
+  unsigned long long me = 0;
+  int nonfinite = 0;
+  for (int j = j0 + tid; j < j1; j += blockDim.x) {
+    const unsigned e = (unsigned)((double_to_bits(val[j]) >> 52) & 0x7FFu);
+    if (e == 2047u) ++nonfinite;
+    else me = e > me ? e : me;
+  }
+  if (nonfinite) atomicAdd(&sc->nonfinite, nonfinite);
+  if (bad_sample && tid == 0) atomicOr(&sc->range_err, 4);
+  const int max_e = (int)block_max_u64(me, red);  // its barriers also end the histogram
+  int used = 0;
+  for (int slot = 0; slot < num_exp; ++slot) {
+    unsigned long long best = 0;
+    for (int e = 1 + tid; e <= 2046; e += blockDim.x) {
+      if (!taken[e] && h[e] > 0) {
+        const unsigned long long key = ((unsigned long long)h[e] << 11) | (unsigned long long)e;
+        best = key > best ? key : best;
+      }
+    }
+    best = block_max_u64(best, red);
+    if (best == 0) break;
+    const int e = (int)(best & 0x7FFu);
+    if (tid == 0) {
+      taken[e] = 1;
+      chosen[used] = e;
+    }
+    ++used;
+    __syncthreads();
+  }
+  unsigned long long ms = 0;
+  for (int e = 1 + tid; e <= 2046; e += blockDim.x)
+    if (h[e] > 0) ms = (unsigned long long)e > ms ? (unsigned long long)e : ms;
+  const int sample_max = (int)block_max_u64(ms, red);
+  if (tid == 0) {
+    if (used == 0) {
+      chosen[0] = 1023;
+      used = 1;
+    } else if (!taken[sample_max]) {
+      chosen[used - 1] = sample_max;
+    }
+    int range_err = 0;
+    for (int i = 0; i < used; ++i)
+      if (chosen[i] < 63) range_err = 1;
+    if (max_e > 0) {
+      bool present = false;
+      for (int i = 0; i < used; ++i) present = present || chosen[i] == max_e;
+      if (!present) {
+        if (used < num_exp) ++used;
+        chosen[used - 1] = max_e;
+        if (max_e < 63) range_err = 1;
+      }
+    }
+    for (int i = 0; i < GSE_MAX_EXP; ++i) {
+      tab[i] = i < used ? (int16_t)(chosen[i] + 1) : (int16_t)0;
+      sem_s[i] = tab[i];
+    }
+    if (range_err) atomicOr(&sc->range_err, 1);
+    atomicMax(&sc->used, used);
+  }
+  __syncthreads();
+  for (int i = tid; i < stride; i += blockDim.x) block_sem[(size_t)b * stride + i] = tab[i];
+  fill_slot_lookup(tab, slot_s);
+  __syncthreads();
+  int bad = 0;
+  unsigned long long covered = 0;
+  for (int j = j0 + tid; j < j1; j += blockDim.x) {
+    int exact = 0;
+    const Words4 w = encode_value(double_to_bits(val[j]), col[j], slot_s, sem_s, idx_bits,
+                                  in_value, &bad, &exact);
+    col_idx[j] = w.c;
+    head[j] = (uint16_t)w.h16;
+    tail1[j] = (uint16_t)w.t1;
+    tail2[j] = w.t2;
+    covered += (unsigned long long)exact;
+  }
+  if (b == (int)gridDim.x - 1) {
+    for (int j = nnz + tid; j < pad; j += blockDim.x) {
+      col_idx[j] = 0u;
+      head[j] = 0;
+      tail1[j] = 0;
+      tail2[j] = 0u;
+    }
+  }
+  if (covered) atomicAdd(&sc->covered, covered);
+  if (bad) atomicOr(&sc->range_err, 2);
 }
 
 // Zero `n` 8-byte words with one workgroup.
@@ -383,8 +550,31 @@ hipError_t launch_encode(const int32_t* row_ptr, const int32_t* col, const doubl
                      in_value ? 1 : 0, A->col_idx, A->head, A->tail1, A->tail2);
   int rbk = (n_rows + 31) / 32;
   rbk = rbk < 1 ? 1 : (rbk > 4096 ? 4096 : rbk);
-  hipLaunchKernelGGL(k_eta, dim3(rbk), dim3(256), 0, st, row_ptr, n_rows, val, A->col_idx, A->head,
-                     A->tail1, A->tail2, sc, col_split(A->idx_bits, in_value));
+  hipLaunchKernelGGL(k_eta<false>, dim3(rbk), dim3(256), 0, st, row_ptr, n_rows, val, A->col_idx,
+                     A->head, A->tail1, A->tail2, sc, col_split(A->idx_bits, in_value),
+                     (const int16_t*)nullptr, 1, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_blocks(const int32_t* row_ptr, const int32_t* col, const double* val,
+                                int32_t n_rows, int32_t nnz, int32_t num_exp,
+                                const int32_t* sample_rows, gse_matrix* A, EncodeScratch* sc,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, st,
+                     reinterpret_cast<unsigned long long*>(sc),
+                     (int)(sizeof(EncodeScratch) / 8));
+  if (n_rows < 1) return hipGetLastError();
+  const int n_blocks = (int)(((int64_t)n_rows + A->block_rows - 1) / A->block_rows);
+  const int pad = (int)((nnz + kPadTo - 1) / kPadTo * kPadTo);
+  const bool in_value = A->idx_layout == GSE_IDX_VALUE;
+  hipLaunchKernelGGL(k_blk_encode, dim3(n_blocks), dim3(256), 0, st, row_ptr, n_rows, col, val, nnz,
+                     pad, A->block_rows, sample_rows, num_exp, A->idx_bits, in_value ? 1 : 0,
+                     A->block_stride, A->block_sem, sc, A->col_idx, A->head, A->tail1, A->tail2);
+  int rbk = (n_rows + 31) / 32;
+  rbk = rbk < 1 ? 1 : (rbk > 4096 ? 4096 : rbk);
+  hipLaunchKernelGGL(k_eta<true>, dim3(rbk), dim3(256), 0, st, row_ptr, n_rows, val, A->col_idx,
+                     A->head, A->tail1, A->tail2, sc, col_split(A->idx_bits, in_value),
+                     (const int16_t*)A->block_sem, A->block_rows, A->block_stride);
   return hipGetLastError();
 }
 

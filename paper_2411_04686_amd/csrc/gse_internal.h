@@ -150,6 +150,13 @@ __host__ __device__ inline ColSplit col_split(int idx_bits, bool in_value = fals
 // Scale table entries: one per slot.
 constexpr int kScaleEntries = GSE_MAX_EXP;
 
+// Per-row-block tables: the row-vector workgroup stages the tables of every
+// block its rows touch.  A workgroup holds at most 2048 rows (one lane per
+// row) and a block at least GSE_MIN_BLOCK_ROWS, so it touches at most
+// (2048 - 1) / GSE_MIN_BLOCK_ROWS + 2 blocks of up to 64 entries each.
+constexpr int kRvMaxRows = 64 * kRvBatch * kWaves;
+constexpr int kBlockTabEntries = ((kRvMaxRows - 1) / GSE_MIN_BLOCK_ROWS + 2) * GSE_MAX_EXP;
+
 // ------------------------------------------------------------- launchers --
 struct SpmvOperand {
   // GSE planes (fmt 1..3) or CSR values (fmt 0)
@@ -168,6 +175,11 @@ struct SpmvOperand {
   int32_t max_row;           // longest row (<= kShortRow selects the short-row tiles)
   ColSplit split;            // column / slot fields of the column words
   int16_t sem[GSE_MAX_EXP];
+  // per-row-block tables (null: the one table `sem`): row r reads
+  // block_sem[(r / block_rows) * block_stride + slot]; row-vector schedule only
+  const int16_t* block_sem;
+  int32_t block_rows;
+  int32_t block_stride;
 };
 
 struct SpmvEpilogue {
@@ -201,6 +213,13 @@ struct EncodeScratch {
 hipError_t launch_encode(const int32_t* row_ptr, const int32_t* col, const double* val,
                          int32_t n_rows, int32_t nnz, int32_t num_exp, const int16_t* sem_in,
                          gse_matrix* A, EncodeScratch* sc, hipStream_t st);
+// Per-row-block tables: one workgroup per block chooses its table (from the
+// block's values, or from sample_rows[b] when given), encodes the block, then
+// the perturbations with every row's own table.
+hipError_t launch_encode_blocks(const int32_t* row_ptr, const int32_t* col, const double* val,
+                                int32_t n_rows, int32_t nnz, int32_t num_exp,
+                                const int32_t* sample_rows, gse_matrix* A, EncodeScratch* sc,
+                                hipStream_t st);
 
 int32_t n_tiles_for(int64_t nnz, int32_t tile_nnz);
 

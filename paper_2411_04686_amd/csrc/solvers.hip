@@ -401,9 +401,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_cg_small(SolverState* Sg, Spm
 
 bool cg_small_path(const SpmvOperand& op) {
   // (the eight slot exponents held in scalar words cover index widths <= 3
-  // in the column word)
+  // in the column word and one table for the whole matrix)
   return op.n_rows <= kSmallRows && op.max_row <= kSmallRow && op.split.slot_mask <= 7u &&
-         op.split.hmask == 0u;
+         op.split.hmask == 0u && op.block_sem == nullptr;
 }
 
 template <int RPT, int L>

@@ -1093,24 +1093,47 @@ hipError_t launch_f(const SpmvOperand& A, const double* x, double* y, const Spmv
 // group then combines its L partial sums with a fixed butterfly.  No LDS
 // staging and no barriers: every wave is independent, which keeps many
 // loads in flight per compute unit.
-template <int FMT, int L>
+//
+// BLK: per-row-block tables.  The workgroup's rows [wr0, wr1) touch the
+// blocks wr0 / R .. (wr1 - 1) / R; their tables are staged back to back in
+// LDS and a row reads its own at offset (r / R - first block) * stride.
+template <int FMT, int L, bool BLK = false>
 __global__ __launch_bounds__(kWG) void k_spmv_rv(SpmvOperand A, const double* __restrict__ x,
                                                  double* __restrict__ y, SpmvEpilogue ep) {
   constexpr int G = 64 / L;
   constexpr int U = kRvBatch;
   constexpr int RB = G * U;  // rows per wave
-  __shared__ uint32_t scale_tab[kScaleEntries];
+  __shared__ uint32_t scale_tab[BLK ? kBlockTabEntries : kScaleEntries];
   __shared__ double red[kWaves];
 
   if (ep.gate && *ep.gate) return;
-  build_scale<FMT>(A.sem, scale_tab, A.split.ei);
+  const int wtile = xcd_tile(blockIdx.x, gridDim.x);
+  int b0 = 0;
+  if constexpr (BLK) {
+    const int wr0 = wtile * (kWaves * RB);
+    const int wr1 = min(wr0 + kWaves * RB, A.n_rows);
+    b0 = wr0 / A.block_rows;
+    const int n = wr1 > wr0 ? ((wr1 - 1) / A.block_rows - b0 + 1) * A.block_stride : 0;
+    build_scale_n<FMT>(A.block_sem + (size_t)b0 * A.block_stride, n, scale_tab, A.split.ei);
+  } else {
+    build_scale<FMT>(A.sem, scale_tab, A.split.ei);
+  }
   const DecodeCtx scale{scale_tab, A.split};
   __syncthreads();
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane / L, sub = lane % L;
-  const int wblk = xcd_tile(blockIdx.x, gridDim.x) * kWaves + wave;
+  const int wblk = wtile * kWaves + wave;
   const int r0 = wblk * RB;
   double acc = 0.0;
+  int toff[U];  // BLK: offset of each row's table in scale_tab
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    toff[u] = 0;
+    if constexpr (BLK) {
+      const int rr = min(r0 + u * G + g, A.n_rows - 1);
+      toff[u] = (rr / A.block_rows - b0) * A.block_stride;
+    }
+  }
 
   int s0[U], s1[U];
   int mylen = 0;
@@ -1146,7 +1169,12 @@ __global__ __launch_bounds__(kWG) void k_spmv_rv(SpmvOperand A, const double* __
     int column[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      d[u] = decode<FMT>(e[u].c, e[u].h, e[u].t1, e[u].t2, e[u].v, scale, column[u]);
+      if constexpr (BLK) {
+        const DecodeCtx own{scale_tab + toff[u], A.split};
+        d[u] = decode<FMT>(e[u].c, e[u].h, e[u].t1, e[u].t2, e[u].v, own, column[u]);
+      } else {
+        d[u] = decode<FMT>(e[u].c, e[u].h, e[u].t1, e[u].t2, e[u].v, scale, column[u]);
+      }
       if (!ok[u]) column[u] = 0;
     }
 #pragma unroll
@@ -1185,28 +1213,35 @@ __global__ __launch_bounds__(kWG) void k_spmv_rv(SpmvOperand A, const double* __
   }
 }
 
-template <int FMT, int L>
+template <int FMT, int L, bool BLK = false>
 hipError_t launch_rv(const SpmvOperand& A, const double* x, double* y, const SpmvEpilogue& ep,
                      hipStream_t st) {
   constexpr int rows_per_wg = (64 / L) * kRvBatch * kWaves;
+  static_assert(rows_per_wg <= kRvMaxRows, "staged block tables sized for kRvMaxRows rows");
+  if constexpr (BLK) {
+    // the staged tables fit kBlockTabEntries only for blocks this tall
+    if (A.n_rows < 1 || !A.block_sem || A.block_rows < GSE_MIN_BLOCK_ROWS ||
+        A.block_stride < 1 || A.block_stride > GSE_MAX_EXP)
+      return hipErrorInvalidValue;
+  }
   int g = (A.n_rows + rows_per_wg - 1) / rows_per_wg;
   if (g < 1) g = 1;
   if (ep.grid_out) *ep.grid_out = g;
-  hipLaunchKernelGGL((k_spmv_rv<FMT, L>), dim3(g), dim3(kWG), 0, st, A, x, y, ep);
+  hipLaunchKernelGGL((k_spmv_rv<FMT, L, BLK>), dim3(g), dim3(kWG), 0, st, A, x, y, ep);
   return hipGetLastError();
 }
 
-template <int FMT>
+template <int FMT, bool BLK = false>
 hipError_t launch_rv_f(const SpmvOperand& A, const double* x, double* y, const SpmvEpilogue& ep,
                        hipStream_t st) {
   switch (A.rv_lanes) {
-    case 1: return launch_rv<FMT, 1>(A, x, y, ep, st);
-    case 2: return launch_rv<FMT, 2>(A, x, y, ep, st);
-    case 4: return launch_rv<FMT, 4>(A, x, y, ep, st);
-    case 8: return launch_rv<FMT, 8>(A, x, y, ep, st);
-    case 16: return launch_rv<FMT, 16>(A, x, y, ep, st);
-    case 32: return launch_rv<FMT, 32>(A, x, y, ep, st);
-    case 64: return launch_rv<FMT, 64>(A, x, y, ep, st);
+    case 1: return launch_rv<FMT, 1, BLK>(A, x, y, ep, st);
+    case 2: return launch_rv<FMT, 2, BLK>(A, x, y, ep, st);
+    case 4: return launch_rv<FMT, 4, BLK>(A, x, y, ep, st);
+    case 8: return launch_rv<FMT, 8, BLK>(A, x, y, ep, st);
+    case 16: return launch_rv<FMT, 16, BLK>(A, x, y, ep, st);
+    case 32: return launch_rv<FMT, 32, BLK>(A, x, y, ep, st);
+    case 64: return launch_rv<FMT, 64, BLK>(A, x, y, ep, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1262,6 +1297,14 @@ int32_t n_tiles_for(int64_t nnz, int32_t tile_nnz) {
 
 hipError_t launch_spmv(int fmt, const SpmvOperand& A, const double* x, double* y,
                        const SpmvEpilogue& ep, hipStream_t st) {
+  if (A.block_sem) {  // per-row-block tables: the row-vector schedule only
+    switch (fmt) {
+      case 1: return launch_rv_f<1, true>(A, x, y, ep, st);
+      case 2: return launch_rv_f<2, true>(A, x, y, ep, st);
+      case 3: return launch_rv_f<3, true>(A, x, y, ep, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (A.rv_lanes > 0) {
     switch (fmt) {
       case 0: return launch_rv_f<0>(A, x, y, ep, st);

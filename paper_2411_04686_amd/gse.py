@@ -39,7 +39,9 @@ class gse_matrix(C.Structure):
                 ("tail1", C.c_void_p), ("tail2", C.c_void_p), ("tile_row", C.c_void_p),
                 ("tile_cap", C.c_int32), ("tile_nnz", C.c_int32), ("n_tiles", C.c_int32),
                 ("rv_lanes", C.c_int32), ("max_row_nnz", C.c_int32),
-                ("eta", C.c_double * 3), ("exact_frac", C.c_double)]
+                ("eta", C.c_double * 3), ("exact_frac", C.c_double),
+                ("block_rows", C.c_int32), ("block_stride", C.c_int32),
+                ("block_sem", C.c_void_p)]
 
 
 class gse_csr(C.Structure):
@@ -118,6 +120,9 @@ _SIGS = {
     "gse_encode_static": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int64, C.c_int32,
                                       _P, C.POINTER(gse_matrix), _P]),
     "gse_encode_static_scratch_bytes": (C.c_size_t, []),
+    "gse_encode_blocks": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int64, C.c_int32,
+                                      C.c_int32, _P, C.POINTER(gse_matrix), _P, C.c_size_t, _P]),
+    "gse_block_table_entries": (C.c_int64, [C.c_int32, C.c_int32, C.c_int32]),
     "gse_plan": (C.c_int32, [C.POINTER(gse_matrix), C.c_int32, C.c_int32, _P]),
     "gse_csr_plan": (C.c_int32, [C.POINTER(gse_csr), C.c_int32, C.c_int32, _P]),
     "gse_spmv": (C.c_int32, [C.POINTER(gse_matrix), C.c_int32, _P, _P, _P]),
@@ -223,6 +228,18 @@ def gse_encode(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, sem_in, A: gse_m
     return _check(lib().gse_encode(_ptr(row_ptr), _ptr(col), _ptr(val), n_rows, n_cols, nnz,
                                    num_exp, si, C.byref(A), _ptr(ws), ws.numel() * ws.element_size(),
                                    _stream(stream)), "gse_encode")
+
+
+def gse_encode_blocks(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, block_rows, sample_rows,
+                      A: gse_matrix, ws, stream=None) -> int:
+    return _check(lib().gse_encode_blocks(_ptr(row_ptr), _ptr(col), _ptr(val), n_rows, n_cols, nnz,
+                                          num_exp, block_rows, _ptr(sample_rows), C.byref(A),
+                                          _ptr(ws), ws.numel() * ws.element_size(),
+                                          _stream(stream)), "gse_encode_blocks")
+
+
+def gse_block_table_entries(n_rows: int, block_rows: int, num_exp: int) -> int:
+    return int(lib().gse_block_table_entries(n_rows, block_rows, num_exp))
 
 
 def gse_encode_static(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, sem_in, A: gse_matrix,
@@ -475,7 +492,11 @@ class GseMatrix:
     """Device planes of one encoded matrix plus its ``gse_matrix`` record."""
 
     def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n_cols: int,
-                 num_exp: int = 8, sem_in=None, stream=None, idx_layout: int = IDX_AUTO):
+                 num_exp: int = 8, sem_in=None, stream=None, idx_layout: int = IDX_AUTO,
+                 block_rows: int = 0, sample_rows: torch.Tensor = None):
+        """block_rows > 0: one table per block of that many rows
+        (gse_encode_blocks), chosen from the device rows ``sample_rows``
+        (one per block) or, when None, from each block's values."""
         dev = row_ptr.device
         n_rows = row_ptr.numel() - 1
         nnz = val.numel()
@@ -497,7 +518,16 @@ class GseMatrix:
         A.tile_cap = cap
         A.idx_layout = idx_layout
         self.A = A
-        gse_encode(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, sem_in, A, self.ws, stream)
+        if block_rows:
+            if sem_in is not None:
+                raise ValueError("per-block tables are chosen by the encoder (no sem_in)")
+            self.block_sem = _alloc(max(gse_block_table_entries(n_rows, block_rows, num_exp), 1),
+                                    torch.int16, dev)
+            A.block_sem = self.block_sem.data_ptr()
+            gse_encode_blocks(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, block_rows,
+                              sample_rows, A, self.ws, stream)
+        else:
+            gse_encode(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, sem_in, A, self.ws, stream)
 
     @property
     def n_rows(self):
@@ -514,6 +544,12 @@ class GseMatrix:
     @property
     def eta(self):
         return list(self.A.eta)
+
+    def block_tables(self):
+        """int16 [n_blocks, 2^idx_bits] host copy of the per-block tables."""
+        stride = self.A.block_stride
+        n = gse_block_table_entries(self.A.n_rows, self.A.block_rows, self.A.num_exp)
+        return self.block_sem[:n].cpu().numpy().reshape(-1, stride)
 
     def planes(self):
         """(col_idx u32, head u16, tail1 u16, tail2 u32) as numpy arrays (host copy)."""

@@ -125,3 +125,36 @@ def test_column_limit_follows_the_index_width(lib):
         st = L.gse_encode(fake, fake, fake, 1, n_cols, 1, k, None, C.byref(A), fake, 1 << 20,
                           None)
         assert st == want, (k, n_cols, st)
+
+
+def test_block_tables_host_side(lib):
+    """Per-row-block tables: the size query and the host checks of
+    gse_encode_blocks (refused before any device work)."""
+    import sys
+    sys.path.insert(0, ROOT)
+    from paper_2411_04686_amd import gse as G
+    L = G.lib()
+    assert G.gse_block_table_entries(1000, 128, 8) == 8 * 8
+    assert G.gse_block_table_entries(1024, 128, 5) == 8 * 8
+    assert G.gse_block_table_entries(1025, 128, 64) == 9 * 64
+    assert G.gse_block_table_entries(300, 128, 1) == 3
+    assert G.gse_block_table_entries(0, 128, 8) == 0
+    assert G.gse_block_table_entries(10, 0, 8) == 0 and G.gse_block_table_entries(10, 128, 65) == 0
+    fake = C.c_void_p(256)
+    A = G.gse_matrix()
+    A.col_idx = A.head = A.tail1 = A.tail2 = A.tile_row = 256
+    A.tile_cap = 1 << 20
+    # blocks below the minimum, then a NULL table buffer: argument errors
+    st = L.gse_encode_blocks(fake, fake, fake, 1000, 1000, 5000, 8, 64, None, C.byref(A), fake,
+                             1 << 20, None)
+    assert st == -1 and b"block_rows" in L.gse_last_error()
+    st = L.gse_encode_blocks(fake, fake, fake, 1000, 1000, 5000, 8, 128, None, C.byref(A), fake,
+                             1 << 20, None)
+    assert st == -1 and b"block_sem" in L.gse_last_error()
+    # a matrix that claims block tables it does not have is refused
+    A.num_exp, A.idx_bits, A.idx_layout = 8, 3, 1
+    A.row_ptr = 256
+    A.tile_nnz, A.n_tiles, A.nnz = 1024, 1, 10
+    A.block_rows, A.block_stride = 128, 8
+    assert L.gse_spmv(C.byref(A), 1, fake, fake, None) == -1
+    assert b"per-block" in L.gse_last_error()
