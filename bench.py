@@ -491,9 +491,8 @@ def leg_blocks(torch, G, seed, copies, block_rows=4096, A_cg=None, b_cg=None, x_
     (128^3, 16 slabs whose coefficients sit at levels spread over eight
     decades, one decade within a slab): encode time of the global table, of
     exact block tables and of tables from one drawn row per block; SpMV time
-    per segment count over rotated copies (block tables run the row-vector
-    schedule; the global table is timed on its own schedule and on the same
-    row-vector one); error against the host FP64 product with x = 1,
+    per segment count over rotated copies (each on its default schedule);
+    error against the host FP64 product with x = 1,
     norm-wise and per row; eta_s and the share of exactly represented
     exponents.  With A_cg given, also the stepped CG on that system with
     exact block tables."""
@@ -515,7 +514,6 @@ def leg_blocks(torch, G, seed, copies, block_rows=4096, A_cg=None, b_cg=None, x_
                 "blocks_sampled": {"block_rows": block_rows, "sample_rows": sr}}
     out = {"workload": "layered3d_128^3_7pt_16slabs_8+1decades", "n_rows": A.n_rows,
            "nnz": A.nnz, "block_rows": block_rows, "seed": seed, "x": "ones"}
-    lanes = None
     for name, kw in variants.items():
         mats = [G.GseMatrix(rp.clone(), ci, va, A.n_cols, **kw) for _ in range(copies)]
         M = mats[0]
@@ -532,9 +530,7 @@ def leg_blocks(torch, G, seed, copies, block_rows=4096, A_cg=None, b_cg=None, x_
             enc_ms.append((time.perf_counter() - t0) * 1e3)
         rec = {"encode_ms": round(float(np.median(enc_ms)), 3), "eta": [float(e) for e in M.eta],
                "exact_frac": round(float(M.A.exact_frac), 4), "rv_lanes": int(M.A.rv_lanes),
-               "kernel": kernel_name(M.A) if not kw else f"k_spmv_rv<s, {M.A.rv_lanes}, blocks>"}
-        if kw:
-            lanes = M.A.rv_lanes
+               "kernel": kernel_name(M.A).replace(">", ", blocks>") if kw else kernel_name(M.A)}
         tables = (G.gse_block_table_entries(A.n_rows, block_rows, 8) * 2) if kw else 0
         for s, pb in ((1, 6), (2, 8), (3, 12)):
             us = rotated_launch_us(torch, stream,
@@ -546,16 +542,6 @@ def leg_blocks(torch, G, seed, copies, block_rows=4096, A_cg=None, b_cg=None, x_
                             **host_product_errors(ys[0], ref),
                             "rowwise": componentwise_errors(ys[0], ref, absref)}
         out[name] = rec
-        del mats
-    if lanes:
-        mats = [G.GseMatrix(rp.clone(), ci, va, A.n_cols) for _ in range(copies)]
-        for m in mats:
-            m.plan(1024, lanes)
-        us = rotated_launch_us(torch, stream,
-                               [lambda m=m, y=y: m.spmv(1, xs, y) for m, y in zip(mats, ys)])
-        nbytes = spmv_bytes(A.n_rows, A.n_cols, A.nnz, 6)
-        out["global_rowvector_s1"] = {"rv_lanes": int(lanes), "mean_us": round(us, 2),
-                                      "GBps": round(nbytes / (us * 1e-6) / 1e9, 1)}
         del mats
     del rp, ci, va, ys
     if A_cg is not None:

@@ -192,11 +192,13 @@ gse_status gse_encode(const int32_t* row_ptr, const int32_t* col, const double* 
  *                 unused slots 0).  Out: block_rows, block_stride, eta,
  *                 exact_frac (measured against each block's own exponents),
  *                 num_used (the most slots any block uses); sem[] is zero.
- * The SpMV of such a matrix runs the row-vector schedule (rv_lanes > 0; the
- * encoder picks the lanes from the mean row length, gse_plan / gse_autotune
- * may change them; rv_lanes 0 there means the same default), reading each
- * row's table from LDS.  gse_spmv, gse_cg and gse_gmres take it; the batched
- * solver and the server do not (GSE_ERR_ARG).
+ * The SpMV of such a matrix stages each row's table in LDS and runs the
+ * row-tile schedule (rv_lanes 0 with 1024-non-zero tiles, rows of at most
+ * eight non-zeros) or the row-vector one (rv_lanes > 0; with rv_lanes 0 on
+ * longer rows, lanes from the mean row length).  The encoder and
+ * gse_plan(A, 1024, -1) choose between them by the longest row;
+ * gse_autotune times both.  gse_spmv, gse_cg and gse_gmres take such a
+ * matrix; the batched solver and the server do not (GSE_ERR_ARG).
  * Errors: those of gse_encode; GSE_ERR_ARG for block_rows below the minimum,
  * a NULL block_sem, or a sample row outside its block.  Synchronizes `stream`. */
 gse_status gse_encode_blocks(const int32_t* row_ptr, const int32_t* col, const double* val,

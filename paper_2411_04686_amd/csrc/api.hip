@@ -45,9 +45,12 @@ int32_t auto_rv(int64_t nnz, int32_t n_rows, int32_t max_row) {
   return 0;
 }
 
-// Lanes per row of the row-vector schedule for per-block tables: the
-// power of two nearest above half the mean row length (1 .. 64).
-int32_t block_lanes(int64_t nnz, int32_t n_rows) {
+// Default schedule for per-block tables: the row-tile ring (rv_lanes 0 with
+// 1024-non-zero tiles) when no row holds more than eight non-zeros, else the
+// row-vector schedule with the power of two nearest above half the mean row
+// length (1 .. 64) lanes per row.
+int32_t block_lanes(int64_t nnz, int32_t n_rows, int32_t max_row) {
+  if (max_row <= 8 && nnz >= kDefaultTile) return 0;
   const int64_t half = n_rows > 0 ? (nnz + 2 * (int64_t)n_rows - 1) / (2 * (int64_t)n_rows) : 1;
   int32_t L = 1;
   while (L < 64 && L < half) L *= 2;
@@ -97,7 +100,6 @@ SpmvOperand operand_of(const gse_matrix* A) {
     o.block_sem = A->block_sem;
     o.block_rows = A->block_rows;
     o.block_stride = A->block_stride;
-    if (o.rv_lanes == 0) o.rv_lanes = block_lanes(A->nnz, A->n_rows);
   }
   return o;
 }
@@ -225,7 +227,7 @@ gse_status encode_blocks(const int32_t* row_ptr, const int32_t* col, const doubl
   if (ps != GSE_OK) return ps;
   A->tile_nnz = kDefaultTile;
   A->n_tiles = nt;
-  A->rv_lanes = block_lanes(nnz, n_rows);
+  A->rv_lanes = block_lanes(nnz, n_rows, mr);
   A->max_row_nnz = mr;
   for (int i = 0; i < GSE_MAX_EXP; ++i) A->sem[i] = 0;
   A->num_used = h.used;
@@ -338,7 +340,7 @@ gse_status gse_plan(gse_matrix* A, int32_t tile_nnz, int32_t rv_lanes, void* str
   A->tile_nnz = tile_nnz;
   A->n_tiles = nt;
   A->rv_lanes = rv;
-  if (A->block_rows > 0 && rv <= 0) A->rv_lanes = block_lanes(A->nnz, A->n_rows);
+  if (A->block_rows > 0 && rv_lanes == -1) A->rv_lanes = block_lanes(A->nnz, A->n_rows, mr);
   A->max_row_nnz = mr;
   return GSE_OK;
 }

@@ -96,7 +96,7 @@ hipError_t time_one(int fmt, SpmvOperand op, const double* x, double* y, int rep
 gse_status autotune(int fmt, int segs, SpmvOperand op, const int32_t* row_ptr, int32_t* tile_row,
                     int32_t tile_cap, int32_t max_row, const double* x, double* y, int32_t reps,
                     hipStream_t st, int32_t* out_tile, int32_t* out_rv, int32_t* out_tiles) {
-  const bool blocks = op.block_sem != nullptr;  // per-block tables: row-vector only
+  const bool blocks = op.block_sem != nullptr;  // per-block tables
   const std::string k = key_of(fmt, segs, op.n_rows, op.nnz, max_row) + (blocks ? "_b" : "");
   {
     std::lock_guard<std::mutex> lock(g_mu);
@@ -115,7 +115,8 @@ gse_status autotune(int fmt, int segs, SpmvOperand op, const int32_t* row_ptr, i
     int tile, rv;
   };
   std::vector<Cand> cands;
-  if (blocks) {
+  if (blocks) {  // the row-tile ring (short rows) or the row-vector schedule
+    if (max_row <= 8 && op.nnz >= 1024) cands.push_back({1024, 0});
     for (int L : {1, 2, 4, 8, 16, 32, 64}) cands.push_back({1024, L});
   } else {
     cands = {{1024, 0}, {2048, 0}, {4096, 0}};

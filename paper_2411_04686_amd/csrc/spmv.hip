@@ -870,7 +870,30 @@ constexpr int kRowTile = kRingConsumers;
 template <int FMT, int B>
 using RowRing = RingGeom<FMT, kRowTile * B + 16, 2>;
 
-template <int FMT, int B>
+// BLK: per-row-block tables.  A tile of 192 rows touches at most
+// kRowTabEntries / 64 blocks (blocks of GSE_MIN_BLOCK_ROWS rows or more);
+// their tables are staged by the consumers, one entry per thread, into one
+// of two halves of scale_tab: tile k reads half k & 1 while the consumers
+// fill the other half for tile k + 1 (the barrier at the end of tile k
+// publishes it).  A row reads its block's table at (r / R - ra / R) * stride.
+constexpr int kRowTabEntries = ((kRowTile - 1) / GSE_MIN_BLOCK_ROWS + 2) * GSE_MAX_EXP;
+static_assert(kRowTabEntries <= kRingConsumers, "one table entry per consumer thread");
+
+template <int FMT>
+__device__ __forceinline__ void stage_tile_tables(const SpmvOperand& A, int t, uint32_t* tab,
+                                                  int tid) {
+  const int ra = t * kRowTile;
+  const int rb = min(ra + kRowTile, A.n_rows);
+  const int b0 = ra / A.block_rows;
+  const int n = ((rb - 1) / A.block_rows - b0 + 1) * A.block_stride;
+  if (tid < n) {
+    const int W = ((FMT == 1) ? 15 : (FMT == 2) ? 31 : 63) - A.split.ei;
+    const int S = A.block_sem[(size_t)b0 * A.block_stride + tid];
+    tab[tid] = S > W ? (uint32_t)(S - W) << 20 : 0u;
+  }
+}
+
+template <int FMT, int B, bool BLK = false>
 __global__ __launch_bounds__(kRingThreads) void k_spmv_rows(SpmvOperand A,
                                                             const double* __restrict__ x,
                                                             double* __restrict__ y, SpmvEpilogue ep) {
@@ -878,19 +901,23 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_rows(SpmvOperand A,
   constexpr int PRODUCER = kRingConsumers / 64;
   __shared__ __attribute__((aligned(16))) char ring_raw[L::D * L::STAGE];
   __shared__ int hdr[L::D][4];  // per stage: first row, row end, first staged non-zero
-  __shared__ uint32_t scale_tab[kScaleEntries];
+  __shared__ uint32_t scale_tab[BLK ? 2 * kRowTabEntries : kScaleEntries];
   __shared__ double red[kRingThreads / 64];
   lds_char* ring = (lds_char*)ring_raw;
 
   if (ep.gate && *ep.gate) return;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  build_scale<FMT>(A.sem, scale_tab, A.split.ei);
-  const DecodeCtx scale{scale_tab, A.split};
   const int pad = (A.nnz + 15) & ~15;
   const int n_rt = (A.n_rows + kRowTile - 1) / kRowTile;
   TileWalk walk(n_rt);
   const int count = walk.t < walk.end ? (walk.end - walk.t + walk.step - 1) / walk.step : 0;
+  if constexpr (BLK) {
+    if (count > 0 && tid < kRingConsumers) stage_tile_tables<FMT>(A, walk.t, scale_tab, tid);
+  } else {
+    build_scale<FMT>(A.sem, scale_tab, A.split.ei);
+  }
+  const DecodeCtx scale{scale_tab, A.split};
   double acc = 0.0;
   __syncthreads();
   if (wave == PRODUCER) {
@@ -919,6 +946,11 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_rows(SpmvOperand A,
   } else {
     for (int k = 0; k < count; ++k) {
       consumer_barrier();  // A
+      if constexpr (BLK) {
+        if (k + 1 < count)
+          stage_tile_tables<FMT>(A, walk.t + (k + 1) * walk.step,
+                                 scale_tab + ((k + 1) & 1) * kRowTabEntries, tid);
+      }
       const int st = k % L::D;
       const lds_char* stage = ring + st * L::STAGE;
       const int ra = hdr[st][0], rb = hdr[st][1], ja = hdr[st][2];
@@ -929,12 +961,16 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_rows(SpmvOperand A,
         const int s0 = rps[tid], s1 = rps[tid + 1];
         const int o = s0 - ja;
         const int len = s1 - s0;
+        DecodeCtx own = scale;
+        if constexpr (BLK)
+          own.tab = scale_tab + (k & 1) * kRowTabEntries +
+                    (r / A.block_rows - ra / A.block_rows) * A.block_stride;
         double v[B], xv[B];
         int c[B];
 #pragma unroll
         for (int q = 0; q < B; ++q) {
           int col;
-          v[q] = ring_value<FMT, L>(stage, o + q, scale, col);
+          v[q] = ring_value<FMT, L>(stage, o + q, own, col);
           c[q] = (q < len) ? col : 0;
         }
 #pragma unroll
@@ -978,7 +1014,7 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_rows(SpmvOperand A,
 // compute and store the same value.
 enum Kind : int { kGeneralTiles = 0, kShortTiles = 1, kRingTiles = 2, kRowTiles = 3 };
 
-template <int FMT, int E, int KIND, int B = 8>
+template <int FMT, int E, int KIND, int B = 8, bool BLK = false>
 int resident_groups() {
   static std::atomic<int> cache{0};
   int cached = cache.load(std::memory_order_relaxed);
@@ -989,7 +1025,8 @@ int resident_groups() {
       return 0;
     hipError_t e;
     if constexpr (KIND == kRowTiles)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv_rows<FMT, B>, kRingThreads, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv_rows<FMT, B, BLK>,
+                                                       kRingThreads, 0);
     else if constexpr (KIND == kRingTiles)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv_ring<FMT>, kRingThreads, 0);
     else if constexpr (KIND == kShortTiles)
@@ -1028,19 +1065,26 @@ hipError_t launch_ring(const SpmvOperand& A, const double* x, double* y, const S
   return hipGetLastError();
 }
 
-template <int FMT, int B>
+template <int FMT, int B, bool BLK = false>
 hipError_t launch_rows(const SpmvOperand& A, const double* x, double* y, const SpmvEpilogue& ep,
                        hipStream_t st) {
-  int g = resident_groups<FMT, 4, kRowTiles, B>();
+  if constexpr (BLK) {
+    // the staged tables fit kRowTabEntries only for blocks this tall
+    if (A.n_rows < 1 || !A.block_sem || A.block_rows < GSE_MIN_BLOCK_ROWS ||
+        A.block_stride < 1 || A.block_stride > GSE_MAX_EXP)
+      return hipErrorInvalidValue;
+  }
+  int g = resident_groups<FMT, 4, kRowTiles, B, BLK>();
   if (g <= 0) return hipErrorInvalidDevice;
   const int n_rt = (A.n_rows + kRowTile - 1) / kRowTile;
   const int need = (n_rt + 7) / 8 * 8;
   if (g > need) g = need;
   if (g < 8) g = 8;
   if (ep.grid_out) *ep.grid_out = g;
-  hipLaunchKernelGGL((k_spmv_rows<FMT, B>), dim3(g), dim3(kRingThreads), 0, st, A, x, y, ep);
+  hipLaunchKernelGGL((k_spmv_rows<FMT, B, BLK>), dim3(g), dim3(kRingThreads), 0, st, A, x, y, ep);
   return hipGetLastError();
 }
+
 
 // Schedule for one tile size.  With the default 1024-non-zero tiles: the
 // row-tile ring when no row holds more than eight non-zeros, the non-zero
@@ -1246,6 +1290,28 @@ hipError_t launch_rv_f(const SpmvOperand& A, const double* x, double* y, const S
   }
 }
 
+// Per-row-block tables: the row-tile ring when a 1024-non-zero tile plan was
+// asked for and no row holds more than eight non-zeros, else the row-vector
+// schedule (its lanes from the plan, or from the mean row length).
+template <int FMT>
+hipError_t launch_blocks(const SpmvOperand& A, const double* x, double* y, const SpmvEpilogue& ep,
+                         hipStream_t st) {
+  if (A.rv_lanes == 0 && A.tile_nnz == kRingTile && A.nnz >= kRingTile && A.max_row <= 8) {
+    if (A.max_row <= 3) return launch_rows<FMT, 3, true>(A, x, y, ep, st);
+    if (A.max_row <= 5) return launch_rows<FMT, 5, true>(A, x, y, ep, st);
+    if (A.max_row <= 7) return launch_rows<FMT, 7, true>(A, x, y, ep, st);
+    return launch_rows<FMT, 8, true>(A, x, y, ep, st);
+  }
+  if (A.rv_lanes > 0) return launch_rv_f<FMT, true>(A, x, y, ep, st);
+  SpmvOperand o = A;
+  const int64_t half = A.n_rows > 0 ? ((int64_t)A.nnz + 2 * (int64_t)A.n_rows - 1) /
+                                          (2 * (int64_t)A.n_rows)
+                                    : 1;
+  o.rv_lanes = 1;
+  while (o.rv_lanes < 64 && o.rv_lanes < half) o.rv_lanes *= 2;
+  return launch_rv_f<FMT, true>(o, x, y, ep, st);
+}
+
 // tile_row[t] = first row whose first non-zero is at or after t*T (lower
 // bound over row_ptr[0..n_rows)), tile_row[n_tiles] = n_rows.
 __global__ void k_plan(const int32_t* __restrict__ row_ptr, int32_t n_rows, int32_t tile_nnz,
@@ -1297,11 +1363,11 @@ int32_t n_tiles_for(int64_t nnz, int32_t tile_nnz) {
 
 hipError_t launch_spmv(int fmt, const SpmvOperand& A, const double* x, double* y,
                        const SpmvEpilogue& ep, hipStream_t st) {
-  if (A.block_sem) {  // per-row-block tables: the row-vector schedule only
+  if (A.block_sem) {  // per-row-block tables
     switch (fmt) {
-      case 1: return launch_rv_f<1, true>(A, x, y, ep, st);
-      case 2: return launch_rv_f<2, true>(A, x, y, ep, st);
-      case 3: return launch_rv_f<3, true>(A, x, y, ep, st);
+      case 1: return launch_blocks<1>(A, x, y, ep, st);
+      case 2: return launch_blocks<2>(A, x, y, ep, st);
+      case 3: return launch_blocks<3>(A, x, y, ep, st);
       default: return hipErrorInvalidValue;
     }
   }

@@ -88,8 +88,8 @@ def check_spmv(A, enc, M, lanes=(0,)):
     xd = torch.from_numpy(x).to(DEV)
     yd = torch.full((A.n_rows,), np.nan, dtype=torch.float64, device=DEV)
     for L in lanes:
-        M.plan(1024, L)
-        assert M.A.rv_lanes == (L if L > 0 else M.A.rv_lanes) and M.A.rv_lanes > 0
+        M.plan(1024, L)  # L = 0: the row-tile ring on rows of <= 8 non-zeros
+        assert M.A.rv_lanes == L
         for s in (1, 2, 3):
             M.spmv(s, xd, yd)
             torch.cuda.synchronize()
@@ -136,7 +136,15 @@ def test_autotune_picks_lanes():
     x = torch.ones(A.n_cols, dtype=torch.float64, device=DEV)
     y = torch.empty(A.n_rows, dtype=torch.float64, device=DEV)
     M.autotune(1, x, y, reps=3)
-    assert M.A.rv_lanes in (1, 2, 4, 8, 16, 32, 64)
+    assert M.A.rv_lanes in (1, 2, 4, 8, 16, 32, 64)  # long rows: no row-tile ring
+    check_spmv(A, enc, M, lanes=(M.A.rv_lanes,))
+    # short rows: the row-tile ring is a candidate too
+    A = layered3d(12, 1)
+    enc, M = encode_both(A, 256)
+    assert M.A.rv_lanes == 0  # default: the row-tile ring
+    x = torch.ones(A.n_cols, dtype=torch.float64, device=DEV)
+    y = torch.empty(A.n_rows, dtype=torch.float64, device=DEV)
+    M.autotune(2, x, y, reps=3)
     check_spmv(A, enc, M, lanes=(M.A.rv_lanes,))
 
 
