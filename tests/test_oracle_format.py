@@ -4,8 +4,9 @@ Nothing here re-runs the oracle's own arithmetic.  The checks come from:
   * the format's definition (Section III-B.2): the stored magnitude is the
     value on its slot's fixed-point grid, truncated toward zero -- computed
     here with exact rational arithmetic (``fractions.Fraction``);
-  * Algorithm 1 as the paper states it for a 16-bit SEM (sign | index |
-    denormalised mantissa), which must agree with the head segment;
+  * the 16-bit SEM word's stated properties (Section III-B.2: sign, exponent
+    index, magnitude on the shared exponent's grid with the hidden one minDiff
+    places down, truncated), which the head segment must have;
   * Algorithm 2's leading-one reconstruction of an FP64 value from the head,
     rebuilt here from IEEE fields, which must agree with the decoder on every
     head pattern;
@@ -125,36 +126,42 @@ def test_encoder_subnormals_and_zero_match_definition():
 
 
 @pytest.mark.parametrize("ei_bit", [0, 3])
-def test_head_agrees_with_algorithm1(ei_bit):
-    """Algorithm 1 (16-bit SEM): sign | index << (15-EI_bit) |
-    ((fraction >> minDiff) >> (37+EI_bit)) | 1 << (15-EI_bit-minDiff).
-    Its mantissa bits must be the head's top 15-EI_bit magnitude bits
-    whenever the hidden one still falls inside them."""
+def test_head_is_the_16_bit_sem_of_section_3b2(ei_bit):
+    """The 16-bit SEM word of Section III-B.2 from the format's stated
+    properties: the sign on top, an EI_bit-bit exponent index below it, and
+    15 - EI_bit magnitude bits holding |v| on the grid of its shared exponent
+    -- the hidden one made explicit minDiff places below the field's top
+    (minDiff = SEM - exponent field, at least 1), the bits below the field
+    dropped (truncation toward zero).  Checked against the head of the
+    oracle's 64-bit words (the index in the value word when EI_bit > 0):
+    magnitude by exact rationals, the leading one's position, the index."""
     rng = np.random.default_rng(3)
     vals = random_values(rng, 3000, spread=24)
     vals = vals[vals != 0]
     sem = np.array([1024, 1027, 1021, 1030, 1017, 1034, 1014, 1036], np.int16)
-    _, h, _, _ = O.encode_values(vals, np.zeros(vals.size, np.int32), sem)
+    ci, h, _, _ = O.encode_values(vals, np.zeros(vals.size, np.int32), sem,
+                                  idx_bits=3, layout=1 if ei_bit else 0)
+    width = 15 - ei_bit  # magnitude bits of the 16-bit word
     checked = 0
     for i, v in enumerate(vals):
-        u = bits(float(v))
-        e = (u >> 52) & 0x7FF
-        if e + 1 in sem:
-            idx, md = int(np.nonzero(sem == e + 1)[0][0]), 1
-        else:
-            d = [(int(s) - e, i2) for i2, s in enumerate(sem) if s - e > 0]
-            md, idx = min(d)
-        if md > 15 - ei_bit:
-            continue
-        frac = u & ((1 << 52) - 1)
-        mant = ((frac >> md) >> (37 + ei_bit)) | (1 << (15 - ei_bit - md))
-        sem16 = ((u >> 48) & 0x8000) | ((idx << (15 - ei_bit)) if ei_bit else 0) | mant
-        head_mag = int(h[i]) & 0x7FFF
-        assert mant == head_mag >> ei_bit, (v, md)
-        assert (sem16 >> 15) & 1 == int(h[i]) >> 15
+        slot = slot_of(float(v), [int(t) for t in sem])
+        S = int(sem[slot])
+        min_diff = S - field(float(v))
+        head = int(h[i])
+        mag = head & ((1 << width) - 1)
+        # |v| on the grid 2^(S - 1023 - width), truncated
+        want = math.floor(abs(Fraction(float(v))) * Fraction(2) ** (width - (S - 1023)))
+        assert mag == want, (v, S)
+        assert head >> 15 == (1 if v < 0 else 0)
         if ei_bit:
-            assert (sem16 >> (15 - ei_bit)) & ((1 << ei_bit) - 1) == idx
-        checked += 1
+            assert (head >> width) & ((1 << ei_bit) - 1) == slot
+        else:
+            assert int(ci[i]) >> 29 == slot
+        if min_diff <= width:  # the hidden one is still inside the field
+            assert mag.bit_length() == width - min_diff + 1
+            checked += 1
+        else:
+            assert mag == 0
     assert checked > 1000
 
 
