@@ -237,6 +237,33 @@ def copy_same_size(G, torch, dev, stream, nbytes, copies):
     return {"bytes": 2 * half, "mean_us": round(us, 2), "GBps": round(2 * half / (us * 1e-6) / 1e9, 1)}
 
 
+def read_ceiling(G, torch, dev, stream, nbytes, copies):
+    """Streaming reduction (eight FP64 read per one written: 89 % reads, the
+    SpMV's mix) moving `nbytes` per launch, rotated over `copies` buffer
+    pairs: the practical ceiling of a read-dominated launch of that size."""
+    n_out = max(1, nbytes // 72)
+    pairs = [(torch.rand(8 * n_out, dtype=torch.float64, device=dev),
+              torch.empty(n_out, dtype=torch.float64, device=dev)) for _ in range(copies)]
+    for a, b in pairs:
+        G.gse_stream_reduce8(a, b, n_out)
+    torch.cuda.synchronize()
+    ok = bool(torch.allclose(pairs[0][1], pairs[0][0].view(-1, 8).sum(dim=1)))
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    rounds = 10
+    e0.record(stream)
+    for _ in range(rounds):
+        for a, b in pairs:
+            G.gse_stream_reduce8(a, b, n_out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / (rounds * copies)
+    moved = 72 * n_out
+    del pairs
+    return {"bytes": moved, "read_frac": round(64 / 72, 3), "mean_us": round(us, 2),
+            "GBps": round(moved / (us * 1e-6) / 1e9, 1), "checked": ok}
+
+
 def progress(msg):
     """A progress line on stderr (the JSON result is the only stdout line)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -347,6 +374,8 @@ def run_spmv_cg(args, torch, G):
         out["spmv_warm"] = spmv_warm(torch, stream, mats[0], csrs[0], xs, ys[0], kinds, A)
         out["copy_same_size"] = copy_same_size(G, torch, dev, stream, spmv["s1"]["bytes"],
                                                args.copies)
+        out["read_ceiling_same_size"] = read_ceiling(G, torch, dev, stream, spmv["s1"]["bytes"],
+                                                     args.copies)
     out["roofline"] = {"bound": "hbm", "achieved": spmv["s1"]["GBps"], "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": spmv["s1"]["frac_peak"],
                        "traffic": measured_traffic(kname, workload), "kernel": kname,

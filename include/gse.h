@@ -498,6 +498,11 @@ gse_status gse_solver_destroy(gse_solver* s);
 /* Diagnostic: dst = src, `bytes` a multiple of 16, both 16-byte aligned;
  * the reference streaming kernel for HBM bandwidth and counter scaling. */
 gse_status gse_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
+/* Diagnostic: dst[i] = src[8i] + ... + src[8i+7] for i < n_out (FP64, src
+ * [8 n_out], dst [n_out], 16-byte aligned): a streaming kernel that reads
+ * eight bytes for each one it writes (89 % reads), the read-dominated mix of
+ * the SpMV, as its bandwidth ceiling.  Asynchronous. */
+gse_status gse_stream_reduce8(const double* src, double* dst, size_t n_out, void* stream);
 
 const char* gse_status_str(gse_status s);
 const char* gse_last_error(void);

@@ -638,6 +638,15 @@ gse_status gse_batch_history(const void* ws, int32_t index, int32_t cap, double*
   return batch_history(ws, index, cap, hist, seg, (hipStream_t)stream);
 }
 
+gse_status gse_stream_reduce8(const double* src, double* dst, size_t n_out, void* stream) {
+  if (!src || !dst || !aligned16(src) || !aligned16(dst))
+    return fail(GSE_ERR_ARG, "reduce needs 16-byte aligned buffers");
+  if (n_out == 0) return GSE_OK;
+  hipError_t e = launch_stream_reduce8(src, dst, n_out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "gse_stream_reduce8");
+  return GSE_OK;
+}
+
 gse_status gse_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
   if (!src || !dst || (bytes & 15u) || !aligned16(src) || !aligned16(dst))
     return fail(GSE_ERR_ARG, "copy needs 16-byte aligned buffers and a multiple of 16 bytes");

@@ -195,6 +195,7 @@ hipError_t launch_spmv(int fmt, const SpmvOperand& A, const double* x, double* y
 hipError_t launch_plan(const int32_t* row_ptr, int32_t n_rows, int32_t nnz, int32_t tile_nnz,
                        int32_t n_tiles, int32_t* tile_row, hipStream_t st);
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
+hipError_t launch_stream_reduce8(const double* src, double* dst, size_t n_out, hipStream_t st);
 hipError_t launch_rowmax(const int32_t* row_ptr, int32_t n_rows, int* out, hipStream_t st);
 
 // Device record of gse_encode (lives at the start of the encode workspace).

@@ -684,49 +684,58 @@ __device__ __forceinline__ void consumer_barrier() {
 // start of the next region, which is loaded later by the same wave and so
 // overwritten (loads of one wave complete in issue order), and the row
 // pointers, loaded last, fill their region exactly.  Chunk addresses are
-// clamped into the padded planes (pad is a multiple of 16, so a chunk is
-// either inside or wholly past it) and row indices to n_rows; clamped data
-// lands in slots that are never read.
+// clamped to the last chunk before jlim (a multiple of 16, at most pad and
+// at least j0 + 16: every chunk is either inside the planes' padding or a
+// repeat of the last one needed) and row indices to rlim (<= n_rows); a
+// repeated address costs no extra memory traffic, and clamped data lands in
+// slots that are never read.
 template <int FMT, class L>
 __device__ __forceinline__ void ring_issue(const SpmvOperand& A, lds_char* stage, int j0, int ra,
-                                           int pad, int lane) {
+                                           int jlim, int rlim, int lane) {
 #pragma unroll
   for (int i = 0; i < L::NCOL; ++i) {
-    const int e = min(j0 + 4 * (i * 64 + lane), pad - 4);
+    const int e = min(j0 + 4 * (i * 64 + lane), jlim - 4);
     __builtin_amdgcn_global_load_lds(A.col + e, (lds_void*)(stage + L::OFF_COL + i * 1024), 16, 0, 0);
   }
   if constexpr (FMT == kCsr64) {
 #pragma unroll
     for (int i = 0; i < L::NVAL; ++i) {
-      const int e = min(j0 + 2 * (i * 64 + lane), pad - 2);
+      const int e = min(j0 + 2 * (i * 64 + lane), jlim - 2);
       __builtin_amdgcn_global_load_lds(A.val + e, (lds_void*)(stage + L::OFF_VAL + i * 1024), 16, 0, 0);
     }
   } else {
 #pragma unroll
     for (int i = 0; i < L::NHALF; ++i) {
-      const int e = min(j0 + 8 * (i * 64 + lane), pad - 8);
+      const int e = min(j0 + 8 * (i * 64 + lane), jlim - 8);
       __builtin_amdgcn_global_load_lds(A.head + e, (lds_void*)(stage + L::OFF_HEAD + i * 1024), 16, 0, 0);
     }
     if constexpr (planes_of(FMT) >= 2) {
 #pragma unroll
       for (int i = 0; i < L::NHALF; ++i) {
-        const int e = min(j0 + 8 * (i * 64 + lane), pad - 8);
+        const int e = min(j0 + 8 * (i * 64 + lane), jlim - 8);
         __builtin_amdgcn_global_load_lds(A.tail1 + e, (lds_void*)(stage + L::OFF_T1 + i * 1024), 16, 0, 0);
       }
     }
     if constexpr (planes_of(FMT) == 3) {
 #pragma unroll
       for (int i = 0; i < L::NCOL; ++i) {
-        const int e = min(j0 + 4 * (i * 64 + lane), pad - 4);
+        const int e = min(j0 + 4 * (i * 64 + lane), jlim - 4);
         __builtin_amdgcn_global_load_lds(A.tail2 + e, (lds_void*)(stage + L::OFF_T2 + i * 1024), 16, 0, 0);
       }
     }
   }
 #pragma unroll
   for (int i = 0; i < L::NRPS; ++i) {
-    const int r = min(ra + i * 64 + lane, A.n_rows);
+    const int r = min(ra + i * 64 + lane, rlim);
     __builtin_amdgcn_global_load_lds(A.row_ptr + r, (lds_void*)(stage + L::OFF_RPS + i * 256), 4, 0, 0);
   }
+}
+
+// The exclusive chunk limit of a staged window [j0, jend): jend rounded up
+// to 16, at least j0 + 16, at most pad (pad >= 16 here: these schedules
+// run on 1024 non-zeros or more).
+__device__ __forceinline__ int window_limit(int j0, int jend, int pad) {
+  return min(max((jend + 15) & ~15, j0 + 16), pad);
 }
 
 // Consumer: the decoded value and column of staged non-zero `pos`.
@@ -780,7 +789,8 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_ring(SpmvOperand A,
       const int ra = trow[t];
       const int rb = trow[t + 1];
       const int st = k % L::D;
-      ring_issue<FMT, L>(A, ring + st * L::STAGE, t * L::T, ra, pad, lane);
+      ring_issue<FMT, L>(A, ring + st * L::STAGE, t * L::T, ra,
+                         window_limit(t * L::T, t * L::T + L::TL, pad), A.n_rows, lane);
       if (lane == 0) {
         hdr[st][0] = ra;
         hdr[st][1] = rb;
@@ -929,7 +939,9 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_rows(SpmvOperand A,
       const int rb = min(ra + kRowTile, A.n_rows);
       const int ja = rp[ra] & ~15;
       const int st = k % L::D;
-      ring_issue<FMT, L>(A, ring + st * L::STAGE, ja, ra, pad, lane);
+      // exactly the tile's non-zeros [rp[ra], rp[rb]) (in 16-entry chunks)
+      // and its rb - ra + 1 row pointers
+      ring_issue<FMT, L>(A, ring + st * L::STAGE, ja, ra, window_limit(ja, rp[rb], pad), rb, lane);
       if (lane == 0) {
         hdr[st][0] = ra;
         hdr[st][1] = rb;
@@ -1354,6 +1366,18 @@ __global__ void k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__
   for (; i < n; i += stride) dst[i] = src[i];
 }
 
+// dst[i] = sum of src[8i .. 8i+7]: four 16-byte loads and one 8-byte store
+// per output, grid-stride.
+__global__ void k_stream_reduce8(const double2* __restrict__ src, double* __restrict__ dst,
+                                 size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    const double2 a = src[4 * i], b = src[4 * i + 1], c = src[4 * i + 2], d = src[4 * i + 3];
+    dst[i] = ((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y));
+  }
+}
+
 }  // namespace
 
 int32_t n_tiles_for(int64_t nnz, int32_t tile_nnz) {
@@ -1409,6 +1433,15 @@ hipError_t launch_rowmax(const int32_t* row_ptr, int32_t n_rows, int* out, hipSt
   int blocks = (n_rows + 255) / 256;
   blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
   hipLaunchKernelGGL(k_rowmax, dim3(blocks), dim3(256), 0, st, row_ptr, n_rows, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_reduce8(const double* src, double* dst, size_t n_out, hipStream_t st) {
+  size_t blocks = (n_out + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_stream_reduce8, dim3((unsigned)blocks), dim3(256), 0, st,
+                     reinterpret_cast<const double2*>(src), dst, n_out);
   return hipGetLastError();
 }
 

@@ -162,6 +162,7 @@ _SIGS = {
     "gse_solver_stats": (C.c_int32, [_P, C.POINTER(gse_server_stats)]),
     "gse_solver_destroy": (C.c_int32, [_P]),
     "gse_stream_copy": (C.c_int32, [_P, _P, C.c_size_t, _P]),
+    "gse_stream_reduce8": (C.c_int32, [_P, _P, C.c_size_t, _P]),
     "gse_status_str": (C.c_char_p, [C.c_int32]),
     "gse_last_error": (C.c_char_p, []),
 }
@@ -476,6 +477,11 @@ class Request:
         rq.x0_given = 0 if x0 is None else 1
         rq.params = params if params is not None else gse_default_params(CG)
         self.rq = rq
+
+
+def gse_stream_reduce8(src: torch.Tensor, dst: torch.Tensor, n_out: int, stream=None) -> int:
+    return _check(lib().gse_stream_reduce8(_ptr(src), _ptr(dst), n_out, _stream(stream)),
+                  "gse_stream_reduce8")
 
 
 def gse_stream_copy(src: torch.Tensor, dst: torch.Tensor, nbytes: int, stream=None) -> int:

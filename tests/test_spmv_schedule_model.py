@@ -207,6 +207,11 @@ def ring_layout(fmt, TL=RING_T + RING_LOOK, D=3):
     return dict(TL=TL, D=D, stage=stage, ni=ni, loads=loads, rps=end)
 
 
+def window_limit(j0, jend, pad):
+    """Exclusive chunk limit of a staged window (the producer's clamp)."""
+    return min(max((jend + 15) // 16 * 16, j0 + 16), pad)
+
+
 def check_ring(indptr, n_cols, cols, fmt):
     L = ring_layout(fmt)
     TL, T = L["TL"], RING_T
@@ -231,11 +236,15 @@ def check_ring(indptr, n_cols, cols, fmt):
     for t in range(n_tiles):
         j0 = t * T
         ra, rb = tile_row[t], tile_row[t + 1]
-        if t < 1 or t >= n_tiles - 2:  # only the first and the last tiles clamp
-            for name, off, size, per, n in L["loads"]:
-                for c in range(n * 64):
-                    e = min(j0 + per * c, pad - per)
-                    assert 0 <= e and e + per <= pad
+        # chunks are clamped to the last one before the window's limit
+        jlim = window_limit(j0, j0 + TL, pad)
+        for name, off, size, per, n in L["loads"]:
+            e = np.minimum(j0 + per * np.arange(n * 64), jlim - per)
+            assert e.min() >= 0 and (e + per).max() <= pad
+            # every position a consumer may read comes from its own chunk
+            used = np.arange(min(TL, pad - j0))
+            assert np.all(j0 + used // per * per <= jlim - per)
+        if t < 1 or t >= n_tiles - 2:  # only the first and the last tiles clamp rows
             for i in range(RING_RP):
                 assert 0 <= min(ra + i, n_rows) <= n_rows
         # consumers: staged positions read by each row (eight-wide batches)
@@ -297,10 +306,19 @@ def check_rows(indptr, n_cols, cols, fmt, D=2):
     for t in range(n_rt):
         ra, rb = t * ROW_TILE, min(t * ROW_TILE + ROW_TILE, n_rows)
         ja = int(indptr[ra]) & ~15
+        # exactly the tile's window: chunks clamped to the last one before
+        # jlim, row pointers to rb
+        jlim = window_limit(ja, int(indptr[rb]), pad)
         for name, off, size, per, n in L["loads"]:
-            e = np.minimum(ja + per * np.arange(n * 64), pad - per)
+            e = np.minimum(ja + per * np.arange(n * 64), jlim - per)
             assert e.min() >= 0 and (e + per).max() <= pad
             assert np.all(e % per == 0)
+            # the tile's non-zeros come from their own (unclamped) chunks
+            need = np.arange(int(indptr[ra]), int(indptr[rb]))
+            if need.size:
+                assert np.all(ja + (need - ja) // per * per <= jlim - per)
+        staged_rows = np.minimum(ra + np.arange(RING_RP), rb)
+        assert np.array_equal(staged_rows[:rb - ra + 1], np.arange(ra, rb + 1))
         assert ra + RING_RP - 1 >= rb  # staged row pointers ra .. rb
         s0 = indptr[ra:rb].astype(np.int64)
         ln = indptr[ra + 1:rb + 1] - s0
