@@ -244,7 +244,7 @@ gse_status gse_csr_plan(gse_csr* M, int32_t tile_nnz, int32_t rv_lanes, void* st
  * Algorithm 2 and its head+tail1 and head+tail1+tail2 variants
  * (Section III-C.2).  Values are read with s planes and multiplied and
  * accumulated in FP64 (Section III-C.2).  x: device [n_cols], y: device
- * [n_rows]; x and y must not overlap.  Asynchronous on `stream`. */
+ * [n_rows]; x and y must not overlap (GSE_ERR_ARG).  Asynchronous on `stream`. */
 gse_status gse_spmv(const gse_matrix* A, int32_t k_segments, const double* x, double* y,
                     void* stream);
 
@@ -501,7 +501,8 @@ gse_status gse_stream_copy(const void* src, void* dst, size_t bytes, void* strea
 /* Diagnostic: dst[i] = src[8i] + ... + src[8i+7] for i < n_out (FP64, src
  * [8 n_out], dst [n_out], 16-byte aligned): a streaming kernel that reads
  * eight bytes for each one it writes (89 % reads), the read-dominated mix of
- * the SpMV, as its bandwidth ceiling.  Asynchronous. */
+ * the SpMV, as its bandwidth ceiling (coalesced non-temporal 16-byte loads,
+ * eight workgroups per CU).  Asynchronous. */
 gse_status gse_stream_reduce8(const double* src, double* dst, size_t n_out, void* stream);
 
 const char* gse_status_str(gse_status s);

@@ -29,6 +29,20 @@ gse_status hip_fail(hipError_t e, const char* where) {
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+// Whether the byte ranges [a, a + na) and [b, b + nb) share a byte.
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return na > 0 && nb > 0 && x < y + nb && y < x + na;
+}
+
+// The SpMV's vectors: x [n_cols] and y [n_rows] FP64, not overlapping.
+gse_status check_spmv_vectors(int32_t n_rows, int32_t n_cols, const double* x, const double* y) {
+  if ((n_cols > 0 && !x) || (n_rows > 0 && !y)) return fail(GSE_ERR_ARG, "NULL vector");
+  if (ranges_overlap(x, sizeof(double) * (size_t)n_cols, y, sizeof(double) * (size_t)n_rows))
+    return fail(GSE_ERR_ARG, "x and y overlap");
+  return GSE_OK;
+}
+
 int64_t pad_nnz(int64_t nnz) { return (nnz + kPadTo - 1) / kPadTo * kPadTo; }
 
 bool valid_tile(int32_t t) { return t == kWG * 4 || t == kWG * 8 || t == kWG * 16; }
@@ -416,7 +430,8 @@ gse_status gse_spmv(const gse_matrix* A, int32_t k_segments, const double* x, do
   gse_status s = check_matrix(A);
   if (s != GSE_OK) return s;
   if (k_segments < 1 || k_segments > 3) return fail(GSE_ERR_ARG, "k_segments must be 1..3");
-  if ((A->n_cols > 0 && !x) || (A->n_rows > 0 && !y)) return fail(GSE_ERR_ARG, "NULL vector");
+  s = check_spmv_vectors(A->n_rows, A->n_cols, x, y);
+  if (s != GSE_OK) return s;
   if (A->n_rows == 0) return GSE_OK;
   SpmvEpilogue ep{};
   ep.epi = kEpiPlain;
@@ -428,7 +443,8 @@ gse_status gse_spmv(const gse_matrix* A, int32_t k_segments, const double* x, do
 gse_status gse_csr_spmv(const gse_csr* M, const double* x, double* y, void* stream) {
   gse_status s = check_csr(M);
   if (s != GSE_OK) return s;
-  if ((M->n_cols > 0 && !x) || (M->n_rows > 0 && !y)) return fail(GSE_ERR_ARG, "NULL vector");
+  s = check_spmv_vectors(M->n_rows, M->n_cols, x, y);
+  if (s != GSE_OK) return s;
   if (M->n_rows == 0) return GSE_OK;
   SpmvEpilogue ep{};
   ep.epi = kEpiPlain;

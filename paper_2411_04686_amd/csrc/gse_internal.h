@@ -231,6 +231,7 @@ gse_status encode_matrix(const int32_t* row_ptr, const int32_t* col, const doubl
                          const int16_t* sem_in, gse_matrix* A, void* ws, size_t ws_bytes,
                          hipStream_t st);
 gse_status fail(gse_status code, const char* fmt, ...);
+gse_status check_spmv_vectors(int32_t n_rows, int32_t n_cols, const double* x, const double* y);
 gse_status hip_fail(hipError_t e, const char* where);
 
 // autotune.hip: time the schedules, plan the fastest (tile_row rewritten)

@@ -288,7 +288,8 @@ gse_status gse_lp_plan(gse_lp_matrix* M, int32_t tile_nnz, int32_t rv_lanes, voi
 gse_status gse_lp_spmv(const gse_lp_matrix* M, const double* x, double* y, void* stream) {
   gse_status s = check_lp(M);
   if (s != GSE_OK) return s;
-  if ((M->n_cols > 0 && !x) || (M->n_rows > 0 && !y)) return fail(GSE_ERR_ARG, "NULL vector");
+  s = check_spmv_vectors(M->n_rows, M->n_cols, x, y);
+  if (s != GSE_OK) return s;
   if (M->n_rows == 0) return GSE_OK;
   SpmvEpilogue ep{};
   ep.epi = kEpiPlain;

@@ -15,7 +15,9 @@
 #include <string.h>
 
 #include <chrono>
+#include <string>
 #include <type_traits>
+#include <vector>
 
 #include "decode.h"
 #include "gse_internal.h"
@@ -537,13 +539,76 @@ int vec_blocks(int n, int cap = kVecBlocks) {
 constexpr int kCgBlocks = 1024;
 
 // Instantiated graphs of one solve, one per segment count.
-struct GraphCache {
-  hipGraphExec_t g[4] = {nullptr, nullptr, nullptr, nullptr};
-  ~GraphCache() {
-    for (auto& x : g)
-      if (x) (void)hipGraphExecDestroy(x);
+// Executable graphs kept across solves of this host thread.  A captured
+// graph holds its kernels' arguments by value; they all follow from the key
+// (device, method, segment count, operand, workspace, vectors and the sizes
+// the workspace is carved by), so a later solve with the same key replays
+// the graph instead of capturing it again.  At most kGraphKeep graphs are
+// kept; the least recently used one is destroyed first.
+constexpr size_t kGraphKeep = 24;
+
+struct GraphKey {
+  std::string bytes;
+  template <typename T>
+  void add(const T& v) {
+    bytes.append(reinterpret_cast<const char*>(&v), sizeof v);
+  }
+  void add_operand(const SpmvOperand& o) {
+    add(o.row_ptr), add(o.tile_row), add(o.col), add(o.head), add(o.tail1), add(o.tail2);
+    add(o.val), add(o.n_rows), add(o.n_tiles), add(o.tile_nnz), add(o.nnz), add(o.rv_lanes);
+    add(o.max_row), add(o.split.shift), add(o.split.slot_mask), add(o.split.col_mask);
+    add(o.split.hshift), add(o.split.hmask), add(o.split.mag_mask), add(o.split.ei);
+    for (int i = 0; i < GSE_MAX_EXP; ++i) add(o.sem[i]);
+    add(o.block_sem), add(o.block_rows), add(o.block_stride);
   }
 };
+
+struct GraphCache {
+  struct Entry {
+    std::string key;
+    hipGraphExec_t exec;
+    unsigned long long used;
+  };
+  std::vector<Entry> entries;
+  unsigned long long tick = 0;
+  ~GraphCache() {
+    for (auto& e : entries) (void)hipGraphExecDestroy(e.exec);
+  }
+  hipGraphExec_t find(const std::string& key) {
+    for (auto& e : entries)
+      if (e.key == key) {
+        e.used = ++tick;
+        return e.exec;
+      }
+    return nullptr;
+  }
+  void put(const std::string& key, hipGraphExec_t exec) {
+    if (entries.size() >= kGraphKeep) {
+      size_t old = 0;
+      for (size_t i = 1; i < entries.size(); ++i)
+        if (entries[i].used < entries[old].used) old = i;
+      (void)hipGraphExecDestroy(entries[old].exec);
+      entries.erase(entries.begin() + (long)old);
+    }
+    entries.push_back(Entry{key, exec, ++tick});
+  }
+};
+
+GraphCache& thread_graphs() {
+  thread_local GraphCache cache;
+  return cache;
+}
+
+// The replayed graph of `key`, captured by `body` on `st` when missing.
+template <typename F>
+hipError_t cached_graph(const GraphKey& key, hipStream_t st, hipGraphExec_t* out, F&& body) {
+  GraphCache& c = thread_graphs();
+  *out = c.find(key.bytes);
+  if (*out) return hipSuccess;
+  hipError_t e = capture(st, out, body);
+  if (e == hipSuccess) c.put(key.bytes, *out);
+  return e;
+}
 
 struct Operator {
   int fmt;  // 1..3 GSE (stepped), 0 a fixed operator (FP64 CSR, FP16 or BF16)
@@ -610,10 +675,19 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
   SolveStream ss(caller);
   if (ss.err != hipSuccess) return hip_fail(ss.err, "cg stream");
   hipStream_t st = ss.s;
-  GraphCache graphs;
   const int n = A.op.n_rows;
   Workspace w = carve(ws, GSE_CG, n, A.op.nnz, p->restart, p->max_iter);
   if (w.bytes > ws_bytes) return fail(GSE_ERR_NOMEM, "solver workspace needs %zu bytes", w.bytes);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(GSE_ERR_HIP, "cg: no device");
+  // what the captured iterations' kernel arguments follow from
+  auto graph_key = [&](int s_use) {
+    GraphKey k;
+    k.add(dev), k.add(GSE_CG), k.add(s_use), k.add(A.fmt), k.add(A.launch_fmt);
+    k.add_operand(A.op);
+    k.add(ws), k.add(n), k.add(A.op.nnz), k.add(p->restart), k.add(p->max_iter), k.add(x), k.add(b);
+    return k;
+  };
   memset(rep, 0, sizeof *rep);
   rep->switch_iter[0] = rep->switch_iter[1] = -1;
   const bool stepped = A.fmt != 0 && p->fixed_segments == 0;
@@ -710,10 +784,10 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
         e = launch_iters(chunk, h.s);
         chunk = chunk < 64 ? chunk * 2 : 64;
       } else {
-        hipGraphExec_t& ge = graphs.g[h.s & 3];
         const int s_use = h.s;
-        e = hipSuccess;
-        if (!ge) e = capture(st, &ge, [&] { return launch_iters(kGraphIters, s_use); });
+        hipGraphExec_t ge = nullptr;
+        e = cached_graph(graph_key(s_use), st, &ge,
+                         [&] { return launch_iters(kGraphIters, s_use); });
         if (e == hipSuccess) e = hipGraphLaunch(ge, st);
       }
       if (e == hipSuccess) e = read_state(w, &h, st);
@@ -1057,12 +1131,21 @@ gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_pa
   SolveStream ss(caller);
   if (ss.err != hipSuccess) return hip_fail(ss.err, "gmres stream");
   hipStream_t st = ss.s;
-  GraphCache graphs;
   const int n = A.op.n_rows;
   const int m = p->restart;
   if (m > 60) return fail(GSE_ERR_ARG, "restart must be <= 60");
   Workspace w = carve(ws, GSE_GMRES, n, A.op.nnz, m, p->max_iter);
   if (w.bytes > ws_bytes) return fail(GSE_ERR_NOMEM, "solver workspace needs %zu bytes", w.bytes);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(GSE_ERR_HIP, "gmres: no device");
+  // what the captured cycle's kernel arguments follow from
+  auto graph_key = [&](int s_use) {
+    GraphKey k;
+    k.add(dev), k.add(GSE_GMRES), k.add(s_use), k.add(A.fmt), k.add(A.launch_fmt);
+    k.add_operand(A.op);
+    k.add(ws), k.add(n), k.add(A.op.nnz), k.add(m), k.add(p->max_iter), k.add(x), k.add(b);
+    return k;
+  };
   memset(rep, 0, sizeof *rep);
   rep->switch_iter[0] = rep->switch_iter[1] = -1;
   const bool stepped = A.fmt != 0 && p->fixed_segments == 0;
@@ -1216,10 +1299,9 @@ gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_pa
     if (p->launch_mode == 1) {
       e = launch_cycle(h.s);
     } else {
-      hipGraphExec_t& ge = graphs.g[h.s & 3];
       const int s_use = h.s;
-      e = hipSuccess;
-      if (!ge) e = capture(st, &ge, [&] { return launch_cycle(s_use); });
+      hipGraphExec_t ge = nullptr;
+      e = cached_graph(graph_key(s_use), st, &ge, [&] { return launch_cycle(s_use); });
       if (e == hipSuccess) e = hipGraphLaunch(ge, st);
     }
     if (e != hipSuccess) return hip_fail(e, "gmres cycle");

@@ -1360,23 +1360,7 @@ __global__ __launch_bounds__(256) void k_rowmax(const int32_t* __restrict__ row_
   }
 }
 
-__global__ void k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) dst[i] = src[i];
-}
 
-// dst[i] = sum of src[8i .. 8i+7]: four 16-byte loads and one 8-byte store
-// per output, grid-stride.
-__global__ void k_stream_reduce8(const double2* __restrict__ src, double* __restrict__ dst,
-                                 size_t n) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) {
-    const double2 a = src[4 * i], b = src[4 * i + 1], c = src[4 * i + 2], d = src[4 * i + 3];
-    dst[i] = ((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y));
-  }
-}
 
 }  // namespace
 
@@ -1433,25 +1417,6 @@ hipError_t launch_rowmax(const int32_t* row_ptr, int32_t n_rows, int* out, hipSt
   int blocks = (n_rows + 255) / 256;
   blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
   hipLaunchKernelGGL(k_rowmax, dim3(blocks), dim3(256), 0, st, row_ptr, n_rows, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_stream_reduce8(const double* src, double* dst, size_t n_out, hipStream_t st) {
-  size_t blocks = (n_out + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_stream_reduce8, dim3((unsigned)blocks), dim3(256), 0, st,
-                     reinterpret_cast<const double2*>(src), dst, n_out);
-  return hipGetLastError();
-}
-
-hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t st) {
-  const size_t n = bytes / 16;
-  size_t blocks = (n + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, st,
-                     reinterpret_cast<const uint4*>(src), reinterpret_cast<uint4*>(dst), n);
   return hipGetLastError();
 }
 

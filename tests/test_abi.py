@@ -158,3 +158,22 @@ def test_block_tables_host_side(lib):
     A.block_rows, A.block_stride = 128, 8
     assert L.gse_spmv(C.byref(A), 1, fake, fake, None) == -1
     assert b"per-block" in L.gse_last_error()
+
+
+def test_spmv_refuses_overlapping_vectors(lib):
+    """x and y of one product may not share memory: refused on the host."""
+    import sys
+    sys.path.insert(0, ROOT)
+    from paper_2411_04686_amd import gse as G
+    L = G.lib()
+    A = G.gse_matrix()
+    A.n_rows = A.n_cols = 100
+    A.nnz = 500
+    A.num_exp, A.idx_bits, A.idx_layout = 8, 3, 1
+    A.row_ptr = A.col_idx = A.head = A.tail1 = A.tail2 = A.tile_row = 256
+    A.tile_cap, A.tile_nnz, A.n_tiles = 8, 1024, 1
+    base = 1 << 20
+    # x spans 800 bytes, y 800: any shared byte is refused
+    for x, y in ((base, base + 400), (base + 400, base), (base, base + 799), (base, base)):
+        st = L.gse_spmv(C.byref(A), 1, C.c_void_p(x), C.c_void_p(y), None)
+        assert st == -1 and b"overlap" in L.gse_last_error(), (x, y)

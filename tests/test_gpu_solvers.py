@@ -421,3 +421,42 @@ def test_stepped_cg_with_the_index_in_the_value():
     torch.cuda.synchronize()
     assert rb.status == G.OK
     assert np.linalg.norm(xb.cpu().numpy() - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+
+
+@pytest.mark.parametrize("method", [G.CG, G.GMRES], ids=["cg", "gmres"])
+def test_graphs_kept_across_solves(method):
+    """A second solve with the same operand, workspace and vectors replays the
+    graphs the first one captured: same bits, same report.  A different
+    matrix on the same workspace and vectors captures its own and still
+    matches the oracle."""
+    A = diffusion3d(24, 5)
+    x_true, b = rhs_from_solution(A, 6)
+    rp, ci, va = to_dev(A)
+    M = G.GseMatrix(rp, ci, va, A.n_cols)
+    p = G.gse_default_params(method)
+    p.max_iter = 5000
+    ws = torch.empty(G.gse_solver_workspace(method, A.n_rows, A.nnz, p.restart, p.max_iter),
+                     dtype=torch.uint8, device=DEV)
+    x = torch.zeros(A.n_rows, dtype=torch.float64, device=DEV)
+    bd = torch.from_numpy(b).to(DEV)
+    fn = G.gse_cg if method == G.CG else G.gse_gmres
+    runs = []
+    for _ in range(3):
+        x.zero_()
+        rep = fn(M.A, bd, x, p, ws)
+        torch.cuda.synchronize()
+        runs.append((rep.as_dict(), x.cpu().numpy().copy()))
+    for r, xs in runs[1:]:
+        assert r["iters"] == runs[0][0]["iters"] and r["switch_iter"] == runs[0][0]["switch_iter"]
+        assert np.array_equal(xs, runs[0][1])
+    # another operator (other coefficients, same shape) on the same buffers
+    A2 = diffusion3d(24, 7)
+    b2 = A2.to_scipy() @ x_true
+    rp2, ci2, va2 = to_dev(A2)
+    M2 = G.GseMatrix(rp2, ci2, va2, A2.n_cols)
+    bd.copy_(torch.from_numpy(b2))
+    x.zero_()
+    rep = fn(M2.A, bd, x, p, ws)
+    torch.cuda.synchronize()
+    assert rep.status == G.OK
+    assert true_relres(A2, x.cpu().numpy(), b2) <= 1e-10
