@@ -1,12 +1,15 @@
 """GPU tests of the solver server (gse_solver_*): requests submitted over
 time complete with the same bits as the batched solver gives each system
-alone; admission keeps the arena within its size; bad requests are refused
-on the host."""
+alone, and agree with the CPU oracle's CG on each request (status, solution
+within 1e-6, iteration count within 10 %, as for the batched solver);
+admission keeps the arena within its size; bad requests are refused on the
+host."""
 import time
 
 import numpy as np
 import pytest
 
+import oracle as O
 from workloads import diffusion2d, diffusion3d, poisson2d, rhs_from_solution
 
 torch = pytest.importorskip("torch")
@@ -84,6 +87,24 @@ def test_server_results_equal_batch_alone():
         ref, xref = batch_alone(A, b, fmt)
         assert rep.iters == ref.iters and list(rep.iters_per_seg) == list(ref.iters_per_seg)
         assert np.array_equal(rq.x, xref)
+        # and the CPU oracle's CG on the same request
+        orc = oracle_cg(A, b, fmt)
+        assert orc.status == O.OK
+        assert np.linalg.norm(rq.x - orc.x) <= 1e-6 * np.linalg.norm(orc.x), A.name
+        assert abs(rep.iters - orc.iters) <= max(3, orc.iters // 10), (A.name, rep.iters, orc.iters)
+        if fmt == G.FMT_GSE:
+            assert sum(rep.iters_per_seg) == rep.iters
+
+
+def oracle_cg(A, b, fmt):
+    """The oracle's CG with the server's defaults (stepped on the request's
+    own table, or FP64 CSR)."""
+    if fmt == G.FMT_GSE:
+        enc = O.encode(A.indptr, A.indices, A.data, A.n_cols)
+        prm = O.make_params(tol=1e-10, max_iter=5000, preset="paper_cg")
+        return O.cg(A.indptr, b, prm, A.indices, A.data, enc)
+    prm = O.make_params(tol=1e-10, max_iter=5000, preset="paper_cg", fixed_segments=-1)
+    return O.cg(A.indptr, b, prm, A.indices, A.data)
 
 
 def test_server_admission_respects_the_arena():
