@@ -118,7 +118,7 @@ def parse():
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copies", type=int, default=4)
-    ap.add_argument("--reps", type=int, default=10, help="SpMV launches per copy per step")
+    ap.add_argument("--reps", type=int, default=20, help="SpMV launches per copy per step")
     ap.add_argument("--no-solve", action="store_true", help="SpMV only (profiling runs)")
     ap.add_argument("--no-legs", dest="legs", action="store_false",
                     help="default workload: skip the Poisson, GMRES and power-law legs")
