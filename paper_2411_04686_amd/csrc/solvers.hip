@@ -891,15 +891,19 @@ gse_status run_cg(const Operator& A, const double* b, double* x, const gse_param
 // Arnoldi with classical Gram-Schmidt applied twice (CGS2); V holds m+1
 // basis vectors of n entries; small arrays: H (m+1) x m row-major, cs, sn,
 // g (m+1 each), h2 scratch.  Per step j (device, gated on stop):
-//   w = A_s v_j                       (SpMV into v_{j+1})
-//   h = V^T w                         (k_gm_dots + k_finish)
-//   w -= V h ; h2 = V^T w             (k_gm_axpy<.., false> + k_finish)
-//   w -= V h2 ; partials of ||w||^2   (k_gm_axpy<.., true>)
-//   H[:,j] = h + h2, ||w||, Givens,   (k_gm_givens_scale: workgroup 0 runs
-//     controller; v_{j+1} = w/||w||     the small steps, the others scale)
-// The finishers stay kernels of their own: summing the (j+1) x 512
-// partials in every workgroup of the next pass instead cost more than the
-// launch it saved.
+//   w = A_s v_j                            (SpMV into v_{j+1})
+//   h = V^T w                              (k_gm_dots + k_finish)
+//   w -= V h ; h2 = V^T w, n1 = ||w||^2    (k_gm_axpy_dots + k_finish)
+//   w -= V h2 ; v_{j+1} = w / b with       (k_gm_axpy_scale: every workgroup
+//     b^2 = n1 - ||h2||^2 ; H[:,j] = h + h2,  updates and scales its rows,
+//     H[j+1,j] = b, Givens, controller        workgroup 0 then runs the rest)
+// b^2 = n1 - ||h2||^2 is ||w - V h2||^2 for orthonormal V (the second pass
+// removes a component of relative size ~ eps, so the difference loses no
+// accuracy), which saves the reduction of a third pass and the separate
+// scaling pass.  A b^2 at or below 1e-28 n1 is taken as 0: w lies in the
+// span of V (the Krylov space is exhausted).  The finishers stay kernels of
+// their own: summing the (j+1) x 512 partials in every workgroup of the
+// next pass instead cost more than the launch it saved.
 constexpr int kGmBlocks = 512;  // measured best for the 1M-row passes (fewer, longer workgroups)
 
 struct GmSmall {
@@ -961,22 +965,23 @@ __global__ __launch_bounds__(kWG) void k_gm_dots(const SolverState* S, const dou
   block_sums_out(acc, j + 1, red, partials, gridDim.x);
 }
 
-// w -= V h (h finished from the previous pass); then partials of V_k . w,
-// or (NORM) of w.w.
-template <int JB, bool NORM>
-__global__ __launch_bounds__(kWG) void k_gm_axpy(const SolverState* S, const double* __restrict__ V,
-                                                 double* __restrict__ w, int n, size_t ld, int j,
-                                                 const double* __restrict__ h,
-                                                 double* __restrict__ partials) {
-  constexpr int NA = NORM ? 1 : JB;
-  __shared__ double red[NA * kWaves];
+// w -= V h (h finished from the previous pass); then partials of V_k . w
+// for k <= j (rows 0..j of `partials`) and of w.w (row j + 1).
+template <int JB>
+__global__ __launch_bounds__(kWG) void k_gm_axpy_dots(const SolverState* S,
+                                                      const double* __restrict__ V,
+                                                      double* __restrict__ w, int n, size_t ld,
+                                                      int j, const double* __restrict__ h,
+                                                      double* __restrict__ partials) {
+  __shared__ double red[(JB + 1) * kWaves];
   __shared__ double hs[JB];
   if (S->stop) return;
   if (threadIdx.x < JB) hs[threadIdx.x] = (threadIdx.x <= j) ? h[threadIdx.x] : 0.0;
   __syncthreads();
-  double acc[NA];
+  double acc[JB];
+  double nrm = 0.0;
 #pragma unroll
-  for (int k = 0; k < NA; ++k) acc[k] = 0.0;
+  for (int k = 0; k < JB; ++k) acc[k] = 0.0;
   for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
     double v[JB];
 #pragma unroll
@@ -986,48 +991,76 @@ __global__ __launch_bounds__(kWG) void k_gm_axpy(const SolverState* S, const dou
 #pragma unroll
     for (int k = 0; k < JB; ++k) wi -= hs[k] * v[k];
     w[i] = wi;
-    if constexpr (NORM) {
-      acc[0] += wi * wi;
-    } else {
+    nrm += wi * wi;
 #pragma unroll
-      for (int k = 0; k < JB; ++k) acc[k] += v[k] * wi;
+    for (int k = 0; k < JB; ++k) acc[k] += v[k] * wi;
+  }
+  // the same arithmetic as block_sums_out, with the norm as row j + 1
+  const int wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < JB; ++k) {
+    if (k <= j) {
+      const double t = wave_sum(acc[k]);
+      if ((threadIdx.x & 63) == 0) red[k * kWaves + wv] = t;
     }
   }
-  block_sums_out(acc, NORM ? 1 : j + 1, red, partials, gridDim.x);
+  {
+    const double t = wave_sum(nrm);
+    if ((threadIdx.x & 63) == 0) red[JB * kWaves + wv] = t;
+  }
+  __syncthreads();
+  const int row = (int)threadIdx.x;
+  if (row <= j + 1) {
+    const int src = row <= j ? row : JB;
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) t += red[src * kWaves + i];
+    partials[(size_t)row * gridDim.x + blockIdx.x] = t;
+  }
 }
 
-// The Arnoldi column j is complete.  Every workgroup sums the norm
-// partials (same order, same bits) into ||w||.  Workgroup 0: H[:,j] = h1 +
-// h2, H[j+1,j] = ||w||, the rotations, the residual estimate and the
-// controller (the column and the earlier rotations are gathered into LDS
-// by all its threads, the rotations run in one thread from there, and the
-// rotated column is written back by all threads).  The other workgroups:
-// v_{j+1} = w / ||w||.  Workgroup 0 may set stop while the others run;
-// whether they still scale then does not matter, because a stopped cycle
-// ends with x += V(:, 0..j) y and never reads v_{j+1}.
-__global__ __launch_bounds__(kWG) void k_gm_givens_scale(SolverState* S, GmSmall sm, int m, int j,
-                                                         const double* __restrict__ h1,
-                                                         const double* __restrict__ h2,
-                                                         const double* __restrict__ norm_partials,
-                                                         int n_partials, double* hist, int* seg_hist,
-                                                         double* __restrict__ w, int n) {
+// The second pass and the end of Arnoldi step j.  Every workgroup: b from
+// n1 = ||w||^2 (h2[j + 1]) and h2 (the same bits everywhere), then for its
+// rows w -= V h2 and v_{j+1} = w / b.  Workgroup 0 afterwards: H[:,j] =
+// h1 + h2, H[j+1,j] = b, the rotations, the residual estimate and the
+// controller (the column and the earlier rotations are gathered into LDS by
+// all its threads, the rotations run in one thread from there, and the
+// rotated column is written back by all threads).  Workgroup 0 may set stop
+// while the others run; whether they still scale then does not matter,
+// because a stopped cycle ends with x += V(:, 0..j) y and never reads
+// v_{j+1}.
+template <int JB>
+__global__ __launch_bounds__(kWG) void k_gm_axpy_scale(SolverState* S, GmSmall sm, int m, int j,
+                                                       const double* __restrict__ V,
+                                                       double* __restrict__ w, int n, size_t ld,
+                                                       const double* __restrict__ h1,
+                                                       double* hist, int* seg_hist) {
   __shared__ double red[kWaves];
+  __shared__ double hs[JB];
   __shared__ double col[64], c_s[64], s_s[64];
   __shared__ int bc_j, bc_s, bc_go;
   __shared__ double bc_rel;
   if (S->stop) return;
-  const double wn2 = sum_partials(norm_partials, n_partials, red);
-  if (blockIdx.x != 0 || gridDim.x == 1) {
-    const double hn = sqrt(wn2);
-    if (hn != 0.0) {
-      const double inv = 1.0 / hn;
-      const int b0 = gridDim.x == 1 ? 0 : (int)blockIdx.x - 1;
-      const int nb = gridDim.x == 1 ? 1 : (int)gridDim.x - 1;
-      for (int i = b0 * kWG + threadIdx.x; i < n; i += nb * kWG) w[i] *= inv;
-    }
-    if (blockIdx.x != 0) return;
+  const double* h2 = sm.h2;
+  if (threadIdx.x < JB) hs[threadIdx.x] = (threadIdx.x <= j) ? h2[threadIdx.x] : 0.0;
+  __syncthreads();
+  const double n1 = h2[j + 1];
+  double t2 = 0.0;
+  for (int k = 0; k <= j; ++k) t2 += hs[k] * hs[k];
+  const double b2 = n1 - t2;
+  const double hn = b2 > 1e-28 * n1 ? sqrt(b2) : 0.0;
+  const double inv = hn != 0.0 ? 1.0 / hn : 1.0;
+  for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
+    double v[JB];
+#pragma unroll
+    for (int k = 0; k < JB; ++k) v[k] = V[(size_t)(k <= j ? k : j) * ld + i];
+    double wi = w[i];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < JB; ++k) wi -= hs[k] * v[k];
+    w[i] = hn != 0.0 ? wi * inv : wi;
   }
-  __syncthreads();  // every thread has read red (sum_partials) before it is reused
+  if (blockIdx.x != 0) return;
   const int t = threadIdx.x;
   if (t <= j) {
     col[t] = h1[t] + h2[t];
@@ -1038,7 +1071,6 @@ __global__ __launch_bounds__(kWG) void k_gm_givens_scale(SolverState* S, GmSmall
   }
   __syncthreads();
   if (t == 0) {
-    const double hn = sqrt(wn2);
     col[j + 1] = hn;
     for (int i = 0; i < j; ++i) {
       const double a = col[i], b = col[i + 1];
@@ -1252,14 +1284,13 @@ gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_pa
         if (err != hipSuccess) return err;
         const int* gate = &w.S->stop;
         double* P = w.partials;
-#define GSE_GM_PASSES(JB)                                                                       \
-  hipLaunchKernelGGL((k_gm_dots<JB>), dim3(gb), dim3(kWG), 0, st, w.S, V, wv, n, ld, j, P);      \
-  hipLaunchKernelGGL(k_finish, dim3(j + 1), dim3(kWG), 0, st, P, gb, gb, j + 1, h1, gate);       \
-  hipLaunchKernelGGL((k_gm_axpy<JB, false>), dim3(gb), dim3(kWG), 0, st, w.S, V, wv, n, ld, j, h1, \
-                     P);                                                                        \
-  hipLaunchKernelGGL(k_finish, dim3(j + 1), dim3(kWG), 0, st, P, gb, gb, j + 1, sm.h2, gate);    \
-  hipLaunchKernelGGL((k_gm_axpy<JB, true>), dim3(gb), dim3(kWG), 0, st, w.S, V, wv, n, ld, j,     \
-                     sm.h2, P)
+#define GSE_GM_PASSES(JB)                                                                         \
+  hipLaunchKernelGGL((k_gm_dots<JB>), dim3(gb), dim3(kWG), 0, st, w.S, V, wv, n, ld, j, P);        \
+  hipLaunchKernelGGL(k_finish, dim3(j + 1), dim3(kWG), 0, st, P, gb, gb, j + 1, h1, gate);         \
+  hipLaunchKernelGGL((k_gm_axpy_dots<JB>), dim3(gb), dim3(kWG), 0, st, w.S, V, wv, n, ld, j, h1, P); \
+  hipLaunchKernelGGL(k_finish, dim3(j + 2), dim3(kWG), 0, st, P, gb, gb, j + 2, sm.h2, gate);      \
+  hipLaunchKernelGGL((k_gm_axpy_scale<JB>), dim3(gb), dim3(kWG), 0, st, w.S, sm, m, j, V, wv, n, ld, \
+                     h1, w.hist, w.seg_hist)
         // vector count rounded up to a multiple of 4 (m <= 60)
         switch ((j + 4) >> 2) {
           case 1: GSE_GM_PASSES(4); break;
@@ -1279,8 +1310,6 @@ gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_pa
           default: GSE_GM_PASSES(60); break;
         }
 #undef GSE_GM_PASSES
-        hipLaunchKernelGGL(k_gm_givens_scale, dim3(gb), dim3(kWG), 0, st, w.S, sm, m, j, h1, sm.h2,
-                           P, gb, w.hist, w.seg_hist, wv, n);
         err = hipGetLastError();
         if (err != hipSuccess) return err;
       }
