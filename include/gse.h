@@ -249,8 +249,10 @@ gse_status gse_spmv(const gse_matrix* A, int32_t k_segments, const double* x, do
                     void* stream);
 
 /* Choose the SpMV schedule of A for k_segments by timing the candidates
- * (tiles of 1024 / 2048 / 4096 non-zeros; 4, 8 or 16 lanes per row when no
- * row is longer than 64) with `reps` launches each on the caller's x
+ * (tiles of 1024 / 2048 / 4096 non-zeros; 1 ... 64 lanes per row, from an
+ * eighth of the longest row up, when no row is longer than 64; for
+ * per-row-block tables the row-tile ring and 1 ... 64 lanes) with `reps`
+ * launches each on the caller's x
  * (device [n_cols]) and y (device [n_rows], overwritten), then plan the
  * fastest.  Results are cached per process by matrix shape and, if the
  * environment variable GSE_AUTOTUNE_CACHE names a file, in that file.

@@ -120,9 +120,9 @@ gse_status autotune(int fmt, int segs, SpmvOperand op, const int32_t* row_ptr, i
     for (int L : {1, 2, 4, 8, 16, 32, 64}) cands.push_back({1024, L});
   } else {
     cands = {{1024, 0}, {2048, 0}, {4096, 0}};
-    if (max_row <= 64)
-      for (int L : {4, 8, 16})
-        if (L >= max_row / 4) cands.push_back({1024, L});
+    if (max_row <= 64)  // row-vector widths from an eighth of the longest row up
+      for (int L : {1, 2, 4, 8, 16, 32, 64})
+        if (L >= max_row / 8) cands.push_back({1024, L});
   }
   Choice best{0, 0, 1e30f};
   for (const Cand& c : cands) {

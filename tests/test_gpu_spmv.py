@@ -235,8 +235,8 @@ def test_autotune_picks_a_candidate_and_stays_exact():
         yd = torch.empty(A.n_rows, dtype=torch.float64, device=DEV)
         for s in (1, 3):
             M.autotune(s, xd, yd, reps=3)
-            assert (M.A.tile_nnz, M.A.rv_lanes) in {(1024, 0), (2048, 0), (4096, 0), (1024, 4),
-                                                     (1024, 8), (1024, 16)}
+            assert (M.A.tile_nnz, M.A.rv_lanes) in {(1024, 0), (2048, 0), (4096, 0)} | {
+                (1024, L) for L in (1, 2, 4, 8, 16, 32, 64)}
             first = (M.A.tile_nnz, M.A.rv_lanes)
             M.autotune(s, xd, yd, reps=3)  # cached: same choice
             assert (M.A.tile_nnz, M.A.rv_lanes) == first
