@@ -74,6 +74,9 @@ def lib():
         L.or_encode_blocks.restype = C.c_int
         L.or_encode_blocks.argtypes = [P, P, P, C.c_int32, C.c_int32, C.c_int64, C.c_int, C.c_int,
                                        C.c_int32, P, P, P, P, P, P, P, P, P]
+        L.or_encode_sampled.restype = C.c_int
+        L.or_encode_sampled.argtypes = [P, P, P, C.c_int32, C.c_int32, C.c_int64, C.c_int, C.c_int,
+                                        C.c_int32, P, P, P, P, P, P, P, P, P]
         L.or_gse_spmv_blocks.restype = None
         L.or_gse_spmv_blocks.argtypes = [C.c_int32, P, P, P, P, P, P, C.c_int32, C.c_int, C.c_int,
                                          C.c_int, P, P]
@@ -273,6 +276,36 @@ def encode_blocks(indptr, indices, data, n_cols: int, num_exp: int = 8, block_ro
     return EncodedBlocks(np.zeros(max(8, num_exp), np.int16), ci[:nnz], h[:nnz], t1[:nnz],
                          t2[:nnz], eta, ef.value, index_bits(num_exp), lo.value,
                          bs[:n_blocks].copy(), block_rows)
+
+
+def encode_sampled(indptr, indices, data, n_cols: int, num_exp: int = 8, block_rows: int = 256,
+                   sample_rows=None, layout: int = -1) -> Encoded:
+    """One table for the matrix from the pooled counts of the drawn rows
+    (one per block of ``block_rows`` rows), the largest exponent added."""
+    indptr = _c(indptr, np.int32)
+    indices = _c(indices, np.int32)
+    data = _c(data, np.float64)
+    n_rows = indptr.size - 1
+    nnz = data.size
+    sem = np.zeros(MAX_EXP, np.int16)
+    ci = np.empty(max(nnz, 1), np.uint32)
+    h = np.empty(max(nnz, 1), np.uint16)
+    t1 = np.empty(max(nnz, 1), np.uint16)
+    t2 = np.empty(max(nnz, 1), np.uint32)
+    eta = np.zeros(3, np.float64)
+    ef = C.c_double(0.0)
+    lo = C.c_int(0)
+    sr = None if sample_rows is None else _c(sample_rows, np.int32)
+    n_blocks = -(-n_rows // block_rows) if block_rows > 0 else 0
+    if sr is not None and sr.size < n_blocks:
+        raise OracleError(ERR_ARG, "sample_rows holds fewer rows than there are blocks")
+    rc = lib().or_encode_sampled(_p(indptr), _p(indices), _p(data), n_rows, n_cols, nnz, num_exp,
+                                 layout, block_rows, _p(sr), _p(sem), _p(ci), _p(h), _p(t1),
+                                 _p(t2), _p(eta), C.addressof(ef), C.addressof(lo))
+    if rc < 0:
+        raise OracleError(rc, "encode_sampled")
+    return Encoded(sem[:max(8, num_exp)].copy(), ci[:nnz], h[:nnz], t1[:nnz], t2[:nnz], eta,
+                   ef.value, index_bits(num_exp), lo.value)
 
 
 def decode_blocks(indptr, enc: EncodedBlocks, s: int):

@@ -341,6 +341,81 @@ int or_encode_blocks(const int32_t* row_ptr, const int32_t* col, const double* v
     return OR_OK;
 }
 
+/* Section III-B.1, sampling, the other reading: ONE table for the matrix,
+ * chosen from the exponent counts of the drawn rows pooled (each block of
+ * block_rows rows contributes the counts of its drawn row, which stands
+ * for every row of the block; blocks hold equally many rows except the
+ * last, so this weights the blocks by their rows up to the last one), by
+ * the global rules, and then the matrix's own largest exponent added when
+ * the pool misses it, as for a block table.  Encoding, eta and exact_frac
+ * (measured on all values) as or_encode with that table. */
+int or_encode_sampled(const int32_t* row_ptr, const int32_t* col, const double* val,
+                      int32_t n_rows, int32_t n_cols, int64_t nnz, int num_exp, int layout,
+                      int32_t block_rows, const int32_t* sample_rows, int16_t* sem_out,
+                      uint32_t* col_idx, uint16_t* head, uint16_t* tail1, uint32_t* tail2,
+                      double* eta3, double* exact_frac, int* layout_out) {
+    if (n_rows < 0 || n_cols < 0 || nnz < 0 || num_exp < 1 || num_exp > OR_MAX_EXP ||
+        block_rows < 1 || !sample_rows)
+        return OR_ERR_ARG;
+    int idx_bits = or_index_bits(num_exp);
+    if (layout < 0) layout = ((int64_t)n_cols > (1ll << (32 - idx_bits))) ? 1 : 0;
+    if (layout != 0 && layout != 1) return OR_ERR_ARG;
+    if (layout_out) *layout_out = layout;
+    if ((layout == 0 && (int64_t)n_cols > (1ll << (32 - idx_bits))) || nnz >= (1ll << 31))
+        return OR_ERR_RANGE;
+    uint32_t* all = (uint32_t*)malloc(2048 * sizeof(uint32_t));
+    uint32_t* pool = (uint32_t*)malloc(2048 * sizeof(uint32_t));
+    uint32_t* one = (uint32_t*)malloc(2048 * sizeof(uint32_t));
+    if (!all || !pool || !one) { free(all); free(pool); free(one); return OR_ERR_ARG; }
+    int rc = OR_OK;
+    if (or_exponent_histogram(val, nnz, all) > 0) rc = OR_ERR_NONFINITE;
+    int max_e = 0;
+    for (int e = 2046; e >= 1 && rc == OR_OK; --e)
+        if (all[e] > 0) { max_e = e; break; }
+    memset(pool, 0, 2048 * sizeof(uint32_t));
+    int32_t n_blocks = (int32_t)(((int64_t)n_rows + block_rows - 1) / block_rows);
+    for (int32_t bk = 0; bk < n_blocks && rc == OR_OK; ++bk) {
+        int32_t r0 = bk * block_rows;
+        int32_t r1 = (int32_t)((int64_t)r0 + block_rows < n_rows ? r0 + block_rows : n_rows);
+        int32_t sr = sample_rows[bk];
+        if (sr < r0 || sr >= r1) { rc = OR_ERR_ARG; break; }
+        or_exponent_histogram(val + row_ptr[sr], row_ptr[sr + 1] - row_ptr[sr], one);
+        for (int e = 0; e < 2048; ++e) pool[e] += one[e];
+    }
+    if (rc == OR_OK) {
+        int used = block_table(pool, max_e, num_exp, sem_out);
+        if (used < 0) rc = used;
+        else {
+            uint64_t covered = 0;
+            for (int i = 0; i < used; ++i) covered += all[sem_out[i] - 1];
+            if (exact_frac) *exact_frac = nnz ? (double)covered / (double)nnz : 1.0;
+            rc = or_encode_values(val, col, nnz, sem_out, idx_bits, layout, col_idx, head, tail1,
+                                  tail2);
+        }
+    }
+    free(all);
+    free(pool);
+    free(one);
+    if (rc != OR_OK) return rc;
+    if (eta3) {
+        double amax = 0.0, emax[3] = {0.0, 0.0, 0.0};
+        for (int32_t r = 0; r < n_rows; ++r) {
+            double a = 0.0, es[3] = {0.0, 0.0, 0.0};
+            for (int32_t j = row_ptr[r]; j < row_ptr[r + 1]; ++j) {
+                a += fabs(val[j]);
+                for (int s = 1; s <= 3; ++s)
+                    es[s - 1] += fabs(val[j] - or_decode_one(col_idx[j], head[j], tail1[j],
+                                                             tail2[j], sem_out, idx_bits, layout,
+                                                             s));
+            }
+            if (a > amax) amax = a;
+            for (int s = 0; s < 3; ++s) if (es[s] > emax[s]) emax[s] = es[s];
+        }
+        for (int s = 0; s < 3; ++s) eta3[s] = amax > 0.0 ? emax[s] / amax : 0.0;
+    }
+    return OR_OK;
+}
+
 /* Algorithm 2 and its wider variants with per-block tables: row r decodes
  * its values with the table of its block. */
 void or_gse_spmv_blocks(int32_t n_rows, const int32_t* row_ptr, const uint32_t* col_idx,

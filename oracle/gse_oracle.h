@@ -99,6 +99,14 @@ int or_encode_blocks(const int32_t* row_ptr, const int32_t* col, const double* v
                      int32_t block_rows, const int32_t* sample_rows, int16_t* block_sem,
                      uint32_t* col_idx, uint16_t* head, uint16_t* tail1, uint32_t* tail2,
                      double* eta3, double* exact_frac, int* layout_out);
+/* One table for the matrix from the pooled exponent counts of one drawn row
+ * per block (sample_rows, required), the matrix's largest exponent added if
+ * missed; sem_out as for or_encode. */
+int or_encode_sampled(const int32_t* row_ptr, const int32_t* col, const double* val,
+                      int32_t n_rows, int32_t n_cols, int64_t nnz, int num_exp, int layout,
+                      int32_t block_rows, const int32_t* sample_rows, int16_t* sem_out64,
+                      uint32_t* col_idx, uint16_t* head, uint16_t* tail1, uint32_t* tail2,
+                      double* eta3, double* exact_frac, int* layout_out);
 void or_gse_spmv_blocks(int32_t n_rows, const int32_t* row_ptr, const uint32_t* col_idx,
                         const uint16_t* head, const uint16_t* tail1, const uint32_t* tail2,
                         const int16_t* block_sem, int32_t block_rows, int idx_bits, int layout,

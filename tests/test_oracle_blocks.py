@@ -17,6 +17,11 @@ misses it.  The checks come from outside the oracle's code:
     block-decoded products, and eta against its definition;
   * argument errors, and that every value of a block is representable even
     when the drawn row misses the block's maximum exponent.
+
+The other reading, one table for the whole matrix from the drawn rows'
+counts pooled, is pinned the same way: brute force over the pooled rows,
+every row drawn reduces to the exact global encode, and its planes are the
+global encoder's with that table reused.
 """
 import collections
 import math
@@ -222,3 +227,48 @@ def test_layered_medium_blocks_beat_the_global_table():
     b = O.encode_blocks(A.indptr, A.indices, A.data, A.n_cols, block_rows=256)
     assert b.exact_frac > g.exact_frac + 0.2
     assert b.eta[0] < g.eta[0]
+
+
+# ---- one table for the matrix from the pooled drawn rows (the other reading) ----
+
+@pytest.mark.parametrize("k", [1, 3, 8, 64])
+def test_pooled_sample_table_matches_brute_force(k):
+    for A, R in small_cases():
+        sr = block_sample_rows(A.n_rows, R, 21)
+        enc = O.encode_sampled(A.indptr, A.indices, A.data, A.n_cols, num_exp=k, block_rows=R,
+                               sample_rows=sr)
+        pooled = np.concatenate([A.data[A.indptr[s]:A.indptr[s + 1]] for s in sr])
+        want = brute_table(pooled, A.data, k)
+        got = [int(t) for t in enc.table]
+        assert got[:len(want)] == want and not any(got[len(want):]), A.name
+        # exact_frac is measured on all values
+        fields = np.array([field(v) for v in A.data])
+        assert enc.exact_frac == pytest.approx(np.isin(fields + 1, want).mean(), abs=1e-15)
+
+
+def test_every_row_drawn_is_the_global_encode():
+    for A, _ in small_cases():
+        enc = O.encode_sampled(A.indptr, A.indices, A.data, A.n_cols, block_rows=1,
+                               sample_rows=np.arange(A.n_rows, dtype=np.int32))
+        g = O.encode(A.indptr, A.indices, A.data, A.n_cols)
+        assert np.array_equal(enc.table, g.table)
+        for a, c in ((enc.col_idx, g.col_idx), (enc.head, g.head), (enc.tail1, g.tail1),
+                     (enc.tail2, g.tail2)):
+            assert np.array_equal(a, c)
+        assert np.array_equal(enc.eta, g.eta) and enc.exact_frac == g.exact_frac
+
+
+def test_pooled_sample_planes_are_the_encode_of_that_table():
+    A, R = small_cases()[0]
+    sr = block_sample_rows(A.n_rows, R, 4)
+    enc = O.encode_sampled(A.indptr, A.indices, A.data, A.n_cols, block_rows=R, sample_rows=sr)
+    again = O.encode(A.indptr, A.indices, A.data, A.n_cols, sem_in=enc.table[:8])
+    for a, c in ((enc.col_idx, again.col_idx), (enc.head, again.head), (enc.tail1, again.tail1),
+                 (enc.tail2, again.tail2)):
+        assert np.array_equal(a, c)
+    assert np.allclose(enc.eta, again.eta, rtol=0, atol=0)
+    bad = sr.copy()
+    bad[0] = R  # a row of the next block
+    with pytest.raises(O.OracleError) as e:
+        O.encode_sampled(A.indptr, A.indices, A.data, A.n_cols, block_rows=R, sample_rows=bad)
+    assert e.value.code == O.ERR_ARG
