@@ -266,6 +266,9 @@ static int block_table(const uint32_t* sample_hist, int block_max_e, int num_exp
     if (block_max_e <= 0) return used;
     for (int i = 0; i < used; ++i)
         if (sem[i] == block_max_e + 1) return used;
+    /* a shared exponent below 63 would put its grid below the normal range
+     * (the same rule as for the sample's own choice) */
+    if (block_max_e < 63) return OR_ERR_RANGE;
     if (used < num_exp) used += 1;
     sem[used - 1] = (int16_t)(block_max_e + 1);
     return used;

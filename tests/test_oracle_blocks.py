@@ -272,3 +272,18 @@ def test_pooled_sample_planes_are_the_encode_of_that_table():
     with pytest.raises(O.OracleError) as e:
         O.encode_sampled(A.indptr, A.indices, A.data, A.n_cols, block_rows=R, sample_rows=bad)
     assert e.value.code == O.ERR_ARG
+
+
+def test_added_maximum_below_the_normal_grid_is_a_range_error():
+    # the drawn row holds only zeros; the block's largest value has exponent
+    # field 10, whose shared exponent 11 would leave the normal range
+    indptr = np.array([0, 2, 4] + [4] * 127, dtype=np.int32)
+    data = np.array([0.0, 0.0, 2.0 ** -1013, 2.0 ** -1014])
+    A = CSR(129, 2, indptr, np.array([0, 1, 0, 1], np.int32), data, "tiny")
+    sr = np.array([0, 128], np.int32)
+    with pytest.raises(O.OracleError) as e:
+        O.encode_blocks(A.indptr, A.indices, A.data, 2, block_rows=128, sample_rows=sr)
+    assert e.value.code == O.ERR_RANGE
+    with pytest.raises(O.OracleError) as e:
+        O.encode_sampled(A.indptr, A.indices, A.data, 2, block_rows=128, sample_rows=sr)
+    assert e.value.code == O.ERR_RANGE
