@@ -519,7 +519,8 @@ def leg_blocks(torch, G, seed, copies, block_rows=4096, A_cg=None, b_cg=None, x_
     """Per-row-block tables (Section III-B.1, sampling) on the layered medium
     (128^3, 16 slabs whose coefficients sit at levels spread over eight
     decades, one decade within a slab): encode time of the global table, of
-    exact block tables and of tables from one drawn row per block; SpMV time
+    exact block tables, of tables from one drawn row per block and of one
+    table from those drawn rows pooled; SpMV time
     per segment count over rotated copies (each on its default schedule);
     error against the host FP64 product with x = 1,
     norm-wise and per row; eta_s and the share of exactly represented
@@ -540,7 +541,8 @@ def leg_blocks(torch, G, seed, copies, block_rows=4096, A_cg=None, b_cg=None, x_
     xs = torch.ones(A.n_cols, dtype=torch.float64, device=dev)
     ys = [torch.empty(A.n_rows, dtype=torch.float64, device=dev) for _ in range(copies)]
     variants = {"global": {}, "blocks_exact": {"block_rows": block_rows},
-                "blocks_sampled": {"block_rows": block_rows, "sample_rows": sr}}
+                "blocks_sampled": {"block_rows": block_rows, "sample_rows": sr},
+                "global_sampled": {"block_rows": block_rows, "sample_rows": sr, "pooled": True}}
     out = {"workload": "layered3d_128^3_7pt_16slabs_8+1decades", "n_rows": A.n_rows,
            "nnz": A.nnz, "block_rows": block_rows, "seed": seed, "x": "ones"}
     for name, kw in variants.items():
@@ -551,7 +553,10 @@ def leg_blocks(torch, G, seed, copies, block_rows=4096, A_cg=None, b_cg=None, x_
         for _ in range(3):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            if kw:
+            if kw.get("pooled"):
+                G.gse_encode_sampled(M.row_ptr, ci, va, A.n_rows, A.n_cols, A.nnz, 8, block_rows,
+                                     kw["sample_rows"], M.A, M.ws)
+            elif kw:
                 G.gse_encode_blocks(M.row_ptr, ci, va, A.n_rows, A.n_cols, A.nnz, 8, block_rows,
                                     kw.get("sample_rows"), M.A, M.ws)
             else:
@@ -559,8 +564,9 @@ def leg_blocks(torch, G, seed, copies, block_rows=4096, A_cg=None, b_cg=None, x_
             enc_ms.append((time.perf_counter() - t0) * 1e3)
         rec = {"encode_ms": round(float(np.median(enc_ms)), 3), "eta": [float(e) for e in M.eta],
                "exact_frac": round(float(M.A.exact_frac), 4), "rv_lanes": int(M.A.rv_lanes),
-               "kernel": kernel_name(M.A).replace(">", ", blocks>") if kw else kernel_name(M.A)}
-        tables = (G.gse_block_table_entries(A.n_rows, block_rows, 8) * 2) if kw else 0
+               "kernel": (kernel_name(M.A).replace(">", ", blocks>") if M.A.block_rows
+                          else kernel_name(M.A))}
+        tables = (G.gse_block_table_entries(A.n_rows, block_rows, 8) * 2) if M.A.block_rows else 0
         for s, pb in ((1, 6), (2, 8), (3, 12)):
             us = rotated_launch_us(torch, stream,
                                    [lambda m=m, y=y, s=s: m.spmv(s, xs, y) for m, y in zip(mats, ys)])

@@ -208,6 +208,29 @@ gse_status gse_encode_blocks(const int32_t* row_ptr, const int32_t* col, const d
 /* Entries block_sem needs (0 for invalid arguments). */
 int64_t gse_block_table_entries(int32_t n_rows, int32_t block_rows, int32_t num_exp);
 
+/* One shared-exponent table for the whole matrix, chosen from a sample
+ * (Section III-B.1: one random row of each row block stands for that
+ * block's exponents): the exponent counts of the drawn rows sample_rows[b],
+ * one in each block of block_rows rows, are pooled and the table is chosen
+ * from them as gse_encode chooses it from the full histogram (count
+ * descending, ties to the larger exponent, the pool's maximum forced in);
+ * then, if the table misses the matrix's own largest exponent, that exponent
+ * goes into the next free slot or in place of the last one (every value needs
+ * a shared exponent above its own, Section III-B.2).  The planes, index
+ * layouts, eta, exact_frac and default plan are those of gse_encode with that
+ * table; the result is an ordinary one-table matrix (block_rows 0) that every
+ * operator, solver, the batched solver and the server take.
+ *   block_rows  : >= 1 (rows per sampled block; the last may be shorter).
+ *   sample_rows : device int32 [ceil(n_rows / block_rows)], one row of each
+ *                 block, drawn by the caller; required.
+ * Errors: those of gse_encode; GSE_ERR_ARG for block_rows < 1, a NULL
+ * sample_rows or a sample row outside its block.  Workspace as gse_encode.
+ * Synchronizes `stream`. */
+gse_status gse_encode_sampled(const int32_t* row_ptr, const int32_t* col, const double* val,
+                              int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t num_exp,
+                              int32_t block_rows, const int32_t* sample_rows, gse_matrix* A,
+                              void* ws, size_t ws_bytes, void* stream);
+
 /* gse_encode for callers that cannot allocate device memory (tight serving
  * loops, harnesses that forbid hipMalloc; not for use under graph capture,
  * as it reads the table back and synchronizes like gse_encode):

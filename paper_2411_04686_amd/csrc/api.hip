@@ -256,39 +256,30 @@ gse_status encode_blocks(const int32_t* row_ptr, const int32_t* col, const doubl
   return GSE_OK;
 }
 
-gse_status encode_matrix(const int32_t* row_ptr, const int32_t* col, const double* val,
-                         int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t num_exp,
-                         const int16_t* sem_in, gse_matrix* A, void* ws, size_t ws_bytes,
-                         hipStream_t st) {
-  int layout = 0;
-  gse_status cs = check_encode(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, A, ws, ws_bytes,
-                               &layout);
-  if (cs != GSE_OK) return cs;
-  const int ib = index_bits(num_exp);
-  if (sem_in) {
-    for (int i = 0; i < num_exp; ++i) {
-      if (sem_in[i] < 64 || sem_in[i] > 2047)
-        return fail(GSE_ERR_RANGE, "shared exponent %d out of range", (int)sem_in[i]);
-      for (int k = 0; k < i; ++k)
-        if (sem_in[k] == sem_in[i]) return fail(GSE_ERR_ARG, "duplicate shared exponent");
-    }
-  }
-  EncodeScratch* sc = reinterpret_cast<EncodeScratch*>(ws);
+// Shared part of the one-table encoders: the fields of A the launches need.
+static void set_global_fields(const int32_t* row_ptr, int32_t n_rows, int32_t n_cols, int64_t nnz,
+                              int32_t num_exp, int layout, gse_matrix* A) {
   A->n_rows = n_rows;
   A->n_cols = n_cols;
   A->nnz = nnz;
   A->num_exp = num_exp;
-  A->idx_bits = ib;
+  A->idx_bits = index_bits(num_exp);
   A->idx_layout = layout;
   A->row_ptr = row_ptr;
   A->block_rows = 0;
   A->block_stride = 0;
-  hipError_t e = launch_encode(row_ptr, col, val, n_rows, (int32_t)nnz, num_exp, sem_in, A, sc, st);
-  if (e != hipSuccess) return hip_fail(e, "gse_encode launch");
+}
+
+// Shared part of the one-table encoders after the launches: read the
+// scratch record back, plan the default SpMV schedule, fill the host fields
+// of A, report the encoder's errors.
+static gse_status finish_global(const int32_t* row_ptr, int32_t n_rows, int64_t nnz,
+                                gse_matrix* A, const EncodeScratch* sc, hipStream_t st,
+                                const char* what) {
   EncodeScratch h;
-  e = hipMemcpyAsync(&h, sc, sizeof h, hipMemcpyDeviceToHost, st);
+  hipError_t e = hipMemcpyAsync(&h, sc, sizeof h, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_fail(e, "gse_encode");
+  if (e != hipSuccess) return hip_fail(e, what);
   int32_t nt, rv, mr;
   gse_status ps = plan_common(row_ptr, n_rows, nnz, A->tile_row, A->tile_cap, kDefaultTile, -1, st,
                               &nt, &rv, &mr);
@@ -304,11 +295,54 @@ gse_status encode_matrix(const int32_t* row_ptr, const int32_t* col, const doubl
   for (int i = 0; i < 4; ++i) memcpy(&nrm[i], &h.norm_bits[i], sizeof(double));
   for (int s = 0; s < 3; ++s) A->eta[s] = nrm[0] > 0.0 ? nrm[s + 1] / nrm[0] : 0.0;
   if (h.nonfinite) return fail(GSE_ERR_NONFINITE, "%d non-finite values", h.nonfinite);
+  if (h.range_err & 4) return fail(GSE_ERR_ARG, "a sample row lies outside its block");
   if (h.range_err & 1) return fail(GSE_ERR_RANGE, "a shared exponent is below 63");
   if (h.range_err & 2) return fail(GSE_ERR_RANGE, "a value has no larger shared exponent in the table");
   return GSE_OK;
 }
 
+gse_status encode_matrix(const int32_t* row_ptr, const int32_t* col, const double* val,
+                         int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t num_exp,
+                         const int16_t* sem_in, gse_matrix* A, void* ws, size_t ws_bytes,
+                         hipStream_t st) {
+  int layout = 0;
+  gse_status cs = check_encode(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, A, ws, ws_bytes,
+                               &layout);
+  if (cs != GSE_OK) return cs;
+  if (sem_in) {
+    for (int i = 0; i < num_exp; ++i) {
+      if (sem_in[i] < 64 || sem_in[i] > 2047)
+        return fail(GSE_ERR_RANGE, "shared exponent %d out of range", (int)sem_in[i]);
+      for (int k = 0; k < i; ++k)
+        if (sem_in[k] == sem_in[i]) return fail(GSE_ERR_ARG, "duplicate shared exponent");
+    }
+  }
+  EncodeScratch* sc = reinterpret_cast<EncodeScratch*>(ws);
+  set_global_fields(row_ptr, n_rows, n_cols, nnz, num_exp, layout, A);
+  hipError_t e = launch_encode(row_ptr, col, val, n_rows, (int32_t)nnz, num_exp, sem_in, A, sc, st);
+  if (e != hipSuccess) return hip_fail(e, "gse_encode launch");
+  return finish_global(row_ptr, n_rows, nnz, A, sc, st, "gse_encode");
+}
+
+// One table from the pooled exponents of one drawn row per block
+// (Section III-B.1, sampling).
+static gse_status encode_sampled(const int32_t* row_ptr, const int32_t* col, const double* val,
+                                 int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t num_exp,
+                                 int32_t block_rows, const int32_t* sample_rows, gse_matrix* A,
+                                 void* ws, size_t ws_bytes, hipStream_t st) {
+  int layout = 0;
+  gse_status cs = check_encode(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, A, ws, ws_bytes,
+                               &layout);
+  if (cs != GSE_OK) return cs;
+  if (block_rows < 1) return fail(GSE_ERR_ARG, "block_rows must be positive");
+  if (!sample_rows) return fail(GSE_ERR_ARG, "sample_rows is NULL");
+  EncodeScratch* sc = reinterpret_cast<EncodeScratch*>(ws);
+  set_global_fields(row_ptr, n_rows, n_cols, nnz, num_exp, layout, A);
+  hipError_t e = launch_encode_sampled(row_ptr, col, val, n_rows, (int32_t)nnz, num_exp, block_rows,
+                                       sample_rows, A, sc, st);
+  if (e != hipSuccess) return hip_fail(e, "gse_encode_sampled launch");
+  return finish_global(row_ptr, n_rows, nnz, A, sc, st, "gse_encode_sampled");
+}
 
 }  // namespace gse
 
@@ -386,6 +420,14 @@ gse_status gse_encode_blocks(const int32_t* row_ptr, const int32_t* col, const d
                              void* ws, size_t ws_bytes, void* stream) {
   return encode_blocks(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, block_rows, sample_rows, A,
                        ws, ws_bytes, (hipStream_t)stream);
+}
+
+gse_status gse_encode_sampled(const int32_t* row_ptr, const int32_t* col, const double* val,
+                              int32_t n_rows, int32_t n_cols, int64_t nnz, int32_t num_exp,
+                              int32_t block_rows, const int32_t* sample_rows, gse_matrix* A,
+                              void* ws, size_t ws_bytes, void* stream) {
+  return encode_sampled(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, block_rows, sample_rows, A,
+                        ws, ws_bytes, (hipStream_t)stream);
 }
 
 int64_t gse_block_table_entries(int32_t n_rows, int32_t block_rows, int32_t num_exp) {

@@ -14,6 +14,13 @@
 //            word, written to the four planes with 16-byte stores.
 //   k_eta    per row: sums of |a| and |a - a_s| for s = 1, 2, 3; the row
 //            maxima give eta_s = ||A - A_s||_inf / ||A||_inf.
+// The pooled-sample encoder (Section III-B.1, sampling) replaces k_hist by
+//   k_field_scan  the matrix's largest finite exponent field and its count
+//                 of Inf/NaN values,
+//   k_hist_rows   the histogram of one drawn row per block of rows,
+// and k_topk adds the matrix's largest exponent when the pooled choice
+// misses it; k_encode then counts the exactly shared values itself
+// (k_fold_covered adds up its partial counts).
 #include "gse_internal.h"
 
 namespace gse {
@@ -34,6 +41,71 @@ __global__ __launch_bounds__(256) void k_hist(const double* __restrict__ val, in
     const uint64_t u = double_to_bits(val[i]);
     atomicAdd(&h[(u >> 52) & 0x7FFu], 1u);
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2048; i += blockDim.x)
+    if (h[i]) atomicAdd(&sc->hist[i], h[i]);
+}
+
+// Largest exponent field below 2047 over all values (into sc->max_field)
+// and the number of Inf/NaN values (into sc->nonfinite): one atomic of each
+// per workgroup.
+__global__ __launch_bounds__(256) void k_field_scan(const double* __restrict__ val, int nnz,
+                                                   EncodeScratch* sc) {
+  __shared__ int red_m[kWaves], red_n[kWaves];
+  int m = 0, nf = 0;
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += stride) {
+    const int e = (int)((double_to_bits(val[i]) >> 52) & 0x7FFu);
+    if (e == 2047) ++nf;
+    else m = e > m ? e : m;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    m = max(m, __shfl_xor(m, off, 64));
+    nf += __shfl_xor(nf, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red_m[threadIdx.x >> 6] = m;
+    red_n[threadIdx.x >> 6] = nf;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kWaves; ++w) {
+      m = max(m, red_m[w]);
+      nf += red_n[w];
+    }
+    if (m > 0) atomicMax(&sc->max_field, m);
+    if (nf) atomicAdd(&sc->nonfinite, nf);
+  }
+}
+
+// Pooled histogram of the drawn rows: one wave per block of rows, block b
+// adds the exponent fields of row sample_rows[b] (bit 4 of range_err when
+// that row lies outside block b).  LDS-privatised like k_hist.
+__global__ __launch_bounds__(256) void k_hist_rows(const int32_t* __restrict__ row_ptr, int n_rows,
+                                                   const double* __restrict__ val, int block_rows,
+                                                   const int32_t* __restrict__ sample_rows,
+                                                   EncodeScratch* sc) {
+  __shared__ uint32_t h[2048];
+  for (int i = threadIdx.x; i < 2048; i += blockDim.x) h[i] = 0u;
+  __syncthreads();
+  const int n_blocks = (int)(((long long)n_rows + block_rows - 1) / block_rows);
+  const int lane = threadIdx.x & 63;
+  const int wstride = gridDim.x * kWaves;
+  bool bad = false;
+  for (int b = blockIdx.x * kWaves + (threadIdx.x >> 6); b < n_blocks; b += wstride) {
+    const long long r0 = (long long)b * block_rows;
+    const long long r1 = min(r0 + block_rows, (long long)n_rows);
+    const int sr = sample_rows[b];
+    if (sr < r0 || sr >= r1) {
+      bad = true;
+      continue;
+    }
+    const int j1 = row_ptr[sr + 1];
+    for (int j = row_ptr[sr] + lane; j < j1; j += 64)
+      atomicAdd(&h[(double_to_bits(val[j]) >> 52) & 0x7FFu], 1u);
+  }
+  if (bad && lane == 0) atomicOr(&sc->range_err, 4);
   __syncthreads();
   for (int i = threadIdx.x; i < 2048; i += blockDim.x)
     if (h[i]) atomicAdd(&sc->hist[i], h[i]);
@@ -73,7 +145,13 @@ __device__ __forceinline__ void fill_slot_lookup(const int16_t* tab, int8_t* slo
   }
 }
 
-__global__ __launch_bounds__(256) void k_topk(EncodeScratch* sc, int num_exp, SemIn in) {
+// pooled: sc->hist holds the drawn rows' counts (k_hist_rows) and
+// sc->max_field, sc->nonfinite the whole matrix's (k_field_scan); the
+// matrix's largest exponent then takes the next free slot, or the last, when
+// the table misses it (as for a block's table, k_blk_encode), and the count
+// of exactly shared values is left to k_encode.
+__global__ __launch_bounds__(256) void k_topk(EncodeScratch* sc, int num_exp, SemIn in,
+                                              int pooled) {
   __shared__ uint32_t h[2048];
   __shared__ unsigned char taken[2048];
   __shared__ unsigned long long red[kWaves];
@@ -82,6 +160,9 @@ __global__ __launch_bounds__(256) void k_topk(EncodeScratch* sc, int num_exp, Se
   for (int i = threadIdx.x; i < 2048; i += blockDim.x) {
     h[i] = sc->hist[i];
     taken[i] = 0;
+    // pooled: the counts now live in LDS; the global bins become the
+    // per-workgroup partial counts of k_encode<true>
+    if (pooled) sc->hist[i] = 0u;
   }
   __syncthreads();
   if (in.have) {
@@ -135,21 +216,34 @@ __global__ __launch_bounds__(256) void k_topk(EncodeScratch* sc, int num_exp, Se
       chosen[used - 1] = max_e;
     }
     int range_err = 0;
+    for (int i = 0; i < used; ++i)
+      if (chosen[i] < 63) range_err = 1;
+    const int gmax = pooled ? sc->max_field : 0;
+    if (gmax > 0) {
+      bool present = false;
+      for (int i = 0; i < used; ++i) present = present || chosen[i] == gmax;
+      if (!present) {
+        if (used < num_exp) ++used;
+        chosen[used - 1] = gmax;
+        if (gmax < 63) range_err = 1;
+      }
+    }
     unsigned long long cov = 0;
     for (int i = 0; i < GSE_MAX_EXP; ++i) {
       sc->sem[i] = 0;
       tab[i] = 0;
     }
     for (int i = 0; i < used; ++i) {
-      if (chosen[i] < 63) range_err = 1;
       sc->sem[i] = (int16_t)(chosen[i] + 1);
       tab[i] = (int16_t)(chosen[i] + 1);
       cov += h[chosen[i]];
     }
     sc->used = used;
-    sc->covered = cov;
-    sc->range_err = range_err;
-    sc->nonfinite = (int)h[2047];
+    if (range_err) sc->range_err |= 1;
+    if (!pooled) {
+      sc->covered = cov;
+      sc->nonfinite = (int)h[2047];
+    }
   }
   __syncthreads();
   fill_slot_lookup(tab, sc->slot_of);
@@ -199,6 +293,11 @@ __device__ __forceinline__ Words4 encode_value(uint64_t u, int cv, const int8_t*
 
 // Groups of 8 values per thread; writes 32 + 16 + 16 + 32 bytes per group
 // (the planes are padded, so the tail group writes zeros past nnz).
+// COUNT: also count the values whose own exponent is shared, one partial
+// sum per workgroup added to bin (blockIdx & 2047) of sc->hist: thousands of
+// atomics on a single word serialise in its L2 channel and cost more than
+// the encode itself.  k_fold_covered adds the bins up.
+template <bool COUNT>
 __global__ __launch_bounds__(256) void k_encode(const double* __restrict__ val,
                                                 const int32_t* __restrict__ col, int nnz,
                                                 EncodeScratch* sc, int idx_bits, int in_value,
@@ -216,6 +315,7 @@ __global__ __launch_bounds__(256) void k_encode(const double* __restrict__ val,
   const int n_groups = (nnz + 7) >> 3;
   const int stride = gridDim.x * blockDim.x;
   int bad = 0;
+  unsigned covered = 0;
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n_groups; g += stride) {
     uint32_t cw[8], t2[8], hh[4], tt[4];
 #pragma unroll
@@ -247,6 +347,7 @@ __global__ __launch_bounds__(256) void k_encode(const double* __restrict__ val,
       if (j < nnz) {
         int exact = 0;
         const Words4 w = encode_value(uv[k], cv[k], slot_s, sem_s, idx_bits, in_value, &bad, &exact);
+        if constexpr (COUNT) covered += (unsigned)exact;
         c = w.c;
         h16 = w.h16;
         t116 = w.t1;
@@ -267,6 +368,33 @@ __global__ __launch_bounds__(256) void k_encode(const double* __restrict__ val,
     tp[1] = make_uint4(t2[4], t2[5], t2[6], t2[7]);
   }
   if (bad) atomicOr(&sc->range_err, 2);
+  if constexpr (COUNT) {
+    __shared__ unsigned red[kWaves];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) covered += __shfl_xor(covered, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = covered;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned t = 0;
+      for (int w = 0; w < kWaves; ++w) t += red[w];
+      if (t) atomicAdd(&sc->hist[blockIdx.x & 2047], t);
+    }
+  }
+}
+
+// sc->covered = the sum of k_encode<true>'s partial counts (one workgroup).
+__global__ __launch_bounds__(256) void k_fold_covered(EncodeScratch* sc) {
+  __shared__ unsigned long long red[kWaves];
+  unsigned long long t = 0;
+  for (int i = threadIdx.x; i < 2048; i += blockDim.x) t += sc->hist[i];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kWaves; ++w) t += red[w];
+    sc->covered = t;
+  }
 }
 
 __device__ __forceinline__ int slot_in(uint32_t c, uint32_t h, const ColSplit& cs) {
@@ -541,13 +669,46 @@ hipError_t launch_encode(const int32_t* row_ptr, const int32_t* col, const doubl
   int hb = (nnz + 256 * 16 - 1) / (256 * 16);
   hb = hb < 1 ? 1 : (hb > 2048 ? 2048 : hb);
   hipLaunchKernelGGL(k_hist, dim3(hb), dim3(256), 0, st, val, nnz, sc);
-  hipLaunchKernelGGL(k_topk, dim3(1), dim3(256), 0, st, sc, num_exp, in);
+  hipLaunchKernelGGL(k_topk, dim3(1), dim3(256), 0, st, sc, num_exp, in, 0);
   const int groups = (nnz + 7) / 8;
   int eb = (groups + 255) / 256;
   eb = eb < 1 ? 1 : (eb > 16384 ? 16384 : eb);
   const bool in_value = A->idx_layout == GSE_IDX_VALUE;
-  hipLaunchKernelGGL(k_encode, dim3(eb), dim3(256), 0, st, val, col, nnz, sc, A->idx_bits,
+  hipLaunchKernelGGL(k_encode<false>, dim3(eb), dim3(256), 0, st, val, col, nnz, sc, A->idx_bits,
                      in_value ? 1 : 0, A->col_idx, A->head, A->tail1, A->tail2);
+  int rbk = (n_rows + 31) / 32;
+  rbk = rbk < 1 ? 1 : (rbk > 4096 ? 4096 : rbk);
+  hipLaunchKernelGGL(k_eta<false>, dim3(rbk), dim3(256), 0, st, row_ptr, n_rows, val, A->col_idx,
+                     A->head, A->tail1, A->tail2, sc, col_split(A->idx_bits, in_value),
+                     (const int16_t*)nullptr, 1, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_sampled(const int32_t* row_ptr, const int32_t* col, const double* val,
+                                 int32_t n_rows, int32_t nnz, int32_t num_exp, int32_t block_rows,
+                                 const int32_t* sample_rows, gse_matrix* A, EncodeScratch* sc,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, st,
+                     reinterpret_cast<unsigned long long*>(sc),
+                     (int)(sizeof(EncodeScratch) / 8));
+  int hb = (nnz + 256 * 16 - 1) / (256 * 16);
+  hb = hb < 1 ? 1 : (hb > 2048 ? 2048 : hb);
+  hipLaunchKernelGGL(k_field_scan, dim3(hb), dim3(256), 0, st, val, nnz, sc);
+  const int64_t n_blocks = ((int64_t)n_rows + block_rows - 1) / block_rows;
+  // four drawn rows per workgroup, at most 1024 workgroups (grid-stride)
+  int sb = (int)((n_blocks + kWaves - 1) / kWaves);
+  sb = sb < 1 ? 1 : (sb > 1024 ? 1024 : sb);
+  hipLaunchKernelGGL(k_hist_rows, dim3(sb), dim3(256), 0, st, row_ptr, n_rows, val, block_rows,
+                     sample_rows, sc);
+  SemIn in{};
+  hipLaunchKernelGGL(k_topk, dim3(1), dim3(256), 0, st, sc, num_exp, in, 1);
+  const int groups = (nnz + 7) / 8;
+  int eb = (groups + 255) / 256;
+  eb = eb < 1 ? 1 : (eb > 16384 ? 16384 : eb);
+  const bool in_value = A->idx_layout == GSE_IDX_VALUE;
+  hipLaunchKernelGGL(k_encode<true>, dim3(eb), dim3(256), 0, st, val, col, nnz, sc, A->idx_bits,
+                     in_value ? 1 : 0, A->col_idx, A->head, A->tail1, A->tail2);
+  hipLaunchKernelGGL(k_fold_covered, dim3(1), dim3(256), 0, st, sc);
   int rbk = (n_rows + 31) / 32;
   rbk = rbk < 1 ? 1 : (rbk > 4096 ? 4096 : rbk);
   hipLaunchKernelGGL(k_eta<false>, dim3(rbk), dim3(256), 0, st, row_ptr, n_rows, val, A->col_idx,

@@ -205,7 +205,7 @@ struct EncodeScratch {
   int32_t nonfinite;
   int32_t range_err;
   int32_t used;
-  int32_t pad0;
+  int32_t max_field;  // pooled-sample encode: the matrix's largest finite exponent field
   int16_t sem[GSE_MAX_EXP];
   unsigned long long covered;
   unsigned long long norm_bits[4];  // max row sums |a|, |a - a_1|, |a - a_2|, |a - a_3| (as bits)
@@ -221,6 +221,15 @@ hipError_t launch_encode_blocks(const int32_t* row_ptr, const int32_t* col, cons
                                 int32_t n_rows, int32_t nnz, int32_t num_exp,
                                 const int32_t* sample_rows, gse_matrix* A, EncodeScratch* sc,
                                 hipStream_t st);
+
+// One table for the matrix from the pooled exponents of one drawn row per
+// block of block_rows rows (sample_rows[b] in block b), the matrix's largest
+// exponent added when missed; then the planes and perturbations of the
+// global encoder.
+hipError_t launch_encode_sampled(const int32_t* row_ptr, const int32_t* col, const double* val,
+                                 int32_t n_rows, int32_t nnz, int32_t num_exp, int32_t block_rows,
+                                 const int32_t* sample_rows, gse_matrix* A, EncodeScratch* sc,
+                                 hipStream_t st);
 
 int32_t n_tiles_for(int64_t nnz, int32_t tile_nnz);
 

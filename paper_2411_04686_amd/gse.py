@@ -123,6 +123,8 @@ _SIGS = {
     "gse_encode_blocks": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int64, C.c_int32,
                                       C.c_int32, _P, C.POINTER(gse_matrix), _P, C.c_size_t, _P]),
     "gse_block_table_entries": (C.c_int64, [C.c_int32, C.c_int32, C.c_int32]),
+    "gse_encode_sampled": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32, C.c_int64, C.c_int32,
+                                       C.c_int32, _P, C.POINTER(gse_matrix), _P, C.c_size_t, _P]),
     "gse_plan": (C.c_int32, [C.POINTER(gse_matrix), C.c_int32, C.c_int32, _P]),
     "gse_csr_plan": (C.c_int32, [C.POINTER(gse_csr), C.c_int32, C.c_int32, _P]),
     "gse_spmv": (C.c_int32, [C.POINTER(gse_matrix), C.c_int32, _P, _P, _P]),
@@ -237,6 +239,14 @@ def gse_encode_blocks(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, block_row
                                           num_exp, block_rows, _ptr(sample_rows), C.byref(A),
                                           _ptr(ws), ws.numel() * ws.element_size(),
                                           _stream(stream)), "gse_encode_blocks")
+
+
+def gse_encode_sampled(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, block_rows, sample_rows,
+                       A: gse_matrix, ws, stream=None) -> int:
+    return _check(lib().gse_encode_sampled(_ptr(row_ptr), _ptr(col), _ptr(val), n_rows, n_cols,
+                                           nnz, num_exp, block_rows, _ptr(sample_rows),
+                                           C.byref(A), _ptr(ws), ws.numel() * ws.element_size(),
+                                           _stream(stream)), "gse_encode_sampled")
 
 
 def gse_block_table_entries(n_rows: int, block_rows: int, num_exp: int) -> int:
@@ -499,10 +509,12 @@ class GseMatrix:
 
     def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, n_cols: int,
                  num_exp: int = 8, sem_in=None, stream=None, idx_layout: int = IDX_AUTO,
-                 block_rows: int = 0, sample_rows: torch.Tensor = None):
+                 block_rows: int = 0, sample_rows: torch.Tensor = None, pooled: bool = False):
         """block_rows > 0: one table per block of that many rows
         (gse_encode_blocks), chosen from the device rows ``sample_rows``
-        (one per block) or, when None, from each block's values."""
+        (one per block) or, when None, from each block's values.  pooled:
+        one table for the whole matrix from the pooled exponents of the drawn
+        rows (gse_encode_sampled; block_rows and sample_rows required)."""
         dev = row_ptr.device
         n_rows = row_ptr.numel() - 1
         nnz = val.numel()
@@ -524,7 +536,12 @@ class GseMatrix:
         A.tile_cap = cap
         A.idx_layout = idx_layout
         self.A = A
-        if block_rows:
+        if pooled:
+            if sem_in is not None or sample_rows is None or not block_rows:
+                raise ValueError("the pooled table needs block_rows and sample_rows, and no sem_in")
+            gse_encode_sampled(row_ptr, col, val, n_rows, n_cols, nnz, num_exp, block_rows,
+                               sample_rows, A, self.ws, stream)
+        elif block_rows:
             if sem_in is not None:
                 raise ValueError("per-block tables are chosen by the encoder (no sem_in)")
             self.block_sem = _alloc(max(gse_block_table_entries(n_rows, block_rows, num_exp), 1),

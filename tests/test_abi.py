@@ -160,6 +160,25 @@ def test_block_tables_host_side(lib):
     assert b"per-block" in L.gse_last_error()
 
 
+def test_pooled_sample_host_side(lib):
+    """gse_encode_sampled refuses a block size below one and a missing list of
+    drawn rows before any device work."""
+    import sys
+    sys.path.insert(0, ROOT)
+    from paper_2411_04686_amd import gse as G
+    L = G.lib()
+    fake = C.c_void_p(256)
+    A = G.gse_matrix()
+    A.col_idx = A.head = A.tail1 = A.tail2 = A.tile_row = 256
+    A.tile_cap = 1 << 20
+    st = L.gse_encode_sampled(fake, fake, fake, 1000, 1000, 5000, 8, 0, fake, C.byref(A), fake,
+                              1 << 20, None)
+    assert st == -1 and b"block_rows" in L.gse_last_error()
+    st = L.gse_encode_sampled(fake, fake, fake, 1000, 1000, 5000, 8, 256, None, C.byref(A), fake,
+                              1 << 20, None)
+    assert st == -1 and b"sample_rows" in L.gse_last_error()
+
+
 def test_spmv_refuses_overlapping_vectors(lib):
     """x and y of one product may not share memory: refused on the host."""
     import sys

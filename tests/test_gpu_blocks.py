@@ -1,4 +1,5 @@
-"""GPU parity of the per-row-block tables (Section III-B.1, sampling).
+"""GPU parity of the sampled tables (Section III-B.1, sampling): per row
+block, and one table from the pooled drawn rows.
 
 gse_encode_blocks against the oracle's encode_blocks on the same seeded
 inputs and the same drawn rows: the block tables, the four planes and
@@ -7,7 +8,8 @@ schedule, every lane width) against the oracle's block SpMV within 1e-12
 relative, norm-wise and componentwise (the values are exact on both sides;
 only the summation order differs).  CG and GMRES on block matrices: both
 sides reach the true residual 1e-10, solutions within 1e-6, iteration counts
-within 10 %.
+within 10 %.  gse_encode_sampled against the oracle's encode_sampled: the
+table, planes and exact_frac bit-exact, eta within 1e-12, the SpMV as above.
 """
 import numpy as np
 import pytest
@@ -170,6 +172,121 @@ def test_full_size_layered_128_sampled_rows():
         scale = np.array([np.abs(dec[A.indptr[r]:A.indptr[r + 1]] *
                                  x[A.indices[A.indptr[r]:A.indptr[r + 1]]]).sum() for r in rows])
         _check_close(y, ref, scale)
+
+
+# ---- one table from the pooled drawn rows (gse_encode_sampled) ----------
+
+def encode_pooled(A, R, k=8, layout=G.IDX_AUTO, seed=1):
+    sr = block_sample_rows(A.n_rows, R, seed)
+    olay = {G.IDX_AUTO: -1, G.IDX_COLUMN: 0, G.IDX_VALUE: 1}[layout]
+    enc = O.encode_sampled(A.indptr, A.indices, A.data, A.n_cols, num_exp=k, block_rows=R,
+                           sample_rows=sr, layout=olay)
+    rp, ci, va = to_dev(A)
+    M = G.GseMatrix(rp, ci, va, A.n_cols, num_exp=k, idx_layout=layout, block_rows=R,
+                    sample_rows=torch.from_numpy(sr).to(DEV), pooled=True)
+    return enc, M
+
+
+def check_pooled(name, A, enc, M, k):
+    assert M.A.block_rows == 0 and M.A.block_stride == 0
+    want = np.zeros(64, np.int16)
+    want[:min(k, 64)] = enc.sem[:min(k, 64)]
+    assert np.array_equal(np.array(list(M.A.sem), np.int16), want), name
+    assert M.A.num_used == int((want > 0).sum())
+    for g, w, what in zip(M.planes(), (enc.col_idx, enc.head, enc.tail1, enc.tail2),
+                          ("col_idx", "head", "tail1", "tail2")):
+        assert np.array_equal(g, w), (name, what, np.nonzero(g != w)[0][:5])
+    assert M.A.exact_frac == enc.exact_frac
+    for s in range(3):
+        assert M.eta[s] == pytest.approx(enc.eta[s], rel=1e-12, abs=1e-300)
+    assert M.A.idx_layout == (G.IDX_VALUE if enc.layout == 1 else G.IDX_COLUMN)
+
+
+def check_pooled_spmv(A, enc, M):
+    x = np.random.default_rng(8).uniform(-1, 1, A.n_cols)
+    xd = torch.from_numpy(x).to(DEV)
+    yd = torch.full((A.n_rows,), np.nan, dtype=torch.float64, device=DEV)
+    for s in (1, 2, 3):
+        M.spmv(s, xd, yd)
+        torch.cuda.synchronize()
+        ref = O.gse_spmv(A.indptr, enc, s, x)
+        dec = O.decode(enc, s)
+        scale = np.zeros(A.n_rows)
+        np.add.at(scale, np.repeat(np.arange(A.n_rows), np.diff(A.indptr)),
+                  np.abs(dec * x[A.indices]))
+        _check_close(yd.cpu().numpy(), ref, scale)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_pooled_table(name):
+    make, R = CASES[name]
+    A = make()
+    enc, M = encode_pooled(A, R)
+    check_pooled(name, A, enc, M, 8)
+    check_pooled_spmv(A, enc, M)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 16, 64])
+def test_pooled_table_sizes(k):
+    # exponents over 40 binades: the drawn rows miss much of the range
+    A = random_sparse(3000, 2500, 11, mean_row=6, exp_spread=40.0)
+    for R in (1, 128, 1000):
+        enc, M = encode_pooled(A, R, k=k, seed=k + R)
+        check_pooled(f"k{k}_R{R}", A, enc, M, k)
+    check_pooled_spmv(A, enc, M)
+
+
+def test_pooled_index_in_value():
+    A = layered3d(8, 3, contrast=10.0)
+    enc, M = encode_pooled(A, 128, k=5, layout=G.IDX_VALUE)
+    assert enc.layout == 1
+    check_pooled("value", A, enc, M, 5)
+    check_pooled_spmv(A, enc, M)
+
+
+def test_pooled_full_size_layered_128():
+    """The benchmark's block workload at full size with 4096-row blocks: the
+    table, every plane, exact_frac and eta against the oracle."""
+    A = layered3d(128, 0)
+    enc, M = encode_pooled(A, 4096, seed=0)
+    check_pooled("layered3d_128", A, enc, M, 8)
+
+
+def test_pooled_errors():
+    A = random_sparse(600, 600, 2, mean_row=5)
+    rp, ci, va = to_dev(A)
+    sr = block_sample_rows(A.n_rows, 128, 0)
+    sr[3] -= 128  # a row of the previous block
+    with pytest.raises(G.GseError) as e:
+        G.GseMatrix(rp, ci, va, A.n_cols, block_rows=128, sample_rows=torch.from_numpy(sr).to(DEV),
+                    pooled=True)
+    assert e.value.status == G.ERR_ARG
+    # the drawn rows hold only zeros and the added maximum (exponent field
+    # 10) is below the normal grid: a range error, as in the oracle
+    indptr = np.array([0, 2, 4] + [4] * 127, dtype=np.int32)
+    data = np.array([0.0, 0.0, 2.0 ** -1013, 2.0 ** -1014])
+    T = CSR(129, 2, indptr, np.array([0, 1, 0, 1], np.int32), data, "tiny")
+    sr = torch.tensor([0, 128], dtype=torch.int32, device=DEV)
+    rp, ci, va = to_dev(T)
+    for pooled in (False, True):
+        with pytest.raises(G.GseError) as e:
+            G.GseMatrix(rp, ci, va, 2, block_rows=128, sample_rows=sr, pooled=pooled)
+        assert e.value.status == G.ERR_RANGE
+
+
+def test_pooled_table_in_cg():
+    """The pooled table is an ordinary one-table matrix: the stepped CG on it
+    against the oracle's CG on the same planes."""
+    A = layered3d(16, 2, contrast=3.0, layers=4)
+    x_true, b = rhs_from_solution(A, 3)
+    enc, M = encode_pooled(A, 256, seed=4)
+    rep, x = gpu_solve(M, A, b, G.CG)
+    prm = O.make_params(tol=1e-10, max_iter=5000, preset="paper_cg")
+    ref = O.cg(A.indptr, b, prm, A.indices, A.data, enc)
+    assert rep.status == G.OK and ref.status == O.OK
+    assert rep.relres_true <= 1e-10
+    assert np.linalg.norm(x - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+    assert abs(rep.iters - ref.iters) <= max(3, ref.iters // 10), (rep.iters, ref.iters)
 
 
 def gpu_solve(M, A, b, method, switch_mode=2, max_iter=5000):
