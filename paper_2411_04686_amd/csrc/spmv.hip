@@ -903,7 +903,12 @@ __device__ __forceinline__ void stage_tile_tables(const SpmvOperand& A, int t, u
   }
 }
 
-template <int FMT, int B, bool BLK = false>
+// IB >= 0: the operand has one table and its slot index in the top IB bits
+// of the column word, fixed at compile time (IB = 3 for tables of five to
+// eight shared exponents, the default k = 8): the field split folds into
+// immediate shifts and masks and only 2^IB scale entries are built.  The
+// general instance (IB = -1) reads the split from the operand.
+template <int FMT, int B, bool BLK = false, int IB = -1>
 __global__ __launch_bounds__(kRingThreads) void k_spmv_rows(SpmvOperand A,
                                                             const double* __restrict__ x,
                                                             double* __restrict__ y, SpmvEpilogue ep) {
@@ -925,9 +930,10 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_rows(SpmvOperand A,
   if constexpr (BLK) {
     if (count > 0 && tid < kRingConsumers) stage_tile_tables<FMT>(A, walk.t, scale_tab, tid);
   } else {
-    build_scale<FMT>(A.sem, scale_tab, A.split.ei);
+    build_scale_n<FMT>(A.sem, IB >= 0 ? (1 << IB) : kScaleEntries, scale_tab,
+                       IB >= 0 ? 0 : A.split.ei);
   }
-  const DecodeCtx scale{scale_tab, A.split};
+  const DecodeCtx scale{scale_tab, IB >= 0 ? col_split(IB, false) : A.split};
   double acc = 0.0;
   __syncthreads();
   if (wave == PRODUCER) {
@@ -1026,7 +1032,7 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_rows(SpmvOperand A,
 // compute and store the same value.
 enum Kind : int { kGeneralTiles = 0, kShortTiles = 1, kRingTiles = 2, kRowTiles = 3 };
 
-template <int FMT, int E, int KIND, int B = 8, bool BLK = false>
+template <int FMT, int E, int KIND, int B = 8, bool BLK = false, int IB = -1>
 int resident_groups() {
   static std::atomic<int> cache{0};
   int cached = cache.load(std::memory_order_relaxed);
@@ -1037,7 +1043,7 @@ int resident_groups() {
       return 0;
     hipError_t e;
     if constexpr (KIND == kRowTiles)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv_rows<FMT, B, BLK>,
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv_rows<FMT, B, BLK, IB>,
                                                        kRingThreads, 0);
     else if constexpr (KIND == kRingTiles)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmv_ring<FMT>, kRingThreads, 0);
@@ -1077,23 +1083,30 @@ hipError_t launch_ring(const SpmvOperand& A, const double* x, double* y, const S
   return hipGetLastError();
 }
 
-template <int FMT, int B, bool BLK = false>
+template <int FMT, int B, bool BLK = false, int IB = -1>
 hipError_t launch_rows(const SpmvOperand& A, const double* x, double* y, const SpmvEpilogue& ep,
                        hipStream_t st) {
+  if constexpr (!BLK && IB < 0 && is_gse(FMT)) {
+    // a 3-bit index in the column word: the instance with the split folded in
+    const ColSplit c3 = col_split(3, false);
+    if (A.split.shift == c3.shift && A.split.slot_mask == c3.slot_mask &&
+        A.split.col_mask == c3.col_mask && A.split.hmask == c3.hmask && A.split.ei == c3.ei)
+      return launch_rows<FMT, B, false, 3>(A, x, y, ep, st);
+  }
   if constexpr (BLK) {
     // the staged tables fit kRowTabEntries only for blocks this tall
     if (A.n_rows < 1 || !A.block_sem || A.block_rows < GSE_MIN_BLOCK_ROWS ||
         A.block_stride < 1 || A.block_stride > GSE_MAX_EXP)
       return hipErrorInvalidValue;
   }
-  int g = resident_groups<FMT, 4, kRowTiles, B, BLK>();
+  int g = resident_groups<FMT, 4, kRowTiles, B, BLK, IB>();
   if (g <= 0) return hipErrorInvalidDevice;
   const int n_rt = (A.n_rows + kRowTile - 1) / kRowTile;
   const int need = (n_rt + 7) / 8 * 8;
   if (g > need) g = need;
   if (g < 8) g = 8;
   if (ep.grid_out) *ep.grid_out = g;
-  hipLaunchKernelGGL((k_spmv_rows<FMT, B, BLK>), dim3(g), dim3(kRingThreads), 0, st, A, x, y, ep);
+  hipLaunchKernelGGL((k_spmv_rows<FMT, B, BLK, IB>), dim3(g), dim3(kRingThreads), 0, st, A, x, y, ep);
   return hipGetLastError();
 }
 
