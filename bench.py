@@ -68,14 +68,19 @@ def spmv_bytes(n_rows, n_cols, nnz, plane_bytes):
 def kernel_name(A):
     """Name of the kernel instance the one-segment SpMV runs on this schedule."""
     if A.rv_lanes > 0:
-        return f"k_spmv_rv<1, {A.rv_lanes}>"
+        return f"k_spmv_rv<1, {A.rv_lanes}{', true' if A.block_rows else ''}>"
     e = A.tile_nnz // 256
     if A.max_row_nnz <= 24:
         if A.tile_nnz == 1024 and A.nnz >= 1024:
             m = A.max_row_nnz
             if m <= 8:
                 b = 3 if m <= 3 else 5 if m <= 5 else 7 if m <= 7 else 8
-                return f"k_spmv_rows<1, {b}>"
+                if A.block_rows:
+                    return f"k_spmv_rows<1, {b}, true, -1>"
+                if A.idx_bits == 3 and A.idx_layout == 1:
+                    # the instance with the 3-bit column-word index folded in
+                    return f"k_spmv_rows<1, {b}, false, 3>"
+                return f"k_spmv_rows<1, {b}, false, -1>"
             return "k_spmv_ring<1>"
         return f"k_spmv_short<1, {e}>"
     return f"k_spmv<1, {e}>"
@@ -300,10 +305,14 @@ def run_spmv_cg(args, torch, G):
     def spmv_pass(record):
         # HIP events on the launch stream around each round of `copies`
         # back-to-back launches (one per copy): the per-launch time is the
-        # round's time over `copies`, launch gaps included
+        # round's time over `copies`, launch gaps included.  Each kind starts
+        # with one untimed round, so that no timed round opens on an idle
+        # queue (after the solves' host work the first launch would otherwise
+        # be timed from the event to the host's next launch call).
         for kname, _ in kinds:
-            for rep in range(args.reps):
-                if record:
+            for rep in range(-1, args.reps):
+                record_this = record and rep >= 0
+                if record_this:
                     e0 = torch.cuda.Event(enable_timing=True)
                     e1 = torch.cuda.Event(enable_timing=True)
                     e0.record(stream)
@@ -312,7 +321,7 @@ def run_spmv_cg(args, torch, G):
                         csrs[c].spmv(xs, ys[c])
                     else:
                         mats[c].spmv(int(kname[1]), xs, ys[c])
-                if record:
+                if record_this:
                     e1.record(stream)
                     times[kname].append((e0, e1))
 
@@ -564,8 +573,7 @@ def leg_blocks(torch, G, seed, copies, block_rows=4096, A_cg=None, b_cg=None, x_
             enc_ms.append((time.perf_counter() - t0) * 1e3)
         rec = {"encode_ms": round(float(np.median(enc_ms)), 3), "eta": [float(e) for e in M.eta],
                "exact_frac": round(float(M.A.exact_frac), 4), "rv_lanes": int(M.A.rv_lanes),
-               "kernel": (kernel_name(M.A).replace(">", ", blocks>") if M.A.block_rows
-                          else kernel_name(M.A))}
+               "kernel": kernel_name(M.A)}
         tables = (G.gse_block_table_entries(A.n_rows, block_rows, 8) * 2) if M.A.block_rows else 0
         for s, pb in ((1, 6), (2, 8), (3, 12)):
             us = rotated_launch_us(torch, stream,

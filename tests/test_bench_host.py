@@ -28,10 +28,18 @@ def test_kernel_name_follows_the_schedule():
         pass
     a = A()
     a.rv_lanes, a.tile_nnz, a.max_row_nnz, a.nnz = 0, 1024, 7, 5000
-    assert b.kernel_name(a) == "k_spmv_rows<1, 7>"
+    # one table, 3-bit index in the column word: the instance with the split
+    # folded in; any other table size, layout or block tables: the general one
+    a.block_rows, a.idx_bits, a.idx_layout = 0, 3, 1
+    assert b.kernel_name(a) == "k_spmv_rows<1, 7, false, 3>"
     for m, bw in ((1, 3), (3, 3), (4, 5), (5, 5), (6, 7), (8, 8)):
         a.max_row_nnz = m
-        assert b.kernel_name(a) == f"k_spmv_rows<1, {bw}>"
+        assert b.kernel_name(a) == f"k_spmv_rows<1, {bw}, false, 3>"
+    a.max_row_nnz = 7
+    for bits, lay, blk, name in ((4, 1, 0, "false"), (3, 2, 0, "false"), (3, 1, 256, "true")):
+        a.idx_bits, a.idx_layout, a.block_rows = bits, lay, blk
+        assert b.kernel_name(a) == f"k_spmv_rows<1, 7, {name}, -1>"
+    a.block_rows, a.idx_bits, a.idx_layout = 0, 3, 1
     for m in (9, 24):
         a.max_row_nnz = m
         assert b.kernel_name(a) == "k_spmv_ring<1>"
