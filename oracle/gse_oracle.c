@@ -764,6 +764,119 @@ static void givens(double a, double b, double* c, double* s) {
  * same stepped operator schedule as CG.  The monitored residual is the
  * least-squares estimate |g_{j+1}|/||b||.  A switch ends the cycle; the next
  * cycle starts from the explicit residual of the new operator. */
+/* One GMRES cycle with Gram-Schmidt applied twice, the second pass delayed
+ * by one step so that each step needs one reduction (delayed classical
+ * Gram-Schmidt, DCGS2: Swirydowicz, Langou, Ananthan, Yang and Thomas,
+ * "Low synchronization Gram-Schmidt and GMRES algorithms", 2020; Bielich et
+ * al., "Low-synch Gram-Schmidt with delayed reorthogonalization for Krylov
+ * solvers", 2022).  Not part of the paper's method: a variant of its GMRES
+ * that reaches the same Krylov iterates with fewer passes over the basis.
+ *
+ * V[0] holds u_0 = r (not normalised).  Step j (0 <= j <= m) starts with
+ * the final basis q_0..q_{j-1} in V[0..j-1] and u_j in V[j], the new
+ * direction after its first projection only.  With z = A_s u_j (not for
+ * j = m) one reduction gives a = Q^T u_j, omega = u_j.u_j, c = Q^T z and
+ * gamma = u_j.z.  Then
+ *   beta = sqrt(omega - |a|^2)   (the norm of u_j after its second projection)
+ *   q_j = (u_j - Q a) / beta
+ * closes Arnoldi column j - 1: H[0..j-1][j-1] = h1 + a, H[j][j-1] = beta,
+ * the rotations and the residual estimate as in the other variants.  With
+ * t = q_j.z = (gamma - a.c) / beta, A q_j = (z - A Q a) / beta and
+ * A Q = Q_j Hbar (the Arnoldi relation of the columns closed so far), the
+ * next direction and its first projection coefficients are
+ *   u_{j+1} = (z - Q c - t q_j) / beta,
+ *   h1 = ([c; t] - Hbar a) / beta       (provisional column j),
+ * so the step reads the basis twice: once for the dots, once for q_j and
+ * u_{j+1}.  The residual estimate of column j - 1 is known only after the
+ * product with u_j, so a cycle that stops at column j - 1 has computed one
+ * product more than the other variants.  beta^2 at or below 1e-28 omega is
+ * taken as 0 (u_j lies in the span of Q: exact in this space).
+ * Returns the number of closed columns; *trig the controller's switch. */
+static int dcgs2_cycle(const or_matrix* A, const or_params* p, int s, int stepped, int m,
+                       int32_t n, size_t nn, double nb, double* V, double* z, double* H,
+                       double* Hu, double* h1, double* av, double* bv, double* cs, double* sn,
+                       double* g, int32_t* it, double* relres, int* trig, or_report* rep,
+                       double* hist, int32_t* seg_hist) {
+#define HH(i, j) H[(size_t)(i) * (size_t)m + (size_t)(j)]
+#define HU(i, j) Hu[(size_t)(i) * (size_t)m + (size_t)(j)]
+    int k_used = 0;
+    for (int j = 0; j <= m; ++j) {
+        double* uj = V + (size_t)j * nn;
+        const int have_z = j < m;
+        if (have_z) apply_op(A, s, uj, z);
+        for (int i = 0; i < j; ++i) av[i] = dot(n, V + (size_t)i * nn, uj);
+        double om = dot(n, uj, uj);
+        double ga = 0.0;
+        if (have_z) {
+            for (int i = 0; i < j; ++i) bv[i] = dot(n, V + (size_t)i * nn, z);
+            ga = dot(n, uj, z);
+        }
+        double aa = 0.0;
+        for (int i = 0; i < j; ++i) aa += av[i] * av[i];
+        double b2 = om - aa;
+        double bet = b2 > 1e-28 * om ? sqrt(b2) : 0.0;
+        if (j == 0) {
+            g[0] = bet;
+        } else {
+            /* Arnoldi column j - 1 is closed */
+            for (int i = 0; i < j; ++i) HU(i, j - 1) = h1[i] + av[i];
+            HU(j, j - 1) = bet;
+            for (int i = 0; i <= j; ++i) HH(i, j - 1) = HU(i, j - 1);
+            for (int i = 0; i < j - 1; ++i) {
+                double t0 = cs[i] * HH(i, j - 1) + sn[i] * HH(i + 1, j - 1);
+                HH(i + 1, j - 1) = -sn[i] * HH(i, j - 1) + cs[i] * HH(i + 1, j - 1);
+                HH(i, j - 1) = t0;
+            }
+            givens(HH(j - 1, j - 1), HH(j, j - 1), &cs[j - 1], &sn[j - 1]);
+            HH(j - 1, j - 1) = cs[j - 1] * HH(j - 1, j - 1) + sn[j - 1] * HH(j, j - 1);
+            HH(j, j - 1) = 0.0;
+            g[j] = -sn[j - 1] * g[j - 1];
+            g[j - 1] = cs[j - 1] * g[j - 1];
+            *it += 1;
+            rep->iters_per_seg[(s > 0 ? s : 3) - 1] += 1;
+            k_used = j;
+            *relres = fabs(g[j]) / nb;
+            if (hist) hist[*it] = *relres;
+            if (seg_hist) seg_hist[*it] = s;
+            if (bet == 0.0) break;  /* happy breakdown: exact in this space */
+            if (*relres <= p->tol) break;
+            if (stepped && s < 3) {
+                double eta = A->eta3 ? A->eta3[s - 1] : 0.0;
+                if (p->floor_c > 0.0 && eta > 0.0 && *relres <= p->floor_c * eta)
+                    *trig = OR_TRIG_FLOOR;
+                else if (hist)
+                    *trig = or_precision_trigger(hist, *it, p);
+                if (*trig != OR_TRIG_NONE) break;
+            }
+            if (j == m || *it >= p->max_iter) break;
+        }
+        if (bet == 0.0) break;  /* r = 0 at the start of the cycle */
+        /* first projection of A q_j, q_j and u_{j+1} */
+        double t = ga;
+        for (int i = 0; i < j; ++i) t -= av[i] * bv[i];
+        t /= bet;
+        for (int i = 0; i <= j; ++i) {
+            double c = i < j ? bv[i] : t;
+            for (int k = 0; k < j; ++k) c -= HU(i, k) * av[k];
+            h1[i] = c / bet;
+        }
+        double* un = V + (size_t)(j + 1) * nn;
+        for (int32_t e = 0; e < n; ++e) {
+            double q = uj[e];
+            for (int i = 0; i < j; ++i) q -= av[i] * V[(size_t)i * nn + e];
+            q /= bet;
+            double u = z[e];
+            for (int i = 0; i < j; ++i) u -= bv[i] * V[(size_t)i * nn + e];
+            u -= t * q;
+            uj[e] = q;
+            un[e] = u / bet;
+        }
+    }
+#undef HH
+#undef HU
+    return k_used;
+}
+
 int or_gmres(const or_matrix* A, const double* b, double* x, const or_params* p,
              or_report* rep, double* hist, int32_t* seg_hist) {
     int32_t n = A->n_rows;
@@ -779,11 +892,19 @@ int or_gmres(const or_matrix* A, const double* b, double* x, const or_params* p,
     double* y = (double*)malloc(sizeof(double) * (size_t)m);
     double* h2 = (double*)malloc(sizeof(double) * (size_t)(m + 1));
     double* w = (double*)malloc(sizeof(double) * nn);
-    if (!V || !H || !cs || !sn || !g || !y || !h2 || !w) {
+    /* delayed CGS2 only: the Hessenberg matrix before the rotations, the
+     * provisional column, and the dots of one step */
+    double* Hu = (double*)calloc((size_t)(m + 1) * (size_t)m, sizeof(double));
+    double* h1 = (double*)malloc(sizeof(double) * (size_t)(m + 1));
+    double* av = (double*)malloc(sizeof(double) * (size_t)(m + 1));
+    double* bv = (double*)malloc(sizeof(double) * (size_t)(m + 1));
+    if (!V || !H || !cs || !sn || !g || !y || !h2 || !w || !Hu || !h1 || !av || !bv) {
         free(V); free(H); free(cs); free(sn); free(g); free(y); free(h2); free(w);
+        free(Hu); free(h1); free(av); free(bv);
         return OR_ERR_ARG;
     }
 #define HH(i, j) H[(size_t)(i) * (size_t)m + (size_t)(j)]
+#define HU(i, j) Hu[(size_t)(i) * (size_t)m + (size_t)(j)]
     int stepped = (p->fixed_segments == 0);
     int s = stepped ? p->start_segments
                     : (p->fixed_segments > 0 ? p->fixed_segments
@@ -825,10 +946,15 @@ int or_gmres(const or_matrix* A, const double* b, double* x, const or_params* p,
             continue;
         }
         if (it >= p->max_iter) break;
-        for (int32_t i = 0; i < n; ++i) V[i] /= beta;
         for (int k = 0; k <= m; ++k) g[k] = 0.0;
-        g[0] = beta;
         int k_used = 0;
+        if (p->orth == 2) {
+            k_used = dcgs2_cycle(A, p, s, stepped, m, n, nn, nb, V, w, H, Hu, h1, av, bv, cs, sn,
+                                 g, &it, &relres, &trig, rep, hist, seg_hist);
+            goto cycle_end;
+        }
+        for (int32_t i = 0; i < n; ++i) V[i] /= beta;
+        g[0] = beta;
         for (int j = 0; j < m && it < p->max_iter; ++j) {
             double* vj = V + (size_t)j * nn;
             apply_op(A, s, vj, w);
@@ -883,6 +1009,7 @@ int or_gmres(const or_matrix* A, const double* b, double* x, const or_params* p,
                 if (trig != OR_TRIG_NONE) break;
             }
         }
+    cycle_end:
         for (int i = k_used - 1; i >= 0; --i) {
             double acc = g[i];
             for (int k = i + 1; k < k_used; ++k) acc -= HH(i, k) * y[k];
@@ -904,6 +1031,8 @@ done:
     rep->relres_recursive = relres;
     rep->relres_true = nb == 0.0 ? 0.0 : sqrt(residual(A, fin, b, x, w)) / nb;
 #undef HH
+#undef HU
     free(V); free(H); free(cs); free(sn); free(g); free(y); free(h2); free(w);
+    free(Hu); free(h1); free(av); free(bv);
     return status;
 }

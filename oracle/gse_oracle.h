@@ -52,7 +52,8 @@ typedef struct {
     double floor_c;          /* switch once relres <= floor_c*eta_s (0: off) */
     int32_t switch_mode;     /* CG after a switch: 0 restart p = r, 1 keep p, 2 keep p while
                                 the residual replacement keeps ||r|| within a factor 2 */
-    int32_t orth;            /* GMRES: 0 MGS, 1 CGS2 */
+    int32_t orth;            /* GMRES: 0 MGS, 1 CGS2, 2 CGS2 with the second pass delayed one step
+                                (one reduction per step) */
 } or_params;
 
 typedef struct {

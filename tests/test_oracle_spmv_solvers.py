@@ -222,7 +222,7 @@ def tiny_nonsym(n, seed):
     return CSR.from_scipy(sp.csr_matrix(D)), D
 
 
-@pytest.mark.parametrize("orth", [0, 1])
+@pytest.mark.parametrize("orth", [0, 1, 2])
 @pytest.mark.parametrize("n", [2, 7, 12])
 def test_gmres_full_restart_is_exact(n, orth):
     A, D = tiny_nonsym(n, n + 10)
@@ -234,15 +234,16 @@ def test_gmres_full_restart_is_exact(n, orth):
     assert np.allclose(r.x, np.linalg.solve(D, b), rtol=1e-9, atol=1e-11)
 
 
-def test_gmres_residual_is_krylov_minimum():
+@pytest.mark.parametrize("orth", [0, 1, 2])
+def test_gmres_residual_is_krylov_minimum(orth):
     """After j steps of one cycle the estimate |g_{j+1}| equals
     min over z in K_j(A, b) of ||b - A z|| (least squares on a basis)."""
     n = 30
     A, D = tiny_nonsym(n, 4)
     b = np.random.default_rng(5).standard_normal(n)
-    for j in (1, 3, 6):
+    for j in (1, 3, 6, 11):
         p = O.make_params(fixed_segments=-1, max_iter=j, restart=30, preset="paper_gmres",
-                          tol=1e-30)
+                          tol=1e-30, orth=orth)
         r = O.gmres(A.indptr, b, p, A.indices, A.data)
         K = np.stack([np.linalg.matrix_power(D, k) @ b for k in range(j)], axis=1)
         Q, _ = np.linalg.qr(K)
@@ -256,7 +257,7 @@ def test_stepped_gmres_reaches_tolerance():
     A = convdiff2d(40, 2)
     x_true, b = rhs_from_solution(A, 2)
     enc = O.encode(A.indptr, A.indices, A.data, A.n_cols)
-    for orth in (0, 1):
+    for orth in (0, 1, 2):
         p = O.make_params(max_iter=15000, preset="paper_gmres", orth=orth)
         r = O.gmres(A.indptr, b, p, A.indices, A.data, enc)
         assert r.status == O.OK and r.relres_true <= 1e-10
@@ -265,3 +266,39 @@ def test_stepped_gmres_reaches_tolerance():
                                                  fixed_segments=-1, orth=orth),
                       A.indices, A.data)
         assert r64.status == O.OK and r64.relres_true <= 1e-10
+
+
+@pytest.mark.parametrize("n", [3, 5, 9])
+def test_dcgs2_exact_in_fewer_steps_than_the_cycle(n):
+    """A cycle longer than the system: the Krylov space is exhausted after n
+    steps (the delayed second pass finds a zero norm) and the solve is exact."""
+    A, D = tiny_nonsym(n, n + 3)
+    b = np.random.default_rng(n + 1).standard_normal(n)
+    p = O.make_params(fixed_segments=-1, max_iter=60, restart=30, preset="paper_gmres",
+                      tol=1e-14, orth=2)
+    r = O.gmres(A.indptr, b, p, A.indices, A.data)
+    assert r.iters <= n
+    assert np.allclose(r.x, np.linalg.solve(D, b), rtol=1e-9, atol=1e-11)
+
+
+def test_dcgs2_follows_cgs2():
+    """The delayed second pass changes only the order in which the same
+    Krylov quantities are formed: over restarted cycles of a nonsymmetric
+    operator (FP64 and the stepped GSE operators) the residual estimates of
+    every iteration agree with those of CGS2 to rounding, with the same
+    iteration counts and switch points."""
+    A = convdiff2d(40, 3)
+    x_true, b = rhs_from_solution(A, 3)
+    enc = O.encode(A.indptr, A.indices, A.data, A.n_cols)
+    for fs in (-1, 0):
+        res = []
+        for orth in (1, 2):
+            p = O.make_params(max_iter=15000, preset="paper_gmres", orth=orth, fixed_segments=fs)
+            res.append(O.gmres(A.indptr, b, p, A.indices, A.data, enc))
+        c, d = res
+        assert c.status == d.status == O.OK
+        assert c.iters == d.iters and c.switch_iter == d.switch_iter
+        assert c.iters_per_seg == d.iters_per_seg
+        k = c.iters + 1
+        np.testing.assert_allclose(d.hist[:k], c.hist[:k], rtol=1e-6)
+        assert np.linalg.norm(d.x - c.x) <= 1e-8 * np.linalg.norm(c.x)
