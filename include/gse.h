@@ -371,6 +371,14 @@ typedef struct gse_params {
                                  (CG on systems of at most 4096 rows whose rows hold at most 8
                                  non-zeros runs every iteration of a segment count in one
                                  launch of one workgroup, in either mode) */
+    int32_t orth;             /* GMRES Gram-Schmidt: 1 classical applied twice (CGS2: two
+                                 reductions and three passes over the basis per step); 2 the
+                                 same with the second pass delayed one step (DCGS2: one
+                                 reduction, two passes; restart <= 32); 0 (default) DCGS2
+                                 when restart <= 32, else CGS2.  Both reach the Krylov
+                                 iterates of Section IV-A's GMRES(30) to rounding; DCGS2
+                                 learns each residual estimate one product later, so a
+                                 cycle that stops computes one product more. */
 } gse_params;
 
 typedef struct gse_report {

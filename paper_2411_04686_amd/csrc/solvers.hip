@@ -485,7 +485,8 @@ int64_t partial_entries(int32_t n_rows, int64_t nnz) {
 // Small per-cycle GMRES arrays: H (m+1) x m, cs, sn, g, y, h scratch.
 int64_t gmres_small_entries(int32_t restart) {
   const int64_t m = restart;
-  return (m + 1) * m + 4 * (m + 1) + 2 * (m + 1);
+  // H, cs, sn, g, h2, h1 and one spare; delayed CGS2: Hu, hp and the sums
+  return (m + 1) * m + 4 * (m + 1) + 2 * (m + 1) + (m + 1) * m + (m + 1) + 2 * (m + 1);
 }
 
 // Row stride of the GMRES basis in doubles: whole 8 KiB pages plus 4 KiB,
@@ -1157,6 +1158,221 @@ __global__ __launch_bounds__(kWG) void k_gm_start(SolverState* S, GmSmall sm, in
   }
 }
 
+// ------------------------------------------------- GMRES, delayed CGS2 ---
+// Gram-Schmidt applied twice with the second pass delayed one step, so each
+// Arnoldi step needs a single reduction (DCGS2: Swirydowicz et al. 2020,
+// Bielich et al. 2022).  V[j] holds u_j, the new direction after its first
+// projection only (V[0] = r, not normalised); q_0..q_{j-1} are final.  Step
+// j (0 <= j <= m):
+//   z = A_s u_j                                   (SpMV into w; not at j = m)
+//   a = Q^T u_j, omega = u_j.u_j, c = Q^T z, gamma = u_j.z
+//                                                 (k_dg_dots + k_finish)
+//   beta = sqrt(omega - |a|^2), t = (gamma - a.c) / beta, and per row
+//   q_j = (u_j - Q a) / beta, u_{j+1} = (z - Q c - t q_j) / beta
+//                                                 (k_dg_axpy, every workgroup)
+// Workgroup 0 of k_dg_axpy then closes Arnoldi column j - 1 (H = hp + a,
+// H[j][j-1] = beta, before the rotations in Hu and rotated in H), runs the
+// rotations, the residual estimate and the controller, and forms the
+// provisional column j, hp = ([c; t] - Hu a) / beta (Hu: the columns closed
+// so far; A Q = Q_j Hu is the Arnoldi relation).  Two passes over the basis
+// and four launches per step, against three passes and six for CGS2; the
+// residual estimate of column j - 1 arrives one product later.
+
+// Longest restart of the delayed CGS2: its dots keep two accumulators per
+// basis vector in each thread.
+constexpr int kDgMaxRestart = 32;
+
+struct DgSmall {
+  double* Hu;    // (m+1) x m, row-major: the Hessenberg matrix before the rotations
+  double* hp;    // m+1: provisional (first-projection) column of the open step
+  double* sums;  // 2m+2: a (j), omega, c (j), gamma of the current step
+};
+
+// Partials of a = Q^T u, omega, c = Q^T z, gamma (rows 0..j-1, j, j+1..2j,
+// 2j+1).  z null (j = m): c and gamma are zero.  Vectors past q_{j-1} are
+// read as u again (a cache hit) and their accumulators discarded.
+template <int JB>
+__global__ __launch_bounds__(kWG) void k_dg_dots(const SolverState* S, const double* __restrict__ V,
+                                                 size_t ld, int n, int j,
+                                                 const double* __restrict__ z,
+                                                 double* __restrict__ partials) {
+  __shared__ double red[(2 * JB + 2) * kWaves];
+  if (S->stop) return;
+  const double* u = V + (size_t)j * ld;
+  double acc_a[JB], acc_c[JB];
+  double om = 0.0, ga = 0.0;
+#pragma unroll
+  for (int k = 0; k < JB; ++k) acc_a[k] = acc_c[k] = 0.0;
+  for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
+    double v[JB];
+#pragma unroll
+    for (int k = 0; k < JB; ++k) v[k] = V[(size_t)(k < j ? k : j) * ld + i];
+    const double ui = u[i];
+    const double zi = z ? z[i] : 0.0;
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < JB; ++k) {
+      acc_a[k] += v[k] * ui;
+      acc_c[k] += v[k] * zi;
+    }
+    om += ui * ui;
+    ga += ui * zi;
+  }
+  // the arithmetic of block_sums_out over the 2j + 2 rows
+  const int wv = threadIdx.x >> 6;
+  const bool lead = (threadIdx.x & 63) == 0;
+#pragma unroll
+  for (int k = 0; k < JB; ++k) {
+    if (k < j) {
+      const double ta = wave_sum(acc_a[k]);
+      const double tc = wave_sum(acc_c[k]);
+      if (lead) {
+        red[k * kWaves + wv] = ta;
+        red[(j + 1 + k) * kWaves + wv] = tc;
+      }
+    }
+  }
+  {
+    const double to = wave_sum(om);
+    const double tg = wave_sum(ga);
+    if (lead) {
+      red[j * kWaves + wv] = to;
+      red[(2 * j + 1) * kWaves + wv] = tg;
+    }
+  }
+  __syncthreads();
+  const int row = (int)threadIdx.x;
+  if (row <= 2 * j + 1) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) t += red[row * kWaves + i];
+    partials[(size_t)row * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// Step j's vector pass and, in workgroup 0, the close of column j - 1.
+template <int JB>
+__global__ __launch_bounds__(kWG) void k_dg_axpy(SolverState* S, GmSmall sm, DgSmall dg, int m,
+                                                 int j, double* __restrict__ V, size_t ld, int n,
+                                                 const double* __restrict__ z, double* hist,
+                                                 int* seg_hist) {
+  __shared__ double red[kWaves];
+  __shared__ double as[JB], cs_[JB];
+  __shared__ double col[64], c_s[64], s_s[64];
+  __shared__ int bc_j, bc_s, bc_go;
+  __shared__ double bc_rel;
+  if (S->stop) return;
+  const double* sums = dg.sums;
+  if (threadIdx.x < JB) {
+    as[threadIdx.x] = (int)threadIdx.x < j ? sums[threadIdx.x] : 0.0;
+    cs_[threadIdx.x] = (int)threadIdx.x < j ? sums[j + 1 + threadIdx.x] : 0.0;
+  }
+  __syncthreads();
+  // the same bits in every workgroup: sums in index order
+  const double om = sums[j];
+  double aa = 0.0, ac = 0.0;
+  for (int k = 0; k < j; ++k) {
+    aa += as[k] * as[k];
+    ac += as[k] * cs_[k];
+  }
+  const double b2 = om - aa;
+  const double bet = b2 > 1e-28 * om ? sqrt(b2) : 0.0;
+  const double inv = bet != 0.0 ? 1.0 / bet : 0.0;
+  const double t = (sums[2 * j + 1] - ac) * inv;
+  if (j < m && bet != 0.0) {
+    double* u = V + (size_t)j * ld;
+    double* un = V + (size_t)(j + 1) * ld;
+    for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
+      double v[JB];
+#pragma unroll
+      for (int k = 0; k < JB; ++k) v[k] = V[(size_t)(k < j ? k : j) * ld + i];
+      double q = u[i];
+      double w = z[i];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < JB; ++k) {
+        q -= as[k] * v[k];
+        w -= cs_[k] * v[k];
+      }
+      q *= inv;
+      w -= t * q;
+      u[i] = q;
+      un[i] = w * inv;
+    }
+  }
+  if (blockIdx.x != 0) return;
+  const int tid = threadIdx.x;
+  if (j == 0) {
+    if (tid == 0) sm.g[0] = bet;
+  } else {
+    // close column j - 1
+    if (tid < j) {
+      const double h = dg.hp[tid] + as[tid];
+      dg.Hu[(size_t)tid * m + (j - 1)] = h;
+      col[tid] = h;
+      if (tid < j - 1) {
+        c_s[tid] = sm.cs[tid];
+        s_s[tid] = sm.sn[tid];
+      }
+    }
+    if (tid == 0) dg.Hu[(size_t)j * m + (j - 1)] = bet;
+    __syncthreads();
+    if (tid == 0) {
+      const int c = j - 1;
+      col[j] = bet;
+      for (int i = 0; i < c; ++i) {
+        const double a = col[i], b = col[i + 1];
+        col[i] = c_s[i] * a + s_s[i] * b;
+        col[i + 1] = -s_s[i] * a + c_s[i] * b;
+      }
+      const double a = col[c], b = col[c + 1];
+      const double rr = sqrt(a * a + b * b);
+      const double cg = rr == 0.0 ? 1.0 : a / rr;
+      const double sg = rr == 0.0 ? 0.0 : b / rr;
+      sm.cs[c] = cg;
+      sm.sn[c] = sg;
+      col[c] = cg * a + sg * b;
+      col[c + 1] = 0.0;
+      const double gc = sm.g[c];
+      sm.g[c + 1] = -sg * gc;
+      sm.g[c] = cg * gc;
+      const int it = S->it + 1;
+      const double rel = fabs(-sg * gc) / S->nb;
+      S->it = it;
+      S->relres = rel;
+      S->scratch[1] = bet;
+      S->scratch[2] = j;  // columns closed in this cycle
+      hist[it] = rel;
+      seg_hist[it] = S->s;
+      bc_j = it;
+      bc_s = S->s;
+      bc_rel = rel;
+      bc_go = bet != 0.0;
+      if (bet == 0.0) S->stop = kConv;  // exact in this space: end the cycle
+    }
+    __syncthreads();
+    if (tid <= j) sm.H[(size_t)tid * m + (j - 1)] = col[tid];  // row-major (m+1) x m
+    if (bc_go) controller(S, hist, red, bc_j, bc_rel, bc_s);
+  }
+  // the provisional column j, from the columns closed so far (Hu reads the
+  // column just written by this workgroup).  Row i of a Hessenberg matrix is
+  // zero left of column i - 1, and those entries of Hu are never written in
+  // this cycle: the sum starts at column i - 1.
+  __syncthreads();
+  if (j < m && bet != 0.0 && tid <= j) {
+    double c = tid < j ? cs_[tid] : t;
+    for (int k = tid > 0 ? tid - 1 : 0; k < j; ++k) c -= dg.Hu[(size_t)tid * m + k] * as[k];
+    dg.hp[tid] = c * inv;
+  }
+}
+
+// Cycle start for DCGS2: V[0] = r stays unnormalised (step 0 normalises it
+// and sets g[0]); g = 0, no column closed yet.
+__global__ __launch_bounds__(kWG) void k_dg_start(SolverState* S, GmSmall sm, int m) {
+  if ((int)threadIdx.x <= m) sm.g[threadIdx.x] = 0.0;
+  if (threadIdx.x == 0) S->scratch[2] = 0.0;
+}
+
 gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_params* p,
                      gse_report* rep, void* ws, size_t ws_bytes, hipStream_t caller) {
   auto t0 = std::chrono::steady_clock::now();
@@ -1166,6 +1382,11 @@ gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_pa
   const int n = A.op.n_rows;
   const int m = p->restart;
   if (m > 60) return fail(GSE_ERR_ARG, "restart must be <= 60");
+  if (p->orth < 0 || p->orth > 2) return fail(GSE_ERR_ARG, "orth must be 0, 1 or 2");
+  if (p->orth == 2 && m > kDgMaxRestart)
+    return fail(GSE_ERR_ARG, "delayed CGS2 takes restart <= %d", kDgMaxRestart);
+  // orth 0: the delayed CGS2 wherever its per-thread accumulators fit
+  const bool dcgs2 = p->orth == 2 || (p->orth == 0 && m <= kDgMaxRestart);
   Workspace w = carve(ws, GSE_GMRES, n, A.op.nnz, m, p->max_iter);
   if (w.bytes > ws_bytes) return fail(GSE_ERR_NOMEM, "solver workspace needs %zu bytes", w.bytes);
   int dev = 0;
@@ -1176,6 +1397,7 @@ gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_pa
     k.add(dev), k.add(GSE_GMRES), k.add(s_use), k.add(A.fmt), k.add(A.launch_fmt);
     k.add_operand(A.op);
     k.add(ws), k.add(n), k.add(A.op.nnz), k.add(m), k.add(p->max_iter), k.add(x), k.add(b);
+    k.add(dcgs2);
     return k;
   };
   memset(rep, 0, sizeof *rep);
@@ -1191,6 +1413,10 @@ gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_pa
   sm.g = sm.sn + (m + 1);
   sm.h2 = sm.g + (m + 1);
   double* h1 = sm.h2 + (m + 1);  // pass-1 dots (m+1), pass-2 dots in sm.h2
+  DgSmall dg;
+  dg.Hu = h1 + 2 * (m + 1);
+  dg.hp = dg.Hu + (size_t)(m + 1) * m;
+  dg.sums = dg.hp + (m + 1);
   const int vb = vec_blocks(n);
   const int gb = vb < kGmBlocks ? vb : kGmBlocks;
   hipError_t e;
@@ -1275,7 +1501,51 @@ gse_status run_gmres(const Operator& A, const double* b, double* x, const gse_pa
     if (e != hipSuccess) return hip_fail(e, "gmres state");
     // one cycle: v_0 = r/beta, m Arnoldi steps (gated: a stop ends the cycle),
     // x += V y
+    // delayed CGS2: steps 0..m, the last one without a product
+    auto launch_cycle_dg = [&](int s_use) -> hipError_t {
+      hipLaunchKernelGGL(k_dg_start, dim3(1), dim3(kWG), 0, st, w.S, sm, m);
+      for (int j = 0; j <= m; ++j) {
+        double* uj = V + (size_t)j * ld;
+        const double* z = j < m ? w.w : nullptr;
+        if (j < m) {
+          hipError_t err = apply(A, s_use, uj, w.w, kEpiPlain, nullptr, nullptr, w, &w.S->stop, st);
+          if (err != hipSuccess) return err;
+        }
+        const int* gate = &w.S->stop;
+        double* P = w.partials;
+#define GSE_DG_STEP(JB)                                                                             \
+  hipLaunchKernelGGL((k_dg_dots<JB>), dim3(gb), dim3(kWG), 0, st, w.S, V, ld, n, j, z, P);         \
+  hipLaunchKernelGGL(k_finish, dim3(2 * j + 2), dim3(kWG), 0, st, P, gb, gb, 2 * j + 2, dg.sums,   \
+                     gate);                                                                        \
+  hipLaunchKernelGGL((k_dg_axpy<JB>), dim3(gb), dim3(kWG), 0, st, w.S, sm, dg, m, j, V, ld, n, z, \
+                     w.hist, w.seg_hist)
+        // final vectors q_0..q_{j-1}, rounded up to a multiple of 4 (m <= 32)
+        switch ((j + 3) >> 2) {
+          case 0:
+          case 1: GSE_DG_STEP(4); break;
+          case 2: GSE_DG_STEP(8); break;
+          case 3: GSE_DG_STEP(12); break;
+          case 4: GSE_DG_STEP(16); break;
+          case 5: GSE_DG_STEP(20); break;
+          case 6: GSE_DG_STEP(24); break;
+          case 7: GSE_DG_STEP(28); break;
+          default: GSE_DG_STEP(32); break;
+        }
+#undef GSE_DG_STEP
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+      }
+#define GSE_GM_UPDATE(JB) \
+  hipLaunchKernelGGL((k_gm_update<JB>), dim3(gb), dim3(kWG), 0, st, w.S, sm, m, V, ld, x, n)
+      if (m <= 8) GSE_GM_UPDATE(8);
+      else if (m <= 16) GSE_GM_UPDATE(16);
+      else if (m <= 24) GSE_GM_UPDATE(24);
+      else GSE_GM_UPDATE(32);
+#undef GSE_GM_UPDATE
+      return hipGetLastError();
+    };
     auto launch_cycle = [&](int s_use) -> hipError_t {
+      if (dcgs2) return launch_cycle_dg(s_use);
       hipLaunchKernelGGL(k_gm_start, dim3(vb), dim3(kWG), 0, st, w.S, sm, m, V, n);
       for (int j = 0; j < m; ++j) {
         double* vj = V + (size_t)j * ld;

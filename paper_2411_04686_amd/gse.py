@@ -58,7 +58,7 @@ class gse_params(C.Structure):
                 ("rsd_limit", C.c_double), ("ndec_limit", C.c_int32),
                 ("reldec_limit", C.c_double), ("ndec_rule", C.c_int32),
                 ("floor_c", C.c_double), ("switch_mode", C.c_int32),
-                ("record_history", C.c_int32), ("launch_mode", C.c_int32)]
+                ("record_history", C.c_int32), ("launch_mode", C.c_int32), ("orth", C.c_int32)]
 
 
 class gse_report(C.Structure):

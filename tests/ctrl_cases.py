@@ -73,7 +73,9 @@ def oracle_params(case, switch_mode: int = 0):
     preset = "paper_gmres" if case["method"] == "gmres" else "paper_cg"
     return O.make_params(tol=1e-10, max_iter=max_iter_of(case), restart=case.get("restart", 30),
                          fixed_segments=case.get("fixed", 0), preset=preset,
-                         switch_mode=switch_mode, orth=1, **case["ctrl"])
+                         switch_mode=switch_mode,
+                         orth=2 if case["method"] == "gmres" and case.get("restart", 30) <= 32
+                         else 1, **case["ctrl"])
 
 
 def head_solution(A, enc, b):

@@ -312,7 +312,7 @@ def test_solvers_on_block_tables(method, sampled):
     enc, M = encode_both(A, 256, sampled=sampled, seed=4)
     rep, x = gpu_solve(M, A, b, method)
     preset = "paper_cg" if method == G.CG else "paper_gmres"
-    prm = O.make_params(tol=1e-10, max_iter=5000, preset=preset, orth=1)
+    prm = O.make_params(tol=1e-10, max_iter=5000, preset=preset, orth=2)
     fn = O.cg if method == G.CG else O.gmres
     ref = fn(A.indptr, b, prm, A.indices, A.data, enc)
     assert rep.status == G.OK and ref.status == O.OK

@@ -101,7 +101,8 @@ def _solve(method, A, b, gfmt, ofmt, restart=30):
     torch.cuda.synchronize()
     plane, _ = O.lp_convert(A.data, ofmt)
     prm = O.make_params(tol=1e-10, max_iter=p.max_iter, restart=restart, fixed_segments=O.S_LP,
-                        preset="paper_gmres" if method == G.GMRES else "paper_cg", orth=1)
+                        preset="paper_gmres" if method == G.GMRES else "paper_cg",
+                        orth=2 if restart <= 32 else 1)
     osolve = O.gmres if method == G.GMRES else O.cg
     ref = osolve(A.indptr, b, prm, A.indices, A.data, lp=(plane, ofmt))
     return rep, x.cpu().numpy(), ref

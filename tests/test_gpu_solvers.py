@@ -72,10 +72,16 @@ def gpu_solve(kind, A: CSR, b, method, fixed=0, max_iter=5000, switch_mode=1, x0
     return rep, x.cpu().numpy(), hist, seg
 
 
+def gmres_orth(restart=30):
+    """The oracle's Gram-Schmidt variant matching the library default:
+    delayed CGS2 (2) for restarts up to 32, CGS2 (1) beyond."""
+    return 2 if restart <= 32 else 1
+
+
 def oracle_params(method, fixed=0, max_iter=5000, switch_mode=1, restart=30):
     preset = "paper_cg" if method == G.CG else "paper_gmres"
     return O.make_params(tol=1e-10, max_iter=max_iter, restart=restart, fixed_segments=fixed,
-                         preset=preset, switch_mode=switch_mode, orth=1)
+                         preset=preset, switch_mode=switch_mode, orth=gmres_orth(restart))
 
 
 def test_cg_fp64_poisson_matches_oracle():
@@ -460,3 +466,38 @@ def test_graphs_kept_across_solves(method):
     torch.cuda.synchronize()
     assert rep.status == G.OK
     assert true_relres(A2, x.cpu().numpy(), b2) <= 1e-10
+
+
+def test_gmres_gram_schmidt_variants():
+    """orth = 1 (CGS2) and 2 (DCGS2, the default up to restart 32) against
+    the oracle's same variant on the stepped 64^2 convection-diffusion
+    system: iteration counts, per-segment counts and switch points equal,
+    solutions within 1e-8; orth 0 is DCGS2 at restart 30 and CGS2 at
+    restart 40, bit for bit; DCGS2 past restart 32 and unknown values are
+    refused."""
+    A = convdiff2d(64, 4)
+    _, b = rhs_from_solution(A, 4)
+    enc = O.encode(A.indptr, A.indices, A.data, A.n_cols)
+    runs = {}
+    for orth, restart in ((1, 30), (2, 30), (0, 30), (0, 40), (1, 40)):
+        rep, x, hist, _ = gpu_solve("gse", A, b, G.GMRES, restart=restart, orth=orth,
+                                    max_iter=15000)
+        runs[(orth, restart)] = (rep, x, hist)
+        if orth == 0:
+            continue
+        prm = O.make_params(tol=1e-10, max_iter=15000, restart=restart, preset="paper_gmres",
+                            orth=orth)
+        ref = O.gmres(A.indptr, b, prm, A.indices, A.data, enc)
+        assert rep.status == G.OK and ref.status == O.OK, (orth, restart)
+        assert rep.iters == ref.iters and list(rep.switch_iter) == list(ref.switch_iter)
+        assert list(rep.iters_per_seg) == list(ref.iters_per_seg)
+        assert np.linalg.norm(x - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
+        k = rep.iters + 1
+        np.testing.assert_allclose(hist[:k], ref.hist[:k], rtol=1e-6)
+    for same, other in (((0, 30), (2, 30)), ((0, 40), (1, 40))):
+        assert np.array_equal(runs[same][1], runs[other][1])
+        assert np.array_equal(runs[same][2], runs[other][2])
+    for orth, restart in ((2, 40), (3, 30), (-1, 30)):
+        with pytest.raises(G.GseError) as e:
+            gpu_solve("gse", A, b, G.GMRES, restart=restart, orth=orth)
+        assert e.value.status == G.ERR_ARG
