@@ -10,16 +10,6 @@
 // workgroup per system.  Kernel boundaries are the only barriers, so no
 // workgroup ever waits on another and there are no cross-XCD fences.
 //
-// An iteration is two launches.  The product of iteration j forms its own
-// direction: it gathers p_j[c] = r_j[c] + beta_{j-1} p_{j-1}[c] from the r
-// and p of the last r step (both unchanged since), so no kernel of its own
-// has to store p_j first; the r step then stores p_j, adds alpha_j p_j to x
-// and updates r.  The closing scalars of an iteration (beta, the history and
-// the controller) run in the workgroup on the system's tile 0 of the next
-// product, and for the epoch's last iteration in one closing launch.  All
-// kernels form p_j with the same rounded operations, so the stored p_j is
-// the one the product used.
-//
 // The kernels read the list lengths from device memory, so the iteration
 // epoch (16 iterations) is captured into a HIP graph once per engine and
 // replayed whatever the batch holds; between epochs the host reads the
@@ -93,28 +83,13 @@ __device__ __forceinline__ double load_decode(const BatchSlot& B, int j, const D
   return decode<FMT>(c, h, t1, t2, v, scale, col);
 }
 
-// The vector a product reads: x itself, or (CHAIN) the direction
-// r + beta x formed element by element -- with explicitly rounded operations,
-// so that every workgroup that forms an element, and the r step that stores
-// it, gets the same bits.
-template <bool CHAIN>
-struct VecIn {
-  const double* __restrict__ x;
-  const double* __restrict__ r;
-  double beta;
-  __device__ __forceinline__ double operator[](int c) const {
-    if constexpr (CHAIN) return __dadd_rn(r[c], __dmul_rn(beta, x[c]));
-    else return x[c];
-  }
-};
-
 // Row sums of a staged tile, one thread per row, BW non-zeros per batch: the
 // gathers of a batch are issued before any is used; slots past the row's
 // end gather x[0] and are left out of the sum.
-template <int BW, class In, class Emit>
+template <int BW, class Emit>
 __device__ __forceinline__ void sum_staged(const BatchSlot& B, int ra, int rb, int j0,
-                                           const double* vals, const int* cols, const In& xin,
-                                           Emit& emit) {
+                                           const double* vals, const int* cols,
+                                           const double* __restrict__ xin, Emit& emit) {
   for (int r = ra + (int)threadIdx.x; r < rb; r += kWG) {
     const int s0 = B.row_ptr[r], s1 = B.row_ptr[r + 1];
     const int o = s0 - j0, len = s1 - s0;
@@ -145,10 +120,10 @@ __device__ __forceinline__ void sum_staged(const BatchSlot& B, int ra, int rb, i
 // order.  Otherwise (a row running far past the tile) short rows are summed
 // from memory by one thread and long ones by the whole workgroup.  Returns
 // this thread's share of the epilogue dot.
-template <int FMT, class In>
-__device__ double tile_rows(const BatchSlot& B, int t, const In& xin, double* __restrict__ yout,
-                            const In& aux, int epi, double* vals, int* cols, uint32_t* scale_tab,
-                            double* red) {
+template <int FMT>
+__device__ double tile_rows(const BatchSlot& B, int t, const double* __restrict__ xin,
+                            double* __restrict__ yout, const double* __restrict__ aux, int epi,
+                            double* vals, int* cols, uint32_t* scale_tab, double* red) {
   const int tid = threadIdx.x;
   const int ra = B.tile_row[t], rb = B.tile_row[t + 1];
   const int j0 = B.row_ptr[ra], j1 = B.row_ptr[rb];
@@ -211,88 +186,32 @@ __device__ double tile_rows(const BatchSlot& B, int t, const In& xin, double* __
   return acc;
 }
 
-template <bool CHAIN>
-__device__ __forceinline__ double tile_any(int f, const BatchSlot& B, int t, const VecIn<CHAIN>& in,
-                                           double* yout, const VecIn<CHAIN>& aux, int epi,
-                                           double* vals, int* cols, uint32_t* scale, double* red) {
-  switch (f) {
-    case 1: return tile_rows<1>(B, t, in, yout, aux, epi, vals, cols, scale, red);
-    case 2: return tile_rows<2>(B, t, in, yout, aux, epi, vals, cols, scale, red);
-    case 3: return tile_rows<3>(B, t, in, yout, aux, epi, vals, cols, scale, red);
-    default: return tile_rows<kCsr64>(B, t, in, yout, aux, epi, vals, cols, scale, red);
-  }
-}
-
-// mode 0 (iteration j): q = A_s p_j and the partials of p_j.q, for systems
-// still running.  With `chain` set, the last r step left r_j and p_{j-1}:
-// every workgroup sums that step's partials into rho_j (the same bits
-// everywhere), p_j = r_j + beta_{j-1} p_{j-1} is formed where it is read,
-// and the workgroup on tile 0 closes iteration j (beta, rho_j, the
-// history, the controller; it may stop the system while the others still
-// multiply, which only wastes their product).  Without it (the first
-// iteration after an action) p already holds p_j.  mode 1 (actions):
-// r = b - A_s x (init / replacement) or w = b - A_3 x (check) and the
-// partials of their squared norms.  A tile item carries its system's first
-// chunk partial in `pad`.
+// mode 0 (iteration): q = A_s p and the partials of p.q, for systems still
+// running.  mode 1 (actions): r = b - A_s x (init / replacement) or
+// w = b - A_3 x (check) and the partials of their squared norms.
 __global__ __launch_bounds__(kWG) void k_b_spmv(BatchView v, int mode) {
   __shared__ __attribute__((aligned(16))) double vals[kNS + 8];
   __shared__ __attribute__((aligned(16))) int cols[kNS + 8];
   __shared__ uint32_t scale[kScaleEntries];
   __shared__ double red[kWaves];
-  __shared__ double bc_rel;
-  __shared__ int bc_stop;
   const int n = v.list.counts[0];
   for (Walk w = walk_of(n); w.i < w.end; w.i += w.step) {
     const WorkItem it = v.list.tiles[w.i];
     const BatchSlot& B = v.slot[it.slot];
-    SolverState* S = v.S + it.slot;
-    if (mode == 0) {
-      // the controller of another workgroup may set stop during this launch:
-      // one read for the whole workgroup, so that its barriers stay matched
-      if (threadIdx.x == 0) bc_stop = S->stop;
-      __syncthreads();
-      const int stop = bc_stop;
-      __syncthreads();
-      if (stop) continue;
-      const int f = B.fmt ? S->s : kCsr64;
-      double acc;
-      if (S->chain) {
-        const int j = S->it_next;
-        const double rho_old = S->rho_p[(j - 1) & 1];
-        const double rho_new = sum_partials(v.part2 + it.pad, B.n_chunks, red);
-        const double beta = rho_new / rho_old;
-        if (it.idx == 0) {
-          const int s = S->s;
-          if (threadIdx.x == 0) {
-            const double rel = sqrt(rho_new) / S->nb;
-            S->beta = beta;
-            S->rho_p[j & 1] = rho_new;
-            S->rho = rho_new;
-            S->it = j;
-            S->relres = rel;
-            S->chain_used = 1;
-            B.hist[j] = rel;
-            B.seg_hist[j] = s;
-            bc_rel = rel;
-          }
-          __syncthreads();
-          controller(S, B.hist, red, j, bc_rel, s);
-          __syncthreads();
-        }
-        const VecIn<true> in{B.p, B.r, beta};
-        acc = tile_any<true>(f, B, it.idx, in, B.q, in, kEpiDot, vals, cols, scale, red);
-      } else {
-        if (it.idx == 0 && threadIdx.x == 0) S->chain_used = 0;
-        const VecIn<false> in{B.p, nullptr, 0.0};
-        acc = tile_any<false>(f, B, it.idx, in, B.q, in, kEpiDot, vals, cols, scale, red);
-      }
-      const double bs = block_sum(acc, red);
-      if (threadIdx.x == 0) v.part[it.part] = bs;
-      continue;
-    }
+    const SolverState* S = v.S + it.slot;
     int f;
+    const double* xin;
     double* yout;
-    {
+    const double* aux;
+    int epi;
+    if (mode == 0) {
+      if (S->stop) continue;
+      f = B.fmt ? S->s : kCsr64;
+      xin = B.p;
+      yout = B.q;
+      aux = B.p;
+      epi = kEpiDot;
+    } else {
       const int a = v.act[it.slot];
       if (a == kActCheck) {
         f = B.fmt ? 3 : kCsr64;
@@ -303,44 +222,40 @@ __global__ __launch_bounds__(kWG) void k_b_spmv(BatchView v, int mode) {
       } else {
         continue;
       }
+      xin = B.x;
+      aux = B.b;
+      epi = kEpiResid;
     }
-    const VecIn<false> in{B.x, nullptr, 0.0}, aux{B.b, nullptr, 0.0};
-    const double acc = tile_any<false>(f, B, it.idx, in, yout, aux, kEpiResid, vals, cols, scale, red);
+    double acc;
+    switch (f) {
+      case 1: acc = tile_rows<1>(B, it.idx, xin, yout, aux, epi, vals, cols, scale, red); break;
+      case 2: acc = tile_rows<2>(B, it.idx, xin, yout, aux, epi, vals, cols, scale, red); break;
+      case 3: acc = tile_rows<3>(B, it.idx, xin, yout, aux, epi, vals, cols, scale, red); break;
+      default: acc = tile_rows<kCsr64>(B, it.idx, xin, yout, aux, epi, vals, cols, scale, red);
+    }
     const double bs = block_sum(acc, red);
     if (threadIdx.x == 0) v.part[it.part] = bs;
   }
 }
 
-// The scalar steps of an iteration run inside the two kernels, as in the
+// The scalar steps of an iteration run inside the vector kernels, as in the
 // single-system solver: every workgroup that works on a system sums that
-// system's partials (a few per system) in a fixed order, and one workgroup
-// publishes the scalars (tile 0 in the product, chunk 0 in the r step).
-// The fields a kernel's workgroups read are not written by that kernel
-// (rho alternates between two slots by iteration parity; the product
-// publishes chain_used and beta for the r step, the r step chain and
-// it_next for the next product), except stop, which each workgroup reads
-// once.  A chunk item carries its system's first tile partial in `pad` and
-// its own chunk partial in `part` (a system's chunk partials are
-// consecutive); a tile item carries the first chunk partial in `pad`.
+// system's partials (a few per system) in a fixed order, and the workgroup
+// on the system's chunk 0 publishes the scalars.  Fields a kernel reads are
+// never written by another workgroup of that kernel (rho alternates between
+// two slots by iteration parity).  A chunk item carries its system's first
+// tile partial in `pad` and its own chunk partial in `part` (a system's
+// chunk partials are consecutive, so they start at part - idx).
 
-// Iteration j after its product: alpha = rho_j / p_j.q; per row chunk
-// p_j (formed as the product formed it, when it did), x += alpha p_j,
-// r -= alpha q, p = p_j, and the partials of r.r; on chunk 0 the scalars
-// the next product reads (it_next, chain).  A breakdown (p.q not positive)
-// stops the system; every workgroup reaches the same verdict.
+// alpha = rho / p.q; r -= alpha q and the partials of r.r, per row chunk.
 __global__ __launch_bounds__(kWG) void k_b_rstep(BatchView v) {
   __shared__ double red[kWaves];
-  __shared__ int bc_stop;
   const int n = v.list.counts[1];
   for (Walk w = walk_of(n); w.i < w.end; w.i += w.step) {
     const WorkItem it = v.list.chunks[w.i];
     SolverState* S = v.S + it.slot;
-    // chunk 0 of a system may set stop during this launch: one read per
-    // workgroup keeps its barriers matched
-    if (threadIdx.x == 0) bc_stop = S->stop;
-    __syncthreads();
-    const int stop = bc_stop;
-    __syncthreads();
+    const int stop = S->stop;
+    if (it.idx == 0 && threadIdx.x == 0) S->go = 0;
     if (stop) continue;
     const BatchSlot& B = v.slot[it.slot];
     const int j = S->it;
@@ -354,27 +269,18 @@ __global__ __launch_bounds__(kWG) void k_b_rstep(BatchView v) {
         S->stop = kBreak;
       } else {
         S->alpha = alpha;
+        S->go = 1;
         S->it_next = j + 1;
-        S->chain = 1;
       }
     }
     if (broke) continue;
-    const bool chained = S->chain_used != 0;
-    const double beta = S->beta;
     const int lo = it.idx * kChunk;
     const int hi = min(B.n_rows, lo + kChunk);
-    double* __restrict__ x = B.x;
-    double* __restrict__ p = B.p;
     double* __restrict__ r = B.r;
     const double* __restrict__ q = B.q;
     double acc = 0.0;
     for (int i = lo + threadIdx.x; i < hi; i += kWG) {
-      const double ri = r[i];
-      const double pv = p[i];
-      const double pj = chained ? __dadd_rn(ri, __dmul_rn(beta, pv)) : pv;
-      x[i] += alpha * pj;
-      p[i] = pj;
-      const double rv = ri - alpha * q[i];
+      const double rv = r[i] - alpha * q[i];
       r[i] = rv;
       acc += rv * rv;
     }
@@ -383,45 +289,40 @@ __global__ __launch_bounds__(kWG) void k_b_rstep(BatchView v) {
   }
 }
 
-// End of an epoch: no iteration stays open across host rounds (the lists,
-// and with them the partials' positions, may change between epochs).  For a
-// system whose last r step left iteration j + 1 unclosed (it_next > it),
-// every workgroup sums that step's partials into rho_{j+1} and stores
-// p_{j+1} = r_{j+1} + beta_j p_j for its chunk, and the workgroup on chunk 0
-// closes the iteration (beta, rho, the history, the controller; the host
-// then advances it).  A system that a product stopped at iteration j (it =
-// it_next) gets p_j = r_j + beta_{j-1} p_{j-1}, the direction a switch that
-// keeps its direction continues with.  Neither it nor it_next nor chain is
-// written here, so every workgroup takes the same branch.
-__global__ __launch_bounds__(kWG) void k_b_close(BatchView v) {
+// beta = rho' / rho; x += alpha p, p = r + beta p per row chunk; on chunk 0
+// the history, the iteration count and the controller.
+__global__ __launch_bounds__(kWG) void k_b_xstep(BatchView v) {
   __shared__ double red[kWaves];
   __shared__ double bc_rel;
   const int n = v.list.counts[1];
   for (Walk w = walk_of(n); w.i < w.end; w.i += w.step) {
     const WorkItem it = v.list.chunks[w.i];
     SolverState* S = v.S + it.slot;
-    if (!S->chain) continue;
+    if (!S->go) continue;
     const BatchSlot& B = v.slot[it.slot];
     const int j = S->it_next;
-    const bool pending = j > S->it;
-    double beta, rho_new = 0.0;
-    if (pending) {
-      rho_new = sum_partials(v.part2 + (it.part - it.idx), B.n_chunks, red);
-      beta = rho_new / S->rho_p[(j - 1) & 1];
-    } else {
-      beta = S->beta;
-    }
+    const double rho_old = S->rho_p[(j - 1) & 1];
+    const double alpha = S->alpha;
+    const double rho_new = sum_partials(v.part2 + (it.part - it.idx), B.n_chunks, red);
+    const double beta = rho_new / rho_old;
     const int lo = it.idx * kChunk;
     const int hi = min(B.n_rows, lo + kChunk);
-    for (int i = lo + threadIdx.x; i < hi; i += kWG)
-      B.p[i] = __dadd_rn(B.r[i], __dmul_rn(beta, B.p[i]));
-    if (!pending || it.idx != 0) continue;
+    double* __restrict__ x = B.x;
+    double* __restrict__ p = B.p;
+    const double* __restrict__ r = B.r;
+    for (int i = lo + threadIdx.x; i < hi; i += kWG) {
+      const double pv = p[i];
+      x[i] += alpha * pv;
+      p[i] = r[i] + beta * pv;
+    }
+    if (it.idx != 0) continue;
     const int s = S->s;
     if (threadIdx.x == 0) {
       const double rel = sqrt(rho_new) / S->nb;
       S->beta = beta;
       S->rho_p[j & 1] = rho_new;
       S->rho = rho_new;
+      S->it = j;
       S->relres = rel;
       B.hist[j] = rel;
       B.seg_hist[j] = s;
@@ -682,7 +583,7 @@ gse_status BatchEngine::upload_list(int l, const std::vector<int>& ids) {
   for (int id : ids) {
     const BatchSlot& B = hslot_[id];
     wsl.push_back(SlotItem{id, (int32_t)pt, (int32_t)pc, 0});
-    for (int t = 0; t < B.n_tiles; ++t) wt.push_back(WorkItem{id, t, (int32_t)(pt + t), (int32_t)pc});
+    for (int t = 0; t < B.n_tiles; ++t) wt.push_back(WorkItem{id, t, (int32_t)(pt + t), 0});
     for (int c = 0; c < B.n_chunks; ++c) wc.push_back(WorkItem{id, c, (int32_t)(pc + c), (int32_t)pt});
     pt += B.n_tiles;
     pc += B.n_chunks;
@@ -726,11 +627,11 @@ hipError_t BatchEngine::launch_epoch_kernels(int iters) {
   for (int k = 0; k < iters; ++k) {
     hipLaunchKernelGGL(k_b_spmv, dim3(grid_spmv_), dim3(kWG), 0, st_, v, 0);
     hipLaunchKernelGGL(k_b_rstep, dim3(grid_vec_), dim3(kWG), 0, st_, v);
+    hipLaunchKernelGGL(k_b_xstep, dim3(grid_vec_), dim3(kWG), 0, st_, v);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_b_close, dim3(grid_vec_), dim3(kWG), 0, st_, v);
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 hipError_t BatchEngine::sync_states_in() {
@@ -841,7 +742,6 @@ gse_status BatchEngine::actions(std::vector<int>* done) {
     SlotHost& m = meta_[id];
     SolverState& S = hS_[id];
     hact_[id] = kActNone;
-    S.chain = 0;  // p holds the direction itself again
     switch (m.phase) {
       case kPhInit:
         if (S.nb == 0.0) {
@@ -934,10 +834,6 @@ gse_status BatchEngine::epoch() {
   for (int id : ids) {
     SlotHost& m = meta_[id];
     SolverState& S = hS_[id];
-    if (S.chain) {  // k_b_close closed the last iteration and stored its direction
-      if (S.it_next > S.it) S.it = S.it_next;
-      S.chain = 0;
-    }
     if (S.stop == kRun) continue;
     int reason = S.stop, trig = S.trig;
     run_dirty_ = true;

@@ -27,14 +27,14 @@ struct SolverState {
   int s;             // segment count in use (0: FP64 CSR)
   int stop;          // Stop
   int trig;          // trigger of a switch
-  int chain;         // batched CG: p holds p_{j-1}; the next product forms p_j = r_j + beta p_{j-1}
+  int k3_armed;      // batched CG: the x/p update of the last completed iteration is pending
   int go;            // CG: this iteration's r step ran (read by the x step)
   int it_next;       // CG: the iteration the r step started
   int max_iter;
   int stepped;
   int fixed;
   int l, t, m, ndec_limit, ndec_rule;
-  int chain_used;    // batched CG: whether the last product formed p itself (read by the r step)
+  int pad0;
   long long hist_off;  // byte offsets of the residual / segment histories
   long long seg_off;   // in the workspace (read by gse_solve_history)
   int hist_cap;
