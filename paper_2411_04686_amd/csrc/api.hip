@@ -640,6 +640,9 @@ static gse_status batch_descs(int32_t n_sys, const gse_system* sys, const gse_pa
       B.max_row = A->max_row_nnz;
       B.split = col_split(A->idx_bits, A->idx_layout == GSE_IDX_VALUE);
       for (int k = 0; k < GSE_MAX_EXP; ++k) B.sem[k] = A->sem[k];
+      B.nnz = (int32_t)A->nnz;
+      B.tile_nnz = A->tile_nnz;
+      B.rv_lanes = A->rv_lanes;
       d.eta = A->eta;
     } else {
       s = check_csr(y.M);
@@ -656,6 +659,9 @@ static gse_status batch_descs(int32_t n_sys, const gse_system* sys, const gse_pa
       B.fmt = 0;
       B.max_row = M->max_row_nnz;
       B.split = col_split(0);
+      B.nnz = (int32_t)M->nnz;
+      B.tile_nnz = M->tile_nnz;
+      B.rv_lanes = M->rv_lanes;
       d.eta = nullptr;
     }
     if (!y.b || !y.x || !aligned16(y.x)) return fail(GSE_ERR_ARG, "system %d: bad b / x", i);

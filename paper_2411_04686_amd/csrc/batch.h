@@ -36,7 +36,26 @@ struct BatchSlot {
   int32_t max_row;  // non-zeros of the longest row
   ColSplit split;   // column / slot fields of the column words
   int16_t sem[GSE_MAX_EXP];
+  // the matrix's own SpMV plan (filled by the caller)
+  int32_t nnz;
+  int32_t tile_nnz;
+  int32_t rv_lanes;
+  // filled by BatchEngine::add: ring = 1 when the system's product runs on
+  // the single-system row-tile ring (large systems of short rows); parts =
+  // partial slots reserved for its product; n_prod = partials the product
+  // writes (n_tiles, or the ring's grid)
+  int32_t ring;
+  int32_t parts;
+  int32_t n_prod;
 };
+
+// Rows from which a system of short rows (at most 8 non-zeros, the default
+// 1024-non-zero plan) takes its batched product from the row-tile ring
+// kernel, one launch per iteration, instead of the batched tile kernel.
+constexpr int32_t kRingRows = 1 << 17;
+
+// The row-tile ring's operand for a batched system.
+SpmvOperand ring_operand(const BatchSlot& B);
 
 // Work items: a tile or a row chunk of one slot, and where its partial sum
 // goes; a slot entry for the per-system finishers with its partial ranges.
@@ -179,6 +198,8 @@ class BatchEngine {
   std::vector<SlotItem> ws_[2];
   std::vector<int> ids_;
   std::vector<int32_t> seg_buf_;
+  std::vector<int32_t> prod_off_;   // first product partial of each slot in list 0
+  std::vector<int> ring_ids_;       // running systems whose product runs on the ring
   int32_t hcounts_[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
   RegionHeader hhdr_{};
   bool run_dirty_ = true;

@@ -23,6 +23,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 
 #include "batch.h"
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(kWG) void k_b_rstep(BatchView v) {
     const BatchSlot& B = v.slot[it.slot];
     const int j = S->it;
     const double rho = S->rho_p[j & 1];
-    const double pq = sum_partials(v.part + it.pad, B.n_tiles, red);
+    const double pq = sum_partials(v.part + it.pad, B.n_prod, red);
     const bool broke = !(pq > 0.0) || !isfinite(pq);
     const double alpha = rho / pq;
     if (it.idx == 0 && threadIdx.x == 0) {
@@ -481,6 +482,8 @@ gse_status BatchEngine::init(void* region, size_t bytes, int cap_slots, int64_t 
   hact_.assign((size_t)cap_slots, 0);
   meta_.assign((size_t)cap_slots, SlotHost{});
   used_.assign((size_t)cap_slots, 0);
+  prod_off_.assign((size_t)cap_slots, 0);
+  ring_ids_.clear();
   for (int l = 0; l < 2; ++l) {
     hcounts_[l][0] = hcounts_[l][1] = hcounts_[l][2] = hcounts_[l][3] = 0;
   }
@@ -514,16 +517,24 @@ int BatchEngine::add(const BatchSlot& d, const gse_params* p, const double* eta)
       break;
     }
   if (id < 0) return fail(GSE_ERR_NOMEM, "no free batch slot");
-  int64_t tiles = d.n_tiles, chunks = d.n_chunks;
+  BatchSlot dd = d;
+  dd.ring = (d.n_rows >= kRingRows && d.tile_nnz == 1024 && d.nnz >= 1024 && d.max_row <= 8 &&
+             d.rv_lanes == 0) ? 1 : 0;
+  // the ring's grid is at most the row tiles rounded up to 8, and at least 8
+  const int32_t rt = (int32_t)(((int64_t)d.n_rows + 191) / 192);
+  const int32_t rt8 = (rt + 7) / 8 * 8;
+  dd.parts = dd.ring ? std::max(d.n_tiles, std::max(rt8, 8)) : d.n_tiles;
+  dd.n_prod = d.n_tiles;
+  int64_t tiles = dd.parts, chunks = d.n_chunks;
   for (int i = 0; i < cap_slots_; ++i)
     if (used_[i] && meta_[i].phase != kPhDone) {
-      tiles += hslot_[i].n_tiles;
+      tiles += hslot_[i].parts;
       chunks += hslot_[i].n_chunks;
     }
   if (tiles > cap_tiles_ || chunks > cap_chunks_)
     return fail(GSE_ERR_NOMEM, "batch lists full (%lld tiles, %lld chunks)", (long long)tiles,
                 (long long)chunks);
-  hslot_[id] = d;
+  hslot_[id] = dd;
   SolverState& S = hS_[id];
   memset(&S, 0, sizeof S);
   const bool gse = d.fmt != 0;
@@ -580,12 +591,19 @@ gse_status BatchEngine::upload_list(int l, const std::vector<int>& ids) {
   wc.clear();
   wsl.clear();
   int64_t pt = 0, pc = 0;
+  if (l == 0) ring_ids_.clear();
   for (int id : ids) {
     const BatchSlot& B = hslot_[id];
     wsl.push_back(SlotItem{id, (int32_t)pt, (int32_t)pc, 0});
-    for (int t = 0; t < B.n_tiles; ++t) wt.push_back(WorkItem{id, t, (int32_t)(pt + t), 0});
+    // in the iteration list a ring system's product is its own launch
+    if (l == 0 && B.ring) {
+      ring_ids_.push_back(id);
+    } else {
+      for (int t = 0; t < B.n_tiles; ++t) wt.push_back(WorkItem{id, t, (int32_t)(pt + t), 0});
+    }
     for (int c = 0; c < B.n_chunks; ++c) wc.push_back(WorkItem{id, c, (int32_t)(pc + c), (int32_t)pt});
-    pt += B.n_tiles;
+    if (l == 0) prod_off_[id] = (int32_t)pt;
+    pt += B.parts;
     pc += B.n_chunks;
   }
   if (pt > cap_tiles_ || pc > cap_chunks_ || (int64_t)ids.size() > cap_slots_)
@@ -626,12 +644,56 @@ hipError_t BatchEngine::launch_epoch_kernels(int iters) {
   const BatchView v = view(0);
   for (int k = 0; k < iters; ++k) {
     hipLaunchKernelGGL(k_b_spmv, dim3(grid_spmv_), dim3(kWG), 0, st_, v, 0);
+    // ring systems: q = A_s p and the partials of p.q on the row-tile ring,
+    // skipped on the device once the system stopped
+    for (int id : ring_ids_) {
+      BatchSlot& B = hslot_[id];
+      const int fmt = B.fmt ? hS_[id].s : kCsr64;
+      SpmvEpilogue ep{};
+      ep.epi = kEpiDot;
+      ep.aux = B.p;
+      ep.partials = part_ + prod_off_[id];
+      ep.gate = &S_[id].stop;
+      int g = 0;
+      ep.grid_out = &g;
+      hipError_t e = launch_spmv(fmt, ring_operand(B), B.p, B.q, ep, st_);
+      if (e != hipSuccess) return e;
+      if (g < 1 || g > B.parts) return hipErrorInvalidValue;
+      if (g != B.n_prod) {  // ordered before the r step that sums them
+        B.n_prod = g;
+        e = hipMemcpyAsync(&slots_[id].n_prod, &B.n_prod, sizeof(int32_t), hipMemcpyHostToDevice, st_);
+        if (e != hipSuccess) return e;
+      }
+    }
     hipLaunchKernelGGL(k_b_rstep, dim3(grid_vec_), dim3(kWG), 0, st_, v);
     hipLaunchKernelGGL(k_b_xstep, dim3(grid_vec_), dim3(kWG), 0, st_, v);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+SpmvOperand ring_operand(const BatchSlot& B) {
+  SpmvOperand op{};
+  op.row_ptr = B.row_ptr;
+  op.tile_row = B.tile_row;
+  op.col = B.col;
+  op.head = B.head;
+  op.tail1 = B.tail1;
+  op.tail2 = B.tail2;
+  op.val = B.val;
+  op.n_rows = B.n_rows;
+  op.n_tiles = B.n_tiles;
+  op.tile_nnz = B.tile_nnz;
+  op.nnz = B.nnz;
+  op.rv_lanes = B.rv_lanes;
+  op.max_row = B.max_row;
+  op.split = B.split;
+  for (int i = 0; i < GSE_MAX_EXP; ++i) op.sem[i] = B.sem[i];
+  op.block_sem = nullptr;
+  op.block_rows = 0;
+  op.block_stride = 0;
+  return op;
 }
 
 hipError_t BatchEngine::sync_states_in() {
@@ -822,7 +884,9 @@ gse_status BatchEngine::epoch() {
   }
   hipError_t e = sync_states_out();
   if (e == hipSuccess) {
-    if (graphs_) {
+    // the captured epoch holds the batched kernels only: epochs with ring
+    // systems (one product launch each, host-side arguments) run directly
+    if (graphs_ && ring_ids_.empty()) {
       if (!graph_) e = capture(st_, &graph_, [&] { return launch_epoch_kernels(kEpochIters); });
       if (e == hipSuccess) e = hipGraphLaunch(graph_, st_);
     } else {
@@ -894,7 +958,9 @@ struct BatchLayout {
 BatchLayout batch_layout(int32_t n_sys, const BatchSystemDesc* d, int32_t max_iter) {
   BatchLayout L;
   for (int i = 0; i < n_sys; ++i) {
-    L.tiles += d[i].n_tiles;
+    // room for the ring's partials too (BatchEngine::add reserves the same)
+    const int64_t rt8 = ((int64_t)(d[i].n_rows + 191) / 192 + 7) / 8 * 8;
+    L.tiles += std::max<int64_t>(d[i].n_tiles, std::max<int64_t>(rt8, 8));
     L.chunks += (d[i].n_rows + kChunk - 1) / kChunk;
   }
   L.engine = BatchEngine::region_bytes(n_sys, L.tiles, L.chunks);

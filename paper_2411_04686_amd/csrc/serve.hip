@@ -162,6 +162,9 @@ gse_status place(gse_solver* s, Ticket& t, gse::BatchSlot* B, const double** eta
     B->max_row = A.max_row_nnz;
     B->split = gse::col_split(A.idx_bits, A.idx_layout == GSE_IDX_VALUE);
     for (int k = 0; k < GSE_MAX_EXP; ++k) B->sem[k] = A.sem[k];
+    B->nnz = (int32_t)A.nnz;
+    B->tile_nnz = A.tile_nnz;
+    B->rv_lanes = A.rv_lanes;
     *eta = t.A.eta;
   } else {
     const int64_t pad = pad16(nnz);
@@ -192,6 +195,9 @@ gse_status place(gse_solver* s, Ticket& t, gse::BatchSlot* B, const double** eta
     B->fmt = 0;
     B->max_row = M.max_row_nnz;
     B->split = gse::col_split(0);
+    B->nnz = (int32_t)M.nnz;
+    B->tile_nnz = M.tile_nnz;
+    B->rv_lanes = M.rv_lanes;
     *eta = nullptr;
   }
   B->b = reinterpret_cast<const double*>(at(L.b));

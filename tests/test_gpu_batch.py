@@ -168,3 +168,25 @@ def test_batch_argument_errors():
     with pytest.raises(G.GseError) as ei:
         G.gse_batch_workspace([], p)
     assert ei.value.status == G.ERR_ARG
+
+
+def test_large_systems_run_their_product_on_the_ring():
+    """Systems of at least 2^17 rows of short rows take their product from
+    the single-system row-tile ring (one launch per iteration) while the
+    others stay on the batched tile kernel: both against the oracle, each
+    alone equal to the mix bit for bit, stepped GSE and FP64 CSR."""
+    systems = [Sys(diffusion3d(52, 7), 7), Sys(diffusion3d(54, 8), 8, kind="csr"),
+               Sys(diffusion3d(12, 9), 9), Sys(poisson2d(30), 10)]
+    assert systems[0].A.n_rows >= 1 << 17 and systems[1].A.n_rows >= 1 << 17
+    res = batch_solve(systems)
+    for s, (r, x, hist, seg) in zip(systems, res):
+        ref = oracle_solve(s)
+        assert r.status == G.OK and ref.status == O.OK, (s.A.name, r.as_dict())
+        assert r.relres_true <= 1e-10 and true_relres(s.A, x, s.b_host) <= 1e-10
+        assert np.linalg.norm(x - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+        assert abs(r.iters - ref.iters) <= max(3, ref.iters // 10), (s.A.name, r.iters, ref.iters)
+    for i in (0, 1, 3):
+        (r1, x1, h1, s1), = batch_solve([systems[i]])
+        r, x, hist, seg = res[i]
+        assert r1.iters == r.iters and list(r1.iters_per_seg) == list(r.iters_per_seg)
+        assert np.array_equal(x1, x) and np.array_equal(h1, hist)
