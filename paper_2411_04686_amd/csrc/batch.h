@@ -52,7 +52,7 @@ struct BatchSlot {
 // Rows from which a system of short rows (at most 8 non-zeros, the default
 // 1024-non-zero plan) takes its batched product from the row-tile ring
 // kernel, one launch per iteration, instead of the batched tile kernel.
-constexpr int32_t kRingRows = 1 << 17;
+constexpr int32_t kRingRows = 1 << 18;
 
 // The row-tile ring's operand for a batched system.
 SpmvOperand ring_operand(const BatchSlot& B);

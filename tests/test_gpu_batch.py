@@ -171,13 +171,13 @@ def test_batch_argument_errors():
 
 
 def test_large_systems_run_their_product_on_the_ring():
-    """Systems of at least 2^17 rows of short rows take their product from
+    """Systems of at least 2^18 rows of short rows take their product from
     the single-system row-tile ring (one launch per iteration) while the
     others stay on the batched tile kernel: both against the oracle, each
     alone equal to the mix bit for bit, stepped GSE and FP64 CSR."""
-    systems = [Sys(diffusion3d(52, 7), 7), Sys(diffusion3d(54, 8), 8, kind="csr"),
+    systems = [Sys(diffusion3d(64, 7), 7), Sys(diffusion3d(65, 8), 8, kind="csr"),
                Sys(diffusion3d(12, 9), 9), Sys(poisson2d(30), 10)]
-    assert systems[0].A.n_rows >= 1 << 17 and systems[1].A.n_rows >= 1 << 17
+    assert systems[0].A.n_rows >= 1 << 18 and systems[1].A.n_rows >= 1 << 18
     res = batch_solve(systems)
     for s, (r, x, hist, seg) in zip(systems, res):
         ref = oracle_solve(s)
