@@ -280,10 +280,27 @@ __global__ __launch_bounds__(kWG) void k_b_rstep(BatchView v) {
     double* __restrict__ r = B.r;
     const double* __restrict__ q = B.q;
     double acc = 0.0;
-    for (int i = lo + threadIdx.x; i < hi; i += kWG) {
-      const double rv = r[i] - alpha * q[i];
-      r[i] = rv;
-      acc += rv * rv;
+    if (hi - lo == kChunk) {
+      // a whole chunk: the same elements per thread, every load issued first
+      constexpr int K = kChunk / kWG;
+      double rv[K], qv[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        rv[k] = r[lo + threadIdx.x + k * kWG];
+        qv[k] = q[lo + threadIdx.x + k * kWG];
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double t = rv[k] - alpha * qv[k];
+        r[lo + threadIdx.x + k * kWG] = t;
+        acc += t * t;
+      }
+    } else {
+      for (int i = lo + threadIdx.x; i < hi; i += kWG) {
+        const double rv = r[i] - alpha * q[i];
+        r[i] = rv;
+        acc += rv * rv;
+      }
     }
     const double bs = block_sum(acc, red);
     if (threadIdx.x == 0) v.part2[it.part] = bs;
@@ -311,10 +328,29 @@ __global__ __launch_bounds__(kWG) void k_b_xstep(BatchView v) {
     double* __restrict__ x = B.x;
     double* __restrict__ p = B.p;
     const double* __restrict__ r = B.r;
-    for (int i = lo + threadIdx.x; i < hi; i += kWG) {
-      const double pv = p[i];
-      x[i] += alpha * pv;
-      p[i] = r[i] + beta * pv;
+    if (hi - lo == kChunk) {
+      // a whole chunk: the same elements per thread, every load issued first
+      constexpr int K = kChunk / kWG;
+      double xv[K], pv[K], rv[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int i = lo + threadIdx.x + k * kWG;
+        xv[k] = x[i];
+        pv[k] = p[i];
+        rv[k] = r[i];
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int i = lo + threadIdx.x + k * kWG;
+        x[i] = xv[k] + alpha * pv[k];
+        p[i] = rv[k] + beta * pv[k];
+      }
+    } else {
+      for (int i = lo + threadIdx.x; i < hi; i += kWG) {
+        const double pv = p[i];
+        x[i] += alpha * pv;
+        p[i] = r[i] + beta * pv;
+      }
     }
     if (it.idx != 0) continue;
     const int s = S->s;
