@@ -188,6 +188,28 @@ def test_gmres_first_cycle_residuals_match_oracle():
     assert np.allclose(hist[:31], ref.hist[:31], rtol=1e-8, atol=1e-15)
 
 
+@pytest.mark.parametrize("restart", [1, 2, 3, 4, 8, 32, 33])
+def test_gmres_short_and_boundary_restarts_first_cycles(restart):
+    """The delayed CGS2's edge steps (a cycle of one to four columns, the
+    last basis tier at 32) and the first CGS2 restart past it (33): the
+    residual estimates of the first cycles follow the oracle's same variant
+    to rounding, on FP64 and on the head-only operator."""
+    A = convdiff2d(40, 9)
+    _, b = rhs_from_solution(A, 9)
+    cycles = 3 * restart
+    enc = O.encode(A.indptr, A.indices, A.data, A.n_cols)
+    for kind, fixed in (("csr", -1), ("gse", 1)):
+        rep, x, hist, _ = gpu_solve(kind, A, b, G.GMRES, fixed=max(fixed, 0), max_iter=cycles,
+                                    restart=restart)
+        ref = O.gmres(A.indptr, b, oracle_params(G.GMRES, fixed=fixed, max_iter=cycles,
+                                                 restart=restart),
+                      A.indices, A.data, enc if kind == "gse" else None)
+        assert rep.iters == ref.iters == cycles, (kind, rep.iters, ref.iters)
+        np.testing.assert_allclose(hist[:cycles + 1], ref.hist[:cycles + 1], rtol=1e-8,
+                                   atol=1e-15)
+        assert np.linalg.norm(x - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
+
+
 @pytest.mark.parametrize("restart", [5, 17, 45, 60])
 def test_gmres_restart_lengths_match_oracle(restart):
     """Every restart length runs its own Gram-Schmidt instantiations (basis
