@@ -264,11 +264,13 @@ __global__ __launch_bounds__(kWG) void k_b_rstep(BatchView v) {
     const double pq = sum_partials(v.part + it.pad, B.n_prod, red);
     const bool broke = !(pq > 0.0) || !isfinite(pq);
     const double alpha = rho / pq;
+    // a breakdown (p.q not positive) leaves go at 0 and becomes a stop in
+    // the x step: stop is not written here, where other workgroups read it
+    // (a stop seen by some waves of a workgroup and not by others would
+    // split its barriers); every workgroup reaches the same verdict from pq
     if (it.idx == 0 && threadIdx.x == 0) {
       S->pq = pq;
-      if (broke) {
-        S->stop = kBreak;
-      } else {
+      if (!broke) {
         S->alpha = alpha;
         S->go = 1;
         S->it_next = j + 1;
@@ -316,7 +318,14 @@ __global__ __launch_bounds__(kWG) void k_b_xstep(BatchView v) {
   for (Walk w = walk_of(n); w.i < w.end; w.i += w.step) {
     const WorkItem it = v.list.chunks[w.i];
     SolverState* S = v.S + it.slot;
-    if (!S->go) continue;
+    if (!S->go) {
+      // the r step found no positive p.q for a running system: stop it
+      if (it.idx == 0 && threadIdx.x == 0 && S->stop == kRun) {
+        const double pq = S->pq;
+        if (!(pq > 0.0) || !isfinite(pq)) S->stop = kBreak;
+      }
+      continue;
+    }
     const BatchSlot& B = v.slot[it.slot];
     const int j = S->it_next;
     const double rho_old = S->rho_p[(j - 1) & 1];

@@ -156,6 +156,9 @@ def test_batch_edge_cases():
     assert r1.status == G.OK and x1[0] == pytest.approx(0.5, rel=1e-15)
     assert ri.status == G.ERR_BREAKDOWN
     assert rn.status == G.OK and true_relres(normal.A, xn, normal.b_host) <= 1e-10
+    # a breakdown beside it leaves the other system's iterates untouched
+    (ra, xa, _, _), = batch_solve([normal])
+    assert ra.iters == rn.iters and np.array_equal(xa, xn)
 
 
 def test_batch_argument_errors():
