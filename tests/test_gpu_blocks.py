@@ -289,6 +289,28 @@ def test_pooled_table_in_cg():
     assert abs(rep.iters - ref.iters) <= max(3, ref.iters // 10), (rep.iters, ref.iters)
 
 
+def test_pooled_table_in_the_batched_solver():
+    """The batched solver takes a pooled-table matrix like any one-table
+    matrix: its CG against the oracle's CG on the oracle's pooled encoding."""
+    A = layered3d(14, 5, contrast=3.0, layers=4)
+    _, b = rhs_from_solution(A, 6)
+    enc, M = encode_pooled(A, 512, seed=2)
+    p = G.gse_default_params(G.CG)
+    p.max_iter = 5000
+    bd = torch.from_numpy(b).to(DEV)
+    x = torch.zeros(A.n_rows, dtype=torch.float64, device=DEV)
+    ws = torch.empty(G.gse_batch_workspace([(M.A, bd, x)], p), dtype=torch.uint8, device=DEV)
+    rep, = G.gse_batch_cg([(M.A, bd, x)], p, ws)
+    torch.cuda.synchronize()
+    ref = O.cg(A.indptr, b, O.make_params(tol=1e-10, max_iter=5000, preset="paper_cg"),
+               A.indices, A.data, enc)
+    xs = x.cpu().numpy()
+    assert rep.status == G.OK and ref.status == O.OK
+    assert np.linalg.norm(b - A.to_scipy() @ xs) <= 1e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(xs - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+    assert abs(rep.iters - ref.iters) <= max(3, ref.iters // 10), (rep.iters, ref.iters)
+
+
 def gpu_solve(M, A, b, method, switch_mode=2, max_iter=5000):
     p = G.gse_default_params(method)
     p.max_iter = max_iter
