@@ -10,9 +10,16 @@
 // workgroup per system.  Kernel boundaries are the only barriers, so no
 // workgroup ever waits on another and there are no cross-XCD fences.
 //
+// A system of at least kRingRows rows of short rows leaves the product
+// list: its product is a launch of the single-system row-tile ring (gated
+// on its stop flag on the device) between the batched product and the r
+// step, with its p.q partials in slots reserved for it; its vector steps
+// stay in the batched kernels.
+//
 // The kernels read the list lengths from device memory, so the iteration
 // epoch (16 iterations) is captured into a HIP graph once per engine and
-// replayed whatever the batch holds; between epochs the host reads the
+// replayed whatever the batch holds (epochs with ring systems, whose
+// launches take host-side arguments, run directly); between epochs the host reads the
 // state records back, runs the actions a switch or a convergence candidate
 // needs (residual replacement, the all-segment residual check) for the
 // systems concerned, and rebuilds the lists when systems finish or arrive.
