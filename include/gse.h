@@ -444,7 +444,10 @@ gse_status gse_solve_history(const void* ws, int32_t cap, double* hist, int32_t*
  * p->launch_mode == 0).  A system's iterates and result are bit-identical
  * whether it is solved alone or in any batch.  The SpMV stages tiles of up to
  * 2048 non-zeros in LDS, so operators planned with tile_nnz 1024 (the
- * default) run fastest; any valid plan is accepted. */
+ * default) run fastest; any valid plan is accepted.  A system of at least
+ * 2^18 rows planned on the row-tile ring (rows of at most 8 non-zeros,
+ * tile_nnz 1024) takes its product from that single-system kernel, one more
+ * launch per iteration; epochs holding such systems are launched directly. */
 typedef struct gse_system {
     const gse_matrix* A;   /* stepped GSE-SEM operator, or NULL */
     const gse_csr* M;      /* FP64 CSR operator, used when A is NULL */
