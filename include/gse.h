@@ -276,10 +276,12 @@ gse_status gse_spmv(const gse_matrix* A, int32_t k_segments, const double* x, do
  * eighth of the longest row up, when no row is longer than 64; for
  * per-row-block tables the row-tile ring and 1 ... 64 lanes) with `reps`
  * launches each on the caller's x
- * (device [n_cols]) and y (device [n_rows], overwritten), then plan the
- * fastest.  Results are cached per process by matrix shape and, if the
- * environment variable GSE_AUTOTUNE_CACHE names a file, in that file.
- * Synchronizes `stream`. */
+ * (device [n_cols]) and y (device [n_rows], overwritten), back to back on
+ * the same operand as the solvers call it, then plan the fastest.  Results
+ * are cached per process by format, segment count, size, longest row and
+ * the share of rows in each power-of-two length class (the row pointers are
+ * read to the host once per call) and, if the environment variable
+ * GSE_AUTOTUNE_CACHE names a file, in that file.  Synchronizes `stream`. */
 gse_status gse_autotune(gse_matrix* A, int32_t k_segments, const double* x, double* y,
                         int32_t reps, void* stream);
 gse_status gse_csr_autotune(gse_csr* M, const double* x, double* y, int32_t reps, void* stream);

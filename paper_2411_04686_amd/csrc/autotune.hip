@@ -1,7 +1,7 @@
 // autotune.hip -- picks the SpMV schedule (tile size / lanes per row) of a
 // matrix by timing the candidates on the device, with a per-process cache
-// and an optional cache file (GSE_AUTOTUNE_CACHE) keyed by a signature of
-// the matrix shape.
+// and an optional cache file (GSE_AUTOTUNE_CACHE) keyed by the matrix shape
+// and a signature of its row lengths.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -37,6 +37,34 @@ std::string key_of(int fmt, int segs, int32_t n_rows, int64_t nnz, int32_t max_r
   return b;
 }
 
+// Row-length signature: the share of rows, in per mille rounded, in each
+// length class 0, 1, 2-3, 4-7, ... (classes under half a per mille left
+// out), read from the device row pointers once per call.  Matrices of one
+// size whose rows are distributed alike share a cache entry; a different
+// mix of row lengths is timed anew.
+hipError_t row_signature(const int32_t* row_ptr, int32_t n_rows, hipStream_t st, std::string* sig) {
+  std::vector<int32_t> rp((size_t)n_rows + 1);
+  hipError_t e = hipMemcpyAsync(rp.data(), row_ptr, rp.size() * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  int64_t cls[33] = {0};
+  for (int32_t r = 0; r < n_rows; ++r) {
+    const uint32_t len = (uint32_t)(rp[r + 1] - rp[r]);
+    ++cls[len == 0 ? 0 : 32 - __builtin_clz(len)];
+  }
+  std::string out = "_r";
+  for (int c = 0; c < 33; ++c) {
+    const long long pm = n_rows > 0 ? (cls[c] * 1000 + n_rows / 2) / n_rows : 0;
+    if (pm == 0) continue;
+    char b[32];
+    snprintf(b, sizeof b, "%s%d.%lld", out.size() > 2 ? "-" : "", c, pm);
+    out += b;
+  }
+  *sig = out;
+  return hipSuccess;
+}
+
 void load_file() {
   if (g_file_loaded) return;
   g_file_loaded = true;
@@ -44,10 +72,10 @@ void load_file() {
   if (!path) return;
   FILE* f = fopen(path, "r");
   if (!f) return;
-  char key[160];
+  char key[512];
   int tile, rv;
   float us;
-  while (fscanf(f, "%159s %d %d %f", key, &tile, &rv, &us) == 4) g_cache[key] = Choice{tile, rv, us};
+  while (fscanf(f, "%511s %d %d %f", key, &tile, &rv, &us) == 4) g_cache[key] = Choice{tile, rv, us};
   fclose(f);
 }
 
@@ -97,7 +125,10 @@ gse_status autotune(int fmt, int segs, SpmvOperand op, const int32_t* row_ptr, i
                     int32_t tile_cap, int32_t max_row, const double* x, double* y, int32_t reps,
                     hipStream_t st, int32_t* out_tile, int32_t* out_rv, int32_t* out_tiles) {
   const bool blocks = op.block_sem != nullptr;  // per-block tables
-  const std::string k = key_of(fmt, segs, op.n_rows, op.nnz, max_row) + (blocks ? "_b" : "");
+  std::string sig;
+  if (hipError_t e = row_signature(row_ptr, op.n_rows, st, &sig); e != hipSuccess)
+    return hip_fail(e, "autotune row signature");
+  const std::string k = key_of(fmt, segs, op.n_rows, op.nnz, max_row) + sig + (blocks ? "_b" : "");
   {
     std::lock_guard<std::mutex> lock(g_mu);
     load_file();

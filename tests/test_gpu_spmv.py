@@ -252,6 +252,51 @@ def test_autotune_picks_a_candidate_and_stays_exact():
         assert np.allclose(yd.cpu().numpy(), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
 
 
+def row_mix_matrix(lengths, seed):
+    """CSR with the given row lengths, distinct random columns in [0, n) and
+    N(0,1) values."""
+    rng = np.random.default_rng(seed)
+    n = len(lengths)
+    indptr = np.zeros(n + 1, dtype=np.int32)
+    indptr[1:] = np.cumsum(lengths)
+    cols = [np.sort(rng.choice(n, size=int(k), replace=False)) for k in lengths]
+    indices = np.concatenate(cols).astype(np.int32)
+    data = rng.standard_normal(indptr[-1])
+    return CSR(n, n, indptr, indices, data, "row_mix")
+
+
+def test_autotune_cache_keys_carry_the_row_length_signature(tmp_path, monkeypatch):
+    """Two matrices of the same size, non-zero count and longest row but a
+    different mix of row lengths (all rows of 4, against half of 2 and half
+    of 6) are tuned separately: the cache file gets two keys that differ in
+    the row-length classes, and a second call on the first matrix is served
+    from the cache (no new key)."""
+    n = 8192
+    a = np.full(n, 4)
+    b = np.where(np.arange(n) % 2 == 0, 2, 6)
+    for L in (a, b):  # one row of 8 and one empty row, the rest as given
+        L[0], L[1] = 8, 0
+    assert a.sum() == b.sum() and a.max() == b.max() == 8
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("GSE_AUTOTUNE_CACHE", str(path))
+    keys = []
+    for L, seed in ((a, 0), (b, 1), (a, 0)):
+        A = row_mix_matrix(L, seed)
+        rp, ci, va = to_dev(A)
+        C64 = G.CsrMatrix(rp, ci, va, A.n_cols)
+        x = torch.ones(A.n_cols, dtype=torch.float64, device=DEV)
+        y = torch.empty(A.n_rows, dtype=torch.float64, device=DEV)
+        C64.autotune(x, y, reps=2)
+        C64.spmv(x, y)
+        torch.cuda.synchronize()
+        ref = O.csr_spmv(A.indptr, A.indices, A.data, np.ones(A.n_cols))
+        assert np.allclose(y.cpu().numpy(), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+        keys = [line.split()[0] for line in path.read_text().splitlines()]
+    assert len(keys) == 2 and keys[0] != keys[1], keys
+    # classes under half a per mille (the empty row, the row of 8) are left out
+    assert "_r3.1000" in keys[0] and "_r2.500-3.500" in keys[1], keys
+
+
 @pytest.mark.parametrize("num_exp", [1, 3, 5])
 @pytest.mark.parametrize("name", ["diffusion3d_24", "powerlaw_20k", "random_ragged",
                                   "convdiff2d_64"])
