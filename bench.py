@@ -118,7 +118,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="spmv_cg",
-                    choices=["spmv_cg", "gmres", "serving", "powerlaw", "poisson", "blocks"])
+                    choices=["spmv_cg", "gmres", "serving", "powerlaw", "poisson", "blocks",
+                             "batch"])
     ap.add_argument("--pl-rows", type=int, default=4_000_000, help="powerlaw: rows")
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--seed", type=int, default=0)
@@ -133,6 +134,12 @@ def parse():
     ap.add_argument("--n-hi", type=float, default=1e5, help="serving: largest request size")
     ap.add_argument("--arena-gb", type=float, default=32.0, help="serving: arena size")
     ap.add_argument("--slots", type=int, default=64, help="serving: batch slots")
+    ap.add_argument("--batch-systems", type=int, default=16, help="batch: systems per batch")
+    ap.add_argument("--batch-grid", type=int, default=48, help="batch: 3-D grid side per system")
+    ap.add_argument("--batch-segments", type=int, default=0,
+                    help="batch: 0 stepped (default), 1-3 a fixed segment count")
+    ap.add_argument("--batch-kinds", default="gse,fp64",
+                    help="batch: comma-separated kinds to solve (gse, fp64)")
     return ap.parse_args()
 
 
@@ -931,6 +938,86 @@ def run_poisson(args, torch, G):
     return out
 
 
+# ---------------------------------------------------------------- batch ---
+def run_batch(args, torch, G):
+    """One batch of K 3-D diffusion systems (grid^3 each, own coefficients
+    and right-hand side per system, below the size that takes the row-tile
+    ring's product), solved together by the batched CG at a fixed segment
+    count, then the same systems as FP64 CSR.  Reports solve time, the
+    iterations and the algorithmic bytes of one batched product at each
+    segment count (every system's planes, row pointers, p and q once), the
+    figure the batched product's kernel time is divided by.  A fixed count
+    below 3 floors the true residual near its eta (about 5e-10 at s = 2 on
+    these systems), so such runs end NOT_CONVERGED: they measure the product,
+    the stepped default the time to 1e-10."""
+    from workloads import diffusion3d, rhs_from_solution
+
+    dev = torch.device("cuda:0")
+    K, s = args.batch_systems, args.batch_segments
+    mats, rhs = [], []
+    for i in range(K):
+        A = diffusion3d(args.batch_grid, args.seed + i)
+        _, b = rhs_from_solution(A, args.seed + i)
+        mats.append(A)
+        rhs.append(torch.from_numpy(b).to(dev))
+    progress(f"batch: {K} systems of {mats[0].n_rows} rows generated")
+    res = {}
+    t0 = time.perf_counter()
+    kinds = [k for k in args.batch_kinds.split(",") if k]
+    if not kinds or any(k not in ("gse", "fp64") for k in kinds):
+        raise SystemExit(f"--batch-kinds: gse and/or fp64, not {args.batch_kinds!r}")
+    for kind in kinds:
+        holders, triples = [], []
+        for A, b in zip(mats, rhs):
+            rp = torch.from_numpy(A.indptr).to(dev)
+            ci = torch.from_numpy(A.indices).to(dev)
+            va = torch.from_numpy(A.data).to(dev)
+            H = G.GseMatrix(rp, ci, va, A.n_cols) if kind == "gse" else G.CsrMatrix(rp, ci, va, A.n_cols)
+            x = torch.zeros(A.n_rows, dtype=torch.float64, device=dev)
+            holders.append((H, rp, ci, va))
+            triples.append((H.A if kind == "gse" else H.M, b, x))
+        p = G.gse_default_params(G.CG)
+        p.max_iter = 20000
+        p.fixed_segments = s if kind == "gse" else 0
+        ws = torch.empty(G.gse_batch_workspace(triples, p), dtype=torch.uint8, device=dev)
+        times = []
+        for rep in range(args.warmup + args.steps):
+            for _, _, x in triples:
+                x.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            reps = G.gse_batch_cg(triples, p, ws)
+            torch.cuda.synchronize()
+            if rep >= args.warmup:
+                times.append((time.perf_counter() - t) * 1e3)
+        segs = (1, 2, 3) if kind == "gse" else (0,)
+        nbytes = {f"s{k}" if k else "fp64":
+                  int(sum(spmv_bytes(A.n_rows, A.n_cols, A.nnz, {0: 12, 1: 6, 2: 8, 3: 12}[k])
+                          for A in mats)) for k in segs}
+        res[kind] = {"solve_ms": round(float(np.median(times)), 3),
+                     "iters": [int(r.iters) for r in reps],
+                     "iters_per_seg_total": [int(sum(r.iters_per_seg[k] for r in reps))
+                                             for k in range(3)],
+                     "status": [int(r.status) for r in reps],
+                     "relres_true_max": float(max(r.relres_true for r in reps)),
+                     "product_bytes": nbytes}
+        progress(f"batch: {kind} {res[kind]['solve_ms']} ms, iterations "
+                 f"{min(res[kind]['iters'])}-{max(res[kind]['iters'])}")
+        del holders, triples, ws
+    wall = time.perf_counter() - t0
+    label = "stepped GSE" if s == 0 else f"GSE s={s}"
+    first = res[kinds[0]]
+    out = base_record(args, f"batched CG time-to-1e-10, {K} systems, {label} vs FP64 CSR",
+                      first["solve_ms"], "ms", wall, higher=False)
+    if "gse" in res and "fp64" in res:
+        out["speedup"] = round(res["fp64"]["solve_ms"] / res["gse"]["solve_ms"], 3)
+    out["config"] = {"workload": f"{K}x diffusion3d_{args.batch_grid}^3_7pt_varcoef_4decades",
+                     "n_rows_each": mats[0].n_rows, "nnz_each": mats[0].nnz,
+                     "fixed_segments": s, "seed": args.seed}
+    out["batch"] = res
+    return out
+
+
 # -------------------------------------------------------------- serving ---
 def run_serving(args, torch, G):
     from workloads import rhs_from_solution, serving_request_matrix, serving_stream
@@ -1053,6 +1140,8 @@ def main():
         out = run_powerlaw(args, torch, G)
     elif args.workload == "poisson":
         out = run_poisson(args, torch, G)
+    elif args.workload == "batch":
+        out = run_batch(args, torch, G)
     elif args.workload == "blocks":
         t0 = time.perf_counter()
         leg = leg_blocks(torch, G, args.seed, args.copies)

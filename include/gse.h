@@ -447,9 +447,10 @@ gse_status gse_solve_history(const void* ws, int32_t cap, double* hist, int32_t*
  * whether it is solved alone or in any batch.  The SpMV stages tiles of up to
  * 2048 non-zeros in LDS, so operators planned with tile_nnz 1024 (the
  * default) run fastest; any valid plan is accepted.  A system of at least
- * 2^18 rows planned on the row-tile ring (rows of at most 8 non-zeros,
- * tile_nnz 1024) takes its product from that single-system kernel, one more
- * launch per iteration; epochs holding such systems are launched directly. */
+ * 2^16 rows planned on the row-tile ring (rows of at most 8 non-zeros,
+ * tile_nnz 1024) takes its product from that single-system kernel: such
+ * systems share one grouped launch per ring instance and iteration, each on
+ * workgroups of its own; epochs holding them are launched directly. */
 typedef struct gse_system {
     const gse_matrix* A;   /* stepped GSE-SEM operator, or NULL */
     const gse_csr* M;      /* FP64 CSR operator, used when A is NULL */

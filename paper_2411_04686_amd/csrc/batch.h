@@ -51,8 +51,9 @@ struct BatchSlot {
 
 // Rows from which a system of short rows (at most 8 non-zeros, the default
 // 1024-non-zero plan) takes its batched product from the row-tile ring
-// kernel, one launch per iteration, instead of the batched tile kernel.
-constexpr int32_t kRingRows = 1 << 18;
+// kernel -- one grouped launch per ring instance and iteration for all such
+// systems -- instead of the batched tile kernel.
+constexpr int32_t kRingRows = 1 << 16;
 
 // The row-tile ring's operand for a batched system.
 SpmvOperand ring_operand(const BatchSlot& B);
@@ -200,6 +201,15 @@ class BatchEngine {
   std::vector<int32_t> seg_buf_;
   std::vector<int32_t> prod_off_;   // first product partial of each slot in list 0
   std::vector<int> ring_ids_;       // running systems whose product runs on the ring
+  // this epoch's grouped ring products: one launch per instance, over the
+  // descriptors [first, first + n) of groups_ and `total` workgroups
+  struct RingLaunch {
+    RowClass c;
+    int first, n, total;
+  };
+  std::vector<RingLaunch> ring_launches_;
+  std::vector<RowGroup> hgroups_;
+  RowGroup* groups_ = nullptr;      // device descriptors, one per slot at most
   int32_t hcounts_[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
   RegionHeader hhdr_{};
   bool run_dirty_ = true;

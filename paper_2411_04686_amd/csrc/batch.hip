@@ -11,15 +11,18 @@
 // workgroup ever waits on another and there are no cross-XCD fences.
 //
 // A system of at least kRingRows rows of short rows leaves the product
-// list: its product is a launch of the single-system row-tile ring (gated
-// on its stop flag on the device) between the batched product and the r
-// step, with its p.q partials in slots reserved for it; its vector steps
-// stay in the batched kernels.
+// list: its product runs on the single-system row-tile ring.  All such
+// systems that run one ring instance (segment count, row bound, index
+// layout) share one grouped launch per iteration, placed between the
+// batched product and the r step; in it each system runs its own plain
+// launch's grid on a range of workgroups of its own (gated on its stop
+// flag on the device) and writes its p.q partials to slots reserved for
+// it.  Its vector steps stay in the batched kernels.
 //
 // The kernels read the list lengths from device memory, so the iteration
 // epoch (16 iterations) is captured into a HIP graph once per engine and
 // replayed whatever the batch holds (epochs with ring systems, whose
-// launches take host-side arguments, run directly); between epochs the host reads the
+// descriptors are uploaded per epoch, run directly); between epochs the host reads the
 // state records back, runs the actions a switch or a convergence candidate
 // needs (residual replacement, the all-segment residual check) for the
 // systems concerned, and rebuilds the lists when systems finish or arrive.
@@ -493,6 +496,7 @@ size_t BatchEngine::region_bytes(int cap_slots, int64_t cap_tiles, int64_t cap_c
   b += align_up((size_t)cap_slots * sizeof(int32_t));
   b += align_up((size_t)cap_tiles * sizeof(double));
   b += align_up((size_t)cap_chunks * sizeof(double));
+  b += align_up((size_t)cap_slots * sizeof(RowGroup));
   return b;
 }
 
@@ -528,6 +532,7 @@ gse_status BatchEngine::init(void* region, size_t bytes, int cap_slots, int64_t 
   act_ = reinterpret_cast<int32_t*>(take((size_t)cap_slots * sizeof(int32_t)));
   part_ = reinterpret_cast<double*>(take((size_t)cap_tiles * sizeof(double)));
   part2_ = reinterpret_cast<double*>(take((size_t)cap_chunks * sizeof(double)));
+  groups_ = reinterpret_cast<RowGroup*>(take((size_t)cap_slots * sizeof(RowGroup)));
 
   hslot_.assign((size_t)cap_slots, BatchSlot{});
   hS_.assign((size_t)cap_slots, SolverState{});
@@ -570,8 +575,8 @@ int BatchEngine::add(const BatchSlot& d, const gse_params* p, const double* eta)
     }
   if (id < 0) return fail(GSE_ERR_NOMEM, "no free batch slot");
   BatchSlot dd = d;
-  dd.ring = (d.n_rows >= kRingRows && d.tile_nnz == 1024 && d.nnz >= 1024 && d.max_row <= 8 &&
-             d.rv_lanes == 0) ? 1 : 0;
+  RowClass rc{};
+  dd.ring = (d.n_rows >= kRingRows && rows_class(d.fmt ? 1 : kCsr64, ring_operand(d), &rc)) ? 1 : 0;
   // the ring's grid is at most the row tiles rounded up to 8, and at least 8
   const int32_t rt = (int32_t)(((int64_t)d.n_rows + 191) / 192);
   const int32_t rt8 = (rt + 7) / 8 * 8;
@@ -694,28 +699,59 @@ BatchView BatchEngine::view(int l) const {
 
 hipError_t BatchEngine::launch_epoch_kernels(int iters) {
   const BatchView v = view(0);
-  for (int k = 0; k < iters; ++k) {
-    hipLaunchKernelGGL(k_b_spmv, dim3(grid_spmv_), dim3(kWG), 0, st_, v, 0);
-    // ring systems: q = A_s p and the partials of p.q on the row-tile ring,
-    // skipped on the device once the system stopped
+  // the ring systems' products at this epoch's segment counts, grouped by
+  // kernel instance: each system keeps the grid and partials of its own
+  // plain launch, so its product does not depend on the batch around it
+  ring_launches_.clear();
+  hgroups_.clear();
+  if (!ring_ids_.empty()) {
+    std::vector<std::pair<RowClass, int>> cls;
     for (int id : ring_ids_) {
+      const BatchSlot& B = hslot_[id];
+      RowClass c{};
+      if (!rows_class(B.fmt ? hS_[id].s : kCsr64, ring_operand(B), &c) || c.grid > B.parts)
+        return hipErrorInvalidValue;
+      cls.push_back({c, id});
+    }
+    auto key = [](const RowClass& c) { return (c.fmt * 16 + c.B) * 8 + (c.IB + 1); };
+    std::stable_sort(cls.begin(), cls.end(),
+                     [&](const std::pair<RowClass, int>& a, const std::pair<RowClass, int>& b) {
+                       return key(a.first) < key(b.first);
+                     });
+    for (size_t i = 0; i < cls.size(); ++i) {
+      const RowClass& c = cls[i].first;
+      const int id = cls[i].second;
+      if (i == 0 || key(c) != key(cls[i - 1].first))
+        ring_launches_.push_back(RingLaunch{c, (int)hgroups_.size(), 0, 0});
+      RingLaunch& L = ring_launches_.back();
       BatchSlot& B = hslot_[id];
-      const int fmt = B.fmt ? hS_[id].s : kCsr64;
       SpmvEpilogue ep{};
       ep.epi = kEpiDot;
       ep.aux = B.p;
       ep.partials = part_ + prod_off_[id];
       ep.gate = &S_[id].stop;
-      int g = 0;
-      ep.grid_out = &g;
-      hipError_t e = launch_spmv(fmt, ring_operand(B), B.p, B.q, ep, st_);
-      if (e != hipSuccess) return e;
-      if (g < 1 || g > B.parts) return hipErrorInvalidValue;
-      if (g != B.n_prod) {  // ordered before the r step that sums them
-        B.n_prod = g;
-        e = hipMemcpyAsync(&slots_[id].n_prod, &B.n_prod, sizeof(int32_t), hipMemcpyHostToDevice, st_);
+      hgroups_.push_back(RowGroup{ring_operand(B), B.p, B.q, ep, L.total, c.grid});
+      L.total += c.grid;
+      ++L.n;
+      if (c.grid != B.n_prod) {  // ordered before the r step that sums them
+        B.n_prod = c.grid;
+        const hipError_t e = hipMemcpyAsync(&slots_[id].n_prod, &B.n_prod, sizeof(int32_t),
+                                            hipMemcpyHostToDevice, st_);
         if (e != hipSuccess) return e;
       }
+    }
+    const hipError_t e = hipMemcpyAsync(groups_, hgroups_.data(), hgroups_.size() * sizeof(RowGroup),
+                                        hipMemcpyHostToDevice, st_);
+    if (e != hipSuccess) return e;
+  }
+  // a captured epoch keeps the batched product whatever the lists hold; a
+  // direct one leaves it out when no system has tiles in it
+  const bool tiles = ring_ids_.empty() || hcounts_[0][0] > 0;
+  for (int k = 0; k < iters; ++k) {
+    if (tiles) hipLaunchKernelGGL(k_b_spmv, dim3(grid_spmv_), dim3(kWG), 0, st_, v, 0);
+    for (const RingLaunch& L : ring_launches_) {
+      const hipError_t e = launch_rows_grouped(L.c, groups_ + L.first, L.n, L.total, st_);
+      if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_b_rstep, dim3(grid_vec_), dim3(kWG), 0, st_, v);
     hipLaunchKernelGGL(k_b_xstep, dim3(grid_vec_), dim3(kWG), 0, st_, v);

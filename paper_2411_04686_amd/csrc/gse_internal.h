@@ -192,6 +192,31 @@ struct SpmvEpilogue {
 
 hipError_t launch_spmv(int fmt, const SpmvOperand& A, const double* x, double* y,
                        const SpmvEpilogue& ep, hipStream_t st);
+
+// One operand of a grouped row-tile launch (a device array the host fills):
+// operand, vectors, epilogue (grid_out unused) and the launch's workgroups
+// [wg0, wg0 + wgs) that run the operand's plain-launch grid.
+struct RowGroup {
+  SpmvOperand A;
+  const double* x;
+  double* y;
+  SpmvEpilogue ep;
+  int32_t wg0, wgs;
+};
+
+// The row-tile ring instance that launch_spmv(fmt, A, ...) runs -- row bound
+// B, index layout IB (3: the 3-bit column-word split fixed at compile time,
+// -1: read from the operand) -- and its grid.  False when A takes another
+// schedule (rows past 8 non-zeros, another tile size, lanes per row, block
+// tables, fewer than 1024 non-zeros).
+struct RowClass {
+  int fmt, B, IB, grid;
+};
+bool rows_class(int fmt, const SpmvOperand& A, RowClass* out);
+// One dispatch over n_groups operands of class c whose ranges ascend and
+// cover [0, total) workgroups.
+hipError_t launch_rows_grouped(const RowClass& c, const RowGroup* groups, int n_groups, int total,
+                               hipStream_t st);
 hipError_t launch_plan(const int32_t* row_ptr, int32_t n_rows, int32_t nnz, int32_t tile_nnz,
                        int32_t n_tiles, int32_t* tile_row, hipStream_t st);
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t st);

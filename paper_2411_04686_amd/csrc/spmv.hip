@@ -217,8 +217,9 @@ __device__ __forceinline__ int pslot(int li) { return li + (li >> 3); }
 // the tiles in flight on an XCD are neighbours and share x in its L2.
 struct TileWalk {
   int t, end, step;
-  __device__ __forceinline__ TileWalk(int n_tiles) {
-    const int g = gridDim.x, wg = blockIdx.x;
+  __device__ __forceinline__ TileWalk(int n_tiles) : TileWalk(n_tiles, blockIdx.x, gridDim.x) {}
+  // workgroup wg of the g (a multiple of 8 when g > 8) that share the tiles
+  __device__ __forceinline__ TileWalk(int n_tiles, int wg, int g) {
     const int xcd = wg & 7, local = wg >> 3;
     const int nx = (g >> 3) + (((g & 7) > xcd) ? 1 : 0);
     const int tb = (int)(((long long)n_tiles * xcd) >> 3);
@@ -908,24 +909,35 @@ __device__ __forceinline__ void stage_tile_tables(const SpmvOperand& A, int t, u
 // eight shared exponents, the default k = 8): the field split folds into
 // immediate shifts and masks and only 2^IB scale entries are built.  The
 // general instance (IB = -1) reads the split from the operand.
-template <int FMT, int B, bool BLK = false, int IB = -1>
-__global__ __launch_bounds__(kRingThreads) void k_spmv_rows(SpmvOperand A,
-                                                            const double* __restrict__ x,
-                                                            double* __restrict__ y, SpmvEpilogue ep) {
+//
+// The body runs for one operand on workgroup wg of the g that share its
+// tiles: the whole grid of a plain launch, or one operand's range of a
+// grouped launch.
+template <int FMT, int B, bool BLK>
+struct RowsLds {
+  using L = RowRing<FMT, B>;
+  __attribute__((aligned(16))) char ring_raw[L::D * L::STAGE];
+  int hdr[L::D][4];  // per stage: first row, row end, first staged non-zero
+  uint32_t scale_tab[BLK ? 2 * kRowTabEntries : kScaleEntries];
+  double red[kRingThreads / 64];
+};
+
+template <int FMT, int B, bool BLK, int IB>
+__device__ __forceinline__ void rows_body(const SpmvOperand& A, const double* __restrict__ x,
+                                          double* __restrict__ y, const SpmvEpilogue& ep, int wg,
+                                          int g, RowsLds<FMT, B, BLK>& lds) {
   using L = RowRing<FMT, B>;
   constexpr int PRODUCER = kRingConsumers / 64;
-  __shared__ __attribute__((aligned(16))) char ring_raw[L::D * L::STAGE];
-  __shared__ int hdr[L::D][4];  // per stage: first row, row end, first staged non-zero
-  __shared__ uint32_t scale_tab[BLK ? 2 * kRowTabEntries : kScaleEntries];
-  __shared__ double red[kRingThreads / 64];
-  lds_char* ring = (lds_char*)ring_raw;
+  auto& hdr = lds.hdr;
+  uint32_t* scale_tab = lds.scale_tab;
+  double* red = lds.red;
+  lds_char* ring = (lds_char*)lds.ring_raw;
 
-  if (ep.gate && *ep.gate) return;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int pad = (A.nnz + 15) & ~15;
   const int n_rt = (A.n_rows + kRowTile - 1) / kRowTile;
-  TileWalk walk(n_rt);
+  TileWalk walk(n_rt, wg, g);
   const int count = walk.t < walk.end ? (walk.end - walk.t + walk.step - 1) / walk.step : 0;
   if constexpr (BLK) {
     if (count > 0 && tid < kRingConsumers) stage_tile_tables<FMT>(A, walk.t, scale_tab, tid);
@@ -1022,9 +1034,40 @@ __global__ __launch_bounds__(kRingThreads) void k_spmv_rows(SpmvOperand A,
       double t = 0.0;
 #pragma unroll
       for (int i = 0; i < kRingThreads / 64; ++i) t += red[i];
-      ep.partials[blockIdx.x] = t;
+      ep.partials[wg] = t;
     }
   }
+}
+
+template <int FMT, int B, bool BLK = false, int IB = -1>
+__global__ __launch_bounds__(kRingThreads) void k_spmv_rows(SpmvOperand A,
+                                                            const double* __restrict__ x,
+                                                            double* __restrict__ y, SpmvEpilogue ep) {
+  __shared__ RowsLds<FMT, B, BLK> lds;
+  if (ep.gate && *ep.gate) return;
+  rows_body<FMT, B, BLK, IB>(A, x, y, ep, blockIdx.x, gridDim.x, lds);
+}
+
+// Grouped launch: the products of several operands of one format, row bound
+// and index layout in one dispatch.  Operand i runs on workgroups
+// [wg0_i, wg0_i + g_i) with g_i its own plain launch's grid (a multiple of
+// 8, so every workgroup sits on the XCD it has in that launch) and writes
+// its partials to its own ep.partials[0, g_i): each product and its
+// partials equal those of the operand's plain launch bit for bit.
+template <int FMT, int B, int IB>
+__global__ __launch_bounds__(kRingThreads) void k_spmv_rows_grouped(const RowGroup* __restrict__ groups,
+                                                                    int n_groups) {
+  const int wg = blockIdx.x;
+  int lo = 0, hi = n_groups - 1;  // the last range that starts at or before wg
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (groups[mid].wg0 <= wg) lo = mid;
+    else hi = mid - 1;
+  }
+  const RowGroup& G = groups[lo];
+  __shared__ RowsLds<FMT, B, false> lds;
+  if (G.ep.gate && *G.ep.gate) return;
+  rows_body<FMT, B, false, IB>(G.A, G.x, G.y, G.ep, wg - G.wg0, G.wgs, lds);
 }
 
 // Resident workgroups of one kernel instance on this device (occupancy x
@@ -1083,6 +1126,19 @@ hipError_t launch_ring(const SpmvOperand& A, const double* x, double* y, const S
   return hipGetLastError();
 }
 
+// Grid of a plain row-tile launch: the instance's resident workgroups, at
+// most the row tiles rounded up to 8, at least 8.
+template <int FMT, int B, bool BLK, int IB>
+int rows_grid(const SpmvOperand& A) {
+  int g = resident_groups<FMT, 4, kRowTiles, B, BLK, IB>();
+  if (g <= 0) return 0;
+  const int n_rt = (A.n_rows + kRowTile - 1) / kRowTile;
+  const int need = (n_rt + 7) / 8 * 8;
+  if (g > need) g = need;
+  if (g < 8) g = 8;
+  return g;
+}
+
 template <int FMT, int B, bool BLK = false, int IB = -1>
 hipError_t launch_rows(const SpmvOperand& A, const double* x, double* y, const SpmvEpilogue& ep,
                        hipStream_t st) {
@@ -1099,15 +1155,62 @@ hipError_t launch_rows(const SpmvOperand& A, const double* x, double* y, const S
         A.block_stride < 1 || A.block_stride > GSE_MAX_EXP)
       return hipErrorInvalidValue;
   }
-  int g = resident_groups<FMT, 4, kRowTiles, B, BLK, IB>();
+  const int g = rows_grid<FMT, B, BLK, IB>(A);
   if (g <= 0) return hipErrorInvalidDevice;
-  const int n_rt = (A.n_rows + kRowTile - 1) / kRowTile;
-  const int need = (n_rt + 7) / 8 * 8;
-  if (g > need) g = need;
-  if (g < 8) g = 8;
   if (ep.grid_out) *ep.grid_out = g;
   hipLaunchKernelGGL((k_spmv_rows<FMT, B, BLK, IB>), dim3(g), dim3(kRingThreads), 0, st, A, x, y, ep);
   return hipGetLastError();
+}
+
+// Class and grid of the row-tile ring for operand A (the choices launch_f
+// and launch_rows make).
+template <int FMT>
+bool rows_class_f(const SpmvOperand& A, RowClass* out) {
+  const int B = A.max_row <= 3 ? 3 : A.max_row <= 5 ? 5 : A.max_row <= 7 ? 7 : 8;
+  bool ib3 = false;
+  if constexpr (is_gse(FMT)) {
+    const ColSplit c3 = col_split(3, false);
+    ib3 = A.split.shift == c3.shift && A.split.slot_mask == c3.slot_mask &&
+          A.split.col_mask == c3.col_mask && A.split.hmask == c3.hmask && A.split.ei == c3.ei;
+  }
+  int g = 0;
+  switch (B) {
+    case 3: g = ib3 ? rows_grid<FMT, 3, false, 3>(A) : rows_grid<FMT, 3, false, -1>(A); break;
+    case 5: g = ib3 ? rows_grid<FMT, 5, false, 3>(A) : rows_grid<FMT, 5, false, -1>(A); break;
+    case 7: g = ib3 ? rows_grid<FMT, 7, false, 3>(A) : rows_grid<FMT, 7, false, -1>(A); break;
+    default: g = ib3 ? rows_grid<FMT, 8, false, 3>(A) : rows_grid<FMT, 8, false, -1>(A); break;
+  }
+  if (g <= 0) return false;
+  *out = RowClass{FMT, B, ib3 ? 3 : -1, g};
+  return true;
+}
+
+template <int FMT, int B, int IB>
+hipError_t launch_grouped_i(const RowGroup* groups, int n_groups, int total, hipStream_t st) {
+  hipLaunchKernelGGL((k_spmv_rows_grouped<FMT, B, IB>), dim3(total), dim3(kRingThreads), 0, st,
+                     groups, n_groups);
+  return hipGetLastError();
+}
+
+template <int FMT, int B>
+hipError_t launch_grouped_b(int IB, const RowGroup* groups, int n_groups, int total, hipStream_t st) {
+  if constexpr (is_gse(FMT)) {
+    if (IB == 3) return launch_grouped_i<FMT, B, 3>(groups, n_groups, total, st);
+  }
+  if (IB != -1) return hipErrorInvalidValue;
+  return launch_grouped_i<FMT, B, -1>(groups, n_groups, total, st);
+}
+
+template <int FMT>
+hipError_t launch_grouped_f(const RowClass& c, const RowGroup* groups, int n_groups, int total,
+                            hipStream_t st) {
+  switch (c.B) {
+    case 3: return launch_grouped_b<FMT, 3>(c.IB, groups, n_groups, total, st);
+    case 5: return launch_grouped_b<FMT, 5>(c.IB, groups, n_groups, total, st);
+    case 7: return launch_grouped_b<FMT, 7>(c.IB, groups, n_groups, total, st);
+    case 8: return launch_grouped_b<FMT, 8>(c.IB, groups, n_groups, total, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 
@@ -1410,6 +1513,31 @@ hipError_t launch_spmv(int fmt, const SpmvOperand& A, const double* x, double* y
     case 3: return launch_f<3>(A, x, y, ep, st);
     case kFp16: return launch_f<kFp16>(A, x, y, ep, st);
     case kBf16: return launch_f<kBf16>(A, x, y, ep, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool rows_class(int fmt, const SpmvOperand& A, RowClass* out) {
+  if (A.block_sem || A.rv_lanes > 0 || A.tile_nnz != kRingTile || A.nnz < kRingTile || A.max_row > 8 ||
+      A.n_rows < 1)
+    return false;
+  switch (fmt) {
+    case 0: return rows_class_f<0>(A, out);
+    case 1: return rows_class_f<1>(A, out);
+    case 2: return rows_class_f<2>(A, out);
+    case 3: return rows_class_f<3>(A, out);
+    default: return false;
+  }
+}
+
+hipError_t launch_rows_grouped(const RowClass& c, const RowGroup* groups, int n_groups, int total,
+                               hipStream_t st) {
+  if (n_groups < 1 || total < 1) return hipErrorInvalidValue;
+  switch (c.fmt) {
+    case 0: return launch_grouped_f<0>(c, groups, n_groups, total, st);
+    case 1: return launch_grouped_f<1>(c, groups, n_groups, total, st);
+    case 2: return launch_grouped_f<2>(c, groups, n_groups, total, st);
+    case 3: return launch_grouped_f<3>(c, groups, n_groups, total, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from workloads import CSR, diffusion3d, poisson2d, rhs_from_solution
+from workloads import CSR, diffusion2d, diffusion3d, poisson2d, rhs_from_solution
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -174,10 +174,10 @@ def test_batch_argument_errors():
 
 
 def test_large_systems_run_their_product_on_the_ring():
-    """Systems of at least 2^18 rows of short rows take their product from
-    the single-system row-tile ring (one launch per iteration) while the
-    others stay on the batched tile kernel: both against the oracle, each
-    alone equal to the mix bit for bit, stepped GSE and FP64 CSR."""
+    """Systems of at least 2^16 rows of short rows take their product from
+    the single-system row-tile ring (grouped launches) while the others stay
+    on the batched tile kernel: both against the oracle, each alone equal to
+    the mix bit for bit, stepped GSE and FP64 CSR."""
     systems = [Sys(diffusion3d(64, 7), 7), Sys(diffusion3d(65, 8), 8, kind="csr"),
                Sys(diffusion3d(12, 9), 9), Sys(poisson2d(30), 10)]
     assert systems[0].A.n_rows >= 1 << 18 and systems[1].A.n_rows >= 1 << 18
@@ -189,6 +189,32 @@ def test_large_systems_run_their_product_on_the_ring():
         assert np.linalg.norm(x - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
         assert abs(r.iters - ref.iters) <= max(3, ref.iters // 10), (s.A.name, r.iters, ref.iters)
     for i in (0, 1, 3):
+        (r1, x1, h1, s1), = batch_solve([systems[i]])
+        r, x, hist, seg = res[i]
+        assert r1.iters == r.iters and list(r1.iters_per_seg) == list(r.iters_per_seg)
+        assert np.array_equal(x1, x) and np.array_equal(h1, hist)
+
+
+def test_medium_systems_share_grouped_ring_launches():
+    """Systems just above 2^16 rows in three ring instances -- two 3-D
+    stencils (rows of 7) and a 2-D one (rows of 5) stepped in GSE-SEM, so
+    each instance holds one or more systems as they step through the
+    segment counts, and a 3-D FP64 CSR one -- beside a small system on the
+    batched tile kernel: every result against the oracle's CG, and each
+    system alone equal to the mix bit for bit (its grid and partials are
+    those of its own plain launch whatever the group holds)."""
+    systems = [Sys(diffusion3d(41, 11), 11), Sys(diffusion3d(42, 12), 12),
+               Sys(diffusion2d(262, 13, decades=1.0), 13), Sys(diffusion3d(41, 14), 14, kind="csr"),
+               Sys(diffusion3d(10, 1), 1)]
+    assert all(s.A.n_rows >= 1 << 16 for s in systems[:4]) and systems[4].A.n_rows < 1 << 16
+    res = batch_solve(systems)
+    for s, (r, x, hist, seg) in zip(systems, res):
+        ref = oracle_solve(s)
+        assert r.status == G.OK and ref.status == O.OK, (s.A.name, r.as_dict())
+        assert r.relres_true <= 1e-10 and true_relres(s.A, x, s.b_host) <= 1e-10
+        assert np.linalg.norm(x - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+        assert abs(r.iters - ref.iters) <= max(3, ref.iters // 10), (s.A.name, r.iters, ref.iters)
+    for i in range(5):
         (r1, x1, h1, s1), = batch_solve([systems[i]])
         r, x, hist, seg = res[i]
         assert r1.iters == r.iters and list(r1.iters_per_seg) == list(r.iters_per_seg)
