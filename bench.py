@@ -427,6 +427,12 @@ def run_spmv_cg(args, torch, G):
         pl = leg_powerlaw(torch, G, args.seed, 1, 1, 5, args.pl_rows)
         pl.pop("wall_s")
         out["powerlaw"] = pl
+        progress("legs: batched CG, 16 x 48^3")
+        bt = run_batch(args, torch, G)
+        out["batch"] = {"config": bt["config"], "speedup": bt.get("speedup"), **bt["batch"]}
+        progress("legs: serving")
+        sv = run_serving(args, torch, G)
+        out["serving"] = {"config": sv["config"], **sv["serving"]}
     if args.cpu_baseline > 0:
         out["cpu_baseline"] = cpu_baseline(A, args.cpu_baseline)
     return out
